@@ -1,0 +1,482 @@
+// Sparse state-vector ORACLE -- test infrastructure only.
+//
+// A plain, slow, obviously correct CPU implementation of the sparse simulation
+// method of Jaques & Haner, "Leveraging state sparsity for more efficient
+// quantum simulations" (arXiv 2105.01533).  Only the test suite, the smoke
+// check and the benchmark's CPU-baseline leg may load this library; the GPU
+// library never does, and the two share no code.
+//
+// The state is the paper's Sec. 3 data structure: unordered (label, amplitude)
+// pairs for the nonzero amplitudes, here std::unordered_map from a 128-bit
+// label to a complex<double>.  Qubit q is bit q of the label (Sec. 2.1: i_k is
+// the k-th bit of i); qubits 64..127 live in the high word.
+//
+// Operations (Sec. 3.1):
+//   * phase/permutation gates (at most one nonzero per row and column):
+//     G(a_b |b>) = f(b) a_b |g(b)>, applied by rebuilding the map;
+//   * branching gates (two nonzeros per row): Eq. 2 on the pair (b, b') with
+//     b' = b xor 2^t; at most one look-up of the partner per label, and when
+//     both partners are present only the label whose target bit is 1 emits;
+//   * measurement: Born rule (Sec. 2.1), projection onto the outcome and
+//     renormalisation.
+// Queued mode (Sec. 3.2) applies a maximal run of phase/permutation gates to
+// each label in turn, composing f and g as in the paper, before inserting the
+// result into the new map.  Gate-by-gate mode rebuilds the map after every
+// gate.  The two must agree bit for bit.
+//
+// Readings where the paper is silent (also listed in the design notes):
+//   * prune T_eps after every applied branching gate: drop an entry iff
+//     re*re + im*im < eps, and always drop exact zeros (the paper stores only
+//     nonzero amplitudes).  Phase/permutation gates never prune.
+//   * a branching gate with cap != 0 is skipped iff 2*nnz > cap.
+//   * measurement: P0, P1 are sums of |a|^2 over labels with the qubit 0 / 1,
+//     taken in ascending label order; outcome 0 iff u < P0/(P0+P1) (unless
+//     forced); the kept amplitudes are scaled by 1/sqrt(P_outcome).
+//   * complex products are (a.re*b.re - a.im*b.im, a.re*b.im + a.im*b.re),
+//     evaluated as written with no fused multiply-add.
+//
+// Built with g++ -O2 -ffp-contract=off.
+#include <algorithm>
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+#include <unordered_map>
+#include <vector>
+
+namespace {
+
+struct Label {
+  uint64_t lo, hi;
+  bool operator==(const Label& o) const { return lo == o.lo && hi == o.hi; }
+  bool operator<(const Label& o) const { return hi != o.hi ? hi < o.hi : lo < o.lo; }
+};
+
+struct LabelHash {
+  size_t operator()(const Label& k) const {
+    uint64_t x = k.lo * 0x9E3779B97F4A7C15ull ^ (k.hi + 0x632BE59BD9B4E019ull) * 0xC2B2AE3D27D4EB4Full;
+    return static_cast<size_t>(x ^ (x >> 29));
+  }
+};
+
+struct Amp {
+  double re, im;
+};
+
+Amp mul(Amp a, Amp b) {
+  Amp r;
+  r.re = a.re * b.re - a.im * b.im;
+  r.im = a.re * b.im + a.im * b.re;
+  return r;
+}
+
+Amp add(Amp a, Amp b) { return Amp{a.re + b.re, a.im + b.im}; }
+
+using State = std::unordered_map<Label, Amp, LabelHash>;
+
+// Op record written by the workload generator (48 bytes, little endian).
+struct OpRecord {
+  uint32_t kind, target;
+  uint64_t ctrl_lo, ctrl_hi;
+  double param;
+  uint64_t cap;
+  int32_t forced;
+  uint32_t pad;
+};
+static_assert(sizeof(OpRecord) == 48, "op record layout");
+
+enum Kind : uint32_t {
+  kX = 0, kY, kZ, kS, kSdg, kT, kTdg, kRz, kPhase,
+  kH = 9, kRx, kRy,
+  kMeasure = 12
+};
+
+bool is_monomial(uint32_t k) { return k <= kPhase; }
+bool is_branching(uint32_t k) { return k >= kH && k <= kRy; }
+
+// A phase/permutation gate as the pair (f, g) of Sec. 3.2:
+//   f(b) = m[bit_t(b)] when the controls are set (and has_phase), else 1;
+//   g(b) = b xor (flip ? 2^t : 0) when the controls are set, else b.
+struct Monomial {
+  Label ctrl;
+  unsigned target;
+  bool flip;
+  bool has_phase;
+  Amp m[2];
+};
+
+// Gate matrices from Sec. 2.1: H = sqrt(0.5)[[1,1],[1,-1]], S = diag(1,i),
+// X, Y, Z, and R_P(theta) = exp(-i theta P / 2).  T = diag(1, e^{i pi/4}) and
+// the adjoints are the textbook definitions.  A column of a permutation-type
+// matrix is read off as "input bit v goes to output bit v xor flip with factor
+// m[v]".
+Monomial monomial_of(const OpRecord& op) {
+  Monomial g;
+  g.ctrl = Label{op.ctrl_lo, op.ctrl_hi};
+  g.target = op.target;
+  g.flip = false;
+  g.has_phase = true;
+  const double h = std::sqrt(0.5);
+  const Amp one{1.0, 0.0};
+  g.m[0] = one;
+  g.m[1] = one;
+  switch (op.kind) {
+    case kX:  // [[0,1],[1,0]]: |0> -> |1>, |1> -> |0>
+      g.flip = true;
+      g.has_phase = false;
+      break;
+    case kY:  // [[0,-i],[i,0]]: |0> -> i|1>, |1> -> -i|0>
+      g.flip = true;
+      g.m[0] = Amp{0.0, 1.0};
+      g.m[1] = Amp{0.0, -1.0};
+      break;
+    case kZ:
+      g.m[1] = Amp{-1.0, 0.0};
+      break;
+    case kS:
+      g.m[1] = Amp{0.0, 1.0};
+      break;
+    case kSdg:
+      g.m[1] = Amp{0.0, -1.0};
+      break;
+    case kT:
+      g.m[1] = Amp{h, h};
+      break;
+    case kTdg:
+      g.m[1] = Amp{h, -h};
+      break;
+    case kRz: {  // exp(-i theta Z / 2) = diag(e^{-i theta/2}, e^{+i theta/2})
+      const double c = std::cos(0.5 * op.param), s = std::sin(0.5 * op.param);
+      g.m[0] = Amp{c, -s};
+      g.m[1] = Amp{c, s};
+      break;
+    }
+    case kPhase:  // diag(1, e^{i theta})
+      g.m[1] = Amp{std::cos(op.param), std::sin(op.param)};
+      break;
+    default:
+      break;
+  }
+  return g;
+}
+
+// Branching 2x2 matrix U (row-major): out0 = U00 a0 + U01 a1, out1 = U10 a0 + U11 a1.
+void matrix_of(const OpRecord& op, Amp u[4]) {
+  const double h = std::sqrt(0.5);
+  const double c = std::cos(0.5 * op.param), s = std::sin(0.5 * op.param);
+  switch (op.kind) {
+    case kH:
+      u[0] = Amp{h, 0.0};
+      u[1] = Amp{h, 0.0};
+      u[2] = Amp{h, 0.0};
+      u[3] = Amp{-h, 0.0};
+      break;
+    case kRx:  // exp(-i theta X / 2) = [[c, -i s], [-i s, c]]
+      u[0] = Amp{c, 0.0};
+      u[1] = Amp{0.0, -s};
+      u[2] = Amp{0.0, -s};
+      u[3] = Amp{c, 0.0};
+      break;
+    case kRy:  // exp(-i theta Y / 2) = [[c, -s], [s, c]]
+      u[0] = Amp{c, 0.0};
+      u[1] = Amp{-s, 0.0};
+      u[2] = Amp{s, 0.0};
+      u[3] = Amp{c, 0.0};
+      break;
+    default:
+      u[0] = u[1] = u[2] = u[3] = Amp{0.0, 0.0};
+  }
+}
+
+bool bit_of(const Label& k, unsigned q) {
+  return q < 64 ? ((k.lo >> q) & 1u) : ((k.hi >> (q - 64)) & 1u);
+}
+
+Label with_bit(Label k, unsigned q, bool v) {
+  uint64_t& w = q < 64 ? k.lo : k.hi;
+  const uint64_t m = 1ull << (q & 63);
+  w = v ? (w | m) : (w & ~m);
+  return k;
+}
+
+bool controls_set(const Label& k, const Label& c) {
+  return (k.lo & c.lo) == c.lo && (k.hi & c.hi) == c.hi;
+}
+
+// (f, g) applied to one (label, amplitude) pair.
+void apply_monomial(const Monomial& g, Label& k, Amp& a) {
+  if (!controls_set(k, g.ctrl)) return;
+  const bool v = bit_of(k, g.target);
+  if (g.has_phase) a = mul(a, g.m[v ? 1 : 0]);
+  if (g.flip) k = with_bit(k, g.target, !v);
+}
+
+struct Trace {           // per-op record returned to the caller
+  uint64_t nnz_in;
+  int32_t applied;       // 1 applied, 0 skipped
+  int32_t outcome;       // MEASURE: outcome, else -1
+  double p0, p1;         // MEASURE: unnormalised probabilities
+};
+static_assert(sizeof(Trace) == 32, "trace layout");
+
+struct Totals {
+  uint64_t updates;      // sum over applied gates of nnz at input
+  uint64_t u2_applied, u2_skipped, measures, mono_gates;
+  uint64_t peak_nnz, pruned;
+  double pruned_mass;
+};
+
+struct Oracle {
+  unsigned n_qubits;
+  double eps;
+  State psi;
+  Totals tot;
+};
+
+bool drop(const Amp& a, double eps) {
+  return (a.re * a.re + a.im * a.im < eps) || (a.re == 0.0 && a.im == 0.0);
+}
+
+void note_peak(Oracle& o) {
+  if (o.psi.size() > o.tot.peak_nnz) o.tot.peak_nnz = o.psi.size();
+}
+
+// Branching operation, Eq. 2, with the pair rule of Sec. 3.1.
+void apply_branching(Oracle& o, const OpRecord& op) {
+  Amp u[4];
+  matrix_of(op, u);
+  const Label ctrl{op.ctrl_lo, op.ctrl_hi};
+  const unsigned t = op.target;
+  State out;
+  out.reserve(o.psi.size() * 2);
+  const Amp zero{0.0, 0.0};
+  for (const auto& kv : o.psi) {
+    const Label& k = kv.first;
+    if (!controls_set(k, ctrl)) {
+      out.emplace(k, kv.second);
+      continue;
+    }
+    const Label k0 = with_bit(k, t, false), k1 = with_bit(k, t, true);
+    const bool v = bit_of(k, t);
+    auto it_partner = o.psi.find(v ? k0 : k1);    // the one look-up
+    const bool partner = it_partner != o.psi.end();
+    if (!v && partner) continue;                   // the bit-1 label emits the pair
+    const Amp a0 = v ? (partner ? it_partner->second : zero) : kv.second;
+    const Amp a1 = v ? kv.second : zero;
+    out.emplace(k0, add(mul(u[0], a0), mul(u[1], a1)));
+    out.emplace(k1, add(mul(u[2], a0), mul(u[3], a1)));
+  }
+  // T_eps on the whole new state.
+  for (auto it = out.begin(); it != out.end();) {
+    if (drop(it->second, o.eps)) {
+      o.tot.pruned++;
+      o.tot.pruned_mass += it->second.re * it->second.re + it->second.im * it->second.im;
+      it = out.erase(it);
+    } else {
+      ++it;
+    }
+  }
+  o.psi.swap(out);
+}
+
+// Apply a run of phase/permutation gates: per label, all gates in order,
+// then one insertion into the new map (Sec. 3.2).
+void apply_monomial_run(Oracle& o, const std::vector<Monomial>& run) {
+  if (run.empty()) return;
+  State out;
+  out.reserve(o.psi.size());
+  for (const auto& kv : o.psi) {
+    Label k = kv.first;
+    Amp a = kv.second;
+    for (const Monomial& g : run) apply_monomial(g, k, a);
+    out.emplace(k, a);
+  }
+  o.psi.swap(out);
+}
+
+std::vector<std::pair<Label, Amp>> sorted_entries(const State& s) {
+  std::vector<std::pair<Label, Amp>> v(s.begin(), s.end());
+  std::sort(v.begin(), v.end(),
+            [](const std::pair<Label, Amp>& a, const std::pair<Label, Amp>& b) { return a.first < b.first; });
+  return v;
+}
+
+void probabilities(const Oracle& o, unsigned q, double* p0, double* p1) {
+  double s0 = 0.0, s1 = 0.0;
+  for (const auto& e : sorted_entries(o.psi)) {
+    const double p = e.second.re * e.second.re + e.second.im * e.second.im;
+    if (bit_of(e.first, q)) s1 += p; else s0 += p;
+  }
+  *p0 = s0;
+  *p1 = s1;
+}
+
+// Returns the outcome, or -1 if the chosen outcome has zero probability.
+int measure(Oracle& o, unsigned q, double u, int forced, double* p0, double* p1) {
+  probabilities(o, q, p0, p1);
+  const double tot = *p0 + *p1;
+  if (!(tot > 0.0)) return -1;
+  int outcome = forced >= 0 ? forced : (u < *p0 / tot ? 0 : 1);
+  const double po = outcome ? *p1 : *p0;
+  if (!(po > 0.0)) return -1;
+  const double scale = 1.0 / std::sqrt(po);
+  State out;
+  out.reserve(o.psi.size());
+  for (const auto& kv : o.psi)
+    if (bit_of(kv.first, q) == (outcome == 1)) out.emplace(kv.first, Amp{kv.second.re * scale, kv.second.im * scale});
+  o.psi.swap(out);
+  return outcome;
+}
+
+bool op_valid(const Oracle& o, const OpRecord& op) {
+  if (op.target >= o.n_qubits) return false;
+  if (op.kind > kMeasure) return false;
+  if (bit_of(Label{op.ctrl_lo, op.ctrl_hi}, op.target)) return false;
+  if (o.n_qubits < 128) {
+    const Label lim = o.n_qubits >= 64 ? Label{~0ull, o.n_qubits == 64 ? 0ull : ((1ull << (o.n_qubits - 64)) - 1)}
+                                       : Label{(1ull << o.n_qubits) - 1, 0ull};
+    if ((op.ctrl_lo & ~lim.lo) || (op.ctrl_hi & ~lim.hi)) return false;
+  }
+  return true;
+}
+
+}  // namespace
+
+extern "C" {
+
+// Error codes: 0 ok, -1 bad argument, -2 zero-probability measurement outcome.
+void* orc_create(unsigned n_qubits, double eps) {
+  if (n_qubits == 0 || n_qubits > 128) return nullptr;
+  Oracle* o = new Oracle();
+  o->n_qubits = n_qubits;
+  o->eps = eps;
+  o->psi.emplace(Label{0, 0}, Amp{1.0, 0.0});
+  std::memset(&o->tot, 0, sizeof(o->tot));
+  o->tot.peak_nnz = 1;
+  return o;
+}
+
+void orc_destroy(void* h) { delete static_cast<Oracle*>(h); }
+
+int orc_set_basis(void* h, uint64_t lo, uint64_t hi) {
+  Oracle& o = *static_cast<Oracle*>(h);
+  o.psi.clear();
+  o.psi.emplace(Label{lo, hi}, Amp{1.0, 0.0});
+  return 0;
+}
+
+// Replace the state by n (label, amplitude) pairs; amp is interleaved re,im.
+int orc_import(void* h, const uint64_t* lo, const uint64_t* hi, const double* amp, uint64_t n) {
+  Oracle& o = *static_cast<Oracle*>(h);
+  State s;
+  s.reserve(n);
+  for (uint64_t i = 0; i < n; ++i)
+    if (!s.emplace(Label{lo[i], hi[i]}, Amp{amp[2 * i], amp[2 * i + 1]}).second) return -1;
+  o.psi.swap(s);
+  note_peak(o);
+  return 0;
+}
+
+uint64_t orc_nnz(void* h) { return static_cast<Oracle*>(h)->psi.size(); }
+
+// Run ops.  queued != 0 applies maximal runs of phase/permutation gates per
+// label (skipped branching gates do not end a run: they leave nnz unchanged).
+// trace (optional, n entries) and outcomes (optional, one per MEASURE) are
+// filled in order.  Returns 0, -1 (invalid op at index *bad) or -2.
+int orc_run(void* h, const OpRecord* ops, uint64_t n, int queued, Trace* trace, int32_t* outcomes,
+            uint64_t* bad) {
+  Oracle& o = *static_cast<Oracle*>(h);
+  std::vector<Monomial> run;
+  uint64_t n_meas = 0;
+  for (uint64_t i = 0; i < n; ++i) {
+    const OpRecord& op = ops[i];
+    if (!op_valid(o, op)) {
+      apply_monomial_run(o, run);
+      if (bad) *bad = i;
+      return -1;
+    }
+    Trace tr{o.psi.size(), 1, -1, 0.0, 0.0};
+    if (is_monomial(op.kind)) {
+      o.tot.updates += o.psi.size();
+      o.tot.mono_gates++;
+      run.push_back(monomial_of(op));
+      if (!queued) {
+        apply_monomial_run(o, run);
+        run.clear();
+      }
+    } else if (is_branching(op.kind)) {
+      if (op.cap != 0 && 2 * o.psi.size() > op.cap) {
+        tr.applied = 0;
+        o.tot.u2_skipped++;
+      } else {
+        apply_monomial_run(o, run);
+        run.clear();
+        o.tot.updates += o.psi.size();
+        o.tot.u2_applied++;
+        apply_branching(o, op);
+        note_peak(o);
+      }
+    } else {  // measurement flushes the queue
+      apply_monomial_run(o, run);
+      run.clear();
+      o.tot.measures++;
+      const int r = measure(o, op.target, op.param, op.forced, &tr.p0, &tr.p1);
+      if (r < 0) {
+        if (bad) *bad = i;
+        return -2;
+      }
+      tr.outcome = r;
+      if (outcomes) outcomes[n_meas] = r;
+      n_meas++;
+    }
+    if (trace) trace[i] = tr;
+  }
+  apply_monomial_run(o, run);
+  return 0;
+}
+
+// Export sorted ascending by (hi, lo).  Returns nnz; writes min(nnz, cap).
+uint64_t orc_export(void* h, uint64_t* lo, uint64_t* hi, double* amp, uint64_t cap) {
+  Oracle& o = *static_cast<Oracle*>(h);
+  const auto v = sorted_entries(o.psi);
+  for (uint64_t i = 0; i < v.size() && i < cap; ++i) {
+    lo[i] = v[i].first.lo;
+    hi[i] = v[i].first.hi;
+    amp[2 * i] = v[i].second.re;
+    amp[2 * i + 1] = v[i].second.im;
+  }
+  return v.size();
+}
+
+int orc_probabilities(void* h, unsigned q, double* p0, double* p1) {
+  Oracle& o = *static_cast<Oracle*>(h);
+  if (q >= o.n_qubits) return -1;
+  probabilities(o, q, p0, p1);
+  return 0;
+}
+
+void orc_totals(void* h, Totals* t) { *t = static_cast<Oracle*>(h)->tot; }
+
+// Apply phase/permutation ops to independent (label, amplitude) samples, one
+// at a time -- f and g composed per label exactly as in a queued run.  Any
+// non-monomial op is an error (-1).  Used to check full-size runs on samples.
+int orc_monomial_samples(const OpRecord* ops, uint64_t n_ops, uint64_t* lo, uint64_t* hi, double* amp,
+                         uint64_t count) {
+  std::vector<Monomial> run;
+  run.reserve(n_ops);
+  for (uint64_t i = 0; i < n_ops; ++i) {
+    if (!is_monomial(ops[i].kind)) return -1;
+    run.push_back(monomial_of(ops[i]));
+  }
+  for (uint64_t j = 0; j < count; ++j) {
+    Label k{lo[j], hi[j]};
+    Amp a{amp[2 * j], amp[2 * j + 1]};
+    for (const Monomial& g : run) apply_monomial(g, k, a);
+    lo[j] = k.lo;
+    hi[j] = k.hi;
+    amp[2 * j] = a.re;
+    amp[2 * j + 1] = a.im;
+  }
+  return 0;
+}
+
+}  // extern "C"
