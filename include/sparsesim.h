@@ -1,0 +1,212 @@
+/*
+ * sparsesim.h -- C-ABI of the MI355X sparse state-vector simulator.
+ *
+ * Method: Jaques & Haner, "Leveraging state sparsity for more efficient
+ * quantum simulations", arXiv 2105.01533.  A state sum_b alpha_b |b> is kept
+ * as the list of its nonzero (label b, amplitude alpha_b) pairs (Sec. 3);
+ * labels are 128-bit, qubit q is bit q of the label (Sec. 2.1), amplitudes
+ * are FP64 complex.
+ *
+ * Device memory: the state lives in HBM as structure-of-arrays
+ * (key_lo[], key_hi[], amp[] as interleaved re,im doubles), double-buffered
+ * as in Sec. 3.1 (each operation that changes the entry count writes the
+ * other buffer), plus a hash index used by branching gates.  All device work
+ * is issued on the stream given at creation; nothing here creates streams.
+ *
+ * Conventions for every call:
+ *   - return 0 (SIM_OK) on success, a negative SIM_E_* code on failure;
+ *     sim_strerror() names the code, sim_last_error() gives detail;
+ *   - a handle is not thread-safe; calls on one handle must not overlap;
+ *   - host pointers are read or written only during the call;
+ *   - on error the simulated state is unchanged unless stated otherwise.
+ */
+#ifndef SPARSESIM_H
+#define SPARSESIM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define SIM_OK 0
+#define SIM_E_ARG (-1)      /* invalid argument (qubit out of range, bad op, duplicate key...) */
+#define SIM_E_NOMEM (-2)    /* device or host allocation failed, or workspace too small */
+#define SIM_E_CAPACITY (-3) /* the state would exceed the configured capacity */
+#define SIM_E_BUFFER (-4)   /* caller buffer too small (required size reported) */
+#define SIM_E_HIP (-5)      /* a HIP runtime call failed */
+#define SIM_E_STATE (-6)    /* measurement of a zero-probability outcome, or empty state */
+
+/* A basis-state label: qubit q is bit q of lo (q < 64) or bit q-64 of hi. */
+typedef struct sim_key {
+  uint64_t lo, hi;
+} sim_key;
+
+/* FP64 complex amplitude. */
+typedef struct sim_c64 {
+  double re, im;
+} sim_c64;
+
+/* Operation classes (Sec. 3.1: at most one nonzero per matrix row = MONO,
+ * "monomial", i.e. a phase/permutation gate; two nonzeros = U2, "branching"). */
+#define SIM_OP_MONO 0u
+#define SIM_OP_U2 1u
+#define SIM_OP_MEASURE 2u
+
+/*
+ * One operation (120 bytes).
+ *
+ * All ops: the op acts only on labels whose control bits (ctrl) are all set
+ * (Sec. 2.1, controlled gates C^n U); ctrl must not contain the target bit
+ * and every bit of ctrl and target must be < n_qubits.
+ *
+ * SIM_OP_MONO, a phase/permutation gate G(a|b>) = f(b) a |g(b)> (Sec. 3.2):
+ *   on a label with controls set, the amplitude is multiplied by m[v] where v
+ *   is the label's target bit before the gate, then the target bit is flipped
+ *   if flip != 0.  When m[0] and m[1] are both exactly 1+0i no multiply is
+ *   done.  Labels without the controls are unchanged.
+ * SIM_OP_U2, a branching single-qubit gate (Eq. 2): m[0..3] is the row-major
+ *   2x2 matrix U; for each label pair (b with target bit 0, b' = b with the
+ *   bit set) alpha'_b = U00 alpha_b + U01 alpha_b', alpha'_b' = U10 alpha_b +
+ *   U11 alpha_b', absent partners counting as 0.  Afterwards every entry with
+ *   re*re + im*im < eps, or exactly zero, is dropped.  If cap != 0 the op is
+ *   skipped when 2*nnz > cap (nnz before the op).
+ * SIM_OP_MEASURE of qubit `target` (Sec. 2.1, Born rule): P0 and P1 are the
+ *   summed |a|^2 over labels with the qubit 0 / 1; the outcome is `forced`
+ *   if forced is 0 or 1, otherwise 0 iff u < P0/(P0+P1); labels with the
+ *   other value are dropped and the rest scaled by 1/sqrt(P_outcome).
+ */
+typedef struct sim_gate {
+  uint32_t op;
+  uint32_t target;
+  sim_key ctrl;
+  uint32_t flip;
+  int32_t forced;
+  sim_c64 m[4];
+  uint64_t cap;
+  double u;
+  uint64_t reserved;
+} sim_gate;
+
+/*
+ * Standard-gate record (48 bytes), the format of generated circuits.
+ * kind: SIM_K_*; param: rotation angle theta (RZ, RX, RY, PHASE) or the
+ * uniform u in [0,1) for MEASURE; cap and forced as in sim_gate.
+ * Gate matrices are those of Sec. 2.1: H = sqrt(.5)[[1,1],[1,-1]],
+ * S = diag(1,i), Pauli X, Y, Z, R_P(theta) = exp(-i theta P / 2); T =
+ * diag(1, e^{i pi/4}), the adjoints, and PHASE(theta) = diag(1, e^{i theta}).
+ */
+#define SIM_K_X 0u
+#define SIM_K_Y 1u
+#define SIM_K_Z 2u
+#define SIM_K_S 3u
+#define SIM_K_SDG 4u
+#define SIM_K_T 5u
+#define SIM_K_TDG 6u
+#define SIM_K_RZ 7u
+#define SIM_K_PHASE 8u
+#define SIM_K_H 9u
+#define SIM_K_RX 10u
+#define SIM_K_RY 11u
+#define SIM_K_MEASURE 12u
+
+typedef struct sim_op {
+  uint32_t kind;
+  uint32_t target;
+  uint64_t ctrl_lo, ctrl_hi;
+  double param;
+  uint64_t cap;
+  int32_t forced;
+  uint32_t pad;
+} sim_op;
+
+/* Creation parameters. Zero fields take the stated defaults. */
+typedef struct sim_config {
+  uint32_t n_qubits;    /* 1..128 */
+  uint32_t fuse_max;    /* max phase/permutation gates per fused pass (default 65536) */
+  uint64_t capacity;    /* max entries the state may hold, < 2^31 (required) */
+  double eps;           /* prune threshold on |a|^2 after branching gates (0 = drop exact zeros only) */
+  double load_factor;   /* hash index target load, (0, 0.9] (default 0.5) */
+  uint32_t block;       /* threads per block of the fused pass: 64, 128 or 256 (default 256) */
+  uint32_t flags;       /* reserved, must be 0 */
+} sim_config;
+
+/* Counters of one sim_apply_gates call (filled when stats != NULL). */
+typedef struct sim_stats {
+  uint64_t gates_applied;  /* ops consumed, including skipped branching gates */
+  uint64_t updates;        /* sum over applied gates of nnz at the gate's input */
+  uint64_t mono_passes;    /* fused phase/permutation kernel launches */
+  uint64_t u2_applied, u2_skipped, measures;
+  uint64_t host_syncs;     /* host waits for a device-computed nnz */
+  uint64_t peak_nnz;       /* largest entry count reached */
+  uint64_t pruned;         /* entries dropped by the eps rule */
+} sim_stats;
+
+typedef struct sim_t sim_t;
+
+/* Device bytes a state with this configuration uses (both entry buffers,
+ * the hash index and per-entry scratch); the size of a caller workspace. */
+size_t sim_workspace_bytes(const sim_config* cfg);
+
+/* Create a simulator in state |0...0>.  stream: a hipStream_t (NULL = the
+ * null stream).  workspace: device memory of at least sim_workspace_bytes(cfg)
+ * bytes, borrowed (it must outlive the handle), or NULL to let the library
+ * allocate it.  Errors: SIM_E_ARG (config), SIM_E_NOMEM, SIM_E_HIP. */
+int sim_create(const sim_config* cfg, void* stream, void* workspace, size_t ws_bytes, sim_t** out);
+
+/* Free what the library allocated; a borrowed workspace is left alone. */
+int sim_destroy(sim_t* s);
+
+/* Reset to the single basis state k with amplitude 1. */
+int sim_set_basis(sim_t* s, sim_key k);
+
+/* Replace the state by n host (key, amplitude) pairs, copied in.  Duplicate
+ * keys or bits above n_qubits -> SIM_E_ARG; n > capacity -> SIM_E_CAPACITY. */
+int sim_import_state(sim_t* s, const sim_key* keys, const sim_c64* amps, uint64_t n);
+
+/* Convert n standard-gate records into sim_gate ops (host only). */
+int sim_gates_from_ops(const sim_op* ops, size_t n, sim_gate* out);
+
+/*
+ * Apply n ops in order.  Consecutive MONO ops (and skipped U2 ops between
+ * them, which leave nnz unchanged) are fused into passes of at most fuse_max
+ * gates, each label taking all of them in turn (Sec. 3.2).  The host reads a
+ * device-computed nnz only when a cap decision or the capacity check needs it.
+ * outcomes (optional): one int32 per MEASURE op, in order.  stats optional.
+ * Returns when all work is done.  SIM_E_CAPACITY: the state is the state
+ * before the failing op and stats->gates_applied counts the ops before it.
+ * SIM_E_ARG: an invalid op; nothing was applied.
+ */
+int sim_apply_gates(sim_t* s, const sim_gate* gates, size_t n, int32_t* outcomes, sim_stats* stats);
+
+/* sim_gates_from_ops followed by sim_apply_gates. */
+int sim_apply_ops(sim_t* s, const sim_op* ops, size_t n, int32_t* outcomes, sim_stats* stats);
+
+/* Measure one qubit (u, forced as for SIM_OP_MEASURE); writes the outcome
+ * and P1/(P0+P1) before collapse.  Synchronizes. */
+int sim_measure(sim_t* s, uint32_t qubit, double u, int32_t forced, int32_t* outcome, double* p1);
+
+/* Current number of stored entries.  Synchronizes. */
+int sim_nnz(sim_t* s, uint64_t* nnz);
+
+/* Wait for all work issued on the handle's stream. */
+int sim_sync(sim_t* s);
+
+/* Copy the state to caller-owned host arrays of `cap` entries, in storage
+ * order (unsorted).  *nnz receives the entry count; if cap < nnz nothing is
+ * copied and SIM_E_BUFFER is returned.  Synchronizes. */
+int sim_export_state(sim_t* s, sim_key* keys, sim_c64* amps, uint64_t cap, uint64_t* nnz);
+
+/* Device addresses of the current state buffers (key_lo, key_hi, amp) and
+ * the device nnz word, for zero-copy inspection; valid until the next call. */
+int sim_device_state(sim_t* s, uint64_t** key_lo, uint64_t** key_hi, double** amp, uint64_t** d_nnz);
+
+/* Name of an error code / detail of the last error in this thread. */
+const char* sim_strerror(int code);
+const char* sim_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SPARSESIM_H */

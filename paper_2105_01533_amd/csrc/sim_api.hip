@@ -1,0 +1,710 @@
+// Host engine and C-ABI of libsparsesim (see include/sparsesim.h).
+//
+// The engine walks the op list once.  Phase/permutation ops accumulate into a
+// pending run that is launched as one fused pass (Sec. 3.2); a branching op
+// with a cap is decided against the exact entry count, which phase/permutation
+// runs never change, so skipped branching ops do not end a run.  The entry
+// count lives on the device; the host keeps an upper bound and reads the
+// exact value only when a cap decision or the capacity check needs it.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/sparsesim.h"
+#include "sim_internal.h"
+
+using namespace sparsesim;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+int fail(int code, const std::string& msg) {
+  g_last_error = msg;
+  return code;
+}
+
+#define HIP_TRY(expr)                                                                        \
+  do {                                                                                       \
+    hipError_t e_ = (expr);                                                                  \
+    if (e_ != hipSuccess)                                                                    \
+      return fail(SIM_E_HIP, std::string(#expr) + ": " + hipGetErrorString(e_));             \
+  } while (0)
+
+constexpr size_t kAlign = 256;
+size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+
+uint64_t next_pow2(uint64_t x) {
+  uint64_t p = 1;
+  while (p < x) p <<= 1;
+  return p;
+}
+
+uint64_t table_slots(uint64_t n, double lf) {
+  const uint64_t want = (uint64_t)std::ceil((double)(n ? n : 1) / lf) + 1;
+  return std::max<uint64_t>(64, next_pow2(want));
+}
+
+struct Layout {
+  size_t buf_lo[2], buf_hi[2], buf_amp[2];
+  size_t table, partner, tot, cnt1, part, ctl, total;
+  uint64_t slots;
+};
+
+bool config_ok(const sim_config* c, std::string* why) {
+  if (!c) return *why = "null config", false;
+  if (c->n_qubits < 1 || c->n_qubits > 128) return *why = "n_qubits must be in 1..128", false;
+  if (c->capacity < 1 || c->capacity >= (1ull << 31)) return *why = "capacity must be in 1..2^31-1", false;
+  if (!(c->eps >= 0.0) || !std::isfinite(c->eps)) return *why = "eps must be finite and >= 0", false;
+  if (c->load_factor != 0.0 && !(c->load_factor > 0.0 && c->load_factor <= 0.9))
+    return *why = "load_factor must be in (0, 0.9]", false;
+  if (c->block != 0 && c->block != 64 && c->block != 128 && c->block != 256)
+    return *why = "block must be 64, 128 or 256", false;
+  if (c->flags != 0) return *why = "flags must be 0", false;
+  return true;
+}
+
+double lf_of(const sim_config* c) { return c->load_factor > 0.0 ? c->load_factor : 0.5; }
+
+Layout layout_of(const sim_config* c) {
+  Layout L{};
+  const uint64_t cap = c->capacity;
+  const bool wide = c->n_qubits > 64;
+  size_t off = 0;
+  for (int b = 0; b < 2; ++b) {
+    L.buf_lo[b] = off;
+    off += align_up(cap * 8);
+    L.buf_hi[b] = wide ? off : (size_t)-1;
+    if (wide) off += align_up(cap * 8);
+    L.buf_amp[b] = off;
+    off += align_up(cap * 16);
+  }
+  L.slots = table_slots(cap, lf_of(c));
+  L.table = off;
+  off += align_up(L.slots * 8);
+  L.partner = off;
+  off += align_up(cap * 4);
+  L.tot = off;
+  off += align_up(kMaxBlocks * 4);
+  L.cnt1 = off;
+  off += align_up(kMaxBlocks * 4);
+  L.part = off;
+  off += align_up(kMaxBlocks * 16);
+  L.ctl = off;
+  off += align_up(sizeof(Ctl));
+  L.total = off;
+  return L;
+}
+
+template <typename T>
+struct DevVec {            // library-owned growable device array
+  T* p = nullptr;
+  size_t n = 0;
+  hipError_t reserve(size_t want) {
+    if (want <= n) return hipSuccess;
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    n = 0;
+    const size_t m = std::max<size_t>(want, 256);
+    hipError_t e = hipMalloc(&p, m * sizeof(T));
+    if (e == hipSuccess) n = m;
+    return e;
+  }
+  void release() {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    n = 0;
+  }
+};
+
+}  // namespace
+
+struct sim_t {
+  sim_config cfg;
+  hipStream_t stream;
+  bool wide;
+  char* ws;
+  bool ws_owned;
+  Layout L;
+  Buf buf[2];
+  int cur;
+  uint64_t* table;
+  uint32_t* partner;
+  BlockScratch bs;
+  Ctl* ctl;
+  uint64_t* h_pinned;          // [0] nnz readback, [1..] scratch
+  Ctl* h_ctl;                  // pinned mirror of ctl
+  DevVec<MonoDesc> descs;
+  DevVec<MeasRec> recs;
+  DevVec<int32_t> outcomes;
+  std::vector<MonoDesc> h_descs;
+  // host knowledge of the entry count
+  bool nnz_known;
+  uint64_t nnz_exact, nnz_ub;
+  uint64_t last_updates, last_pruned;
+};
+
+namespace {
+
+int block_of(const sim_t* s) { return s->cfg.block ? (int)s->cfg.block : 256; }
+
+int mono_grid(const sim_t* s, uint64_t n) {
+  const uint64_t per = (uint64_t)block_of(s) * 4;
+  const uint64_t g = (n + per - 1) / per;
+  return (int)std::max<uint64_t>(1, std::min<uint64_t>(g, 2048));
+}
+
+int chunk_grid(uint64_t n) {
+  const uint64_t g = (n + 2047) / 2048;
+  return (int)std::max<uint64_t>(1, std::min<uint64_t>(g, kMaxBlocks));
+}
+
+int flat_grid(uint64_t n) {
+  const uint64_t g = (n + 255) / 256;
+  return (int)std::max<uint64_t>(1, std::min<uint64_t>(g, 4096));
+}
+
+uint64_t* d_nnz(sim_t* s, int b) { return &s->ctl->nnz[b]; }
+
+int read_nnz(sim_t* s, uint64_t* out) {
+  HIP_TRY(hipMemcpyAsync(s->h_pinned, d_nnz(s, s->cur), 8, hipMemcpyDeviceToHost, s->stream));
+  HIP_TRY(hipStreamSynchronize(s->stream));
+  *out = s->h_pinned[0];
+  s->nnz_known = true;
+  s->nnz_exact = s->nnz_ub = *out;
+  return SIM_OK;
+}
+
+bool key_in_range(const sim_t* s, uint64_t lo, uint64_t hi) {
+  const unsigned n = s->cfg.n_qubits;
+  if (n >= 128) return true;
+  if (n > 64) return (hi >> (n - 64)) == 0;
+  return hi == 0 && (n == 64 || (lo >> n) == 0);
+}
+
+bool qubit_ok(const sim_t* s, uint32_t q) { return q < s->cfg.n_qubits; }
+
+bool finite_c(const sim_c64& c) { return std::isfinite(c.re) && std::isfinite(c.im); }
+
+int validate(const sim_t* s, const sim_gate& g, size_t i) {
+  char msg[160];
+  if (g.op > SIM_OP_MEASURE) {
+    snprintf(msg, sizeof msg, "op %zu: unknown op class %u", i, g.op);
+    return fail(SIM_E_ARG, msg);
+  }
+  if (!qubit_ok(s, g.target) || !key_in_range(s, g.ctrl.lo, g.ctrl.hi)) {
+    snprintf(msg, sizeof msg, "op %zu: qubit out of range", i);
+    return fail(SIM_E_ARG, msg);
+  }
+  const uint64_t tw = g.target < 64 ? g.ctrl.lo : g.ctrl.hi;
+  if ((tw >> (g.target & 63)) & 1ull) {
+    snprintf(msg, sizeof msg, "op %zu: target is also a control", i);
+    return fail(SIM_E_ARG, msg);
+  }
+  if (g.op == SIM_OP_MEASURE) {
+    if (g.ctrl.lo || g.ctrl.hi) return fail(SIM_E_ARG, "measurement cannot be controlled");
+    if (g.forced < -1 || g.forced > 1) return fail(SIM_E_ARG, "forced must be -1, 0 or 1");
+    if (g.forced < 0 && !(g.u >= 0.0 && g.u < 1.0)) return fail(SIM_E_ARG, "measurement u must be in [0, 1)");
+  } else {
+    const int nm = g.op == SIM_OP_MONO ? 2 : 4;
+    for (int k = 0; k < nm; ++k)
+      if (!finite_c(g.m[k])) return fail(SIM_E_ARG, "non-finite gate coefficient");
+  }
+  return SIM_OK;
+}
+
+MonoDesc mono_desc(const sim_gate& g) {
+  MonoDesc d{};
+  d.ctrl_lo = g.ctrl.lo;
+  d.ctrl_hi = g.ctrl.hi;
+  d.target = g.target;
+  const bool unit = g.m[0].re == 1.0 && g.m[0].im == 0.0 && g.m[1].re == 1.0 && g.m[1].im == 0.0;
+  d.flags = (unit ? 0u : kHasPhase) | (g.flip ? kFlip : 0u);
+  d.m0 = make_double2(g.m[0].re, g.m[0].im);
+  d.m1 = make_double2(g.m[1].re, g.m[1].im);
+  return d;
+}
+
+// Branching op: index, count, scan, (capacity check), write, swap.
+int run_u2(sim_t* s, const sim_gate& g, bool* over) {
+  *over = false;
+  const uint64_t cap = s->cfg.capacity;
+  uint64_t ub = s->nnz_known ? s->nnz_exact : s->nnz_ub;
+  bool check = false;
+  if (2 * ub > cap) {
+    uint64_t n;
+    int rc = read_nnz(s, &n);
+    if (rc) return rc;
+    ub = n;
+    check = 2 * n > cap;
+  }
+  const double lf = lf_of(&s->cfg);
+  const uint64_t slots = std::min<uint64_t>(table_slots(ub, lf), s->L.slots);
+  const int other = s->cur ^ 1;
+  const uint64_t* nnz_in = d_nnz(s, s->cur);
+  U2Desc d{};
+  d.ctrl_lo = g.ctrl.lo;
+  d.ctrl_hi = g.ctrl.hi;
+  d.target = g.target;
+  d.eps = s->cfg.eps;
+  for (int k = 0; k < 4; ++k) d.u[k] = make_double2(g.m[k].re, g.m[k].im);
+  const int G = chunk_grid(ub);
+  launch_fill(s->stream, s->table, kEmptySlot, slots);
+  launch_index_build(s->stream, s->wide, s->buf[s->cur], nnz_in, s->table, slots - 1, flat_grid(ub), 256);
+  launch_u2_count(s->stream, s->wide, s->buf[s->cur], nnz_in, s->table, slots - 1, d, s->partner, s->bs.tot, s->ctl,
+                  G, 256);
+  launch_scan(s->stream, s->bs.tot, G, d_nnz(s, other), s->ctl);
+  HIP_TRY(hipGetLastError());
+  if (check) {
+    HIP_TRY(hipMemcpyAsync(s->h_pinned, d_nnz(s, other), 8, hipMemcpyDeviceToHost, s->stream));
+    HIP_TRY(hipStreamSynchronize(s->stream));
+    if (s->h_pinned[0] > cap) {
+      *over = true;
+      return SIM_OK;
+    }
+  }
+  launch_u2_write(s->stream, s->wide, s->buf[s->cur], s->buf[other], nnz_in, s->partner, s->bs.tot, d, G, 256);
+  HIP_TRY(hipGetLastError());
+  s->cur = other;
+  s->nnz_known = false;
+  s->nnz_ub = std::min<uint64_t>(2 * ub, cap);
+  return SIM_OK;
+}
+
+int run_measure(sim_t* s, uint32_t q, double u, int32_t forced, MeasRec* rec, int32_t* outcome, bool* bad) {
+  *bad = false;
+  const uint64_t ub = s->nnz_known ? s->nnz_exact : s->nnz_ub;
+  const int G = chunk_grid(ub);
+  const int other = s->cur ^ 1;
+  const uint64_t* nnz_in = d_nnz(s, s->cur);
+  launch_measure_reduce(s->stream, s->wide, s->buf[s->cur], nnz_in, q, s->bs, G, 256);
+  launch_measure_decide(s->stream, s->bs, G, nnz_in, d_nnz(s, other), u, forced, rec, outcome, s->ctl);
+  HIP_TRY(hipGetLastError());
+  if (forced >= 0 || ub == 0) {
+    // A forced outcome may have zero probability: decide before touching the state.
+    HIP_TRY(hipMemcpyAsync(s->h_pinned + 1, &rec->outcome, 4, hipMemcpyDeviceToHost, s->stream));
+    HIP_TRY(hipStreamSynchronize(s->stream));
+    int32_t o;
+    std::memcpy(&o, s->h_pinned + 1, 4);
+    if (o < 0) {
+      *bad = true;
+      return SIM_OK;
+    }
+  }
+  launch_measure_write(s->stream, s->wide, s->buf[s->cur], s->buf[other], nnz_in, q, rec, s->bs.tot, G, 256);
+  HIP_TRY(hipGetLastError());
+  s->cur = other;
+  s->nnz_known = false;
+  s->nnz_ub = ub;
+  return SIM_OK;
+}
+
+int read_ctl(sim_t* s) {
+  HIP_TRY(hipMemcpyAsync(s->h_ctl, s->ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s->stream));
+  HIP_TRY(hipStreamSynchronize(s->stream));
+  return SIM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t sim_workspace_bytes(const sim_config* cfg) {
+  std::string why;
+  if (!config_ok(cfg, &why)) return 0;
+  return layout_of(cfg).total;
+}
+
+int sim_create(const sim_config* cfg, void* stream, void* workspace, size_t ws_bytes, sim_t** out) {
+  std::string why;
+  if (!out) return fail(SIM_E_ARG, "null output handle");
+  *out = nullptr;
+  if (!config_ok(cfg, &why)) return fail(SIM_E_ARG, why);
+  sim_t* s = new (std::nothrow) sim_t();
+  if (!s) return fail(SIM_E_NOMEM, "host allocation failed");
+  s->cfg = *cfg;
+  if (!s->cfg.fuse_max) s->cfg.fuse_max = 65536;
+  s->stream = static_cast<hipStream_t>(stream);
+  s->wide = cfg->n_qubits > 64;
+  s->L = layout_of(cfg);
+  if (workspace) {
+    if (ws_bytes < s->L.total) {
+      delete s;
+      return fail(SIM_E_NOMEM, "workspace smaller than sim_workspace_bytes()");
+    }
+    s->ws = static_cast<char*>(workspace);
+    s->ws_owned = false;
+  } else {
+    if (hipMalloc(&s->ws, s->L.total) != hipSuccess) {
+      delete s;
+      return fail(SIM_E_NOMEM, "hipMalloc of the state workspace failed");
+    }
+    s->ws_owned = true;
+  }
+  for (int b = 0; b < 2; ++b) {
+    s->buf[b].key_lo = reinterpret_cast<uint64_t*>(s->ws + s->L.buf_lo[b]);
+    s->buf[b].key_hi = s->wide ? reinterpret_cast<uint64_t*>(s->ws + s->L.buf_hi[b]) : nullptr;
+    s->buf[b].amp = reinterpret_cast<double2*>(s->ws + s->L.buf_amp[b]);
+  }
+  s->table = reinterpret_cast<uint64_t*>(s->ws + s->L.table);
+  s->partner = reinterpret_cast<uint32_t*>(s->ws + s->L.partner);
+  s->bs.tot = reinterpret_cast<uint32_t*>(s->ws + s->L.tot);
+  s->bs.cnt1 = reinterpret_cast<uint32_t*>(s->ws + s->L.cnt1);
+  s->bs.part = reinterpret_cast<double2*>(s->ws + s->L.part);
+  s->ctl = reinterpret_cast<Ctl*>(s->ws + s->L.ctl);
+  if (hipHostMalloc(&s->h_pinned, 64) != hipSuccess || hipHostMalloc(&s->h_ctl, sizeof(Ctl)) != hipSuccess) {
+    sim_destroy(s);
+    return fail(SIM_E_NOMEM, "pinned host allocation failed");
+  }
+  std::memset(s->h_ctl, 0, sizeof(Ctl));
+  if (hipMemcpyAsync(s->ctl, s->h_ctl, sizeof(Ctl), hipMemcpyHostToDevice, s->stream) != hipSuccess) {
+    sim_destroy(s);
+    return fail(SIM_E_HIP, "initialising the control block failed");
+  }
+  s->cur = 0;
+  launch_set_basis(s->stream, s->buf[0], d_nnz(s, 0), 0, 0);
+  if (hipStreamSynchronize(s->stream) != hipSuccess || hipGetLastError() != hipSuccess) {
+    sim_destroy(s);
+    return fail(SIM_E_HIP, "initial state setup failed");
+  }
+  s->nnz_known = true;
+  s->nnz_exact = s->nnz_ub = 1;
+  s->last_updates = s->last_pruned = 0;
+  *out = s;
+  return SIM_OK;
+}
+
+int sim_destroy(sim_t* s) {
+  if (!s) return SIM_OK;
+  if (s->stream || s->ws) (void)hipStreamSynchronize(s->stream);
+  s->descs.release();
+  s->recs.release();
+  s->outcomes.release();
+  if (s->h_pinned) (void)hipHostFree(s->h_pinned);
+  if (s->h_ctl) (void)hipHostFree(s->h_ctl);
+  if (s->ws_owned && s->ws) (void)hipFree(s->ws);
+  delete s;
+  return SIM_OK;
+}
+
+int sim_set_basis(sim_t* s, sim_key k) {
+  if (!s) return fail(SIM_E_ARG, "null handle");
+  if (!key_in_range(s, k.lo, k.hi)) return fail(SIM_E_ARG, "basis key has bits above n_qubits");
+  launch_set_basis(s->stream, s->buf[s->cur], d_nnz(s, s->cur), k.lo, k.hi);
+  HIP_TRY(hipGetLastError());
+  HIP_TRY(hipStreamSynchronize(s->stream));
+  s->nnz_known = true;
+  s->nnz_exact = s->nnz_ub = 1;
+  return SIM_OK;
+}
+
+int sim_import_state(sim_t* s, const sim_key* keys, const sim_c64* amps, uint64_t n) {
+  if (!s) return fail(SIM_E_ARG, "null handle");
+  if (n > s->cfg.capacity) return fail(SIM_E_CAPACITY, "import larger than capacity");
+  if (n && (!keys || !amps)) return fail(SIM_E_ARG, "null import arrays");
+  std::vector<uint64_t> lo(n), hi(n);
+  for (uint64_t i = 0; i < n; ++i) {
+    if (!key_in_range(s, keys[i].lo, keys[i].hi)) return fail(SIM_E_ARG, "import key has bits above n_qubits");
+    lo[i] = keys[i].lo;
+    hi[i] = keys[i].hi;
+  }
+  {
+    std::vector<sim_key> sorted(keys, keys + n);
+    std::sort(sorted.begin(), sorted.end(), [](const sim_key& a, const sim_key& b) {
+      return a.hi != b.hi ? a.hi < b.hi : a.lo < b.lo;
+    });
+    for (uint64_t i = 1; i < n; ++i)
+      if (sorted[i].lo == sorted[i - 1].lo && sorted[i].hi == sorted[i - 1].hi)
+        return fail(SIM_E_ARG, "duplicate key in import");
+  }
+  HIP_TRY(hipStreamSynchronize(s->stream));
+  const Buf& b = s->buf[s->cur];
+  if (n) {
+    HIP_TRY(hipMemcpy(b.key_lo, lo.data(), n * 8, hipMemcpyHostToDevice));
+    if (s->wide) HIP_TRY(hipMemcpy(b.key_hi, hi.data(), n * 8, hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(b.amp, amps, n * 16, hipMemcpyHostToDevice));
+  }
+  s->h_pinned[2] = n;
+  HIP_TRY(hipMemcpyAsync(d_nnz(s, s->cur), s->h_pinned + 2, 8, hipMemcpyHostToDevice, s->stream));
+  HIP_TRY(hipStreamSynchronize(s->stream));
+  s->nnz_known = true;
+  s->nnz_exact = s->nnz_ub = n;
+  return SIM_OK;
+}
+
+int sim_gates_from_ops(const sim_op* ops, size_t n, sim_gate* out) {
+  if (n && (!ops || !out)) return fail(SIM_E_ARG, "null op arrays");
+  const double h = M_SQRT1_2;
+  for (size_t i = 0; i < n; ++i) {
+    const sim_op& o = ops[i];
+    sim_gate g;
+    std::memset(&g, 0, sizeof g);
+    g.target = o.target;
+    g.ctrl.lo = o.ctrl_lo;
+    g.ctrl.hi = o.ctrl_hi;
+    g.cap = o.cap;
+    g.forced = -1;
+    for (int k = 0; k < 4; ++k) g.m[k] = sim_c64{0.0, 0.0};
+    const double c2 = std::cos(0.5 * o.param), s2 = std::sin(0.5 * o.param);
+    g.op = SIM_OP_MONO;
+    g.m[0] = g.m[1] = sim_c64{1.0, 0.0};
+    switch (o.kind) {
+      case SIM_K_X: g.flip = 1; break;
+      case SIM_K_Y: g.flip = 1; g.m[0] = sim_c64{0.0, 1.0}; g.m[1] = sim_c64{0.0, -1.0}; break;
+      case SIM_K_Z: g.m[1] = sim_c64{-1.0, 0.0}; break;
+      case SIM_K_S: g.m[1] = sim_c64{0.0, 1.0}; break;
+      case SIM_K_SDG: g.m[1] = sim_c64{0.0, -1.0}; break;
+      case SIM_K_T: g.m[1] = sim_c64{h, h}; break;
+      case SIM_K_TDG: g.m[1] = sim_c64{h, -h}; break;
+      case SIM_K_RZ: g.m[0] = sim_c64{c2, -s2}; g.m[1] = sim_c64{c2, s2}; break;
+      case SIM_K_PHASE: g.m[1] = sim_c64{std::cos(o.param), std::sin(o.param)}; break;
+      case SIM_K_H:
+        g.op = SIM_OP_U2;
+        g.m[0] = sim_c64{h, 0.0}; g.m[1] = sim_c64{h, 0.0}; g.m[2] = sim_c64{h, 0.0}; g.m[3] = sim_c64{-h, 0.0};
+        break;
+      case SIM_K_RX:
+        g.op = SIM_OP_U2;
+        g.m[0] = sim_c64{c2, 0.0}; g.m[1] = sim_c64{0.0, -s2}; g.m[2] = sim_c64{0.0, -s2}; g.m[3] = sim_c64{c2, 0.0};
+        break;
+      case SIM_K_RY:
+        g.op = SIM_OP_U2;
+        g.m[0] = sim_c64{c2, 0.0}; g.m[1] = sim_c64{-s2, 0.0}; g.m[2] = sim_c64{s2, 0.0}; g.m[3] = sim_c64{c2, 0.0};
+        break;
+      case SIM_K_MEASURE:
+        g.op = SIM_OP_MEASURE;
+        g.m[0] = g.m[1] = sim_c64{0.0, 0.0};
+        g.u = o.param;
+        g.forced = o.forced;
+        g.cap = 0;
+        break;
+      default: {
+        char msg[96];
+        snprintf(msg, sizeof msg, "op %zu: unknown gate kind %u", i, o.kind);
+        return fail(SIM_E_ARG, msg);
+      }
+    }
+    out[i] = g;
+  }
+  return SIM_OK;
+}
+
+int sim_apply_gates(sim_t* s, const sim_gate* gates, size_t n, int32_t* outcomes, sim_stats* stats) {
+  if (!s) return fail(SIM_E_ARG, "null handle");
+  if (n && !gates) return fail(SIM_E_ARG, "null gate array");
+  sim_stats st;
+  std::memset(&st, 0, sizeof st);
+  // Validate everything first: an invalid op applies nothing.
+  size_t n_mono = 0, n_meas = 0;
+  for (size_t i = 0; i < n; ++i) {
+    int rc = validate(s, gates[i], i);
+    if (rc) return rc;
+    if (gates[i].op == SIM_OP_MONO) ++n_mono;
+    if (gates[i].op == SIM_OP_MEASURE) ++n_meas;
+  }
+  // Stage the phase/permutation descriptors in one upload.
+  s->h_descs.resize(n_mono);
+  for (size_t i = 0, k = 0; i < n; ++i)
+    if (gates[i].op == SIM_OP_MONO) s->h_descs[k++] = mono_desc(gates[i]);
+  HIP_TRY(s->descs.reserve(n_mono));
+  HIP_TRY(s->recs.reserve(n_meas));
+  HIP_TRY(s->outcomes.reserve(n_meas));
+  if (n_mono)
+    HIP_TRY(hipMemcpyAsync(s->descs.p, s->h_descs.data(), n_mono * sizeof(MonoDesc), hipMemcpyHostToDevice,
+                           s->stream));
+
+  int result = SIM_OK;
+  size_t run_begin = 0, run_len = 0, mono_seen = 0, meas_seen = 0;
+  auto flush = [&]() -> int {
+    if (!run_len) return SIM_OK;
+    const uint64_t ub = s->nnz_known ? s->nnz_exact : s->nnz_ub;
+    launch_mono(s->stream, s->wide, s->buf[s->cur], d_nnz(s, s->cur), s->descs.p + run_begin, (uint32_t)run_len,
+                &s->ctl->updates, mono_grid(s, ub), block_of(s));
+    HIP_TRY(hipGetLastError());
+    st.mono_passes++;
+    run_begin += run_len;
+    run_len = 0;
+    return SIM_OK;
+  };
+  size_t i = 0;
+  for (; i < n; ++i) {
+    const sim_gate& g = gates[i];
+    if (g.op == SIM_OP_MONO) {
+      if (run_len == 0) run_begin = mono_seen;
+      ++run_len;
+      ++mono_seen;
+      if (run_len >= s->cfg.fuse_max) {
+        int rc = flush();
+        if (rc) return rc;
+      }
+      continue;
+    }
+    if (g.op == SIM_OP_U2) {
+      if (g.cap) {
+        uint64_t nnz = s->nnz_exact;
+        if (!s->nnz_known) {
+          int rc = read_nnz(s, &nnz);
+          if (rc) return rc;
+          st.host_syncs++;
+        }
+        if (2 * nnz > g.cap) {
+          st.u2_skipped++;
+          continue;
+        }
+      }
+      int rc = flush();
+      if (rc) return rc;
+      bool over = false;
+      const bool was_known = s->nnz_known;
+      rc = run_u2(s, g, &over);
+      if (rc) return rc;
+      if (!was_known && s->nnz_known) st.host_syncs++;
+      if (over) {
+        result = fail(SIM_E_CAPACITY, "branching gate would exceed the state capacity");
+        break;
+      }
+      st.u2_applied++;
+      continue;
+    }
+    // measurement
+    int rc = flush();
+    if (rc) return rc;
+    bool bad = false;
+    rc = run_measure(s, g.target, g.u, g.forced, s->recs.p + meas_seen, s->outcomes.p + meas_seen, &bad);
+    if (rc) return rc;
+    if (bad) {
+      result = fail(SIM_E_STATE, "measurement outcome has zero probability");
+      break;
+    }
+    st.measures++;
+    ++meas_seen;
+  }
+  if (result == SIM_OK) {
+    int rc = flush();
+    if (rc) return rc;
+  }
+  if (outcomes && meas_seen)
+    HIP_TRY(hipMemcpyAsync(outcomes, s->outcomes.p, meas_seen * 4, hipMemcpyDeviceToHost, s->stream));
+  int rc = read_ctl(s);
+  if (rc) return rc;
+  if (result == SIM_OK && s->h_ctl->error) {
+    s->h_ctl->error = 0;
+    HIP_TRY(hipMemcpyAsync(&s->ctl->error, &s->h_ctl->error, 4, hipMemcpyHostToDevice, s->stream));
+    HIP_TRY(hipStreamSynchronize(s->stream));
+    result = fail(SIM_E_STATE, "measurement of an empty state");
+  }
+  st.gates_applied = i;
+  st.updates = s->h_ctl->updates - s->last_updates;
+  st.pruned = s->h_ctl->pruned - s->last_pruned;
+  st.peak_nnz = s->h_ctl->peak;
+  s->last_updates = s->h_ctl->updates;
+  s->last_pruned = s->h_ctl->pruned;
+  s->nnz_known = true;
+  s->nnz_exact = s->nnz_ub = s->h_ctl->nnz[s->cur];
+  if (s->nnz_exact > st.peak_nnz) st.peak_nnz = s->nnz_exact;
+  if (stats) *stats = st;
+  return result;
+}
+
+int sim_apply_ops(sim_t* s, const sim_op* ops, size_t n, int32_t* outcomes, sim_stats* stats) {
+  std::vector<sim_gate> g(n);
+  int rc = sim_gates_from_ops(ops, n, g.data());
+  if (rc) return rc;
+  return sim_apply_gates(s, g.data(), n, outcomes, stats);
+}
+
+int sim_measure(sim_t* s, uint32_t qubit, double u, int32_t forced, int32_t* outcome, double* p1) {
+  if (!s) return fail(SIM_E_ARG, "null handle");
+  sim_gate g;
+  std::memset(&g, 0, sizeof g);
+  g.op = SIM_OP_MEASURE;
+  g.target = qubit;
+  g.u = u;
+  g.forced = forced;
+  int rc = validate(s, g, 0);
+  if (rc) return rc;
+  HIP_TRY(s->recs.reserve(1));
+  HIP_TRY(s->outcomes.reserve(1));
+  bool bad = false;
+  rc = run_measure(s, qubit, u, forced, s->recs.p, s->outcomes.p, &bad);
+  if (rc) return rc;
+  MeasRec rec;
+  HIP_TRY(hipMemcpyAsync(s->h_pinned + 4, s->recs.p, sizeof(MeasRec), hipMemcpyDeviceToHost, s->stream));
+  rc = read_ctl(s);
+  if (rc) return rc;
+  std::memcpy(&rec, s->h_pinned + 4, sizeof rec);
+  s->nnz_known = true;
+  s->nnz_exact = s->nnz_ub = s->h_ctl->nnz[s->cur];
+  if (bad || rec.outcome < 0) {
+    if (s->h_ctl->error) {
+      s->h_ctl->error = 0;
+      HIP_TRY(hipMemcpyAsync(&s->ctl->error, &s->h_ctl->error, 4, hipMemcpyHostToDevice, s->stream));
+      HIP_TRY(hipStreamSynchronize(s->stream));
+    }
+    return fail(SIM_E_STATE, "measurement outcome has zero probability or the state is empty");
+  }
+  if (outcome) *outcome = rec.outcome;
+  if (p1) *p1 = rec.p1 / (rec.p0 + rec.p1);
+  return SIM_OK;
+}
+
+int sim_nnz(sim_t* s, uint64_t* nnz) {
+  if (!s || !nnz) return fail(SIM_E_ARG, "null argument");
+  return read_nnz(s, nnz);
+}
+
+int sim_sync(sim_t* s) {
+  if (!s) return fail(SIM_E_ARG, "null handle");
+  HIP_TRY(hipStreamSynchronize(s->stream));
+  return SIM_OK;
+}
+
+int sim_export_state(sim_t* s, sim_key* keys, sim_c64* amps, uint64_t cap, uint64_t* nnz) {
+  if (!s || !nnz) return fail(SIM_E_ARG, "null argument");
+  uint64_t n;
+  int rc = read_nnz(s, &n);
+  if (rc) return rc;
+  *nnz = n;
+  if (cap < n) return fail(SIM_E_BUFFER, "export buffer smaller than nnz");
+  if (!n) return SIM_OK;
+  if (!keys || !amps) return fail(SIM_E_ARG, "null export arrays");
+  std::vector<uint64_t> lo(n), hi(n, 0);
+  const Buf& b = s->buf[s->cur];
+  HIP_TRY(hipMemcpy(lo.data(), b.key_lo, n * 8, hipMemcpyDeviceToHost));
+  if (s->wide) HIP_TRY(hipMemcpy(hi.data(), b.key_hi, n * 8, hipMemcpyDeviceToHost));
+  HIP_TRY(hipMemcpy(amps, b.amp, n * 16, hipMemcpyDeviceToHost));
+  for (uint64_t i = 0; i < n; ++i) keys[i] = sim_key{lo[i], hi[i]};
+  return SIM_OK;
+}
+
+int sim_device_state(sim_t* s, uint64_t** key_lo, uint64_t** key_hi, double** amp, uint64_t** dn) {
+  if (!s) return fail(SIM_E_ARG, "null handle");
+  const Buf& b = s->buf[s->cur];
+  if (key_lo) *key_lo = b.key_lo;
+  if (key_hi) *key_hi = b.key_hi;
+  if (amp) *amp = reinterpret_cast<double*>(b.amp);
+  if (dn) *dn = d_nnz(s, s->cur);
+  return SIM_OK;
+}
+
+const char* sim_strerror(int code) {
+  switch (code) {
+    case SIM_OK: return "ok";
+    case SIM_E_ARG: return "invalid argument";
+    case SIM_E_NOMEM: return "out of memory";
+    case SIM_E_CAPACITY: return "state capacity exceeded";
+    case SIM_E_BUFFER: return "buffer too small";
+    case SIM_E_HIP: return "HIP runtime error";
+    case SIM_E_STATE: return "invalid state for the operation";
+    default: return "unknown error";
+  }
+}
+
+const char* sim_last_error(void) { return g_last_error.c_str(); }
+
+}  // extern "C"

@@ -1,0 +1,83 @@
+// Internal declarations shared by the HIP kernels and the host engine of
+// libsparsesim (not part of the public C-ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace sparsesim {
+
+constexpr uint64_t kEmptySlot = ~0ull;   // hash index: free slot
+constexpr uint32_t kNoPartner = ~0u;     // partner look-up miss
+constexpr int kMaxBlocks = 8192;         // blocks of the chunked (ordered) kernels
+
+// One state buffer (structure of arrays).  key_hi is null for states of at
+// most 64 qubits, whose labels fit in key_lo.
+struct Buf {
+  uint64_t* key_lo;
+  uint64_t* key_hi;
+  double2* amp;
+};
+
+// Fused phase/permutation gate, read wave-uniformly through the scalar cache.
+struct MonoDesc {
+  uint64_t ctrl_lo, ctrl_hi;
+  uint32_t target;
+  uint32_t flags;              // kHasPhase | kFlip
+  uint32_t pad0, pad1;
+  double2 m0, m1;              // factor for target bit 0 / 1 (before the flip)
+};
+static_assert(sizeof(MonoDesc) == 64, "MonoDesc is 64 bytes");
+constexpr uint32_t kHasPhase = 1u, kFlip = 2u;
+
+// Branching 2x2 gate (Eq. 2), passed by value.
+struct U2Desc {
+  uint64_t ctrl_lo, ctrl_hi;
+  uint32_t target, pad;
+  double eps;
+  double2 u[4];                // row-major
+};
+
+// Device control block.
+struct Ctl {
+  uint64_t nnz[2];             // entries in buffer 0 / 1
+  uint64_t updates;            // sum over applied gates of nnz at input
+  uint64_t peak;
+  uint64_t pruned;
+  uint32_t error;              // nonzero: a measurement had no valid outcome
+  uint32_t pad;
+};
+
+// Per-measurement record written by the decide kernel.
+struct MeasRec {
+  double p0, p1, scale;
+  int32_t outcome, pad;
+};
+
+// Scratch of the chunked kernels, kMaxBlocks entries each.
+struct BlockScratch {
+  uint32_t* tot;               // per-block emitted counts, scanned in place to offsets
+  uint32_t* cnt1;              // measurement: per-block count of labels with the qubit set
+  double2* part;               // measurement: per-block (P0, P1)
+};
+
+// ---- launchers (sim_kernels.hip) -------------------------------------------
+void launch_set_basis(hipStream_t st, Buf b, uint64_t* nnz, uint64_t lo, uint64_t hi);
+void launch_mono(hipStream_t st, bool wide, Buf b, const uint64_t* nnz, const MonoDesc* g, uint32_t ng,
+                 uint64_t* updates, int grid, int block);
+void launch_fill(hipStream_t st, uint64_t* p, uint64_t v, uint64_t n);
+void launch_index_build(hipStream_t st, bool wide, Buf b, const uint64_t* nnz, uint64_t* table, uint64_t mask,
+                        int grid, int block);
+void launch_u2_count(hipStream_t st, bool wide, Buf b, const uint64_t* nnz, const uint64_t* table, uint64_t mask,
+                     const U2Desc& d, uint32_t* partner, uint32_t* tot, Ctl* ctl, int grid, int block);
+void launch_scan(hipStream_t st, uint32_t* tot, int nblocks, uint64_t* nnz_out, Ctl* ctl);
+void launch_u2_write(hipStream_t st, bool wide, Buf in, Buf out, const uint64_t* nnz, const uint32_t* partner,
+                     const uint32_t* off, const U2Desc& d, int grid, int block);
+void launch_measure_reduce(hipStream_t st, bool wide, Buf b, const uint64_t* nnz, uint32_t q, BlockScratch s,
+                           int grid, int block);
+void launch_measure_decide(hipStream_t st, BlockScratch s, int nblocks, const uint64_t* nnz_in, uint64_t* nnz_out,
+                           double u, int32_t forced, MeasRec* rec, int32_t* outcome, Ctl* ctl);
+void launch_measure_write(hipStream_t st, bool wide, Buf in, Buf out, const uint64_t* nnz, uint32_t q,
+                          const MeasRec* rec, const uint32_t* off, int grid, int block);
+
+}  // namespace sparsesim

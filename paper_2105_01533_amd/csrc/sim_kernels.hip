@@ -1,0 +1,572 @@
+// HIP kernels of libsparsesim for gfx950 (wave64).
+//
+// The state is a structure-of-arrays list of (label, amplitude) pairs.  Every
+// kernel reads the live entry count from device memory, so the host never has
+// to know it to launch work.  Kernels that change the entry count (branching
+// gates, measurement) are "chunked": block b owns the contiguous entry range
+// [b*chunk, (b+1)*chunk) with chunk = ceil(nnz / gridDim.x), counts what it
+// will emit, a one-block scan turns the counts into output offsets, and the
+// write kernel emits in entry order.  Output order is therefore a fixed
+// function of the input order: runs are deterministic and no floating-point
+// value is ever accumulated with atomics.
+//
+// Arithmetic is fixed so that results match a plain sequential evaluation:
+// complex products are (a.re*b.re - a.im*b.im, a.re*b.im + a.im*b.re), sums of
+// two products are evaluated left to right, |a|^2 = re*re + im*im, and the
+// library is compiled with -ffp-contract=off.
+#include "sim_internal.h"
+
+namespace sparsesim {
+namespace {
+
+__device__ __forceinline__ double2 cmul(double2 a, double2 b) {
+  return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+
+__device__ __forceinline__ double2 cadd(double2 a, double2 b) { return make_double2(a.x + b.x, a.y + b.y); }
+
+// T_eps: an entry survives iff |a|^2 >= eps and it is not exactly zero.
+__device__ __forceinline__ bool survives(double2 a, double eps) {
+  return !((a.x * a.x + a.y * a.y < eps) || (a.x == 0.0 && a.y == 0.0));
+}
+
+// 64-bit finalizer of MurmurHash3 (Appleby), applied to a 128-bit label.
+__device__ __forceinline__ uint64_t hash_label(uint64_t lo, uint64_t hi) {
+  uint64_t k = lo + hi * 0x9E3779B97F4A7C15ull;
+  k ^= k >> 33;
+  k *= 0xff51afd7ed558ccdull;
+  k ^= k >> 33;
+  k *= 0xc4ceb9fe1a85ec53ull;
+  k ^= k >> 33;
+  return k;
+}
+
+__device__ __forceinline__ void chunk_range(uint64_t n, uint64_t& begin, uint64_t& end) {
+  const uint64_t chunk = (n + gridDim.x - 1) / gridDim.x;
+  begin = (uint64_t)blockIdx.x * chunk;
+  end = begin + chunk < n ? begin + chunk : n;
+  if (begin > end) begin = end;
+}
+
+// Exclusive prefix over the block of per-thread counts e in {0,1,2}, in
+// thread order.  Returns the thread's offset; *total gets the block sum.
+// Every thread of the block must call it.
+__device__ __forceinline__ uint32_t block_prefix012(uint32_t e, uint32_t* s_wave, uint32_t* total) {
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  const uint64_t b1 = __ballot(e >= 1), b2 = __ballot(e >= 2);
+  const uint64_t lt = lane == 0 ? 0ull : (~0ull >> (64 - lane));
+  const uint32_t pre = __popcll(b1 & lt) + __popcll(b2 & lt);
+  if (lane == 0) s_wave[wid] = __popcll(b1) + __popcll(b2);
+  __syncthreads();
+  uint32_t woff = 0, tot = 0;
+  for (int w = 0; w < nw; ++w) {
+    const uint32_t x = s_wave[w];
+    woff += w < wid ? x : 0u;
+    tot += x;
+  }
+  __syncthreads();
+  *total = tot;
+  return woff + pre;
+}
+
+// Sum over the block in a fixed tree order (deterministic).
+template <typename T>
+__device__ __forceinline__ T block_sum(T v, T* sh) {
+  sh[threadIdx.x] = v;
+  __syncthreads();
+  for (unsigned s = blockDim.x >> 1; s > 0; s >>= 1) {
+    if (threadIdx.x < s) sh[threadIdx.x] = sh[threadIdx.x] + sh[threadIdx.x + s];
+    __syncthreads();
+  }
+  const T r = sh[0];
+  __syncthreads();
+  return r;
+}
+
+__device__ __forceinline__ double2 operator+(double2 a, double2 b) { return cadd(a, b); }
+
+// ---------------------------------------------------------------------------
+__global__ void k_set_basis(Buf b, uint64_t* nnz, uint64_t lo, uint64_t hi) {
+  b.key_lo[0] = lo;
+  if (b.key_hi) b.key_hi[0] = hi;
+  b.amp[0] = make_double2(1.0, 0.0);
+  *nnz = 1;
+}
+
+__global__ void k_fill(uint64_t* __restrict__ p, uint64_t v, uint64_t n) {
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x)
+    p[i] = v;
+}
+
+// ---------------------------------------------------------------------------
+// Fused phase/permutation pass (Sec. 3.2): each label takes every gate of the
+// run in order, G_n o ... o G_1, entirely in registers; one read and one
+// write of the entry per run.  Gate descriptors are wave-uniform.
+template <bool WIDE, int ITEMS>
+__global__ __launch_bounds__(256) void k_mono(Buf b, const uint64_t* __restrict__ nnz_p,
+                                              const MonoDesc* __restrict__ g, uint32_t ng,
+                                              unsigned long long* updates) {
+  const uint64_t n = *nnz_p;
+  if (blockIdx.x == 0 && threadIdx.x == 0) atomicAdd(updates, (unsigned long long)(n * ng));
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x * ITEMS;
+  for (uint64_t base = (uint64_t)blockIdx.x * blockDim.x * ITEMS; base < n; base += stride) {
+    uint64_t lo[ITEMS], hi[ITEMS];
+    double2 a[ITEMS];
+#pragma unroll
+    for (int i = 0; i < ITEMS; ++i) {
+      const uint64_t idx = base + (uint64_t)i * blockDim.x + threadIdx.x;
+      const bool ok = idx < n;
+      lo[i] = ok ? b.key_lo[idx] : 0ull;
+      hi[i] = (WIDE && ok) ? b.key_hi[idx] : 0ull;
+      a[i] = ok ? b.amp[idx] : make_double2(0.0, 0.0);
+    }
+    for (uint32_t j = 0; j < ng; ++j) {
+      const MonoDesc d = g[j];
+      const uint32_t t = d.target;
+      const bool thi = WIDE && t >= 64;
+      const uint64_t tbit = 1ull << (t & 63);
+#pragma unroll
+      for (int i = 0; i < ITEMS; ++i) {
+        bool c = (lo[i] & d.ctrl_lo) == d.ctrl_lo;
+        if (WIDE) c = c && ((hi[i] & d.ctrl_hi) == d.ctrl_hi);
+        const uint64_t w = thi ? hi[i] : lo[i];
+        if (d.flags & kHasPhase) {
+          const double2 m = (w & tbit) ? d.m1 : d.m0;
+          const double2 r = cmul(a[i], m);
+          a[i] = c ? r : a[i];
+        }
+        if (d.flags & kFlip) {
+          const uint64_t f = c ? tbit : 0ull;
+          if (thi)
+            hi[i] ^= f;
+          else
+            lo[i] ^= f;
+        }
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < ITEMS; ++i) {
+      const uint64_t idx = base + (uint64_t)i * blockDim.x + threadIdx.x;
+      if (idx < n) {
+        b.key_lo[idx] = lo[i];
+        if (WIDE) b.key_hi[idx] = hi[i];
+        b.amp[idx] = a[i];
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Hash index: open addressing with linear probing over a power-of-two table
+// of 64-bit slots (fingerprint << 32 | entry index), claimed with 64-bit CAS.
+// Labels are unique, so an insert never meets its own label.
+template <bool WIDE>
+__global__ __launch_bounds__(256) void k_index_build(Buf b, const uint64_t* __restrict__ nnz_p,
+                                                     unsigned long long* table, uint64_t mask) {
+  const uint64_t n = *nnz_p;
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x) {
+    const uint64_t lo = b.key_lo[i];
+    const uint64_t hi = WIDE ? b.key_hi[i] : 0ull;
+    const uint64_t h = hash_label(lo, hi);
+    const unsigned long long val = ((h >> 32) << 32) | i;
+    uint64_t slot = h & mask;
+    for (uint64_t p = 0; p <= mask; ++p) {
+      if (atomicCAS(&table[slot], (unsigned long long)kEmptySlot, val) == kEmptySlot) break;
+      slot = (slot + 1) & mask;
+    }
+  }
+}
+
+template <bool WIDE>
+__device__ __forceinline__ uint32_t find_label(const Buf& b, const uint64_t* __restrict__ table, uint64_t mask,
+                                               uint64_t lo, uint64_t hi) {
+  const uint64_t h = hash_label(lo, hi);
+  const uint32_t fp = (uint32_t)(h >> 32);
+  uint64_t slot = h & mask;
+  for (uint64_t p = 0; p <= mask; ++p) {
+    const uint64_t s = table[slot];
+    if (s == kEmptySlot) return kNoPartner;
+    if ((uint32_t)(s >> 32) == fp) {
+      const uint32_t j = (uint32_t)s;
+      if (b.key_lo[j] == lo && (!WIDE || b.key_hi[j] == hi)) return j;
+    }
+    slot = (slot + 1) & mask;
+  }
+  return kNoPartner;
+}
+
+// Branching gate outputs of entry i, given its partner index j (Eq. 2 with the
+// pair rule of Sec. 3.1).  mode: 0 = label outside the controls (passes
+// through), 1 = the label emits the pair, 2 = its partner emits (nothing here).
+struct U2Out {
+  int mode;
+  double2 o0, o1;   // mode 1: amplitudes of the bit-0 and bit-1 labels; mode 0: o0 = a
+};
+
+template <bool WIDE>
+__device__ __forceinline__ U2Out u2_eval(const Buf& b, const U2Desc& d, uint64_t lo, uint64_t hi, double2 a,
+                                         uint32_t j) {
+  U2Out r;
+  bool c = (lo & d.ctrl_lo) == d.ctrl_lo;
+  if (WIDE) c = c && ((hi & d.ctrl_hi) == d.ctrl_hi);
+  if (!c) {
+    r.mode = 0;
+    r.o0 = a;
+    r.o1 = a;
+    return r;
+  }
+  const uint64_t w = (WIDE && d.target >= 64) ? hi : lo;
+  const bool v = (w >> (d.target & 63)) & 1ull;
+  if (!v && j != kNoPartner) {
+    r.mode = 2;
+    r.o0 = r.o1 = a;
+    return r;
+  }
+  const double2 zero = make_double2(0.0, 0.0);
+  const double2 a0 = v ? (j != kNoPartner ? b.amp[j] : zero) : a;
+  const double2 a1 = v ? a : zero;
+  r.mode = 1;
+  r.o0 = cadd(cmul(d.u[0], a0), cmul(d.u[1], a1));
+  r.o1 = cadd(cmul(d.u[2], a0), cmul(d.u[3], a1));
+  return r;
+}
+
+template <bool WIDE>
+__global__ __launch_bounds__(256) void k_u2_count(Buf b, const uint64_t* __restrict__ nnz_p,
+                                                  const uint64_t* __restrict__ table, uint64_t mask, U2Desc d,
+                                                  uint32_t* __restrict__ partner, uint32_t* __restrict__ tot,
+                                                  Ctl* ctl) {
+  __shared__ uint32_t sh[256];
+  const uint64_t n = *nnz_p;
+  uint64_t begin, end;
+  chunk_range(n, begin, end);
+  uint32_t emit = 0, dropped = 0;
+  const uint64_t tbit = 1ull << (d.target & 63);
+  const bool thi = WIDE && d.target >= 64;
+  for (uint64_t i = begin + threadIdx.x; i < end; i += blockDim.x) {
+    const uint64_t lo = b.key_lo[i];
+    const uint64_t hi = WIDE ? b.key_hi[i] : 0ull;
+    bool c = (lo & d.ctrl_lo) == d.ctrl_lo;
+    if (WIDE) c = c && ((hi & d.ctrl_hi) == d.ctrl_hi);
+    uint32_t j = kNoPartner;
+    if (c) j = find_label<WIDE>(b, table, mask, thi ? lo : (lo ^ tbit), thi ? (hi ^ tbit) : hi);
+    partner[i] = j;
+    const U2Out r = u2_eval<WIDE>(b, d, lo, hi, b.amp[i], j);
+    if (r.mode == 0) {
+      const uint32_t k = survives(r.o0, d.eps) ? 1u : 0u;
+      emit += k;
+      dropped += 1u - k;
+    } else if (r.mode == 1) {
+      const uint32_t k = (survives(r.o0, d.eps) ? 1u : 0u) + (survives(r.o1, d.eps) ? 1u : 0u);
+      emit += k;
+      dropped += 2u - k;
+    }
+  }
+  emit = block_sum(emit, sh);
+  dropped = block_sum(dropped, sh);
+  if (threadIdx.x == 0) {
+    tot[blockIdx.x] = emit;
+    if (dropped) atomicAdd((unsigned long long*)&ctl->pruned, (unsigned long long)dropped);
+    if (blockIdx.x == 0) atomicAdd((unsigned long long*)&ctl->updates, (unsigned long long)n);
+  }
+}
+
+// One block: exclusive scan of per-block counts in place; the total becomes
+// the entry count of the output buffer.
+__global__ __launch_bounds__(1024) void k_scan(uint32_t* __restrict__ tot, int nb, uint64_t* nnz_out, Ctl* ctl) {
+  __shared__ uint32_t sh[1024];
+  const int per = (nb + blockDim.x - 1) / blockDim.x;
+  const int first = threadIdx.x * per;
+  uint32_t s = 0;
+  for (int k = 0; k < per; ++k)
+    if (first + k < nb) s += tot[first + k];
+  sh[threadIdx.x] = s;
+  __syncthreads();
+  // Hillis-Steele inclusive scan over thread sums.
+  for (unsigned off = 1; off < blockDim.x; off <<= 1) {
+    const uint32_t x = threadIdx.x >= off ? sh[threadIdx.x - off] : 0u;
+    __syncthreads();
+    sh[threadIdx.x] += x;
+    __syncthreads();
+  }
+  uint32_t run = sh[threadIdx.x] - s;
+  for (int k = 0; k < per; ++k) {
+    if (first + k < nb) {
+      const uint32_t x = tot[first + k];
+      tot[first + k] = run;
+      run += x;
+    }
+  }
+  if (threadIdx.x == blockDim.x - 1) {
+    const uint64_t total = sh[threadIdx.x];
+    *nnz_out = total;
+    if (total > ctl->peak) ctl->peak = total;
+  }
+}
+
+template <bool WIDE>
+__global__ __launch_bounds__(256) void k_u2_write(Buf in, Buf out, const uint64_t* __restrict__ nnz_p,
+                                                  const uint32_t* __restrict__ partner,
+                                                  const uint32_t* __restrict__ off, U2Desc d) {
+  __shared__ uint32_t s_wave[16];
+  const uint64_t n = *nnz_p;
+  uint64_t begin, end;
+  chunk_range(n, begin, end);
+  uint64_t base = off[blockIdx.x];
+  const uint64_t tbit = 1ull << (d.target & 63);
+  const bool thi = WIDE && d.target >= 64;
+  for (uint64_t tile = begin; tile < end; tile += blockDim.x) {
+    const uint64_t i = tile + threadIdx.x;
+    uint32_t e = 0;
+    bool k0 = false, k1 = false;
+    U2Out r;
+    uint64_t lo = 0, hi = 0;
+    r.mode = 2;
+    if (i < end) {
+      lo = in.key_lo[i];
+      hi = WIDE ? in.key_hi[i] : 0ull;
+      r = u2_eval<WIDE>(in, d, lo, hi, in.amp[i], partner[i]);
+      if (r.mode == 0) {
+        k0 = survives(r.o0, d.eps);
+      } else if (r.mode == 1) {
+        k0 = survives(r.o0, d.eps);
+        k1 = survives(r.o1, d.eps);
+      }
+      e = (k0 ? 1u : 0u) + (k1 ? 1u : 0u);
+    }
+    uint32_t tile_total;
+    uint64_t pos = base + block_prefix012(e, s_wave, &tile_total);
+    if (r.mode == 0) {
+      if (k0) {
+        out.key_lo[pos] = lo;
+        if (WIDE) out.key_hi[pos] = hi;
+        out.amp[pos] = r.o0;
+      }
+    } else if (r.mode == 1) {
+      const uint64_t lo0 = thi ? lo : (lo & ~tbit), hi0 = thi ? (hi & ~tbit) : hi;
+      if (k0) {
+        out.key_lo[pos] = lo0;
+        if (WIDE) out.key_hi[pos] = hi0;
+        out.amp[pos] = r.o0;
+        ++pos;
+      }
+      if (k1) {
+        out.key_lo[pos] = thi ? lo : (lo | tbit);
+        if (WIDE) out.key_hi[pos] = thi ? (hi | tbit) : hi;
+        out.amp[pos] = r.o1;
+      }
+    }
+    base += tile_total;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Measurement (Born rule): per-block sums of |a|^2 split by the measured bit,
+// a one-block decision, then an ordered compaction that scales the survivors.
+template <bool WIDE>
+__global__ __launch_bounds__(256) void k_measure_reduce(Buf b, const uint64_t* __restrict__ nnz_p, uint32_t q,
+                                                        double2* __restrict__ part, uint32_t* __restrict__ cnt1) {
+  __shared__ double2 shd[256];
+  __shared__ uint32_t shu[256];
+  const uint64_t n = *nnz_p;
+  uint64_t begin, end;
+  chunk_range(n, begin, end);
+  double p0 = 0.0, p1 = 0.0;
+  uint32_t c1 = 0;
+  const bool qhi = WIDE && q >= 64;
+  for (uint64_t i = begin + threadIdx.x; i < end; i += blockDim.x) {
+    const uint64_t w = qhi ? b.key_hi[i] : b.key_lo[i];
+    const double2 a = b.amp[i];
+    const double p = a.x * a.x + a.y * a.y;
+    if ((w >> (q & 63)) & 1ull) {
+      p1 += p;
+      ++c1;
+    } else {
+      p0 += p;
+    }
+  }
+  const double2 s = block_sum(make_double2(p0, p1), shd);
+  const uint32_t c = block_sum(c1, shu);
+  if (threadIdx.x == 0) {
+    part[blockIdx.x] = s;
+    cnt1[blockIdx.x] = c;
+  }
+}
+
+__global__ __launch_bounds__(1024) void k_measure_decide(const double2* __restrict__ part,
+                                                         const uint32_t* __restrict__ cnt1,
+                                                         uint32_t* __restrict__ off, int nb,
+                                                         const uint64_t* __restrict__ nnz_in, uint64_t* nnz_out,
+                                                         double u, int32_t forced, MeasRec* rec, int32_t* outcome,
+                                                         Ctl* ctl) {
+  __shared__ double2 shd[1024];
+  __shared__ uint32_t shu[1024];
+  __shared__ int s_o;
+  double2 acc = make_double2(0.0, 0.0);
+  for (int k = threadIdx.x; k < nb; k += blockDim.x) acc = cadd(acc, part[k]);
+  const double2 P = block_sum(acc, shd);
+  if (threadIdx.x == 0) {
+    const double tot = P.x + P.y;
+    int o = forced >= 0 ? forced : (u < P.x / tot ? 0 : 1);
+    const double po = o ? P.y : P.x;
+    double scale = 1.0 / sqrt(po);
+    if (!(tot > 0.0) || !(po > 0.0)) {
+      atomicOr(&ctl->error, 1u);
+      o = -1;
+      scale = 0.0;
+    }
+    rec->p0 = P.x;
+    rec->p1 = P.y;
+    rec->scale = scale;
+    rec->outcome = o;
+    *outcome = o;
+    s_o = o;
+  }
+  __syncthreads();
+  const int o = s_o;
+  // Output counts per block for the chosen outcome, then exclusive scan.
+  const uint64_t n = *nnz_in;
+  const uint64_t chunk = (n + nb - 1) / nb;
+  const int per = (nb + blockDim.x - 1) / blockDim.x;
+  const int first = threadIdx.x * per;
+  uint32_t s = 0;
+  for (int k = 0; k < per; ++k) {
+    const int bidx = first + k;
+    if (bidx < nb) {
+      uint64_t bb = (uint64_t)bidx * chunk, be = bb + chunk < n ? bb + chunk : n;
+      if (bb > be) bb = be;
+      const uint32_t len = (uint32_t)(be - bb);
+      s += o == 1 ? cnt1[bidx] : (o == 0 ? len - cnt1[bidx] : 0u);
+    }
+  }
+  shu[threadIdx.x] = s;
+  __syncthreads();
+  for (unsigned d = 1; d < blockDim.x; d <<= 1) {
+    const uint32_t x = threadIdx.x >= d ? shu[threadIdx.x - d] : 0u;
+    __syncthreads();
+    shu[threadIdx.x] += x;
+    __syncthreads();
+  }
+  uint32_t run = shu[threadIdx.x] - s;
+  for (int k = 0; k < per; ++k) {
+    const int bidx = first + k;
+    if (bidx < nb) {
+      uint64_t bb = (uint64_t)bidx * chunk, be = bb + chunk < n ? bb + chunk : n;
+      if (bb > be) bb = be;
+      const uint32_t len = (uint32_t)(be - bb);
+      off[bidx] = run;
+      run += o == 1 ? cnt1[bidx] : (o == 0 ? len - cnt1[bidx] : 0u);
+    }
+  }
+  if (threadIdx.x == blockDim.x - 1) *nnz_out = shu[threadIdx.x];
+}
+
+template <bool WIDE>
+__global__ __launch_bounds__(256) void k_measure_write(Buf in, Buf out, const uint64_t* __restrict__ nnz_p,
+                                                       uint32_t q, const MeasRec* __restrict__ rec,
+                                                       const uint32_t* __restrict__ off) {
+  __shared__ uint32_t s_wave[16];
+  const uint64_t n = *nnz_p;
+  uint64_t begin, end;
+  chunk_range(n, begin, end);
+  const int o = rec->outcome;
+  const double scale = rec->scale;
+  uint64_t base = off[blockIdx.x];
+  const bool qhi = WIDE && q >= 64;
+  for (uint64_t tile = begin; tile < end; tile += blockDim.x) {
+    const uint64_t i = tile + threadIdx.x;
+    bool keep = false;
+    uint64_t lo = 0, hi = 0;
+    if (i < end && o >= 0) {
+      lo = in.key_lo[i];
+      hi = WIDE ? in.key_hi[i] : 0ull;
+      const uint64_t w = qhi ? hi : lo;
+      keep = (int)((w >> (q & 63)) & 1ull) == o;
+    }
+    uint32_t tile_total;
+    const uint64_t pos = base + block_prefix012(keep ? 1u : 0u, s_wave, &tile_total);
+    if (keep) {
+      const double2 a = in.amp[i];
+      out.key_lo[pos] = lo;
+      if (WIDE) out.key_hi[pos] = hi;
+      out.amp[pos] = make_double2(a.x * scale, a.y * scale);
+    }
+    base += tile_total;
+  }
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// Launchers.
+void launch_set_basis(hipStream_t st, Buf b, uint64_t* nnz, uint64_t lo, uint64_t hi) {
+  hipLaunchKernelGGL(k_set_basis, dim3(1), dim3(1), 0, st, b, nnz, lo, hi);
+}
+
+void launch_fill(hipStream_t st, uint64_t* p, uint64_t v, uint64_t n) {
+  const uint64_t blocks = (n + 255) / 256;
+  const int grid = (int)(blocks < 16384 ? (blocks ? blocks : 1) : 16384);
+  hipLaunchKernelGGL(k_fill, dim3(grid), dim3(256), 0, st, p, v, n);
+}
+
+void launch_mono(hipStream_t st, bool wide, Buf b, const uint64_t* nnz, const MonoDesc* g, uint32_t ng,
+                 uint64_t* updates, int grid, int block) {
+  auto* up = reinterpret_cast<unsigned long long*>(updates);
+  if (wide)
+    hipLaunchKernelGGL((k_mono<true, 4>), dim3(grid), dim3(block), 0, st, b, nnz, g, ng, up);
+  else
+    hipLaunchKernelGGL((k_mono<false, 4>), dim3(grid), dim3(block), 0, st, b, nnz, g, ng, up);
+}
+
+void launch_index_build(hipStream_t st, bool wide, Buf b, const uint64_t* nnz, uint64_t* table, uint64_t mask,
+                        int grid, int block) {
+  auto* t = reinterpret_cast<unsigned long long*>(table);
+  if (wide)
+    hipLaunchKernelGGL(k_index_build<true>, dim3(grid), dim3(block), 0, st, b, nnz, t, mask);
+  else
+    hipLaunchKernelGGL(k_index_build<false>, dim3(grid), dim3(block), 0, st, b, nnz, t, mask);
+}
+
+void launch_u2_count(hipStream_t st, bool wide, Buf b, const uint64_t* nnz, const uint64_t* table, uint64_t mask,
+                     const U2Desc& d, uint32_t* partner, uint32_t* tot, Ctl* ctl, int grid, int block) {
+  if (wide)
+    hipLaunchKernelGGL(k_u2_count<true>, dim3(grid), dim3(block), 0, st, b, nnz, table, mask, d, partner, tot, ctl);
+  else
+    hipLaunchKernelGGL(k_u2_count<false>, dim3(grid), dim3(block), 0, st, b, nnz, table, mask, d, partner, tot, ctl);
+}
+
+void launch_scan(hipStream_t st, uint32_t* tot, int nblocks, uint64_t* nnz_out, Ctl* ctl) {
+  hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, st, tot, nblocks, nnz_out, ctl);
+}
+
+void launch_u2_write(hipStream_t st, bool wide, Buf in, Buf out, const uint64_t* nnz, const uint32_t* partner,
+                     const uint32_t* off, const U2Desc& d, int grid, int block) {
+  if (wide)
+    hipLaunchKernelGGL(k_u2_write<true>, dim3(grid), dim3(block), 0, st, in, out, nnz, partner, off, d);
+  else
+    hipLaunchKernelGGL(k_u2_write<false>, dim3(grid), dim3(block), 0, st, in, out, nnz, partner, off, d);
+}
+
+void launch_measure_reduce(hipStream_t st, bool wide, Buf b, const uint64_t* nnz, uint32_t q, BlockScratch s,
+                           int grid, int block) {
+  if (wide)
+    hipLaunchKernelGGL(k_measure_reduce<true>, dim3(grid), dim3(block), 0, st, b, nnz, q, s.part, s.cnt1);
+  else
+    hipLaunchKernelGGL(k_measure_reduce<false>, dim3(grid), dim3(block), 0, st, b, nnz, q, s.part, s.cnt1);
+}
+
+void launch_measure_decide(hipStream_t st, BlockScratch s, int nblocks, const uint64_t* nnz_in, uint64_t* nnz_out,
+                           double u, int32_t forced, MeasRec* rec, int32_t* outcome, Ctl* ctl) {
+  hipLaunchKernelGGL(k_measure_decide, dim3(1), dim3(1024), 0, st, s.part, s.cnt1, s.tot, nblocks, nnz_in, nnz_out,
+                     u, forced, rec, outcome, ctl);
+}
+
+void launch_measure_write(hipStream_t st, bool wide, Buf in, Buf out, const uint64_t* nnz, uint32_t q,
+                          const MeasRec* rec, const uint32_t* off, int grid, int block) {
+  if (wide)
+    hipLaunchKernelGGL(k_measure_write<true>, dim3(grid), dim3(block), 0, st, in, out, nnz, q, rec, off);
+  else
+    hipLaunchKernelGGL(k_measure_write<false>, dim3(grid), dim3(block), 0, st, in, out, nnz, q, rec, off);
+}
+
+}  // namespace sparsesim

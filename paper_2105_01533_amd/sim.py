@@ -1,0 +1,266 @@
+"""ctypes binding of libsparsesim (include/sparsesim.h) -- argument marshalling only.
+
+Every step of the simulation runs in the HIP library; this module only
+converts numpy arrays and torch device memory/streams into the C-ABI's plain
+pointers.  Functions keep the C names.  ``Simulator`` is a small convenience
+wrapper that borrows its workspace from torch and runs on torch's current
+stream.
+
+The library must be built (``python -m paper_2105_01533_amd.build``); there is
+no fallback: a missing library raises ``ImportError`` at load time.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+# torch first: it loads the HIP runtime that libsparsesim then shares.
+import torch  # noqa: F401
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libsparsesim.so")
+
+SIM_OK, SIM_E_ARG, SIM_E_NOMEM, SIM_E_CAPACITY, SIM_E_BUFFER, SIM_E_HIP, SIM_E_STATE = 0, -1, -2, -3, -4, -5, -6
+SIM_OP_MONO, SIM_OP_U2, SIM_OP_MEASURE = 0, 1, 2
+
+GATE_DTYPE = np.dtype([
+    ("op", "<u4"), ("target", "<u4"), ("ctrl_lo", "<u8"), ("ctrl_hi", "<u8"),
+    ("flip", "<u4"), ("forced", "<i4"), ("m", "<c16", (4,)), ("cap", "<u8"), ("u", "<f8"),
+    ("reserved", "<u8"),
+])
+assert GATE_DTYPE.itemsize == 120
+KEY_DTYPE = np.dtype([("lo", "<u8"), ("hi", "<u8")])
+
+
+class sim_config(ctypes.Structure):
+    _fields_ = [("n_qubits", ctypes.c_uint32), ("fuse_max", ctypes.c_uint32), ("capacity", ctypes.c_uint64),
+                ("eps", ctypes.c_double), ("load_factor", ctypes.c_double), ("block", ctypes.c_uint32),
+                ("flags", ctypes.c_uint32)]
+
+
+class sim_stats(ctypes.Structure):
+    _fields_ = [(f, ctypes.c_uint64) for f in (
+        "gates_applied", "updates", "mono_passes", "u2_applied", "u2_skipped", "measures", "host_syncs",
+        "peak_nnz", "pruned")]
+
+    def as_dict(self):
+        return {f: int(getattr(self, f)) for f, _ in self._fields_}
+
+
+class sim_key(ctypes.Structure):
+    _fields_ = [("lo", ctypes.c_uint64), ("hi", ctypes.c_uint64)]
+
+
+class SimError(RuntimeError):
+    def __init__(self, code: int, where: str):
+        self.code = code
+        super().__init__(f"{where}: {sim_strerror(code)} ({code}): {sim_last_error()}")
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is not built; run `python -m paper_2105_01533_amd.build`")
+    L = ctypes.CDLL(LIB_PATH)
+    vp, u64, i32, u32, f64, sz = (ctypes.c_void_p, ctypes.c_uint64, ctypes.c_int32, ctypes.c_uint32,
+                                  ctypes.c_double, ctypes.c_size_t)
+    sig = {
+        "sim_workspace_bytes": (sz, [vp]),
+        "sim_create": (i32, [vp, vp, vp, sz, ctypes.POINTER(vp)]),
+        "sim_destroy": (i32, [vp]),
+        "sim_set_basis": (i32, [vp, sim_key]),
+        "sim_import_state": (i32, [vp, vp, vp, u64]),
+        "sim_gates_from_ops": (i32, [vp, sz, vp]),
+        "sim_apply_gates": (i32, [vp, vp, sz, vp, vp]),
+        "sim_apply_ops": (i32, [vp, vp, sz, vp, vp]),
+        "sim_measure": (i32, [vp, u32, f64, i32, ctypes.POINTER(i32), ctypes.POINTER(f64)]),
+        "sim_nnz": (i32, [vp, ctypes.POINTER(u64)]),
+        "sim_sync": (i32, [vp]),
+        "sim_export_state": (i32, [vp, vp, vp, u64, ctypes.POINTER(u64)]),
+        "sim_device_state": (i32, [vp, vp, vp, vp, vp]),
+        "sim_strerror": (ctypes.c_char_p, [ctypes.c_int]),
+        "sim_last_error": (ctypes.c_char_p, []),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(L, name)
+        f.restype = res
+        f.argtypes = args
+    return L
+
+
+_lib = _load()
+
+
+def _ptr(a):
+    return None if a is None else a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _check(rc: int, where: str):
+    if rc != SIM_OK:
+        raise SimError(rc, where)
+
+
+# --- C names -----------------------------------------------------------------
+def sim_strerror(code: int) -> str:
+    return _lib.sim_strerror(code).decode()
+
+
+def sim_last_error() -> str:
+    return _lib.sim_last_error().decode()
+
+
+def sim_workspace_bytes(cfg: sim_config) -> int:
+    return int(_lib.sim_workspace_bytes(ctypes.byref(cfg)))
+
+
+def sim_create(cfg: sim_config, stream: int | None = None, workspace: int | None = None, ws_bytes: int = 0):
+    h = ctypes.c_void_p()
+    _check(_lib.sim_create(ctypes.byref(cfg), stream, workspace, ws_bytes, ctypes.byref(h)), "sim_create")
+    return h
+
+
+def sim_destroy(h):
+    _check(_lib.sim_destroy(h), "sim_destroy")
+
+
+def sim_set_basis(h, lo: int = 0, hi: int = 0):
+    _check(_lib.sim_set_basis(h, sim_key(lo, hi)), "sim_set_basis")
+
+
+def sim_import_state(h, lo, hi, amp):
+    keys = np.empty(len(lo), KEY_DTYPE)
+    keys["lo"], keys["hi"] = lo, hi
+    amp = np.ascontiguousarray(amp, dtype=np.complex128)
+    _check(_lib.sim_import_state(h, _ptr(keys), _ptr(amp), len(keys)), "sim_import_state")
+
+
+def sim_gates_from_ops(ops: np.ndarray) -> np.ndarray:
+    ops = np.ascontiguousarray(ops)
+    assert ops.dtype.itemsize == 48
+    out = np.zeros(len(ops), GATE_DTYPE)
+    _check(_lib.sim_gates_from_ops(_ptr(ops), len(ops), _ptr(out)), "sim_gates_from_ops")
+    return out
+
+
+def _n_meas_gates(gates):
+    return int(np.count_nonzero(gates["op"] == SIM_OP_MEASURE))
+
+
+def sim_apply_gates(h, gates: np.ndarray, raise_on_error: bool = True):
+    """Returns (rc, outcomes, stats dict)."""
+    gates = np.ascontiguousarray(gates, dtype=GATE_DTYPE)
+    outcomes = np.full(max(_n_meas_gates(gates), 1), -1, np.int32)
+    st = sim_stats()
+    rc = _lib.sim_apply_gates(h, _ptr(gates), len(gates), _ptr(outcomes), ctypes.byref(st))
+    if raise_on_error:
+        _check(rc, "sim_apply_gates")
+    return rc, outcomes[:_n_meas_gates(gates)], st.as_dict()
+
+
+def sim_apply_ops(h, ops: np.ndarray, raise_on_error: bool = True):
+    """Returns (rc, outcomes, stats dict)."""
+    ops = np.ascontiguousarray(ops)
+    assert ops.dtype.itemsize == 48
+    n_meas = int(np.count_nonzero(ops["kind"] == 12))
+    outcomes = np.full(max(n_meas, 1), -1, np.int32)
+    st = sim_stats()
+    rc = _lib.sim_apply_ops(h, _ptr(ops), len(ops), _ptr(outcomes), ctypes.byref(st))
+    if raise_on_error:
+        _check(rc, "sim_apply_ops")
+    return rc, outcomes[:n_meas], st.as_dict()
+
+
+def sim_measure(h, qubit: int, u: float, forced: int = -1):
+    o, p1 = ctypes.c_int32(), ctypes.c_double()
+    _check(_lib.sim_measure(h, qubit, u, forced, ctypes.byref(o), ctypes.byref(p1)), "sim_measure")
+    return o.value, p1.value
+
+
+def sim_nnz(h) -> int:
+    n = ctypes.c_uint64()
+    _check(_lib.sim_nnz(h, ctypes.byref(n)), "sim_nnz")
+    return n.value
+
+
+def sim_sync(h):
+    _check(_lib.sim_sync(h), "sim_sync")
+
+
+def sim_export_state(h, sort: bool = True):
+    """(lo, hi, amp) numpy arrays; sorted ascending by (hi, lo) when sort."""
+    n = sim_nnz(h)
+    keys = np.empty(max(n, 1), KEY_DTYPE)
+    amp = np.empty(max(n, 1), np.complex128)
+    got = ctypes.c_uint64()
+    _check(_lib.sim_export_state(h, _ptr(keys), _ptr(amp), len(keys), ctypes.byref(got)), "sim_export_state")
+    n = got.value
+    lo, hi, amp = keys["lo"][:n].copy(), keys["hi"][:n].copy(), amp[:n].copy()
+    if sort:
+        order = np.lexsort((lo, hi))
+        lo, hi, amp = lo[order], hi[order], amp[order]
+    return lo, hi, amp
+
+
+def sim_device_state(h):
+    lo, hi, amp, nnz = ctypes.c_void_p(), ctypes.c_void_p(), ctypes.c_void_p(), ctypes.c_void_p()
+    _check(_lib.sim_device_state(h, ctypes.byref(lo), ctypes.byref(hi), ctypes.byref(amp), ctypes.byref(nnz)),
+           "sim_device_state")
+    return lo.value, hi.value, amp.value, nnz.value
+
+
+# --- convenience wrapper -----------------------------------------------------
+class Simulator:
+    """One sparse state on the current torch device and stream."""
+
+    def __init__(self, n_qubits: int, capacity: int, eps: float = 0.0, fuse_max: int = 0,
+                 load_factor: float = 0.0, block: int = 0, device: str = "cuda"):
+        self.cfg = sim_config(n_qubits=n_qubits, fuse_max=fuse_max, capacity=capacity, eps=eps,
+                              load_factor=load_factor, block=block, flags=0)
+        nbytes = sim_workspace_bytes(self.cfg)
+        if nbytes == 0:
+            raise SimError(SIM_E_ARG, "sim_workspace_bytes")
+        self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=device)
+        self.stream = torch.cuda.current_stream(self.workspace.device)
+        self.h = sim_create(self.cfg, self.stream.cuda_stream, self.workspace.data_ptr(), nbytes)
+
+    def close(self):
+        if getattr(self, "h", None):
+            sim_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_basis(self, lo=0, hi=0):
+        sim_set_basis(self.h, lo, hi)
+
+    def import_state(self, lo, hi, amp):
+        sim_import_state(self.h, lo, hi, amp)
+
+    def apply_ops(self, ops, raise_on_error=True):
+        return sim_apply_ops(self.h, ops, raise_on_error)
+
+    def apply_gates(self, gates, raise_on_error=True):
+        return sim_apply_gates(self.h, gates, raise_on_error)
+
+    def measure(self, q, u, forced=-1):
+        return sim_measure(self.h, q, u, forced)
+
+    @property
+    def nnz(self):
+        return sim_nnz(self.h)
+
+    def export(self, sort=True):
+        return sim_export_state(self.h, sort)
+
+
+def run_workload(w, **kw):
+    """Simulate a workloads.Workload from its basis state; returns (sim, outcomes, stats)."""
+    s = Simulator(w.n_qubits, w.capacity, w.eps, **kw)
+    s.set_basis(*w.basis)
+    _, outcomes, stats = s.apply_ops(w.ops)
+    return s, outcomes, stats

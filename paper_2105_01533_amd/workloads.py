@@ -327,3 +327,53 @@ def serving_trace(seed: int = 4242, requests: int = 512, rate: float = 100.0,
         w.meta.update({"family": fam, "cap_log2": lg, "request": r})
         out.append((t, w))
     return out
+
+
+# --- random sparse states (counter-based SplitMix64, vectorised) --------------
+_GAMMA = np.uint64(0x9E3779B97F4A7C15)
+
+
+def splitmix64_array(seed: int, start: int, count: int) -> np.ndarray:
+    """Outputs start..start+count-1 of the SplitMix64 stream of `seed`
+    (output i mixes seed + (i+1)*gamma), as uint64."""
+    with np.errstate(over="ignore"):
+        i = np.arange(start + 1, start + count + 1, dtype=np.uint64)
+        z = np.uint64(seed) + i * _GAMMA
+        z = (z ^ (z >> np.uint64(30))) * np.uint64(0xBF58476D1CE4E5B9)
+        z = (z ^ (z >> np.uint64(27))) * np.uint64(0x94D049BB133111EB)
+        return z ^ (z >> np.uint64(31))
+
+
+def random_state(seed: int, n_entries: int, n_qubits: int, normalise: bool = True):
+    """n_entries distinct random labels below 2^n_qubits with random complex
+    amplitudes (re, im uniform in [-1, 1)), returned as (lo, hi, amp)."""
+    assert n_qubits >= 64 or n_entries <= (1 << n_qubits)
+    lo_mask = np.uint64((1 << min(n_qubits, 64)) - 1)
+    hi_mask = np.uint64((1 << max(n_qubits - 64, 0)) - 1)
+    keys: dict = {}
+    lo = np.empty(0, np.uint64)
+    hi = np.empty(0, np.uint64)
+    ctr = 0
+    while len(lo) < n_entries:
+        m = 2 * (n_entries - len(lo)) + 16
+        r = splitmix64_array(seed, ctr, 2 * m)
+        ctr += 2 * m
+        cand_lo = r[0::2] & lo_mask
+        cand_hi = r[1::2] & hi_mask
+        lo = np.concatenate([lo, cand_lo])
+        hi = np.concatenate([hi, cand_hi])
+        _, first = np.unique(np.stack([hi, lo], axis=1), axis=0, return_index=True)
+        first.sort()
+        lo, hi = lo[first], hi[first]
+    lo, hi = lo[:n_entries], hi[:n_entries]
+    return lo, hi, random_amplitudes(seed, n_entries, normalise)
+
+
+def random_amplitudes(seed: int, n: int, normalise: bool = True) -> np.ndarray:
+    """n random complex amplitudes, re and im uniform in [-1, 1)."""
+    r = splitmix64_array(seed ^ 0x5DEECE66D, 0, 2 * n)
+    u = (r >> np.uint64(11)).astype(np.float64) * (1.0 / 9007199254740992.0)
+    amp = (2.0 * u[0::2] - 1.0) + 1j * (2.0 * u[1::2] - 1.0)
+    if normalise and n:
+        amp = amp / np.sqrt(np.sum(np.abs(amp) ** 2))
+    return amp

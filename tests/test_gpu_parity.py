@@ -1,0 +1,341 @@
+"""GPU parity: the HIP library against the CPU oracle, through the C-ABI.
+
+Bar: sorted label sets bit-exact, amplitudes within 1e-12 (complex modulus),
+identical measurement outcomes and skip decisions.  Sizes span many blocks
+and ragged tails; the full-size workloads are checked against the oracle
+where it finishes in seconds, against golden oracle digests where it does not
+(tests/golden/make_golden.py), and on oracle-computed samples at the largest
+size.
+"""
+import json
+import math
+import os
+import sys
+
+import numpy as np
+import pytest
+
+from helpers import assert_same_state, keys_digest, lookup, sorted_unique
+from oracle import Oracle, monomial_samples, run_workload as oracle_run
+from paper_2105_01533_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+
+def say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+@pytest.fixture(scope="module")
+def sim():
+    from paper_2105_01533_amd import sim as S
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    return S
+
+
+def gpu_run(S, w, **kw):
+    say(f"[gpu] {w.name} ops={len(w.ops)} n={w.n_qubits} cap={w.capacity} {kw}")
+    s, outcomes, stats = S.run_workload(w, **kw)
+    out = s.export()
+    s.close()
+    return out, outcomes, stats
+
+
+def check_vs_oracle(S, w, tol=1e-12, **kw):
+    g, gout, gst = gpu_run(S, w, **kw)
+    o, oout, _ = oracle_run(w)
+    assert list(gout) == list(oout), "measurement outcomes differ"
+    assert_same_state(g, o.export(), tol, w.name)
+    t = o.totals()
+    assert gst["u2_applied"] == t["u2_applied"] and gst["u2_skipped"] == t["u2_skipped"]
+    assert gst["updates"] == t["updates"]
+    return g, gst
+
+
+# --- worked states ------------------------------------------------------------
+def test_bell_ghz_x128(sim):
+    for n in (2, 64, 65, 128):
+        c = W.Circuit()
+        c.h(0)
+        for q in range(1, n):
+            c.x(q, (q - 1,))
+        w = W.Workload(f"ghz{n}", n, 0.0, c.array(), capacity=4)
+        g, _ = check_vs_oracle(sim, w)
+        assert len(g[0]) == 2 and g[2][0] == math.sqrt(0.5)
+    c = W.Circuit()
+    for q in range(128):
+        c.x(q)
+    g, _ = check_vs_oracle(sim, W.Workload("x128", 128, 0.0, c.array(), capacity=2))
+    assert g[0].tolist() == [2 ** 64 - 1] and g[1].tolist() == [2 ** 64 - 1] and g[2][0] == 1.0
+
+
+def test_hh_identity_prunes(sim):
+    c = W.Circuit()
+    c.h(3)
+    c.h(3)
+    g, st = check_vs_oracle(sim, W.Workload("hh", 8, 1e-20, c.array(), capacity=4))
+    assert g[0].tolist() == [0] and st["pruned"] == 1
+
+
+# --- random circuits, every gate kind, narrow and wide labels ---------------------
+@pytest.mark.parametrize("n,seed", [(7, 1), (20, 2), (64, 3), (70, 4), (100, 5), (128, 6)])
+def test_random_circuits(sim, n, seed):
+    w = W.random_circuit(seed, n=n, gates=400, h_frac=0.12, ctrl_max=3, measure_frac=0.01)
+    w.capacity = 1 << 16
+    check_vs_oracle(sim, w)
+
+
+@pytest.mark.parametrize("eps", [0.0, 1e-6])
+def test_random_circuits_eps(sim, eps):
+    w = W.random_circuit(77, n=12, gates=500, h_frac=0.3, ctrl_max=2)
+    w.eps = eps
+    w.capacity = 1 << 12
+    check_vs_oracle(sim, w)
+
+
+# --- scaled and full configs -------------------------------------------------------
+def test_config0_full(sim):
+    check_vs_oracle(sim, W.config0())
+
+
+def test_config1_scaled(sim):
+    check_vs_oracle(sim, W.config1(5, w=10, adds=12, n=64))
+
+
+def test_config2_scaled(sim):
+    check_vs_oracle(sim, W.config2(6, n=100, h_qubits=12, gates=20000, round_gates=4000, meas_per_round=4))
+
+
+def test_config3_scaled(sim):
+    check_vs_oracle(sim, W.config3(7, terms=80))
+
+
+def _golden(name):
+    with open(os.path.join(GOLDEN, f"{name}.json")) as f:
+        return json.load(f)
+
+
+def _check_golden(S, w, doc):
+    g, gout, gst = gpu_run(S, w)
+    lo, hi, amp = g
+    assert len(lo) == doc["nnz"]
+    assert keys_digest(lo, hi) == doc["keys_sha256"]
+    assert list(gout) == doc["outcomes"]
+    assert gst["updates"] == doc["updates"] and gst["u2_applied"] == doc["u2_applied"]
+    assert gst["u2_skipped"] == doc["u2_skipped"]
+    err = 0.0
+    for k, (slo, shi, re_, im_) in enumerate(doc["samples"]):
+        i = k * doc["stride"]
+        assert int(lo[i]) == slo and int(hi[i]) == shi
+        err = max(err, abs(amp[i] - complex(float.fromhex(re_), float.fromhex(im_))))
+    assert err <= 1e-12, err
+    assert abs(np.sum(np.abs(amp) ** 2) - float.fromhex(doc["norm2"])) < 1e-10
+
+
+def test_config1_full_golden(sim):
+    _check_golden(sim, W.config1(), _golden("config1_full"))
+
+
+def test_config3_full_golden(sim):
+    _check_golden(sim, W.config3(), _golden("config3_full"))
+
+
+def test_config2_full_first_round_samples(sim):
+    """100 qubits, 2^24 entries: the first 20,000 gates of the full workload
+    (every H is skipped at this size) on a seeded random state, checked on
+    65,536 entries computed one at a time by the oracle."""
+    w = W.config2()
+    body = w.ops[24:24 + 20000]
+    assert not np.any(body["kind"] == W.K_MEASURE)
+    n = 1 << 24
+    lo0 = np.arange(n, dtype=np.uint64)
+    hi0 = np.zeros(n, np.uint64)
+    amp0 = W.random_amplitudes(2024, n)
+    from paper_2105_01533_amd.sim import Simulator
+    s = Simulator(100, n, 1e-20)
+    s.import_state(lo0, hi0, amp0)
+    say("[gpu] c2 first round on 2^24 imported entries")
+    _, _, st = s.apply_ops(body)
+    assert st["u2_applied"] == 0 and st["u2_skipped"] == int(np.sum(body["kind"] == W.K_H))
+    lo, hi, amp = s.export()
+    s.close()
+    assert len(lo) == n
+    rng = np.random.default_rng(5)
+    pick = np.sort(rng.choice(n, 65536, replace=False))
+    mono = body[body["kind"] != W.K_H]
+    elo, ehi, eamp = monomial_samples(mono, lo0[pick], hi0[pick], amp0[pick])
+    idx = lookup(lo, hi, elo, ehi)
+    assert np.all(idx >= 0)
+    assert np.max(np.abs(amp[idx] - eamp)) <= 1e-12
+    assert sorted_unique(lo, hi)          # a permutation image: labels stay distinct
+
+
+def test_config2_full_properties(sim):
+    """Full 200,000-gate workload: the normalisation restored by every
+    measurement, nnz within the cap, and bitwise determinism."""
+    w = W.config2()
+    g1, out1, st1 = gpu_run(sim, w)
+    assert len(g1[0]) <= 1 << 24 and st1["measures"] == 80
+    assert abs(np.sum(np.abs(g1[2]) ** 2) - 1.0) < 1e-9
+    g2, out2, st2 = gpu_run(sim, w)
+    assert list(out1) == list(out2) and st1 == st2
+    for a, b in zip(g1, g2):
+        assert a.tobytes() == b.tobytes()
+
+
+# --- multi-tile, ragged sizes, imported states -------------------------------------
+@pytest.mark.parametrize("n_entries", [1, 63, 64, 65, 255, 2047, 2048, 2049, 100_003, (1 << 20) + 17])
+def test_ragged_sizes(sim, n_entries):
+    nq = 100 if n_entries % 2 else 40
+    lo0, hi0, amp0 = W.random_state(n_entries, n_entries, nq)
+    rng = W.SplitMix64(n_entries)
+    c = W.Circuit()
+    for _ in range(300):
+        W._random_mono(rng, c, nq, 0.6, 0.4, 0)
+    for q in rng.distinct(nq, 3 if n_entries < 100_000 else 1):
+        c.h(q)
+    t, ctl = rng.distinct(nq, 2)
+    c.gate(W.K_RY, t, (ctl,), param=0.3)
+    for _ in range(100):
+        W._random_mono(rng, c, nq, 0.6, 0.4, 0)
+    c.measure(rng.randint(nq), rng.uniform())
+    c.h(5, cap=4 * n_entries)
+    ops = c.array()
+    from paper_2105_01533_amd.sim import Simulator
+    s = Simulator(nq, 16 * n_entries + 64, 1e-24)
+    s.import_state(lo0, hi0, amp0)
+    say(f"[gpu] ragged n={n_entries} nq={nq}")
+    _, gout, gst = s.apply_ops(ops)
+    g = s.export()
+    s.close()
+    o = Oracle(nq, 1e-24)
+    o.import_state(lo0, hi0, amp0)
+    oout, _ = o.run(ops)
+    assert list(gout) == list(oout)
+    assert_same_state(g, o.export(), what=f"ragged {n_entries}")
+
+
+# --- launch-shape independence and determinism --------------------------------------
+def test_tuning_knobs_do_not_change_results(sim):
+    w = W.config2(31, n=100, h_qubits=11, gates=6000, round_gates=2000, meas_per_round=3)
+    ref, _, _ = gpu_run(sim, w)
+    for kw in [dict(fuse_max=1), dict(fuse_max=7), dict(block=64), dict(block=128), dict(load_factor=0.25),
+               dict(load_factor=0.9)]:
+        g, _, _ = gpu_run(sim, w, **kw)
+        for a, b in zip(ref, g):
+            assert a.tobytes() == b.tobytes(), kw
+
+
+# --- errors and edge cases ------------------------------------------------------------
+def test_capacity_error_leaves_state(sim):
+    from paper_2105_01533_amd.sim import Simulator, SIM_E_CAPACITY
+    s = Simulator(30, 16, 0.0)
+    c = W.Circuit()
+    for q in range(4):
+        c.h(q)                      # 16 entries: fits
+    c.x(9, (1,))
+    c.h(5)                          # would need 32
+    c.h(6)
+    s.apply_ops(c.array()[:5])
+    before = s.export()
+    rc, _, st = s.apply_ops(c.array()[5:], raise_on_error=False)
+    assert rc == SIM_E_CAPACITY and st["gates_applied"] == 0
+    after = s.export()
+    for a, b in zip(before, after):
+        assert a.tobytes() == b.tobytes()
+    s.close()
+
+
+def test_invalid_ops_apply_nothing(sim):
+    from paper_2105_01533_amd.sim import Simulator, SimError, SIM_E_ARG
+    s = Simulator(10, 64, 0.0)
+    s.apply_ops(W.config0(1, n=10, h_qubits=3, gates=50, cap=64, measured=0).ops)
+    before = s.export()
+    for bad in [dict(target=10), dict(target=3, ctrl=(3,)), dict(target=1, ctrl=(12,))]:
+        c = W.Circuit()
+        c.x(0)
+        c.gate(W.K_X, bad["target"], bad.get("ctrl", ()))
+        with pytest.raises(SimError) as e:
+            s.apply_ops(c.array())
+        assert e.value.code == SIM_E_ARG
+    c = W.Circuit()
+    c.measure(2, 1.5)
+    with pytest.raises(SimError):
+        s.apply_ops(c.array())
+    after = s.export()
+    for a, b in zip(before, after):
+        assert a.tobytes() == b.tobytes()
+    s.close()
+
+
+def test_forced_zero_probability_measurement(sim):
+    from paper_2105_01533_amd.sim import Simulator, SimError, SIM_E_STATE
+    s = Simulator(5, 8, 0.0)
+    c = W.Circuit()
+    c.h(0)
+    s.apply_ops(c.array())
+    m = W.Circuit()
+    m.measure(1, 0.0, forced=1)      # qubit 1 is 0 everywhere
+    rc, _, _ = s.apply_ops(m.array(), raise_on_error=False)
+    assert rc == SIM_E_STATE
+    assert s.nnz == 2
+    o, p1 = s.measure(0, 0.0, forced=1)
+    assert o == 1 and abs(p1 - 0.5) < 1e-15
+    lo, hi, amp = s.export()
+    assert lo.tolist() == [1] and abs(amp[0] - 1) < 1e-15
+    s.close()
+
+
+def test_everything_pruned_then_measure(sim):
+    from paper_2105_01533_amd.sim import Simulator, SIM_E_STATE
+    s = Simulator(6, 8, 10.0)        # eps above any |a|^2: a branching gate empties the state
+    c = W.Circuit()
+    c.h(0)
+    s.apply_ops(c.array())
+    assert s.nnz == 0
+    m = W.Circuit()
+    m.measure(0, 0.3)
+    rc, _, _ = s.apply_ops(m.array(), raise_on_error=False)
+    assert rc == SIM_E_STATE and s.nnz == 0
+    s.close()
+
+
+def test_import_export_roundtrip_and_errors(sim):
+    from paper_2105_01533_amd.sim import Simulator, SimError, SIM_E_ARG, SIM_E_CAPACITY
+    lo, hi, amp = W.random_state(3, 5000, 128)
+    s = Simulator(128, 5000, 0.0)
+    s.import_state(lo, hi, amp)
+    glo, ghi, gamp = s.export()
+    order = np.lexsort((lo, hi))
+    assert np.array_equal(glo, lo[order]) and np.array_equal(ghi, hi[order])
+    assert gamp.tobytes() == amp[order].tobytes()
+    with pytest.raises(SimError) as e:
+        s.import_state(np.array([1, 1], np.uint64), np.zeros(2, np.uint64), np.ones(2))
+    assert e.value.code == SIM_E_ARG
+    with pytest.raises(SimError) as e:
+        s.import_state(*W.random_state(4, 5001, 128))
+    assert e.value.code == SIM_E_CAPACITY
+    s.close()
+    s = Simulator(10, 4, 0.0)
+    with pytest.raises(SimError) as e:
+        s.import_state(np.array([1 << 10], np.uint64), np.zeros(1, np.uint64), np.ones(1))
+    assert e.value.code == SIM_E_ARG
+    s.close()
+
+
+def test_empty_and_single_entry(sim):
+    from paper_2105_01533_amd.sim import Simulator
+    s = Simulator(8, 4, 0.0)
+    s.import_state(np.zeros(0, np.uint64), np.zeros(0, np.uint64), np.zeros(0))
+    _, _, st = s.apply_ops(W.config0(2, n=8, h_qubits=0, gates=200, cap=4, measured=0).ops)
+    assert s.nnz == 0 and st["updates"] == 0
+    s.set_basis(5, 0)
+    c = W.Circuit()
+    c.x(0)
+    c.gate(W.K_S, 2)
+    s.apply_ops(c.array())
+    lo, hi, amp = s.export()
+    assert lo.tolist() == [4] and amp[0] == 1j
+    s.close()
