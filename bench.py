@@ -1,12 +1,21 @@
 """Benchmark: nonzero-amplitude gate updates/s of the sparse simulator on one MI355X.
 
 A step simulates one whole synthetic circuit from its initial basis state
-through the C-ABI (state resident in HBM; the op list, its conversion and
-upload are inside the timed region).  Default workload: the 100-qubit random
-circuit (H on 24 qubits -> 2^24 entries, 200,000 gates, 8 measurements every
-20,000 gates).  Prints one JSON line.
+through the C-ABI, with the state resident in HBM; converting and uploading
+the op list is inside the timed region.  Default workload: the 100-qubit
+random circuit (H on 24 qubits -> 2^24 entries, 200,000 gates: 80 %
+X/CNOT/Toffoli, 15 % Z/S/T/Rz, 5 % H capped at 2^24 entries, 8 qubits
+measured after every 20,000 gates).  Prints one JSON line.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload c2]
+
+Roofline: every kernel launch of the timed steps is bracketed by HIP events
+on the library's stream (sim_set_profiling); the fused phase/permutation
+pass dominates, and its algorithmic bytes per launch (label read, label
+write when a gate flips, amplitude read+write when a gate has a phase:
+16+16+32 B per entry for 128-bit labels) over its mean launch time give
+`achieved`.  A second measurement sweeps the fusion depth F on a 2^24-entry
+state to show the pass where it is HBM-bound.
 """
 from __future__ import annotations
 
@@ -35,8 +44,8 @@ def log(*a):
 
 def cpu_baseline(w, seconds_budget: float = 20.0):
     """The oracle as it stands, single-threaded, on a bounded prefix of the
-    same workload: the initial H layer plus as many following gates as fit the
-    budget (estimated from a short calibration prefix)."""
+    same workload: the initial H layer plus as many following gates as fit
+    the budget (grown from a short calibration prefix)."""
     import numpy as np
 
     from oracle import Oracle
@@ -44,8 +53,7 @@ def cpu_baseline(w, seconds_budget: float = 20.0):
 
     ops = w.ops
     kinds = ops["kind"]
-    first_body = int(np.argmax(~np.isin(kinds, (W.K_H,)))) if np.any(kinds != W.K_H) else len(ops)
-    best = None
+    first_body = int(np.argmax(kinds != W.K_H)) if np.any(kinds != W.K_H) else len(ops)
     n_body = 64
     while True:
         o = Oracle(w.n_qubits, w.eps)
@@ -64,6 +72,43 @@ def cpu_baseline(w, seconds_budget: float = 20.0):
                       f"{upd} updates in {dt:.1f} s, single thread"}
 
 
+def hbm_sweep(sim, W, n_qubits=100, log2n=24, depths=(1, 2, 4, 16, 64)):
+    """Fused-pass bandwidth vs fusion depth F on a 2^log2n-entry state: 64
+    phase/permutation gates of the random mix, passes of F gates."""
+    import numpy as np
+
+    s = sim.Simulator(n_qubits, 1 << log2n, 0.0)
+    c = W.Circuit()
+    for q in range(log2n):
+        c.h(q)
+    s.apply_ops(c.array())
+    rng = W.SplitMix64(77)
+    body = W.Circuit()
+    while len(body) < 64:
+        W._random_mono(rng, body, n_qubits, 0.8, 0.2, 0)
+    ops = body.array()
+    ops = ops[ops["kind"] != W.K_H]
+    out = []
+    for mode, name in ((sim.SIM_MONO_DIRECT, "direct"), (sim.SIM_MONO_BITSLICE, "bitslice")):
+        for F in depths:
+            sim.sim_set_tuning(s.h, fuse_max=F, mono_mode=mode)
+            s.apply_ops(ops)                             # warm
+            sim.sim_set_profiling(s.h, True)
+            sim.sim_kernel_stats_reset(s.h)
+            for _ in range(3):
+                s.apply_ops(ops)
+            k = sim.sim_kernel_stats(s.h)["mono_pass"]
+            sim.sim_set_profiling(s.h, False)
+            gbs = k["alg_bytes"] / (k["total_ms"] * 1e-3) / 1e9
+            out.append({"kernel": name, "F": F, "launches": k["launches"],
+                        "ms_per_launch": k["total_ms"] / k["launches"], "GB/s": round(gbs, 1),
+                        "frac": round(gbs / HBM_PEAK_GBS, 4),
+                        "updates_per_s": k["updates"] / (k["total_ms"] * 1e-3)})
+            log(f"[bench] sweep {name} F={F}: {out[-1]}")
+    s.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -71,7 +116,10 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="c2", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-sweep", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
+    ap.add_argument("--mono-mode", type=int, default=0, help="0 auto, 1 direct, 2 bit-sliced")
+    ap.add_argument("--fuse-max", type=int, default=0)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (got --gpus {args.gpus}); this build has no multi-GPU path.",
@@ -85,12 +133,14 @@ def main():
     fn, desc = WORKLOADS[args.workload]
     w = getattr(W, fn)()
     log(f"[bench] workload {w.name}: {len(w.ops)} ops, capacity {w.capacity}")
-    s = sim.Simulator(w.n_qubits, w.capacity, w.eps)
+    s = sim.Simulator(w.n_qubits, w.capacity, w.eps, mono_mode=args.mono_mode, fuse_max=args.fuse_max)
     gates = sim.sim_gates_from_ops(w.ops)
     for i in range(args.warmup):
         s.set_basis(*w.basis)
         _, _, st = s.apply_gates(gates)
         log(f"[bench] warmup {i}: {st}")
+    sim.sim_set_profiling(s.h, True)
+    sim.sim_kernel_stats_reset(s.h)
     torch.cuda.synchronize()
     updates = 0
     t0 = time.perf_counter()
@@ -100,7 +150,22 @@ def main():
         updates += st["updates"]
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
+    ks = sim.sim_kernel_stats(s.h)
+    sim.sim_set_profiling(s.h, False)
     log(f"[bench] timed {args.steps} steps in {dt:.3f} s; last stats {st}")
+    kernel_ms = {k: round(v["total_ms"] / args.steps, 3) for k, v in ks.items() if v["launches"]}
+    log(f"[bench] kernel ms/step {kernel_ms}")
+    dom = max(ks, key=lambda k: ks[k]["total_ms"])
+    mono = ks["mono_pass"]
+    ach = mono["alg_bytes"] / (mono["total_ms"] * 1e-3) / 1e9 if mono["total_ms"] > 0 else 0.0
+    roofline = {
+        "kernel": "mono_pass", "dominant_kernel": dom, "bound": "hbm", "achieved": round(ach, 2),
+        "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 5), "traffic": None,
+        "launches_per_step": mono["launches"] / args.steps,
+        "alg_bytes_per_launch": mono["alg_bytes"] / max(mono["launches"], 1),
+        "ms_per_launch": mono["total_ms"] / max(mono["launches"], 1),
+        "updates_per_s_in_kernel": mono["updates"] / (mono["total_ms"] * 1e-3) if mono["total_ms"] else 0.0,
+    }
     value = updates / dt
     out = {
         "metric": "nonzero-amplitude gate updates/s",
@@ -109,10 +174,15 @@ def main():
         "vs_baseline": None, "dtype": "f64", "data": "synthetic",
         "config": {"workload": w.name, "description": desc, "n_qubits": w.n_qubits,
                    "ops": int(len(w.ops)), "capacity": w.capacity, "eps": w.eps,
-                   "updates_per_step": st["updates"], "peak_nnz": st["peak_nnz"]},
-        "roofline": None,
+                   "updates_per_step": st["updates"], "peak_nnz": st["peak_nnz"],
+                   "mono_passes_per_step": st["mono_passes"], "bitslice_passes_per_step": st["bitslice_passes"],
+                   "u2_applied": st["u2_applied"], "u2_skipped": st["u2_skipped"], "measures": st["measures"],
+                   "kernel_ms_per_step": kernel_ms},
+        "roofline": roofline,
     }
     s.close()
+    if not args.no_sweep:
+        out["hbm_sweep"] = hbm_sweep(sim, W)
     if not args.no_cpu_baseline:
         log("[bench] cpu baseline (oracle) ...")
         out["cpu_baseline"] = cpu_baseline(w, args.cpu_seconds)

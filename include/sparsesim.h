@@ -128,9 +128,23 @@ typedef struct sim_config {
   uint64_t capacity;    /* max entries the state may hold, < 2^31 (required) */
   double eps;           /* prune threshold on |a|^2 after branching gates (0 = drop exact zeros only) */
   double load_factor;   /* hash index target load, (0, 0.9] (default 0.5) */
-  uint32_t block;       /* threads per block of the fused pass: 64, 128 or 256 (default 256) */
+  uint32_t block;       /* threads per block of the per-entry fused pass: 64, 128 or 256 (default 256) */
   uint32_t flags;       /* reserved, must be 0 */
+  uint32_t mono_mode;   /* fused-pass kernel: SIM_MONO_AUTO, SIM_MONO_DIRECT or SIM_MONO_BITSLICE */
+  uint32_t bs_min_gates; /* SIM_MONO_AUTO: bit-sliced pass for runs of at least this many gates (default 16) */
 } sim_config;
+
+/* Fused phase/permutation pass variants.  DIRECT evaluates every gate on every
+ * entry with sequential complex products (results bit-identical to a plain
+ * sequential evaluation).  BITSLICE transposes 2048-entry tiles into bit-planes
+ * (one 32-bit word per qubit per lane), applies permutations as plane
+ * operations and accumulates phases exactly as turn fractions, multiplying
+ * each amplitude once per run (results differ from sequential products by
+ * rounding only).  It applies to runs whose gates have at most 4 controls and
+ * unit-modulus factors; other runs use DIRECT. */
+#define SIM_MONO_AUTO 0u
+#define SIM_MONO_DIRECT 1u
+#define SIM_MONO_BITSLICE 2u
 
 /* Counters of one sim_apply_gates call (filled when stats != NULL). */
 typedef struct sim_stats {
@@ -141,6 +155,7 @@ typedef struct sim_stats {
   uint64_t host_syncs;     /* host waits for a device-computed nnz */
   uint64_t peak_nnz;       /* largest entry count reached */
   uint64_t pruned;         /* entries dropped by the eps rule */
+  uint64_t bitslice_passes; /* fused passes that ran the bit-sliced kernel */
 } sim_stats;
 
 typedef struct sim_t sim_t;
@@ -201,6 +216,33 @@ int sim_export_state(sim_t* s, sim_key* keys, sim_c64* amps, uint64_t cap, uint6
 /* Device addresses of the current state buffers (key_lo, key_hi, amp) and
  * the device nnz word, for zero-copy inspection; valid until the next call. */
 int sim_device_state(sim_t* s, uint64_t** key_lo, uint64_t** key_hi, double** amp, uint64_t** d_nnz);
+
+/* Per-kernel-class counters, cumulative since creation or the last reset.
+ * With profiling on (sim_set_profiling), every launch is bracketed by HIP
+ * events on the handle's stream and total_ms sums their elapsed times;
+ * otherwise total_ms is 0.  alg_bytes is the algorithmic HBM traffic of the
+ * fused phase/permutation pass (label read, label write if any gate flips,
+ * amplitude read+write if any gate has a phase), 0 for the other classes;
+ * updates counts gate-entry updates done by the class. */
+typedef struct sim_kernel_stat {
+  char name[32];
+  uint64_t launches;
+  double total_ms;
+  double alg_bytes;
+  double updates;
+} sim_kernel_stat;
+
+/* Change the launch tuning of a live handle: fuse_max, block, mono_mode and
+ * bs_min_gates are taken from t (zero = default); load_factor is taken if it
+ * is at least the creation value (the index was sized for that one); other
+ * fields of t are ignored.  Results change only by rounding (mono_mode) or
+ * not at all.  SIM_E_ARG on invalid values. */
+int sim_set_tuning(sim_t* s, const sim_config* t);
+
+int sim_set_profiling(sim_t* s, int on);
+/* Writes up to cap records; *n receives the number of kernel classes. */
+int sim_kernel_stats(sim_t* s, sim_kernel_stat* out, int cap, int* n);
+int sim_kernel_stats_reset(sim_t* s);
 
 /* Name of an error code / detail of the last error in this thread. */
 const char* sim_strerror(int code);

@@ -67,6 +67,7 @@ bool config_ok(const sim_config* c, std::string* why) {
   if (c->block != 0 && c->block != 64 && c->block != 128 && c->block != 256)
     return *why = "block must be 64, 128 or 256", false;
   if (c->flags != 0) return *why = "flags must be 0", false;
+  if (c->mono_mode > SIM_MONO_BITSLICE) return *why = "unknown mono_mode", false;
   return true;
 }
 
@@ -125,8 +126,23 @@ struct DevVec {            // library-owned growable device array
 
 }  // namespace
 
+// Kernel classes timed by the profiler.
+enum KClass { KC_MONO = 0, KC_FILL, KC_BUILD, KC_U2_COUNT, KC_SCAN, KC_U2_WRITE, KC_M_REDUCE, KC_M_DECIDE,
+              KC_M_WRITE, KC_COUNT };
+static const char* const kClassNames[KC_COUNT] = {"mono_pass", "index_fill", "index_build", "u2_count",
+                                                  "block_scan", "u2_write", "measure_reduce", "measure_decide",
+                                                  "measure_write"};
+
 struct sim_t {
   sim_config cfg;
+  // profiling
+  bool profile = false;
+  std::vector<hipEvent_t> ev_pool;
+  size_t ev_used = 0;
+  std::vector<std::pair<int, size_t>> ev_pending;   // (class, index of start event)
+  uint64_t k_launches[KC_COUNT] = {};
+  double k_ms[KC_COUNT] = {};
+  uint64_t mono_bytes_base = 0, mono_updates = 0;
   hipStream_t stream;
   bool wide;
   char* ws;
@@ -141,6 +157,16 @@ struct sim_t {
   uint64_t* h_pinned;          // [0] nnz readback, [1..] scratch
   Ctl* h_ctl;                  // pinned mirror of ctl
   DevVec<MonoDesc> descs;
+  // bit-sliced bytecode of the current call, per phase/permutation op
+  struct BsGate {
+    bool eligible, phase, turns;
+    uint8_t words_read, words_write, g_omega;
+    uint64_t g_turn;
+  };
+  DevVec<BsOp> bs_ops;
+  std::vector<BsOp> h_bs;
+  std::vector<uint32_t> bs_start;
+  std::vector<BsGate> bs_gate;
   DevVec<MeasRec> recs;
   DevVec<int32_t> outcomes;
   std::vector<MonoDesc> h_descs;
@@ -153,6 +179,46 @@ struct sim_t {
 namespace {
 
 int block_of(const sim_t* s) { return s->cfg.block ? (int)s->cfg.block : 256; }
+
+// Profiler: bracket a launch with two events from the pool.
+hipEvent_t next_event(sim_t* s) {
+  if (s->ev_used == s->ev_pool.size()) {
+    hipEvent_t e;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    s->ev_pool.push_back(e);
+  }
+  return s->ev_pool[s->ev_used++];
+}
+
+struct KTimer {
+  sim_t* s;
+  int cls;
+  size_t idx = 0;
+  bool on = false;
+  KTimer(sim_t* s_, int c) : s(s_), cls(c) {
+    s->k_launches[c]++;
+    if (!s->profile) return;
+    idx = s->ev_used;
+    hipEvent_t e = next_event(s);
+    on = e && hipEventRecord(e, s->stream) == hipSuccess;
+  }
+  ~KTimer() {
+    if (!on) return;
+    hipEvent_t e = next_event(s);
+    if (e && hipEventRecord(e, s->stream) == hipSuccess) s->ev_pending.emplace_back(cls, idx);
+  }
+};
+
+// After a stream synchronisation: fold pending event pairs into the totals.
+void resolve_events(sim_t* s) {
+  for (const auto& p : s->ev_pending) {
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, s->ev_pool[p.second], s->ev_pool[p.second + 1]) == hipSuccess)
+      s->k_ms[p.first] += ms;
+  }
+  s->ev_pending.clear();
+  s->ev_used = 0;
+}
 
 int mono_grid(const sim_t* s, uint64_t n) {
   const uint64_t per = (uint64_t)block_of(s) * 4;
@@ -175,6 +241,7 @@ uint64_t* d_nnz(sim_t* s, int b) { return &s->ctl->nnz[b]; }
 int read_nnz(sim_t* s, uint64_t* out) {
   HIP_TRY(hipMemcpyAsync(s->h_pinned, d_nnz(s, s->cur), 8, hipMemcpyDeviceToHost, s->stream));
   HIP_TRY(hipStreamSynchronize(s->stream));
+  resolve_events(s);
   *out = s->h_pinned[0];
   s->nnz_known = true;
   s->nnz_exact = s->nnz_ub = *out;
@@ -231,6 +298,131 @@ MonoDesc mono_desc(const sim_gate& g) {
   return d;
 }
 
+// ---- bit-sliced pass compilation ---------------------------------------------
+// Exact eighth-turn factors omega^k = e^{i pi k / 4}; -1 if m is not one.
+int omega_index(const double2& m) {
+  const double h = M_SQRT1_2;
+  const double re[8] = {1.0, h, 0.0, -h, -1.0, -h, 0.0, h};
+  const double im[8] = {0.0, h, 1.0, h, 0.0, -h, -1.0, -h};
+  for (int k = 0; k < 8; ++k)
+    if (m.x == re[k] && m.y == im[k]) return k;
+  return -1;
+}
+
+bool unit_modulus(const double2& m) { return std::fabs(m.x * m.x + m.y * m.y - 1.0) <= 1e-14; }
+
+// Argument of m as a turn fraction in units of 2^-64 turn (wraps exactly).
+uint64_t turn_of(const double2& m) {
+  const long double tau = (long double)std::atan2(m.y, m.x) / (2.0L * (long double)M_PI);   // [-1/2, 1/2]
+  long double v = tau * 18446744073709551616.0L;
+  if (v >= 9223372036854775807.0L) v -= 18446744073709551616.0L;
+  return (uint64_t)(int64_t)std::llroundl(v);
+}
+
+uint8_t word_bit(uint32_t q) { return (uint8_t)(1u << (q >> 5)); }
+
+// Per op: a factor m0 on labels with the target bit 0 and m1 with it 1 equals
+// m0 everywhere (under the controls) times m1/m0 where the target bit is 1.
+void compile_bitslice(sim_t* s, size_t n_mono) {
+  s->h_bs.clear();
+  s->bs_start.assign(n_mono + 1, 0);
+  s->bs_gate.assign(n_mono, sim_t::BsGate{});
+  for (size_t k = 0; k < n_mono; ++k) {
+    const MonoDesc& d = s->h_descs[k];
+    sim_t::BsGate& inf = s->bs_gate[k];
+    s->bs_start[k] = (uint32_t)s->h_bs.size();
+    inf.eligible = true;
+    BsOp base{};
+    base.target = (uint8_t)d.target;
+    uint8_t rd = 0;
+    for (int w = 0; w < 2; ++w) {
+      uint64_t m = w ? d.ctrl_hi : d.ctrl_lo;
+      while (m) {
+        const uint32_t q = (uint32_t)__builtin_ctzll(m) + 64u * w;
+        m &= m - 1;
+        if (base.nctrl == kBsMaxCtrl) {
+          inf.eligible = false;
+          break;
+        }
+        base.ctrl[base.nctrl++] = (uint8_t)q;
+        rd |= word_bit(q);
+      }
+    }
+    if (!inf.eligible) continue;
+    auto emit = [&](uint8_t op, uint8_t cmode, uint64_t arg) {
+      BsOp o = base;
+      o.op = op;
+      o.cmode = cmode;
+      o.arg = arg;
+      s->h_bs.push_back(o);
+      if (cmode) rd |= word_bit(d.target);
+    };
+    if (d.flags & kHasPhase) {
+      const int k0 = omega_index(d.m0), k1 = omega_index(d.m1);
+      if (k0 >= 0 && k1 >= 0) {
+        if (k0) {
+          if (base.nctrl == 0) inf.g_omega = (uint8_t)((inf.g_omega + k0) & 7);
+          else emit(kBsOmega, 0, (uint64_t)k0);
+        }
+        const uint32_t dk = (uint32_t)(k1 - k0) & 7u;
+        if (dk) emit(kBsOmega, 1, dk);
+      } else if (unit_modulus(d.m0) && unit_modulus(d.m1)) {
+        const uint64_t t0 = turn_of(d.m0), t1 = turn_of(d.m1);
+        if (t0) {
+          if (base.nctrl == 0) inf.g_turn += t0;
+          else {
+            emit(kBsTurn, 0, t0);
+            inf.turns = true;
+          }
+        }
+        if (t1 - t0) {
+          emit(kBsTurn, 1, t1 - t0);
+          inf.turns = true;
+        }
+      } else {
+        inf.eligible = false;
+        continue;
+      }
+      inf.phase = true;
+    }
+    if (d.flags & kFlip) {
+      emit(kBsFlip, 0, 0);
+      inf.words_write = word_bit(d.target);
+    }
+    inf.words_read = rd;
+  }
+  s->bs_start[n_mono] = (uint32_t)s->h_bs.size();
+}
+
+bool use_bitslice(sim_t* s, size_t begin, size_t len, BsRun* br) {
+  const uint32_t min_gates = s->cfg.bs_min_gates ? s->cfg.bs_min_gates : 16u;
+  if (s->cfg.mono_mode == SIM_MONO_AUTO && len < min_gates) return false;
+  std::memset(br, 0, sizeof *br);
+  uint32_t g_omega = 0;
+  for (size_t k = begin; k < begin + len; ++k) {
+    const sim_t::BsGate& g = s->bs_gate[k];
+    if (!g.eligible) return false;
+    br->words_read |= g.words_read | g.words_write;
+    br->words_write |= g.words_write;
+    br->has_phase |= g.phase ? 1u : 0u;
+    br->has_turns |= g.turns ? 1u : 0u;
+    g_omega += g.g_omega;
+    br->g_turn += g.g_turn;
+  }
+  if (br->words_write & 3u) br->words_read |= 3u;
+  if (br->words_write & 12u) br->words_read |= 12u;
+  br->g_omega = g_omega & 7u;
+  br->n_planes = s->cfg.n_qubits;
+  br->n_gates = (uint32_t)len;
+  return true;
+}
+
+int bs_grid(const sim_t* s, uint64_t n) {
+  const uint64_t tiles = (n + 2047) / 2048;
+  const uint64_t per_cu = std::max<uint64_t>(1, (160u * 1024u) / ((uint64_t)s->cfg.n_qubits * 256u));
+  return (int)std::max<uint64_t>(1, std::min<uint64_t>(tiles, 256u * per_cu));
+}
+
 // Branching op: index, count, scan, (capacity check), write, swap.
 int run_u2(sim_t* s, const sim_gate& g, bool* over) {
   *over = false;
@@ -255,11 +447,20 @@ int run_u2(sim_t* s, const sim_gate& g, bool* over) {
   d.eps = s->cfg.eps;
   for (int k = 0; k < 4; ++k) d.u[k] = make_double2(g.m[k].re, g.m[k].im);
   const int G = chunk_grid(ub);
-  launch_fill(s->stream, s->table, kEmptySlot, slots);
-  launch_index_build(s->stream, s->wide, s->buf[s->cur], nnz_in, s->table, slots - 1, flat_grid(ub), 256);
+  {
+    KTimer t_(s, KC_FILL);
+    launch_fill(s->stream, s->table, kEmptySlot, slots);
+  }
+  {
+    KTimer t_(s, KC_BUILD);
+    launch_index_build(s->stream, s->wide, s->buf[s->cur], nnz_in, s->table, slots - 1, flat_grid(ub), 256);
+  }
   launch_u2_count(s->stream, s->wide, s->buf[s->cur], nnz_in, s->table, slots - 1, d, s->partner, s->bs.tot, s->ctl,
                   G, 256);
-  launch_scan(s->stream, s->bs.tot, G, d_nnz(s, other), s->ctl);
+  {
+    KTimer t_(s, KC_SCAN);
+    launch_scan(s->stream, s->bs.tot, G, d_nnz(s, other), s->ctl);
+  }
   HIP_TRY(hipGetLastError());
   if (check) {
     HIP_TRY(hipMemcpyAsync(s->h_pinned, d_nnz(s, other), 8, hipMemcpyDeviceToHost, s->stream));
@@ -283,8 +484,14 @@ int run_measure(sim_t* s, uint32_t q, double u, int32_t forced, MeasRec* rec, in
   const int G = chunk_grid(ub);
   const int other = s->cur ^ 1;
   const uint64_t* nnz_in = d_nnz(s, s->cur);
-  launch_measure_reduce(s->stream, s->wide, s->buf[s->cur], nnz_in, q, s->bs, G, 256);
-  launch_measure_decide(s->stream, s->bs, G, nnz_in, d_nnz(s, other), u, forced, rec, outcome, s->ctl);
+  {
+    KTimer t_(s, KC_M_REDUCE);
+    launch_measure_reduce(s->stream, s->wide, s->buf[s->cur], nnz_in, q, s->bs, G, 256);
+  }
+  {
+    KTimer t_(s, KC_M_DECIDE);
+    launch_measure_decide(s->stream, s->bs, G, nnz_in, d_nnz(s, other), u, forced, rec, outcome, s->ctl);
+  }
   HIP_TRY(hipGetLastError());
   if (forced >= 0 || ub == 0) {
     // A forced outcome may have zero probability: decide before touching the state.
@@ -297,7 +504,10 @@ int run_measure(sim_t* s, uint32_t q, double u, int32_t forced, MeasRec* rec, in
       return SIM_OK;
     }
   }
-  launch_measure_write(s->stream, s->wide, s->buf[s->cur], s->buf[other], nnz_in, q, rec, s->bs.tot, G, 256);
+  {
+    KTimer t_(s, KC_M_WRITE);
+    launch_measure_write(s->stream, s->wide, s->buf[s->cur], s->buf[other], nnz_in, q, rec, s->bs.tot, G, 256);
+  }
   HIP_TRY(hipGetLastError());
   s->cur = other;
   s->nnz_known = false;
@@ -308,6 +518,7 @@ int run_measure(sim_t* s, uint32_t q, double u, int32_t forced, MeasRec* rec, in
 int read_ctl(sim_t* s) {
   HIP_TRY(hipMemcpyAsync(s->h_ctl, s->ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s->stream));
   HIP_TRY(hipStreamSynchronize(s->stream));
+  resolve_events(s);
   return SIM_OK;
 }
 
@@ -384,8 +595,10 @@ int sim_destroy(sim_t* s) {
   if (!s) return SIM_OK;
   if (s->stream || s->ws) (void)hipStreamSynchronize(s->stream);
   s->descs.release();
+  s->bs_ops.release();
   s->recs.release();
   s->outcomes.release();
+  for (hipEvent_t e : s->ev_pool) (void)hipEventDestroy(e);
   if (s->h_pinned) (void)hipHostFree(s->h_pinned);
   if (s->h_ctl) (void)hipHostFree(s->h_ctl);
   if (s->ws_owned && s->ws) (void)hipFree(s->ws);
@@ -511,20 +724,48 @@ int sim_apply_gates(sim_t* s, const sim_gate* gates, size_t n, int32_t* outcomes
   s->h_descs.resize(n_mono);
   for (size_t i = 0, k = 0; i < n; ++i)
     if (gates[i].op == SIM_OP_MONO) s->h_descs[k++] = mono_desc(gates[i]);
+  // Bit-sliced bytecode of every phase/permutation op (used by eligible runs).
+  const bool bs_allowed = s->cfg.mono_mode != SIM_MONO_DIRECT;
+  if (bs_allowed) compile_bitslice(s, n_mono);
   HIP_TRY(s->descs.reserve(n_mono));
   HIP_TRY(s->recs.reserve(n_meas));
   HIP_TRY(s->outcomes.reserve(n_meas));
   if (n_mono)
     HIP_TRY(hipMemcpyAsync(s->descs.p, s->h_descs.data(), n_mono * sizeof(MonoDesc), hipMemcpyHostToDevice,
                            s->stream));
+  if (bs_allowed && !s->h_bs.empty()) {
+    HIP_TRY(s->bs_ops.reserve(s->h_bs.size()));
+    HIP_TRY(hipMemcpyAsync(s->bs_ops.p, s->h_bs.data(), s->h_bs.size() * sizeof(BsOp), hipMemcpyHostToDevice,
+                           s->stream));
+  }
 
   int result = SIM_OK;
   size_t run_begin = 0, run_len = 0, mono_seen = 0, meas_seen = 0;
   auto flush = [&]() -> int {
     if (!run_len) return SIM_OK;
     const uint64_t ub = s->nnz_known ? s->nnz_exact : s->nnz_ub;
-    launch_mono(s->stream, s->wide, s->buf[s->cur], d_nnz(s, s->cur), s->descs.p + run_begin, (uint32_t)run_len,
-                &s->ctl->updates, mono_grid(s, ub), block_of(s));
+    uint32_t run_flags = 0;
+    for (size_t k = run_begin; k < run_begin + run_len; ++k) {
+      if (s->h_descs[k].flags & kHasPhase) run_flags |= kRunPhase;
+      if (s->h_descs[k].flags & kFlip) run_flags |= kRunFlip;
+    }
+    // Algorithmic bytes per entry: label read (+ write if a gate flips),
+    // amplitude read and write if a gate has a phase.
+    const uint32_t kb = s->wide ? 16u : 8u;
+    const uint32_t run_bpe = kb + ((run_flags & kRunFlip) ? kb : 0u) + ((run_flags & kRunPhase) ? 32u : 0u);
+    BsRun br;
+    if (bs_allowed && use_bitslice(s, run_begin, run_len, &br)) {
+      br.bytes_per_entry = run_bpe;
+      const uint32_t op0 = s->bs_start[run_begin], nops = s->bs_start[run_begin + run_len] - op0;
+      KTimer t_(s, KC_MONO);
+      launch_mono_bs(s->stream, s->buf[s->cur], d_nnz(s, s->cur), s->bs_ops.p + op0, nops, br, s->ctl,
+                     bs_grid(s, ub));
+      st.bitslice_passes++;
+    } else {
+      KTimer t_(s, KC_MONO);
+      launch_mono(s->stream, s->wide, s->buf[s->cur], d_nnz(s, s->cur), s->descs.p + run_begin, (uint32_t)run_len,
+                  run_flags, run_bpe, s->ctl, mono_grid(s, ub), block_of(s));
+    }
     HIP_TRY(hipGetLastError());
     st.mono_passes++;
     run_begin += run_len;
@@ -689,6 +930,61 @@ int sim_device_state(sim_t* s, uint64_t** key_lo, uint64_t** key_hi, double** am
   if (key_hi) *key_hi = b.key_hi;
   if (amp) *amp = reinterpret_cast<double*>(b.amp);
   if (dn) *dn = d_nnz(s, s->cur);
+  return SIM_OK;
+}
+
+int sim_set_tuning(sim_t* s, const sim_config* t) {
+  if (!s || !t) return fail(SIM_E_ARG, "null argument");
+  if (t->block != 0 && t->block != 64 && t->block != 128 && t->block != 256)
+    return fail(SIM_E_ARG, "block must be 64, 128 or 256");
+  if (t->mono_mode > SIM_MONO_BITSLICE) return fail(SIM_E_ARG, "unknown mono_mode");
+  if (t->load_factor != 0.0 && !(t->load_factor > 0.0 && t->load_factor <= 0.9))
+    return fail(SIM_E_ARG, "load_factor must be in (0, 0.9]");
+  s->cfg.fuse_max = t->fuse_max ? t->fuse_max : 65536;
+  s->cfg.block = t->block;
+  s->cfg.mono_mode = t->mono_mode;
+  s->cfg.bs_min_gates = t->bs_min_gates;
+  if (t->load_factor >= lf_of(&s->cfg)) s->cfg.load_factor = t->load_factor;
+  return SIM_OK;
+}
+
+int sim_set_profiling(sim_t* s, int on) {
+  if (!s) return fail(SIM_E_ARG, "null handle");
+  HIP_TRY(hipStreamSynchronize(s->stream));
+  resolve_events(s);
+  s->profile = on != 0;
+  return SIM_OK;
+}
+
+int sim_kernel_stats(sim_t* s, sim_kernel_stat* out, int cap, int* n) {
+  if (!s || !n) return fail(SIM_E_ARG, "null argument");
+  int rc = read_ctl(s);
+  if (rc) return rc;
+  *n = KC_COUNT;
+  for (int c = 0; c < KC_COUNT && c < cap; ++c) {
+    sim_kernel_stat& k = out[c];
+    std::memset(&k, 0, sizeof k);
+    std::snprintf(k.name, sizeof k.name, "%s", kClassNames[c]);
+    k.launches = s->k_launches[c];
+    k.total_ms = s->k_ms[c];
+    if (c == KC_MONO) {
+      k.alg_bytes = (double)(s->h_ctl->mono_bytes - s->mono_bytes_base);
+      k.updates = (double)(s->h_ctl->mono_updates - s->mono_updates);
+    }
+  }
+  return SIM_OK;
+}
+
+int sim_kernel_stats_reset(sim_t* s) {
+  if (!s) return fail(SIM_E_ARG, "null handle");
+  int rc = read_ctl(s);
+  if (rc) return rc;
+  for (int c = 0; c < KC_COUNT; ++c) {
+    s->k_launches[c] = 0;
+    s->k_ms[c] = 0.0;
+  }
+  s->mono_bytes_base = s->h_ctl->mono_bytes;
+  s->mono_updates = s->h_ctl->mono_updates;
   return SIM_OK;
 }
 

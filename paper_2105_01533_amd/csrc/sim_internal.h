@@ -29,6 +29,35 @@ struct MonoDesc {
 };
 static_assert(sizeof(MonoDesc) == 64, "MonoDesc is 64 bytes");
 constexpr uint32_t kHasPhase = 1u, kFlip = 2u;
+// Run-level flags of a fused pass: some gate multiplies amplitudes / flips labels.
+constexpr uint32_t kRunPhase = 1u, kRunFlip = 2u;
+
+// Bit-sliced pass bytecode: one op per plane update.
+//   kBsFlip:  plane[target] ^= AND(control planes)
+//   kBsOmega: 3-bit counter += arg (eighths of a turn) where the condition holds
+//   kBsTurn:  per-entry turn accumulator += arg (turn * 2^64) where it holds
+// condition = AND(control planes) [& plane[target] when cmode == 1].
+constexpr uint8_t kBsFlip = 0, kBsOmega = 1, kBsTurn = 2;
+constexpr int kBsMaxCtrl = 4;
+struct BsOp {
+  uint8_t op, target, nctrl, cmode;
+  uint8_t ctrl[kBsMaxCtrl];
+  uint64_t arg;
+};
+static_assert(sizeof(BsOp) == 16, "BsOp is 16 bytes");
+
+// Run-level parameters of a bit-sliced pass.
+struct BsRun {
+  uint32_t n_planes;           // LDS planes per wave (= qubit count)
+  uint32_t n_gates;            // gates in the run (update accounting)
+  uint32_t words_read;         // 32-bit label words to transpose in (bit w = qubits 32w..32w+31)
+  uint32_t words_write;        // label words to write back
+  uint32_t has_phase;          // amplitudes change
+  uint32_t has_turns;          // some kBsTurn op (per-entry 64-bit accumulators)
+  uint32_t g_omega;            // entry-independent eighths of a turn
+  uint32_t bytes_per_entry;    // algorithmic bytes per entry (accounting)
+  uint64_t g_turn;             // entry-independent turn fraction * 2^64
+};
 
 // Branching 2x2 gate (Eq. 2), passed by value.
 struct U2Desc {
@@ -44,6 +73,8 @@ struct Ctl {
   uint64_t updates;            // sum over applied gates of nnz at input
   uint64_t peak;
   uint64_t pruned;
+  uint64_t mono_bytes;         // algorithmic bytes of the fused phase/permutation passes
+  uint64_t mono_updates;       // gate-entry updates of the fused passes
   uint32_t error;              // nonzero: a measurement had no valid outcome
   uint32_t pad;
 };
@@ -64,7 +95,9 @@ struct BlockScratch {
 // ---- launchers (sim_kernels.hip) -------------------------------------------
 void launch_set_basis(hipStream_t st, Buf b, uint64_t* nnz, uint64_t lo, uint64_t hi);
 void launch_mono(hipStream_t st, bool wide, Buf b, const uint64_t* nnz, const MonoDesc* g, uint32_t ng,
-                 uint64_t* updates, int grid, int block);
+                 uint32_t run_flags, uint32_t bytes_per_entry, Ctl* ctl, int grid, int block);
+void launch_mono_bs(hipStream_t st, Buf b, const uint64_t* nnz, const BsOp* ops, uint32_t nops, const BsRun& run,
+                    Ctl* ctl, int grid);
 void launch_fill(hipStream_t st, uint64_t* p, uint64_t v, uint64_t n);
 void launch_index_build(hipStream_t st, bool wide, Buf b, const uint64_t* nnz, uint64_t* table, uint64_t mask,
                         int grid, int block);

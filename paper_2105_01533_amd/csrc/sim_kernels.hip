@@ -104,10 +104,15 @@ __global__ void k_fill(uint64_t* __restrict__ p, uint64_t v, uint64_t n) {
 // write of the entry per run.  Gate descriptors are wave-uniform.
 template <bool WIDE, int ITEMS>
 __global__ __launch_bounds__(256) void k_mono(Buf b, const uint64_t* __restrict__ nnz_p,
-                                              const MonoDesc* __restrict__ g, uint32_t ng,
-                                              unsigned long long* updates) {
+                                              const MonoDesc* __restrict__ g, uint32_t ng, uint32_t rf,
+                                              uint32_t bpe, Ctl* ctl) {
   const uint64_t n = *nnz_p;
-  if (blockIdx.x == 0 && threadIdx.x == 0) atomicAdd(updates, (unsigned long long)(n * ng));
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    atomicAdd((unsigned long long*)&ctl->updates, (unsigned long long)(n * ng));
+    atomicAdd((unsigned long long*)&ctl->mono_bytes, (unsigned long long)(n * bpe));
+    atomicAdd((unsigned long long*)&ctl->mono_updates, (unsigned long long)(n * ng));
+  }
+  const bool run_phase = rf & kRunPhase, run_flip = rf & kRunFlip;
   const uint64_t stride = (uint64_t)gridDim.x * blockDim.x * ITEMS;
   for (uint64_t base = (uint64_t)blockIdx.x * blockDim.x * ITEMS; base < n; base += stride) {
     uint64_t lo[ITEMS], hi[ITEMS];
@@ -118,7 +123,7 @@ __global__ __launch_bounds__(256) void k_mono(Buf b, const uint64_t* __restrict_
       const bool ok = idx < n;
       lo[i] = ok ? b.key_lo[idx] : 0ull;
       hi[i] = (WIDE && ok) ? b.key_hi[idx] : 0ull;
-      a[i] = ok ? b.amp[idx] : make_double2(0.0, 0.0);
+      a[i] = (ok && run_phase) ? b.amp[idx] : make_double2(0.0, 0.0);
     }
     for (uint32_t j = 0; j < ng; ++j) {
       const MonoDesc d = g[j];
@@ -148,9 +153,11 @@ __global__ __launch_bounds__(256) void k_mono(Buf b, const uint64_t* __restrict_
     for (int i = 0; i < ITEMS; ++i) {
       const uint64_t idx = base + (uint64_t)i * blockDim.x + threadIdx.x;
       if (idx < n) {
-        b.key_lo[idx] = lo[i];
-        if (WIDE) b.key_hi[idx] = hi[i];
-        b.amp[idx] = a[i];
+        if (run_flip) {
+          b.key_lo[idx] = lo[i];
+          if (WIDE) b.key_hi[idx] = hi[i];
+        }
+        if (run_phase) b.amp[idx] = a[i];
       }
     }
   }
@@ -510,12 +517,13 @@ void launch_fill(hipStream_t st, uint64_t* p, uint64_t v, uint64_t n) {
 }
 
 void launch_mono(hipStream_t st, bool wide, Buf b, const uint64_t* nnz, const MonoDesc* g, uint32_t ng,
-                 uint64_t* updates, int grid, int block) {
-  auto* up = reinterpret_cast<unsigned long long*>(updates);
+                 uint32_t run_flags, uint32_t bytes_per_entry, Ctl* ctl, int grid, int block) {
   if (wide)
-    hipLaunchKernelGGL((k_mono<true, 4>), dim3(grid), dim3(block), 0, st, b, nnz, g, ng, up);
+    hipLaunchKernelGGL((k_mono<true, 4>), dim3(grid), dim3(block), 0, st, b, nnz, g, ng, run_flags, bytes_per_entry,
+                       ctl);
   else
-    hipLaunchKernelGGL((k_mono<false, 4>), dim3(grid), dim3(block), 0, st, b, nnz, g, ng, up);
+    hipLaunchKernelGGL((k_mono<false, 4>), dim3(grid), dim3(block), 0, st, b, nnz, g, ng, run_flags, bytes_per_entry,
+                       ctl);
 }
 
 void launch_index_build(hipStream_t st, bool wide, Buf b, const uint64_t* nnz, uint64_t* table, uint64_t mask,

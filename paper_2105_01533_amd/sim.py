@@ -24,6 +24,7 @@ LIB_PATH = os.path.join(_HERE, "libsparsesim.so")
 
 SIM_OK, SIM_E_ARG, SIM_E_NOMEM, SIM_E_CAPACITY, SIM_E_BUFFER, SIM_E_HIP, SIM_E_STATE = 0, -1, -2, -3, -4, -5, -6
 SIM_OP_MONO, SIM_OP_U2, SIM_OP_MEASURE = 0, 1, 2
+SIM_MONO_AUTO, SIM_MONO_DIRECT, SIM_MONO_BITSLICE = 0, 1, 2
 
 GATE_DTYPE = np.dtype([
     ("op", "<u4"), ("target", "<u4"), ("ctrl_lo", "<u8"), ("ctrl_hi", "<u8"),
@@ -37,13 +38,13 @@ KEY_DTYPE = np.dtype([("lo", "<u8"), ("hi", "<u8")])
 class sim_config(ctypes.Structure):
     _fields_ = [("n_qubits", ctypes.c_uint32), ("fuse_max", ctypes.c_uint32), ("capacity", ctypes.c_uint64),
                 ("eps", ctypes.c_double), ("load_factor", ctypes.c_double), ("block", ctypes.c_uint32),
-                ("flags", ctypes.c_uint32)]
+                ("flags", ctypes.c_uint32), ("mono_mode", ctypes.c_uint32), ("bs_min_gates", ctypes.c_uint32)]
 
 
 class sim_stats(ctypes.Structure):
     _fields_ = [(f, ctypes.c_uint64) for f in (
         "gates_applied", "updates", "mono_passes", "u2_applied", "u2_skipped", "measures", "host_syncs",
-        "peak_nnz", "pruned")]
+        "peak_nnz", "pruned", "bitslice_passes")]
 
     def as_dict(self):
         return {f: int(getattr(self, f)) for f, _ in self._fields_}
@@ -51,6 +52,11 @@ class sim_stats(ctypes.Structure):
 
 class sim_key(ctypes.Structure):
     _fields_ = [("lo", ctypes.c_uint64), ("hi", ctypes.c_uint64)]
+
+
+class sim_kernel_stat(ctypes.Structure):
+    _fields_ = [("name", ctypes.c_char * 32), ("launches", ctypes.c_uint64), ("total_ms", ctypes.c_double),
+                ("alg_bytes", ctypes.c_double), ("updates", ctypes.c_double)]
 
 
 class SimError(RuntimeError):
@@ -79,6 +85,10 @@ def _load():
         "sim_sync": (i32, [vp]),
         "sim_export_state": (i32, [vp, vp, vp, u64, ctypes.POINTER(u64)]),
         "sim_device_state": (i32, [vp, vp, vp, vp, vp]),
+        "sim_set_tuning": (i32, [vp, vp]),
+        "sim_set_profiling": (i32, [vp, ctypes.c_int]),
+        "sim_kernel_stats": (i32, [vp, vp, ctypes.c_int, ctypes.POINTER(ctypes.c_int)]),
+        "sim_kernel_stats_reset": (i32, [vp]),
         "sim_strerror": (ctypes.c_char_p, [ctypes.c_int]),
         "sim_last_error": (ctypes.c_char_p, []),
     }
@@ -209,14 +219,41 @@ def sim_device_state(h):
     return lo.value, hi.value, amp.value, nnz.value
 
 
+def sim_set_tuning(h, fuse_max: int = 0, block: int = 0, mono_mode: int = 0, bs_min_gates: int = 0,
+                   load_factor: float = 0.0):
+    t = sim_config(fuse_max=fuse_max, block=block, mono_mode=mono_mode, bs_min_gates=bs_min_gates,
+                   load_factor=load_factor)
+    _check(_lib.sim_set_tuning(h, ctypes.byref(t)), "sim_set_tuning")
+
+
+def sim_set_profiling(h, on: bool):
+    _check(_lib.sim_set_profiling(h, int(bool(on))), "sim_set_profiling")
+
+
+def sim_kernel_stats(h) -> dict:
+    """{class name: {launches, total_ms, alg_bytes, updates}}."""
+    arr = (sim_kernel_stat * 32)()
+    n = ctypes.c_int()
+    _check(_lib.sim_kernel_stats(h, arr, 32, ctypes.byref(n)), "sim_kernel_stats")
+    return {arr[i].name.decode(): {"launches": int(arr[i].launches), "total_ms": arr[i].total_ms,
+                                   "alg_bytes": arr[i].alg_bytes, "updates": arr[i].updates}
+            for i in range(min(n.value, 32))}
+
+
+def sim_kernel_stats_reset(h):
+    _check(_lib.sim_kernel_stats_reset(h), "sim_kernel_stats_reset")
+
+
 # --- convenience wrapper -----------------------------------------------------
 class Simulator:
     """One sparse state on the current torch device and stream."""
 
     def __init__(self, n_qubits: int, capacity: int, eps: float = 0.0, fuse_max: int = 0,
-                 load_factor: float = 0.0, block: int = 0, device: str = "cuda"):
+                 load_factor: float = 0.0, block: int = 0, mono_mode: int = 0, bs_min_gates: int = 0,
+                 device: str = "cuda"):
         self.cfg = sim_config(n_qubits=n_qubits, fuse_max=fuse_max, capacity=capacity, eps=eps,
-                              load_factor=load_factor, block=block, flags=0)
+                              load_factor=load_factor, block=block, flags=0, mono_mode=mono_mode,
+                              bs_min_gates=bs_min_gates)
         nbytes = sim_workspace_bytes(self.cfg)
         if nbytes == 0:
             raise SimError(SIM_E_ARG, "sim_workspace_bytes")

@@ -83,7 +83,7 @@ def test_hh_identity_prunes(sim):
 @pytest.mark.parametrize("n,seed", [(7, 1), (20, 2), (64, 3), (70, 4), (100, 5), (128, 6)])
 def test_random_circuits(sim, n, seed):
     w = W.random_circuit(seed, n=n, gates=400, h_frac=0.12, ctrl_max=3, measure_frac=0.01)
-    w.capacity = 1 << 16
+    w.capacity = 1 << 20
     check_vs_oracle(sim, w)
 
 
@@ -217,15 +217,74 @@ def test_ragged_sizes(sim, n_entries):
     assert_same_state(g, o.export(), what=f"ragged {n_entries}")
 
 
+# --- bit-sliced fused pass ---------------------------------------------------------------
+@pytest.mark.parametrize("n,seed", [(5, 11), (31, 12), (33, 13), (64, 14), (65, 15), (100, 16), (128, 17)])
+def test_bitslice_random_circuits(sim, n, seed):
+    """Every phase/permutation kind with up to 3 controls through the
+    bit-sliced pass (forced), narrow and wide labels."""
+    w = W.random_circuit(seed, n=n, gates=600, h_frac=0.02, ctrl_max=3, measure_frac=0.005)
+    w.capacity = 1 << 16
+    _, st = check_vs_oracle(sim, w, mono_mode=sim.SIM_MONO_BITSLICE)
+    assert st["bitslice_passes"] > 0
+
+
+@pytest.mark.parametrize("n_entries", [1, 2047, 2048, 2049, 6145, 100_003])
+def test_bitslice_ragged_tiles(sim, n_entries):
+    nq = 100 if n_entries % 2 else 50
+    lo0, hi0, amp0 = W.random_state(7 * n_entries, n_entries, nq)
+    rng = W.SplitMix64(n_entries + 5)
+    c = W.Circuit()
+    for _ in range(400):
+        W._random_mono(rng, c, nq, 0.7, 0.3, 0)
+    c.gate(W.K_Y, 3, (7,))
+    c.gate(W.K_PHASE, nq - 2, (2, 9), param=0.77)
+    c.gate(W.K_RZ, nq - 1, (0, 1, 2, 4), param=-2.5)
+    ops = c.array()
+    from paper_2105_01533_amd.sim import Simulator, SIM_MONO_BITSLICE
+    s = Simulator(nq, n_entries, 0.0, mono_mode=SIM_MONO_BITSLICE)
+    s.import_state(lo0, hi0, amp0)
+    say(f"[gpu] bitslice ragged n={n_entries}")
+    _, _, st = s.apply_ops(ops)
+    g = s.export()
+    s.close()
+    assert st["bitslice_passes"] == 1
+    o = Oracle(nq, 0.0)
+    o.import_state(lo0, hi0, amp0)
+    o.run(ops)
+    assert_same_state(g, o.export(), what=f"bitslice ragged {n_entries}")
+
+
+def test_bitslice_full_configs(sim):
+    check_vs_oracle(sim, W.config0(), mono_mode=sim.SIM_MONO_BITSLICE)
+    check_vs_oracle(sim, W.config1(5, w=10, adds=12, n=64), mono_mode=sim.SIM_MONO_BITSLICE)
+    check_vs_oracle(sim, W.config2(6, n=100, h_qubits=12, gates=20000, round_gates=4000, meas_per_round=4),
+                    mono_mode=sim.SIM_MONO_BITSLICE)
+    check_vs_oracle(sim, W.config3(7, terms=80), mono_mode=sim.SIM_MONO_BITSLICE)
+
+
+def test_direct_mode_full_configs(sim):
+    check_vs_oracle(sim, W.config0(), mono_mode=sim.SIM_MONO_DIRECT)
+    check_vs_oracle(sim, W.config2(6, n=100, h_qubits=12, gates=20000, round_gates=4000, meas_per_round=4),
+                    mono_mode=sim.SIM_MONO_DIRECT)
+
+
 # --- launch-shape independence and determinism --------------------------------------
 def test_tuning_knobs_do_not_change_results(sim):
+    """Launch shapes and index load factor leave results bitwise unchanged for
+    a given fused-pass kernel; switching kernels changes rounding only."""
     w = W.config2(31, n=100, h_qubits=11, gates=6000, round_gates=2000, meas_per_round=3)
-    ref, _, _ = gpu_run(sim, w)
-    for kw in [dict(fuse_max=1), dict(fuse_max=7), dict(block=64), dict(block=128), dict(load_factor=0.25),
-               dict(load_factor=0.9)]:
-        g, _, _ = gpu_run(sim, w, **kw)
-        for a, b in zip(ref, g):
-            assert a.tobytes() == b.tobytes(), kw
+    for mode in (sim.SIM_MONO_DIRECT, sim.SIM_MONO_BITSLICE):
+        ref, _, _ = gpu_run(sim, w, mono_mode=mode)
+        knobs = [dict(block=64), dict(block=128), dict(load_factor=0.25), dict(load_factor=0.9)]
+        if mode == sim.SIM_MONO_DIRECT:
+            knobs.append(dict(fuse_max=7))       # per-entry products: run boundaries do not matter
+        for kw in knobs:
+            g, _, _ = gpu_run(sim, w, mono_mode=mode, **kw)
+            for a, b in zip(ref, g):
+                assert a.tobytes() == b.tobytes(), (mode, kw)
+    d, _, _ = gpu_run(sim, w, mono_mode=sim.SIM_MONO_DIRECT, fuse_max=1)
+    b, _, _ = gpu_run(sim, w, mono_mode=sim.SIM_MONO_BITSLICE)
+    assert_same_state(d, b, what="direct vs bit-sliced")
 
 
 # --- errors and edge cases ------------------------------------------------------------
