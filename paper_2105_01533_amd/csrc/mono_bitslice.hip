@@ -101,15 +101,45 @@ __device__ __forceinline__ double2 omega_pow(uint32_t k) {
   return make_double2(re, im);
 }
 
+// One op of a group: fields broadcast from the lane that loaded it.
+struct OpS {
+  uint32_t op, t, p0, p1, p2, k;
+  uint64_t tau;
+};
+
+__device__ __forceinline__ OpS op_from_lane(const uint4& v, int src) {
+  const uint32_t x = __builtin_amdgcn_readlane(v.x, src);
+  const uint32_t y = __builtin_amdgcn_readlane(v.y, src);
+  const uint32_t z = __builtin_amdgcn_readlane(v.z, src);
+  const uint32_t w = __builtin_amdgcn_readlane(v.w, src);
+  OpS o;
+  o.op = x & 0xffu;
+  o.t = ((x >> 8) & 0xffu) * 64u;
+  o.p0 = ((x >> 16) & 0xffu) * 64u;
+  o.p1 = (x >> 24) * 64u;
+  o.p2 = (y & 0xffu) * 64u;
+  o.k = (y >> 8) & 0xffu;
+  o.tau = ((uint64_t)w << 32) | z;
+  return o;
+}
+
+// Ops arrive 64 at a time, one per lane (one vector load per 64 ops, the next
+// batch in flight while the current one is used); each group of kBsGroup ops
+// is broadcast with readlane, all its plane reads are issued, then it computes
+// and writes.  The LDS holds nq label planes, an all-ones plane (index nq) that
+// unused condition slots name, and a scratch plane (nq + 1) for padding ops.
 template <bool TURNS>
 __global__ __launch_bounds__(64) void k_mono_bs(Buf b, const uint64_t* __restrict__ nnz_p,
-                                                const BsOp* __restrict__ ops, uint32_t nops, BsRun run,
+                                                const BsOpG* __restrict__ ops, uint32_t ngroups, BsRun run,
                                                 Ctl* ctl) {
   extern __shared__ uint32_t lds_all[];
   const int lane = threadIdx.x;
   uint32_t* L = lds_all + lane;
   const uint64_t n = *nnz_p;
   const int nq = (int)run.n_planes;
+  const uint4* opv = reinterpret_cast<const uint4*>(ops);
+  const uint32_t nops = ngroups * kBsGroup;
+  L[nq * 64] = ~0u;
   if (blockIdx.x == 0 && lane == 0) {
     atomicAdd((unsigned long long*)&ctl->updates, (unsigned long long)(n * run.n_gates));
     atomicAdd((unsigned long long*)&ctl->mono_updates, (unsigned long long)(n * run.n_gates));
@@ -126,28 +156,40 @@ __global__ __launch_bounds__(64) void k_mono_bs(Buf b, const uint64_t* __restric
     uint64_t turns[TURNS ? 32 : 1];
 #pragma unroll
     for (int j = 0; j < (TURNS ? 32 : 1); ++j) turns[j] = 0;
-    for (uint32_t i = 0; i < nops; ++i) {
-      const BsOp op = ops[i];
-      uint32_t cond = ~0u;
-      if (op.nctrl > 0) cond &= L[op.ctrl[0] * 64u];
-      if (op.nctrl > 1) cond &= L[op.ctrl[1] * 64u];
-      if (op.nctrl > 2) cond &= L[op.ctrl[2] * 64u];
-      if (op.nctrl > 3) cond &= L[op.ctrl[3] * 64u];
-      if (op.op == kBsFlip) {
-        L[op.target * 64u] ^= cond;
-      } else {
-        const uint32_t x = op.cmode ? (cond & L[op.target * 64u]) : cond;
-        if (op.op == kBsOmega) {
-          omega_add(e0, e1, e2, x, (uint32_t)op.arg);
-        } else if (TURNS) {
-          const uint32_t tlo = (uint32_t)op.arg, thi = (uint32_t)(op.arg >> 32);
+    uint4 cur = lane < (int)nops ? opv[lane] : make_uint4(0, 0, 0, 0);
+    for (uint32_t b0 = 0; b0 < nops; b0 += 64) {
+      const uint4 nxt = b0 + 64 + lane < nops ? opv[b0 + 64 + lane] : make_uint4(0, 0, 0, 0);
+      const uint32_t gend = (nops - b0 < 64 ? nops - b0 : 64);
+      for (uint32_t g = 0; g < gend; g += kBsGroup) {
+        OpS o[kBsGroup];
+        uint32_t cond[kBsGroup], tv[kBsGroup];
 #pragma unroll
-          for (int j = 0; j < 32; ++j) {
-            const uint32_t m = (uint32_t)(-(int32_t)((x >> j) & 1u));
-            turns[j] += ((uint64_t)(thi & m) << 32) | (tlo & m);
+        for (int u = 0; u < kBsGroup; ++u) o[u] = op_from_lane(cur, g + u);
+#pragma unroll
+        for (int u = 0; u < kBsGroup; ++u) {
+          cond[u] = L[o[u].p0] & L[o[u].p1] & L[o[u].p2];
+          tv[u] = L[o[u].t];
+        }
+        // Every op writes its plane t: flips xor the condition in, phase ops
+        // name the all-ones plane and write it back unchanged.
+#pragma unroll
+        for (int u = 0; u < kBsGroup; ++u) L[o[u].t] = tv[u] ^ (o[u].op == kBsFlip ? cond[u] : 0u);
+#pragma unroll
+        for (int u = 0; u < kBsGroup; ++u) {
+          if (o[u].op == kBsFlip) {
+          } else if (o[u].op == kBsOmega) {
+            omega_add(e0, e1, e2, cond[u], o[u].k);
+          } else if (TURNS) {
+            const uint32_t tlo = (uint32_t)o[u].tau, thi = (uint32_t)(o[u].tau >> 32);
+#pragma unroll
+            for (int j = 0; j < 32; ++j) {
+              const uint32_t m = (uint32_t)(-(int32_t)((cond[u] >> j) & 1u));
+              turns[j] += ((uint64_t)(thi & m) << 32) | (tlo & m);
+            }
           }
         }
       }
+      cur = nxt;
     }
     // Labels back to memory (only words some gate flips).
     if (run.words_write & 3u) store_pair(b.key_lo + base + lane, lim, L, 0, nq);
@@ -176,13 +218,13 @@ __global__ __launch_bounds__(64) void k_mono_bs(Buf b, const uint64_t* __restric
 
 }  // namespace
 
-void launch_mono_bs(hipStream_t st, Buf b, const uint64_t* nnz, const BsOp* ops, uint32_t nops, const BsRun& run,
+void launch_mono_bs(hipStream_t st, Buf b, const uint64_t* nnz, const BsOpG* ops, uint32_t ngroups, const BsRun& run,
                     Ctl* ctl, int grid) {
-  const size_t lds = (size_t)run.n_planes * 64 * 4;
+  const size_t lds = (size_t)(run.n_planes + 2) * 64 * 4;
   if (run.has_turns)
-    hipLaunchKernelGGL(k_mono_bs<true>, dim3(grid), dim3(64), lds, st, b, nnz, ops, nops, run, ctl);
+    hipLaunchKernelGGL(k_mono_bs<true>, dim3(grid), dim3(64), lds, st, b, nnz, ops, ngroups, run, ctl);
   else
-    hipLaunchKernelGGL(k_mono_bs<false>, dim3(grid), dim3(64), lds, st, b, nnz, ops, nops, run, ctl);
+    hipLaunchKernelGGL(k_mono_bs<false>, dim3(grid), dim3(64), lds, st, b, nnz, ops, ngroups, run, ctl);
 }
 
 }  // namespace sparsesim

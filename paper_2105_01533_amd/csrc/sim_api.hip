@@ -163,7 +163,8 @@ struct sim_t {
     uint8_t words_read, words_write, g_omega;
     uint64_t g_turn;
   };
-  DevVec<BsOp> bs_ops;
+  DevVec<BsOpG> grp_ops;
+  std::vector<BsOpG> h_grp;
   std::vector<BsOp> h_bs;
   std::vector<uint32_t> bs_start;
   std::vector<BsGate> bs_gate;
@@ -356,6 +357,7 @@ void compile_bitslice(sim_t* s, size_t n_mono) {
       o.arg = arg;
       s->h_bs.push_back(o);
       if (cmode) rd |= word_bit(d.target);
+      if (base.nctrl + cmode > 3) inf.eligible = false;   // three condition slots per op
     };
     if (d.flags & kHasPhase) {
       const int k0 = omega_index(d.m0), k1 = omega_index(d.m1);
@@ -417,6 +419,60 @@ bool use_bitslice(sim_t* s, size_t begin, size_t len, BsRun* br) {
   return true;
 }
 
+// Pack the ops [op0, op1) into groups of kBsGroup consecutive ops that touch
+// no plane another member of the group writes (so the kernel may read all of
+// a group's planes before any write), padding groups with no-op flips of the
+// scratch plane.  Order is kept across groups; within a group the ops are
+// independent, and phase accumulations commute exactly.
+void group_ops(sim_t* s, uint32_t op0, uint32_t op1) {
+  const uint8_t ones = (uint8_t)s->cfg.n_qubits, scratch = (uint8_t)(s->cfg.n_qubits + 1);
+  struct Mask {
+    uint64_t lo = 0, hi = 0;
+    void set(uint32_t q) { (q < 64 ? lo : hi) |= 1ull << (q & 63); }
+    bool meets(const Mask& o) const { return (lo & o.lo) || (hi & o.hi); }
+    void add(const Mask& o) { lo |= o.lo; hi |= o.hi; }
+  };
+  Mask gr, gw;
+  int in_group = 0;
+  auto close = [&]() {
+    for (; in_group && in_group < kBsGroup; ++in_group) {
+      BsOpG pad{};
+      pad.op = kBsFlip;
+      pad.t = scratch;
+      pad.p0 = pad.p1 = pad.p2 = ones;
+      s->h_grp.push_back(pad);
+    }
+    in_group = 0;
+    gr = Mask{};
+    gw = Mask{};
+  };
+  for (uint32_t i = op0; i < op1; ++i) {
+    const BsOp& o = s->h_bs[i];
+    Mask r, w;
+    for (int c = 0; c < o.nctrl; ++c) r.set(o.ctrl[c]);
+    if (o.cmode || o.op == kBsFlip) r.set(o.target);
+    if (o.op == kBsFlip) w.set(o.target);
+    if (in_group == kBsGroup || w.meets(gr) || w.meets(gw) || r.meets(gw)) close();
+    BsOpG g{};
+    g.op = o.op;
+    g.t = o.op == kBsFlip ? o.target : ones;
+    uint8_t slot[3] = {ones, ones, ones};
+    int ns = 0;
+    for (int c = 0; c < o.nctrl; ++c) slot[ns++] = o.ctrl[c];
+    if (o.cmode) slot[ns++] = o.target;
+    g.p0 = slot[0];
+    g.p1 = slot[1];
+    g.p2 = slot[2];
+    g.k = o.op == kBsOmega ? (uint8_t)o.arg : 0;
+    g.tau = o.op == kBsTurn ? o.arg : 0;
+    s->h_grp.push_back(g);
+    gr.add(r);
+    gw.add(w);
+    ++in_group;
+  }
+  close();
+}
+
 int bs_grid(const sim_t* s, uint64_t n) {
   const uint64_t tiles = (n + 2047) / 2048;
   const uint64_t per_cu = std::max<uint64_t>(1, (160u * 1024u) / ((uint64_t)s->cfg.n_qubits * 256u));
@@ -455,8 +511,11 @@ int run_u2(sim_t* s, const sim_gate& g, bool* over) {
     KTimer t_(s, KC_BUILD);
     launch_index_build(s->stream, s->wide, s->buf[s->cur], nnz_in, s->table, slots - 1, flat_grid(ub), 256);
   }
-  launch_u2_count(s->stream, s->wide, s->buf[s->cur], nnz_in, s->table, slots - 1, d, s->partner, s->bs.tot, s->ctl,
-                  G, 256);
+  {
+    KTimer t_(s, KC_U2_COUNT);
+    launch_u2_count(s->stream, s->wide, s->buf[s->cur], nnz_in, s->table, slots - 1, d, s->partner, s->bs.tot,
+                    s->ctl, G, 256);
+  }
   {
     KTimer t_(s, KC_SCAN);
     launch_scan(s->stream, s->bs.tot, G, d_nnz(s, other), s->ctl);
@@ -470,7 +529,10 @@ int run_u2(sim_t* s, const sim_gate& g, bool* over) {
       return SIM_OK;
     }
   }
-  launch_u2_write(s->stream, s->wide, s->buf[s->cur], s->buf[other], nnz_in, s->partner, s->bs.tot, d, G, 256);
+  {
+    KTimer t_(s, KC_U2_WRITE);
+    launch_u2_write(s->stream, s->wide, s->buf[s->cur], s->buf[other], nnz_in, s->partner, s->bs.tot, d, G, 256);
+  }
   HIP_TRY(hipGetLastError());
   s->cur = other;
   s->nnz_known = false;
@@ -595,7 +657,7 @@ int sim_destroy(sim_t* s) {
   if (!s) return SIM_OK;
   if (s->stream || s->ws) (void)hipStreamSynchronize(s->stream);
   s->descs.release();
-  s->bs_ops.release();
+  s->grp_ops.release();
   s->recs.release();
   s->outcomes.release();
   for (hipEvent_t e : s->ev_pool) (void)hipEventDestroy(e);
@@ -733,10 +795,13 @@ int sim_apply_gates(sim_t* s, const sim_gate* gates, size_t n, int32_t* outcomes
   if (n_mono)
     HIP_TRY(hipMemcpyAsync(s->descs.p, s->h_descs.data(), n_mono * sizeof(MonoDesc), hipMemcpyHostToDevice,
                            s->stream));
-  if (bs_allowed && !s->h_bs.empty()) {
-    HIP_TRY(s->bs_ops.reserve(s->h_bs.size()));
-    HIP_TRY(hipMemcpyAsync(s->bs_ops.p, s->h_bs.data(), s->h_bs.size() * sizeof(BsOp), hipMemcpyHostToDevice,
-                           s->stream));
+  // Grouped kernel ops of the bit-sliced runs, appended run by run; padding
+  // at most triples the count, so reserving up front keeps the host copies
+  // of in-flight uploads in place.
+  s->h_grp.clear();
+  if (bs_allowed) {
+    s->h_grp.reserve(kBsGroup * s->h_bs.size() + kBsGroup);
+    HIP_TRY(s->grp_ops.reserve(kBsGroup * s->h_bs.size() + kBsGroup));
   }
 
   int result = SIM_OK;
@@ -756,9 +821,15 @@ int sim_apply_gates(sim_t* s, const sim_gate* gates, size_t n, int32_t* outcomes
     BsRun br;
     if (bs_allowed && use_bitslice(s, run_begin, run_len, &br)) {
       br.bytes_per_entry = run_bpe;
-      const uint32_t op0 = s->bs_start[run_begin], nops = s->bs_start[run_begin + run_len] - op0;
+      const uint32_t op0 = s->bs_start[run_begin], op1 = s->bs_start[run_begin + run_len];
+      const size_t g0 = s->h_grp.size();
+      group_ops(s, op0, op1);
+      const size_t ng = (s->h_grp.size() - g0) / kBsGroup;
+      if (ng)
+        HIP_TRY(hipMemcpyAsync(s->grp_ops.p + g0, s->h_grp.data() + g0, (s->h_grp.size() - g0) * sizeof(BsOpG),
+                               hipMemcpyHostToDevice, s->stream));
       KTimer t_(s, KC_MONO);
-      launch_mono_bs(s->stream, s->buf[s->cur], d_nnz(s, s->cur), s->bs_ops.p + op0, nops, br, s->ctl,
+      launch_mono_bs(s->stream, s->buf[s->cur], d_nnz(s, s->cur), s->grp_ops.p + g0, (uint32_t)ng, br, s->ctl,
                      bs_grid(s, ub));
       st.bitslice_passes++;
     } else {

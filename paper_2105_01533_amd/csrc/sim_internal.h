@@ -38,13 +38,25 @@ constexpr uint32_t kRunPhase = 1u, kRunFlip = 2u;
 //   kBsTurn:  per-entry turn accumulator += arg (turn * 2^64) where it holds
 // condition = AND(control planes) [& plane[target] when cmode == 1].
 constexpr uint8_t kBsFlip = 0, kBsOmega = 1, kBsTurn = 2;
-constexpr int kBsMaxCtrl = 4;
+constexpr int kBsMaxCtrl = 3;
 struct BsOp {
   uint8_t op, target, nctrl, cmode;
-  uint8_t ctrl[kBsMaxCtrl];
+  uint8_t ctrl[4];
   uint64_t arg;
 };
 static_assert(sizeof(BsOp) == 16, "BsOp is 16 bytes");
+
+// Kernel form of a BsOp: the condition is the AND of three plane slots
+// (p0, p1, p2; unused slots name the all-ones plane), FLIP xors it into plane
+// t.  Ops are issued in groups of kBsGroup whose members touch no plane another
+// member writes, so a group's plane reads can all be in flight at once.
+constexpr int kBsGroup = 4;
+struct BsOpG {
+  uint8_t op, t, p0, p1;
+  uint8_t p2, k, pad0, pad1;
+  uint64_t tau;
+};
+static_assert(sizeof(BsOpG) == 16, "BsOpG is 16 bytes");
 
 // Run-level parameters of a bit-sliced pass.
 struct BsRun {
@@ -96,7 +108,7 @@ struct BlockScratch {
 void launch_set_basis(hipStream_t st, Buf b, uint64_t* nnz, uint64_t lo, uint64_t hi);
 void launch_mono(hipStream_t st, bool wide, Buf b, const uint64_t* nnz, const MonoDesc* g, uint32_t ng,
                  uint32_t run_flags, uint32_t bytes_per_entry, Ctl* ctl, int grid, int block);
-void launch_mono_bs(hipStream_t st, Buf b, const uint64_t* nnz, const BsOp* ops, uint32_t nops, const BsRun& run,
+void launch_mono_bs(hipStream_t st, Buf b, const uint64_t* nnz, const BsOpG* ops, uint32_t ngroups, const BsRun& run,
                     Ctl* ctl, int grid);
 void launch_fill(hipStream_t st, uint64_t* p, uint64_t v, uint64_t n);
 void launch_index_build(hipStream_t st, bool wide, Buf b, const uint64_t* nnz, uint64_t* table, uint64_t mask,
