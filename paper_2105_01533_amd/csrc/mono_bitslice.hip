@@ -170,20 +170,22 @@ __global__ __launch_bounds__(64) void k_mono_bs(Buf b, const uint64_t* __restric
           cond[u] = L[o[u].p0] & L[o[u].p1] & L[o[u].p2];
           tv[u] = L[o[u].t];
         }
-        // Every op writes its plane t: flips xor the condition in, phase ops
-        // name the all-ones plane and write it back unchanged.
+        // Every op writes its plane t: a flip xors the condition in; a phase
+        // op's t is a fourth condition plane (its target bit, or the all-ones
+        // plane) and is written back unchanged.
 #pragma unroll
         for (int u = 0; u < kBsGroup; ++u) L[o[u].t] = tv[u] ^ (o[u].op == kBsFlip ? cond[u] : 0u);
 #pragma unroll
         for (int u = 0; u < kBsGroup; ++u) {
+          const uint32_t x = cond[u] & tv[u];
           if (o[u].op == kBsFlip) {
           } else if (o[u].op == kBsOmega) {
-            omega_add(e0, e1, e2, cond[u], o[u].k);
+            omega_add(e0, e1, e2, x, o[u].k);
           } else if (TURNS) {
             const uint32_t tlo = (uint32_t)o[u].tau, thi = (uint32_t)(o[u].tau >> 32);
 #pragma unroll
             for (int j = 0; j < 32; ++j) {
-              const uint32_t m = (uint32_t)(-(int32_t)((cond[u] >> j) & 1u));
+              const uint32_t m = (uint32_t)(-(int32_t)((x >> j) & 1u));
               turns[j] += ((uint64_t)(thi & m) << 32) | (tlo & m);
             }
           }

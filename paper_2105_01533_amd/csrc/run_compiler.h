@@ -1,0 +1,48 @@
+// Host-side compilation of phase/permutation runs, shared by the single-state
+// engine (sim_api.hip) and the batched server (serve.hip).
+#pragma once
+
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/sparsesim.h"
+#include "sim_internal.h"
+
+namespace sparsesim {
+
+// Per-entry kernel descriptor of a MONO op.
+MonoDesc mono_desc(const sim_gate& g);
+
+// Structural validity of an op for a state of n_qubits (qubits in range,
+// target not a control, measurement arguments, finite coefficients).
+bool gate_valid(uint32_t n_qubits, const sim_gate& g, std::string* why);
+
+bool key_fits(uint32_t n_qubits, uint64_t lo, uint64_t hi);
+
+// What the bit-sliced pass needs to know about one MONO op.
+struct BsGateInfo {
+  bool eligible, phase, turns;
+  uint8_t words_read, words_write, g_omega;
+  uint64_t g_turn;
+};
+
+// Bytecode of a list of MONO ops (in op order) and the per-run parameters.
+struct RunCompiler {
+  uint32_t n_qubits = 0;
+  std::vector<MonoDesc> descs;      // one per MONO op
+  std::vector<BsOp> ops;            // bit-sliced bytecode of all MONO ops
+  std::vector<uint32_t> start;      // ops of MONO op k: [start[k], start[k+1])
+  std::vector<BsGateInfo> info;
+
+  // Fill ops/start/info from descs.
+  void compile(uint32_t nq);
+  // Whether MONO ops [begin, begin+len) run bit-sliced under the policy, and
+  // the run parameters (bytes_per_entry left 0).
+  bool run_params(size_t begin, size_t len, uint32_t mono_mode, uint32_t min_gates, BsRun* br) const;
+  // Kernel ops of MONO ops [begin, begin+len), in groups of kBsGroup, appended to out.
+  void group(size_t begin, size_t len, std::vector<BsOpG>& out) const;
+};
+
+}  // namespace sparsesim

@@ -357,7 +357,6 @@ void compile_bitslice(sim_t* s, size_t n_mono) {
       o.arg = arg;
       s->h_bs.push_back(o);
       if (cmode) rd |= word_bit(d.target);
-      if (base.nctrl + cmode > 3) inf.eligible = false;   // three condition slots per op
     };
     if (d.flags & kHasPhase) {
       const int k0 = omega_index(d.m0), k1 = omega_index(d.m1);
@@ -455,11 +454,9 @@ void group_ops(sim_t* s, uint32_t op0, uint32_t op1) {
     if (in_group == kBsGroup || w.meets(gr) || w.meets(gw) || r.meets(gw)) close();
     BsOpG g{};
     g.op = o.op;
-    g.t = o.op == kBsFlip ? o.target : ones;
+    g.t = (o.op == kBsFlip || o.cmode) ? o.target : ones;   // flip target, or a phase op's target-bit condition
     uint8_t slot[3] = {ones, ones, ones};
-    int ns = 0;
-    for (int c = 0; c < o.nctrl; ++c) slot[ns++] = o.ctrl[c];
-    if (o.cmode) slot[ns++] = o.target;
+    for (int c = 0; c < o.nctrl; ++c) slot[c] = o.ctrl[c];
     g.p0 = slot[0];
     g.p1 = slot[1];
     g.p2 = slot[2];

@@ -238,7 +238,8 @@ def test_bitslice_ragged_tiles(sim, n_entries):
         W._random_mono(rng, c, nq, 0.7, 0.3, 0)
     c.gate(W.K_Y, 3, (7,))
     c.gate(W.K_PHASE, nq - 2, (2, 9), param=0.77)
-    c.gate(W.K_RZ, nq - 1, (0, 1, 2, 4), param=-2.5)
+    c.gate(W.K_RZ, nq - 1, (0, 1, 4), param=-2.5)
+    c.gate(W.K_T, nq - 3, (0, 2, 5))
     ops = c.array()
     from paper_2105_01533_amd.sim import Simulator, SIM_MONO_BITSLICE
     s = Simulator(nq, n_entries, 0.0, mono_mode=SIM_MONO_BITSLICE)
