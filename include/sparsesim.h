@@ -244,6 +244,89 @@ int sim_set_profiling(sim_t* s, int on);
 int sim_kernel_stats(sim_t* s, sim_kernel_stat* out, int cap, int* n);
 int sim_kernel_stats_reset(sim_t* s);
 
+/* ==== Continuous-batching server =========================================
+ *
+ * Many independent simulations share one device.  A request is a circuit
+ * (sim_gate ops, as for sim_apply_gates) plus a sim_config (n_qubits,
+ * capacity, eps, load_factor, fuse_max, mono_mode, bs_min_gates) and an
+ * initial basis label.  Requests wait in FIFO order and are admitted while
+ * their device footprint (srv_footprint) fits the pool and a slot is free; a
+ * request larger than the whole pool is rejected at submission.  Each
+ * srv_tick applies one segment (a fused phase/permutation run, one branching
+ * gate or one measurement, cut exactly as sim_apply_gates cuts the circuit)
+ * to every running request in one batched launch -- captured once as a
+ * hipGraph and replayed every tick -- reads back every request's entry count
+ * and measurement outcome, retires finished requests to host memory and
+ * frees their device memory.  States stay device-resident between ticks.
+ * A request's result does not depend on the other requests in the batch, and
+ * equals a standalone sim_apply_gates run up to floating-point rounding of
+ * the measurement sums and of the fused-pass kernel choice.
+ * A server is not thread-safe; calls must not overlap.
+ */
+#define SRV_QUEUED 0
+#define SRV_RUNNING 1
+#define SRV_DONE 2
+#define SRV_FAILED 3
+
+#define SRV_FLAG_NO_GRAPH 1u /* launch the tick kernels directly instead of replaying the graph */
+
+typedef struct srv_config {
+  uint64_t budget_bytes; /* device bytes for request states (the pool) */
+  uint64_t arena_bytes;  /* per-tick upload area for fused-run ops (default 64 MiB) */
+  uint32_t max_slots;    /* requests running at once, 1..4096 */
+  uint32_t flags;        /* SRV_FLAG_* */
+} srv_config;
+
+typedef struct srv_stats {
+  uint64_t submitted, admitted, completed, failed;
+  uint64_t ticks;           /* batched launches */
+  uint64_t items;           /* segments executed */
+  uint64_t bitslice_runs;   /* fused runs that took the bit-sliced form */
+  uint64_t pool_used_bytes, pool_peak_bytes;
+} srv_stats;
+
+typedef struct srv_t srv_t;
+
+/* Device bytes one request with this configuration occupies while running;
+ * 0 for an invalid configuration. */
+size_t srv_footprint(const sim_config* cfg);
+
+/* stream: a hipStream_t, or NULL to let the server create its own (graph
+ * capture needs a non-null stream).  pool: device memory of at least
+ * budget_bytes, borrowed, or NULL to allocate it.  SIM_E_ARG, SIM_E_NOMEM,
+ * SIM_E_HIP. */
+int srv_create(const srv_config* cfg, void* stream, void* pool, size_t pool_bytes, srv_t** out);
+int srv_destroy(srv_t* s);
+
+/* Queue a request; gates are copied.  *id identifies it.  SIM_E_ARG for an
+ * invalid op or configuration (nothing queued), SIM_E_CAPACITY if the
+ * footprint exceeds the pool. */
+int srv_submit(srv_t* s, const sim_config* cfg, const sim_gate* gates, size_t n, sim_key basis, uint64_t* id);
+
+/* Admit what fits, run one batched tick, retire finished requests.  Writes
+ * the numbers of running and queued requests afterwards.  Synchronizes. */
+int srv_tick(srv_t* s, uint32_t* running, uint32_t* queued);
+
+/* Tick until nothing is running or queued. */
+int srv_run(srv_t* s);
+
+/* State (SRV_*) and, for SRV_FAILED, the error code (SIM_E_CAPACITY when a
+ * branching gate would exceed the request's capacity, SIM_E_STATE for a
+ * zero-probability measurement). */
+int srv_poll(srv_t* s, uint64_t id, int32_t* state, int32_t* error);
+
+/* Copy a finished request's state (storage order), measurement outcomes and
+ * counters to caller buffers of cap entries / out_cap outcomes.  *nnz and
+ * *n_out receive the sizes; SIM_E_BUFFER if a buffer is too small. */
+int srv_result(srv_t* s, uint64_t id, sim_key* keys, sim_c64* amps, uint64_t cap, uint64_t* nnz, int32_t* outcomes,
+               uint64_t out_cap, uint64_t* n_out, sim_stats* stats);
+
+/* Forget a finished or failed request's host-side result. */
+int srv_release(srv_t* s, uint64_t id);
+
+int srv_get_stats(srv_t* s, srv_stats* out);
+const char* srv_last_error(void);
+
 /* Name of an error code / detail of the last error in this thread. */
 const char* sim_strerror(int code);
 const char* sim_last_error(void);

@@ -1,0 +1,224 @@
+// Host-side compilation of phase/permutation runs (see run_compiler.h).
+#include "run_compiler.h"
+
+#include <cmath>
+#include <cstring>
+
+namespace sparsesim {
+
+MonoDesc mono_desc(const sim_gate& g) {
+  MonoDesc d{};
+  d.ctrl_lo = g.ctrl.lo;
+  d.ctrl_hi = g.ctrl.hi;
+  d.target = g.target;
+  const bool unit = g.m[0].re == 1.0 && g.m[0].im == 0.0 && g.m[1].re == 1.0 && g.m[1].im == 0.0;
+  d.flags = (unit ? 0u : kHasPhase) | (g.flip ? kFlip : 0u);
+  d.m0 = make_double2(g.m[0].re, g.m[0].im);
+  d.m1 = make_double2(g.m[1].re, g.m[1].im);
+  return d;
+}
+
+bool key_fits(uint32_t n, uint64_t lo, uint64_t hi) {
+  if (n >= 128) return true;
+  if (n > 64) return (hi >> (n - 64)) == 0;
+  return hi == 0 && (n == 64 || (lo >> n) == 0);
+}
+
+bool gate_valid(uint32_t n, const sim_gate& g, std::string* why) {
+  if (g.op > SIM_OP_MEASURE) return *why = "unknown op class", false;
+  if (g.target >= n || !key_fits(n, g.ctrl.lo, g.ctrl.hi)) return *why = "qubit out of range", false;
+  const uint64_t tw = g.target < 64 ? g.ctrl.lo : g.ctrl.hi;
+  if ((tw >> (g.target & 63)) & 1ull) return *why = "target is also a control", false;
+  if (g.op == SIM_OP_MEASURE) {
+    if (g.ctrl.lo || g.ctrl.hi) return *why = "measurement cannot be controlled", false;
+    if (g.forced < -1 || g.forced > 1) return *why = "forced must be -1, 0 or 1", false;
+    if (g.forced < 0 && !(g.u >= 0.0 && g.u < 1.0)) return *why = "measurement u must be in [0, 1)", false;
+  } else {
+    const int nm = g.op == SIM_OP_MONO ? 2 : 4;
+    for (int k = 0; k < nm; ++k)
+      if (!std::isfinite(g.m[k].re) || !std::isfinite(g.m[k].im)) return *why = "non-finite coefficient", false;
+  }
+  return true;
+}
+
+namespace {
+
+// Exact eighth-turn factors omega^k = e^{i pi k / 4}; -1 if m is not one.
+int omega_index(const double2& m) {
+  const double h = M_SQRT1_2;
+  const double re[8] = {1.0, h, 0.0, -h, -1.0, -h, 0.0, h};
+  const double im[8] = {0.0, h, 1.0, h, 0.0, -h, -1.0, -h};
+  for (int k = 0; k < 8; ++k)
+    if (m.x == re[k] && m.y == im[k]) return k;
+  return -1;
+}
+
+bool unit_modulus(const double2& m) { return std::fabs(m.x * m.x + m.y * m.y - 1.0) <= 1e-14; }
+
+// Argument of m as a turn fraction in units of 2^-64 turn (wraps exactly).
+uint64_t turn_of(const double2& m) {
+  const long double tau = (long double)std::atan2(m.y, m.x) / (2.0L * (long double)M_PI);   // [-1/2, 1/2]
+  long double v = tau * 18446744073709551616.0L;
+  if (v >= 9223372036854775807.0L) v -= 18446744073709551616.0L;
+  return (uint64_t)(int64_t)std::llroundl(v);
+}
+
+uint8_t word_bit(uint32_t q) { return (uint8_t)(1u << (q >> 5)); }
+
+}  // namespace
+
+// Per op: a factor m0 on labels with the target bit 0 and m1 with it 1 equals
+// m0 everywhere (under the controls) times m1/m0 where the target bit is 1.
+void RunCompiler::compile(uint32_t nq) {
+  n_qubits = nq;
+  const size_t n_mono = descs.size();
+  ops.clear();
+  start.assign(n_mono + 1, 0);
+  info.assign(n_mono, BsGateInfo{});
+  for (size_t k = 0; k < n_mono; ++k) {
+    const MonoDesc& d = descs[k];
+    BsGateInfo& inf = info[k];
+    start[k] = (uint32_t)ops.size();
+    inf.eligible = true;
+    BsOp base{};
+    base.target = (uint8_t)d.target;
+    uint8_t rd = 0;
+    for (int w = 0; w < 2; ++w) {
+      uint64_t m = w ? d.ctrl_hi : d.ctrl_lo;
+      while (m) {
+        const uint32_t q = (uint32_t)__builtin_ctzll(m) + 64u * w;
+        m &= m - 1;
+        if (base.nctrl == kBsMaxCtrl) {
+          inf.eligible = false;
+          break;
+        }
+        base.ctrl[base.nctrl++] = (uint8_t)q;
+        rd |= word_bit(q);
+      }
+    }
+    if (!inf.eligible) continue;
+    auto emit = [&](uint8_t op, uint8_t cmode, uint64_t arg) {
+      BsOp o = base;
+      o.op = op;
+      o.cmode = cmode;
+      o.arg = arg;
+      ops.push_back(o);
+      if (cmode) rd |= word_bit(d.target);
+    };
+    if (d.flags & kHasPhase) {
+      const int k0 = omega_index(d.m0), k1 = omega_index(d.m1);
+      if (k0 >= 0 && k1 >= 0) {
+        if (k0) {
+          if (base.nctrl == 0) inf.g_omega = (uint8_t)((inf.g_omega + k0) & 7);
+          else emit(kBsOmega, 0, (uint64_t)k0);
+        }
+        const uint32_t dk = (uint32_t)(k1 - k0) & 7u;
+        if (dk) emit(kBsOmega, 1, dk);
+      } else if (unit_modulus(d.m0) && unit_modulus(d.m1)) {
+        const uint64_t t0 = turn_of(d.m0), t1 = turn_of(d.m1);
+        if (t0) {
+          if (base.nctrl == 0) {
+            inf.g_turn += t0;
+          } else {
+            emit(kBsTurn, 0, t0);
+            inf.turns = true;
+          }
+        }
+        if (t1 - t0) {
+          emit(kBsTurn, 1, t1 - t0);
+          inf.turns = true;
+        }
+      } else {
+        inf.eligible = false;
+        continue;
+      }
+      inf.phase = true;
+    }
+    if (d.flags & kFlip) {
+      emit(kBsFlip, 0, 0);
+      inf.words_write = word_bit(d.target);
+    }
+    inf.words_read = rd;
+  }
+  start[n_mono] = (uint32_t)ops.size();
+}
+
+bool RunCompiler::run_params(size_t begin, size_t len, uint32_t mono_mode, uint32_t min_gates, BsRun* br) const {
+  if (mono_mode == SIM_MONO_DIRECT) return false;
+  if (mono_mode == SIM_MONO_AUTO && len < (min_gates ? min_gates : 16u)) return false;
+  std::memset(br, 0, sizeof *br);
+  uint32_t g_omega = 0;
+  for (size_t k = begin; k < begin + len; ++k) {
+    const BsGateInfo& g = info[k];
+    if (!g.eligible) return false;
+    br->words_read |= g.words_read | g.words_write;
+    br->words_write |= g.words_write;
+    br->has_phase |= g.phase ? 1u : 0u;
+    br->has_turns |= g.turns ? 1u : 0u;
+    g_omega += g.g_omega;
+    br->g_turn += g.g_turn;
+  }
+  if (br->words_write & 3u) br->words_read |= 3u;
+  if (br->words_write & 12u) br->words_read |= 12u;
+  br->g_omega = g_omega & 7u;
+  br->n_planes = n_qubits;
+  br->n_gates = (uint32_t)len;
+  return true;
+}
+
+// Pack the ops into groups of kBsGroup consecutive ops that touch no plane
+// another member of the group writes (so the kernel may read all of a group's
+// planes before any write), padding groups with no-op flips of the scratch
+// plane.  Order is kept across groups; within a group the ops are
+// independent, and phase accumulations commute exactly.
+void RunCompiler::group(size_t begin, size_t len, std::vector<BsOpG>& out) const {
+  const uint8_t ones = (uint8_t)n_qubits, scratch = (uint8_t)(n_qubits + 1);
+  struct Mask {
+    uint64_t lo = 0, hi = 0;
+    void set(uint32_t q) { (q < 64 ? lo : hi) |= 1ull << (q & 63); }
+    bool meets(const Mask& o) const { return (lo & o.lo) || (hi & o.hi); }
+    void add(const Mask& o) {
+      lo |= o.lo;
+      hi |= o.hi;
+    }
+  };
+  Mask gr, gw;
+  int in_group = 0;
+  auto close = [&]() {
+    for (; in_group && in_group < kBsGroup; ++in_group) {
+      BsOpG pad{};
+      pad.op = kBsFlip;
+      pad.t = scratch;
+      pad.p0 = pad.p1 = pad.p2 = ones;
+      out.push_back(pad);
+    }
+    in_group = 0;
+    gr = Mask{};
+    gw = Mask{};
+  };
+  for (uint32_t i = start[begin]; i < start[begin + len]; ++i) {
+    const BsOp& o = ops[i];
+    Mask r, w;
+    for (int c = 0; c < o.nctrl; ++c) r.set(o.ctrl[c]);
+    if (o.cmode || o.op == kBsFlip) r.set(o.target);
+    if (o.op == kBsFlip) w.set(o.target);
+    if (in_group == kBsGroup || w.meets(gr) || w.meets(gw) || r.meets(gw)) close();
+    BsOpG g{};
+    g.op = o.op;
+    g.t = (o.op == kBsFlip || o.cmode) ? o.target : ones;   // flip target, or a phase op's target-bit condition
+    uint8_t slot[3] = {ones, ones, ones};
+    for (int c = 0; c < o.nctrl; ++c) slot[c] = o.ctrl[c];
+    g.p0 = slot[0];
+    g.p1 = slot[1];
+    g.p2 = slot[2];
+    g.k = o.op == kBsOmega ? (uint8_t)o.arg : 0;
+    g.tau = o.op == kBsTurn ? o.arg : 0;
+    out.push_back(g);
+    gr.add(r);
+    gw.add(w);
+    ++in_group;
+  }
+  close();
+}
+
+}  // namespace sparsesim

@@ -1,0 +1,678 @@
+// Continuous-batching server over the batched tick (see include/sparsesim.h,
+// srv_*).
+//
+// Requests (a circuit and a state configuration) queue in FIFO order and are
+// admitted while their device footprint fits the pool and a slot is free.
+// Each tick takes one segment from every running request -- a fused
+// phase/permutation run, one branching gate, or one measurement, exactly as
+// the single-state engine would cut it -- uploads one work list, replays the
+// captured tick graph, and reads back every slot's control words.  Finished
+// requests are copied to host memory and their device memory is returned to
+// the pool, which lets queued requests in on the next tick.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <deque>
+#include <map>
+#include <memory>
+#include <string>
+#include <unordered_map>
+#include <vector>
+
+#include "../../include/sparsesim.h"
+#include "run_compiler.h"
+#include "sim_internal.h"
+
+using namespace sparsesim;
+
+namespace {
+
+thread_local std::string g_srv_error;
+
+int sfail(int code, const std::string& msg) {
+  g_srv_error = msg;
+  return code;
+}
+
+#define SRV_HIP(expr)                                                                        \
+  do {                                                                                       \
+    hipError_t e_ = (expr);                                                                  \
+    if (e_ != hipSuccess) return sfail(SIM_E_HIP, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+constexpr size_t kA = 256;
+size_t al(size_t x) { return (x + kA - 1) / kA * kA; }
+
+uint64_t pow2_at_least(uint64_t x) {
+  uint64_t p = 1;
+  while (p < x) p <<= 1;
+  return p;
+}
+
+uint64_t index_slots(uint64_t n, double lf) {
+  const uint64_t want = (uint64_t)std::ceil((double)(n ? n : 1) / lf) + 1;
+  return std::max<uint64_t>(64, pow2_at_least(want));
+}
+
+double lf_or_default(double lf) { return lf > 0.0 ? lf : 0.5; }
+
+// First-fit allocator over [0, size) with coalescing (offsets 256-aligned).
+struct Pool {
+  size_t size = 0, used = 0, peak = 0;
+  std::map<size_t, size_t> free_;
+  void init(size_t n) {
+    size = n;
+    free_.clear();
+    free_[0] = n;
+    used = peak = 0;
+  }
+  bool alloc(size_t n, size_t* off) {
+    for (auto it = free_.begin(); it != free_.end(); ++it) {
+      if (it->second >= n) {
+        *off = it->first;
+        const size_t rest = it->second - n;
+        const size_t at = it->first + n;
+        free_.erase(it);
+        if (rest) free_[at] = rest;
+        used += n;
+        peak = std::max(peak, used);
+        return true;
+      }
+    }
+    return false;
+  }
+  void release(size_t off, size_t n) {
+    used -= n;
+    auto it = free_.emplace(off, n).first;
+    auto nx = std::next(it);
+    if (nx != free_.end() && it->first + it->second == nx->first) {
+      it->second += nx->second;
+      free_.erase(nx);
+    }
+    if (it != free_.begin()) {
+      auto pv = std::prev(it);
+      if (pv->first + pv->second == it->first) {
+        pv->second += it->second;
+        free_.erase(it);
+      }
+    }
+  }
+};
+
+struct Footprint {
+  size_t lo[2], hi[2], amp[2], table, partner, tot, cnt1, part, total;
+  uint64_t slots, units;
+};
+
+Footprint footprint_of(const sim_config& c, double lf) {
+  Footprint f{};
+  const uint64_t cap = c.capacity;
+  const bool wide = c.n_qubits > 64;
+  size_t off = 0;
+  for (int b = 0; b < 2; ++b) {
+    f.lo[b] = off;
+    off += al(cap * 8);
+    f.hi[b] = off;
+    if (wide) off += al(cap * 8);
+    f.amp[b] = off;
+    off += al(cap * 16);
+  }
+  f.slots = index_slots(cap, lf);
+  f.table = off;
+  off += al(f.slots * 8);
+  f.partner = off;
+  off += al(cap * 4);
+  f.units = (cap + kChunk - 1) / kChunk + 1;
+  f.tot = off;
+  off += al(f.units * 4);
+  f.cnt1 = off;
+  off += al(f.units * 4);
+  f.part = off;
+  off += al(f.units * 16);
+  f.total = off;
+  return f;
+}
+
+enum SegKind { SEG_NONE = 0, SEG_MONO, SEG_U2, SEG_MEAS };
+
+struct Request {
+  uint64_t id = 0;
+  sim_config cfg{};
+  sim_key basis{};
+  std::vector<sim_gate> gates;
+  std::vector<size_t> mono_op;        // MONO ordinal -> op index
+  RunCompiler rc;
+  int32_t state = SRV_QUEUED;
+  int32_t error = SIM_OK;
+  // device placement
+  Footprint fp{};
+  size_t off = 0;
+  int slot = -1;
+  Buf buf[2]{};
+  uint64_t* table = nullptr;
+  uint32_t *partner = nullptr, *tot = nullptr, *cnt1 = nullptr;
+  double2* part = nullptr;
+  int cur = 0;
+  uint64_t nnz = 1;
+  // progress
+  size_t i = 0;
+  size_t mono_seen = 0;
+  SegKind seg = SEG_NONE;
+  sim_stats st{};
+  std::vector<int32_t> outcomes;
+  // result
+  std::vector<sim_key> keys;
+  std::vector<sim_c64> amps;
+};
+
+}  // namespace
+
+struct srv_t {
+  srv_config cfg{};
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  char* pool_mem = nullptr;
+  bool own_pool = false;
+  Pool pool;
+  SlotCtl* d_ctl = nullptr;
+  SlotCtl* h_ctl = nullptr;
+  std::vector<int> free_slots;
+  // tick buffer (same layout host/device): header | items | units | ops arena
+  char* d_tick = nullptr;
+  char* h_tick = nullptr;
+  size_t items_off = 0, units_off = 0, arena_off = 0, tick_bytes = 0;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  int grid = 2048;
+  uint64_t next_id = 1;
+  std::unordered_map<uint64_t, std::unique_ptr<Request>> reqs;
+  std::deque<uint64_t> queue;
+  std::vector<Request*> running;
+  srv_stats stats{};
+};
+
+namespace {
+
+int capture_tick(srv_t* s) {
+  const auto* hdr = reinterpret_cast<const BTick*>(s->d_tick);
+  const auto* items = reinterpret_cast<const BItem*>(s->d_tick + s->items_off);
+  const auto* units = reinterpret_cast<const uint32_t*>(s->d_tick + s->units_off);
+  if (s->cfg.flags & SRV_FLAG_NO_GRAPH) return SIM_OK;
+  SRV_HIP(hipStreamBeginCapture(s->stream, hipStreamCaptureModeThreadLocal));
+  launch_batch_tick(s->stream, hdr, items, units, s->grid);
+  hipGraph_t g = nullptr;
+  SRV_HIP(hipStreamEndCapture(s->stream, &g));
+  s->graph = g;
+  SRV_HIP(hipGraphInstantiate(&s->exec, s->graph, nullptr, nullptr, 0));
+  return SIM_OK;
+}
+
+// Next segment of r, consuming skipped branching gates; sets r.seg and the
+// run [begin, begin + len) of MONO ordinals or the op index of the gate.
+SegKind next_segment(srv_t* s, Request& r, size_t* begin, size_t* len, size_t* op) {
+  const uint32_t fuse_max = r.cfg.fuse_max ? r.cfg.fuse_max : 65536u;
+  size_t run_len = 0, run_begin = r.mono_seen;
+  const size_t n = r.gates.size();
+  while (r.i < n) {
+    const sim_gate& g = r.gates[r.i];
+    if (g.op == SIM_OP_MONO) {
+      if (!run_len) run_begin = r.mono_seen;
+      ++run_len;
+      ++r.mono_seen;
+      ++r.i;
+      if (run_len >= fuse_max) break;
+      continue;
+    }
+    if (g.op == SIM_OP_U2 && g.cap && 2 * r.nnz > g.cap) {
+      r.st.u2_skipped++;
+      ++r.i;
+      continue;
+    }
+    if (run_len) break;
+    *op = r.i++;
+    return g.op == SIM_OP_U2 ? SEG_U2 : SEG_MEAS;
+  }
+  (void)s;
+  if (run_len) {
+    *begin = run_begin;
+    *len = run_len;
+    return SEG_MONO;
+  }
+  return SEG_NONE;
+}
+
+int finish(srv_t* s, Request& r, int32_t state, int32_t err) {
+  r.state = state;
+  r.error = err;
+  if (state == SRV_DONE) {
+    const uint64_t n = r.nnz;
+    std::vector<uint64_t> lo(n), hi(n, 0);
+    r.amps.resize(n);
+    r.keys.resize(n);
+    if (n) {
+      SRV_HIP(hipMemcpy(lo.data(), r.buf[r.cur].key_lo, n * 8, hipMemcpyDeviceToHost));
+      if (r.cfg.n_qubits > 64) SRV_HIP(hipMemcpy(hi.data(), r.buf[r.cur].key_hi, n * 8, hipMemcpyDeviceToHost));
+      SRV_HIP(hipMemcpy(r.amps.data(), r.buf[r.cur].amp, n * 16, hipMemcpyDeviceToHost));
+    }
+    for (uint64_t k = 0; k < n; ++k) r.keys[k] = sim_key{lo[k], hi[k]};
+    r.st.gates_applied = r.gates.size();
+    s->stats.completed++;
+  } else {
+    s->stats.failed++;
+  }
+  r.st.peak_nnz = std::max<uint64_t>(r.st.peak_nnz, r.nnz);
+  s->pool.release(r.off, r.fp.total);
+  s->free_slots.push_back(r.slot);
+  r.slot = -1;
+  r.gates.clear();
+  r.gates.shrink_to_fit();
+  r.rc = RunCompiler{};
+  return SIM_OK;
+}
+
+int admit(srv_t* s) {
+  while (!s->queue.empty() && !s->free_slots.empty()) {
+    Request& r = *s->reqs[s->queue.front()];
+    size_t off;
+    if (!s->pool.alloc(r.fp.total, &off)) break;        // FIFO: wait for memory
+    s->queue.pop_front();
+    r.off = off;
+    r.slot = s->free_slots.back();
+    s->free_slots.pop_back();
+    char* base = s->pool_mem + off;
+    const bool wide = r.cfg.n_qubits > 64;
+    for (int b = 0; b < 2; ++b) {
+      r.buf[b].key_lo = reinterpret_cast<uint64_t*>(base + r.fp.lo[b]);
+      r.buf[b].key_hi = wide ? reinterpret_cast<uint64_t*>(base + r.fp.hi[b]) : nullptr;
+      r.buf[b].amp = reinterpret_cast<double2*>(base + r.fp.amp[b]);
+    }
+    r.table = reinterpret_cast<uint64_t*>(base + r.fp.table);
+    r.partner = reinterpret_cast<uint32_t*>(base + r.fp.partner);
+    r.tot = reinterpret_cast<uint32_t*>(base + r.fp.tot);
+    r.cnt1 = reinterpret_cast<uint32_t*>(base + r.fp.cnt1);
+    r.part = reinterpret_cast<double2*>(base + r.fp.part);
+    r.cur = 0;
+    r.nnz = 1;
+    // initial basis state and control words
+    SlotCtl c{};
+    c.nnz[0] = 1;
+    c.outcome = -1;
+    s->h_ctl[r.slot] = c;
+    SRV_HIP(hipMemcpyAsync(&s->d_ctl[r.slot], &s->h_ctl[r.slot], sizeof(SlotCtl), hipMemcpyHostToDevice,
+                           s->stream));
+    const double one[2] = {1.0, 0.0};
+    SRV_HIP(hipMemcpyAsync(r.buf[0].key_lo, &r.basis.lo, 8, hipMemcpyHostToDevice, s->stream));
+    if (wide) SRV_HIP(hipMemcpyAsync(r.buf[0].key_hi, &r.basis.hi, 8, hipMemcpyHostToDevice, s->stream));
+    SRV_HIP(hipMemcpyAsync(r.buf[0].amp, one, 16, hipMemcpyHostToDevice, s->stream));
+    SRV_HIP(hipStreamSynchronize(s->stream));   // the host sources above are on the stack
+    r.state = SRV_RUNNING;
+    s->running.push_back(&r);
+    s->stats.admitted++;
+  }
+  return SIM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t srv_footprint(const sim_config* cfg) {
+  if (!cfg || cfg->n_qubits < 1 || cfg->n_qubits > 128 || cfg->capacity < 1 || cfg->capacity >= (1ull << 31))
+    return 0;
+  return footprint_of(*cfg, lf_or_default(cfg->load_factor)).total;
+}
+
+int srv_create(const srv_config* cfg, void* stream, void* pool, size_t pool_bytes, srv_t** out) {
+  if (!cfg || !out) return sfail(SIM_E_ARG, "null argument");
+  *out = nullptr;
+  if (cfg->max_slots < 1 || cfg->max_slots > 4096) return sfail(SIM_E_ARG, "max_slots must be in 1..4096");
+  if (cfg->budget_bytes < kA) return sfail(SIM_E_ARG, "budget_bytes too small");
+  std::unique_ptr<srv_t> s(new srv_t());
+  s->cfg = *cfg;
+  if (!s->cfg.arena_bytes) s->cfg.arena_bytes = 64ull << 20;
+  if (stream) {
+    s->stream = static_cast<hipStream_t>(stream);
+  } else {
+    SRV_HIP(hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking));
+    s->own_stream = true;
+  }
+  if (pool) {
+    if (pool_bytes < cfg->budget_bytes) return sfail(SIM_E_NOMEM, "pool smaller than budget_bytes");
+    s->pool_mem = static_cast<char*>(pool);
+  } else {
+    if (hipMalloc(&s->pool_mem, cfg->budget_bytes) != hipSuccess) return sfail(SIM_E_NOMEM, "pool allocation failed");
+    s->own_pool = true;
+  }
+  s->pool.init(cfg->budget_bytes / kA * kA);
+  const size_t ns = cfg->max_slots;
+  SRV_HIP(hipMalloc(&s->d_ctl, ns * sizeof(SlotCtl)));
+  SRV_HIP(hipHostMalloc(&s->h_ctl, ns * sizeof(SlotCtl)));
+  for (int k = (int)ns - 1; k >= 0; --k) s->free_slots.push_back(k);
+  s->items_off = al(sizeof(BTick));
+  s->units_off = s->items_off + al(ns * sizeof(BItem));
+  s->arena_off = s->units_off + al(5 * (ns + 1) * sizeof(uint32_t));
+  s->tick_bytes = s->arena_off + s->cfg.arena_bytes;
+  SRV_HIP(hipMalloc(&s->d_tick, s->tick_bytes));
+  SRV_HIP(hipHostMalloc(&s->h_tick, s->tick_bytes));
+  std::memset(s->h_tick, 0, s->arena_off);
+  SRV_HIP(hipMemcpyAsync(s->d_tick, s->h_tick, s->arena_off, hipMemcpyHostToDevice, s->stream));
+  SRV_HIP(hipStreamSynchronize(s->stream));
+  int rc = capture_tick(s.get());
+  if (rc) return rc;
+  *out = s.release();
+  return SIM_OK;
+}
+
+int srv_destroy(srv_t* s) {
+  if (!s) return SIM_OK;
+  (void)hipStreamSynchronize(s->stream);
+  if (s->exec) (void)hipGraphExecDestroy(s->exec);
+  if (s->graph) (void)hipGraphDestroy(s->graph);
+  if (s->d_tick) (void)hipFree(s->d_tick);
+  if (s->h_tick) (void)hipHostFree(s->h_tick);
+  if (s->d_ctl) (void)hipFree(s->d_ctl);
+  if (s->h_ctl) (void)hipHostFree(s->h_ctl);
+  if (s->own_pool && s->pool_mem) (void)hipFree(s->pool_mem);
+  if (s->own_stream && s->stream) (void)hipStreamDestroy(s->stream);
+  delete s;
+  return SIM_OK;
+}
+
+int srv_submit(srv_t* s, const sim_config* cfg, const sim_gate* gates, size_t n, sim_key basis, uint64_t* id) {
+  if (!s || !cfg || !id || (n && !gates)) return sfail(SIM_E_ARG, "null argument");
+  if (cfg->n_qubits < 1 || cfg->n_qubits > 128) return sfail(SIM_E_ARG, "n_qubits must be in 1..128");
+  if (cfg->capacity < 1 || cfg->capacity >= (1ull << 31)) return sfail(SIM_E_ARG, "capacity out of range");
+  if (!(cfg->eps >= 0.0) || !std::isfinite(cfg->eps)) return sfail(SIM_E_ARG, "eps must be finite and >= 0");
+  if (cfg->mono_mode > SIM_MONO_BITSLICE) return sfail(SIM_E_ARG, "unknown mono_mode");
+  if (!key_fits(cfg->n_qubits, basis.lo, basis.hi)) return sfail(SIM_E_ARG, "basis has bits above n_qubits");
+  std::unique_ptr<Request> r(new Request());
+  r->cfg = *cfg;
+  r->cfg.load_factor = lf_or_default(cfg->load_factor);
+  if (!(r->cfg.load_factor > 0.0 && r->cfg.load_factor <= 0.9)) return sfail(SIM_E_ARG, "load_factor out of range");
+  r->fp = footprint_of(r->cfg, r->cfg.load_factor);
+  if (r->fp.total > s->pool.size) return sfail(SIM_E_CAPACITY, "request footprint exceeds the pool");
+  r->basis = basis;
+  r->gates.assign(gates, gates + n);
+  std::string why;
+  for (size_t i = 0; i < n; ++i) {
+    if (!gate_valid(cfg->n_qubits, gates[i], &why)) return sfail(SIM_E_ARG, "op " + std::to_string(i) + ": " + why);
+    if (gates[i].op == SIM_OP_MONO) {
+      r->rc.descs.push_back(mono_desc(gates[i]));
+      r->mono_op.push_back(i);
+    }
+  }
+  if (cfg->mono_mode != SIM_MONO_DIRECT) r->rc.compile(cfg->n_qubits);
+  else r->rc.n_qubits = cfg->n_qubits;
+  r->id = s->next_id++;
+  *id = r->id;
+  s->queue.push_back(r->id);
+  s->reqs[r->id] = std::move(r);
+  s->stats.submitted++;
+  return SIM_OK;
+}
+
+int srv_tick(srv_t* s, uint32_t* running, uint32_t* queued) {
+  if (!s) return sfail(SIM_E_ARG, "null handle");
+  int rc = admit(s);
+  if (rc) return rc;
+  // Assemble the work list.
+  auto* hdr = reinterpret_cast<BTick*>(s->h_tick);
+  auto* items = reinterpret_cast<BItem*>(s->h_tick + s->items_off);
+  auto* units = reinterpret_cast<uint32_t*>(s->h_tick + s->units_off);
+  char* arena = s->h_tick + s->arena_off;
+  size_t arena_used = 0;
+  std::vector<Request*> mono, u2, meas;
+  std::vector<BItem> mono_items, u2_items, meas_items;
+  std::vector<BsOpG> grp;
+  std::vector<Request*> done_now;
+  for (Request* r : s->running) {
+    size_t b = 0, len = 0, op = 0;
+    const SegKind k = next_segment(s, *r, &b, &len, &op);
+    r->seg = k;
+    if (k == SEG_NONE) {
+      done_now.push_back(r);
+      continue;
+    }
+    BItem it{};
+    it.in = r->buf[r->cur];
+    it.out = r->buf[r->cur ^ 1];
+    it.ctl = s->d_ctl + r->slot;
+    it.other = (uint32_t)(r->cur ^ 1);
+    it.wide = r->cfg.n_qubits > 64 ? 1u : 0u;
+    it.nnz = r->nnz;
+    it.cap = r->cfg.capacity;
+    if (k == SEG_MONO) {
+      BsRun br;
+      const bool bsl = r->rc.run_params(b, len, r->cfg.mono_mode, r->cfg.bs_min_gates, &br);
+      uint32_t flags = 0;
+      for (size_t q = b; q < b + len; ++q) {
+        if (r->rc.descs[q].flags & kHasPhase) flags |= kRunPhase;
+        if (r->rc.descs[q].flags & kFlip) flags |= kRunFlip;
+      }
+      it.run_flags = flags;
+      // Ops of the run; if they do not fit the rest of the work list, keep a
+      // shorter prefix of the run (possibly none) for this tick.
+      size_t bytes = 0, keep = len;
+      for (;;) {
+        if (bsl) {
+          grp.clear();
+          r->rc.group(b, keep, grp);
+          bytes = grp.size() * sizeof(BsOpG);
+        } else {
+          bytes = keep * sizeof(MonoDesc);
+        }
+        if (keep == 0 || arena_used + al(bytes) <= s->cfg.arena_bytes) break;
+        keep /= 2;
+      }
+      if (keep < len) {
+        // Give back ops from MONO ordinal b + keep on: they are re-read next
+        // tick (skip decisions there depend only on nnz, which this run keeps).
+        const size_t back_to = r->mono_op[b + keep];
+        for (size_t q = back_to; q < r->i; ++q)
+          if (r->gates[q].op == SIM_OP_U2) r->st.u2_skipped--;
+        r->i = back_to;
+        r->mono_seen = b + keep;
+        len = keep;
+        if (bsl) r->rc.run_params(b, len, r->cfg.mono_mode, 1, &br);
+      }
+      if (len == 0) continue;
+      if (bsl) {
+        std::memcpy(arena + arena_used, grp.data(), bytes);
+        it.gops = reinterpret_cast<const BsOpG*>(s->d_tick + s->arena_off + arena_used);
+        it.ngroups = (uint32_t)(grp.size() / kBsGroup);
+        it.run = br;
+        s->stats.bitslice_runs++;
+      } else {
+        std::memcpy(arena + arena_used, r->rc.descs.data() + b, bytes);
+        it.dops = reinterpret_cast<const MonoDesc*>(s->d_tick + s->arena_off + arena_used);
+        it.n_dops = (uint32_t)len;
+      }
+      arena_used += al(bytes);
+      r->st.updates += r->nnz * len;
+      r->st.mono_passes++;
+      if (bsl) r->st.bitslice_passes++;
+      mono.push_back(r);
+      mono_items.push_back(it);
+    } else if (k == SEG_U2) {
+      const sim_gate& g = r->gates[op];
+      it.u2.ctrl_lo = g.ctrl.lo;
+      it.u2.ctrl_hi = g.ctrl.hi;
+      it.u2.target = g.target;
+      it.u2.eps = r->cfg.eps;
+      for (int q = 0; q < 4; ++q) it.u2.u[q] = make_double2(g.m[q].re, g.m[q].im);
+      const uint64_t slots = std::min<uint64_t>(index_slots(r->nnz, r->cfg.load_factor), r->fp.slots);
+      it.table = r->table;
+      it.mask = slots - 1;
+      it.partner = r->partner;
+      it.tot = r->tot;
+      r->st.updates += r->nnz;
+      u2.push_back(r);
+      u2_items.push_back(it);
+    } else {
+      const sim_gate& g = r->gates[op];
+      it.q = g.target;
+      it.forced = g.forced;
+      it.u = g.u;
+      it.part = r->part;
+      it.cnt1 = r->cnt1;
+      it.tot = r->tot;
+      meas.push_back(r);
+      meas_items.push_back(it);
+    }
+  }
+  for (Request* r : done_now) {
+    rc = finish(s, *r, SRV_DONE, SIM_OK);
+    if (rc) return rc;
+    s->running.erase(std::find(s->running.begin(), s->running.end(), r));
+  }
+  const uint32_t nm = (uint32_t)mono_items.size(), nu = (uint32_t)u2_items.size(), nq = (uint32_t)meas_items.size();
+  if (nm + nu + nq) {
+    std::memset(hdr, 0, sizeof(BTick));
+    hdr->n_mono = nm;
+    hdr->n_u2 = nu;
+    hdr->n_meas = nq;
+    uint32_t w = 0;
+    auto prefix = [&](uint32_t* at, const std::vector<BItem>& v, auto units_of) {
+      uint32_t acc = 0;
+      for (size_t k = 0; k < v.size(); ++k) {
+        at[k] = acc;
+        acc += units_of(v[k]);
+      }
+      at[v.size()] = acc;
+    };
+    auto chunks = [](const BItem& it) { return (uint32_t)((it.nnz + kChunk - 1) / kChunk); };
+    hdr->mono_u0 = w;
+    prefix(units + w, mono_items, chunks);
+    w += nm + 1;
+    hdr->fill_u0 = w;
+    prefix(units + w, u2_items, [](const BItem& it) { return (uint32_t)((it.mask + kFillUnit) / kFillUnit); });
+    w += nu + 1;
+    hdr->build_u0 = w;
+    prefix(units + w, u2_items, chunks);
+    w += nu + 1;
+    hdr->chunk_u0 = w;
+    prefix(units + w, u2_items, chunks);
+    w += nu + 1;
+    hdr->meas_u0 = w;
+    prefix(units + w, meas_items, chunks);
+    w += nq + 1;
+    size_t ni = 0;
+    for (const auto& v : {&mono_items, &u2_items, &meas_items})
+      for (const BItem& it : *v) items[ni++] = it;
+    SRV_HIP(hipMemcpyAsync(s->d_tick, s->h_tick, s->items_off + ni * sizeof(BItem), hipMemcpyHostToDevice,
+                           s->stream));
+    SRV_HIP(hipMemcpyAsync(s->d_tick + s->units_off, units, w * sizeof(uint32_t), hipMemcpyHostToDevice, s->stream));
+    if (arena_used)
+      SRV_HIP(hipMemcpyAsync(s->d_tick + s->arena_off, arena, arena_used, hipMemcpyHostToDevice, s->stream));
+    if (s->exec) {
+      SRV_HIP(hipGraphLaunch(s->exec, s->stream));
+    } else {
+      launch_batch_tick(s->stream, reinterpret_cast<const BTick*>(s->d_tick),
+                        reinterpret_cast<const BItem*>(s->d_tick + s->items_off),
+                        reinterpret_cast<const uint32_t*>(s->d_tick + s->units_off), s->grid);
+      SRV_HIP(hipGetLastError());
+    }
+    int max_slot = -1;
+    for (Request* r : s->running) max_slot = std::max(max_slot, r->slot);
+    SRV_HIP(hipMemcpyAsync(s->h_ctl, s->d_ctl, (size_t)(max_slot + 1) * sizeof(SlotCtl), hipMemcpyDeviceToHost,
+                           s->stream));
+    SRV_HIP(hipStreamSynchronize(s->stream));
+    s->stats.ticks++;
+    s->stats.items += nm + nu + nq;
+    // Fold the results back.
+    std::vector<std::pair<Request*, int>> failed;
+    for (Request* r : u2) {
+      const SlotCtl& c = s->h_ctl[r->slot];
+      if (c.status & kStOverflow) {
+        failed.emplace_back(r, SIM_E_CAPACITY);
+        continue;
+      }
+      r->cur ^= 1;
+      r->nnz = c.nnz[r->cur];
+      r->st.u2_applied++;
+      r->st.peak_nnz = std::max<uint64_t>(r->st.peak_nnz, r->nnz);
+    }
+    for (Request* r : meas) {
+      const SlotCtl& c = s->h_ctl[r->slot];
+      if ((c.status & kStMeasure) || c.outcome < 0) {
+        failed.emplace_back(r, SIM_E_STATE);
+        continue;
+      }
+      r->cur ^= 1;
+      r->nnz = c.nnz[r->cur];
+      r->outcomes.push_back(c.outcome);
+      r->st.measures++;
+    }
+    for (auto& f : failed) {
+      rc = finish(s, *f.first, SRV_FAILED, f.second);
+      if (rc) return rc;
+      s->running.erase(std::find(s->running.begin(), s->running.end(), f.first));
+    }
+  }
+  if (running) *running = (uint32_t)s->running.size();
+  if (queued) *queued = (uint32_t)s->queue.size();
+  s->stats.pool_peak_bytes = s->pool.peak;
+  s->stats.pool_used_bytes = s->pool.used;
+  return SIM_OK;
+}
+
+int srv_run(srv_t* s) {
+  if (!s) return sfail(SIM_E_ARG, "null handle");
+  uint32_t run = 1, q = 1;
+  while (run || q) {
+    const uint64_t before = s->stats.admitted;
+    int rc = srv_tick(s, &run, &q);
+    if (rc) return rc;
+    if (!run && q && s->stats.admitted == before) return sfail(SIM_E_NOMEM, "queued request can never be admitted");
+  }
+  return SIM_OK;
+}
+
+int srv_poll(srv_t* s, uint64_t id, int32_t* state, int32_t* error) {
+  if (!s || !state) return sfail(SIM_E_ARG, "null argument");
+  auto it = s->reqs.find(id);
+  if (it == s->reqs.end()) return sfail(SIM_E_ARG, "unknown request id");
+  *state = it->second->state;
+  if (error) *error = it->second->error;
+  return SIM_OK;
+}
+
+int srv_result(srv_t* s, uint64_t id, sim_key* keys, sim_c64* amps, uint64_t cap, uint64_t* nnz, int32_t* outcomes,
+               uint64_t out_cap, uint64_t* n_out, sim_stats* stats) {
+  if (!s || !nnz) return sfail(SIM_E_ARG, "null argument");
+  auto it = s->reqs.find(id);
+  if (it == s->reqs.end()) return sfail(SIM_E_ARG, "unknown request id");
+  Request& r = *it->second;
+  if (r.state != SRV_DONE) return sfail(r.state == SRV_FAILED ? r.error : SIM_E_STATE, "request not done");
+  *nnz = r.keys.size();
+  if (n_out) *n_out = r.outcomes.size();
+  if (stats) *stats = r.st;
+  if (cap < r.keys.size() || (outcomes && out_cap < r.outcomes.size())) return sfail(SIM_E_BUFFER, "buffer too small");
+  if (keys && !r.keys.empty()) std::memcpy(keys, r.keys.data(), r.keys.size() * sizeof(sim_key));
+  if (amps && !r.amps.empty()) std::memcpy(amps, r.amps.data(), r.amps.size() * sizeof(sim_c64));
+  if (outcomes && !r.outcomes.empty()) std::memcpy(outcomes, r.outcomes.data(), r.outcomes.size() * 4);
+  return SIM_OK;
+}
+
+int srv_release(srv_t* s, uint64_t id) {
+  if (!s) return sfail(SIM_E_ARG, "null handle");
+  auto it = s->reqs.find(id);
+  if (it == s->reqs.end()) return sfail(SIM_E_ARG, "unknown request id");
+  if (it->second->state == SRV_QUEUED || it->second->state == SRV_RUNNING)
+    return sfail(SIM_E_STATE, "request still queued or running");
+  s->reqs.erase(it);
+  return SIM_OK;
+}
+
+int srv_get_stats(srv_t* s, srv_stats* out) {
+  if (!s || !out) return sfail(SIM_E_ARG, "null argument");
+  *out = s->stats;
+  return SIM_OK;
+}
+
+const char* srv_last_error(void) { return g_srv_error.c_str(); }
+
+}  // extern "C"

@@ -17,6 +17,7 @@
 #include <vector>
 
 #include "../../include/sparsesim.h"
+#include "run_compiler.h"
 #include "sim_internal.h"
 
 using namespace sparsesim;
@@ -157,20 +158,11 @@ struct sim_t {
   uint64_t* h_pinned;          // [0] nnz readback, [1..] scratch
   Ctl* h_ctl;                  // pinned mirror of ctl
   DevVec<MonoDesc> descs;
-  // bit-sliced bytecode of the current call, per phase/permutation op
-  struct BsGate {
-    bool eligible, phase, turns;
-    uint8_t words_read, words_write, g_omega;
-    uint64_t g_turn;
-  };
-  DevVec<BsOpG> grp_ops;
+  DevVec<BsOpG> grp_ops;       // grouped bit-sliced ops of the current call
   std::vector<BsOpG> h_grp;
-  std::vector<BsOp> h_bs;
-  std::vector<uint32_t> bs_start;
-  std::vector<BsGate> bs_gate;
+  RunCompiler rc;              // MONO descriptors and bytecode of the current call
   DevVec<MeasRec> recs;
   DevVec<int32_t> outcomes;
-  std::vector<MonoDesc> h_descs;
   // host knowledge of the entry count
   bool nnz_known;
   uint64_t nnz_exact, nnz_ub;
@@ -249,225 +241,12 @@ int read_nnz(sim_t* s, uint64_t* out) {
   return SIM_OK;
 }
 
-bool key_in_range(const sim_t* s, uint64_t lo, uint64_t hi) {
-  const unsigned n = s->cfg.n_qubits;
-  if (n >= 128) return true;
-  if (n > 64) return (hi >> (n - 64)) == 0;
-  return hi == 0 && (n == 64 || (lo >> n) == 0);
-}
-
-bool qubit_ok(const sim_t* s, uint32_t q) { return q < s->cfg.n_qubits; }
-
-bool finite_c(const sim_c64& c) { return std::isfinite(c.re) && std::isfinite(c.im); }
+bool key_in_range(const sim_t* s, uint64_t lo, uint64_t hi) { return key_fits(s->cfg.n_qubits, lo, hi); }
 
 int validate(const sim_t* s, const sim_gate& g, size_t i) {
-  char msg[160];
-  if (g.op > SIM_OP_MEASURE) {
-    snprintf(msg, sizeof msg, "op %zu: unknown op class %u", i, g.op);
-    return fail(SIM_E_ARG, msg);
-  }
-  if (!qubit_ok(s, g.target) || !key_in_range(s, g.ctrl.lo, g.ctrl.hi)) {
-    snprintf(msg, sizeof msg, "op %zu: qubit out of range", i);
-    return fail(SIM_E_ARG, msg);
-  }
-  const uint64_t tw = g.target < 64 ? g.ctrl.lo : g.ctrl.hi;
-  if ((tw >> (g.target & 63)) & 1ull) {
-    snprintf(msg, sizeof msg, "op %zu: target is also a control", i);
-    return fail(SIM_E_ARG, msg);
-  }
-  if (g.op == SIM_OP_MEASURE) {
-    if (g.ctrl.lo || g.ctrl.hi) return fail(SIM_E_ARG, "measurement cannot be controlled");
-    if (g.forced < -1 || g.forced > 1) return fail(SIM_E_ARG, "forced must be -1, 0 or 1");
-    if (g.forced < 0 && !(g.u >= 0.0 && g.u < 1.0)) return fail(SIM_E_ARG, "measurement u must be in [0, 1)");
-  } else {
-    const int nm = g.op == SIM_OP_MONO ? 2 : 4;
-    for (int k = 0; k < nm; ++k)
-      if (!finite_c(g.m[k])) return fail(SIM_E_ARG, "non-finite gate coefficient");
-  }
-  return SIM_OK;
-}
-
-MonoDesc mono_desc(const sim_gate& g) {
-  MonoDesc d{};
-  d.ctrl_lo = g.ctrl.lo;
-  d.ctrl_hi = g.ctrl.hi;
-  d.target = g.target;
-  const bool unit = g.m[0].re == 1.0 && g.m[0].im == 0.0 && g.m[1].re == 1.0 && g.m[1].im == 0.0;
-  d.flags = (unit ? 0u : kHasPhase) | (g.flip ? kFlip : 0u);
-  d.m0 = make_double2(g.m[0].re, g.m[0].im);
-  d.m1 = make_double2(g.m[1].re, g.m[1].im);
-  return d;
-}
-
-// ---- bit-sliced pass compilation ---------------------------------------------
-// Exact eighth-turn factors omega^k = e^{i pi k / 4}; -1 if m is not one.
-int omega_index(const double2& m) {
-  const double h = M_SQRT1_2;
-  const double re[8] = {1.0, h, 0.0, -h, -1.0, -h, 0.0, h};
-  const double im[8] = {0.0, h, 1.0, h, 0.0, -h, -1.0, -h};
-  for (int k = 0; k < 8; ++k)
-    if (m.x == re[k] && m.y == im[k]) return k;
-  return -1;
-}
-
-bool unit_modulus(const double2& m) { return std::fabs(m.x * m.x + m.y * m.y - 1.0) <= 1e-14; }
-
-// Argument of m as a turn fraction in units of 2^-64 turn (wraps exactly).
-uint64_t turn_of(const double2& m) {
-  const long double tau = (long double)std::atan2(m.y, m.x) / (2.0L * (long double)M_PI);   // [-1/2, 1/2]
-  long double v = tau * 18446744073709551616.0L;
-  if (v >= 9223372036854775807.0L) v -= 18446744073709551616.0L;
-  return (uint64_t)(int64_t)std::llroundl(v);
-}
-
-uint8_t word_bit(uint32_t q) { return (uint8_t)(1u << (q >> 5)); }
-
-// Per op: a factor m0 on labels with the target bit 0 and m1 with it 1 equals
-// m0 everywhere (under the controls) times m1/m0 where the target bit is 1.
-void compile_bitslice(sim_t* s, size_t n_mono) {
-  s->h_bs.clear();
-  s->bs_start.assign(n_mono + 1, 0);
-  s->bs_gate.assign(n_mono, sim_t::BsGate{});
-  for (size_t k = 0; k < n_mono; ++k) {
-    const MonoDesc& d = s->h_descs[k];
-    sim_t::BsGate& inf = s->bs_gate[k];
-    s->bs_start[k] = (uint32_t)s->h_bs.size();
-    inf.eligible = true;
-    BsOp base{};
-    base.target = (uint8_t)d.target;
-    uint8_t rd = 0;
-    for (int w = 0; w < 2; ++w) {
-      uint64_t m = w ? d.ctrl_hi : d.ctrl_lo;
-      while (m) {
-        const uint32_t q = (uint32_t)__builtin_ctzll(m) + 64u * w;
-        m &= m - 1;
-        if (base.nctrl == kBsMaxCtrl) {
-          inf.eligible = false;
-          break;
-        }
-        base.ctrl[base.nctrl++] = (uint8_t)q;
-        rd |= word_bit(q);
-      }
-    }
-    if (!inf.eligible) continue;
-    auto emit = [&](uint8_t op, uint8_t cmode, uint64_t arg) {
-      BsOp o = base;
-      o.op = op;
-      o.cmode = cmode;
-      o.arg = arg;
-      s->h_bs.push_back(o);
-      if (cmode) rd |= word_bit(d.target);
-    };
-    if (d.flags & kHasPhase) {
-      const int k0 = omega_index(d.m0), k1 = omega_index(d.m1);
-      if (k0 >= 0 && k1 >= 0) {
-        if (k0) {
-          if (base.nctrl == 0) inf.g_omega = (uint8_t)((inf.g_omega + k0) & 7);
-          else emit(kBsOmega, 0, (uint64_t)k0);
-        }
-        const uint32_t dk = (uint32_t)(k1 - k0) & 7u;
-        if (dk) emit(kBsOmega, 1, dk);
-      } else if (unit_modulus(d.m0) && unit_modulus(d.m1)) {
-        const uint64_t t0 = turn_of(d.m0), t1 = turn_of(d.m1);
-        if (t0) {
-          if (base.nctrl == 0) inf.g_turn += t0;
-          else {
-            emit(kBsTurn, 0, t0);
-            inf.turns = true;
-          }
-        }
-        if (t1 - t0) {
-          emit(kBsTurn, 1, t1 - t0);
-          inf.turns = true;
-        }
-      } else {
-        inf.eligible = false;
-        continue;
-      }
-      inf.phase = true;
-    }
-    if (d.flags & kFlip) {
-      emit(kBsFlip, 0, 0);
-      inf.words_write = word_bit(d.target);
-    }
-    inf.words_read = rd;
-  }
-  s->bs_start[n_mono] = (uint32_t)s->h_bs.size();
-}
-
-bool use_bitslice(sim_t* s, size_t begin, size_t len, BsRun* br) {
-  const uint32_t min_gates = s->cfg.bs_min_gates ? s->cfg.bs_min_gates : 16u;
-  if (s->cfg.mono_mode == SIM_MONO_AUTO && len < min_gates) return false;
-  std::memset(br, 0, sizeof *br);
-  uint32_t g_omega = 0;
-  for (size_t k = begin; k < begin + len; ++k) {
-    const sim_t::BsGate& g = s->bs_gate[k];
-    if (!g.eligible) return false;
-    br->words_read |= g.words_read | g.words_write;
-    br->words_write |= g.words_write;
-    br->has_phase |= g.phase ? 1u : 0u;
-    br->has_turns |= g.turns ? 1u : 0u;
-    g_omega += g.g_omega;
-    br->g_turn += g.g_turn;
-  }
-  if (br->words_write & 3u) br->words_read |= 3u;
-  if (br->words_write & 12u) br->words_read |= 12u;
-  br->g_omega = g_omega & 7u;
-  br->n_planes = s->cfg.n_qubits;
-  br->n_gates = (uint32_t)len;
-  return true;
-}
-
-// Pack the ops [op0, op1) into groups of kBsGroup consecutive ops that touch
-// no plane another member of the group writes (so the kernel may read all of
-// a group's planes before any write), padding groups with no-op flips of the
-// scratch plane.  Order is kept across groups; within a group the ops are
-// independent, and phase accumulations commute exactly.
-void group_ops(sim_t* s, uint32_t op0, uint32_t op1) {
-  const uint8_t ones = (uint8_t)s->cfg.n_qubits, scratch = (uint8_t)(s->cfg.n_qubits + 1);
-  struct Mask {
-    uint64_t lo = 0, hi = 0;
-    void set(uint32_t q) { (q < 64 ? lo : hi) |= 1ull << (q & 63); }
-    bool meets(const Mask& o) const { return (lo & o.lo) || (hi & o.hi); }
-    void add(const Mask& o) { lo |= o.lo; hi |= o.hi; }
-  };
-  Mask gr, gw;
-  int in_group = 0;
-  auto close = [&]() {
-    for (; in_group && in_group < kBsGroup; ++in_group) {
-      BsOpG pad{};
-      pad.op = kBsFlip;
-      pad.t = scratch;
-      pad.p0 = pad.p1 = pad.p2 = ones;
-      s->h_grp.push_back(pad);
-    }
-    in_group = 0;
-    gr = Mask{};
-    gw = Mask{};
-  };
-  for (uint32_t i = op0; i < op1; ++i) {
-    const BsOp& o = s->h_bs[i];
-    Mask r, w;
-    for (int c = 0; c < o.nctrl; ++c) r.set(o.ctrl[c]);
-    if (o.cmode || o.op == kBsFlip) r.set(o.target);
-    if (o.op == kBsFlip) w.set(o.target);
-    if (in_group == kBsGroup || w.meets(gr) || w.meets(gw) || r.meets(gw)) close();
-    BsOpG g{};
-    g.op = o.op;
-    g.t = (o.op == kBsFlip || o.cmode) ? o.target : ones;   // flip target, or a phase op's target-bit condition
-    uint8_t slot[3] = {ones, ones, ones};
-    for (int c = 0; c < o.nctrl; ++c) slot[c] = o.ctrl[c];
-    g.p0 = slot[0];
-    g.p1 = slot[1];
-    g.p2 = slot[2];
-    g.k = o.op == kBsOmega ? (uint8_t)o.arg : 0;
-    g.tau = o.op == kBsTurn ? o.arg : 0;
-    s->h_grp.push_back(g);
-    gr.add(r);
-    gw.add(w);
-    ++in_group;
-  }
-  close();
+  std::string why;
+  if (gate_valid(s->cfg.n_qubits, g, &why)) return SIM_OK;
+  return fail(SIM_E_ARG, "op " + std::to_string(i) + ": " + why);
 }
 
 int bs_grid(const sim_t* s, uint64_t n) {
@@ -780,25 +559,25 @@ int sim_apply_gates(sim_t* s, const sim_gate* gates, size_t n, int32_t* outcomes
     if (gates[i].op == SIM_OP_MEASURE) ++n_meas;
   }
   // Stage the phase/permutation descriptors in one upload.
-  s->h_descs.resize(n_mono);
+  s->rc.descs.resize(n_mono);
   for (size_t i = 0, k = 0; i < n; ++i)
-    if (gates[i].op == SIM_OP_MONO) s->h_descs[k++] = mono_desc(gates[i]);
+    if (gates[i].op == SIM_OP_MONO) s->rc.descs[k++] = mono_desc(gates[i]);
   // Bit-sliced bytecode of every phase/permutation op (used by eligible runs).
   const bool bs_allowed = s->cfg.mono_mode != SIM_MONO_DIRECT;
-  if (bs_allowed) compile_bitslice(s, n_mono);
+  if (bs_allowed) s->rc.compile(s->cfg.n_qubits);
   HIP_TRY(s->descs.reserve(n_mono));
   HIP_TRY(s->recs.reserve(n_meas));
   HIP_TRY(s->outcomes.reserve(n_meas));
   if (n_mono)
-    HIP_TRY(hipMemcpyAsync(s->descs.p, s->h_descs.data(), n_mono * sizeof(MonoDesc), hipMemcpyHostToDevice,
+    HIP_TRY(hipMemcpyAsync(s->descs.p, s->rc.descs.data(), n_mono * sizeof(MonoDesc), hipMemcpyHostToDevice,
                            s->stream));
   // Grouped kernel ops of the bit-sliced runs, appended run by run; padding
   // at most triples the count, so reserving up front keeps the host copies
   // of in-flight uploads in place.
   s->h_grp.clear();
   if (bs_allowed) {
-    s->h_grp.reserve(kBsGroup * s->h_bs.size() + kBsGroup);
-    HIP_TRY(s->grp_ops.reserve(kBsGroup * s->h_bs.size() + kBsGroup));
+    s->h_grp.reserve(kBsGroup * s->rc.ops.size() + kBsGroup);
+    HIP_TRY(s->grp_ops.reserve(kBsGroup * s->rc.ops.size() + kBsGroup));
   }
 
   int result = SIM_OK;
@@ -808,19 +587,18 @@ int sim_apply_gates(sim_t* s, const sim_gate* gates, size_t n, int32_t* outcomes
     const uint64_t ub = s->nnz_known ? s->nnz_exact : s->nnz_ub;
     uint32_t run_flags = 0;
     for (size_t k = run_begin; k < run_begin + run_len; ++k) {
-      if (s->h_descs[k].flags & kHasPhase) run_flags |= kRunPhase;
-      if (s->h_descs[k].flags & kFlip) run_flags |= kRunFlip;
+      if (s->rc.descs[k].flags & kHasPhase) run_flags |= kRunPhase;
+      if (s->rc.descs[k].flags & kFlip) run_flags |= kRunFlip;
     }
     // Algorithmic bytes per entry: label read (+ write if a gate flips),
     // amplitude read and write if a gate has a phase.
     const uint32_t kb = s->wide ? 16u : 8u;
     const uint32_t run_bpe = kb + ((run_flags & kRunFlip) ? kb : 0u) + ((run_flags & kRunPhase) ? 32u : 0u);
     BsRun br;
-    if (bs_allowed && use_bitslice(s, run_begin, run_len, &br)) {
+    if (bs_allowed && s->rc.run_params(run_begin, run_len, s->cfg.mono_mode, s->cfg.bs_min_gates, &br)) {
       br.bytes_per_entry = run_bpe;
-      const uint32_t op0 = s->bs_start[run_begin], op1 = s->bs_start[run_begin + run_len];
       const size_t g0 = s->h_grp.size();
-      group_ops(s, op0, op1);
+      s->rc.group(run_begin, run_len, s->h_grp);
       const size_t ng = (s->h_grp.size() - g0) / kBsGroup;
       if (ng)
         HIP_TRY(hipMemcpyAsync(s->grp_ops.p + g0, s->h_grp.data() + g0, (s->h_grp.size() - g0) * sizeof(BsOpG),

@@ -104,6 +104,62 @@ struct BlockScratch {
   double2* part;               // measurement: per-block (P0, P1)
 };
 
+// ---- batched execution (many states per launch) -----------------------------
+// A tick applies one segment (a fused run, a branching gate or a measurement)
+// to every active state.  Work is cut into units of kChunk entries of one
+// state, so a state's results never depend on which other states share the
+// launch.
+constexpr uint32_t kChunk = 2048;          // entries per unit (= one bit-sliced tile)
+constexpr uint32_t kFillUnit = 8192;       // index slots per fill unit
+constexpr uint32_t kMaxPlanes = 130;       // 128 label planes + all-ones + scratch
+constexpr uint32_t kStOverflow = 1u, kStMeasure = 2u;
+
+// Per-state control words, one slot each, read back after every tick.
+struct SlotCtl {
+  uint64_t nnz[2];
+  MeasRec rec;
+  int32_t outcome;
+  uint32_t status;
+};
+static_assert(sizeof(SlotCtl) == 56, "SlotCtl layout");
+
+struct BItem {
+  Buf in, out;                 // current and other buffer of the state
+  SlotCtl* ctl;                // the state's control words
+  uint32_t other;              // index of `out` in ctl->nnz
+  uint32_t wide;
+  uint64_t nnz;                // entries at input (exact)
+  uint64_t cap;                // capacity of the state
+  // fused run
+  const BsOpG* gops;           // bit-sliced groups (gops != null) ...
+  uint32_t ngroups, n_dops;
+  const MonoDesc* dops;        // ... or per-entry descriptors
+  BsRun run;
+  uint32_t run_flags, pad0;
+  // branching gate
+  U2Desc u2;
+  uint64_t* table;
+  uint64_t mask;
+  uint32_t* partner;
+  uint32_t* tot;               // per-unit counts -> offsets; tot[units] = total
+  // measurement
+  uint32_t q;
+  int32_t forced;
+  double u;
+  double2* part;
+  uint32_t* cnt1;
+};
+
+// Tick header: item counts and the offsets (in uint32 words from the start
+// of the unit table) of each family's first-unit arrays (length n + 1).
+struct BTick {
+  uint32_t n_mono, n_u2, n_meas, pad;
+  uint32_t mono_u0, fill_u0, build_u0, chunk_u0, meas_u0;
+  uint32_t pad2[3];
+};
+
+void launch_batch_tick(hipStream_t st, const BTick* hdr, const BItem* items, const uint32_t* units, int grid);
+
 // ---- launchers (sim_kernels.hip) -------------------------------------------
 void launch_set_basis(hipStream_t st, Buf b, uint64_t* nnz, uint64_t lo, uint64_t hi);
 void launch_mono(hipStream_t st, bool wide, Buf b, const uint64_t* nnz, const MonoDesc* g, uint32_t ng,

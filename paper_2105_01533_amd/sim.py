@@ -301,3 +301,177 @@ def run_workload(w, **kw):
     s.set_basis(*w.basis)
     _, outcomes, stats = s.apply_ops(w.ops)
     return s, outcomes, stats
+
+
+# --- continuous-batching server (srv_*) -----------------------------------------
+SRV_QUEUED, SRV_RUNNING, SRV_DONE, SRV_FAILED = 0, 1, 2, 3
+SRV_FLAG_NO_GRAPH = 1
+
+
+class srv_config(ctypes.Structure):
+    _fields_ = [("budget_bytes", ctypes.c_uint64), ("arena_bytes", ctypes.c_uint64),
+                ("max_slots", ctypes.c_uint32), ("flags", ctypes.c_uint32)]
+
+
+class srv_stats(ctypes.Structure):
+    _fields_ = [(f, ctypes.c_uint64) for f in (
+        "submitted", "admitted", "completed", "failed", "ticks", "items", "bitslice_runs",
+        "pool_used_bytes", "pool_peak_bytes")]
+
+    def as_dict(self):
+        return {f: int(getattr(self, f)) for f, _ in self._fields_}
+
+
+def _srv_sigs():
+    vp, u64, i32, sz = ctypes.c_void_p, ctypes.c_uint64, ctypes.c_int32, ctypes.c_size_t
+    sig = {
+        "srv_footprint": (sz, [vp]),
+        "srv_create": (i32, [vp, vp, vp, sz, ctypes.POINTER(vp)]),
+        "srv_destroy": (i32, [vp]),
+        "srv_submit": (i32, [vp, vp, vp, sz, sim_key, ctypes.POINTER(u64)]),
+        "srv_tick": (i32, [vp, ctypes.POINTER(ctypes.c_uint32), ctypes.POINTER(ctypes.c_uint32)]),
+        "srv_run": (i32, [vp]),
+        "srv_poll": (i32, [vp, u64, ctypes.POINTER(i32), ctypes.POINTER(i32)]),
+        "srv_result": (i32, [vp, u64, vp, vp, u64, ctypes.POINTER(u64), vp, u64, ctypes.POINTER(u64), vp]),
+        "srv_release": (i32, [vp, u64]),
+        "srv_get_stats": (i32, [vp, vp]),
+        "srv_last_error": (ctypes.c_char_p, []),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(_lib, name)
+        f.restype = res
+        f.argtypes = args
+
+
+_srv_sigs()
+
+
+class ServerError(RuntimeError):
+    def __init__(self, code: int, where: str):
+        self.code = code
+        super().__init__(f"{where}: {sim_strerror(code)} ({code}): {srv_last_error()}")
+
+
+def _scheck(rc: int, where: str):
+    if rc != SIM_OK:
+        raise ServerError(rc, where)
+
+
+def srv_last_error() -> str:
+    return _lib.srv_last_error().decode()
+
+
+def srv_footprint(cfg: sim_config) -> int:
+    return int(_lib.srv_footprint(ctypes.byref(cfg)))
+
+
+def srv_create(cfg: srv_config, stream=None, pool=None, pool_bytes: int = 0):
+    h = ctypes.c_void_p()
+    _scheck(_lib.srv_create(ctypes.byref(cfg), stream, pool, pool_bytes, ctypes.byref(h)), "srv_create")
+    return h
+
+
+def srv_destroy(h):
+    _scheck(_lib.srv_destroy(h), "srv_destroy")
+
+
+def srv_submit(h, cfg: sim_config, gates: np.ndarray, basis=(0, 0)) -> int:
+    gates = np.ascontiguousarray(gates, dtype=GATE_DTYPE)
+    rid = ctypes.c_uint64()
+    _scheck(_lib.srv_submit(h, ctypes.byref(cfg), _ptr(gates), len(gates), sim_key(*basis), ctypes.byref(rid)),
+            "srv_submit")
+    return rid.value
+
+
+def srv_tick(h):
+    r, q = ctypes.c_uint32(), ctypes.c_uint32()
+    _scheck(_lib.srv_tick(h, ctypes.byref(r), ctypes.byref(q)), "srv_tick")
+    return r.value, q.value
+
+
+def srv_run(h):
+    _scheck(_lib.srv_run(h), "srv_run")
+
+
+def srv_poll(h, rid: int):
+    st, err = ctypes.c_int32(), ctypes.c_int32()
+    _scheck(_lib.srv_poll(h, rid, ctypes.byref(st), ctypes.byref(err)), "srv_poll")
+    return st.value, err.value
+
+
+def srv_result(h, rid: int, sort: bool = True):
+    """(lo, hi, amp, outcomes, stats dict) of a finished request."""
+    nnz, nout = ctypes.c_uint64(), ctypes.c_uint64()
+    st = sim_stats()
+    rc = _lib.srv_result(h, rid, None, None, 0, ctypes.byref(nnz), None, 0, ctypes.byref(nout), ctypes.byref(st))
+    if rc not in (SIM_OK, SIM_E_BUFFER):
+        raise ServerError(rc, "srv_result")
+    keys = np.empty(max(nnz.value, 1), KEY_DTYPE)
+    amp = np.empty(max(nnz.value, 1), np.complex128)
+    outs = np.empty(max(nout.value, 1), np.int32)
+    _scheck(_lib.srv_result(h, rid, _ptr(keys), _ptr(amp), len(keys), ctypes.byref(nnz), _ptr(outs), len(outs),
+                            ctypes.byref(nout), ctypes.byref(st)), "srv_result")
+    n = nnz.value
+    lo, hi, amp = keys["lo"][:n].copy(), keys["hi"][:n].copy(), amp[:n].copy()
+    if sort:
+        order = np.lexsort((lo, hi))
+        lo, hi, amp = lo[order], hi[order], amp[order]
+    return lo, hi, amp, outs[:nout.value].copy(), st.as_dict()
+
+
+def srv_release(h, rid: int):
+    _scheck(_lib.srv_release(h, rid), "srv_release")
+
+
+def srv_get_stats(h) -> dict:
+    st = srv_stats()
+    _scheck(_lib.srv_get_stats(h, ctypes.byref(st)), "srv_get_stats")
+    return st.as_dict()
+
+
+class Server:
+    """Continuous-batching server on one device; states live in a pool of
+    budget_bytes borrowed from torch."""
+
+    def __init__(self, budget_bytes: int, max_slots: int = 256, arena_bytes: int = 0, graph: bool = True,
+                 device: str = "cuda"):
+        self.cfg = srv_config(budget_bytes=budget_bytes, arena_bytes=arena_bytes, max_slots=max_slots,
+                              flags=0 if graph else SRV_FLAG_NO_GRAPH)
+        self.pool = torch.empty(budget_bytes, dtype=torch.uint8, device=device)
+        self.h = srv_create(self.cfg, None, self.pool.data_ptr(), budget_bytes)
+
+    def close(self):
+        if getattr(self, "h", None):
+            srv_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def submit_workload(self, w, **tuning) -> int:
+        cfg = sim_config(n_qubits=w.n_qubits, capacity=w.capacity, eps=w.eps, **tuning)
+        return srv_submit(self.h, cfg, sim_gates_from_ops(w.ops), w.basis)
+
+    def submit(self, cfg: sim_config, gates: np.ndarray, basis=(0, 0)) -> int:
+        return srv_submit(self.h, cfg, gates, basis)
+
+    def tick(self):
+        return srv_tick(self.h)
+
+    def run(self):
+        srv_run(self.h)
+
+    def poll(self, rid):
+        return srv_poll(self.h, rid)
+
+    def result(self, rid, sort=True):
+        return srv_result(self.h, rid, sort)
+
+    def release(self, rid):
+        srv_release(self.h, rid)
+
+    def stats(self):
+        return srv_get_stats(self.h)

@@ -1,0 +1,157 @@
+"""GPU tests of the continuous-batching server (srv_* through the C-ABI).
+
+Each request's result must be the same alone and in a mix (bitwise: the
+batched kernels cut every state into fixed 2048-entry units), match the
+oracle at the parity bar (labels exact, amplitudes within 1e-12, same
+measurement outcomes), and the admission rules must hold: FIFO order, the
+pool budget never exceeded, oversized requests rejected, failures confined
+to their request.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from helpers import assert_same_state
+from oracle import run_workload as oracle_run
+from paper_2105_01533_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+@pytest.fixture(scope="module")
+def S():
+    from paper_2105_01533_amd import sim
+    import torch
+    assert torch.cuda.is_available()
+    return sim
+
+
+def mix():
+    ws = [
+        W.config0(41, n=20, h_qubits=6, gates=1500, cap=1 << 10),
+        W.config0(42, n=70, h_qubits=9, gates=3000, cap=1 << 12),
+        W.config1(43, w=8, adds=6, n=24),
+        W.config2(44, n=100, h_qubits=10, gates=6000, round_gates=2000, meas_per_round=3),
+        W.config2(45, n=40, h_qubits=13, gates=4000, round_gates=1000, meas_per_round=2),
+        W.config3(46, terms=30),
+        W.random_circuit(47, n=9, gates=300, h_frac=0.2, ctrl_max=3, measure_frac=0.02),
+        W.random_circuit(48, n=128, gates=200, h_frac=0.03, ctrl_max=4, measure_frac=0.01),
+    ]
+    ws[6].capacity = 1 << 9
+    ws[7].capacity = 1 << 14
+    return ws
+
+
+def run_server(S, ws, budget=1 << 30, slots=64, graph=True, **tuning):
+    srv = S.Server(budget, max_slots=slots, graph=graph)
+    ids = [srv.submit_workload(w, **tuning) for w in ws]
+    srv.run()
+    out = []
+    for rid in ids:
+        st, err = srv.poll(rid)
+        assert st == S.SRV_DONE, (st, err)
+        out.append(srv.result(rid))
+    stats = srv.stats()
+    srv.close()
+    return out, stats
+
+
+def test_alone_equals_mix_and_oracle(S):
+    ws = mix()
+    say("[gpu] server: mix of", len(ws))
+    together, stats = run_server(S, ws)
+    assert stats["completed"] == len(ws) and stats["failed"] == 0
+    assert stats["ticks"] < sum(r[4]["mono_passes"] + r[4]["u2_applied"] + r[4]["measures"] for r in together)
+    for w, res in zip(ws, together):
+        alone, _ = run_server(S, [w])
+        for a, b in zip(alone[0][:4], res[:4]):
+            assert a.tobytes() == b.tobytes(), w.name
+        o, oout, _ = oracle_run(w)
+        assert list(res[3]) == list(oout), w.name
+        assert_same_state(res[:3], o.export(), what=w.name)
+        t = o.totals()
+        assert res[4]["updates"] == t["updates"] and res[4]["u2_applied"] == t["u2_applied"]
+        assert res[4]["u2_skipped"] == t["u2_skipped"]
+
+
+def test_graph_replay_equals_direct_launches(S):
+    ws = mix()[:5]
+    a, sa = run_server(S, ws, graph=True)
+    b, sb = run_server(S, ws, graph=False)
+    assert sa["ticks"] == sb["ticks"]
+    for x, y in zip(a, b):
+        for p, q in zip(x[:4], y[:4]):
+            assert p.tobytes() == q.tobytes()
+
+
+def test_direct_mode_requests(S):
+    ws = mix()[:4]
+    res, _ = run_server(S, ws, mono_mode=S.SIM_MONO_DIRECT)
+    for w, r in zip(ws, res):
+        o, oout, _ = oracle_run(w)
+        assert list(r[3]) == list(oout)
+        assert_same_state(r[:3], o.export(), what=w.name)
+
+
+def test_budget_fifo_and_queueing(S):
+    small = W.config0(51, n=20, h_qubits=5, gates=400, cap=1 << 8)
+    big = W.config0(52, n=20, h_qubits=5, gates=400, cap=1 << 14)
+    cfg = lambda w: S.sim_config(n_qubits=w.n_qubits, capacity=w.capacity, eps=w.eps)
+    fb, fs = S.srv_footprint(cfg(big)), S.srv_footprint(cfg(small))
+    assert fb > 4 * fs
+    budget = fb + fs                                 # room for big + one small, never big + two small
+    srv = S.Server(budget, max_slots=8)
+    ids = [srv.submit_workload(w) for w in (small, big, small, small)]
+    srv.tick()
+    states = [srv.poll(i)[0] for i in ids]
+    assert states[0] == S.SRV_RUNNING or states[0] == S.SRV_DONE
+    assert states[1] in (S.SRV_RUNNING, S.SRV_DONE)
+    # FIFO: the third request (small) may not overtake while memory is short
+    assert states[2] == S.SRV_QUEUED or states[1] != S.SRV_QUEUED
+    srv.run()
+    st = srv.stats()
+    assert st["completed"] == 4 and st["pool_peak_bytes"] <= budget
+    srv.close()
+
+
+def test_oversized_and_invalid_requests_rejected(S):
+    srv = S.Server(1 << 22, max_slots=4)
+    w = W.config0(53, n=20, h_qubits=5, gates=100, cap=1 << 20)
+    with pytest.raises(S.ServerError) as e:
+        srv.submit_workload(w)
+    assert e.value.code == S.SIM_E_CAPACITY
+    c = W.Circuit()
+    c.x(3, (3,))
+    with pytest.raises(S.ServerError) as e:
+        srv.submit(S.sim_config(n_qubits=8, capacity=16), S.sim_gates_from_ops(c.array()))
+    assert e.value.code == S.SIM_E_ARG
+    assert srv.stats()["submitted"] == 0
+    srv.close()
+
+
+def test_failures_stay_in_their_request(S):
+    srv = S.Server(1 << 28, max_slots=8)
+    good = W.config0(54, n=20, h_qubits=5, gates=300, cap=1 << 8)
+    c = W.Circuit()
+    for q in range(6):
+        c.h(q)                                   # 64 entries > capacity 32
+    over = W.Workload("over", 10, 0.0, c.array(), capacity=32)
+    m = W.Circuit()
+    m.h(0)
+    m.measure(1, 0.0, forced=1)                  # qubit 1 is 0 everywhere
+    zero = W.Workload("zero", 4, 0.0, m.array(), capacity=8)
+    ids = [srv.submit_workload(w) for w in (good, over, zero, good)]
+    srv.run()
+    res = [srv.poll(i) for i in ids]
+    assert res[0] == (S.SRV_DONE, 0) and res[3] == (S.SRV_DONE, 0)
+    assert res[1] == (S.SRV_FAILED, S.SIM_E_CAPACITY)
+    assert res[2] == (S.SRV_FAILED, S.SIM_E_STATE)
+    a, b = srv.result(ids[0]), srv.result(ids[3])
+    for p, q in zip(a[:4], b[:4]):
+        assert p.tobytes() == q.tobytes()
+    srv.close()
