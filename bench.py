@@ -109,6 +109,46 @@ def hbm_sweep(sim, W, n_qubits=100, log2n=24, depths=(1, 2, 4, 16, 64)):
     return out
 
 
+def serving_bench(sim, W, requests=128, max_log2=18, max_gates=50_000, budget_gib=32, check=True):
+    """Continuous batching vs one-at-a-time plain launches on one Poisson
+    trace (config-0..2 families, entry caps 2^8..2^max_log2, 10^3..max_gates
+    gates).  The arrival rate is 0.8x the one-at-a-time service rate measured
+    on the same requests back to back."""
+    import numpy as np
+
+    from paper_2105_01533_amd import serving
+
+    trace = W.serving_trace(4242, requests=requests, rate=1.0, cap_log2=(8, max_log2),
+                            gates_range=(1000, max_gates))
+    reqs = serving.prepare(trace)
+    closed, _ = serving.run_one_at_a_time(reqs, arrivals=False)
+    rate = 0.8 * closed["requests_per_s"]
+    scale = 1.0 / rate                           # trace was drawn at rate 1
+    for r, (t, _) in zip(reqs, trace):
+        r.arrival = t * scale
+    log(f"[bench] serving: closed-loop one-at-a-time {closed['requests_per_s']:.1f} req/s -> lambda {rate:.1f}/s")
+    base, rb = serving.run_one_at_a_time(reqs, arrivals=True, keep_results=check)
+    log(f"[bench] serving one-at-a-time: {base}")
+    bat, rs = serving.run_batched(reqs, budget_gib << 30, arrivals=True, keep_results=check)
+    log(f"[bench] serving batched: {bat}")
+    worst = 0.0
+    mism = 0
+    if check:
+        for x, y in zip(rb, rs):
+            if x is None or y is None or x[0] is None:
+                continue
+            (lo, hi, amp), outs = x[0], x[1]
+            if not (np.array_equal(lo, y[0]) and np.array_equal(hi, y[1]) and list(outs) == list(y[3])):
+                mism += 1
+            elif len(amp):
+                worst = max(worst, float(np.max(np.abs(amp - y[2]))))
+    return {"trace": f"{requests} Poisson requests, families c0/c1/c2, caps 2^8..2^{max_log2}, "
+                     f"1e3..{max_gates} gates, lambda = 0.8 x one-at-a-time rate = {rate:.2f}/s",
+            "batched": bat, "one_at_a_time": base,
+            "throughput_ratio": bat["requests_per_s"] / base["requests_per_s"],
+            "results_max_abs_diff": worst, "results_label_mismatches": mism}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -117,6 +157,10 @@ def main():
     ap.add_argument("--workload", default="c2", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-sweep", action="store_true")
+    ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--serving-requests", type=int, default=128)
+    ap.add_argument("--serving-max-log2", type=int, default=18)
+    ap.add_argument("--serving-max-gates", type=int, default=50_000)
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--mono-mode", type=int, default=0, help="0 auto, 1 direct, 2 bit-sliced")
     ap.add_argument("--fuse-max", type=int, default=0)
@@ -183,6 +227,9 @@ def main():
     s.close()
     if not args.no_sweep:
         out["hbm_sweep"] = hbm_sweep(sim, W)
+    if not args.no_serving:
+        out["serving"] = serving_bench(sim, W, args.serving_requests, args.serving_max_log2,
+                                       args.serving_max_gates)
     if not args.no_cpu_baseline:
         log("[bench] cpu baseline (oracle) ...")
         out["cpu_baseline"] = cpu_baseline(w, args.cpu_seconds)
