@@ -158,6 +158,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-sweep", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="run the 1 GiB reference copy kernel (for hardware byte-counter scaling) first")
     ap.add_argument("--serving-requests", type=int, default=128)
     ap.add_argument("--serving-max-log2", type=int, default=18)
     ap.add_argument("--serving-max-gates", type=int, default=50_000)
@@ -174,6 +176,13 @@ def main():
 
     from paper_2105_01533_amd import sim, workloads as W
 
+    if args.calibrate_copy:
+        a = torch.empty(1 << 30, dtype=torch.uint8, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(3):
+            sim.sim_device_copy(b.data_ptr(), a.data_ptr(), 1 << 30, torch.cuda.current_stream().cuda_stream)
+        torch.cuda.synchronize()
+        del a, b
     fn, desc = WORKLOADS[args.workload]
     w = getattr(W, fn)()
     log(f"[bench] workload {w.name}: {len(w.ops)} ops, capacity {w.capacity}")

@@ -239,6 +239,12 @@ typedef struct sim_kernel_stat {
  * not at all.  SIM_E_ARG on invalid values. */
 int sim_set_tuning(sim_t* s, const sim_config* t);
 
+/* Bandwidth reference: copy `bytes` (a multiple of 16) from device src to
+ * device dst with a plain streaming kernel on `stream` (NULL = null stream);
+ * asynchronous.  Used to calibrate hardware byte counters against a kernel
+ * that moves a known number of bytes.  SIM_E_ARG for a bad size. */
+int sim_device_copy(void* dst, const void* src, size_t bytes, void* stream);
+
 int sim_set_profiling(sim_t* s, int on);
 /* Writes up to cap records; *n receives the number of kernel classes. */
 int sim_kernel_stats(sim_t* s, sim_kernel_stat* out, int cap, int* n);

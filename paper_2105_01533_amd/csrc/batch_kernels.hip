@@ -121,7 +121,7 @@ __device__ __forceinline__ uint32_t prefix012(uint32_t e, uint32_t* s_wave, uint
 }
 
 // ---- fused runs: one 2048-entry tile per unit, one wave per block ----------
-__global__ __launch_bounds__(64) void kb_mono(const BTick* __restrict__ hdr, const BItem* __restrict__ items,
+__global__ __launch_bounds__(64, 2) void kb_mono(const BTick* __restrict__ hdr, const BItem* __restrict__ items,
                                               const uint32_t* __restrict__ units) {
   extern __shared__ uint32_t lds_all[];
   uint32_t* L = lds_all + threadIdx.x;
@@ -135,7 +135,6 @@ __global__ __launch_bounds__(64) void kb_mono(const BTick* __restrict__ hdr, con
     const uint64_t base = (uint64_t)(u - u0[i]) * kChunk;
     const uint32_t lim = (uint32_t)(it.nnz - base < kChunk ? it.nnz - base : kChunk);
     if (it.gops) {
-      L[it.run.n_planes * 64] = ~0u;
       if (it.run.has_turns)
         bs::bs_tile<true>(it.in, base, lim, it.gops, it.ngroups, it.run, L);
       else

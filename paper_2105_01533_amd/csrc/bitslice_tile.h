@@ -124,7 +124,10 @@ __device__ __forceinline__ void bs_tile(const Buf& b, uint64_t base, uint32_t li
   const uint32_t nops = ngroups * kBsGroup;
     const uint32_t rw = run.words_read | run.words_write;
     if (rw & 3u) load_pair(b.key_lo + base + lane, lim, L, 0, nq);
+    __builtin_amdgcn_sched_barrier(0);
     if (rw & 12u) load_pair(b.key_hi + base + lane, lim, L, 2, nq);
+    __builtin_amdgcn_sched_barrier(0);
+    L[nq * 64] = ~0u;                     // the all-ones plane (the previous tile may have reused it)
     uint32_t e0 = 0, e1 = 0, e2 = 0;
     uint64_t turns[TURNS ? 32 : 1];
 #pragma unroll
@@ -167,20 +170,33 @@ __device__ __forceinline__ void bs_tile(const Buf& b, uint64_t base, uint32_t li
       cur = nxt;
     }
     // Labels back to memory (only words some gate flips).
+    __builtin_amdgcn_sched_barrier(0);
     if (run.words_write & 3u) store_pair(b.key_lo + base + lane, lim, L, 0, nq);
+    __builtin_amdgcn_sched_barrier(0);
     if (run.words_write & 12u) store_pair(b.key_hi + base + lane, lim, L, 2, nq);
-    // One complex multiply per amplitude by the accumulated phase.
+    __builtin_amdgcn_sched_barrier(0);
+    // One complex multiply per amplitude by the accumulated phase.  The label
+    // planes are dead now: the turn accumulators move to LDS (two words per
+    // entry per lane) so the loop below need not be unrolled.
     if (run.has_phase) {
-      double2* amp = b.amp + base + lane;
+      if (TURNS) {
 #pragma unroll
+        for (int j = 0; j < 32; ++j) {
+          L[(2 * j) * 64] = (uint32_t)turns[j];
+          L[(2 * j + 1) * 64] = (uint32_t)(turns[j] >> 32);
+        }
+      }
+      double2* amp = b.amp + base + lane;
+#pragma unroll 1
       for (int j = 0; j < 32; ++j) {
-        if (64u * j + lane >= lim) continue;
+        if (64u * j + lane >= lim) break;
         const uint32_t k = ((((e2 >> j) & 1u) << 2) | (((e1 >> j) & 1u) << 1) | ((e0 >> j) & 1u)) + run.g_omega;
         double2 f;
         if (!TURNS && run.g_turn == 0) {
           f = omega_pow(k);
         } else {
-          const uint64_t T = (TURNS ? turns[j] : 0ull) + run.g_turn + ((uint64_t)(k & 7u) << 61);
+          const uint64_t tj = TURNS ? (((uint64_t)L[(2 * j + 1) * 64] << 32) | L[(2 * j) * 64]) : 0ull;
+          const uint64_t T = tj + run.g_turn + ((uint64_t)(k & 7u) << 61);
           double sn, cs;
           sincospi((double)(T >> 11) * 0x1p-52, &sn, &cs);   // angle = 2 pi T / 2^64
           f = make_double2(cs, sn);

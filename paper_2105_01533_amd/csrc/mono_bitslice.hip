@@ -24,13 +24,12 @@ namespace sparsesim {
 namespace {
 
 template <bool TURNS>
-__global__ __launch_bounds__(64) void k_mono_bs(Buf b, const uint64_t* __restrict__ nnz_p,
+__global__ __launch_bounds__(64, 2) void k_mono_bs(Buf b, const uint64_t* __restrict__ nnz_p,
                                                 const BsOpG* __restrict__ ops, uint32_t ngroups, BsRun run,
                                                 Ctl* ctl) {
   extern __shared__ uint32_t lds_all[];
   uint32_t* L = lds_all + threadIdx.x;
   const uint64_t n = *nnz_p;
-  L[run.n_planes * 64] = ~0u;
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     atomicAdd((unsigned long long*)&ctl->updates, (unsigned long long)(n * run.n_gates));
     atomicAdd((unsigned long long*)&ctl->mono_updates, (unsigned long long)(n * run.n_gates));
@@ -48,7 +47,8 @@ __global__ __launch_bounds__(64) void k_mono_bs(Buf b, const uint64_t* __restric
 
 void launch_mono_bs(hipStream_t st, Buf b, const uint64_t* nnz, const BsOpG* ops, uint32_t ngroups, const BsRun& run,
                     Ctl* ctl, int grid) {
-  const size_t lds = (size_t)(run.n_planes + 2) * 64 * 4;
+  const size_t planes = run.has_turns && run.n_planes + 2 < 64 ? 64 : run.n_planes + 2;   // turns reuse the planes
+  const size_t lds = planes * 64 * 4;
   if (run.has_turns)
     hipLaunchKernelGGL(k_mono_bs<true>, dim3(grid), dim3(64), lds, st, b, nnz, ops, ngroups, run, ctl);
   else

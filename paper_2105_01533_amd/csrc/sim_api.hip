@@ -249,10 +249,11 @@ int validate(const sim_t* s, const sim_gate& g, size_t i) {
   return fail(SIM_E_ARG, "op " + std::to_string(i) + ": " + why);
 }
 
+// One 2048-entry tile per block: the hardware balances the tiles over the CUs.
 int bs_grid(const sim_t* s, uint64_t n) {
+  (void)s;
   const uint64_t tiles = (n + 2047) / 2048;
-  const uint64_t per_cu = std::max<uint64_t>(1, (160u * 1024u) / ((uint64_t)s->cfg.n_qubits * 256u));
-  return (int)std::max<uint64_t>(1, std::min<uint64_t>(tiles, 256u * per_cu));
+  return (int)std::max<uint64_t>(1, std::min<uint64_t>(tiles, 1u << 30));
 }
 
 // Branching op: index, count, scan, (capacity check), write, swap.
@@ -791,6 +792,13 @@ int sim_set_tuning(sim_t* s, const sim_config* t) {
   s->cfg.mono_mode = t->mono_mode;
   s->cfg.bs_min_gates = t->bs_min_gates;
   if (t->load_factor >= lf_of(&s->cfg)) s->cfg.load_factor = t->load_factor;
+  return SIM_OK;
+}
+
+int sim_device_copy(void* dst, const void* src, size_t bytes, void* stream) {
+  if (!dst || !src || bytes % 16) return fail(SIM_E_ARG, "sim_device_copy needs device pointers and a multiple of 16 bytes");
+  launch_copy16(static_cast<hipStream_t>(stream), dst, src, bytes / 16);
+  HIP_TRY(hipGetLastError());
   return SIM_OK;
 }
 

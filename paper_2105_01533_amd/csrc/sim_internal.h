@@ -167,6 +167,7 @@ void launch_mono(hipStream_t st, bool wide, Buf b, const uint64_t* nnz, const Mo
 void launch_mono_bs(hipStream_t st, Buf b, const uint64_t* nnz, const BsOpG* ops, uint32_t ngroups, const BsRun& run,
                     Ctl* ctl, int grid);
 void launch_fill(hipStream_t st, uint64_t* p, uint64_t v, uint64_t n);
+void launch_copy16(hipStream_t st, void* dst, const void* src, uint64_t n16);
 void launch_index_build(hipStream_t st, bool wide, Buf b, const uint64_t* nnz, uint64_t* table, uint64_t mask,
                         int grid, int block);
 void launch_u2_count(hipStream_t st, bool wide, Buf b, const uint64_t* nnz, const uint64_t* table, uint64_t mask,

@@ -578,3 +578,19 @@ void launch_measure_write(hipStream_t st, bool wide, Buf in, Buf out, const uint
 }
 
 }  // namespace sparsesim
+
+// ---------------------------------------------------------------------------
+// Plain streaming copy (bandwidth reference for hardware byte counters).
+namespace sparsesim {
+namespace {
+__global__ __launch_bounds__(256) void k_copy16(uint4* __restrict__ dst, const uint4* __restrict__ src, uint64_t n) {
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x)
+    dst[i] = src[i];
+}
+}  // namespace
+
+void launch_copy16(hipStream_t st, void* dst, const void* src, uint64_t n16) {
+  hipLaunchKernelGGL(k_copy16, dim3(8192), dim3(256), 0, st, static_cast<uint4*>(dst), static_cast<const uint4*>(src),
+                     n16);
+}
+}  // namespace sparsesim

@@ -86,6 +86,7 @@ def _load():
         "sim_export_state": (i32, [vp, vp, vp, u64, ctypes.POINTER(u64)]),
         "sim_device_state": (i32, [vp, vp, vp, vp, vp]),
         "sim_set_tuning": (i32, [vp, vp]),
+        "sim_device_copy": (i32, [vp, vp, sz, vp]),
         "sim_set_profiling": (i32, [vp, ctypes.c_int]),
         "sim_kernel_stats": (i32, [vp, vp, ctypes.c_int, ctypes.POINTER(ctypes.c_int)]),
         "sim_kernel_stats_reset": (i32, [vp]),
@@ -224,6 +225,10 @@ def sim_set_tuning(h, fuse_max: int = 0, block: int = 0, mono_mode: int = 0, bs_
     t = sim_config(fuse_max=fuse_max, block=block, mono_mode=mono_mode, bs_min_gates=bs_min_gates,
                    load_factor=load_factor)
     _check(_lib.sim_set_tuning(h, ctypes.byref(t)), "sim_set_tuning")
+
+
+def sim_device_copy(dst: int, src: int, nbytes: int, stream: int | None = None):
+    _check(_lib.sim_device_copy(dst, src, nbytes, stream), "sim_device_copy")
 
 
 def sim_set_profiling(h, on: bool):
