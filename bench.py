@@ -127,6 +127,8 @@ def serving_bench(sim, W, requests=128, max_log2=18, max_gates=50_000, budget_gi
     for r, (t, _) in zip(reqs, trace):
         r.arrival = t * scale
     log(f"[bench] serving: closed-loop one-at-a-time {closed['requests_per_s']:.1f} req/s -> lambda {rate:.1f}/s")
+    sat, _ = serving.run_batched(reqs, budget_gib << 30, arrivals=False)
+    log(f"[bench] serving batched, all requests at t=0: {sat}")
     base, rb = serving.run_one_at_a_time(reqs, arrivals=True, keep_results=check)
     log(f"[bench] serving one-at-a-time: {base}")
     bat, rs = serving.run_batched(reqs, budget_gib << 30, arrivals=True, keep_results=check)
@@ -145,8 +147,31 @@ def serving_bench(sim, W, requests=128, max_log2=18, max_gates=50_000, budget_gi
     return {"trace": f"{requests} Poisson requests, families c0/c1/c2, caps 2^8..2^{max_log2}, "
                      f"1e3..{max_gates} gates, lambda = 0.8 x one-at-a-time rate = {rate:.2f}/s",
             "batched": bat, "one_at_a_time": base,
+            "saturated": {"batched_requests_per_s": sat["requests_per_s"],
+                          "one_at_a_time_requests_per_s": closed["requests_per_s"],
+                          "batched_updates_per_s": sat["updates_per_s"],
+                          "one_at_a_time_updates_per_s": closed["updates_per_s"],
+                          "throughput_ratio": sat["requests_per_s"] / closed["requests_per_s"]},
             "throughput_ratio": bat["requests_per_s"] / base["requests_per_s"],
             "results_max_abs_diff": worst, "results_label_mismatches": mism}
+
+
+def measured_traffic():
+    """Per-launch HBM bytes of the fused pass from the committed counter runs
+    (profiles/mono_pass_traffic.json), or None if the kernel sources changed
+    since the counters were taken."""
+    import hashlib
+
+    p = os.path.join(ROOT, "profiles", "mono_pass_traffic.json")
+    if not os.path.exists(p):
+        return None
+    with open(p) as f:
+        doc = json.load(f)
+    h = hashlib.sha256()
+    for s in doc["sources"]:
+        with open(os.path.join(ROOT, s), "rb") as f:
+            h.update(f.read())
+    return doc["traffic_bytes_per_launch"] if h.hexdigest() == doc["sources_sha256"] else None
 
 
 def main():
@@ -213,7 +238,7 @@ def main():
     ach = mono["alg_bytes"] / (mono["total_ms"] * 1e-3) / 1e9 if mono["total_ms"] > 0 else 0.0
     roofline = {
         "kernel": "mono_pass", "dominant_kernel": dom, "bound": "hbm", "achieved": round(ach, 2),
-        "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 5), "traffic": None,
+        "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 5), "traffic": measured_traffic(),
         "launches_per_step": mono["launches"] / args.steps,
         "alg_bytes_per_launch": mono["alg_bytes"] / max(mono["launches"], 1),
         "ms_per_launch": mono["total_ms"] / max(mono["launches"], 1),

@@ -140,7 +140,7 @@ typedef struct sim_config {
  * (one 32-bit word per qubit per lane), applies permutations as plane
  * operations and accumulates phases exactly as turn fractions, multiplying
  * each amplitude once per run (results differ from sequential products by
- * rounding only).  It applies to runs whose gates have at most 4 controls and
+ * rounding only).  It applies to runs whose gates have at most 3 controls and
  * unit-modulus factors; other runs use DIRECT. */
 #define SIM_MONO_AUTO 0u
 #define SIM_MONO_DIRECT 1u
@@ -281,6 +281,9 @@ typedef struct srv_config {
   uint64_t arena_bytes;  /* per-tick upload area for fused-run ops (default 64 MiB) */
   uint32_t max_slots;    /* requests running at once, 1..4096 */
   uint32_t flags;        /* SRV_FLAG_* */
+  uint64_t tick_updates; /* cap on one request's fused-run work per tick, in gate-entry updates
+                            (nnz x gates; at least one gate); 0 = no cap.  Keeps ticks short so
+                            small requests are not held behind long runs of large ones. */
 } srv_config;
 
 typedef struct srv_stats {

@@ -213,7 +213,8 @@ int capture_tick(srv_t* s) {
 // Next segment of r, consuming skipped branching gates; sets r.seg and the
 // run [begin, begin + len) of MONO ordinals or the op index of the gate.
 SegKind next_segment(srv_t* s, Request& r, size_t* begin, size_t* len, size_t* op) {
-  const uint32_t fuse_max = r.cfg.fuse_max ? r.cfg.fuse_max : 65536u;
+  uint64_t fuse_max = r.cfg.fuse_max ? r.cfg.fuse_max : 65536u;
+  if (s->cfg.tick_updates) fuse_max = std::min<uint64_t>(fuse_max, std::max<uint64_t>(1, s->cfg.tick_updates / std::max<uint64_t>(r.nnz, 1)));
   size_t run_len = 0, run_begin = r.mono_seen;
   const size_t n = r.gates.size();
   while (r.i < n) {
@@ -235,7 +236,6 @@ SegKind next_segment(srv_t* s, Request& r, size_t* begin, size_t* len, size_t* o
     *op = r.i++;
     return g.op == SIM_OP_U2 ? SEG_U2 : SEG_MEAS;
   }
-  (void)s;
   if (run_len) {
     *begin = run_begin;
     *len = run_len;

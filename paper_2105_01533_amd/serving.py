@@ -65,9 +65,18 @@ def run_one_at_a_time(reqs, arrivals=True, keep_results=False):
     return out, results
 
 
-def run_batched(reqs, budget_bytes: int, max_slots: int = 256, arrivals=True, keep_results=False, graph=True):
-    """Open-loop replay through the continuous-batching server."""
-    srv = S.Server(budget_bytes, max_slots=max_slots, graph=graph)
+def run_batched(reqs, budget_bytes: int, max_slots: int = 256, arrivals=True, keep_results=False, graph=True,
+                tick_updates: int = 1 << 27, tuning: dict | None = None):
+    """Replay through the continuous-batching server (open loop when
+    arrivals, else every request at time 0).  tuning: optional autotuner
+    table; each request then runs with the knobs of its bucket."""
+    from . import autotune
+
+    srv = S.Server(budget_bytes, max_slots=max_slots, graph=graph, tick_updates=tick_updates)
+    if tuning:
+        for r in reqs:
+            k = autotune.lookup(tuning, r.w.n_qubits, r.w.capacity)
+            r.cfg = S.sim_config(n_qubits=r.w.n_qubits, capacity=r.w.capacity, eps=r.w.eps, **k)
     n = len(reqs)
     ids = [None] * n
     done = [0.0] * n

@@ -315,7 +315,7 @@ SRV_FLAG_NO_GRAPH = 1
 
 class srv_config(ctypes.Structure):
     _fields_ = [("budget_bytes", ctypes.c_uint64), ("arena_bytes", ctypes.c_uint64),
-                ("max_slots", ctypes.c_uint32), ("flags", ctypes.c_uint32)]
+                ("max_slots", ctypes.c_uint32), ("flags", ctypes.c_uint32), ("tick_updates", ctypes.c_uint64)]
 
 
 class srv_stats(ctypes.Structure):
@@ -439,9 +439,9 @@ class Server:
     budget_bytes borrowed from torch."""
 
     def __init__(self, budget_bytes: int, max_slots: int = 256, arena_bytes: int = 0, graph: bool = True,
-                 device: str = "cuda"):
+                 tick_updates: int = 0, device: str = "cuda"):
         self.cfg = srv_config(budget_bytes=budget_bytes, arena_bytes=arena_bytes, max_slots=max_slots,
-                              flags=0 if graph else SRV_FLAG_NO_GRAPH)
+                              flags=0 if graph else SRV_FLAG_NO_GRAPH, tick_updates=tick_updates)
         self.pool = torch.empty(budget_bytes, dtype=torch.uint8, device=device)
         self.h = srv_create(self.cfg, None, self.pool.data_ptr(), budget_bytes)
 
