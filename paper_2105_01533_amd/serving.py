@@ -30,8 +30,9 @@ def _pct(xs, p):
     return float(np.percentile(np.asarray(xs), p)) if xs else 0.0
 
 
-def _summary(name, reqs, done, t0, t_end, updates):
-    lat = [done[i] - reqs[i].arrival for i in range(len(reqs))]
+def _summary(name, reqs, done, t0, t_end, updates, arrivals=True):
+    # Without arrivals every request is submitted at time 0.
+    lat = [done[i] - (reqs[i].arrival if arrivals else 0.0) for i in range(len(reqs))]
     span = t_end - t0
     return {"system": name, "requests": len(reqs), "makespan_s": span, "requests_per_s": len(reqs) / span,
             "updates_per_s": updates / span, "p50_ms": 1e3 * _pct(lat, 50), "p99_ms": 1e3 * _pct(lat, 99),
@@ -61,7 +62,7 @@ def run_one_at_a_time(reqs, arrivals=True, keep_results=False):
         done[i] = time.perf_counter() - t0
     torch.cuda.synchronize()
     t_end = time.perf_counter()
-    out = _summary("one_at_a_time", reqs, done, 0.0, t_end - t0, updates)
+    out = _summary("one_at_a_time", reqs, done, 0.0, t_end - t0, updates, arrivals)
     return out, results
 
 
@@ -111,6 +112,6 @@ def run_batched(reqs, budget_bytes: int, max_slots: int = 256, arrivals=True, ke
     t_end = time.perf_counter() - t0
     stats = srv.stats()
     srv.close()
-    out = _summary("batched", reqs, done, 0.0, t_end, updates)
+    out = _summary("batched", reqs, done, 0.0, t_end, updates, arrivals)
     out["server"] = stats
     return out, results
