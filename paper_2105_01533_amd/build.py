@@ -15,6 +15,10 @@ FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
     "-ffp-contract=off",                      # no fused multiply-add: fixed rounding
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # Branches on wave-uniform values (the fused pass's per-group dispatch)
+    # stay plain scalar branches instead of being rewritten as exec-masked
+    # flow blocks.
+    "-mllvm", "-structurizecfg-skip-uniform-regions",
     "-Wall", "-Wno-unused-function",
 ]
 

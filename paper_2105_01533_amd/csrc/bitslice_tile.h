@@ -85,43 +85,25 @@ __device__ __forceinline__ double2 omega_pow(uint32_t k) {
   return make_double2(re, im);
 }
 
-// One op of a group: fields broadcast from the lane that loaded it.
-struct OpS {
-  uint32_t op, t, p0, p1, p2, k;
-  uint64_t tau;
-};
+// Turn fractions are read wave-uniformly through the constant address space
+// (scalar loads).
+typedef const __attribute__((address_space(4))) uint32_t* TauPtr;
 
-__device__ __forceinline__ OpS op_from_lane(const uint4& v, int src) {
-  const uint32_t x = __builtin_amdgcn_readlane(v.x, src);
-  const uint32_t y = __builtin_amdgcn_readlane(v.y, src);
-  const uint32_t z = __builtin_amdgcn_readlane(v.z, src);
-  const uint32_t w = __builtin_amdgcn_readlane(v.w, src);
-  OpS o;
-  o.op = x & 0xffu;
-  o.t = ((x >> 8) & 0xffu) * 64u;
-  o.p0 = ((x >> 16) & 0xffu) * 64u;
-  o.p1 = (x >> 24) * 64u;
-  o.p2 = (y & 0xffu) * 64u;
-  o.k = (y >> 8) & 0xffu;
-  o.tau = ((uint64_t)w << 32) | z;
-  return o;
-}
+// LDS word at byte offset off from the lane's base (L = LDS base + lane).
+__device__ __forceinline__ uint32_t& plane(char* Lb, uint32_t off) { return *reinterpret_cast<uint32_t*>(Lb + off); }
+__device__ __forceinline__ uint32_t off_t(uint32_t a) { return a & 0xff00u; }
+__device__ __forceinline__ uint32_t off_p0(uint32_t a) { return (a >> 8) & 0xff00u; }
+__device__ __forceinline__ uint32_t off_p1(uint32_t a) { return (a >> 16) & 0xff00u; }
+__device__ __forceinline__ uint32_t off_p2(uint32_t b) { return b & 0xff00u; }
 
-// Ops arrive 64 at a time, one per lane (one vector load per 64 ops, the next
-// batch in flight while the current one is used); each group of kBsGroup ops
-// is broadcast with readlane, all its plane reads are issued, then it computes
-// and writes.  The LDS holds nq label planes, an all-ones plane (index nq) that
-// unused condition slots name, and a scratch plane (nq + 1) for padding ops.
 // Apply ngroups grouped ops to the 2048-entry tile at base (lim valid
 // entries): labels to LDS planes, gates, labels back, one phase multiply per
 // amplitude.  L = LDS base + lane; the all-ones plane must be set.
 template <bool TURNS>
-__device__ __forceinline__ void bs_tile(const Buf& b, uint64_t base, uint32_t lim, const BsOpG* __restrict__ ops,
+__device__ __forceinline__ void bs_tile(const Buf& b, uint64_t base, uint32_t lim, const BsGroup* __restrict__ groups,
                                         uint32_t ngroups, const BsRun& run, uint32_t* L) {
   const int lane = threadIdx.x;
   const int nq = (int)run.n_planes;
-  const uint4* opv = reinterpret_cast<const uint4*>(ops);
-  const uint32_t nops = ngroups * kBsGroup;
     const uint32_t rw = run.words_read | run.words_write;
     if (rw & 3u) load_pair(b.key_lo + base + lane, lim, L, 0, nq);
     __builtin_amdgcn_sched_barrier(0);
@@ -132,42 +114,125 @@ __device__ __forceinline__ void bs_tile(const Buf& b, uint64_t base, uint32_t li
     uint64_t turns[TURNS ? 32 : 1];
 #pragma unroll
     for (int j = 0; j < (TURNS ? 32 : 1); ++j) turns[j] = 0;
-    uint4 cur = lane < (int)nops ? opv[lane] : make_uint4(0, 0, 0, 0);
-    for (uint32_t b0 = 0; b0 < nops; b0 += 64) {
-      const uint4 nxt = b0 + 64 + lane < nops ? opv[b0 + 64 + lane] : make_uint4(0, 0, 0, 0);
-      const uint32_t gend = (nops - b0 < 64 ? nops - b0 : 64);
-      for (uint32_t g = 0; g < gend; g += kBsGroup) {
-        OpS o[kBsGroup];
-        uint32_t cond[kBsGroup], tv[kBsGroup];
+    char* Lb = reinterpret_cast<char*>(L);
+    // Groups arrive 64 at a time, one per lane: the a words (and the b words)
+    // of a group in one 16-byte vector load, the next batch in flight while
+    // this one is used, broadcast with readlane at the group's lane.  A TURN
+    // group's turn fractions are read with scalar loads.
+    const uint4* gv = reinterpret_cast<const uint4*>(groups);
+    const TauPtr taus = (TauPtr)groups;
+    uint4 ca = lane < (int)ngroups ? gv[4 * lane] : make_uint4(0, 0, 0, 0);
+    uint4 cb = lane < (int)ngroups ? gv[4 * lane + 1] : make_uint4(0, 0, 0, 0);
+    // Wait for the first batch here, so that the loops below see it ready.
+    asm volatile("" ::"v"(ca.x), "v"(ca.y), "v"(ca.z), "v"(ca.w), "v"(cb.x), "v"(cb.y), "v"(cb.z), "v"(cb.w));
+    for (uint32_t g0 = 0; g0 < ngroups; g0 += 64) {
+      const bool more = g0 + 64 + lane < ngroups;
+      const uint4 na = more ? gv[4 * (g0 + 64 + lane)] : make_uint4(0, 0, 0, 0);
+      const uint4 nb = more ? gv[4 * (g0 + 64 + lane) + 1] : make_uint4(0, 0, 0, 0);
+      const uint32_t gend = (ngroups - g0 < 64 ? ngroups - g0 : 64);
+      uint32_t g = 0;
+      while (g < gend) {
+        // Groups up to the next TURN group (the turn accumulators stay
+        // untouched in this loop).
+        for (; g < gend; ++g) {
+          uint32_t a[kBsGroup];
+          a[0] = __builtin_amdgcn_readlane(ca.x, g);
+          a[1] = __builtin_amdgcn_readlane(ca.y, g);
+          a[2] = __builtin_amdgcn_readlane(ca.z, g);
+          a[3] = __builtin_amdgcn_readlane(ca.w, g);
+          const uint32_t shape = bs_shape(a[0]);
+          if (shape == kShapeTurn) break;
+          if (shape == kShapeX) {
+            uint32_t tv[kBsGroup];
 #pragma unroll
-        for (int u = 0; u < kBsGroup; ++u) o[u] = op_from_lane(cur, g + u);
+            for (int u = 0; u < kBsGroup; ++u) tv[u] = plane(Lb, off_t(a[u]));
 #pragma unroll
-        for (int u = 0; u < kBsGroup; ++u) {
-          cond[u] = L[o[u].p0] & L[o[u].p1] & L[o[u].p2];
-          tv[u] = L[o[u].t];
+            for (int u = 0; u < kBsGroup; ++u) plane(Lb, off_t(a[u])) = ~tv[u];
+          } else if (shape == kShapeCX) {
+            uint32_t tv[kBsGroup], c0[kBsGroup];
+#pragma unroll
+            for (int u = 0; u < kBsGroup; ++u) {
+              c0[u] = plane(Lb, off_p0(a[u]));
+              tv[u] = plane(Lb, off_t(a[u]));
+            }
+#pragma unroll
+            for (int u = 0; u < kBsGroup; ++u) plane(Lb, off_t(a[u])) = tv[u] ^ c0[u];
+          } else if (shape == kShapeCCX) {
+            uint32_t tv[kBsGroup], c0[kBsGroup], c1[kBsGroup];
+#pragma unroll
+            for (int u = 0; u < kBsGroup; ++u) {
+              c0[u] = plane(Lb, off_p0(a[u]));
+              c1[u] = plane(Lb, off_p1(a[u]));
+              tv[u] = plane(Lb, off_t(a[u]));
+            }
+#pragma unroll
+            for (int u = 0; u < kBsGroup; ++u) plane(Lb, off_t(a[u])) = tv[u] ^ (c0[u] & c1[u]);
+          } else {
+            // General group: every op writes its plane t; a flip xors the
+            // condition in, an eighth-turn phase op's t is a fourth condition
+            // plane (its target bit, or the all-ones plane) and is written
+            // back unchanged.
+            uint32_t bw[kBsGroup];
+            bw[0] = __builtin_amdgcn_readlane(cb.x, g);
+            bw[1] = __builtin_amdgcn_readlane(cb.y, g);
+            bw[2] = __builtin_amdgcn_readlane(cb.z, g);
+            bw[3] = __builtin_amdgcn_readlane(cb.w, g);
+            uint32_t c0[kBsGroup], c1[kBsGroup], c2[kBsGroup], tv[kBsGroup];
+#pragma unroll
+            for (int u = 0; u < kBsGroup; ++u) {
+              c0[u] = plane(Lb, off_p0(a[u]));
+              c1[u] = plane(Lb, off_p1(a[u]));
+              c2[u] = plane(Lb, off_p2(bw[u]));
+              tv[u] = plane(Lb, off_t(a[u]));
+            }
+            __builtin_amdgcn_sched_barrier(0);
+            uint32_t cond[kBsGroup];
+#pragma unroll
+            for (int u = 0; u < kBsGroup; ++u) {
+              cond[u] = c0[u] & c1[u] & c2[u];
+              const uint32_t fm = (a[u] & 3u) == kBsFlip ? ~0u : 0u;
+              plane(Lb, off_t(a[u])) = tv[u] ^ (cond[u] & fm);
+            }
+            if (shape == kShapePhase) {
+#pragma unroll
+              for (int u = 0; u < kBsGroup; ++u)
+                if ((a[u] & 3u) == kBsOmega) omega_add(e0, e1, e2, cond[u] & tv[u], (a[u] >> 2) & 7u);
+            }
+          }
         }
-        // Every op writes its plane t: a flip xors the condition in; a phase
-        // op's t is a fourth condition plane (its target bit, or the all-ones
-        // plane) and is written back unchanged.
+        if (g >= gend) break;
+        // A TURN group: four turn ops (read-only on the planes).
+        if (TURNS) {
+          uint32_t a[kBsGroup], bw[kBsGroup];
+          a[0] = __builtin_amdgcn_readlane(ca.x, g);
+          a[1] = __builtin_amdgcn_readlane(ca.y, g);
+          a[2] = __builtin_amdgcn_readlane(ca.z, g);
+          a[3] = __builtin_amdgcn_readlane(ca.w, g);
+          bw[0] = __builtin_amdgcn_readlane(cb.x, g);
+          bw[1] = __builtin_amdgcn_readlane(cb.y, g);
+          bw[2] = __builtin_amdgcn_readlane(cb.z, g);
+          bw[3] = __builtin_amdgcn_readlane(cb.w, g);
+          uint32_t x[kBsGroup];
 #pragma unroll
-        for (int u = 0; u < kBsGroup; ++u) L[o[u].t] = tv[u] ^ (o[u].op == kBsFlip ? cond[u] : 0u);
+          for (int u = 0; u < kBsGroup; ++u)
+            x[u] = plane(Lb, off_p0(a[u])) & plane(Lb, off_p1(a[u])) & plane(Lb, off_p2(bw[u])) &
+                   plane(Lb, off_t(a[u]));
+          const uint32_t tg = 16u * (g0 + g) + 8u;   // the group's turn fractions, in 32-bit words
 #pragma unroll
-        for (int u = 0; u < kBsGroup; ++u) {
-          const uint32_t x = cond[u] & tv[u];
-          if (o[u].op == kBsFlip) {
-          } else if (o[u].op == kBsOmega) {
-            omega_add(e0, e1, e2, x, o[u].k);
-          } else if (TURNS) {
-            const uint32_t tlo = (uint32_t)o[u].tau, thi = (uint32_t)(o[u].tau >> 32);
+          for (int u = 0; u < kBsGroup; ++u) {
+            const uint32_t tlo = taus[tg + 2 * u], thi = taus[tg + 2 * u + 1];
+            if ((tlo | thi) == 0u) continue;   // padding
 #pragma unroll
             for (int j = 0; j < 32; ++j) {
-              const uint32_t m = (uint32_t)(-(int32_t)((x >> j) & 1u));
+              const uint32_t m = (uint32_t)(-(int32_t)((x[u] >> j) & 1u));
               turns[j] += ((uint64_t)(thi & m) << 32) | (tlo & m);
             }
           }
         }
+        ++g;
       }
-      cur = nxt;
+      ca = na;
+      cb = nb;
     }
     // Labels back to memory (only words some gate flips).
     __builtin_amdgcn_sched_barrier(0);

@@ -25,7 +25,7 @@ namespace {
 
 template <bool TURNS>
 __global__ __launch_bounds__(64, 2) void k_mono_bs(Buf b, const uint64_t* __restrict__ nnz_p,
-                                                const BsOpG* __restrict__ ops, uint32_t ngroups, BsRun run,
+                                                const BsGroup* __restrict__ groups, uint32_t ngroups, BsRun run,
                                                 Ctl* ctl) {
   extern __shared__ uint32_t lds_all[];
   uint32_t* L = lds_all + threadIdx.x;
@@ -39,20 +39,20 @@ __global__ __launch_bounds__(64, 2) void k_mono_bs(Buf b, const uint64_t* __rest
   for (uint64_t tile = blockIdx.x; tile < tiles; tile += gridDim.x) {
     const uint64_t base = tile * 2048;
     const uint32_t lim = (uint32_t)(n - base < 2048 ? n - base : 2048);
-    bs::bs_tile<TURNS>(b, base, lim, ops, ngroups, run, L);
+    bs::bs_tile<TURNS>(b, base, lim, groups, ngroups, run, L);
   }
 }
 
 }  // namespace
 
-void launch_mono_bs(hipStream_t st, Buf b, const uint64_t* nnz, const BsOpG* ops, uint32_t ngroups, const BsRun& run,
+void launch_mono_bs(hipStream_t st, Buf b, const uint64_t* nnz, const BsGroup* groups, uint32_t ngroups, const BsRun& run,
                     Ctl* ctl, int grid) {
   const size_t planes = run.has_turns && run.n_planes + 2 < 64 ? 64 : run.n_planes + 2;   // turns reuse the planes
   const size_t lds = planes * 64 * 4;
   if (run.has_turns)
-    hipLaunchKernelGGL(k_mono_bs<true>, dim3(grid), dim3(64), lds, st, b, nnz, ops, ngroups, run, ctl);
+    hipLaunchKernelGGL(k_mono_bs<true>, dim3(grid), dim3(64), lds, st, b, nnz, groups, ngroups, run, ctl);
   else
-    hipLaunchKernelGGL(k_mono_bs<false>, dim3(grid), dim3(64), lds, st, b, nnz, ops, ngroups, run, ctl);
+    hipLaunchKernelGGL(k_mono_bs<false>, dim3(grid), dim3(64), lds, st, b, nnz, groups, ngroups, run, ctl);
 }
 
 }  // namespace sparsesim

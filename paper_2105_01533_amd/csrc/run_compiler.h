@@ -42,7 +42,7 @@ struct RunCompiler {
   // the run parameters (bytes_per_entry left 0).
   bool run_params(size_t begin, size_t len, uint32_t mono_mode, uint32_t min_gates, BsRun* br) const;
   // Kernel ops of MONO ops [begin, begin+len), in groups of kBsGroup, appended to out.
-  void group(size_t begin, size_t len, std::vector<BsOpG>& out) const;
+  void group(size_t begin, size_t len, std::vector<BsGroup>& out) const;
 };
 
 }  // namespace sparsesim

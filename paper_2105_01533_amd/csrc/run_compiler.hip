@@ -166,13 +166,18 @@ bool RunCompiler::run_params(size_t begin, size_t len, uint32_t mono_mode, uint3
   return true;
 }
 
-// Pack the ops into groups of kBsGroup consecutive ops that touch no plane
-// another member of the group writes (so the kernel may read all of a group's
-// planes before any write), padding groups with no-op flips of the scratch
-// plane.  Order is kept across groups; within a group the ops are
-// independent, and phase accumulations commute exactly.
-void RunCompiler::group(size_t begin, size_t len, std::vector<BsOpG>& out) const {
-  const uint8_t ones = (uint8_t)n_qubits, scratch = (uint8_t)(n_qubits + 1);
+// Pack the ops into groups of kBsGroup ops that touch no plane another member
+// of the group writes (so the kernel may read all of a group's planes before
+// any write), padding groups with no-op flips of the scratch plane.
+//
+// Ops are list-scheduled: an op may be taken ahead of earlier ops still
+// waiting when it commutes with each of them, i.e. neither writes a plane the
+// other reads or writes (phase accumulations commute exactly, so phase ops
+// only conflict through the planes they read).  Among the ops of a window that
+// may go next, groups whose four ops are flips with the same number of
+// controls are preferred, because the kernel reads only those planes for them.
+void RunCompiler::group(size_t begin, size_t len, std::vector<BsGroup>& out) const {
+  const uint32_t ones = n_qubits, scratch = n_qubits + 1;
   struct Mask {
     uint64_t lo = 0, hi = 0;
     void set(uint32_t q) { (q < 64 ? lo : hi) |= 1ull << (q & 63); }
@@ -182,43 +187,102 @@ void RunCompiler::group(size_t begin, size_t len, std::vector<BsOpG>& out) const
       hi |= o.hi;
     }
   };
-  Mask gr, gw;
-  int in_group = 0;
-  auto close = [&]() {
-    for (; in_group && in_group < kBsGroup; ++in_group) {
-      BsOpG pad{};
-      pad.op = kBsFlip;
-      pad.t = scratch;
-      pad.p0 = pad.p1 = pad.p2 = ones;
-      out.push_back(pad);
-    }
-    in_group = 0;
-    gr = Mask{};
-    gw = Mask{};
-  };
-  for (uint32_t i = start[begin]; i < start[begin + len]; ++i) {
-    const BsOp& o = ops[i];
+  struct Item {
     Mask r, w;
-    for (int c = 0; c < o.nctrl; ++c) r.set(o.ctrl[c]);
-    if (o.cmode || o.op == kBsFlip) r.set(o.target);
-    if (o.op == kBsFlip) w.set(o.target);
-    if (in_group == kBsGroup || w.meets(gr) || w.meets(gw) || r.meets(gw)) close();
-    BsOpG g{};
-    g.op = o.op;
-    g.t = (o.op == kBsFlip || o.cmode) ? o.target : ones;   // flip target, or a phase op's target-bit condition
-    uint8_t slot[3] = {ones, ones, ones};
+    uint32_t shape;   // kShapeX/CX/CCX for flips with 0..2 controls, else kShapeGeneric
+    bool phase;
+    uint32_t a, b;
+    uint64_t tau;
+  };
+  const uint32_t i0 = start[begin], i1 = start[begin + len];
+  const uint32_t n = i1 - i0;
+  std::vector<Item> items(n);
+  for (uint32_t i = 0; i < n; ++i) {
+    const BsOp& o = ops[i0 + i];
+    Item& it = items[i];
+    for (int c = 0; c < o.nctrl; ++c) it.r.set(o.ctrl[c]);
+    if (o.cmode || o.op == kBsFlip) it.r.set(o.target);
+    if (o.op == kBsFlip) it.w.set(o.target);
+    it.phase = o.op != kBsFlip;
+    it.shape = o.op == kBsTurn ? kShapeTurn : o.op == kBsFlip && o.nctrl <= 2 ? kShapeX + o.nctrl : kShapeGeneric;
+    uint32_t slot[3] = {ones, ones, ones};
     for (int c = 0; c < o.nctrl; ++c) slot[c] = o.ctrl[c];
-    g.p0 = slot[0];
-    g.p1 = slot[1];
-    g.p2 = slot[2];
-    g.k = o.op == kBsOmega ? (uint8_t)o.arg : 0;
-    g.tau = o.op == kBsTurn ? o.arg : 0;
-    out.push_back(g);
-    gr.add(r);
-    gw.add(w);
-    ++in_group;
+    const uint32_t t = (o.op == kBsFlip || o.cmode) ? o.target : ones;   // flip target, or a phase op's target-bit condition
+    const uint32_t k = o.op == kBsOmega ? (uint32_t)(o.arg & 7u) : 0u;
+    it.a = bs_pack_a(o.op, k, t, slot[0], slot[1]);
+    it.b = bs_pack_b(slot[2]);
+    it.tau = o.op == kBsTurn ? o.arg : 0;
   }
-  close();
+  // Relative cost of one op slot in a group of each shape (LDS accesses plus
+  // vector instructions in the kernel's group bodies).
+  auto slot_cost = [](uint32_t shape) { return shape == kShapeX ? 4 : shape == kShapeCX ? 6 : shape == kShapeCCX ? 8 : 12; };
+  constexpr uint32_t kWindow = 32;
+  std::vector<char> done(n, 0);
+  uint32_t head = 0;
+  std::vector<uint32_t> pick, best;
+  // Select up to kBsGroup ops from the window starting at head; `want` is a
+  // shape all picks must have, or kShapeGeneric for any but turn ops (which
+  // only go in TURN groups).
+  auto select = [&](uint32_t want, std::vector<uint32_t>& sel) {
+    sel.clear();
+    Mask gr, gw, br, bw;   // group reads / writes, reads / writes of ops passed over
+    uint32_t seen = 0;
+    for (uint32_t j = head; j < n && seen < kWindow && sel.size() < (size_t)kBsGroup; ++j) {
+      if (done[j]) continue;
+      ++seen;
+      const Item& it = items[j];
+      const bool commutes = !it.w.meets(br) && !it.w.meets(bw) && !it.r.meets(bw);
+      const bool fits = !it.w.meets(gr) && !it.w.meets(gw) && !it.r.meets(gw);
+      const bool shape_ok = want == kShapeGeneric ? it.shape != kShapeTurn : it.shape == want;
+      if (commutes && fits && shape_ok) {
+        sel.push_back(j);
+        gr.add(it.r);
+        gw.add(it.w);
+      } else {
+        br.add(it.r);
+        bw.add(it.w);
+      }
+    }
+  };
+  while (head < n) {
+    const uint32_t hs = items[head].shape;
+    select(hs, pick);
+    uint32_t shape = hs;
+    if (hs != kShapeGeneric && hs != kShapeTurn && pick.size() < (size_t)kBsGroup) {
+      // A mixed group may carry more ops than a padded uniform one.
+      select(kShapeGeneric, best);
+      uint32_t s0 = items[best[0]].shape;
+      for (uint32_t j : best)
+        if (items[j].shape != s0) s0 = kShapeGeneric;
+      if ((double)kBsGroup * slot_cost(s0) / best.size() < (double)kBsGroup * slot_cost(hs) / pick.size()) {
+        pick.swap(best);
+        shape = s0;
+      }
+    }
+    bool phase = false;
+    BsGroup grp{};
+    size_t u = 0;
+    for (uint32_t j : pick) {
+      done[j] = 1;
+      phase |= items[j].phase;
+      grp.a[u] = items[j].a;
+      grp.b[u] = items[j].b;
+      grp.tau[u] = items[j].tau;
+      ++u;
+    }
+    for (; u < (size_t)kBsGroup; ++u) {
+      if (shape == kShapeTurn) {
+        grp.a[u] = bs_pack_a(kBsTurn, 0, ones, ones, ones);     // adds 0 turns
+      } else {
+        grp.a[u] = bs_pack_a(kBsFlip, 0, scratch, ones, ones);  // scratch ^= ones, or scratch = ~scratch
+      }
+      grp.b[u] = bs_pack_b(ones);
+      grp.tau[u] = 0;
+    }
+    grp.a[0] |= (shape == kShapeGeneric && phase ? kShapePhase : shape) << 5;
+    out.push_back(grp);
+    while (head < n && done[head]) ++head;
+  }
 }
 
 }  // namespace sparsesim

@@ -426,7 +426,7 @@ int srv_tick(srv_t* s, uint32_t* running, uint32_t* queued) {
   size_t arena_used = 0;
   std::vector<Request*> mono, u2, meas;
   std::vector<BItem> mono_items, u2_items, meas_items;
-  std::vector<BsOpG> grp;
+  std::vector<BsGroup> grp;
   std::vector<Request*> done_now;
   for (Request* r : s->running) {
     size_t b = 0, len = 0, op = 0;
@@ -460,7 +460,7 @@ int srv_tick(srv_t* s, uint32_t* running, uint32_t* queued) {
         if (bsl) {
           grp.clear();
           r->rc.group(b, keep, grp);
-          bytes = grp.size() * sizeof(BsOpG);
+          bytes = grp.size() * sizeof(BsGroup);
         } else {
           bytes = keep * sizeof(MonoDesc);
         }
@@ -481,8 +481,8 @@ int srv_tick(srv_t* s, uint32_t* running, uint32_t* queued) {
       if (len == 0) continue;
       if (bsl) {
         std::memcpy(arena + arena_used, grp.data(), bytes);
-        it.gops = reinterpret_cast<const BsOpG*>(s->d_tick + s->arena_off + arena_used);
-        it.ngroups = (uint32_t)(grp.size() / kBsGroup);
+        it.gops = reinterpret_cast<const BsGroup*>(s->d_tick + s->arena_off + arena_used);
+        it.ngroups = (uint32_t)grp.size();
         it.run = br;
         s->stats.bitslice_runs++;
       } else {

@@ -158,8 +158,8 @@ struct sim_t {
   uint64_t* h_pinned;          // [0] nnz readback, [1..] scratch
   Ctl* h_ctl;                  // pinned mirror of ctl
   DevVec<MonoDesc> descs;
-  DevVec<BsOpG> grp_ops;       // grouped bit-sliced ops of the current call
-  std::vector<BsOpG> h_grp;
+  DevVec<BsGroup> grp_ops;     // grouped bit-sliced ops of the current call
+  std::vector<BsGroup> h_grp;
   RunCompiler rc;              // MONO descriptors and bytecode of the current call
   DevVec<MeasRec> recs;
   DevVec<int32_t> outcomes;
@@ -572,13 +572,13 @@ int sim_apply_gates(sim_t* s, const sim_gate* gates, size_t n, int32_t* outcomes
   if (n_mono)
     HIP_TRY(hipMemcpyAsync(s->descs.p, s->rc.descs.data(), n_mono * sizeof(MonoDesc), hipMemcpyHostToDevice,
                            s->stream));
-  // Grouped kernel ops of the bit-sliced runs, appended run by run; padding
-  // at most triples the count, so reserving up front keeps the host copies
-  // of in-flight uploads in place.
+  // Grouped kernel ops of the bit-sliced runs, appended run by run; every
+  // group holds at least one op, so reserving one group per op up front keeps
+  // the host copies of in-flight uploads in place.
   s->h_grp.clear();
   if (bs_allowed) {
-    s->h_grp.reserve(kBsGroup * s->rc.ops.size() + kBsGroup);
-    HIP_TRY(s->grp_ops.reserve(kBsGroup * s->rc.ops.size() + kBsGroup));
+    s->h_grp.reserve(s->rc.ops.size() + 1);
+    HIP_TRY(s->grp_ops.reserve(s->rc.ops.size() + 1));
   }
 
   int result = SIM_OK;
@@ -600,10 +600,10 @@ int sim_apply_gates(sim_t* s, const sim_gate* gates, size_t n, int32_t* outcomes
       br.bytes_per_entry = run_bpe;
       const size_t g0 = s->h_grp.size();
       s->rc.group(run_begin, run_len, s->h_grp);
-      const size_t ng = (s->h_grp.size() - g0) / kBsGroup;
+      const size_t ng = s->h_grp.size() - g0;
       if (ng)
-        HIP_TRY(hipMemcpyAsync(s->grp_ops.p + g0, s->h_grp.data() + g0, (s->h_grp.size() - g0) * sizeof(BsOpG),
-                               hipMemcpyHostToDevice, s->stream));
+        HIP_TRY(hipMemcpyAsync(s->grp_ops.p + g0, s->h_grp.data() + g0, ng * sizeof(BsGroup), hipMemcpyHostToDevice,
+                               s->stream));
       KTimer t_(s, KC_MONO);
       launch_mono_bs(s->stream, s->buf[s->cur], d_nnz(s, s->cur), s->grp_ops.p + g0, (uint32_t)ng, br, s->ctl,
                      bs_grid(s, ub));

@@ -46,17 +46,34 @@ struct BsOp {
 };
 static_assert(sizeof(BsOp) == 16, "BsOp is 16 bytes");
 
-// Kernel form of a BsOp: the condition is the AND of three plane slots
-// (p0, p1, p2; unused slots name the all-ones plane), FLIP xors it into plane
-// t.  Ops are issued in groups of kBsGroup whose members touch no plane another
-// member writes, so a group's plane reads can all be in flight at once.
+// Kernel form of BsOps: groups of kBsGroup ops whose members touch no plane
+// another member writes, so a group's plane reads can all be in flight at
+// once.  In each op the condition is the AND of three plane slots (p0, p1, p2;
+// unused slots name the all-ones plane); a flip xors it into plane t.
+//
+// Group-major, 64 bytes per group: the a words of the four ops, their b words,
+// then their turn fractions.  Packed so that a plane's LDS byte offset
+// (plane * 256) is a mask or a shift-and-mask of a word:
+//   a: bits 0-1 op, 2-4 k (omega eighths), 5-7 group shape (first op only),
+//      8-15 t, 16-23 p0, 24-31 p1
+//   b: bits 8-15 p2
+// The shape tells the kernel that all four ops are flips with the same number
+// of controls (X, CX, CCX: only those planes are read, all named by a), that
+// they are all turn ops (TURN; padding ops have tau = 0), or that the group is
+// general (three condition slots; flips and eighth-turn phase ops), PHASE when
+// it holds a phase op.
 constexpr int kBsGroup = 4;
-struct BsOpG {
-  uint8_t op, t, p0, p1;
-  uint8_t p2, k, pad0, pad1;
-  uint64_t tau;
+constexpr uint32_t kShapeGeneric = 0, kShapeX = 1, kShapeCX = 2, kShapeCCX = 3, kShapeTurn = 4, kShapePhase = 5;
+struct BsGroup {
+  uint32_t a[kBsGroup], b[kBsGroup];
+  uint64_t tau[kBsGroup];
 };
-static_assert(sizeof(BsOpG) == 16, "BsOpG is 16 bytes");
+static_assert(sizeof(BsGroup) == 64, "BsGroup is 64 bytes");
+__host__ __device__ constexpr uint32_t bs_pack_a(uint32_t op, uint32_t k, uint32_t t, uint32_t p0, uint32_t p1) {
+  return op | (k << 2) | (t << 8) | (p0 << 16) | (p1 << 24);
+}
+__host__ __device__ constexpr uint32_t bs_pack_b(uint32_t p2) { return p2 << 8; }
+__host__ __device__ constexpr uint32_t bs_shape(uint32_t a0) { return (a0 >> 5) & 7u; }
 
 // Run-level parameters of a bit-sliced pass.
 struct BsRun {
@@ -131,7 +148,7 @@ struct BItem {
   uint64_t nnz;                // entries at input (exact)
   uint64_t cap;                // capacity of the state
   // fused run
-  const BsOpG* gops;           // bit-sliced groups (gops != null) ...
+  const BsGroup* gops;         // bit-sliced groups (gops != null) ...
   uint32_t ngroups, n_dops;
   const MonoDesc* dops;        // ... or per-entry descriptors
   BsRun run;
@@ -164,7 +181,7 @@ void launch_batch_tick(hipStream_t st, const BTick* hdr, const BItem* items, con
 void launch_set_basis(hipStream_t st, Buf b, uint64_t* nnz, uint64_t lo, uint64_t hi);
 void launch_mono(hipStream_t st, bool wide, Buf b, const uint64_t* nnz, const MonoDesc* g, uint32_t ng,
                  uint32_t run_flags, uint32_t bytes_per_entry, Ctl* ctl, int grid, int block);
-void launch_mono_bs(hipStream_t st, Buf b, const uint64_t* nnz, const BsOpG* ops, uint32_t ngroups, const BsRun& run,
+void launch_mono_bs(hipStream_t st, Buf b, const uint64_t* nnz, const BsGroup* groups, uint32_t ngroups, const BsRun& run,
                     Ctl* ctl, int grid);
 void launch_fill(hipStream_t st, uint64_t* p, uint64_t v, uint64_t n);
 void launch_copy16(hipStream_t st, void* dst, const void* src, uint64_t n16);
