@@ -218,12 +218,16 @@ int sim_export_state(sim_t* s, sim_key* keys, sim_c64* amps, uint64_t cap, uint6
 int sim_device_state(sim_t* s, uint64_t** key_lo, uint64_t** key_hi, double** amp, uint64_t** d_nnz);
 
 /* Per-kernel-class counters, cumulative since creation or the last reset.
- * With profiling on (sim_set_profiling), every launch is bracketed by HIP
- * events on the handle's stream and total_ms sums their elapsed times;
- * otherwise total_ms is 0.  alg_bytes is the algorithmic HBM traffic of the
+ * With profiling on for a class (sim_set_profiling), every launch of it is
+ * bracketed by HIP events on the handle's stream and total_ms sums their
+ * elapsed times; otherwise total_ms is 0.  alg_bytes is the algorithmic HBM traffic of the
  * fused phase/permutation pass (label read, label write if any gate flips,
  * amplitude read+write if any gate has a phase), 0 for the other classes;
- * updates counts gate-entry updates done by the class. */
+ * updates counts gate-entry updates done by the class.  Three host classes
+ * follow the kernel classes, always measured on the host's wall clock:
+ * host_prepare (validation and op compilation at the start of a call),
+ * host_group (grouping of bit-sliced runs) and host_sync (time blocked in
+ * stream synchronisations); their launches count calls. */
 typedef struct sim_kernel_stat {
   char name[32];
   uint64_t launches;
@@ -245,8 +249,15 @@ int sim_set_tuning(sim_t* s, const sim_config* t);
  * that moves a known number of bytes.  SIM_E_ARG for a bad size. */
 int sim_device_copy(void* dst, const void* src, size_t bytes, void* stream);
 
+/* Profiling mode: SIM_PROFILE_OFF, SIM_PROFILE_ALL (every kernel launch is
+ * bracketed by events) or SIM_PROFILE_MONO (only the fused phase/permutation
+ * passes, for timing them with fewer events in flight).  Synchronises the
+ * handle's stream.  SIM_E_ARG for another value. */
+#define SIM_PROFILE_OFF 0
+#define SIM_PROFILE_ALL 1
+#define SIM_PROFILE_MONO 2
 int sim_set_profiling(sim_t* s, int on);
-/* Writes up to cap records; *n receives the number of kernel classes. */
+/* Writes up to cap records; *n receives the number of classes. */
 int sim_kernel_stats(sim_t* s, sim_kernel_stat* out, int cap, int* n);
 int sim_kernel_stats_reset(sim_t* s);
 

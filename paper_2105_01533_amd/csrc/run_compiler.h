@@ -43,6 +43,8 @@ struct RunCompiler {
   bool run_params(size_t begin, size_t len, uint32_t mono_mode, uint32_t min_gates, BsRun* br) const;
   // Kernel ops of MONO ops [begin, begin+len), in groups of kBsGroup, appended to out.
   void group(size_t begin, size_t len, std::vector<BsGroup>& out) const;
+  // Groups of the bit-sliced ops [i0, i1), appended to out.
+  void group_range(uint32_t i0, uint32_t i1, std::vector<BsGroup>& out) const;
 };
 
 }  // namespace sparsesim

@@ -1,8 +1,10 @@
 // Host-side compilation of phase/permutation runs (see run_compiler.h).
 #include "run_compiler.h"
 
+#include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <thread>
 
 namespace sparsesim {
 
@@ -65,80 +67,122 @@ uint64_t turn_of(const double2& m) {
 
 uint8_t word_bit(uint32_t q) { return (uint8_t)(1u << (q >> 5)); }
 
+// Run f(begin, end, part) over up to kHostThreads contiguous parts of [0, n),
+// each at least min_part long, on host threads (part 0 on the caller's).
+constexpr unsigned kHostThreads = 8;
+template <class F>
+void parallel_parts(size_t n, size_t min_part, F&& f) {
+  const unsigned hw = std::max(1u, std::thread::hardware_concurrency());
+  const size_t parts = std::min<size_t>(std::min(kHostThreads, hw), n / std::max<size_t>(min_part, 1));
+  if (parts <= 1) {
+    f(0, n, 0);
+    return;
+  }
+  std::vector<std::thread> th;
+  th.reserve(parts - 1);
+  for (size_t p = 1; p < parts; ++p) th.emplace_back([&, p]() { f(n * p / parts, n * (p + 1) / parts, p); });
+  f(0, n / parts, 0);
+  for (auto& t : th) t.join();
+}
+
+}  // namespace
+
+namespace {
+
+// Bit-sliced ops of one MONO op, appended to out; inf describes them.
+void compile_one(const MonoDesc& d, BsGateInfo& inf, std::vector<BsOp>& out) {
+  inf.eligible = true;
+  BsOp base{};
+  base.target = (uint8_t)d.target;
+  uint8_t rd = 0;
+  for (int w = 0; w < 2; ++w) {
+    uint64_t m = w ? d.ctrl_hi : d.ctrl_lo;
+    while (m) {
+      const uint32_t q = (uint32_t)__builtin_ctzll(m) + 64u * w;
+      m &= m - 1;
+      if (base.nctrl == kBsMaxCtrl) {
+        inf.eligible = false;
+        break;
+      }
+      base.ctrl[base.nctrl++] = (uint8_t)q;
+      rd |= word_bit(q);
+    }
+  }
+  if (!inf.eligible) return;
+  auto emit = [&](uint8_t op, uint8_t cmode, uint64_t arg) {
+    BsOp o = base;
+    o.op = op;
+    o.cmode = cmode;
+    o.arg = arg;
+    out.push_back(o);
+    if (cmode) rd |= word_bit(d.target);
+  };
+  if (d.flags & kHasPhase) {
+    const int k0 = omega_index(d.m0), k1 = omega_index(d.m1);
+    if (k0 >= 0 && k1 >= 0) {
+      if (k0) {
+        if (base.nctrl == 0) inf.g_omega = (uint8_t)((inf.g_omega + k0) & 7);
+        else emit(kBsOmega, 0, (uint64_t)k0);
+      }
+      const uint32_t dk = (uint32_t)(k1 - k0) & 7u;
+      if (dk) emit(kBsOmega, 1, dk);
+    } else if (unit_modulus(d.m0) && unit_modulus(d.m1)) {
+      const uint64_t t0 = turn_of(d.m0), t1 = turn_of(d.m1);
+      if (t0) {
+        if (base.nctrl == 0) {
+          inf.g_turn += t0;
+        } else {
+          emit(kBsTurn, 0, t0);
+          inf.turns = true;
+        }
+      }
+      if (t1 - t0) {
+        emit(kBsTurn, 1, t1 - t0);
+        inf.turns = true;
+      }
+    } else {
+      inf.eligible = false;
+      return;
+    }
+    inf.phase = true;
+  }
+  if (d.flags & kFlip) {
+    emit(kBsFlip, 0, 0);
+    inf.words_write = word_bit(d.target);
+  }
+  inf.words_read = rd;
+}
+
 }  // namespace
 
 // Per op: a factor m0 on labels with the target bit 0 and m1 with it 1 equals
 // m0 everywhere (under the controls) times m1/m0 where the target bit is 1.
+// Large lists are compiled in parts on host threads.
 void RunCompiler::compile(uint32_t nq) {
   n_qubits = nq;
   const size_t n_mono = descs.size();
   ops.clear();
   start.assign(n_mono + 1, 0);
   info.assign(n_mono, BsGateInfo{});
-  for (size_t k = 0; k < n_mono; ++k) {
-    const MonoDesc& d = descs[k];
-    BsGateInfo& inf = info[k];
-    start[k] = (uint32_t)ops.size();
-    inf.eligible = true;
-    BsOp base{};
-    base.target = (uint8_t)d.target;
-    uint8_t rd = 0;
-    for (int w = 0; w < 2; ++w) {
-      uint64_t m = w ? d.ctrl_hi : d.ctrl_lo;
-      while (m) {
-        const uint32_t q = (uint32_t)__builtin_ctzll(m) + 64u * w;
-        m &= m - 1;
-        if (base.nctrl == kBsMaxCtrl) {
-          inf.eligible = false;
-          break;
-        }
-        base.ctrl[base.nctrl++] = (uint8_t)q;
-        rd |= word_bit(q);
-      }
+  std::vector<std::vector<BsOp>> part_ops(kHostThreads);
+  std::vector<size_t> pb(kHostThreads, 0), pe(kHostThreads, 0);
+  parallel_parts(n_mono, 16384, [&](size_t b, size_t e, size_t p) {
+    std::vector<BsOp>& out = part_ops[p];
+    out.reserve(2 * (e - b));
+    pb[p] = b;
+    pe[p] = e;
+    for (size_t k = b; k < e; ++k) {
+      start[k] = (uint32_t)out.size();   // local to the part until the parts are joined
+      compile_one(descs[k], info[k], out);
     }
-    if (!inf.eligible) continue;
-    auto emit = [&](uint8_t op, uint8_t cmode, uint64_t arg) {
-      BsOp o = base;
-      o.op = op;
-      o.cmode = cmode;
-      o.arg = arg;
-      ops.push_back(o);
-      if (cmode) rd |= word_bit(d.target);
-    };
-    if (d.flags & kHasPhase) {
-      const int k0 = omega_index(d.m0), k1 = omega_index(d.m1);
-      if (k0 >= 0 && k1 >= 0) {
-        if (k0) {
-          if (base.nctrl == 0) inf.g_omega = (uint8_t)((inf.g_omega + k0) & 7);
-          else emit(kBsOmega, 0, (uint64_t)k0);
-        }
-        const uint32_t dk = (uint32_t)(k1 - k0) & 7u;
-        if (dk) emit(kBsOmega, 1, dk);
-      } else if (unit_modulus(d.m0) && unit_modulus(d.m1)) {
-        const uint64_t t0 = turn_of(d.m0), t1 = turn_of(d.m1);
-        if (t0) {
-          if (base.nctrl == 0) {
-            inf.g_turn += t0;
-          } else {
-            emit(kBsTurn, 0, t0);
-            inf.turns = true;
-          }
-        }
-        if (t1 - t0) {
-          emit(kBsTurn, 1, t1 - t0);
-          inf.turns = true;
-        }
-      } else {
-        inf.eligible = false;
-        continue;
-      }
-      inf.phase = true;
-    }
-    if (d.flags & kFlip) {
-      emit(kBsFlip, 0, 0);
-      inf.words_write = word_bit(d.target);
-    }
-    inf.words_read = rd;
+  });
+  size_t total = 0;
+  for (auto& v : part_ops) total += v.size();
+  ops.reserve(total);
+  for (size_t p = 0; p < kHostThreads; ++p) {
+    const uint32_t base = (uint32_t)ops.size();
+    for (size_t k = pb[p]; k < pe[p]; ++k) start[k] += base;
+    ops.insert(ops.end(), part_ops[p].begin(), part_ops[p].end());
   }
   start[n_mono] = (uint32_t)ops.size();
 }
@@ -176,12 +220,25 @@ bool RunCompiler::run_params(size_t begin, size_t len, uint32_t mono_mode, uint3
 // only conflict through the planes they read).  Among the ops of a window that
 // may go next, groups whose four ops are flips with the same number of
 // controls are preferred, because the kernel reads only those planes for them.
+// Large runs are grouped in parts on host threads (ops never move between
+// parts, so the parts' groups concatenate in order).
 void RunCompiler::group(size_t begin, size_t len, std::vector<BsGroup>& out) const {
+  const uint32_t i0 = start[begin], i1 = start[begin + len];
+  if (i1 - i0 < 2 * 2048) {
+    group_range(i0, i1, out);
+    return;
+  }
+  std::vector<std::vector<BsGroup>> parts(kHostThreads);
+  parallel_parts(i1 - i0, 2048, [&](size_t b, size_t e, size_t p) { group_range(i0 + (uint32_t)b, i0 + (uint32_t)e, parts[p]); });
+  for (auto& v : parts) out.insert(out.end(), v.begin(), v.end());
+}
+
+void RunCompiler::group_range(uint32_t i0, uint32_t i1, std::vector<BsGroup>& out) const {
   const uint32_t ones = n_qubits, scratch = n_qubits + 1;
   struct Mask {
     uint64_t lo = 0, hi = 0;
     void set(uint32_t q) { (q < 64 ? lo : hi) |= 1ull << (q & 63); }
-    bool meets(const Mask& o) const { return (lo & o.lo) || (hi & o.hi); }
+    bool meets(const Mask& o) const { return ((lo & o.lo) | (hi & o.hi)) != 0; }
     void add(const Mask& o) {
       lo |= o.lo;
       hi |= o.hi;
@@ -189,14 +246,14 @@ void RunCompiler::group(size_t begin, size_t len, std::vector<BsGroup>& out) con
   };
   struct Item {
     Mask r, w;
-    uint32_t shape;   // kShapeX/CX/CCX for flips with 0..2 controls, else kShapeGeneric
-    bool phase;
-    uint32_t a, b;
-    uint64_t tau;
+    uint32_t shape;   // kShapeX/CX/CCX for flips with 0..2 controls, TURN, else kShapeGeneric
+    uint32_t phase;
   };
-  const uint32_t i0 = start[begin], i1 = start[begin + len];
   const uint32_t n = i1 - i0;
+  if (n == 0) return;
   std::vector<Item> items(n);
+  // Pending ops as a doubly linked list in op order (index n = end).
+  std::vector<uint32_t> nxt(n + 1), prv(n + 1);
   for (uint32_t i = 0; i < n; ++i) {
     const BsOp& o = ops[i0 + i];
     Item& it = items[i];
@@ -205,37 +262,32 @@ void RunCompiler::group(size_t begin, size_t len, std::vector<BsGroup>& out) con
     if (o.op == kBsFlip) it.w.set(o.target);
     it.phase = o.op != kBsFlip;
     it.shape = o.op == kBsTurn ? kShapeTurn : o.op == kBsFlip && o.nctrl <= 2 ? kShapeX + o.nctrl : kShapeGeneric;
-    uint32_t slot[3] = {ones, ones, ones};
-    for (int c = 0; c < o.nctrl; ++c) slot[c] = o.ctrl[c];
-    const uint32_t t = (o.op == kBsFlip || o.cmode) ? o.target : ones;   // flip target, or a phase op's target-bit condition
-    const uint32_t k = o.op == kBsOmega ? (uint32_t)(o.arg & 7u) : 0u;
-    it.a = bs_pack_a(o.op, k, t, slot[0], slot[1]);
-    it.b = bs_pack_b(slot[2]);
-    it.tau = o.op == kBsTurn ? o.arg : 0;
+    nxt[i] = i + 1;
+    prv[i + 1] = i;
   }
+  prv[0] = n;
+  nxt[n] = 0;   // the list is 0 .. n-1; nxt[n] is the head
+  auto unlink = [&](uint32_t j) {
+    nxt[prv[j]] = nxt[j];
+    prv[nxt[j]] = prv[j];
+  };
   // Relative cost of one op slot in a group of each shape (LDS accesses plus
   // vector instructions in the kernel's group bodies).
   auto slot_cost = [](uint32_t shape) { return shape == kShapeX ? 4 : shape == kShapeCX ? 6 : shape == kShapeCCX ? 8 : 12; };
   constexpr uint32_t kWindow = 32;
-  std::vector<char> done(n, 0);
-  uint32_t head = 0;
-  std::vector<uint32_t> pick, best;
-  // Select up to kBsGroup ops from the window starting at head; `want` is a
+  // Select up to kBsGroup ops from the first kWindow pending ops; `want` is a
   // shape all picks must have, or kShapeGeneric for any but turn ops (which
   // only go in TURN groups).
-  auto select = [&](uint32_t want, std::vector<uint32_t>& sel) {
-    sel.clear();
+  auto select = [&](uint32_t want, uint32_t* sel) -> uint32_t {
+    uint32_t k = 0, seen = 0;
     Mask gr, gw, br, bw;   // group reads / writes, reads / writes of ops passed over
-    uint32_t seen = 0;
-    for (uint32_t j = head; j < n && seen < kWindow && sel.size() < (size_t)kBsGroup; ++j) {
-      if (done[j]) continue;
-      ++seen;
+    for (uint32_t j = nxt[n]; j != n && seen < kWindow && k < (uint32_t)kBsGroup; j = nxt[j], ++seen) {
       const Item& it = items[j];
+      const bool shape_ok = want == kShapeGeneric ? it.shape != kShapeTurn : it.shape == want;
       const bool commutes = !it.w.meets(br) && !it.w.meets(bw) && !it.r.meets(bw);
       const bool fits = !it.w.meets(gr) && !it.w.meets(gw) && !it.r.meets(gw);
-      const bool shape_ok = want == kShapeGeneric ? it.shape != kShapeTurn : it.shape == want;
-      if (commutes && fits && shape_ok) {
-        sel.push_back(j);
+      if (shape_ok && commutes && fits) {
+        sel[k++] = j;
         gr.add(it.r);
         gw.add(it.w);
       } else {
@@ -243,34 +295,42 @@ void RunCompiler::group(size_t begin, size_t len, std::vector<BsGroup>& out) con
         bw.add(it.w);
       }
     }
+    return k;
   };
-  while (head < n) {
-    const uint32_t hs = items[head].shape;
-    select(hs, pick);
+  uint32_t pick[kBsGroup], best[kBsGroup];
+  while (nxt[n] != n) {
+    const uint32_t hs = items[nxt[n]].shape;
+    uint32_t np = select(hs, pick);
     uint32_t shape = hs;
-    if (hs != kShapeGeneric && hs != kShapeTurn && pick.size() < (size_t)kBsGroup) {
+    if (hs != kShapeGeneric && hs != kShapeTurn && np < (uint32_t)kBsGroup) {
       // A mixed group may carry more ops than a padded uniform one.
-      select(kShapeGeneric, best);
+      const uint32_t nb = select(kShapeGeneric, best);
       uint32_t s0 = items[best[0]].shape;
-      for (uint32_t j : best)
-        if (items[j].shape != s0) s0 = kShapeGeneric;
-      if ((double)kBsGroup * slot_cost(s0) / best.size() < (double)kBsGroup * slot_cost(hs) / pick.size()) {
-        pick.swap(best);
+      for (uint32_t u = 1; u < nb; ++u)
+        if (items[best[u]].shape != s0) s0 = kShapeGeneric;
+      if ((double)slot_cost(s0) / nb < (double)slot_cost(hs) / np) {
+        for (uint32_t u = 0; u < nb; ++u) pick[u] = best[u];
+        np = nb;
         shape = s0;
       }
     }
-    bool phase = false;
-    BsGroup grp{};
-    size_t u = 0;
-    for (uint32_t j : pick) {
-      done[j] = 1;
+    uint32_t phase = 0;
+    BsGroup grp;
+    uint32_t u = 0;
+    for (; u < np; ++u) {
+      const uint32_t j = pick[u];
+      unlink(j);
       phase |= items[j].phase;
-      grp.a[u] = items[j].a;
-      grp.b[u] = items[j].b;
-      grp.tau[u] = items[j].tau;
-      ++u;
+      const BsOp& o = ops[i0 + j];
+      uint32_t slot[3] = {ones, ones, ones};
+      for (int c = 0; c < o.nctrl; ++c) slot[c] = o.ctrl[c];
+      const uint32_t t = (o.op == kBsFlip || o.cmode) ? o.target : ones;   // flip target, or a phase op's target-bit condition
+      const uint32_t k = o.op == kBsOmega ? (uint32_t)(o.arg & 7u) : 0u;
+      grp.a[u] = bs_pack_a(o.op, k, t, slot[0], slot[1]);
+      grp.b[u] = bs_pack_b(slot[2]);
+      grp.tau[u] = o.op == kBsTurn ? o.arg : 0;
     }
-    for (; u < (size_t)kBsGroup; ++u) {
+    for (; u < (uint32_t)kBsGroup; ++u) {
       if (shape == kShapeTurn) {
         grp.a[u] = bs_pack_a(kBsTurn, 0, ones, ones, ones);     // adds 0 turns
       } else {
@@ -281,7 +341,6 @@ void RunCompiler::group(size_t begin, size_t len, std::vector<BsGroup>& out) con
     }
     grp.a[0] |= (shape == kShapeGeneric && phase ? kShapePhase : shape) << 5;
     out.push_back(grp);
-    while (head < n && done[head]) ++head;
   }
 }
 

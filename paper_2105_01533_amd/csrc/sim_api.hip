@@ -9,11 +9,13 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
 #include <new>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "../../include/sparsesim.h"
@@ -128,16 +130,19 @@ struct DevVec {            // library-owned growable device array
 }  // namespace
 
 // Kernel classes timed by the profiler.
+// Host classes (wall clock, always measured): validation and op compilation
+// at the start of a call, grouping of bit-sliced runs, and time blocked in
+// stream synchronisations.
 enum KClass { KC_MONO = 0, KC_FILL, KC_BUILD, KC_U2_COUNT, KC_SCAN, KC_U2_WRITE, KC_M_REDUCE, KC_M_DECIDE,
-              KC_M_WRITE, KC_COUNT };
+              KC_M_WRITE, KC_KERNELS, KC_H_PREPARE = KC_KERNELS, KC_H_GROUP, KC_H_SYNC, KC_COUNT };
 static const char* const kClassNames[KC_COUNT] = {"mono_pass", "index_fill", "index_build", "u2_count",
                                                   "block_scan", "u2_write", "measure_reduce", "measure_decide",
-                                                  "measure_write"};
+                                                  "measure_write", "host_prepare", "host_group", "host_sync"};
 
 struct sim_t {
   sim_config cfg;
   // profiling
-  bool profile = false;
+  uint32_t profile = 0;          // bit c: kernel class c is timed with events
   std::vector<hipEvent_t> ev_pool;
   size_t ev_used = 0;
   std::vector<std::pair<int, size_t>> ev_pending;   // (class, index of start event)
@@ -183,6 +188,23 @@ hipEvent_t next_event(sim_t* s) {
   return s->ev_pool[s->ev_used++];
 }
 
+// Wall-clock timer of a host class.
+struct HTimer {
+  sim_t* s;
+  int cls;
+  std::chrono::steady_clock::time_point t0;
+  HTimer(sim_t* s_, int c) : s(s_), cls(c), t0(std::chrono::steady_clock::now()) {}
+  ~HTimer() {
+    s->k_launches[cls]++;
+    s->k_ms[cls] += std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  }
+};
+
+hipError_t timed_sync(sim_t* s) {
+  HTimer t_(s, KC_H_SYNC);
+  return hipStreamSynchronize(s->stream);
+}
+
 struct KTimer {
   sim_t* s;
   int cls;
@@ -190,7 +212,7 @@ struct KTimer {
   bool on = false;
   KTimer(sim_t* s_, int c) : s(s_), cls(c) {
     s->k_launches[c]++;
-    if (!s->profile) return;
+    if (!((s->profile >> c) & 1u)) return;
     idx = s->ev_used;
     hipEvent_t e = next_event(s);
     on = e && hipEventRecord(e, s->stream) == hipSuccess;
@@ -233,7 +255,7 @@ uint64_t* d_nnz(sim_t* s, int b) { return &s->ctl->nnz[b]; }
 
 int read_nnz(sim_t* s, uint64_t* out) {
   HIP_TRY(hipMemcpyAsync(s->h_pinned, d_nnz(s, s->cur), 8, hipMemcpyDeviceToHost, s->stream));
-  HIP_TRY(hipStreamSynchronize(s->stream));
+  HIP_TRY(timed_sync(s));
   resolve_events(s);
   *out = s->h_pinned[0];
   s->nnz_known = true;
@@ -300,7 +322,7 @@ int run_u2(sim_t* s, const sim_gate& g, bool* over) {
   HIP_TRY(hipGetLastError());
   if (check) {
     HIP_TRY(hipMemcpyAsync(s->h_pinned, d_nnz(s, other), 8, hipMemcpyDeviceToHost, s->stream));
-    HIP_TRY(hipStreamSynchronize(s->stream));
+    HIP_TRY(timed_sync(s));
     if (s->h_pinned[0] > cap) {
       *over = true;
       return SIM_OK;
@@ -335,7 +357,7 @@ int run_measure(sim_t* s, uint32_t q, double u, int32_t forced, MeasRec* rec, in
   if (forced >= 0 || ub == 0) {
     // A forced outcome may have zero probability: decide before touching the state.
     HIP_TRY(hipMemcpyAsync(s->h_pinned + 1, &rec->outcome, 4, hipMemcpyDeviceToHost, s->stream));
-    HIP_TRY(hipStreamSynchronize(s->stream));
+    HIP_TRY(timed_sync(s));
     int32_t o;
     std::memcpy(&o, s->h_pinned + 1, 4);
     if (o < 0) {
@@ -356,7 +378,7 @@ int run_measure(sim_t* s, uint32_t q, double u, int32_t forced, MeasRec* rec, in
 
 int read_ctl(sim_t* s) {
   HIP_TRY(hipMemcpyAsync(s->h_ctl, s->ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s->stream));
-  HIP_TRY(hipStreamSynchronize(s->stream));
+  HIP_TRY(timed_sync(s));
   resolve_events(s);
   return SIM_OK;
 }
@@ -450,7 +472,7 @@ int sim_set_basis(sim_t* s, sim_key k) {
   if (!key_in_range(s, k.lo, k.hi)) return fail(SIM_E_ARG, "basis key has bits above n_qubits");
   launch_set_basis(s->stream, s->buf[s->cur], d_nnz(s, s->cur), k.lo, k.hi);
   HIP_TRY(hipGetLastError());
-  HIP_TRY(hipStreamSynchronize(s->stream));
+  HIP_TRY(timed_sync(s));
   s->nnz_known = true;
   s->nnz_exact = s->nnz_ub = 1;
   return SIM_OK;
@@ -475,7 +497,7 @@ int sim_import_state(sim_t* s, const sim_key* keys, const sim_c64* amps, uint64_
       if (sorted[i].lo == sorted[i - 1].lo && sorted[i].hi == sorted[i - 1].hi)
         return fail(SIM_E_ARG, "duplicate key in import");
   }
-  HIP_TRY(hipStreamSynchronize(s->stream));
+  HIP_TRY(timed_sync(s));
   const Buf& b = s->buf[s->cur];
   if (n) {
     HIP_TRY(hipMemcpy(b.key_lo, lo.data(), n * 8, hipMemcpyHostToDevice));
@@ -484,7 +506,7 @@ int sim_import_state(sim_t* s, const sim_key* keys, const sim_c64* amps, uint64_
   }
   s->h_pinned[2] = n;
   HIP_TRY(hipMemcpyAsync(d_nnz(s, s->cur), s->h_pinned + 2, 8, hipMemcpyHostToDevice, s->stream));
-  HIP_TRY(hipStreamSynchronize(s->stream));
+  HIP_TRY(timed_sync(s));
   s->nnz_known = true;
   s->nnz_exact = s->nnz_ub = n;
   return SIM_OK;
@@ -551,21 +573,32 @@ int sim_apply_gates(sim_t* s, const sim_gate* gates, size_t n, int32_t* outcomes
   if (n && !gates) return fail(SIM_E_ARG, "null gate array");
   sim_stats st;
   std::memset(&st, 0, sizeof st);
-  // Validate everything first: an invalid op applies nothing.
   size_t n_mono = 0, n_meas = 0;
-  for (size_t i = 0; i < n; ++i) {
-    int rc = validate(s, gates[i], i);
-    if (rc) return rc;
-    if (gates[i].op == SIM_OP_MONO) ++n_mono;
-    if (gates[i].op == SIM_OP_MEASURE) ++n_meas;
-  }
-  // Stage the phase/permutation descriptors in one upload.
-  s->rc.descs.resize(n_mono);
-  for (size_t i = 0, k = 0; i < n; ++i)
-    if (gates[i].op == SIM_OP_MONO) s->rc.descs[k++] = mono_desc(gates[i]);
-  // Bit-sliced bytecode of every phase/permutation op (used by eligible runs).
   const bool bs_allowed = s->cfg.mono_mode != SIM_MONO_DIRECT;
-  if (bs_allowed) s->rc.compile(s->cfg.n_qubits);
+  {
+    HTimer t_(s, KC_H_PREPARE);
+    // Validate everything first: an invalid op applies nothing.
+    for (size_t i = 0; i < n; ++i) {
+      int rc = validate(s, gates[i], i);
+      if (rc) return rc;
+      if (gates[i].op == SIM_OP_MONO) ++n_mono;
+      if (gates[i].op == SIM_OP_MEASURE) ++n_meas;
+    }
+    // Stage the phase/permutation descriptors in one upload.
+    s->rc.descs.resize(n_mono);
+    for (size_t i = 0, k = 0; i < n; ++i)
+      if (gates[i].op == SIM_OP_MONO) s->rc.descs[k++] = mono_desc(gates[i]);
+  }
+  // Bit-sliced bytecode of every phase/permutation op (used by eligible
+  // runs), compiled on a host thread while the first ops run; joined before
+  // the first run needs it (and on every way out of this call).
+  struct Joiner {
+    std::thread t;
+    ~Joiner() {
+      if (t.joinable()) t.join();
+    }
+  } compiler;
+  if (bs_allowed) compiler.t = std::thread([s]() { s->rc.compile(s->cfg.n_qubits); });
   HIP_TRY(s->descs.reserve(n_mono));
   HIP_TRY(s->recs.reserve(n_meas));
   HIP_TRY(s->outcomes.reserve(n_meas));
@@ -573,13 +606,21 @@ int sim_apply_gates(sim_t* s, const sim_gate* gates, size_t n, int32_t* outcomes
     HIP_TRY(hipMemcpyAsync(s->descs.p, s->rc.descs.data(), n_mono * sizeof(MonoDesc), hipMemcpyHostToDevice,
                            s->stream));
   // Grouped kernel ops of the bit-sliced runs, appended run by run; every
-  // group holds at least one op, so reserving one group per op up front keeps
-  // the host copies of in-flight uploads in place.
+  // group holds at least one op, so reserving one group per op before the
+  // first run keeps the host copies of in-flight uploads in place.
   s->h_grp.clear();
-  if (bs_allowed) {
+  bool compiled = !bs_allowed;
+  auto ensure_compiled = [&]() -> int {
+    if (compiled) return SIM_OK;
+    {
+      HTimer t_(s, KC_H_PREPARE);
+      compiler.t.join();
+    }
+    compiled = true;
     s->h_grp.reserve(s->rc.ops.size() + 1);
     HIP_TRY(s->grp_ops.reserve(s->rc.ops.size() + 1));
-  }
+    return SIM_OK;
+  };
 
   int result = SIM_OK;
   size_t run_begin = 0, run_len = 0, mono_seen = 0, meas_seen = 0;
@@ -596,10 +637,17 @@ int sim_apply_gates(sim_t* s, const sim_gate* gates, size_t n, int32_t* outcomes
     const uint32_t kb = s->wide ? 16u : 8u;
     const uint32_t run_bpe = kb + ((run_flags & kRunFlip) ? kb : 0u) + ((run_flags & kRunPhase) ? 32u : 0u);
     BsRun br;
+    if (bs_allowed) {
+      int rc = ensure_compiled();
+      if (rc) return rc;
+    }
     if (bs_allowed && s->rc.run_params(run_begin, run_len, s->cfg.mono_mode, s->cfg.bs_min_gates, &br)) {
       br.bytes_per_entry = run_bpe;
       const size_t g0 = s->h_grp.size();
-      s->rc.group(run_begin, run_len, s->h_grp);
+      {
+        HTimer tg_(s, KC_H_GROUP);
+        s->rc.group(run_begin, run_len, s->h_grp);
+      }
       const size_t ng = s->h_grp.size() - g0;
       if (ng)
         HIP_TRY(hipMemcpyAsync(s->grp_ops.p + g0, s->h_grp.data() + g0, ng * sizeof(BsGroup), hipMemcpyHostToDevice,
@@ -633,7 +681,9 @@ int sim_apply_gates(sim_t* s, const sim_gate* gates, size_t n, int32_t* outcomes
       continue;
     }
     if (g.op == SIM_OP_U2) {
-      if (g.cap) {
+      // Skipped iff 2 * nnz > cap.  The exact count is read back only when
+      // the tracked upper bound cannot settle it.
+      if (g.cap && 2 * (s->nnz_known ? s->nnz_exact : s->nnz_ub) > g.cap) {
         uint64_t nnz = s->nnz_exact;
         if (!s->nnz_known) {
           int rc = read_nnz(s, &nnz);
@@ -683,7 +733,7 @@ int sim_apply_gates(sim_t* s, const sim_gate* gates, size_t n, int32_t* outcomes
   if (result == SIM_OK && s->h_ctl->error) {
     s->h_ctl->error = 0;
     HIP_TRY(hipMemcpyAsync(&s->ctl->error, &s->h_ctl->error, 4, hipMemcpyHostToDevice, s->stream));
-    HIP_TRY(hipStreamSynchronize(s->stream));
+    HIP_TRY(timed_sync(s));
     result = fail(SIM_E_STATE, "measurement of an empty state");
   }
   st.gates_applied = i;
@@ -732,7 +782,7 @@ int sim_measure(sim_t* s, uint32_t qubit, double u, int32_t forced, int32_t* out
     if (s->h_ctl->error) {
       s->h_ctl->error = 0;
       HIP_TRY(hipMemcpyAsync(&s->ctl->error, &s->h_ctl->error, 4, hipMemcpyHostToDevice, s->stream));
-      HIP_TRY(hipStreamSynchronize(s->stream));
+      HIP_TRY(timed_sync(s));
     }
     return fail(SIM_E_STATE, "measurement outcome has zero probability or the state is empty");
   }
@@ -748,7 +798,7 @@ int sim_nnz(sim_t* s, uint64_t* nnz) {
 
 int sim_sync(sim_t* s) {
   if (!s) return fail(SIM_E_ARG, "null handle");
-  HIP_TRY(hipStreamSynchronize(s->stream));
+  HIP_TRY(timed_sync(s));
   return SIM_OK;
 }
 
@@ -804,9 +854,10 @@ int sim_device_copy(void* dst, const void* src, size_t bytes, void* stream) {
 
 int sim_set_profiling(sim_t* s, int on) {
   if (!s) return fail(SIM_E_ARG, "null handle");
-  HIP_TRY(hipStreamSynchronize(s->stream));
+  HIP_TRY(timed_sync(s));
   resolve_events(s);
-  s->profile = on != 0;
+  if (on < 0 || on > SIM_PROFILE_MONO) return fail(SIM_E_ARG, "profiling mode must be 0, 1 or 2");
+  s->profile = on == SIM_PROFILE_ALL ? (1u << KC_KERNELS) - 1u : on == SIM_PROFILE_MONO ? 1u << KC_MONO : 0u;
   return SIM_OK;
 }
 

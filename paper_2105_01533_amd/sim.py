@@ -25,6 +25,7 @@ LIB_PATH = os.path.join(_HERE, "libsparsesim.so")
 SIM_OK, SIM_E_ARG, SIM_E_NOMEM, SIM_E_CAPACITY, SIM_E_BUFFER, SIM_E_HIP, SIM_E_STATE = 0, -1, -2, -3, -4, -5, -6
 SIM_OP_MONO, SIM_OP_U2, SIM_OP_MEASURE = 0, 1, 2
 SIM_MONO_AUTO, SIM_MONO_DIRECT, SIM_MONO_BITSLICE = 0, 1, 2
+SIM_PROFILE_OFF, SIM_PROFILE_ALL, SIM_PROFILE_MONO = 0, 1, 2
 
 GATE_DTYPE = np.dtype([
     ("op", "<u4"), ("target", "<u4"), ("ctrl_lo", "<u8"), ("ctrl_hi", "<u8"),
@@ -231,8 +232,10 @@ def sim_device_copy(dst: int, src: int, nbytes: int, stream: int | None = None):
     _check(_lib.sim_device_copy(dst, src, nbytes, stream), "sim_device_copy")
 
 
-def sim_set_profiling(h, on: bool):
-    _check(_lib.sim_set_profiling(h, int(bool(on))), "sim_set_profiling")
+def sim_set_profiling(h, on):
+    """on: False/True (off / every kernel class) or a SIM_PROFILE_* mode."""
+    mode = int(on) if not isinstance(on, bool) else (SIM_PROFILE_ALL if on else SIM_PROFILE_OFF)
+    _check(_lib.sim_set_profiling(h, mode), "sim_set_profiling")
 
 
 def sim_kernel_stats(h) -> dict:
