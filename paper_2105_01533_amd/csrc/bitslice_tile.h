@@ -36,6 +36,33 @@ __device__ __forceinline__ void omega_add(uint32_t& e0, uint32_t& e1, uint32_t& 
   e2 ^= b2 ^ c1;
 }
 
+// omega_add for a wave-uniform k: only the counter bits k touches.
+__device__ __forceinline__ void omega_add_k(uint32_t& e0, uint32_t& e1, uint32_t& e2, uint32_t x, uint32_t k) {
+  switch (k) {
+    case 1: {
+      const uint32_t c0 = e0 & x;
+      e0 ^= x;
+      e2 ^= e1 & c0;
+      e1 ^= c0;
+      break;
+    }
+    case 2:
+      e2 ^= e1 & x;
+      e1 ^= x;
+      break;
+    case 4:
+      e2 ^= x;
+      break;
+    case 6:
+      e2 ^= x ^ (e1 & x);
+      e1 ^= x;
+      break;
+    default:
+      omega_add(e0, e1, e2, x, k);
+      break;
+  }
+}
+
 // Load the lane's 32 labels' 64-bit word (src already offset by base + lane;
 // entry j at src[64 j]) and transpose both 32-bit halves into planes
 // 32*w0 .. 32*w0+63 of LDS.
@@ -96,6 +123,40 @@ __device__ __forceinline__ uint32_t off_p0(uint32_t a) { return (a >> 8) & 0xff0
 __device__ __forceinline__ uint32_t off_p1(uint32_t a) { return (a >> 16) & 0xff00u; }
 __device__ __forceinline__ uint32_t off_p2(uint32_t b) { return b & 0xff00u; }
 
+// Flip bodies over N mutually independent ops (all reads, then all writes):
+// plane t ^= AND of 0, 1 or 2 control planes.
+template <int N>
+__device__ __forceinline__ void flip_x(char* Lb, const uint32_t* a) {
+  uint32_t tv[N];
+#pragma unroll
+  for (int u = 0; u < N; ++u) tv[u] = plane(Lb, off_t(a[u]));
+#pragma unroll
+  for (int u = 0; u < N; ++u) plane(Lb, off_t(a[u])) = ~tv[u];
+}
+template <int N>
+__device__ __forceinline__ void flip_cx(char* Lb, const uint32_t* a) {
+  uint32_t tv[N], c0[N];
+#pragma unroll
+  for (int u = 0; u < N; ++u) {
+    c0[u] = plane(Lb, off_p0(a[u]));
+    tv[u] = plane(Lb, off_t(a[u]));
+  }
+#pragma unroll
+  for (int u = 0; u < N; ++u) plane(Lb, off_t(a[u])) = tv[u] ^ c0[u];
+}
+template <int N>
+__device__ __forceinline__ void flip_ccx(char* Lb, const uint32_t* a) {
+  uint32_t tv[N], c0[N], c1[N];
+#pragma unroll
+  for (int u = 0; u < N; ++u) {
+    c0[u] = plane(Lb, off_p0(a[u]));
+    c1[u] = plane(Lb, off_p1(a[u]));
+    tv[u] = plane(Lb, off_t(a[u]));
+  }
+#pragma unroll
+  for (int u = 0; u < N; ++u) plane(Lb, off_t(a[u])) = tv[u] ^ (c0[u] & c1[u]);
+}
+
 // Apply ngroups grouped ops to the 2048-entry tile at base (lim valid
 // entries): labels to LDS planes, gates, labels back, one phase multiply per
 // amplitude.  L = LDS base + lane; the all-ones plane must be set.
@@ -142,31 +203,38 @@ __device__ __forceinline__ void bs_tile(const Buf& b, uint64_t base, uint32_t li
           a[3] = __builtin_amdgcn_readlane(ca.w, g);
           const uint32_t shape = bs_shape(a[0]);
           if (shape == kShapeTurn) break;
-          if (shape == kShapeX) {
+          // Eight independent flips of one shape when paired with the next
+          // group (its a words are at the next lane).
+#define BS_FLIP_CASE(SHAPE, BODY)                                  \
+  case SHAPE:                                                      \
+    if (a[1] & kPairBit) {                                         \
+      uint32_t a8[2 * kBsGroup] = {a[0], a[1], a[2], a[3],         \
+                                   (uint32_t)__builtin_amdgcn_readlane(ca.x, g + 1), \
+                                   (uint32_t)__builtin_amdgcn_readlane(ca.y, g + 1), \
+                                   (uint32_t)__builtin_amdgcn_readlane(ca.z, g + 1), \
+                                   (uint32_t)__builtin_amdgcn_readlane(ca.w, g + 1)}; \
+      BODY<2 * kBsGroup>(Lb, a8);                                  \
+      ++g;                                                         \
+    } else {                                                       \
+      BODY<kBsGroup>(Lb, a);                                       \
+    }                                                              \
+    continue;
+          switch (shape) {
+            BS_FLIP_CASE(kShapeX, flip_x)
+            BS_FLIP_CASE(kShapeCX, flip_cx)
+            BS_FLIP_CASE(kShapeCCX, flip_ccx)
+            default:
+              break;
+          }
+#undef BS_FLIP_CASE
+          if (shape == kShapeOmega) {
+            // Eighth-turn phase ops conditioned on their target bit only
+            // (Z, S, T and their adjoints): read-only on the planes.
             uint32_t tv[kBsGroup];
 #pragma unroll
             for (int u = 0; u < kBsGroup; ++u) tv[u] = plane(Lb, off_t(a[u]));
 #pragma unroll
-            for (int u = 0; u < kBsGroup; ++u) plane(Lb, off_t(a[u])) = ~tv[u];
-          } else if (shape == kShapeCX) {
-            uint32_t tv[kBsGroup], c0[kBsGroup];
-#pragma unroll
-            for (int u = 0; u < kBsGroup; ++u) {
-              c0[u] = plane(Lb, off_p0(a[u]));
-              tv[u] = plane(Lb, off_t(a[u]));
-            }
-#pragma unroll
-            for (int u = 0; u < kBsGroup; ++u) plane(Lb, off_t(a[u])) = tv[u] ^ c0[u];
-          } else if (shape == kShapeCCX) {
-            uint32_t tv[kBsGroup], c0[kBsGroup], c1[kBsGroup];
-#pragma unroll
-            for (int u = 0; u < kBsGroup; ++u) {
-              c0[u] = plane(Lb, off_p0(a[u]));
-              c1[u] = plane(Lb, off_p1(a[u]));
-              tv[u] = plane(Lb, off_t(a[u]));
-            }
-#pragma unroll
-            for (int u = 0; u < kBsGroup; ++u) plane(Lb, off_t(a[u])) = tv[u] ^ (c0[u] & c1[u]);
+            for (int u = 0; u < kBsGroup; ++u) omega_add_k(e0, e1, e2, tv[u], (a[u] >> 2) & 7u);
           } else {
             // General group: every op writes its plane t; a flip xors the
             // condition in, an eighth-turn phase op's t is a fourth condition
@@ -218,14 +286,53 @@ __device__ __forceinline__ void bs_tile(const Buf& b, uint64_t base, uint32_t li
             x[u] = plane(Lb, off_p0(a[u])) & plane(Lb, off_p1(a[u])) & plane(Lb, off_p2(bw[u])) &
                    plane(Lb, off_t(a[u]));
           const uint32_t tg = 16u * (g0 + g) + 8u;   // the group's turn fractions, in 32-bit words
+          uint64_t tau[kBsGroup];
 #pragma unroll
-          for (int u = 0; u < kBsGroup; ++u) {
-            const uint32_t tlo = taus[tg + 2 * u], thi = taus[tg + 2 * u + 1];
-            if ((tlo | thi) == 0u) continue;   // padding
+          for (int u = 0; u < kBsGroup; ++u) tau[u] = ((uint64_t)taus[tg + 2 * u + 1] << 32) | taus[tg + 2 * u];
+          // An entry gains the sum of the fractions of the ops whose condition
+          // holds for it: one of 16 subset sums, kept in every 16-lane quarter
+          // of the wave (lane l holds the sum over the ops named by l's low
+          // four bits) and fetched per entry with a lane permute.
+          uint64_t S = 0;
 #pragma unroll
-            for (int j = 0; j < 32; ++j) {
-              const uint32_t m = (uint32_t)(-(int32_t)((x[u] >> j) & 1u));
-              turns[j] += ((uint64_t)(thi & m) << 32) | (tlo & m);
+          for (int u = 0; u < kBsGroup; ++u) S += tau[u] & (0ull - (uint64_t)((lane >> u) & 1));
+          const int s_lo = (int)(uint32_t)S, s_hi = (int)(uint32_t)(S >> 32);
+          // Nibble i of W[c] = the ops (bit u = op u) that hold for entry
+          // 8c + i: a byte transpose of the four masks, then each word's
+          // 4 x 8 bit matrix transposed by rotating its bit index
+          // (u1 u0 i2 i1 i0) -> (i2 i1 i0 u1 u0) with four delta swaps.
+          uint32_t W[4];
+#pragma unroll
+          for (int c = 0; c < 4; ++c) {
+            uint32_t w = ((x[0] >> (8 * c)) & 0xffu) | (((x[1] >> (8 * c)) & 0xffu) << 8) |
+                         (((x[2] >> (8 * c)) & 0xffu) << 16) | (((x[3] >> (8 * c)) & 0xffu) << 24);
+            uint32_t t;
+            t = (w ^ (w >> 12)) & 0x0000F0F0u; w ^= t ^ (t << 12);   // index bits 2 <-> 4
+            t = (w ^ (w >> 6)) & 0x00CC00CCu;  w ^= t ^ (t << 6);    // 1 <-> 3
+            t = (w ^ (w >> 3)) & 0x0A0A0A0Au;  w ^= t ^ (t << 3);    // 0 <-> 2
+            t = (w ^ (w >> 1)) & 0x22222222u;  w ^= t ^ (t << 1);    // 0 <-> 1
+            W[c] = w;
+          }
+          // Permutes go out seven entries (14 lane-permutes, within the LDS
+          // counter's reach) at a time before their sums are added.
+#pragma unroll
+          for (int j0 = 0; j0 < 32; j0 += 7) {
+            uint32_t lo[7], hi[7];
+#pragma unroll
+            for (int k = 0; k < 7 && j0 + k < 32; ++k) {
+              const int j = j0 + k, c = j >> 3, i = j & 7;
+              // Permute byte address: the nibble in bits 2-5 (bits 0-1 are
+              // ignored by the permute, bits 6-7 are zero).
+              const uint32_t addr = i ? __builtin_amdgcn_ubfe(W[c], 4 * i - 2, 6) : (W[c] << 2) & 0x3cu;
+              lo[k] = (uint32_t)__builtin_amdgcn_ds_bpermute((int)addr, s_lo);
+              hi[k] = (uint32_t)__builtin_amdgcn_ds_bpermute((int)addr, s_hi);
+            }
+            __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+            for (int k = 0; k < 7 && j0 + k < 32; ++k) {
+              uint64_t v = ((uint64_t)hi[k] << 32) | lo[k];
+              asm("" : "+v"(v));   // one register pair, added once
+              turns[j0 + k] += v;
             }
           }
         }

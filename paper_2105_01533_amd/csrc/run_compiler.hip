@@ -261,7 +261,10 @@ void RunCompiler::group_range(uint32_t i0, uint32_t i1, std::vector<BsGroup>& ou
     if (o.cmode || o.op == kBsFlip) it.r.set(o.target);
     if (o.op == kBsFlip) it.w.set(o.target);
     it.phase = o.op != kBsFlip;
-    it.shape = o.op == kBsTurn ? kShapeTurn : o.op == kBsFlip && o.nctrl <= 2 ? kShapeX + o.nctrl : kShapeGeneric;
+    it.shape = o.op == kBsTurn                           ? kShapeTurn
+               : o.op == kBsFlip && o.nctrl <= 2          ? kShapeX + o.nctrl
+               : o.op == kBsOmega && o.nctrl == 0 && o.cmode ? kShapeOmega
+                                                          : kShapeGeneric;
     nxt[i] = i + 1;
     prv[i + 1] = i;
   }
@@ -273,15 +276,20 @@ void RunCompiler::group_range(uint32_t i0, uint32_t i1, std::vector<BsGroup>& ou
   };
   // Relative cost of one op slot in a group of each shape (LDS accesses plus
   // vector instructions in the kernel's group bodies).
-  auto slot_cost = [](uint32_t shape) { return shape == kShapeX ? 4 : shape == kShapeCX ? 6 : shape == kShapeCCX ? 8 : 12; };
+  auto slot_cost = [](uint32_t shape) {
+    return shape == kShapeX ? 4 : shape == kShapeCX ? 6 : shape == kShapeCCX ? 8 : shape == kShapeOmega ? 5 : 12;
+  };
   constexpr uint32_t kWindow = 32;
-  // Select up to kBsGroup ops from the first kWindow pending ops; `want` is a
+  // Select up to kBsGroup ops from the first pending ops; `want` is a
   // shape all picks must have, or kShapeGeneric for any but turn ops (which
   // only go in TURN groups).
-  auto select = [&](uint32_t want, uint32_t* sel) -> uint32_t {
+  // Turn ops are sparse but commute with every op that does not flip one of
+  // their condition planes, so TURN groups look further ahead.
+  auto select = [&](uint32_t want, uint32_t* sel, uint32_t cap) -> uint32_t {
     uint32_t k = 0, seen = 0;
+    const uint32_t window = want == kShapeTurn ? 4 * kWindow : cap > (uint32_t)kBsGroup ? 2 * kWindow : kWindow;
     Mask gr, gw, br, bw;   // group reads / writes, reads / writes of ops passed over
-    for (uint32_t j = nxt[n]; j != n && seen < kWindow && k < (uint32_t)kBsGroup; j = nxt[j], ++seen) {
+    for (uint32_t j = nxt[n]; j != n && seen < window && k < cap; j = nxt[j], ++seen) {
       const Item& it = items[j];
       const bool shape_ok = want == kShapeGeneric ? it.shape != kShapeTurn : it.shape == want;
       const bool commutes = !it.w.meets(br) && !it.w.meets(bw) && !it.r.meets(bw);
@@ -297,28 +305,13 @@ void RunCompiler::group_range(uint32_t i0, uint32_t i1, std::vector<BsGroup>& ou
     }
     return k;
   };
-  uint32_t pick[kBsGroup], best[kBsGroup];
-  while (nxt[n] != n) {
-    const uint32_t hs = items[nxt[n]].shape;
-    uint32_t np = select(hs, pick);
-    uint32_t shape = hs;
-    if (hs != kShapeGeneric && hs != kShapeTurn && np < (uint32_t)kBsGroup) {
-      // A mixed group may carry more ops than a padded uniform one.
-      const uint32_t nb = select(kShapeGeneric, best);
-      uint32_t s0 = items[best[0]].shape;
-      for (uint32_t u = 1; u < nb; ++u)
-        if (items[best[u]].shape != s0) s0 = kShapeGeneric;
-      if ((double)slot_cost(s0) / nb < (double)slot_cost(hs) / np) {
-        for (uint32_t u = 0; u < nb; ++u) pick[u] = best[u];
-        np = nb;
-        shape = s0;
-      }
-    }
+  // Append a group of the picked ops (np <= kBsGroup), padded.
+  auto emit = [&](const uint32_t* picked, uint32_t np, uint32_t shape) {
     uint32_t phase = 0;
     BsGroup grp;
     uint32_t u = 0;
     for (; u < np; ++u) {
-      const uint32_t j = pick[u];
+      const uint32_t j = picked[u];
       unlink(j);
       phase |= items[j].phase;
       const BsOp& o = ops[i0 + j];
@@ -333,6 +326,8 @@ void RunCompiler::group_range(uint32_t i0, uint32_t i1, std::vector<BsGroup>& ou
     for (; u < (uint32_t)kBsGroup; ++u) {
       if (shape == kShapeTurn) {
         grp.a[u] = bs_pack_a(kBsTurn, 0, ones, ones, ones);     // adds 0 turns
+      } else if (shape == kShapeOmega) {
+        grp.a[u] = bs_pack_a(kBsOmega, 0, ones, ones, ones);    // adds 0 eighths
       } else {
         grp.a[u] = bs_pack_a(kBsFlip, 0, scratch, ones, ones);  // scratch ^= ones, or scratch = ~scratch
       }
@@ -341,7 +336,41 @@ void RunCompiler::group_range(uint32_t i0, uint32_t i1, std::vector<BsGroup>& ou
     }
     grp.a[0] |= (shape == kShapeGeneric && phase ? kShapePhase : shape) << 5;
     out.push_back(grp);
+  };
+  const size_t base = out.size();
+  uint32_t pick[2 * kBsGroup], best[kBsGroup];
+  while (nxt[n] != n) {
+    const uint32_t hs = items[nxt[n]].shape;
+    const bool flip = hs == kShapeX || hs == kShapeCX || hs == kShapeCCX;
+    // Flip groups at even positions may pair with the next group: eight
+    // mutually independent ops of one shape, read together by the kernel.
+    const bool can_pair = flip && ((out.size() - base) & 1) == 0;
+    uint32_t np = select(hs, pick, can_pair ? 2 * kBsGroup : kBsGroup);
+    if (np == 2 * kBsGroup) {
+      emit(pick, kBsGroup, hs);
+      out.back().a[1] |= kPairBit;
+      emit(pick + kBsGroup, kBsGroup, hs);
+      continue;
+    }
+    np = std::min<uint32_t>(np, kBsGroup);
+    uint32_t shape = hs;
+    if (hs != kShapeGeneric && hs != kShapeTurn && np < (uint32_t)kBsGroup) {
+      // A mixed general group may carry more ops than a padded uniform one
+      // (an OMEGA head may also join a general group).
+      const uint32_t nb = select(kShapeGeneric, best, kBsGroup);
+      uint32_t s0 = items[best[0]].shape;
+      for (uint32_t u = 1; u < nb; ++u)
+        if (items[best[u]].shape != s0) s0 = kShapeGeneric;
+      if ((double)slot_cost(s0) / nb < (double)slot_cost(hs) / np) {
+        for (uint32_t u = 0; u < nb; ++u) pick[u] = best[u];
+        np = nb;
+        shape = s0;
+      }
+    }
+    emit(pick, np, shape);
   }
+  // An even count keeps pairs aligned when ranges are concatenated.
+  if ((out.size() - base) & 1) emit(pick, 0, kShapeX);
 }
 
 }  // namespace sparsesim

@@ -605,9 +605,10 @@ int sim_apply_gates(sim_t* s, const sim_gate* gates, size_t n, int32_t* outcomes
   if (n_mono)
     HIP_TRY(hipMemcpyAsync(s->descs.p, s->rc.descs.data(), n_mono * sizeof(MonoDesc), hipMemcpyHostToDevice,
                            s->stream));
-  // Grouped kernel ops of the bit-sliced runs, appended run by run; every
-  // group holds at least one op, so reserving one group per op before the
-  // first run keeps the host copies of in-flight uploads in place.
+  // Grouped kernel ops of the bit-sliced runs, appended run by run.  A run
+  // of k > 0 ops has at most k + 1 groups (every group but an evening pad
+  // holds an op), so reserving two groups per op before the first run keeps
+  // the host copies of in-flight uploads in place.
   s->h_grp.clear();
   bool compiled = !bs_allowed;
   auto ensure_compiled = [&]() -> int {
@@ -617,8 +618,8 @@ int sim_apply_gates(sim_t* s, const sim_gate* gates, size_t n, int32_t* outcomes
       compiler.t.join();
     }
     compiled = true;
-    s->h_grp.reserve(s->rc.ops.size() + 1);
-    HIP_TRY(s->grp_ops.reserve(s->rc.ops.size() + 1));
+    s->h_grp.reserve(2 * s->rc.ops.size() + 2);
+    HIP_TRY(s->grp_ops.reserve(2 * s->rc.ops.size() + 2));
     return SIM_OK;
   };
 
@@ -649,6 +650,7 @@ int sim_apply_gates(sim_t* s, const sim_gate* gates, size_t n, int32_t* outcomes
         s->rc.group(run_begin, run_len, s->h_grp);
       }
       const size_t ng = s->h_grp.size() - g0;
+      if (s->h_grp.size() > s->grp_ops.n) return fail(SIM_E_STATE, "bit-sliced op groups exceed their buffer");
       if (ng)
         HIP_TRY(hipMemcpyAsync(s->grp_ops.p + g0, s->h_grp.data() + g0, ng * sizeof(BsGroup), hipMemcpyHostToDevice,
                                s->stream));

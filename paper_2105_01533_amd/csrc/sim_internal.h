@@ -59,11 +59,18 @@ static_assert(sizeof(BsOp) == 16, "BsOp is 16 bytes");
 //   b: bits 8-15 p2
 // The shape tells the kernel that all four ops are flips with the same number
 // of controls (X, CX, CCX: only those planes are read, all named by a), that
-// they are all turn ops (TURN; padding ops have tau = 0), or that the group is
-// general (three condition slots; flips and eighth-turn phase ops), PHASE when
-// it holds a phase op.
+// they are all turn ops (TURN; padding ops have tau = 0), that they are all
+// eighth-turn ops conditioned on their target bit only (OMEGA; padding ops
+// have k = 0), or that the group is general (three condition slots; flips and
+// eighth-turn phase ops), PHASE when it holds a phase op.
 constexpr int kBsGroup = 4;
-constexpr uint32_t kShapeGeneric = 0, kShapeX = 1, kShapeCX = 2, kShapeCCX = 3, kShapeTurn = 4, kShapePhase = 5;
+constexpr uint32_t kShapeGeneric = 0, kShapeX = 1, kShapeCX = 2, kShapeCCX = 3, kShapeTurn = 4, kShapePhase = 5,
+                   kShapeOmega = 6;
+// In a[1] of an X, CX or CCX group at an even position of its run: the next
+// group has the same shape and no plane conflict with this one, so the kernel
+// applies the eight ops as one (all reads, then all writes).  Every run has an
+// even number of groups.
+constexpr uint32_t kPairBit = 1u << 5;
 struct BsGroup {
   uint32_t a[kBsGroup], b[kBsGroup];
   uint64_t tau[kBsGroup];

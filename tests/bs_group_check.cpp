@@ -62,12 +62,49 @@ uint32_t f_p0(uint32_t a) { return (a >> 16) & 0xffu; }
 uint32_t f_p1(uint32_t a) { return a >> 24; }
 uint32_t f_p2(uint32_t b) { return (b >> 8) & 0xffu; }
 
+// Paired flip groups: eight independent ops of one shape applied as one
+// (all reads before all writes).
+bool apply_pair(State& s, const BsGroup& G0, const BsGroup& G1, uint32_t nq, std::string* why) {
+  const uint32_t shape = f_shape(G0.a[0]), scratch = nq + 1;
+  if (shape < kShapeX || shape > kShapeCCX || f_shape(G1.a[0]) != shape) return *why = "bad pair shapes", false;
+  if (G1.a[1] & kPairBit) return *why = "pair flag on a pair's second group", false;
+  uint32_t a[8];
+  for (int u = 0; u < 4; ++u) a[u] = G0.a[u], a[4 + u] = G1.a[u];
+  for (int u = 0; u < 8; ++u) {
+    if (f_op(a[u]) != kBsFlip) return *why = "non-flip op in a pair", false;
+    if (f_t(a[u]) == scratch) continue;
+    for (int v = 0; v < 8; ++v) {
+      if (v == u) continue;
+      const uint32_t r[3] = {f_t(a[v]), shape >= kShapeCX ? f_p0(a[v]) : 0xffffu, shape >= kShapeCCX ? f_p1(a[v]) : 0xffffu};
+      for (uint32_t q : r)
+        if (q == f_t(a[u])) return *why = "pair members conflict", false;
+    }
+  }
+  for (int w = 0; w < kWords; ++w) {
+    uint32_t tv[8], c[8];
+    for (int u = 0; u < 8; ++u) {
+      tv[u] = s.p(f_t(a[u]), w);
+      c[u] = (shape >= kShapeCX ? s.p(f_p0(a[u]), w) : ~0u) & (shape >= kShapeCCX ? s.p(f_p1(a[u]), w) : ~0u);
+    }
+    for (int u = 0; u < 8; ++u) s.p(f_t(a[u]), w) = tv[u] ^ c[u];
+  }
+  return true;
+}
+
 bool apply_groups(State& s, const std::vector<BsGroup>& groups, uint32_t nq, std::string* why) {
   const uint32_t scratch = nq + 1;
-  for (const BsGroup& G : groups) {
+  if (groups.size() & 1) return *why = "odd number of groups", false;
+  for (size_t gi = 0; gi < groups.size(); ++gi) {
+    const BsGroup& G = groups[gi];
+    if (G.a[1] & kPairBit) {
+      if (gi & 1) return *why = "pair at an odd position", false;
+      if (!apply_pair(s, G, groups[gi + 1], nq, why)) return false;
+      ++gi;
+      continue;
+    }
     const uint32_t shape = f_shape(G.a[0]);
     for (int u = 1; u < kBsGroup; ++u)
-      if (f_shape(G.a[u])) return *why = "shape set on a non-first op", false;
+      if (f_shape(G.a[u])) return *why = "shape or pair bits set on a non-first op", false;
     // Independence: no member writes a plane another member reads or writes
     // (padding flips of the scratch plane excepted).
     for (int u = 0; u < kBsGroup; ++u) {
@@ -84,9 +121,20 @@ bool apply_groups(State& s, const std::vector<BsGroup>& groups, uint32_t nq, std
       uint32_t tv[kBsGroup], c0[kBsGroup], c1[kBsGroup], c2[kBsGroup];
       for (int u = 0; u < kBsGroup; ++u) {   // every read before any write
         tv[u] = s.p(f_t(G.a[u]), w);
-        c0[u] = shape == kShapeX ? ~0u : s.p(f_p0(G.a[u]), w);
-        c1[u] = shape == kShapeX || shape == kShapeCX ? ~0u : s.p(f_p1(G.a[u]), w);
+        c0[u] = shape == kShapeX || shape == kShapeOmega ? ~0u : s.p(f_p0(G.a[u]), w);
+        c1[u] = shape == kShapeX || shape == kShapeCX || shape == kShapeOmega ? ~0u : s.p(f_p1(G.a[u]), w);
         c2[u] = shape == kShapeGeneric || shape == kShapePhase || shape == kShapeTurn ? s.p(f_p2(G.b[u]), w) : ~0u;
+      }
+      if (shape == kShapeOmega) {   // target-bit-only eighth turns; planes untouched
+        for (int u = 0; u < kBsGroup; ++u) {
+          if (f_op(G.a[u]) != kBsOmega) return *why = "non-omega op in an OMEGA group", false;
+          if (f_p0(G.a[u]) != nq || f_p1(G.a[u]) != nq || f_p2(G.b[u]) != nq)
+            return *why = "controlled op in an OMEGA group", false;
+          for (int j = 0; j < 32; ++j)
+            if ((tv[u] >> j) & 1u)
+              s.omega[(size_t)w * 32 + j] = (uint8_t)((s.omega[(size_t)w * 32 + j] + f_k(G.a[u])) & 7u);
+        }
+        continue;
       }
       if (shape == kShapeTurn) {
         for (int u = 0; u < kBsGroup; ++u) {
@@ -97,7 +145,7 @@ bool apply_groups(State& s, const std::vector<BsGroup>& groups, uint32_t nq, std
         }
         continue;
       }
-      if (shape > kShapePhase) return *why = "unknown shape", false;
+      if (shape > kShapeOmega) return *why = "unknown shape", false;
       for (int u = 0; u < kBsGroup; ++u) {
         const uint32_t cond = c0[u] & c1[u] & c2[u];
         if (shape != kShapeGeneric && shape != kShapePhase && f_op(G.a[u]) != kBsFlip)
