@@ -303,6 +303,9 @@ typedef struct srv_stats {
   uint64_t items;           /* segments executed */
   uint64_t bitslice_runs;   /* fused runs that took the bit-sliced form */
   uint64_t pool_used_bytes, pool_peak_bytes;
+  double host_ms;           /* wall time in srv_tick outside the wait for the GPU */
+  double wait_ms;           /* wall time srv_tick waited for the GPU */
+  double group_ms;          /* of host_ms: grouping fused runs for the bit-sliced form */
 } srv_stats;
 
 typedef struct srv_t srv_t;

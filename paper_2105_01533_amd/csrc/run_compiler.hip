@@ -1,10 +1,11 @@
 // Host-side compilation of phase/permutation runs (see run_compiler.h).
 #include "run_compiler.h"
 
+#include "host_pool.h"
+
 #include <algorithm>
 #include <cmath>
 #include <cstring>
-#include <thread>
 
 namespace sparsesim {
 
@@ -68,21 +69,17 @@ uint64_t turn_of(const double2& m) {
 uint8_t word_bit(uint32_t q) { return (uint8_t)(1u << (q >> 5)); }
 
 // Run f(begin, end, part) over up to kHostThreads contiguous parts of [0, n),
-// each at least min_part long, on host threads (part 0 on the caller's).
-constexpr unsigned kHostThreads = 8;
+// each at least min_part long, on the host thread pool.
+constexpr unsigned kHostThreads = HostPool::kMaxThreads;
 template <class F>
 void parallel_parts(size_t n, size_t min_part, F&& f) {
-  const unsigned hw = std::max(1u, std::thread::hardware_concurrency());
-  const size_t parts = std::min<size_t>(std::min(kHostThreads, hw), n / std::max<size_t>(min_part, 1));
+  HostPool& pool = HostPool::get();
+  const size_t parts = std::min<size_t>(pool.threads(), n / std::max<size_t>(min_part, 1));
   if (parts <= 1) {
     f(0, n, 0);
     return;
   }
-  std::vector<std::thread> th;
-  th.reserve(parts - 1);
-  for (size_t p = 1; p < parts; ++p) th.emplace_back([&, p]() { f(n * p / parts, n * (p + 1) / parts, p); });
-  f(0, n / parts, 0);
-  for (auto& t : th) t.join();
+  pool.run(parts, [&](size_t p) { f(n * p / parts, n * (p + 1) / parts, p); });
 }
 
 }  // namespace

@@ -23,6 +23,7 @@
 #include <vector>
 
 #include "../../include/sparsesim.h"
+#include "host_pool.h"
 #include "run_compiler.h"
 #include "sim_internal.h"
 
@@ -145,6 +146,7 @@ struct Request {
   std::vector<sim_gate> gates;
   std::vector<size_t> mono_op;        // MONO ordinal -> op index
   RunCompiler rc;
+  bool compiled = false;              // descriptors and bit-sliced ops built (at admission)
   int32_t state = SRV_QUEUED;
   int32_t error = SIM_OK;
   // device placement
@@ -273,7 +275,24 @@ int finish(srv_t* s, Request& r, int32_t state, int32_t err) {
   return SIM_OK;
 }
 
+// Descriptors and bit-sliced ops of a request's circuit.
+void compile_request(Request& r) {
+  for (size_t i = 0; i < r.gates.size(); ++i)
+    if (r.gates[i].op == SIM_OP_MONO) {
+      r.rc.descs.push_back(mono_desc(r.gates[i]));
+      r.mono_op.push_back(i);
+    }
+  if (r.cfg.mono_mode != SIM_MONO_DIRECT) r.rc.compile(r.cfg.n_qubits);
+  else r.rc.n_qubits = r.cfg.n_qubits;
+  r.compiled = true;
+}
+
+// Admission uploads read from these (and from the request and the pinned
+// control words), which outlive the copies.
+const double kUnitAmp[2] = {1.0, 0.0};
+
 int admit(srv_t* s) {
+  std::vector<Request*> fresh;
   while (!s->queue.empty() && !s->free_slots.empty()) {
     Request& r = *s->reqs[s->queue.front()];
     size_t off;
@@ -303,15 +322,16 @@ int admit(srv_t* s) {
     s->h_ctl[r.slot] = c;
     SRV_HIP(hipMemcpyAsync(&s->d_ctl[r.slot], &s->h_ctl[r.slot], sizeof(SlotCtl), hipMemcpyHostToDevice,
                            s->stream));
-    const double one[2] = {1.0, 0.0};
     SRV_HIP(hipMemcpyAsync(r.buf[0].key_lo, &r.basis.lo, 8, hipMemcpyHostToDevice, s->stream));
     if (wide) SRV_HIP(hipMemcpyAsync(r.buf[0].key_hi, &r.basis.hi, 8, hipMemcpyHostToDevice, s->stream));
-    SRV_HIP(hipMemcpyAsync(r.buf[0].amp, one, 16, hipMemcpyHostToDevice, s->stream));
-    SRV_HIP(hipStreamSynchronize(s->stream));   // the host sources above are on the stack
+    SRV_HIP(hipMemcpyAsync(r.buf[0].amp, kUnitAmp, 16, hipMemcpyHostToDevice, s->stream));
     r.state = SRV_RUNNING;
     s->running.push_back(&r);
     s->stats.admitted++;
+    if (!r.compiled) fresh.push_back(&r);
   }
+  // Newly admitted circuits are compiled on the host thread pool.
+  HostPool::get().run(fresh.size(), [&](size_t k) { compile_request(*fresh[k]); });
   return SIM_OK;
 }
 
@@ -397,15 +417,8 @@ int srv_submit(srv_t* s, const sim_config* cfg, const sim_gate* gates, size_t n,
   r->basis = basis;
   r->gates.assign(gates, gates + n);
   std::string why;
-  for (size_t i = 0; i < n; ++i) {
+  for (size_t i = 0; i < n; ++i)
     if (!gate_valid(cfg->n_qubits, gates[i], &why)) return sfail(SIM_E_ARG, "op " + std::to_string(i) + ": " + why);
-    if (gates[i].op == SIM_OP_MONO) {
-      r->rc.descs.push_back(mono_desc(gates[i]));
-      r->mono_op.push_back(i);
-    }
-  }
-  if (cfg->mono_mode != SIM_MONO_DIRECT) r->rc.compile(cfg->n_qubits);
-  else r->rc.n_qubits = cfg->n_qubits;
   r->id = s->next_id++;
   *id = r->id;
   s->queue.push_back(r->id);
@@ -414,8 +427,22 @@ int srv_submit(srv_t* s, const sim_config* cfg, const sim_gate* gates, size_t n,
   return SIM_OK;
 }
 
+namespace {
+double ms_since(std::chrono::steady_clock::time_point t0) {
+  return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+}
+}  // namespace
+
 int srv_tick(srv_t* s, uint32_t* running, uint32_t* queued) {
   if (!s) return sfail(SIM_E_ARG, "null handle");
+  const auto t_tick = std::chrono::steady_clock::now();
+  const double wait0 = s->stats.wait_ms;
+  struct HostTime {
+    srv_t* s;
+    std::chrono::steady_clock::time_point t0;
+    double wait0;
+    ~HostTime() { s->stats.host_ms += ms_since(t0) - (s->stats.wait_ms - wait0); }
+  } host_time{s, t_tick, wait0};
   int rc = admit(s);
   if (rc) return rc;
   // Assemble the work list.
@@ -426,16 +453,49 @@ int srv_tick(srv_t* s, uint32_t* running, uint32_t* queued) {
   size_t arena_used = 0;
   std::vector<Request*> mono, u2, meas;
   std::vector<BItem> mono_items, u2_items, meas_items;
-  std::vector<BsGroup> grp;
   std::vector<Request*> done_now;
-  for (Request* r : s->running) {
+  // Every request's next segment; the fused runs that take the bit-sliced
+  // form are grouped on the host thread pool, one request per task (runs of
+  // different requests are independent).
+  struct Seg {
+    Request* r;
+    SegKind k;
     size_t b = 0, len = 0, op = 0;
-    const SegKind k = next_segment(s, *r, &b, &len, &op);
-    r->seg = k;
-    if (k == SEG_NONE) {
+    bool bsl = false;
+    BsRun br{};
+    std::vector<BsGroup> grp;
+  };
+  std::vector<Seg> segs;
+  segs.reserve(s->running.size());
+  std::vector<size_t> to_group;
+  for (Request* r : s->running) {
+    Seg sg{r, SEG_NONE};
+    sg.k = next_segment(s, *r, &sg.b, &sg.len, &sg.op);
+    r->seg = sg.k;
+    if (sg.k == SEG_NONE) {
       done_now.push_back(r);
       continue;
     }
+    if (sg.k == SEG_MONO) {
+      sg.bsl = r->rc.run_params(sg.b, sg.len, r->cfg.mono_mode, r->cfg.bs_min_gates, &sg.br);
+      if (sg.bsl) to_group.push_back(segs.size());
+    }
+    segs.push_back(std::move(sg));
+  }
+  {
+    const auto t_g = std::chrono::steady_clock::now();
+    HostPool::get().run(to_group.size(), [&](size_t t) {
+      Seg& sg = segs[to_group[t]];
+      sg.r->rc.group(sg.b, sg.len, sg.grp);
+    });
+    s->stats.group_ms += ms_since(t_g);
+  }
+  for (Seg& sg : segs) {
+    Request* r = sg.r;
+    const SegKind k = sg.k;
+    size_t b = sg.b, len = sg.len;
+    const size_t op = sg.op;
+    std::vector<BsGroup>& grp = sg.grp;
     BItem it{};
     it.in = r->buf[r->cur];
     it.out = r->buf[r->cur ^ 1];
@@ -445,8 +505,8 @@ int srv_tick(srv_t* s, uint32_t* running, uint32_t* queued) {
     it.nnz = r->nnz;
     it.cap = r->cfg.capacity;
     if (k == SEG_MONO) {
-      BsRun br;
-      const bool bsl = r->rc.run_params(b, len, r->cfg.mono_mode, r->cfg.bs_min_gates, &br);
+      BsRun br = sg.br;
+      const bool bsl = sg.bsl;
       uint32_t flags = 0;
       for (size_t q = b; q < b + len; ++q) {
         if (r->rc.descs[q].flags & kHasPhase) flags |= kRunPhase;
@@ -458,8 +518,12 @@ int srv_tick(srv_t* s, uint32_t* running, uint32_t* queued) {
       size_t bytes = 0, keep = len;
       for (;;) {
         if (bsl) {
-          grp.clear();
-          r->rc.group(b, keep, grp);
+          if (keep < len) {   // the whole run did not fit: regroup a prefix
+            grp.clear();
+            const auto t_g = std::chrono::steady_clock::now();
+            r->rc.group(b, keep, grp);
+            s->stats.group_ms += ms_since(t_g);
+          }
           bytes = grp.size() * sizeof(BsGroup);
         } else {
           bytes = keep * sizeof(MonoDesc);
@@ -579,7 +643,11 @@ int srv_tick(srv_t* s, uint32_t* running, uint32_t* queued) {
     for (Request* r : s->running) max_slot = std::max(max_slot, r->slot);
     SRV_HIP(hipMemcpyAsync(s->h_ctl, s->d_ctl, (size_t)(max_slot + 1) * sizeof(SlotCtl), hipMemcpyDeviceToHost,
                            s->stream));
-    SRV_HIP(hipStreamSynchronize(s->stream));
+    {
+      const auto t_w = std::chrono::steady_clock::now();
+      SRV_HIP(hipStreamSynchronize(s->stream));
+      s->stats.wait_ms += ms_since(t_w);
+    }
     s->stats.ticks++;
     s->stats.items += nm + nu + nq;
     // Fold the results back.

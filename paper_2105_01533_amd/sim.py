@@ -324,10 +324,11 @@ class srv_config(ctypes.Structure):
 class srv_stats(ctypes.Structure):
     _fields_ = [(f, ctypes.c_uint64) for f in (
         "submitted", "admitted", "completed", "failed", "ticks", "items", "bitslice_runs",
-        "pool_used_bytes", "pool_peak_bytes")]
+        "pool_used_bytes", "pool_peak_bytes")] + [(f, ctypes.c_double) for f in ("host_ms", "wait_ms", "group_ms")]
 
     def as_dict(self):
-        return {f: int(getattr(self, f)) for f, _ in self._fields_}
+        return {f: (round(getattr(self, f), 3) if t is ctypes.c_double else int(getattr(self, f)))
+                for f, t in self._fields_}
 
 
 def _srv_sigs():
