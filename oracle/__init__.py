@@ -66,7 +66,9 @@ def lib():
         L.orc_probabilities.argtypes = [vp, ctypes.c_uint, ctypes.POINTER(f64), ctypes.POINTER(f64)]
         L.orc_totals.argtypes = [vp, ctypes.POINTER(Totals)]
         L.orc_monomial_samples.argtypes = [vp, u64, vp, vp, vp, u64]
-        for f in ("orc_set_basis", "orc_import", "orc_run", "orc_probabilities", "orc_monomial_samples"):
+        L.orc_run_commuting.argtypes = [vp, vp, u64, vp, u64, ctypes.POINTER(u64), vp, ctypes.POINTER(u64)]
+        for f in ("orc_set_basis", "orc_import", "orc_run", "orc_probabilities", "orc_monomial_samples",
+                  "orc_run_commuting"):
             getattr(L, f).restype = i32
         _lib = L
     return _lib
@@ -120,6 +122,26 @@ class Oracle:
         if rc == -2:
             raise OracleError(f"zero-probability measurement at index {bad.value}")
         return outcomes[:n_meas], tr
+
+    def run_commuting(self, ops: np.ndarray):
+        """Apply op records through the gate-commuting queues (Sec. 3.3).
+        Returns (outcomes, log): log holds the op records sent to the state,
+        in order (the queues' contents as they were executed)."""
+        ops = np.ascontiguousarray(ops)
+        assert ops.dtype.itemsize == 48
+        n_meas = int(np.count_nonzero(ops["kind"] == 12))
+        outcomes = np.full(max(n_meas, 1), -1, dtype=np.int32)
+        log = np.zeros(max(len(ops), 1), dtype=ops.dtype)
+        n_log = ctypes.c_uint64(0)
+        bad = ctypes.c_uint64(0)
+        rc = lib().orc_run_commuting(self.h, _ptr(ops), len(ops), _ptr(log), len(log), ctypes.byref(n_log),
+                                     _ptr(outcomes), ctypes.byref(bad))
+        if rc == -1:
+            raise OracleError(f"invalid op at index {bad.value}")
+        if rc == -2:
+            raise OracleError(f"zero-probability measurement at index {bad.value}")
+        assert n_log.value <= len(log), "applied-gate log longer than the input"
+        return outcomes[:n_meas], log[:n_log.value]
 
     @property
     def nnz(self) -> int:

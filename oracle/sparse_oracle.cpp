@@ -35,6 +35,12 @@
 //   * complex products are (a.re*b.re - a.im*b.im, a.re*b.im + a.im*b.re),
 //     evaluated as written with no fused multiply-add.
 //
+// Gate commuting (Sec. 3.3, Fig. 1): orc_run_commuting keeps, per qubit,
+// queues of H, Rx and Ry gates that are pending after the phase/permutation
+// queue, and commutes each incoming gate through them where a simple relation
+// holds; otherwise it executes the queues of the qubits involved.  Its
+// readings are listed at that function.
+//
 // Built with g++ -O2 -ffp-contract=off.
 #include <algorithm>
 #include <cmath>
@@ -432,6 +438,180 @@ int orc_run(void* h, const OpRecord* ops, uint64_t n, int queued, Trace* trace, 
   }
   apply_monomial_run(o, run);
   return 0;
+}
+
+// ---- gate commuting (Sec. 3.3) ------------------------------------------------
+//
+// Pending gates, in the order they act after the state: the phase/permutation
+// queue Q, then on each qubit q an H (if h[q]), then Rx(rx[q]), then Ry(ry[q])
+// (the figure's rows, applied bottom-up).  An incoming gate G is moved ahead of
+// the pending gates of its qubits by these relations; where none applies, the
+// gates pending on G's qubits are executed first (Q as a whole, then each such
+// qubit's H, Rx, Ry), and G is then queued or applied.
+//   * H on q:   H Ry(a) = Ry(-a) H, then H H = I (the H queue bit toggles);
+//               an Rx pending on q has no such relation -> execute q first.
+//   * Rx on q:  joins Rx(a): Rx(b) Rx(a) = Rx(a + b); an Ry pending on q sits
+//               after it -> execute q first.
+//   * Ry on q:  joins Ry(a): Ry(a + b).
+//     A joined angle of exactly 0 leaves no gate.
+//   * phase/permutation gate: on a qubit with H pending, an X or Z (possibly
+//     controlled) whose target is that qubit becomes Z or X (X H = H Z and
+//     Z H = H X); any other pending gate on one of its qubits -> execute them
+//     first; the gate then joins Q.
+//   * a branching gate with controls or a skip cap, and a measurement: execute
+//     the gates pending on its qubits, then apply it (a measurement also needs
+//     Q, which is executed with them).
+//   * at the end everything pending is executed (qubits in ascending order).
+// Every gate applied to the state is appended to `log` (when given), in order.
+namespace {
+
+struct Commuter {
+  Oracle& o;
+  std::vector<uint8_t> h, has_rx, has_ry;
+  std::vector<double> rx, ry;
+  std::vector<OpRecord> q;
+  std::vector<OpRecord>* log;
+
+  Commuter(Oracle& o_, std::vector<OpRecord>* log_)
+      : o(o_), h(o_.n_qubits, 0), has_rx(o_.n_qubits, 0), has_ry(o_.n_qubits, 0), rx(o_.n_qubits, 0.0),
+        ry(o_.n_qubits, 0.0), log(log_) {}
+
+  static OpRecord single(uint32_t kind, unsigned t, double param) {
+    OpRecord r{};
+    r.kind = kind;
+    r.target = t;
+    r.param = param;
+    r.forced = -1;
+    return r;
+  }
+  void record(const OpRecord& r) {
+    if (log) log->push_back(r);
+  }
+  void apply_u2(const OpRecord& r) {
+    record(r);
+    o.tot.updates += o.psi.size();
+    o.tot.u2_applied++;
+    apply_branching(o, r);
+    note_peak(o);
+  }
+  void execute_q() {
+    std::vector<Monomial> run;
+    for (const OpRecord& r : q) {
+      record(r);
+      o.tot.updates += o.psi.size();
+      o.tot.mono_gates++;
+      run.push_back(monomial_of(r));
+    }
+    apply_monomial_run(o, run);
+    q.clear();
+  }
+  bool pending(unsigned t) const { return h[t] || has_rx[t] || has_ry[t]; }
+  // Execute Q and the gates pending on the qubits in `qs` (ascending).
+  void execute(std::vector<unsigned> qs) {
+    std::sort(qs.begin(), qs.end());
+    qs.erase(std::unique(qs.begin(), qs.end()), qs.end());
+    execute_q();
+    for (unsigned t : qs) {
+      if (h[t]) apply_u2(single(kH, t, 0.0));
+      if (has_rx[t]) apply_u2(single(kRx, t, rx[t]));
+      if (has_ry[t]) apply_u2(single(kRy, t, ry[t]));
+      h[t] = has_rx[t] = has_ry[t] = 0;
+      rx[t] = ry[t] = 0.0;
+    }
+  }
+  static std::vector<unsigned> qubits_of(const OpRecord& r) {
+    std::vector<unsigned> qs{r.target};
+    for (unsigned c = 0; c < 128; ++c)
+      if (bit_of(Label{r.ctrl_lo, r.ctrl_hi}, c)) qs.push_back(c);
+    return qs;
+  }
+  void join(uint8_t& has, double& angle, double add) {
+    const double a = has ? angle + add : add;
+    has = a != 0.0;
+    angle = has ? a : 0.0;
+  }
+};
+
+}  // namespace
+
+// Returns 0, -1 (invalid op at *bad) or -2 (measurement with no valid outcome
+// at *bad).  n_log receives the number of applied gates (all of them are
+// written when log_cap allows).
+int orc_run_commuting(void* hnd, const OpRecord* ops, uint64_t n, OpRecord* log, uint64_t log_cap, uint64_t* n_log,
+                      int32_t* outcomes, uint64_t* bad) {
+  Oracle& o = *static_cast<Oracle*>(hnd);
+  std::vector<OpRecord> applied;
+  Commuter c(o, &applied);
+  uint64_t n_meas = 0;
+  int rc = 0;
+  for (uint64_t i = 0; i < n && rc == 0; ++i) {
+    const OpRecord& op = ops[i];
+    if (!op_valid(o, op)) {
+      c.execute({});
+      if (bad) *bad = i;
+      rc = -1;
+      break;
+    }
+    const unsigned t = op.target;
+    const bool plain = op.ctrl_lo == 0 && op.ctrl_hi == 0 && op.cap == 0;
+    if (is_monomial(op.kind)) {
+      const std::vector<unsigned> qs = Commuter::qubits_of(op);
+      std::vector<unsigned> hard;
+      for (unsigned qb : qs) {
+        const bool swappable = qb == t && (op.kind == kX || op.kind == kZ) && !c.has_rx[qb] && !c.has_ry[qb];
+        if (c.has_rx[qb] || c.has_ry[qb] || (c.h[qb] && !swappable)) hard.push_back(qb);
+      }
+      if (!hard.empty()) c.execute(hard);
+      OpRecord g = op;
+      if (c.h[t]) g.kind = op.kind == kX ? kZ : kX;   // X H = H Z, Z H = H X
+      c.q.push_back(g);
+    } else if (op.kind == kH && plain) {
+      if (c.has_rx[t]) {
+        c.execute({t});
+        c.h[t] = 1;
+      } else {
+        if (c.has_ry[t]) c.ry[t] = -c.ry[t];
+        c.h[t] ^= 1;
+      }
+    } else if (op.kind == kRx && plain) {
+      if (c.has_ry[t]) c.execute({t});
+      c.join(c.has_rx[t], c.rx[t], op.param);
+    } else if (op.kind == kRy && plain) {
+      c.join(c.has_ry[t], c.ry[t], op.param);
+    } else if (is_branching(op.kind)) {
+      // Sent to the state as is; a capped gate may then be skipped there.
+      c.execute(Commuter::qubits_of(op));
+      if (op.cap != 0 && 2 * o.psi.size() > op.cap) {
+        c.record(op);
+        o.tot.u2_skipped++;
+      } else {
+        c.apply_u2(op);
+      }
+    } else {  // measurement
+      c.execute({t});
+      c.record(op);
+      o.tot.measures++;
+      double p0, p1;
+      const int r = measure(o, t, op.param, op.forced, &p0, &p1);
+      if (r < 0) {
+        if (bad) *bad = i;
+        rc = -2;
+        break;
+      }
+      if (outcomes) outcomes[n_meas] = r;
+      n_meas++;
+    }
+  }
+  if (rc == 0) {
+    std::vector<unsigned> all;
+    for (unsigned qb = 0; qb < o.n_qubits; ++qb)
+      if (c.pending(qb)) all.push_back(qb);
+    c.execute(all);
+  }
+  if (n_log) *n_log = applied.size();
+  if (log)
+    for (uint64_t k = 0; k < applied.size() && k < log_cap; ++k) log[k] = applied[k];
+  return rc;
 }
 
 // Export sorted ascending by (hi, lo).  Returns nnz; writes min(nnz, cap).
