@@ -195,6 +195,24 @@ int sim_gates_from_ops(const sim_op* ops, size_t n, sim_gate* out);
  */
 int sim_apply_gates(sim_t* s, const sim_gate* gates, size_t n, int32_t* outcomes, sim_stats* stats);
 
+/*
+ * Gate commuting (Sec. 3.3, Fig. 1), host only.  Passes n standard-gate
+ * records through per-qubit queues of H, Rx and Ry gates that act after the
+ * phase/permutation queue, and writes the ops the queues send on, in order,
+ * to out (at most n of them; *n_out receives the count).  Relations used:
+ * H Ry(a) = Ry(-a) H and H H = I for an incoming H; Rx and Ry angles add up
+ * (an exact 0 sum leaves no gate); an incoming X or Z, possibly controlled,
+ * whose target has an H pending becomes Z or X.  Where no relation applies,
+ * the phase/permutation queue and then the H, Rx, Ry pending on the op's
+ * qubits are sent first (qubits in ascending order); controlled or capped
+ * branching ops and measurements are sent after that as they are; at the end
+ * everything pending is sent.  Applying the output (sim_apply_ops) simulates
+ * the circuit with the paper's queues; a capped op is then skipped or not
+ * where it is applied.  SIM_E_ARG for an invalid op (nothing written);
+ * SIM_E_BUFFER if cap is too small (*n_out set).
+ */
+int sim_commute_ops(const sim_op* in, size_t n, uint32_t n_qubits, sim_op* out, size_t cap, size_t* n_out);
+
 /* sim_gates_from_ops followed by sim_apply_gates. */
 int sim_apply_ops(sim_t* s, const sim_op* ops, size_t n, int32_t* outcomes, sim_stats* stats);
 

@@ -5,7 +5,12 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <string>
+
 namespace sparsesim {
+
+// Record an error for sim_last_error; returns code (sim_api.hip).
+int set_error(int code, const std::string& msg);
 
 constexpr uint64_t kEmptySlot = ~0ull;   // hash index: free slot
 constexpr uint32_t kNoPartner = ~0u;     // partner look-up miss

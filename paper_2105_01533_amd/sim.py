@@ -79,6 +79,7 @@ def _load():
         "sim_set_basis": (i32, [vp, sim_key]),
         "sim_import_state": (i32, [vp, vp, vp, u64]),
         "sim_gates_from_ops": (i32, [vp, sz, vp]),
+        "sim_commute_ops": (i32, [vp, sz, ctypes.c_uint32, vp, sz, ctypes.POINTER(sz)]),
         "sim_apply_gates": (i32, [vp, vp, sz, vp, vp]),
         "sim_apply_ops": (i32, [vp, vp, sz, vp, vp]),
         "sim_measure": (i32, [vp, u32, f64, i32, ctypes.POINTER(i32), ctypes.POINTER(f64)]),
@@ -153,6 +154,18 @@ def sim_gates_from_ops(ops: np.ndarray) -> np.ndarray:
     out = np.zeros(len(ops), GATE_DTYPE)
     _check(_lib.sim_gates_from_ops(_ptr(ops), len(ops), _ptr(out)), "sim_gates_from_ops")
     return out
+
+
+def sim_commute_ops(ops: np.ndarray, n_qubits: int) -> np.ndarray:
+    """Gate commuting (Sec. 3.3): the op records the per-qubit H/Rx/Ry queues
+    send on, in order (at most len(ops) of them)."""
+    ops = np.ascontiguousarray(ops)
+    assert ops.dtype.itemsize == 48
+    out = np.zeros(max(len(ops), 1), ops.dtype)
+    n = ctypes.c_size_t(0)
+    _check(_lib.sim_commute_ops(_ptr(ops), len(ops), n_qubits, _ptr(out), len(out), ctypes.byref(n)),
+           "sim_commute_ops")
+    return out[:n.value]
 
 
 def _n_meas_gates(gates):
@@ -303,11 +316,14 @@ class Simulator:
         return sim_export_state(self.h, sort)
 
 
-def run_workload(w, **kw):
-    """Simulate a workloads.Workload from its basis state; returns (sim, outcomes, stats)."""
+def run_workload(w, commute: bool = False, **kw):
+    """Simulate a workloads.Workload from its basis state; returns (sim,
+    outcomes, stats).  commute: pass the ops through the gate-commuting queues
+    first (sim_commute_ops)."""
     s = Simulator(w.n_qubits, w.capacity, w.eps, **kw)
     s.set_basis(*w.basis)
-    _, outcomes, stats = s.apply_ops(w.ops)
+    ops = sim_commute_ops(w.ops, w.n_qubits) if commute else w.ops
+    _, outcomes, stats = s.apply_ops(ops)
     return s, outcomes, stats
 
 
