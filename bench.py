@@ -162,6 +162,31 @@ def serving_bench(sim, W, requests=128, max_log2=18, max_gates=50_000, budget_gi
             "results_max_abs_diff": worst, "results_label_mismatches": mism}
 
 
+def commuting_bench(sim, W, n=64, superposed=20, blocks=2000):
+    """Gate commuting (Sec. 3.3) on phase-oracle blocks (H, multi-controlled
+    X, H on a target: a controlled Z): the same circuit applied as is and
+    after sim_commute_ops, from its basis state, on the GPU."""
+    import torch
+
+    w = W.phase_oracle_blocks(n=n, superposed=superposed, blocks=blocks)
+    out = {"workload": f"{w.name}: H on {superposed} qubits (2^{superposed} entries), {blocks} blocks of "
+                       f"H / multi-controlled X / H on a random target"}
+    for name, commute in (("plain", False), ("commuting", True)):
+        s = sim.Simulator(w.n_qubits, w.capacity, w.eps)
+        t0 = time.perf_counter()
+        ops = sim.sim_commute_ops(w.ops, w.n_qubits) if commute else w.ops
+        s.set_basis(*w.basis)
+        _, _, st = s.apply_ops(ops)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        s.close()
+        out[name] = {"ms": round(1e3 * dt, 2), "ops_applied": int(len(ops)), "u2_applied": st["u2_applied"],
+                     "peak_nnz": st["peak_nnz"], "updates": st["updates"]}
+        log(f"[bench] commuting {name}: {out[name]}")
+    out["speedup"] = round(out["plain"]["ms"] / out["commuting"]["ms"], 2)
+    return out
+
+
 def measured_traffic():
     """Per-launch HBM bytes of the fused pass from the committed counter runs
     (profiles/mono_pass_traffic.json), or None if the kernel sources changed
@@ -189,6 +214,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-sweep", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--no-commuting", action="store_true", help="skip the gate-commuting comparison")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run the 1 GiB reference copy kernel (for hardware byte-counter scaling) first")
     ap.add_argument("--serving-requests", type=int, default=128)
@@ -293,6 +319,8 @@ def main():
     if not args.no_serving:
         out["serving"] = serving_bench(sim, W, args.serving_requests, args.serving_max_log2,
                                        args.serving_max_gates)
+    if not args.no_commuting:
+        out["commuting"] = commuting_bench(sim, W)
     if not args.no_cpu_baseline:
         log("[bench] cpu baseline (oracle) ...")
         out["cpu_baseline"] = cpu_baseline(w, args.cpu_seconds)

@@ -255,6 +255,29 @@ def pauli_exp(c: Circuit, qubits: list[int], paulis: list[str], theta: float):
             c.gate(K_S, q)
 
 
+def phase_oracle_blocks(seed: int = 5151, n: int = 64, superposed: int = 20, blocks: int = 2000,
+                        ctrl_max: int = 3, eps: float = 1e-20) -> Workload:
+    """H on q0..q(superposed-1), then `blocks` phase-oracle blocks: H on a
+    target t, an X on t with 1..ctrl_max controls, H on t (together a
+    controlled Z), each followed with probability 1/4 by an X or Z on a random
+    qubit.  Targets and controls are uniform over all qubits."""
+    rng = SplitMix64(seed)
+    c = Circuit()
+    for q in range(superposed):
+        c.h(q)
+    for _ in range(blocks):
+        k = 1 + rng.randint(ctrl_max)
+        qs = rng.distinct(n, k + 1)
+        t, ctrls = qs[-1], qs[:-1]
+        c.h(t)
+        c.x(t, ctrls)
+        c.h(t)
+        if rng.randint(4) == 0:
+            c.gate((K_X, K_Z)[rng.randint(2)], rng.randint(n))
+    return Workload(f"phase_oracle_{n}q_{blocks}b", n, eps, c.array(), capacity=1 << (superposed + 1),
+                    meta={"seed": seed, "superposed": superposed, "blocks": blocks})
+
+
 def config3(seed: int = seed_for(3), n: int = 40, set_bits: int = 20, terms: int = 500,
             locality: int = 4, capacity: int = 1 << 22) -> Workload:
     """Chemistry-like Trotter step: start from the basis state with q0..q19 set,

@@ -345,6 +345,13 @@ def test_commuting_random(sim, n, seed):
     check_commuting(sim, w, mono_mode=sim.SIM_MONO_DIRECT)
 
 
+def test_commuting_phase_oracle_blocks(sim):
+    w = W.phase_oracle_blocks(7, n=100, superposed=10, blocks=400)
+    check_vs_oracle(sim, w)
+    g, st = check_commuting(sim, w)
+    assert st["u2_applied"] <= 10 + 2   # the blocks' H pairs never reach the state
+
+
 def test_commuting_trotter_and_adder(sim):
     for w in (W.config3(9, terms=18), W.config1(4, w=8, adds=6, n=32)):
         check_commuting(sim, w)
