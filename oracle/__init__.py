@@ -67,8 +67,9 @@ def lib():
         L.orc_totals.argtypes = [vp, ctypes.POINTER(Totals)]
         L.orc_monomial_samples.argtypes = [vp, u64, vp, vp, vp, u64]
         L.orc_run_commuting.argtypes = [vp, vp, u64, vp, u64, ctypes.POINTER(u64), vp, ctypes.POINTER(u64)]
+        L.orc_run_pauli.argtypes = [vp, vp, u64, vp, ctypes.POINTER(u64)]
         for f in ("orc_set_basis", "orc_import", "orc_run", "orc_probabilities", "orc_monomial_samples",
-                  "orc_run_commuting"):
+                  "orc_run_commuting", "orc_run_pauli"):
             getattr(L, f).restype = i32
         _lib = L
     return _lib
@@ -143,6 +144,19 @@ class Oracle:
         assert n_log.value <= len(log), "applied-gate log longer than the input"
         return outcomes[:n_meas], log[:n_log.value]
 
+    def run_pauli(self, terms: np.ndarray, trace: bool = False):
+        """Apply Pauli-exponential records exp(-i theta P) in order (64-byte
+        records: x, z, ctrl masks as lo/hi pairs, theta, cap).  Returns the
+        trace or None."""
+        terms = np.ascontiguousarray(terms)
+        assert terms.dtype.itemsize == 64
+        tr = np.zeros(len(terms), dtype=TRACE_DTYPE) if trace else None
+        bad = ctypes.c_uint64(0)
+        rc = lib().orc_run_pauli(self.h, _ptr(terms), len(terms), _ptr(tr) if trace else None, ctypes.byref(bad))
+        if rc == -1:
+            raise OracleError(f"invalid Pauli term at index {bad.value}")
+        return tr
+
     @property
     def nnz(self) -> int:
         return int(lib().orc_nnz(self.h))
@@ -186,3 +200,11 @@ def run_workload(w, queued: bool = True, trace: bool = False):
     o.set_basis(*w.basis)
     outcomes, tr = o.run(w.ops, queued=queued, trace=trace)
     return o, outcomes, tr
+
+
+def run_pauli_workload(w, trace: bool = False):
+    """Run a workloads.PauliWorkload from its basis state; returns (oracle, trace)."""
+    o = Oracle(w.n_qubits, w.eps)
+    o.set_basis(*w.basis)
+    tr = o.run_pauli(w.terms, trace=trace)
+    return o, tr

@@ -35,6 +35,10 @@
 //   * complex products are (a.re*b.re - a.im*b.im, a.re*b.im + a.im*b.re),
 //     evaluated as written with no fused multiply-add.
 //
+// Pauli exponentials exp(-i theta P), controlled or not (Sec. 3's intrinsic
+// operations): orc_run_pauli, from the closed form cos(theta) I - i sin(theta) P;
+// its readings are listed at that function.
+//
 // Gate commuting (Sec. 3.3, Fig. 1): orc_run_commuting keeps, per qubit,
 // queues of H, Rx and Ry gates that are pending after the phase/permutation
 // queue, and commutes each incoming gate through them where a simple relation
@@ -612,6 +616,128 @@ int orc_run_commuting(void* hnd, const OpRecord* ops, uint64_t n, OpRecord* log,
   if (log)
     for (uint64_t k = 0; k < applied.size() && k < log_cap; ++k) log[k] = applied[k];
   return rc;
+}
+
+// ---- Pauli exponentials (Sec. 3: an intrinsic operation with at most two ----
+// nonzeros per row) -------------------------------------------------------------
+//
+// exp(-i theta P) for a Pauli string P, optionally controlled.  P is given by
+// two masks: P acts as X on the qubits in x only, Y on those in both x and z,
+// Z on those in z only, and as the identity elsewhere.  Since P^2 = I the
+// operator is cos(theta) I - i sin(theta) P, and P|b> = c(b)|b xor x> with c(b)
+// the product of the single-qubit entries of Sec. 2.1's X, Y, Z in the column
+// of b's bit.  The oracle applies exactly that: every label b (with the
+// controls set) sends cos(theta) a_b to b and -i sin(theta) c(b) a_b to b xor x.
+// Readings: a term with x != 0 is a branching operation (T_eps afterwards, the
+// cap rule 2*nnz > cap skips it); a term with x == 0 is diagonal, a phase gate
+// that never prunes and ignores the cap.
+namespace {
+
+struct PauliRecord {      // 64 bytes, little endian
+  uint64_t x_lo, x_hi, z_lo, z_hi, ctrl_lo, ctrl_hi;
+  double theta;
+  uint64_t cap;
+};
+static_assert(sizeof(PauliRecord) == 64, "Pauli record layout");
+
+// c(b): X = [[0,1],[1,0]], Y = [[0,-i],[i,0]], Z = [[1,0],[0,-1]], entry in
+// row (bit xor x-bit), column (bit).
+Amp pauli_coef(const PauliRecord& p, const Label& b, unsigned n_qubits) {
+  const Label x{p.x_lo, p.x_hi}, z{p.z_lo, p.z_hi};
+  Amp c{1.0, 0.0};
+  for (unsigned q = 0; q < n_qubits; ++q) {
+    const bool xq = bit_of(x, q), zq = bit_of(z, q), v = bit_of(b, q);
+    Amp e;
+    if (xq && zq)
+      e = v ? Amp{0.0, -1.0} : Amp{0.0, 1.0};   // Y|0> = i|1>, Y|1> = -i|0>
+    else if (xq)
+      e = Amp{1.0, 0.0};                          // X
+    else if (zq)
+      e = v ? Amp{-1.0, 0.0} : Amp{1.0, 0.0};     // Z
+    else
+      continue;
+    c = mul(c, e);
+  }
+  return c;
+}
+
+void accumulate(State& s, const Label& k, const Amp& a) {
+  auto r = s.emplace(k, a);
+  if (!r.second) r.first->second = add(r.first->second, a);
+}
+
+void apply_pauli_exp(Oracle& o, const PauliRecord& p) {
+  const Label ctrl{p.ctrl_lo, p.ctrl_hi};
+  const bool branching = p.x_lo != 0 || p.x_hi != 0;
+  const Amp cos_t{std::cos(p.theta), 0.0};
+  const Amp misin_t{0.0, -std::sin(p.theta)};     // -i sin(theta)
+  State out;
+  out.reserve(o.psi.size() * (branching ? 2 : 1));
+  for (const auto& kv : o.psi) {
+    const Label& b = kv.first;
+    if (!controls_set(b, ctrl)) {
+      accumulate(out, b, kv.second);
+      continue;
+    }
+    accumulate(out, b, mul(cos_t, kv.second));
+    const Label bx{b.lo ^ p.x_lo, b.hi ^ p.x_hi};
+    accumulate(out, bx, mul(mul(misin_t, pauli_coef(p, b, o.n_qubits)), kv.second));
+  }
+  if (branching) {
+    for (auto it = out.begin(); it != out.end();) {
+      if (drop(it->second, o.eps)) {
+        o.tot.pruned++;
+        o.tot.pruned_mass += it->second.re * it->second.re + it->second.im * it->second.im;
+        it = out.erase(it);
+      } else {
+        ++it;
+      }
+    }
+  }
+  o.psi.swap(out);
+}
+
+bool pauli_valid(const Oracle& o, const PauliRecord& p) {
+  Label lim{~0ull, ~0ull};
+  if (o.n_qubits < 128)
+    lim = o.n_qubits >= 64 ? Label{~0ull, o.n_qubits == 64 ? 0ull : ((1ull << (o.n_qubits - 64)) - 1)}
+                           : Label{(1ull << o.n_qubits) - 1, 0ull};
+  const uint64_t all_lo = p.x_lo | p.z_lo | p.ctrl_lo, all_hi = p.x_hi | p.z_hi | p.ctrl_hi;
+  if ((all_lo & ~lim.lo) || (all_hi & ~lim.hi)) return false;
+  if (((p.x_lo | p.z_lo) & p.ctrl_lo) || ((p.x_hi | p.z_hi) & p.ctrl_hi)) return false;
+  return std::isfinite(p.theta);
+}
+
+}  // namespace
+
+// Apply n Pauli-exponential terms in order.  trace (optional) as for orc_run
+// (applied = 0 for a skipped branching term).  Returns 0 or -1 (invalid term
+// at index *bad; the terms before it are applied).
+int orc_run_pauli(void* h, const PauliRecord* terms, uint64_t n, Trace* trace, uint64_t* bad) {
+  Oracle& o = *static_cast<Oracle*>(h);
+  for (uint64_t i = 0; i < n; ++i) {
+    const PauliRecord& p = terms[i];
+    if (!pauli_valid(o, p)) {
+      if (bad) *bad = i;
+      return -1;
+    }
+    Trace tr{o.psi.size(), 1, -1, 0.0, 0.0};
+    const bool branching = p.x_lo != 0 || p.x_hi != 0;
+    if (branching && p.cap != 0 && 2 * o.psi.size() > p.cap) {
+      tr.applied = 0;
+      o.tot.u2_skipped++;
+    } else {
+      o.tot.updates += o.psi.size();
+      if (branching)
+        o.tot.u2_applied++;
+      else
+        o.tot.mono_gates++;
+      apply_pauli_exp(o, p);
+      note_peak(o);
+    }
+    if (trace) trace[i] = tr;
+  }
+  return 0;
 }
 
 // Export sorted ascending by (hi, lo).  Returns nnz; writes min(nnz, cap).

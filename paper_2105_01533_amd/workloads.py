@@ -48,6 +48,15 @@ OP_DTYPE = np.dtype([
 ])
 assert OP_DTYPE.itemsize == 48
 
+# Pauli-exponential records ("Pauli terms"), exp(-i theta P): P acts as X on
+# the qubits in x only, Y on those in x and z, Z on those in z only; ctrl as
+# for op records; cap skips a term with x != 0 iff cap != 0 and 2*nnz > cap.
+PAULI_DTYPE = np.dtype([
+    ("x_lo", "<u8"), ("x_hi", "<u8"), ("z_lo", "<u8"), ("z_hi", "<u8"),
+    ("ctrl_lo", "<u8"), ("ctrl_hi", "<u8"), ("theta", "<f8"), ("cap", "<u8"),
+])
+assert PAULI_DTYPE.itemsize == 64
+
 MASK64 = (1 << 64) - 1
 
 
@@ -232,6 +241,31 @@ def config2(seed: int = seed_for(2), n: int = 100, h_qubits: int = 24, gates: in
                     meta={"seed": seed, "gates": gates, "h_qubits": h_qubits})
 
 
+def pauli_term(qubits, paulis, theta: float, ctrls=(), cap: int = 0) -> tuple:
+    """One PAULI_DTYPE record for exp(-i theta P), P = paulis[k] on qubits[k]
+    ("I", "X", "Y" or "Z"), controlled on ctrls."""
+    x = z = cm = 0
+    for q, p in zip(qubits, paulis):
+        if p in ("X", "Y"):
+            x |= 1 << q
+        if p in ("Z", "Y"):
+            z |= 1 << q
+    for q in ctrls:
+        cm |= 1 << q
+    return (x & MASK64, x >> 64, z & MASK64, z >> 64, cm & MASK64, cm >> 64, float(theta), int(cap))
+
+
+@dataclass
+class PauliWorkload:
+    name: str
+    n_qubits: int
+    eps: float
+    terms: np.ndarray             # PAULI_DTYPE records
+    capacity: int
+    basis: tuple[int, int] = (0, 0)
+    meta: dict = field(default_factory=dict)
+
+
 def pauli_exp(c: Circuit, qubits: list[int], paulis: list[str], theta: float):
     """exp(-i theta P) for a Pauli string P on distinct ascending qubits:
     basis change to Z (X: H; Y: S^dagger then H), CNOT parity ladder onto the
@@ -283,16 +317,58 @@ def config3(seed: int = seed_for(3), n: int = 40, set_bits: int = 20, terms: int
     """Chemistry-like Trotter step: start from the basis state with q0..q19 set,
     apply 500 factors exp(-i theta P) with P a random 4-local Pauli string over
     {X, Y, Z} and theta = 0.01 N(0, 1); prune |a|^2 < 1e-10."""
-    rng = SplitMix64(seed)
     c = Circuit()
-    for _ in range(terms):
-        qs = sorted(rng.distinct(n, locality))
-        ps = ["XYZ"[rng.randint(3)] for _ in qs]
-        theta = 0.01 * rng.normal()
+    for qs, ps, theta in _trotter_terms(seed, n, terms, locality):
         pauli_exp(c, qs, ps, theta)
     basis = (1 << set_bits) - 1
     return Workload(f"c3_trotter_{n}q", n, 1e-10, c.array(), capacity=capacity,
                     basis=(basis & MASK64, basis >> 64), meta={"seed": seed, "terms": terms})
+
+
+def _trotter_terms(seed: int, n: int, terms: int, locality: int):
+    rng = SplitMix64(seed)
+    out = []
+    for _ in range(terms):
+        qs = sorted(rng.distinct(n, locality))
+        ps = ["XYZ"[rng.randint(3)] for _ in qs]
+        theta = 0.01 * rng.normal()
+        out.append((qs, ps, theta))
+    return out
+
+
+def config3_terms(seed: int = seed_for(3), n: int = 40, set_bits: int = 20, terms: int = 500,
+                  locality: int = 4, capacity: int = 1 << 22) -> PauliWorkload:
+    """The same Trotter step as config3 (same draws), as native Pauli terms
+    exp(-i theta P) instead of basis-change / CNOT-ladder / Rz circuits."""
+    recs = [pauli_term(qs, ps, theta) for qs, ps, theta in _trotter_terms(seed, n, terms, locality)]
+    basis = (1 << set_bits) - 1
+    return PauliWorkload(f"c3_trotter_{n}q_native", n, 1e-10, np.array(recs, dtype=PAULI_DTYPE),
+                         capacity=capacity, basis=(basis & MASK64, basis >> 64), meta={"seed": seed, "terms": terms})
+
+
+def random_pauli_terms(seed: int, n: int, count: int, max_weight: int = 4, ctrl_max: int = 2,
+                       diag_frac: float = 0.2, ident_frac: float = 0.05, cap: int = 0,
+                       theta_scale: float = math.pi) -> np.ndarray:
+    """Random Pauli terms for tests: weight 1..max_weight over {X, Y, Z} (a
+    diag_frac share Z-only, an ident_frac share the identity), 0..ctrl_max
+    controls on other qubits, theta uniform in [-theta_scale, theta_scale)."""
+    rng = SplitMix64(seed)
+    recs = []
+    for _ in range(count):
+        u = rng.uniform()
+        w = 1 + rng.randint(max_weight)
+        nc = rng.randint(ctrl_max + 1)
+        qs = rng.distinct(n, min(n, w + nc))
+        ctrls, qs = qs[:nc], qs[nc:]
+        if u < ident_frac:
+            ps = ["I"] * len(qs)
+        elif u < ident_frac + diag_frac:
+            ps = ["Z"] * len(qs)
+        else:
+            ps = ["XYZ"[rng.randint(3)] for _ in qs]
+        theta = (rng.uniform() * 2.0 - 1.0) * theta_scale
+        recs.append(pauli_term(qs, ps, theta, ctrls, cap))
+    return np.array(recs, dtype=PAULI_DTYPE)
 
 
 def random_circuit(seed: int, n: int, gates: int, h_frac: float = 0.1, ctrl_max: int = 2,
