@@ -55,7 +55,7 @@ typedef struct sim_c64 {
 #define SIM_OP_MEASURE 2u
 
 /*
- * One operation (120 bytes).
+ * One operation (152 bytes).
  *
  * All ops: the op acts only on labels whose control bits (ctrl) are all set
  * (Sec. 2.1, controlled gates C^n U); ctrl must not contain the target bit
@@ -66,16 +66,23 @@ typedef struct sim_c64 {
  *   is the label's target bit before the gate, then the target bit is flipped
  *   if flip != 0.  When m[0] and m[1] are both exactly 1+0i no multiply is
  *   done.  Labels without the controls are unchanged.
- * SIM_OP_U2, a branching single-qubit gate (Eq. 2): m[0..3] is the row-major
- *   2x2 matrix U; for each label pair (b with target bit 0, b' = b with the
- *   bit set) alpha'_b = U00 alpha_b + U01 alpha_b', alpha'_b' = U10 alpha_b +
- *   U11 alpha_b', absent partners counting as 0.  Afterwards every entry with
- *   re*re + im*im < eps, or exactly zero, is dropped.  If cap != 0 the op is
- *   skipped when 2*nnz > cap (nnz before the op).
+ * SIM_OP_U2, a branching gate (Eq. 2; Sec. 3.1: the coefficients may depend
+ *   on the label and the partner label is easy to compute): a label's
+ *   partner is label ^ x, where x is the partner mask (x = 0 stands for the
+ *   target bit alone); target is the pivot, a bit of x.  For each pair (b
+ *   with the pivot bit 0, b' = b ^ x), with s = (-1)^popcount(b & z):
+ *   alpha'_b = U00 alpha_b + s U01 alpha_b', alpha'_b' = s U10 alpha_b + U11
+ *   alpha_b', absent partners counting as 0; m[0..3] is U row-major.  A
+ *   single-qubit gate has x = 0 (or the target bit) and z = 0; a Pauli
+ *   exponential has x and z from its Pauli string (sim_gates_from_pauli).
+ *   Afterwards every entry with re*re + im*im < eps, or exactly zero, is
+ *   dropped.  If cap != 0 the op is skipped when 2*nnz > cap (nnz before the
+ *   op).  x and z must lie below n_qubits and not meet ctrl.
  * SIM_OP_MEASURE of qubit `target` (Sec. 2.1, Born rule): P0 and P1 are the
  *   summed |a|^2 over labels with the qubit 0 / 1; the outcome is `forced`
  *   if forced is 0 or 1, otherwise 0 iff u < P0/(P0+P1); labels with the
  *   other value are dropped and the rest scaled by 1/sqrt(P_outcome).
+ * x and z are used by SIM_OP_U2 only and must be 0 for the other classes.
  */
 typedef struct sim_gate {
   uint32_t op;
@@ -87,6 +94,8 @@ typedef struct sim_gate {
   uint64_t cap;
   double u;
   uint64_t reserved;
+  sim_key x;   /* SIM_OP_U2: partner mask */
+  sim_key z;   /* SIM_OP_U2: off-diagonal sign mask */
 } sim_gate;
 
 /*
@@ -120,6 +129,26 @@ typedef struct sim_op {
   int32_t forced;
   uint32_t pad;
 } sim_op;
+
+/*
+ * Pauli-exponential term (64 bytes): exp(-i theta P), one of the intrinsic
+ * operations of Sec. 3 (at most two nonzeros per row), optionally controlled.
+ * P acts as X on the qubits in x only, as Y on those in both x and z, as Z on
+ * those in z only, and as the identity elsewhere; Sec. 2.1's Pauli rotation
+ * R_P(phi) is theta = phi / 2.  Since P^2 = I the term is cos(theta) I -
+ * i sin(theta) P, and P|b> = c(b)|b ^ x> with c(b) = i^popcount(x & z)
+ * (-1)^popcount(b & z).  A term with x != 0 is a branching operation (pruned
+ * afterwards, skipped when cap != 0 and 2*nnz > cap); a term with x == 0 is
+ * a phase gate (no pruning, cap ignored).  x, z and ctrl must lie below
+ * n_qubits, and ctrl must not meet x or z.
+ */
+typedef struct sim_pauli {
+  sim_key x;
+  sim_key z;
+  sim_key ctrl;
+  double theta;
+  uint64_t cap;
+} sim_pauli;
 
 /* Creation parameters. Zero fields take the stated defaults. */
 typedef struct sim_config {
@@ -212,6 +241,25 @@ int sim_apply_gates(sim_t* s, const sim_gate* gates, size_t n, int32_t* outcomes
  * SIM_E_BUFFER if cap is too small (*n_out set).
  */
 int sim_commute_ops(const sim_op* in, size_t n, uint32_t n_qubits, sim_op* out, size_t cap, size_t* n_out);
+
+/*
+ * Convert n Pauli terms into sim_gate ops (host only), written to out (at
+ * most cap of them; *n_out receives the count).  A term with x != 0 becomes
+ * one SIM_OP_U2 op whose pivot is the lowest bit of x, with U = [[cos theta,
+ * u01], [u10, cos theta]], u10 = -i sin(theta) i^popcount(x & z) and u01 =
+ * u10 (-1)^popcount(x & z), and the term's x, z, ctrl and cap.  A term with
+ * x == 0 and k > 0 qubits in z becomes 2k - 1 phase/permutation ops: CNOTs
+ * from the other z qubits onto the lowest one, the controlled factor
+ * diag(e^{-i theta}, e^{i theta}) there, and the CNOTs again; with z == 0 it
+ * is the controlled global factor e^{-i theta} (one op).  At most 255 ops per
+ * term.  SIM_E_ARG for an invalid term (nothing written); SIM_E_BUFFER if cap
+ * is too small (*n_out set).
+ */
+int sim_gates_from_pauli(const sim_pauli* terms, size_t n, uint32_t n_qubits, sim_gate* out, size_t cap,
+                         size_t* n_out);
+
+/* sim_gates_from_pauli followed by sim_apply_gates (no measurements). */
+int sim_apply_pauli(sim_t* s, const sim_pauli* terms, size_t n, sim_stats* stats);
 
 /* sim_gates_from_ops followed by sim_apply_gates. */
 int sim_apply_ops(sim_t* s, const sim_op* ops, size_t n, int32_t* outcomes, sim_stats* stats);

@@ -67,8 +67,13 @@ __device__ __forceinline__ uint32_t find_label2(const BItem& it, uint64_t lo, ui
   return kNoPartner;
 }
 
-// Eq. 2 for one entry, given its partner: mode 0 passes through, 1 emits the
-// pair (o0 for the bit-0 label, o1 for the bit-1 label), 2 emits nothing.
+__device__ __forceinline__ bool pivot_set2(const U2Desc& d, uint64_t lo, uint64_t hi, bool wide) {
+  const uint64_t w = (wide && d.target >= 64) ? hi : lo;
+  return ((w >> (d.target & 63)) & 1ull) != 0;
+}
+
+// Eq. 2 for one entry, given its partner (label ^ x): mode 0 passes through, 1
+// emits the pair (o0 for the pivot-0 label b0, o1 for b0 ^ x), 2 emits nothing.
 __device__ __forceinline__ int u2_entry(const BItem& it, uint64_t lo, uint64_t hi, double2 a, uint32_t j,
                                         double2* o0, double2* o1) {
   const U2Desc& d = it.u2;
@@ -76,14 +81,21 @@ __device__ __forceinline__ int u2_entry(const BItem& it, uint64_t lo, uint64_t h
     *o0 = a;
     return 0;
   }
-  const uint64_t w = (it.wide && d.target >= 64) ? hi : lo;
-  const bool v = (w >> (d.target & 63)) & 1ull;
+  const bool v = pivot_set2(d, lo, hi, it.wide);
   if (!v && j != kNoPartner) return 2;
   const double2 zero = make_double2(0.0, 0.0);
   const double2 a0 = v ? (j != kNoPartner ? it.in.amp[j] : zero) : a;
   const double2 a1 = v ? a : zero;
-  *o0 = cadd2(cmul2(d.u[0], a0), cmul2(d.u[1], a1));
-  *o1 = cadd2(cmul2(d.u[2], a0), cmul2(d.u[3], a1));
+  // off-diagonal sign from b0, the pair's label with the pivot bit clear
+  const uint64_t b0lo = v ? lo ^ d.x_lo : lo, b0hi = v ? hi ^ d.x_hi : hi;
+  const bool odd = ((__popcll(b0lo & d.z_lo) + (it.wide ? __popcll(b0hi & d.z_hi) : 0)) & 1) != 0;
+  double2 p01 = cmul2(d.u[1], a1), p10 = cmul2(d.u[2], a0);
+  if (odd) {
+    p01 = make_double2(-p01.x, -p01.y);
+    p10 = make_double2(-p10.x, -p10.y);
+  }
+  *o0 = cadd2(cmul2(d.u[0], a0), p01);
+  *o1 = cadd2(p10, cmul2(d.u[3], a1));
   return 1;
 }
 
@@ -229,13 +241,11 @@ __global__ __launch_bounds__(256) void kb_u2_count(const BTick* __restrict__ hdr
     const uint32_t c = u - u0[i];
     const uint64_t e0 = (uint64_t)c * kChunk;
     const uint64_t e1 = e0 + kChunk < it.nnz ? e0 + kChunk : it.nnz;
-    const uint64_t tbit = 1ull << (it.u2.target & 63);
-    const bool thi = it.wide && it.u2.target >= 64;
     uint32_t emit = 0;
     for (uint64_t e = e0 + threadIdx.x; e < e1; e += blockDim.x) {
       const uint64_t lo = it.in.key_lo[e], hi = it.wide ? it.in.key_hi[e] : 0ull;
       uint32_t j = kNoPartner;
-      if (ctrl_ok(it.u2, lo, hi, it.wide)) j = find_label2(it, thi ? lo : (lo ^ tbit), thi ? (hi ^ tbit) : hi);
+      if (ctrl_ok(it.u2, lo, hi, it.wide)) j = find_label2(it, lo ^ it.u2.x_lo, it.wide ? (hi ^ it.u2.x_hi) : 0ull);
       it.partner[e] = j;
       double2 o0, o1;
       const int mode = u2_entry(it, lo, hi, it.in.amp[e], j, &o0, &o1);
@@ -304,8 +314,6 @@ __global__ __launch_bounds__(256) void kb_u2_write(const BTick* __restrict__ hdr
     if (it.tot[u0[i + 1] - u0[i]] > it.cap) continue;          // overflow: leave the state alone
     const uint64_t e0 = (uint64_t)c * kChunk;
     const uint64_t e1 = e0 + kChunk < it.nnz ? e0 + kChunk : it.nnz;
-    const uint64_t tbit = 1ull << (it.u2.target & 63);
-    const bool thi = it.wide && it.u2.target >= 64;
     uint64_t base = it.tot[c];
     for (uint64_t tile = e0; tile < e1; tile += blockDim.x) {
       const uint64_t e = tile + threadIdx.x;
@@ -332,15 +340,17 @@ __global__ __launch_bounds__(256) void kb_u2_write(const BTick* __restrict__ hdr
         if (it.wide) it.out.key_hi[pos] = hi;
         it.out.amp[pos] = o0;
       } else if (mode == 1) {
+        const bool v = pivot_set2(it.u2, lo, hi, it.wide);
+        const uint64_t lo0 = v ? lo ^ it.u2.x_lo : lo, hi0 = v ? hi ^ it.u2.x_hi : hi;
         if (k0) {
-          it.out.key_lo[pos] = thi ? lo : (lo & ~tbit);
-          if (it.wide) it.out.key_hi[pos] = thi ? (hi & ~tbit) : hi;
+          it.out.key_lo[pos] = lo0;
+          if (it.wide) it.out.key_hi[pos] = hi0;
           it.out.amp[pos] = o0;
           ++pos;
         }
         if (k1) {
-          it.out.key_lo[pos] = thi ? lo : (lo | tbit);
-          if (it.wide) it.out.key_hi[pos] = thi ? (hi | tbit) : hi;
+          it.out.key_lo[pos] = lo0 ^ it.u2.x_lo;
+          if (it.wide) it.out.key_hi[pos] = hi0 ^ it.u2.x_hi;
           it.out.amp[pos] = o1;
         }
       }

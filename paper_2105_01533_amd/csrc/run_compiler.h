@@ -15,6 +15,9 @@ namespace sparsesim {
 // Per-entry kernel descriptor of a MONO op.
 MonoDesc mono_desc(const sim_gate& g);
 
+// The kernel descriptor of a validated SIM_OP_U2 gate (x = 0 -> the target bit).
+U2Desc u2_desc(const sim_gate& g, double eps);
+
 // Structural validity of an op for a state of n_qubits (qubits in range,
 // target not a control, measurement arguments, finite coefficients).
 bool gate_valid(uint32_t n_qubits, const sim_gate& g, std::string* why);

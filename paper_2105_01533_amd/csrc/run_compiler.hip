@@ -27,11 +27,35 @@ bool key_fits(uint32_t n, uint64_t lo, uint64_t hi) {
   return hi == 0 && (n == 64 || (lo >> n) == 0);
 }
 
+U2Desc u2_desc(const sim_gate& g, double eps) {
+  U2Desc d{};
+  d.ctrl_lo = g.ctrl.lo;
+  d.ctrl_hi = g.ctrl.hi;
+  const bool single = g.x.lo == 0 && g.x.hi == 0;
+  d.x_lo = single ? (g.target < 64 ? 1ull << g.target : 0ull) : g.x.lo;
+  d.x_hi = single ? (g.target >= 64 ? 1ull << (g.target - 64) : 0ull) : g.x.hi;
+  d.z_lo = g.z.lo;
+  d.z_hi = g.z.hi;
+  d.target = g.target;
+  d.eps = eps;
+  for (int k = 0; k < 4; ++k) d.u[k] = make_double2(g.m[k].re, g.m[k].im);
+  return d;
+}
+
 bool gate_valid(uint32_t n, const sim_gate& g, std::string* why) {
   if (g.op > SIM_OP_MEASURE) return *why = "unknown op class", false;
   if (g.target >= n || !key_fits(n, g.ctrl.lo, g.ctrl.hi)) return *why = "qubit out of range", false;
   const uint64_t tw = g.target < 64 ? g.ctrl.lo : g.ctrl.hi;
   if ((tw >> (g.target & 63)) & 1ull) return *why = "target is also a control", false;
+  if (g.op == SIM_OP_U2) {
+    if (!key_fits(n, g.x.lo, g.x.hi) || !key_fits(n, g.z.lo, g.z.hi)) return *why = "x or z out of range", false;
+    if (((g.x.lo | g.z.lo) & g.ctrl.lo) || ((g.x.hi | g.z.hi) & g.ctrl.hi))
+      return *why = "x or z meets the controls", false;
+    const uint64_t xw = g.target < 64 ? g.x.lo : g.x.hi;
+    if ((g.x.lo || g.x.hi) && !((xw >> (g.target & 63)) & 1ull)) return *why = "the target is not a bit of x", false;
+  } else if (g.x.lo || g.x.hi || g.z.lo || g.z.hi) {
+    return *why = "x and z are for branching ops only", false;
+  }
   if (g.op == SIM_OP_MEASURE) {
     if (g.ctrl.lo || g.ctrl.hi) return *why = "measurement cannot be controlled", false;
     if (g.forced < -1 || g.forced > 1) return *why = "forced must be -1, 0 or 1", false;

@@ -562,11 +562,7 @@ int srv_tick(srv_t* s, uint32_t* running, uint32_t* queued) {
       mono_items.push_back(it);
     } else if (k == SEG_U2) {
       const sim_gate& g = r->gates[op];
-      it.u2.ctrl_lo = g.ctrl.lo;
-      it.u2.ctrl_hi = g.ctrl.hi;
-      it.u2.target = g.target;
-      it.u2.eps = r->cfg.eps;
-      for (int q = 0; q < 4; ++q) it.u2.u[q] = make_double2(g.m[q].re, g.m[q].im);
+      it.u2 = u2_desc(g, r->cfg.eps);
       const uint64_t slots = std::min<uint64_t>(index_slots(r->nnz, r->cfg.load_factor), r->fp.slots);
       it.table = r->table;
       it.mask = slots - 1;

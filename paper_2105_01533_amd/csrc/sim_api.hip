@@ -302,12 +302,7 @@ int run_u2(sim_t* s, const sim_gate& g, bool* over) {
   const uint64_t slots = std::min<uint64_t>(table_slots(ub, lf), s->L.slots);
   const int other = s->cur ^ 1;
   const uint64_t* nnz_in = d_nnz(s, s->cur);
-  U2Desc d{};
-  d.ctrl_lo = g.ctrl.lo;
-  d.ctrl_hi = g.ctrl.hi;
-  d.target = g.target;
-  d.eps = s->cfg.eps;
-  for (int k = 0; k < 4; ++k) d.u[k] = make_double2(g.m[k].re, g.m[k].im);
+  const U2Desc d = u2_desc(g, s->cfg.eps);
   const int G = chunk_grid(ub);
   {
     KTimer t_(s, KC_FILL);
@@ -763,6 +758,16 @@ int sim_apply_ops(sim_t* s, const sim_op* ops, size_t n, int32_t* outcomes, sim_
   int rc = sim_gates_from_ops(ops, n, g.data());
   if (rc) return rc;
   return sim_apply_gates(s, g.data(), n, outcomes, stats);
+}
+
+int sim_apply_pauli(sim_t* s, const sim_pauli* terms, size_t n, sim_stats* stats) {
+  if (!s) return fail(SIM_E_ARG, "null handle");
+  if (n && !terms) return fail(SIM_E_ARG, "null term array");
+  std::vector<sim_gate> g(pauli_op_count(terms, n));
+  size_t total = 0;
+  int rc = sim_gates_from_pauli(terms, n, s->cfg.n_qubits, g.data(), g.size(), &total);
+  if (rc) return rc;
+  return sim_apply_gates(s, g.data(), total, nullptr, stats);
 }
 
 int sim_measure(sim_t* s, uint32_t qubit, double u, int32_t forced, int32_t* outcome, double* p1) {

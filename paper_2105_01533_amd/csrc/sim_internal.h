@@ -7,10 +7,15 @@
 
 #include <string>
 
+#include "../../include/sparsesim.h"
+
 namespace sparsesim {
 
 // Record an error for sim_last_error; returns code (sim_api.hip).
 int set_error(int code, const std::string& msg);
+
+// Ops that sim_gates_from_pauli writes for these terms.
+size_t pauli_op_count(const sim_pauli* terms, size_t n);
 
 constexpr uint64_t kEmptySlot = ~0ull;   // hash index: free slot
 constexpr uint32_t kNoPartner = ~0u;     // partner look-up miss
@@ -100,10 +105,16 @@ struct BsRun {
   uint64_t g_turn;             // entry-independent turn fraction * 2^64
 };
 
-// Branching 2x2 gate (Eq. 2), passed by value.
+// Branching operation (Eq. 2 with coefficients that depend on the label),
+// passed by value.  A label's partner is label ^ x; of a pair, b0 is the label
+// whose pivot bit (target, a bit of x) is 0 and b1 = b0 ^ x:
+//   alpha'_b0 = u0 alpha_b0 + s u1 alpha_b1,  alpha'_b1 = s u2 alpha_b0 + u3 alpha_b1,
+// s = (-1)^popcount(b0 & z).  A single-qubit gate has x = the target bit, z = 0.
 struct U2Desc {
   uint64_t ctrl_lo, ctrl_hi;
-  uint32_t target, pad;
+  uint64_t x_lo, x_hi;         // partner mask
+  uint64_t z_lo, z_hi;         // off-diagonal sign mask
+  uint32_t target, pad;        // pivot bit
   double eps;
   double2 u[4];                // row-major
 };

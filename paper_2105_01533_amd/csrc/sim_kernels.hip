@@ -202,8 +202,15 @@ __device__ __forceinline__ uint32_t find_label(const Buf& b, const uint64_t* __r
   return kNoPartner;
 }
 
+template <bool WIDE>
+__device__ __forceinline__ bool pivot_set(const U2Desc& d, uint64_t lo, uint64_t hi) {
+  const uint64_t w = (WIDE && d.target >= 64) ? hi : lo;
+  return ((w >> (d.target & 63)) & 1ull) != 0;
+}
+
 // Branching gate outputs of entry i, given its partner index j (Eq. 2 with the
-// pair rule of Sec. 3.1).  mode: 0 = label outside the controls (passes
+// pair rule of Sec. 3.1: of two present partners the one with the pivot bit
+// set emits).  mode: 0 = label outside the controls (passes
 // through), 1 = the label emits the pair, 2 = its partner emits (nothing here).
 struct U2Out {
   int mode;
@@ -222,8 +229,7 @@ __device__ __forceinline__ U2Out u2_eval(const Buf& b, const U2Desc& d, uint64_t
     r.o1 = a;
     return r;
   }
-  const uint64_t w = (WIDE && d.target >= 64) ? hi : lo;
-  const bool v = (w >> (d.target & 63)) & 1ull;
+  const bool v = pivot_set<WIDE>(d, lo, hi);
   if (!v && j != kNoPartner) {
     r.mode = 2;
     r.o0 = r.o1 = a;
@@ -232,9 +238,17 @@ __device__ __forceinline__ U2Out u2_eval(const Buf& b, const U2Desc& d, uint64_t
   const double2 zero = make_double2(0.0, 0.0);
   const double2 a0 = v ? (j != kNoPartner ? b.amp[j] : zero) : a;
   const double2 a1 = v ? a : zero;
+  // The off-diagonal sign comes from b0, the pair's label with the pivot clear.
+  const uint64_t b0lo = v ? lo ^ d.x_lo : lo, b0hi = v ? hi ^ d.x_hi : hi;
+  const bool odd = ((__popcll(b0lo & d.z_lo) + (WIDE ? __popcll(b0hi & d.z_hi) : 0)) & 1) != 0;
+  double2 p01 = cmul(d.u[1], a1), p10 = cmul(d.u[2], a0);
+  if (odd) {
+    p01 = make_double2(-p01.x, -p01.y);
+    p10 = make_double2(-p10.x, -p10.y);
+  }
   r.mode = 1;
-  r.o0 = cadd(cmul(d.u[0], a0), cmul(d.u[1], a1));
-  r.o1 = cadd(cmul(d.u[2], a0), cmul(d.u[3], a1));
+  r.o0 = cadd(cmul(d.u[0], a0), p01);
+  r.o1 = cadd(p10, cmul(d.u[3], a1));
   return r;
 }
 
@@ -248,15 +262,13 @@ __global__ __launch_bounds__(256) void k_u2_count(Buf b, const uint64_t* __restr
   uint64_t begin, end;
   chunk_range(n, begin, end);
   uint32_t emit = 0, dropped = 0;
-  const uint64_t tbit = 1ull << (d.target & 63);
-  const bool thi = WIDE && d.target >= 64;
   for (uint64_t i = begin + threadIdx.x; i < end; i += blockDim.x) {
     const uint64_t lo = b.key_lo[i];
     const uint64_t hi = WIDE ? b.key_hi[i] : 0ull;
     bool c = (lo & d.ctrl_lo) == d.ctrl_lo;
     if (WIDE) c = c && ((hi & d.ctrl_hi) == d.ctrl_hi);
     uint32_t j = kNoPartner;
-    if (c) j = find_label<WIDE>(b, table, mask, thi ? lo : (lo ^ tbit), thi ? (hi ^ tbit) : hi);
+    if (c) j = find_label<WIDE>(b, table, mask, lo ^ d.x_lo, WIDE ? (hi ^ d.x_hi) : 0ull);
     partner[i] = j;
     const U2Out r = u2_eval<WIDE>(b, d, lo, hi, b.amp[i], j);
     if (r.mode == 0) {
@@ -320,8 +332,6 @@ __global__ __launch_bounds__(256) void k_u2_write(Buf in, Buf out, const uint64_
   uint64_t begin, end;
   chunk_range(n, begin, end);
   uint64_t base = off[blockIdx.x];
-  const uint64_t tbit = 1ull << (d.target & 63);
-  const bool thi = WIDE && d.target >= 64;
   for (uint64_t tile = begin; tile < end; tile += blockDim.x) {
     const uint64_t i = tile + threadIdx.x;
     uint32_t e = 0;
@@ -350,7 +360,8 @@ __global__ __launch_bounds__(256) void k_u2_write(Buf in, Buf out, const uint64_
         out.amp[pos] = r.o0;
       }
     } else if (r.mode == 1) {
-      const uint64_t lo0 = thi ? lo : (lo & ~tbit), hi0 = thi ? (hi & ~tbit) : hi;
+      const bool v = pivot_set<WIDE>(d, lo, hi);
+      const uint64_t lo0 = v ? lo ^ d.x_lo : lo, hi0 = v ? hi ^ d.x_hi : hi;
       if (k0) {
         out.key_lo[pos] = lo0;
         if (WIDE) out.key_hi[pos] = hi0;
@@ -358,8 +369,8 @@ __global__ __launch_bounds__(256) void k_u2_write(Buf in, Buf out, const uint64_
         ++pos;
       }
       if (k1) {
-        out.key_lo[pos] = thi ? lo : (lo | tbit);
-        if (WIDE) out.key_hi[pos] = thi ? (hi | tbit) : hi;
+        out.key_lo[pos] = lo0 ^ d.x_lo;
+        if (WIDE) out.key_hi[pos] = hi0 ^ d.x_hi;
         out.amp[pos] = r.o1;
       }
     }

@@ -30,9 +30,9 @@ SIM_PROFILE_OFF, SIM_PROFILE_ALL, SIM_PROFILE_MONO = 0, 1, 2
 GATE_DTYPE = np.dtype([
     ("op", "<u4"), ("target", "<u4"), ("ctrl_lo", "<u8"), ("ctrl_hi", "<u8"),
     ("flip", "<u4"), ("forced", "<i4"), ("m", "<c16", (4,)), ("cap", "<u8"), ("u", "<f8"),
-    ("reserved", "<u8"),
+    ("reserved", "<u8"), ("x_lo", "<u8"), ("x_hi", "<u8"), ("z_lo", "<u8"), ("z_hi", "<u8"),
 ])
-assert GATE_DTYPE.itemsize == 120
+assert GATE_DTYPE.itemsize == 152
 KEY_DTYPE = np.dtype([("lo", "<u8"), ("hi", "<u8")])
 
 
@@ -80,6 +80,8 @@ def _load():
         "sim_import_state": (i32, [vp, vp, vp, u64]),
         "sim_gates_from_ops": (i32, [vp, sz, vp]),
         "sim_commute_ops": (i32, [vp, sz, ctypes.c_uint32, vp, sz, ctypes.POINTER(sz)]),
+        "sim_gates_from_pauli": (i32, [vp, sz, ctypes.c_uint32, vp, sz, ctypes.POINTER(sz)]),
+        "sim_apply_pauli": (i32, [vp, vp, sz, vp]),
         "sim_apply_gates": (i32, [vp, vp, sz, vp, vp]),
         "sim_apply_ops": (i32, [vp, vp, sz, vp, vp]),
         "sim_measure": (i32, [vp, u32, f64, i32, ctypes.POINTER(i32), ctypes.POINTER(f64)]),
@@ -166,6 +168,33 @@ def sim_commute_ops(ops: np.ndarray, n_qubits: int) -> np.ndarray:
     _check(_lib.sim_commute_ops(_ptr(ops), len(ops), n_qubits, _ptr(out), len(out), ctypes.byref(n)),
            "sim_commute_ops")
     return out[:n.value]
+
+
+def sim_gates_from_pauli(terms: np.ndarray, n_qubits: int) -> np.ndarray:
+    """Pauli-exponential records (64 bytes: x, z, ctrl masks, theta, cap) as
+    sim_gate ops: one branching op per term with x != 0, a CNOT-gathered
+    parity phase for a diagonal term."""
+    terms = np.ascontiguousarray(terms)
+    assert terms.dtype.itemsize == 64
+    n = ctypes.c_size_t(0)
+    rc = _lib.sim_gates_from_pauli(_ptr(terms), len(terms), n_qubits, None, 0, ctypes.byref(n))
+    if rc not in (SIM_OK, SIM_E_BUFFER):
+        _check(rc, "sim_gates_from_pauli")
+    out = np.zeros(max(n.value, 1), GATE_DTYPE)
+    _check(_lib.sim_gates_from_pauli(_ptr(terms), len(terms), n_qubits, _ptr(out), len(out), ctypes.byref(n)),
+           "sim_gates_from_pauli")
+    return out[:n.value]
+
+
+def sim_apply_pauli(h, terms: np.ndarray, raise_on_error: bool = True):
+    """Returns (rc, stats dict)."""
+    terms = np.ascontiguousarray(terms)
+    assert terms.dtype.itemsize == 64
+    st = sim_stats()
+    rc = _lib.sim_apply_pauli(h, _ptr(terms), len(terms), ctypes.byref(st))
+    if raise_on_error:
+        _check(rc, "sim_apply_pauli")
+    return rc, st.as_dict()
 
 
 def _n_meas_gates(gates):
@@ -305,6 +334,9 @@ class Simulator:
     def apply_gates(self, gates, raise_on_error=True):
         return sim_apply_gates(self.h, gates, raise_on_error)
 
+    def apply_pauli(self, terms, raise_on_error=True):
+        return sim_apply_pauli(self.h, terms, raise_on_error)
+
     def measure(self, q, u, forced=-1):
         return sim_measure(self.h, q, u, forced)
 
@@ -325,6 +357,15 @@ def run_workload(w, commute: bool = False, **kw):
     ops = sim_commute_ops(w.ops, w.n_qubits) if commute else w.ops
     _, outcomes, stats = s.apply_ops(ops)
     return s, outcomes, stats
+
+
+def run_pauli_workload(w, **kw):
+    """Simulate a workloads.PauliWorkload (native exp(-i theta P) terms) from
+    its basis state; returns (sim, stats)."""
+    s = Simulator(w.n_qubits, w.capacity, w.eps, **kw)
+    s.set_basis(*w.basis)
+    _, stats = s.apply_pauli(w.terms)
+    return s, stats
 
 
 # --- continuous-batching server (srv_*) -----------------------------------------

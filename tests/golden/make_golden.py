@@ -1,6 +1,7 @@
 """Write the oracle's results for the full-size workloads whose oracle run is
 too slow to repeat inside a test (config 1: 64-qubit adder, ~1 min; config 3:
-40-qubit Trotter step, ~2.5 min).  Calls only the oracle and the workload
+40-qubit Trotter step, ~2.5 min; the same Trotter step as native Pauli
+terms, ~20 s).  Calls only the oracle and the workload
 generators; run from the repository root:
 
     python tests/golden/make_golden.py
@@ -21,7 +22,7 @@ import numpy as np
 ROOT = os.path.dirname(os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
 sys.path.insert(0, ROOT)
 
-from oracle import run_workload  # noqa: E402
+from oracle import run_pauli_workload, run_workload  # noqa: E402
 from paper_2105_01533_amd import workloads as W  # noqa: E402
 
 HERE = os.path.dirname(os.path.abspath(__file__))
@@ -35,14 +36,19 @@ def keys_digest(lo: np.ndarray, hi: np.ndarray) -> str:
 
 def golden(name: str, w):
     t0 = time.time()
-    o, outcomes, _ = run_workload(w)
+    if isinstance(w, W.PauliWorkload):
+        o, _ = run_pauli_workload(w)
+        outcomes, n_ops = [], len(w.terms)
+    else:
+        o, outcomes, _ = run_workload(w)
+        n_ops = len(w.ops)
     lo, hi, amp = o.export()
     tot = o.totals()
     stride = max(1, len(lo) // N_SAMPLES)
     idx = np.arange(0, len(lo), stride)[:N_SAMPLES]
     doc = {
         "workload": name, "seed": w.meta.get("seed"), "n_qubits": w.n_qubits, "eps": w.eps,
-        "n_ops": len(w.ops), "nnz": int(len(lo)), "keys_sha256": keys_digest(lo, hi),
+        "n_ops": n_ops, "nnz": int(len(lo)), "keys_sha256": keys_digest(lo, hi),
         "norm2": float(np.sum(np.abs(amp) ** 2)).hex(),
         "outcomes": [int(x) for x in outcomes],
         "updates": int(tot["updates"]), "u2_applied": int(tot["u2_applied"]),
@@ -59,3 +65,4 @@ def golden(name: str, w):
 if __name__ == "__main__":
     golden("config1_full", W.config1())
     golden("config3_full", W.config3())
+    golden("config3_native_full", W.config3_terms())
