@@ -78,6 +78,44 @@ def cpu_baseline(w, seconds_budget: float = 20.0):
                       f"{upd} updates in {dt:.1f} s, single thread"}
 
 
+def cpu_parallel(h_qubits: int = 20, body: int = 1200, threads: int = 0):
+    """Sec. 5's multithreaded queue in the oracle (queues of more than 64 gates
+    on more than 4096 entries run on several threads) against the same oracle
+    serial, on the c2 generator at 2^h_qubits entries: the H layer plus the
+    next `body` gates.  Context for a multi-core CPU comparison; the oracle's
+    single-thread figure stays `cpu_baseline`."""
+    import numpy as np
+
+    from oracle import Oracle
+    from paper_2105_01533_amd import workloads as W
+
+    threads = threads or min(16, os.cpu_count() or 1)
+    w = W.config2(h_qubits=h_qubits, gates=body + 64)
+    first = int(np.argmax(w.ops["kind"] != W.K_H))
+    ops = w.ops[:first + body]
+    res = {}
+    for t in (1, threads):
+        o = Oracle(w.n_qubits, w.eps)
+        o.set_threads(t)
+        o.set_basis(*w.basis)
+        t0 = time.perf_counter()
+        o.run(ops[:first])
+        t1 = time.perf_counter()
+        o.run(ops[first:])
+        t2 = time.perf_counter()
+        tot = o.totals()
+        res[t] = (t2 - t0, t2 - t1, tot["updates"], tot["parallel_runs"])
+        del o
+    (s_all, s_body, upd, _), (p_all, p_body, upd_p, pruns) = res[1], res[threads]
+    assert upd == upd_p
+    return {"value": upd / p_all, "unit": "updates/s", "cores": threads, "kind": "oracle, Sec. 5 parallel queue",
+            "serial_value": upd / s_all, "speedup": round(s_all / p_all, 2),
+            "queue_speedup": round(s_body / p_body, 2), "parallel_runs": pruns,
+            "sample": f"c2 generator at 2^{h_qubits} entries: {first} H gates + next {body} gates, {upd} updates; "
+                      f"serial {s_all:.1f} s (queue {s_body:.1f} s), {threads} threads {p_all:.1f} s "
+                      f"(queue {p_body:.1f} s)"}
+
+
 def hbm_sweep(sim, W, n_qubits=100, log2n=24, depths=(1, 2, 4, 16, 64)):
     """Fused-pass bandwidth vs fusion depth F on a 2^log2n-entry state: 64
     phase/permutation gates of the random mix, passes of F gates."""
@@ -249,6 +287,7 @@ def main():
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--no-commuting", action="store_true", help="skip the gate-commuting comparison")
     ap.add_argument("--no-pauli", action="store_true", help="skip the native Pauli-exponential comparison")
+    ap.add_argument("--no-cpu-parallel", action="store_true", help="skip the multithreaded-oracle leg")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run the 1 GiB reference copy kernel (for hardware byte-counter scaling) first")
     ap.add_argument("--serving-requests", type=int, default=128)
@@ -360,6 +399,11 @@ def main():
     if not args.no_cpu_baseline:
         log("[bench] cpu baseline (oracle) ...")
         out["cpu_baseline"] = cpu_baseline(w, args.cpu_seconds)
+        log(f"[bench] cpu baseline: {out['cpu_baseline']}")
+        if not args.no_cpu_parallel:
+            log("[bench] cpu parallel queue (oracle, Sec. 5) ...")
+            out["cpu_parallel"] = cpu_parallel()
+            log(f"[bench] cpu parallel: {out['cpu_parallel']}")
     print(json.dumps(out), flush=True)
 
 

@@ -30,7 +30,8 @@ class Totals(ctypes.Structure):
     _fields_ = [("updates", ctypes.c_uint64), ("u2_applied", ctypes.c_uint64),
                 ("u2_skipped", ctypes.c_uint64), ("measures", ctypes.c_uint64),
                 ("mono_gates", ctypes.c_uint64), ("peak_nnz", ctypes.c_uint64),
-                ("pruned", ctypes.c_uint64), ("pruned_mass", ctypes.c_double)]
+                ("pruned", ctypes.c_uint64), ("pruned_mass", ctypes.c_double),
+                ("parallel_runs", ctypes.c_uint64)]
 
 
 def build(force: bool = True) -> str:
@@ -68,6 +69,8 @@ def lib():
         L.orc_monomial_samples.argtypes = [vp, u64, vp, vp, vp, u64]
         L.orc_run_commuting.argtypes = [vp, vp, u64, vp, u64, ctypes.POINTER(u64), vp, ctypes.POINTER(u64)]
         L.orc_run_pauli.argtypes = [vp, vp, u64, vp, ctypes.POINTER(u64)]
+        L.orc_set_threads.restype = ctypes.c_uint
+        L.orc_set_threads.argtypes = [vp, ctypes.c_uint]
         for f in ("orc_set_basis", "orc_import", "orc_run", "orc_probabilities", "orc_monomial_samples",
                   "orc_run_commuting", "orc_run_pauli"):
             getattr(L, f).restype = i32
@@ -97,6 +100,11 @@ class Oracle:
         if getattr(self, "h", None):
             lib().orc_destroy(self.h)
             self.h = None
+
+    def set_threads(self, n: int = 0) -> int:
+        """Threads for queues of more than 64 gates on more than 4096 entries
+        (Sec. 5); 0 = all hardware threads.  Returns the count in use."""
+        return int(lib().orc_set_threads(self.h, n))
 
     def set_basis(self, lo: int = 0, hi: int = 0):
         lib().orc_set_basis(self.h, lo, hi)

@@ -22,7 +22,9 @@
 // Queued mode (Sec. 3.2) applies a maximal run of phase/permutation gates to
 // each label in turn, composing f and g as in the paper, before inserting the
 // result into the new map.  Gate-by-gate mode rebuilds the map after every
-// gate.  The two must agree bit for bit.
+// gate.  The two must agree bit for bit.  With orc_set_threads > 1, a queue of
+// more than 64 gates on more than 4096 entries is applied by several threads
+// (Sec. 5), again bit for bit as the serial loop.
 //
 // Readings where the paper is silent (also listed in the design notes):
 //   * prune T_eps after every applied branching gate: drop an entry iff
@@ -50,6 +52,7 @@
 #include <cmath>
 #include <cstdint>
 #include <cstring>
+#include <thread>
 #include <unordered_map>
 #include <vector>
 
@@ -233,6 +236,7 @@ struct Totals {
   uint64_t u2_applied, u2_skipped, measures, mono_gates;
   uint64_t peak_nnz, pruned;
   double pruned_mass;
+  uint64_t parallel_runs;   // queues applied by several threads (Sec. 5)
 };
 
 struct Oracle {
@@ -240,6 +244,7 @@ struct Oracle {
   double eps;
   State psi;
   Totals tot;
+  unsigned threads = 1;   // queue application (Sec. 5); 1 = serial
 };
 
 bool drop(const Amp& a, double eps) {
@@ -288,10 +293,52 @@ void apply_branching(Oracle& o, const OpRecord& op) {
   o.psi.swap(out);
 }
 
+// Sec. 5: a queue longer than 64 gates on a state of more than 4096 entries is
+// processed by several threads.  Here each thread takes a contiguous range of
+// the map's buckets (reading a map concurrently is safe), applies every queued
+// gate to each of its labels and keeps the results in a list of its own; the
+// lists are then inserted into the new map one after the other.  Labels are
+// independent, so every (label, amplitude) is bitwise what the serial loop
+// computes; only the map's internal order can differ, and nothing downstream
+// depends on it (branching outputs are written once per label, two-term sums
+// commute, measurement sums run in sorted label order).
+constexpr size_t kParallelMinGates = 64, kParallelMinStates = 4096;
+
+void apply_monomial_run_parallel(Oracle& o, const std::vector<Monomial>& run) {
+  const size_t nb = o.psi.bucket_count();
+  const unsigned nt = o.threads;
+  std::vector<std::vector<std::pair<Label, Amp>>> part(nt);
+  std::vector<std::thread> pool;
+  for (unsigned t = 0; t < nt; ++t) {
+    pool.emplace_back([&, t] {
+      const size_t b0 = nb * t / nt, b1 = nb * (t + 1) / nt;
+      auto& mine = part[t];
+      for (size_t b = b0; b < b1; ++b)
+        for (auto it = o.psi.begin(b); it != o.psi.end(b); ++it) {
+          Label k = it->first;
+          Amp a = it->second;
+          for (const Monomial& g : run) apply_monomial(g, k, a);
+          mine.emplace_back(k, a);
+        }
+    });
+  }
+  for (auto& th : pool) th.join();
+  State out;
+  out.reserve(o.psi.size());
+  for (const auto& mine : part)
+    for (const auto& e : mine) out.emplace(e.first, e.second);
+  o.psi.swap(out);
+}
+
 // Apply a run of phase/permutation gates: per label, all gates in order,
 // then one insertion into the new map (Sec. 3.2).
 void apply_monomial_run(Oracle& o, const std::vector<Monomial>& run) {
   if (run.empty()) return;
+  if (o.threads > 1 && run.size() > kParallelMinGates && o.psi.size() > kParallelMinStates) {
+    apply_monomial_run_parallel(o, run);
+    o.tot.parallel_runs++;
+    return;
+  }
   State out;
   out.reserve(o.psi.size());
   for (const auto& kv : o.psi) {
@@ -387,6 +434,15 @@ int orc_import(void* h, const uint64_t* lo, const uint64_t* hi, const double* am
 }
 
 uint64_t orc_nnz(void* h) { return static_cast<Oracle*>(h)->psi.size(); }
+
+// Threads for queue application (Sec. 5); 0 = the hardware's count.  Returns
+// the count in use.
+unsigned orc_set_threads(void* h, unsigned n) {
+  Oracle& o = *static_cast<Oracle*>(h);
+  if (n == 0) n = std::max(1u, std::thread::hardware_concurrency());
+  o.threads = n;
+  return n;
+}
 
 // Run ops.  queued != 0 applies maximal runs of phase/permutation gates per
 // label (skipped branching gates do not end a run: they leave nnz unchanged).
