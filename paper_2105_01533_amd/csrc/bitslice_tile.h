@@ -281,22 +281,29 @@ __device__ __forceinline__ void bs_tile(const Buf& b, uint64_t base, uint32_t li
           bw[2] = __builtin_amdgcn_readlane(cb.z, g);
           bw[3] = __builtin_amdgcn_readlane(cb.w, g);
           uint32_t x[kBsGroup];
+          if (a[1] & kBareBit) {
 #pragma unroll
-          for (int u = 0; u < kBsGroup; ++u)
-            x[u] = plane(Lb, off_p0(a[u])) & plane(Lb, off_p1(a[u])) & plane(Lb, off_p2(bw[u])) &
-                   plane(Lb, off_t(a[u]));
+            for (int u = 0; u < kBsGroup; ++u) x[u] = plane(Lb, off_t(a[u]));
+          } else {
+#pragma unroll
+            for (int u = 0; u < kBsGroup; ++u)
+              x[u] = plane(Lb, off_p0(a[u])) & plane(Lb, off_p1(a[u])) & plane(Lb, off_p2(bw[u])) &
+                     plane(Lb, off_t(a[u]));
+          }
           const uint32_t tg = 16u * (g0 + g) + 8u;   // the group's turn fractions, in 32-bit words
           uint64_t tau[kBsGroup];
 #pragma unroll
           for (int u = 0; u < kBsGroup; ++u) tau[u] = ((uint64_t)taus[tg + 2 * u + 1] << 32) | taus[tg + 2 * u];
           // An entry gains the sum of the fractions of the ops whose condition
-          // holds for it: one of 16 subset sums, kept in every 16-lane quarter
-          // of the wave (lane l holds the sum over the ops named by l's low
-          // four bits) and fetched per entry with a lane permute.
+          // holds for it: one of 16 subset sums, kept as 8-byte words in the
+          // table plane (entry m = the sum over the ops named by m's bits) and
+          // read per entry with one 64-bit LDS load.  The wave's LDS accesses
+          // complete in order, so the table is written before any load of it.
           uint64_t S = 0;
 #pragma unroll
           for (int u = 0; u < kBsGroup; ++u) S += tau[u] & (0ull - (uint64_t)((lane >> u) & 1));
-          const int s_lo = (int)(uint32_t)S, s_hi = (int)(uint32_t)(S >> 32);
+          char* table = Lb - 4 * lane + (nq + 2) * 256;
+          if (lane < 16) *reinterpret_cast<uint64_t*>(table + 8 * lane) = S;
           // Nibble i of W[c] = the ops (bit u = op u) that hold for entry
           // 8c + i: a byte transpose of the four masks, then each word's
           // 4 x 8 bit matrix transposed by rotating its bit index
@@ -313,27 +320,20 @@ __device__ __forceinline__ void bs_tile(const Buf& b, uint64_t base, uint32_t li
             t = (w ^ (w >> 1)) & 0x22222222u;  w ^= t ^ (t << 1);    // 0 <-> 1
             W[c] = w;
           }
-          // Permutes go out seven entries (14 lane-permutes, within the LDS
-          // counter's reach) at a time before their sums are added.
+          // Table loads go out fourteen at a time (the LDS counter counts to
+          // fifteen) before their sums are added.
 #pragma unroll
-          for (int j0 = 0; j0 < 32; j0 += 7) {
-            uint32_t lo[7], hi[7];
+          for (int j0 = 0; j0 < 32; j0 += 14) {
+            uint64_t v[14];
 #pragma unroll
-            for (int k = 0; k < 7 && j0 + k < 32; ++k) {
+            for (int k = 0; k < 14 && j0 + k < 32; ++k) {
               const int j = j0 + k, c = j >> 3, i = j & 7;
-              // Permute byte address: the nibble in bits 2-5 (bits 0-1 are
-              // ignored by the permute, bits 6-7 are zero).
-              const uint32_t addr = i ? __builtin_amdgcn_ubfe(W[c], 4 * i - 2, 6) : (W[c] << 2) & 0x3cu;
-              lo[k] = (uint32_t)__builtin_amdgcn_ds_bpermute((int)addr, s_lo);
-              hi[k] = (uint32_t)__builtin_amdgcn_ds_bpermute((int)addr, s_hi);
+              const uint32_t nib = __builtin_amdgcn_ubfe(W[c], 4 * i, 4);
+              v[k] = *reinterpret_cast<const uint64_t*>(table + 8 * nib);
             }
             __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-            for (int k = 0; k < 7 && j0 + k < 32; ++k) {
-              uint64_t v = ((uint64_t)hi[k] << 32) | lo[k];
-              asm("" : "+v"(v));   // one register pair, added once
-              turns[j0 + k] += v;
-            }
+            for (int k = 0; k < 14 && j0 + k < 32; ++k) turns[j0 + k] += v[k];
           }
         }
         ++g;

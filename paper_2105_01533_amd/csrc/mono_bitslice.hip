@@ -47,7 +47,8 @@ __global__ __launch_bounds__(64, 2) void k_mono_bs(Buf b, const uint64_t* __rest
 
 void launch_mono_bs(hipStream_t st, Buf b, const uint64_t* nnz, const BsGroup* groups, uint32_t ngroups, const BsRun& run,
                     Ctl* ctl, int grid) {
-  const size_t planes = run.has_turns && run.n_planes + 2 < 64 ? 64 : run.n_planes + 2;   // turns reuse the planes
+  // The turn accumulators move into the first 64 planes at the end of a tile.
+  const size_t planes = run.has_turns && run.n_planes + kExtraPlanes < 64 ? 64 : run.n_planes + kExtraPlanes;
   const size_t lds = planes * 64 * 4;
   if (run.has_turns)
     hipLaunchKernelGGL(k_mono_bs<true>, dim3(grid), dim3(64), lds, st, b, nnz, groups, ngroups, run, ctl);

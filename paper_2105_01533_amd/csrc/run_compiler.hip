@@ -356,6 +356,11 @@ void RunCompiler::group_range(uint32_t i0, uint32_t i1, std::vector<BsGroup>& ou
       grp.tau[u] = 0;
     }
     grp.a[0] |= (shape == kShapeGeneric && phase ? kShapePhase : shape) << 5;
+    if (shape == kShapeTurn) {
+      bool bare = true;
+      for (uint32_t v = 0; v < np; ++v) bare = bare && ops[i0 + picked[v]].nctrl == 0;
+      if (bare) grp.a[1] |= kBareBit;
+    }
     out.push_back(grp);
   };
   const size_t base = out.size();

@@ -103,8 +103,17 @@ bool apply_groups(State& s, const std::vector<BsGroup>& groups, uint32_t nq, std
       continue;
     }
     const uint32_t shape = f_shape(G.a[0]);
+    const bool bare = (G.a[1] & kBareBit) != 0;
+    if (bare) {
+      // The kernel then reads only each op's target plane: every other
+      // condition plane must be the all-ones plane.
+      if (shape != kShapeTurn) return *why = "bare flag on a non-TURN group", false;
+      for (int u = 0; u < kBsGroup; ++u)
+        if (((G.a[u] >> 16) & 0xffu) != nq || ((G.a[u] >> 24) & 0xffu) != nq || ((G.b[u] >> 8) & 0xffu) != nq)
+          return *why = "bare TURN group with a control plane", false;
+    }
     for (int u = 1; u < kBsGroup; ++u)
-      if (f_shape(G.a[u])) return *why = "shape or pair bits set on a non-first op", false;
+      if (f_shape(G.a[u] & ~(u == 1 ? kBareBit : 0u))) return *why = "shape or pair bits set on a non-first op", false;
     // Independence: no member writes a plane another member reads or writes
     // (padding flips of the scratch plane excepted).
     for (int u = 0; u < kBsGroup; ++u) {
