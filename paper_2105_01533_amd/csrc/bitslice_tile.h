@@ -36,31 +36,16 @@ __device__ __forceinline__ void omega_add(uint32_t& e0, uint32_t& e1, uint32_t& 
   e2 ^= b2 ^ c1;
 }
 
-// omega_add for a wave-uniform k: only the counter bits k touches.
-__device__ __forceinline__ void omega_add_k(uint32_t& e0, uint32_t& e1, uint32_t& e2, uint32_t x, uint32_t k) {
-  switch (k) {
-    case 1: {
-      const uint32_t c0 = e0 & x;
-      e0 ^= x;
-      e2 ^= e1 & c0;
-      e1 ^= c0;
-      break;
-    }
-    case 2:
-      e2 ^= e1 & x;
-      e1 ^= x;
-      break;
-    case 4:
-      e2 ^= x;
-      break;
-    case 6:
-      e2 ^= x ^ (e1 & x);
-      e1 ^= x;
-      break;
-    default:
-      omega_add(e0, e1, e2, x, k);
-      break;
-  }
+// omega_add without branches: k's bits arrive as wave-uniform masks m0, m1,
+// m2 (each 0 or ~0).
+__device__ __forceinline__ void omega_add_m(uint32_t& e0, uint32_t& e1, uint32_t& e2, uint32_t x, uint32_t m0,
+                                            uint32_t m1, uint32_t m2) {
+  const uint32_t b0 = x & m0, b1 = x & m1, b2 = x & m2;
+  const uint32_t c0 = e0 & b0;
+  e0 ^= b0;
+  const uint32_t c1 = (e1 & b1) | ((e1 ^ b1) & c0);
+  e1 ^= b1 ^ c0;
+  e2 ^= b2 ^ c1;
 }
 
 // Load the lane's 32 labels' 64-bit word (src already offset by base + lane;
@@ -171,7 +156,9 @@ __device__ __forceinline__ void bs_tile(const Buf& b, uint64_t base, uint32_t li
     if (rw & 12u) load_pair(b.key_hi + base + lane, lim, L, 2, nq);
     __builtin_amdgcn_sched_barrier(0);
     L[nq * 64] = ~0u;                     // the all-ones plane (the previous tile may have reused it)
-    uint32_t e0 = 0, e1 = 0, e2 = 0;
+    // Eighth-turn counters: OMEGA groups alternate their ops between (e) and
+    // (f), two independent dependency chains, summed once at the end.
+    uint32_t e0 = 0, e1 = 0, e2 = 0, f0 = 0, f1 = 0, f2 = 0;
     uint64_t turns[TURNS ? 32 : 1];
 #pragma unroll
     for (int j = 0; j < (TURNS ? 32 : 1); ++j) turns[j] = 0;
@@ -234,7 +221,15 @@ __device__ __forceinline__ void bs_tile(const Buf& b, uint64_t base, uint32_t li
 #pragma unroll
             for (int u = 0; u < kBsGroup; ++u) tv[u] = plane(Lb, off_t(a[u]));
 #pragma unroll
-            for (int u = 0; u < kBsGroup; ++u) omega_add_k(e0, e1, e2, tv[u], (a[u] >> 2) & 7u);
+            for (int u = 0; u < kBsGroup; ++u) {
+              const uint32_t m0 = (uint32_t)__builtin_amdgcn_sbfe((int)a[u], 2, 1);
+              const uint32_t m1 = (uint32_t)__builtin_amdgcn_sbfe((int)a[u], 3, 1);
+              const uint32_t m2 = (uint32_t)__builtin_amdgcn_sbfe((int)a[u], 4, 1);
+              if (u & 1)
+                omega_add_m(f0, f1, f2, tv[u], m0, m1, m2);
+              else
+                omega_add_m(e0, e1, e2, tv[u], m0, m1, m2);
+            }
           } else {
             // General group: every op writes its plane t; a flip xors the
             // condition in, an eighth-turn phase op's t is a fourth condition
@@ -340,6 +335,14 @@ __device__ __forceinline__ void bs_tile(const Buf& b, uint64_t base, uint32_t li
       }
       ca = na;
       cb = nb;
+    }
+    {
+      // (e) += (f), bit-sliced, modulo 8.
+      const uint32_t c0 = e0 & f0;
+      e0 ^= f0;
+      const uint32_t c1 = (e1 & f1) | ((e1 ^ f1) & c0);
+      e1 ^= f1 ^ c0;
+      e2 ^= f2 ^ c1;
     }
     // Labels back to memory (only words some gate flips).
     __builtin_amdgcn_sched_barrier(0);
