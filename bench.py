@@ -48,6 +48,21 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+def host_cpu() -> dict:
+    """The host CPU the CPU legs ran on: model name, logical CPUs, CPUs this
+    process may use."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"model": model, "nproc": os.cpu_count(), "usable": len(os.sched_getaffinity(0))}
+
+
 def cpu_baseline(w, seconds_budget: float = 20.0):
     """The oracle as it stands, single-threaded, on a bounded prefix of the
     same workload: the initial H layer plus as many following gates as fit
@@ -75,7 +90,7 @@ def cpu_baseline(w, seconds_budget: float = 20.0):
     n_body, dt, upd = best
     return {"value": upd / dt, "unit": "updates/s", "cores": 1, "kind": "oracle",
             "sample": f"{w.name}: initial {first_body} H gates + next {n_body} gates, "
-                      f"{upd} updates in {dt:.1f} s, single thread"}
+                      f"{upd} updates in {dt:.1f} s, single thread", "host": host_cpu()}
 
 
 def cpu_parallel(h_qubits: int = 20, body: int = 1200, threads: int = 0):
@@ -110,7 +125,7 @@ def cpu_parallel(h_qubits: int = 20, body: int = 1200, threads: int = 0):
     assert upd == upd_p
     return {"value": upd / p_all, "unit": "updates/s", "cores": threads, "kind": "oracle, Sec. 5 parallel queue",
             "serial_value": upd / s_all, "speedup": round(s_all / p_all, 2),
-            "queue_speedup": round(s_body / p_body, 2), "parallel_runs": pruns,
+            "queue_speedup": round(s_body / p_body, 2), "parallel_runs": pruns, "host": host_cpu(),
             "sample": f"c2 generator at 2^{h_qubits} entries: {first} H gates + next {body} gates, {upd} updates; "
                       f"serial {s_all:.1f} s (queue {s_body:.1f} s), {threads} threads {p_all:.1f} s "
                       f"(queue {p_body:.1f} s)"}

@@ -125,4 +125,17 @@ class HostPool {
   bool stop_ = false;
 };
 
+// f(begin, end, part) over [0, n) cut into at most threads() parts of at
+// least min_part items each (one part, on the caller, when n is small).
+template <class F>
+void parallel_parts(size_t n, size_t min_part, F&& f) {
+  HostPool& pool = HostPool::get();
+  const size_t parts = std::min<size_t>(pool.threads(), n / std::max<size_t>(min_part, 1));
+  if (parts <= 1) {
+    f(size_t(0), n, size_t(0));
+    return;
+  }
+  pool.run(parts, [&](size_t p) { f(n * p / parts, n * (p + 1) / parts, p); });
+}
+
 }  // namespace sparsesim

@@ -38,16 +38,22 @@ struct RunCompiler {
   std::vector<BsOp> ops;            // bit-sliced bytecode of all MONO ops
   std::vector<uint32_t> start;      // ops of MONO op k: [start[k], start[k+1])
   std::vector<BsGateInfo> info;
+  std::vector<std::vector<BsOp>> part_ops;   // compile's per-thread output, kept between calls
 
   // Fill ops/start/info from descs.
   void compile(uint32_t nq);
   // Whether MONO ops [begin, begin+len) run bit-sliced under the policy, and
   // the run parameters (bytes_per_entry left 0).
   bool run_params(size_t begin, size_t len, uint32_t mono_mode, uint32_t min_gates, BsRun* br) const;
-  // Kernel ops of MONO ops [begin, begin+len), in groups of kBsGroup, appended to out.
-  void group(size_t begin, size_t len, std::vector<BsGroup>& out) const;
-  // Groups of the bit-sliced ops [i0, i1), appended to out.
-  void group_range(uint32_t i0, uint32_t i1, std::vector<BsGroup>& out) const;
+  // Kernel ops of MONO ops [begin, begin+len), in groups of kBsGroup, appended
+  // to out; the run constants of br (from run_params) take the phase the
+  // rewrite of uncontrolled X gates moves into them.
+  void group(size_t begin, size_t len, std::vector<BsGroup>& out, BsRun* br) const;
+  // The ops with uncontrolled X gates carried to the end of the run, and the
+  // eighth turns and turns that become run constants.
+  void defer_x(const BsOp* in, uint32_t n, std::vector<BsOp>& out, uint32_t* d_omega, uint64_t* d_turn) const;
+  // Groups of n bit-sliced ops, appended to out.
+  void group_range(const BsOp* src, uint32_t n, std::vector<BsGroup>& out) const;
 };
 
 }  // namespace sparsesim

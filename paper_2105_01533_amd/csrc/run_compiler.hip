@@ -92,19 +92,7 @@ uint64_t turn_of(const double2& m) {
 
 uint8_t word_bit(uint32_t q) { return (uint8_t)(1u << (q >> 5)); }
 
-// Run f(begin, end, part) over up to kHostThreads contiguous parts of [0, n),
-// each at least min_part long, on the host thread pool.
 constexpr unsigned kHostThreads = HostPool::kMaxThreads;
-template <class F>
-void parallel_parts(size_t n, size_t min_part, F&& f) {
-  HostPool& pool = HostPool::get();
-  const size_t parts = std::min<size_t>(pool.threads(), n / std::max<size_t>(min_part, 1));
-  if (parts <= 1) {
-    f(0, n, 0);
-    return;
-  }
-  pool.run(parts, [&](size_t p) { f(n * p / parts, n * (p + 1) / parts, p); });
-}
 
 }  // namespace
 
@@ -185,7 +173,8 @@ void RunCompiler::compile(uint32_t nq) {
   ops.clear();
   start.assign(n_mono + 1, 0);
   info.assign(n_mono, BsGateInfo{});
-  std::vector<std::vector<BsOp>> part_ops(kHostThreads);
+  part_ops.resize(kHostThreads);
+  for (auto& v : part_ops) v.clear();
   std::vector<size_t> pb(kHostThreads, 0), pe(kHostThreads, 0);
   parallel_parts(n_mono, 16384, [&](size_t b, size_t e, size_t p) {
     std::vector<BsOp>& out = part_ops[p];
@@ -243,18 +232,89 @@ bool RunCompiler::run_params(size_t begin, size_t len, uint32_t mono_mode, uint3
 // controls are preferred, because the kernel reads only those planes for them.
 // Large runs are grouped in parts on host threads (ops never move between
 // parts, so the parts' groups concatenate in order).
-void RunCompiler::group(size_t begin, size_t len, std::vector<BsGroup>& out) const {
+void RunCompiler::group(size_t begin, size_t len, std::vector<BsGroup>& out, BsRun* br) const {
   const uint32_t i0 = start[begin], i1 = start[begin + len];
-  if (i1 - i0 < 2 * 2048) {
-    group_range(i0, i1, out);
+  std::vector<BsOp> xo;
+  uint32_t d_omega = 0;
+  uint64_t d_turn = 0;
+  defer_x(ops.data() + i0, i1 - i0, xo, &d_omega, &d_turn);
+  if (br) {
+    br->g_omega = (br->g_omega + d_omega) & 7u;
+    br->g_turn += d_turn;
+  }
+  const uint32_t n = (uint32_t)xo.size();
+  if (n < 2 * 2048) {
+    group_range(xo.data(), n, out);
     return;
   }
   std::vector<std::vector<BsGroup>> parts(kHostThreads);
-  parallel_parts(i1 - i0, 2048, [&](size_t b, size_t e, size_t p) { group_range(i0 + (uint32_t)b, i0 + (uint32_t)e, parts[p]); });
+  parallel_parts(n, 2048, [&](size_t b, size_t e, size_t p) { group_range(xo.data() + b, (uint32_t)(e - b), parts[p]); });
   for (auto& v : parts) out.insert(out.end(), v.begin(), v.end());
 }
 
-void RunCompiler::group_range(uint32_t i0, uint32_t i1, std::vector<BsGroup>& out) const {
+// Uncontrolled X gates only relabel: instead of flipping a plane each time,
+// a run carries them as a pending mask P (the stored plane q is the true
+// bit q xor P_q) and applies what is left once, at the end of the run.  An op
+// meeting a pending bit is rewritten, exactly:
+//   * X on q: P_q ^= 1, no op;
+//   * CNOT with a pending control: t ^= NOT c is t ^= c followed by an X on
+//     t, so the CNOT stays and P_t toggles;
+//   * a phase op conditioned on its target bit alone, the bit pending: adding
+//     a where the bit is 0 equals adding a everywhere (a run constant) and -a
+//     where it is 1;
+//   * any other op with a pending control (or a controlled phase op with its
+//     target pending): the pending X on those planes is applied first.
+// A flip's own target may be pending: plane t ^= cond keeps t xor P_t right.
+void RunCompiler::defer_x(const BsOp* in, uint32_t n, std::vector<BsOp>& out, uint32_t* d_omega,
+                          uint64_t* d_turn) const {
+  uint64_t P[2] = {0, 0};
+  auto pending = [&](uint32_t q) { return ((P[q >> 6] >> (q & 63)) & 1ull) != 0; };
+  auto toggle = [&](uint32_t q) { P[q >> 6] ^= 1ull << (q & 63); };
+  auto apply_pending = [&](uint32_t q) {
+    if (!pending(q)) return;
+    BsOp x{};
+    x.op = kBsFlip;
+    x.target = (uint8_t)q;
+    out.push_back(x);
+    toggle(q);
+  };
+  out.reserve(n + n_qubits);
+  for (uint32_t i = 0; i < n; ++i) {
+    const BsOp& o = in[i];
+    if (o.op == kBsFlip) {
+      if (o.nctrl == 0) {
+        toggle(o.target);
+        continue;
+      }
+      if (o.nctrl == 1) {
+        out.push_back(o);
+        if (pending(o.ctrl[0])) toggle(o.target);
+        continue;
+      }
+      for (int c = 0; c < o.nctrl; ++c) apply_pending(o.ctrl[c]);
+      out.push_back(o);
+      continue;
+    }
+    if (o.nctrl == 0 && o.cmode && pending(o.target)) {
+      BsOp p = o;
+      if (o.op == kBsOmega) {
+        *d_omega += (uint32_t)o.arg;
+        p.arg = (8u - (uint32_t)o.arg) & 7u;
+      } else {
+        *d_turn += o.arg;
+        p.arg = 0ull - o.arg;
+      }
+      out.push_back(p);
+      continue;
+    }
+    for (int c = 0; c < o.nctrl; ++c) apply_pending(o.ctrl[c]);
+    if (o.cmode) apply_pending(o.target);
+    out.push_back(o);
+  }
+  for (uint32_t q = 0; q < n_qubits; ++q) apply_pending(q);
+}
+
+void RunCompiler::group_range(const BsOp* src, uint32_t n, std::vector<BsGroup>& out) const {
   const uint32_t ones = n_qubits, scratch = n_qubits + 1;
   struct Mask {
     uint64_t lo = 0, hi = 0;
@@ -270,13 +330,12 @@ void RunCompiler::group_range(uint32_t i0, uint32_t i1, std::vector<BsGroup>& ou
     uint32_t shape;   // kShapeX/CX/CCX for flips with 0..2 controls, TURN, else kShapeGeneric
     uint32_t phase;
   };
-  const uint32_t n = i1 - i0;
   if (n == 0) return;
   std::vector<Item> items(n);
   // Pending ops as a doubly linked list in op order (index n = end).
   std::vector<uint32_t> nxt(n + 1), prv(n + 1);
   for (uint32_t i = 0; i < n; ++i) {
-    const BsOp& o = ops[i0 + i];
+    const BsOp& o = src[i];
     Item& it = items[i];
     for (int c = 0; c < o.nctrl; ++c) it.r.set(o.ctrl[c]);
     if (o.cmode || o.op == kBsFlip) it.r.set(o.target);
@@ -335,7 +394,7 @@ void RunCompiler::group_range(uint32_t i0, uint32_t i1, std::vector<BsGroup>& ou
       const uint32_t j = picked[u];
       unlink(j);
       phase |= items[j].phase;
-      const BsOp& o = ops[i0 + j];
+      const BsOp& o = src[j];
       uint32_t slot[3] = {ones, ones, ones};
       for (int c = 0; c < o.nctrl; ++c) slot[c] = o.ctrl[c];
       const uint32_t t = (o.op == kBsFlip || o.cmode) ? o.target : ones;   // flip target, or a phase op's target-bit condition
@@ -358,7 +417,7 @@ void RunCompiler::group_range(uint32_t i0, uint32_t i1, std::vector<BsGroup>& ou
     grp.a[0] |= (shape == kShapeGeneric && phase ? kShapePhase : shape) << 5;
     if (shape == kShapeTurn) {
       bool bare = true;
-      for (uint32_t v = 0; v < np; ++v) bare = bare && ops[i0 + picked[v]].nctrl == 0;
+      for (uint32_t v = 0; v < np; ++v) bare = bare && src[picked[v]].nctrl == 0;
       if (bare) grp.a[1] |= kBareBit;
     }
     out.push_back(grp);

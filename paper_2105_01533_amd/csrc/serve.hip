@@ -486,7 +486,7 @@ int srv_tick(srv_t* s, uint32_t* running, uint32_t* queued) {
     const auto t_g = std::chrono::steady_clock::now();
     HostPool::get().run(to_group.size(), [&](size_t t) {
       Seg& sg = segs[to_group[t]];
-      sg.r->rc.group(sg.b, sg.len, sg.grp);
+      sg.r->rc.group(sg.b, sg.len, sg.grp, &sg.br);
     });
     s->stats.group_ms += ms_since(t_g);
   }
@@ -521,7 +521,8 @@ int srv_tick(srv_t* s, uint32_t* running, uint32_t* queued) {
           if (keep < len) {   // the whole run did not fit: regroup a prefix
             grp.clear();
             const auto t_g = std::chrono::steady_clock::now();
-            r->rc.group(b, keep, grp);
+            r->rc.run_params(b, keep, r->cfg.mono_mode, 1, &br);
+            r->rc.group(b, keep, grp, &br);
             s->stats.group_ms += ms_since(t_g);
           }
           bytes = grp.size() * sizeof(BsGroup);
@@ -540,7 +541,6 @@ int srv_tick(srv_t* s, uint32_t* running, uint32_t* queued) {
         r->i = back_to;
         r->mono_seen = b + keep;
         len = keep;
-        if (bsl) r->rc.run_params(b, len, r->cfg.mono_mode, 1, &br);
       }
       if (len == 0) continue;
       if (bsl) {

@@ -11,14 +11,17 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <cstdint>
 #include <cstdio>
 #include <cstring>
+#include <memory>
 #include <new>
 #include <string>
 #include <thread>
 #include <vector>
 
 #include "../../include/sparsesim.h"
+#include "host_pool.h"
 #include "run_compiler.h"
 #include "sim_internal.h"
 
@@ -134,6 +137,30 @@ struct DevVec {            // library-owned growable device array
   }
 };
 
+template <class T>
+struct HostVec {           // library-owned growable pinned host array (async uploads)
+  T* p = nullptr;
+  size_t n = 0;
+  // Growing frees the old array, so the stream is drained first: no copy in
+  // flight may still read it.
+  hipError_t reserve(size_t want, hipStream_t st) {
+    if (want <= n) return hipSuccess;
+    hipError_t e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return e;
+    release();
+    const size_t m = std::max<size_t>(want + want / 4, 256);
+    e = hipHostMalloc(&p, m * sizeof(T));
+    if (e == hipSuccess) n = m;
+    else p = nullptr;
+    return e;
+  }
+  void release() {
+    if (p) (void)hipHostFree(p);
+    p = nullptr;
+    n = 0;
+  }
+};
+
 }  // namespace
 
 // Kernel classes timed by the profiler.
@@ -172,6 +199,9 @@ struct sim_t {
   DevVec<MonoDesc> descs;
   DevVec<BsGroup> grp_ops;     // grouped bit-sliced ops of the current call
   std::vector<BsGroup> h_grp;
+  HostVec<MonoDesc> h_desc;    // pinned staging of descriptor uploads
+  HostVec<BsGroup> h_grp_pin;  // pinned staging of group uploads
+  std::vector<sim_gate> conv;  // sim_apply_ops: converted ops, kept between calls
   RunCompiler rc;              // MONO descriptors and bytecode of the current call
   DevVec<MeasRec> recs;
   DevVec<int32_t> outcomes;
@@ -459,6 +489,8 @@ int sim_destroy(sim_t* s) {
   if (s->stream || s->ws) (void)hipStreamSynchronize(s->stream);
   s->descs.release();
   s->grp_ops.release();
+  s->h_desc.release();
+  s->h_grp_pin.release();
   s->recs.release();
   s->outcomes.release();
   for (hipEvent_t e : s->ev_pool) (void)hipEventDestroy(e);
@@ -514,58 +546,75 @@ int sim_import_state(sim_t* s, const sim_key* keys, const sim_c64* amps, uint64_
   return SIM_OK;
 }
 
+namespace {
+
+// One standard-gate record as a sim_gate; false for an unknown kind.
+bool convert_op(const sim_op& o, sim_gate& out) {
+  const double h = M_SQRT1_2;
+  sim_gate g;
+  std::memset(&g, 0, sizeof g);
+  g.target = o.target;
+  g.ctrl.lo = o.ctrl_lo;
+  g.ctrl.hi = o.ctrl_hi;
+  g.cap = o.cap;
+  g.forced = -1;
+  for (int k = 0; k < 4; ++k) g.m[k] = sim_c64{0.0, 0.0};
+  const double c2 = std::cos(0.5 * o.param), s2 = std::sin(0.5 * o.param);
+  g.op = SIM_OP_MONO;
+  g.m[0] = g.m[1] = sim_c64{1.0, 0.0};
+  switch (o.kind) {
+    case SIM_K_X: g.flip = 1; break;
+    case SIM_K_Y: g.flip = 1; g.m[0] = sim_c64{0.0, 1.0}; g.m[1] = sim_c64{0.0, -1.0}; break;
+    case SIM_K_Z: g.m[1] = sim_c64{-1.0, 0.0}; break;
+    case SIM_K_S: g.m[1] = sim_c64{0.0, 1.0}; break;
+    case SIM_K_SDG: g.m[1] = sim_c64{0.0, -1.0}; break;
+    case SIM_K_T: g.m[1] = sim_c64{h, h}; break;
+    case SIM_K_TDG: g.m[1] = sim_c64{h, -h}; break;
+    case SIM_K_RZ: g.m[0] = sim_c64{c2, -s2}; g.m[1] = sim_c64{c2, s2}; break;
+    case SIM_K_PHASE: g.m[1] = sim_c64{std::cos(o.param), std::sin(o.param)}; break;
+    case SIM_K_H:
+      g.op = SIM_OP_U2;
+      g.m[0] = sim_c64{h, 0.0}; g.m[1] = sim_c64{h, 0.0}; g.m[2] = sim_c64{h, 0.0}; g.m[3] = sim_c64{-h, 0.0};
+      break;
+    case SIM_K_RX:
+      g.op = SIM_OP_U2;
+      g.m[0] = sim_c64{c2, 0.0}; g.m[1] = sim_c64{0.0, -s2}; g.m[2] = sim_c64{0.0, -s2}; g.m[3] = sim_c64{c2, 0.0};
+      break;
+    case SIM_K_RY:
+      g.op = SIM_OP_U2;
+      g.m[0] = sim_c64{c2, 0.0}; g.m[1] = sim_c64{-s2, 0.0}; g.m[2] = sim_c64{s2, 0.0}; g.m[3] = sim_c64{c2, 0.0};
+      break;
+    case SIM_K_MEASURE:
+      g.op = SIM_OP_MEASURE;
+      g.m[0] = g.m[1] = sim_c64{0.0, 0.0};
+      g.u = o.param;
+      g.forced = o.forced;
+      g.cap = 0;
+      break;
+    default:
+      return false;
+  }
+  out = g;
+  return true;
+}
+
+}  // namespace
+
 int sim_gates_from_ops(const sim_op* ops, size_t n, sim_gate* out) {
   if (n && (!ops || !out)) return fail(SIM_E_ARG, "null op arrays");
-  const double h = M_SQRT1_2;
-  for (size_t i = 0; i < n; ++i) {
-    const sim_op& o = ops[i];
-    sim_gate g;
-    std::memset(&g, 0, sizeof g);
-    g.target = o.target;
-    g.ctrl.lo = o.ctrl_lo;
-    g.ctrl.hi = o.ctrl_hi;
-    g.cap = o.cap;
-    g.forced = -1;
-    for (int k = 0; k < 4; ++k) g.m[k] = sim_c64{0.0, 0.0};
-    const double c2 = std::cos(0.5 * o.param), s2 = std::sin(0.5 * o.param);
-    g.op = SIM_OP_MONO;
-    g.m[0] = g.m[1] = sim_c64{1.0, 0.0};
-    switch (o.kind) {
-      case SIM_K_X: g.flip = 1; break;
-      case SIM_K_Y: g.flip = 1; g.m[0] = sim_c64{0.0, 1.0}; g.m[1] = sim_c64{0.0, -1.0}; break;
-      case SIM_K_Z: g.m[1] = sim_c64{-1.0, 0.0}; break;
-      case SIM_K_S: g.m[1] = sim_c64{0.0, 1.0}; break;
-      case SIM_K_SDG: g.m[1] = sim_c64{0.0, -1.0}; break;
-      case SIM_K_T: g.m[1] = sim_c64{h, h}; break;
-      case SIM_K_TDG: g.m[1] = sim_c64{h, -h}; break;
-      case SIM_K_RZ: g.m[0] = sim_c64{c2, -s2}; g.m[1] = sim_c64{c2, s2}; break;
-      case SIM_K_PHASE: g.m[1] = sim_c64{std::cos(o.param), std::sin(o.param)}; break;
-      case SIM_K_H:
-        g.op = SIM_OP_U2;
-        g.m[0] = sim_c64{h, 0.0}; g.m[1] = sim_c64{h, 0.0}; g.m[2] = sim_c64{h, 0.0}; g.m[3] = sim_c64{-h, 0.0};
-        break;
-      case SIM_K_RX:
-        g.op = SIM_OP_U2;
-        g.m[0] = sim_c64{c2, 0.0}; g.m[1] = sim_c64{0.0, -s2}; g.m[2] = sim_c64{0.0, -s2}; g.m[3] = sim_c64{c2, 0.0};
-        break;
-      case SIM_K_RY:
-        g.op = SIM_OP_U2;
-        g.m[0] = sim_c64{c2, 0.0}; g.m[1] = sim_c64{-s2, 0.0}; g.m[2] = sim_c64{s2, 0.0}; g.m[3] = sim_c64{c2, 0.0};
-        break;
-      case SIM_K_MEASURE:
-        g.op = SIM_OP_MEASURE;
-        g.m[0] = g.m[1] = sim_c64{0.0, 0.0};
-        g.u = o.param;
-        g.forced = o.forced;
-        g.cap = 0;
-        break;
-      default: {
-        char msg[96];
-        snprintf(msg, sizeof msg, "op %zu: unknown gate kind %u", i, o.kind);
-        return fail(SIM_E_ARG, msg);
+  std::vector<size_t> bad(HostPool::kMaxThreads, SIZE_MAX);
+  parallel_parts(n, 16384, [&](size_t b, size_t e, size_t p) {
+    for (size_t i = b; i < e; ++i)
+      if (!convert_op(ops[i], out[i])) {
+        bad[p] = i;
+        return;
       }
-    }
-    out[i] = g;
+  });
+  const size_t i = *std::min_element(bad.begin(), bad.end());
+  if (i != SIZE_MAX) {
+    char msg[96];
+    snprintf(msg, sizeof msg, "op %zu: unknown gate kind %u", i, ops[i].kind);
+    return fail(SIM_E_ARG, msg);
   }
   return SIM_OK;
 }
@@ -579,17 +628,33 @@ int sim_apply_gates(sim_t* s, const sim_gate* gates, size_t n, int32_t* outcomes
   const bool bs_allowed = s->cfg.mono_mode != SIM_MONO_DIRECT;
   {
     HTimer t_(s, KC_H_PREPARE);
-    // Validate everything first: an invalid op applies nothing.
-    for (size_t i = 0; i < n; ++i) {
-      int rc = validate(s, gates[i], i);
-      if (rc) return rc;
-      if (gates[i].op == SIM_OP_MONO) ++n_mono;
-      if (gates[i].op == SIM_OP_MEASURE) ++n_meas;
+    // Validate everything first (an invalid op applies nothing), count the
+    // classes and build the phase/permutation descriptors, on the host pool.
+    std::vector<size_t> bad(HostPool::kMaxThreads, SIZE_MAX), pm(HostPool::kMaxThreads + 1, 0),
+        pmeas(HostPool::kMaxThreads, 0);
+    parallel_parts(n, 16384, [&](size_t b, size_t e, size_t p) {
+      std::string why;
+      for (size_t i = b; i < e; ++i) {
+        if (!gate_valid(s->cfg.n_qubits, gates[i], &why)) {
+          bad[p] = i;
+          return;
+        }
+        pm[p + 1] += gates[i].op == SIM_OP_MONO;
+        pmeas[p] += gates[i].op == SIM_OP_MEASURE;
+      }
+    });
+    const size_t first_bad = *std::min_element(bad.begin(), bad.end());
+    if (first_bad != SIZE_MAX) return validate(s, gates[first_bad], first_bad);
+    for (size_t p = 0; p < HostPool::kMaxThreads; ++p) {
+      pm[p + 1] += pm[p];
+      n_meas += pmeas[p];
     }
-    // Stage the phase/permutation descriptors in one upload.
+    n_mono = pm[HostPool::kMaxThreads];
     s->rc.descs.resize(n_mono);
-    for (size_t i = 0, k = 0; i < n; ++i)
-      if (gates[i].op == SIM_OP_MONO) s->rc.descs[k++] = mono_desc(gates[i]);
+    parallel_parts(n, 16384, [&](size_t b, size_t e, size_t p) {
+      for (size_t i = b, k = pm[p]; i < e; ++i)
+        if (gates[i].op == SIM_OP_MONO) s->rc.descs[k++] = mono_desc(gates[i]);
+    });
   }
   // Bit-sliced bytecode of every phase/permutation op (used by eligible
   // runs), compiled on a host thread while the first ops run; joined before
@@ -604,9 +669,9 @@ int sim_apply_gates(sim_t* s, const sim_gate* gates, size_t n, int32_t* outcomes
   HIP_TRY(s->descs.reserve(n_mono));
   HIP_TRY(s->recs.reserve(n_meas));
   HIP_TRY(s->outcomes.reserve(n_meas));
-  if (n_mono)
-    HIP_TRY(hipMemcpyAsync(s->descs.p, s->rc.descs.data(), n_mono * sizeof(MonoDesc), hipMemcpyHostToDevice,
-                           s->stream));
+  // Descriptors are uploaded run by run, for the runs that take the
+  // per-entry kernel, from pinned staging (asynchronous).
+  HIP_TRY(s->h_desc.reserve(n_mono, s->stream));
   // Grouped kernel ops of the bit-sliced runs, appended run by run.  A run
   // of k > 0 ops has at most k + 1 groups (every group but an evening pad
   // holds an op), so reserving two groups per op before the first run keeps
@@ -622,6 +687,7 @@ int sim_apply_gates(sim_t* s, const sim_gate* gates, size_t n, int32_t* outcomes
     compiled = true;
     s->h_grp.reserve(2 * s->rc.ops.size() + 2);
     HIP_TRY(s->grp_ops.reserve(2 * s->rc.ops.size() + 2));
+    HIP_TRY(s->h_grp_pin.reserve(2 * s->rc.ops.size() + 2, s->stream));
     return SIM_OK;
   };
 
@@ -649,18 +715,23 @@ int sim_apply_gates(sim_t* s, const sim_gate* gates, size_t n, int32_t* outcomes
       const size_t g0 = s->h_grp.size();
       {
         HTimer tg_(s, KC_H_GROUP);
-        s->rc.group(run_begin, run_len, s->h_grp);
+        s->rc.group(run_begin, run_len, s->h_grp, &br);
       }
       const size_t ng = s->h_grp.size() - g0;
       if (s->h_grp.size() > s->grp_ops.n) return fail(SIM_E_STATE, "bit-sliced op groups exceed their buffer");
-      if (ng)
-        HIP_TRY(hipMemcpyAsync(s->grp_ops.p + g0, s->h_grp.data() + g0, ng * sizeof(BsGroup), hipMemcpyHostToDevice,
+      if (ng) {
+        std::memcpy(s->h_grp_pin.p + g0, s->h_grp.data() + g0, ng * sizeof(BsGroup));
+        HIP_TRY(hipMemcpyAsync(s->grp_ops.p + g0, s->h_grp_pin.p + g0, ng * sizeof(BsGroup), hipMemcpyHostToDevice,
                                s->stream));
+      }
       KTimer t_(s, KC_MONO);
       launch_mono_bs(s->stream, s->buf[s->cur], d_nnz(s, s->cur), s->grp_ops.p + g0, (uint32_t)ng, br, s->ctl,
                      bs_grid(s, ub));
       st.bitslice_passes++;
     } else {
+      std::memcpy(s->h_desc.p + run_begin, s->rc.descs.data() + run_begin, run_len * sizeof(MonoDesc));
+      HIP_TRY(hipMemcpyAsync(s->descs.p + run_begin, s->h_desc.p + run_begin, run_len * sizeof(MonoDesc),
+                             hipMemcpyHostToDevice, s->stream));
       KTimer t_(s, KC_MONO);
       launch_mono(s->stream, s->wide, s->buf[s->cur], d_nnz(s, s->cur), s->descs.p + run_begin, (uint32_t)run_len,
                   run_flags, run_bpe, s->ctl, mono_grid(s, ub), block_of(s));
@@ -754,10 +825,17 @@ int sim_apply_gates(sim_t* s, const sim_gate* gates, size_t n, int32_t* outcomes
 }
 
 int sim_apply_ops(sim_t* s, const sim_op* ops, size_t n, int32_t* outcomes, sim_stats* stats) {
-  std::vector<sim_gate> g(n);
-  int rc = sim_gates_from_ops(ops, n, g.data());
+  if (!s) return fail(SIM_E_ARG, "null handle");
+  // The conversion buffer stays with the handle, so repeated calls reuse
+  // memory that is already mapped.
+  try {
+    if (s->conv.size() < n) s->conv.resize(n);
+  } catch (const std::bad_alloc&) {
+    return fail(SIM_E_NOMEM, "host allocation of the converted ops failed");
+  }
+  int rc = sim_gates_from_ops(ops, n, s->conv.data());
   if (rc) return rc;
-  return sim_apply_gates(s, g.data(), n, outcomes, stats);
+  return sim_apply_gates(s, s->conv.data(), n, outcomes, stats);
 }
 
 int sim_apply_pauli(sim_t* s, const sim_pauli* terms, size_t n, sim_stats* stats) {

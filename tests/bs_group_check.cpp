@@ -210,7 +210,8 @@ int main(int argc, char** argv) {
     }
     rc.start = {0u, nops};
     std::vector<BsGroup> gops;
-    rc.group(0, 1, gops);
+    BsRun br{};
+    rc.group(0, 1, gops, &br);
 
     State ref, got;
     ref.P.resize((size_t)(nq + 2) * kWords);
@@ -225,6 +226,10 @@ int main(int argc, char** argv) {
       printf("case %d (nq %u, ops %u): %s\n", c, nq, nops, why.c_str());
       return 1;
     }
+    // Phase moved into the run constants by the rewrite of uncontrolled X
+    // gates applies to every entry.
+    for (auto& k : got.omega) k = (uint8_t)((k + br.g_omega) & 7u);
+    for (auto& t : got.turns) t += br.g_turn;
     for (uint32_t q = 0; q <= nq; ++q)
       for (int w = 0; w < kWords; ++w)
         if (ref.p(q, w) != got.p(q, w)) {
