@@ -177,14 +177,18 @@ void RunCompiler::compile(uint32_t nq) {
   for (auto& v : part_ops) v.clear();
   std::vector<size_t> pb(kHostThreads, 0), pe(kHostThreads, 0);
   parallel_parts(n_mono, 16384, [&](size_t b, size_t e, size_t p) {
-    std::vector<BsOp>& out = part_ops[p];
+    // Appends go to a vector on this thread's stack (neighbouring vectors in
+    // part_ops share cache lines); its storage is kept in part_ops between calls.
+    std::vector<BsOp> out;
+    out.swap(part_ops[p]);
     out.reserve(2 * (e - b));
-    pb[p] = b;
-    pe[p] = e;
     for (size_t k = b; k < e; ++k) {
       start[k] = (uint32_t)out.size();   // local to the part until the parts are joined
       compile_one(descs[k], info[k], out);
     }
+    part_ops[p].swap(out);
+    pb[p] = b;
+    pe[p] = e;
   });
   size_t total = 0;
   for (auto& v : part_ops) total += v.size();
@@ -248,7 +252,11 @@ void RunCompiler::group(size_t begin, size_t len, std::vector<BsGroup>& out, BsR
     return;
   }
   std::vector<std::vector<BsGroup>> parts(kHostThreads);
-  parallel_parts(n, 2048, [&](size_t b, size_t e, size_t p) { group_range(xo.data() + b, (uint32_t)(e - b), parts[p]); });
+  parallel_parts(n, 2048, [&](size_t b, size_t e, size_t p) {
+    std::vector<BsGroup> mine;   // on this thread's stack: the parts' vectors share cache lines
+    group_range(xo.data() + b, (uint32_t)(e - b), mine);
+    parts[p].swap(mine);
+  });
   for (auto& v : parts) out.insert(out.end(), v.begin(), v.end());
 }
 

@@ -167,9 +167,9 @@ struct HostVec {           // library-owned growable pinned host array (async up
 // Host classes (wall clock, always measured): validation and op compilation
 // at the start of a call, grouping of bit-sliced runs, and time blocked in
 // stream synchronisations.
-enum KClass { KC_MONO = 0, KC_FILL, KC_BUILD, KC_U2_COUNT, KC_SCAN, KC_U2_WRITE, KC_M_REDUCE, KC_M_DECIDE,
-              KC_M_WRITE, KC_KERNELS, KC_H_PREPARE = KC_KERNELS, KC_H_GROUP, KC_H_SYNC, KC_COUNT };
-static const char* const kClassNames[KC_COUNT] = {"mono_pass", "index_fill", "index_build", "u2_count",
+enum KClass { KC_MONO = 0, KC_FILL, KC_BUILD, KC_U2_PROBE, KC_U2_COUNT, KC_SCAN, KC_U2_WRITE, KC_M_REDUCE,
+              KC_M_DECIDE, KC_M_WRITE, KC_KERNELS, KC_H_PREPARE = KC_KERNELS, KC_H_GROUP, KC_H_SYNC, KC_COUNT };
+static const char* const kClassNames[KC_COUNT] = {"mono_pass", "index_fill", "index_build", "u2_probe", "u2_count",
                                                   "block_scan", "u2_write", "measure_reduce", "measure_decide",
                                                   "measure_write", "host_prepare", "host_group", "host_sync"};
 
@@ -340,12 +340,17 @@ int run_u2(sim_t* s, const sim_gate& g, bool* over) {
   }
   {
     KTimer t_(s, KC_BUILD);
-    launch_index_build(s->stream, s->wide, s->buf[s->cur], nnz_in, s->table, slots - 1, flat_grid(ub), 256);
+    launch_index_build(s->stream, s->wide, s->buf[s->cur], nnz_in, s->table, slots - 1, d, s->partner,
+                       flat_grid(ub), 256);
+  }
+  {
+    KTimer t_(s, KC_U2_PROBE);
+    launch_u2_probe(s->stream, s->wide, s->buf[s->cur], nnz_in, s->table, slots - 1, d, s->partner, flat_grid(ub),
+                    256);
   }
   {
     KTimer t_(s, KC_U2_COUNT);
-    launch_u2_count(s->stream, s->wide, s->buf[s->cur], nnz_in, s->table, slots - 1, d, s->partner, s->bs.tot,
-                    s->ctl, G, 256);
+    launch_u2_count(s->stream, s->wide, s->buf[s->cur], nnz_in, d, s->partner, s->bs.tot, s->ctl, G, 256);
   }
   {
     KTimer t_(s, KC_SCAN);
@@ -634,14 +639,17 @@ int sim_apply_gates(sim_t* s, const sim_gate* gates, size_t n, int32_t* outcomes
         pmeas(HostPool::kMaxThreads, 0);
     parallel_parts(n, 16384, [&](size_t b, size_t e, size_t p) {
       std::string why;
+      size_t mono = 0, meas = 0;   // counted locally: the shared arrays are written once per part
       for (size_t i = b; i < e; ++i) {
         if (!gate_valid(s->cfg.n_qubits, gates[i], &why)) {
           bad[p] = i;
           return;
         }
-        pm[p + 1] += gates[i].op == SIM_OP_MONO;
-        pmeas[p] += gates[i].op == SIM_OP_MEASURE;
+        mono += gates[i].op == SIM_OP_MONO;
+        meas += gates[i].op == SIM_OP_MEASURE;
       }
+      pm[p + 1] = mono;
+      pmeas[p] = meas;
     });
     const size_t first_bad = *std::min_element(bad.begin(), bad.end());
     if (first_bad != SIZE_MAX) return validate(s, gates[first_bad], first_bad);
@@ -691,6 +699,24 @@ int sim_apply_gates(sim_t* s, const sim_gate* gates, size_t n, int32_t* outcomes
     return SIM_OK;
   };
 
+  // Speculative grouping.  Before the host blocks to read an entry count
+  // for a cap decision (the GPU drains meanwhile), a helper thread groups the
+  // run that follows if this and every later capped branching gate up to the
+  // next stop are skipped -- the usual case once the state sits at its cap.
+  // When the run then ends exactly there, its groups are ready and the GPU
+  // does not wait for the host to group it; otherwise they are dropped.
+  struct Spec {
+    std::thread t;
+    bool ready = false;          // t has run (or runs) for [begin, begin + len)
+    size_t begin = 0, len = 0;
+    std::vector<BsGroup> grp;
+    BsRun delta{};               // run constants the grouping moved (see RunCompiler::group)
+    void join() {
+      if (t.joinable()) t.join();
+    }
+    ~Spec() { join(); }
+  } spec;
+
   int result = SIM_OK;
   size_t run_begin = 0, run_len = 0, mono_seen = 0, meas_seen = 0;
   auto flush = [&]() -> int {
@@ -715,7 +741,15 @@ int sim_apply_gates(sim_t* s, const sim_gate* gates, size_t n, int32_t* outcomes
       const size_t g0 = s->h_grp.size();
       {
         HTimer tg_(s, KC_H_GROUP);
-        s->rc.group(run_begin, run_len, s->h_grp, &br);
+        if (spec.ready && spec.begin == run_begin && spec.len == run_len) {
+          spec.join();
+          s->h_grp.insert(s->h_grp.end(), spec.grp.begin(), spec.grp.end());
+          br.g_omega = (br.g_omega + spec.delta.g_omega) & 7u;
+          br.g_turn += spec.delta.g_turn;
+          spec.ready = false;
+        } else {
+          s->rc.group(run_begin, run_len, s->h_grp, &br);
+        }
       }
       const size_t ng = s->h_grp.size() - g0;
       if (s->h_grp.size() > s->grp_ops.n) return fail(SIM_E_STATE, "bit-sliced op groups exceed their buffer");
@@ -742,6 +776,34 @@ int sim_apply_gates(sim_t* s, const sim_gate* gates, size_t n, int32_t* outcomes
     run_len = 0;
     return SIM_OK;
   };
+  // Start the speculative grouping of the run that would follow a skip of
+  // capped gate i (see Spec).
+  auto speculate = [&](size_t i) -> int {
+    if (!bs_allowed) return SIM_OK;
+    int rc = ensure_compiled();
+    if (rc) return rc;
+    const size_t begin = run_len ? run_begin : mono_seen;
+    size_t len = run_len;
+    for (size_t j = i + 1; j < n && len < s->cfg.fuse_max; ++j) {
+      const sim_gate& h = gates[j];
+      if (h.op == SIM_OP_MONO) ++len;
+      else if (h.op != SIM_OP_U2 || !h.cap) break;
+    }
+    if (len == 0) return SIM_OK;
+    BsRun probe;
+    if (!s->rc.run_params(begin, len, s->cfg.mono_mode, s->cfg.bs_min_gates, &probe)) return SIM_OK;
+    if (spec.ready && spec.begin == begin && spec.len == len) return SIM_OK;
+    spec.join();
+    spec.ready = true;
+    spec.begin = begin;
+    spec.len = len;
+    spec.t = std::thread([s, &spec]() {
+      spec.grp.clear();
+      spec.delta = BsRun{};
+      s->rc.group(spec.begin, spec.len, spec.grp, &spec.delta);
+    });
+    return SIM_OK;
+  };
   size_t i = 0;
   for (; i < n; ++i) {
     const sim_gate& g = gates[i];
@@ -761,7 +823,9 @@ int sim_apply_gates(sim_t* s, const sim_gate* gates, size_t n, int32_t* outcomes
       if (g.cap && 2 * (s->nnz_known ? s->nnz_exact : s->nnz_ub) > g.cap) {
         uint64_t nnz = s->nnz_exact;
         if (!s->nnz_known) {
-          int rc = read_nnz(s, &nnz);
+          int rc = speculate(i);
+          if (rc) return rc;
+          rc = read_nnz(s, &nnz);
           if (rc) return rc;
           st.host_syncs++;
         }

@@ -215,9 +215,11 @@ void launch_mono_bs(hipStream_t st, Buf b, const uint64_t* nnz, const BsGroup* g
 void launch_fill(hipStream_t st, uint64_t* p, uint64_t v, uint64_t n);
 void launch_copy16(hipStream_t st, void* dst, const void* src, uint64_t n16);
 void launch_index_build(hipStream_t st, bool wide, Buf b, const uint64_t* nnz, uint64_t* table, uint64_t mask,
-                        int grid, int block);
-void launch_u2_count(hipStream_t st, bool wide, Buf b, const uint64_t* nnz, const uint64_t* table, uint64_t mask,
-                     const U2Desc& d, uint32_t* partner, uint32_t* tot, Ctl* ctl, int grid, int block);
+                        const U2Desc& d, uint32_t* partner, int grid, int block);
+void launch_u2_probe(hipStream_t st, bool wide, Buf b, const uint64_t* nnz, const uint64_t* table, uint64_t mask,
+                     const U2Desc& d, uint32_t* partner, int grid, int block);
+void launch_u2_count(hipStream_t st, bool wide, Buf b, const uint64_t* nnz, const U2Desc& d, const uint32_t* partner,
+                     uint32_t* tot, Ctl* ctl, int grid, int block);
 void launch_scan(hipStream_t st, uint32_t* tot, int nblocks, uint64_t* nnz_out, Ctl* ctl);
 void launch_u2_write(hipStream_t st, bool wide, Buf in, Buf out, const uint64_t* nnz, const uint32_t* partner,
                      const uint32_t* off, const U2Desc& d, int grid, int block);

@@ -167,13 +167,23 @@ __global__ __launch_bounds__(256) void k_mono(Buf b, const uint64_t* __restrict_
 // Hash index: open addressing with linear probing over a power-of-two table
 // of 64-bit slots (fingerprint << 32 | entry index), claimed with 64-bit CAS.
 // Labels are unique, so an insert never meets its own label.
+//
+// Only the entries a partner look-up can ask for are indexed: those under
+// the op's controls with the pivot bit clear (the look-ups come from their
+// partners, whose pivot bit is set).  Every entry's partner slot starts empty.
 template <bool WIDE>
 __global__ __launch_bounds__(256) void k_index_build(Buf b, const uint64_t* __restrict__ nnz_p,
-                                                     unsigned long long* table, uint64_t mask) {
+                                                     unsigned long long* table, uint64_t mask, U2Desc d,
+                                                     uint32_t* __restrict__ partner) {
   const uint64_t n = *nnz_p;
   for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x) {
+    partner[i] = kNoPartner;
     const uint64_t lo = b.key_lo[i];
     const uint64_t hi = WIDE ? b.key_hi[i] : 0ull;
+    bool c = (lo & d.ctrl_lo) == d.ctrl_lo;
+    if (WIDE) c = c && ((hi & d.ctrl_hi) == d.ctrl_hi);
+    const uint64_t w = (WIDE && d.target >= 64) ? hi : lo;
+    if (!c || ((w >> (d.target & 63)) & 1ull)) continue;
     const uint64_t h = hash_label(lo, hi);
     const unsigned long long val = ((h >> 32) << 32) | i;
     uint64_t slot = h & mask;
@@ -200,6 +210,29 @@ __device__ __forceinline__ uint32_t find_label(const Buf& b, const uint64_t* __r
     slot = (slot + 1) & mask;
   }
   return kNoPartner;
+}
+
+// Partner look-up (Sec. 3.1: at most one per label): each entry under the
+// controls with the pivot bit set looks up label ^ x among the indexed
+// entries; when found, both entries record each other (a pivot-0 entry has at
+// most one such partner, so the writes never collide).
+template <bool WIDE>
+__global__ __launch_bounds__(256) void k_u2_probe(Buf b, const uint64_t* __restrict__ nnz_p,
+                                                  const uint64_t* __restrict__ table, uint64_t mask, U2Desc d,
+                                                  uint32_t* __restrict__ partner) {
+  const uint64_t n = *nnz_p;
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x) {
+    const uint64_t lo = b.key_lo[i];
+    const uint64_t hi = WIDE ? b.key_hi[i] : 0ull;
+    bool c = (lo & d.ctrl_lo) == d.ctrl_lo;
+    if (WIDE) c = c && ((hi & d.ctrl_hi) == d.ctrl_hi);
+    const uint64_t w = (WIDE && d.target >= 64) ? hi : lo;
+    if (!c || !((w >> (d.target & 63)) & 1ull)) continue;
+    const uint32_t j = find_label<WIDE>(b, table, mask, lo ^ d.x_lo, WIDE ? (hi ^ d.x_hi) : 0ull);
+    if (j == kNoPartner) continue;
+    partner[i] = j;
+    partner[j] = (uint32_t)i;
+  }
 }
 
 template <bool WIDE>
@@ -253,9 +286,8 @@ __device__ __forceinline__ U2Out u2_eval(const Buf& b, const U2Desc& d, uint64_t
 }
 
 template <bool WIDE>
-__global__ __launch_bounds__(256) void k_u2_count(Buf b, const uint64_t* __restrict__ nnz_p,
-                                                  const uint64_t* __restrict__ table, uint64_t mask, U2Desc d,
-                                                  uint32_t* __restrict__ partner, uint32_t* __restrict__ tot,
+__global__ __launch_bounds__(256) void k_u2_count(Buf b, const uint64_t* __restrict__ nnz_p, U2Desc d,
+                                                  const uint32_t* __restrict__ partner, uint32_t* __restrict__ tot,
                                                   Ctl* ctl) {
   __shared__ uint32_t sh[256];
   const uint64_t n = *nnz_p;
@@ -265,12 +297,7 @@ __global__ __launch_bounds__(256) void k_u2_count(Buf b, const uint64_t* __restr
   for (uint64_t i = begin + threadIdx.x; i < end; i += blockDim.x) {
     const uint64_t lo = b.key_lo[i];
     const uint64_t hi = WIDE ? b.key_hi[i] : 0ull;
-    bool c = (lo & d.ctrl_lo) == d.ctrl_lo;
-    if (WIDE) c = c && ((hi & d.ctrl_hi) == d.ctrl_hi);
-    uint32_t j = kNoPartner;
-    if (c) j = find_label<WIDE>(b, table, mask, lo ^ d.x_lo, WIDE ? (hi ^ d.x_hi) : 0ull);
-    partner[i] = j;
-    const U2Out r = u2_eval<WIDE>(b, d, lo, hi, b.amp[i], j);
+    const U2Out r = u2_eval<WIDE>(b, d, lo, hi, b.amp[i], partner[i]);
     if (r.mode == 0) {
       const uint32_t k = survives(r.o0, d.eps) ? 1u : 0u;
       emit += k;
@@ -538,20 +565,28 @@ void launch_mono(hipStream_t st, bool wide, Buf b, const uint64_t* nnz, const Mo
 }
 
 void launch_index_build(hipStream_t st, bool wide, Buf b, const uint64_t* nnz, uint64_t* table, uint64_t mask,
-                        int grid, int block) {
+                        const U2Desc& d, uint32_t* partner, int grid, int block) {
   auto* t = reinterpret_cast<unsigned long long*>(table);
   if (wide)
-    hipLaunchKernelGGL(k_index_build<true>, dim3(grid), dim3(block), 0, st, b, nnz, t, mask);
+    hipLaunchKernelGGL(k_index_build<true>, dim3(grid), dim3(block), 0, st, b, nnz, t, mask, d, partner);
   else
-    hipLaunchKernelGGL(k_index_build<false>, dim3(grid), dim3(block), 0, st, b, nnz, t, mask);
+    hipLaunchKernelGGL(k_index_build<false>, dim3(grid), dim3(block), 0, st, b, nnz, t, mask, d, partner);
 }
 
-void launch_u2_count(hipStream_t st, bool wide, Buf b, const uint64_t* nnz, const uint64_t* table, uint64_t mask,
-                     const U2Desc& d, uint32_t* partner, uint32_t* tot, Ctl* ctl, int grid, int block) {
+void launch_u2_probe(hipStream_t st, bool wide, Buf b, const uint64_t* nnz, const uint64_t* table, uint64_t mask,
+                     const U2Desc& d, uint32_t* partner, int grid, int block) {
   if (wide)
-    hipLaunchKernelGGL(k_u2_count<true>, dim3(grid), dim3(block), 0, st, b, nnz, table, mask, d, partner, tot, ctl);
+    hipLaunchKernelGGL(k_u2_probe<true>, dim3(grid), dim3(block), 0, st, b, nnz, table, mask, d, partner);
   else
-    hipLaunchKernelGGL(k_u2_count<false>, dim3(grid), dim3(block), 0, st, b, nnz, table, mask, d, partner, tot, ctl);
+    hipLaunchKernelGGL(k_u2_probe<false>, dim3(grid), dim3(block), 0, st, b, nnz, table, mask, d, partner);
+}
+
+void launch_u2_count(hipStream_t st, bool wide, Buf b, const uint64_t* nnz, const U2Desc& d, const uint32_t* partner,
+                     uint32_t* tot, Ctl* ctl, int grid, int block) {
+  if (wide)
+    hipLaunchKernelGGL(k_u2_count<true>, dim3(grid), dim3(block), 0, st, b, nnz, d, partner, tot, ctl);
+  else
+    hipLaunchKernelGGL(k_u2_count<false>, dim3(grid), dim3(block), 0, st, b, nnz, d, partner, tot, ctl);
 }
 
 void launch_scan(hipStream_t st, uint32_t* tot, int nblocks, uint64_t* nnz_out, Ctl* ctl) {
