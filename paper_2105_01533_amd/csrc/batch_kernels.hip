@@ -215,7 +215,12 @@ __global__ __launch_bounds__(256) void kb_build(const BTick* __restrict__ hdr, c
     const uint64_t e1 = e0 + kChunk < it.nnz ? e0 + kChunk : it.nnz;
     auto* table = reinterpret_cast<unsigned long long*>(it.table);
     for (uint64_t e = e0 + threadIdx.x; e < e1; e += blockDim.x) {
+      // Only entries under the controls with the pivot bit clear are indexed
+      // (the partner look-ups come from the pivot-1 entries); every partner
+      // slot starts empty.
+      it.partner[e] = kNoPartner;
       const uint64_t lo = it.in.key_lo[e], hi = it.wide ? it.in.key_hi[e] : 0ull;
+      if (!ctrl_ok(it.u2, lo, hi, it.wide) || pivot_set2(it.u2, lo, hi, it.wide)) continue;
       const uint64_t h = hash_label2(lo, hi);
       const unsigned long long val = ((h >> 32) << 32) | e;
       uint64_t slot = h & it.mask;
@@ -223,6 +228,31 @@ __global__ __launch_bounds__(256) void kb_build(const BTick* __restrict__ hdr, c
         if (atomicCAS(&table[slot], (unsigned long long)kEmptySlot, val) == kEmptySlot) break;
         slot = (slot + 1) & it.mask;
       }
+    }
+  }
+}
+
+// Each entry under the controls with the pivot bit set looks up label ^ x;
+// a hit records the two entries as each other's partner.
+__global__ __launch_bounds__(256) void kb_u2_probe(const BTick* __restrict__ hdr, const BItem* __restrict__ items,
+                                                   const uint32_t* __restrict__ units) {
+  const int n = (int)hdr->n_u2;
+  if (n == 0) return;
+  const BItem* u2 = items + hdr->n_mono;
+  const uint32_t* u0 = units + hdr->build_u0;
+  const uint32_t total = u0[n];
+  for (uint32_t u = blockIdx.x; u < total; u += gridDim.x) {
+    const int i = find_item(u0, n, u);
+    const BItem& it = u2[i];
+    const uint64_t e0 = (uint64_t)(u - u0[i]) * kChunk;
+    const uint64_t e1 = e0 + kChunk < it.nnz ? e0 + kChunk : it.nnz;
+    for (uint64_t e = e0 + threadIdx.x; e < e1; e += blockDim.x) {
+      const uint64_t lo = it.in.key_lo[e], hi = it.wide ? it.in.key_hi[e] : 0ull;
+      if (!ctrl_ok(it.u2, lo, hi, it.wide) || !pivot_set2(it.u2, lo, hi, it.wide)) continue;
+      const uint32_t j = find_label2(it, lo ^ it.u2.x_lo, it.wide ? (hi ^ it.u2.x_hi) : 0ull);
+      if (j == kNoPartner) continue;
+      it.partner[e] = j;
+      it.partner[j] = (uint32_t)e;
     }
   }
 }
@@ -244,11 +274,8 @@ __global__ __launch_bounds__(256) void kb_u2_count(const BTick* __restrict__ hdr
     uint32_t emit = 0;
     for (uint64_t e = e0 + threadIdx.x; e < e1; e += blockDim.x) {
       const uint64_t lo = it.in.key_lo[e], hi = it.wide ? it.in.key_hi[e] : 0ull;
-      uint32_t j = kNoPartner;
-      if (ctrl_ok(it.u2, lo, hi, it.wide)) j = find_label2(it, lo ^ it.u2.x_lo, it.wide ? (hi ^ it.u2.x_hi) : 0ull);
-      it.partner[e] = j;
       double2 o0, o1;
-      const int mode = u2_entry(it, lo, hi, it.in.amp[e], j, &o0, &o1);
+      const int mode = u2_entry(it, lo, hi, it.in.amp[e], it.partner[e], &o0, &o1);
       if (mode == 0) emit += survives2(o0, it.u2.eps) ? 1u : 0u;
       else if (mode == 1) emit += (survives2(o0, it.u2.eps) ? 1u : 0u) + (survives2(o1, it.u2.eps) ? 1u : 0u);
     }
@@ -511,6 +538,7 @@ void launch_batch_tick(hipStream_t st, const BTick* hdr, const BItem* items, con
   hipLaunchKernelGGL(kb_mono, dim3(grid), dim3(64), lds, st, hdr, items, units);
   hipLaunchKernelGGL(kb_fill, dim3(grid), dim3(256), 0, st, hdr, items, units);
   hipLaunchKernelGGL(kb_build, dim3(grid), dim3(256), 0, st, hdr, items, units);
+  hipLaunchKernelGGL(kb_u2_probe, dim3(grid), dim3(256), 0, st, hdr, items, units);
   hipLaunchKernelGGL(kb_u2_count, dim3(grid), dim3(256), 0, st, hdr, items, units);
   hipLaunchKernelGGL(kb_u2_scan, dim3(grid), dim3(256), 0, st, hdr, items, units);
   hipLaunchKernelGGL(kb_u2_write, dim3(grid), dim3(256), 0, st, hdr, items, units);

@@ -15,6 +15,7 @@
 #include <cstdio>
 #include <cstring>
 #include <memory>
+#include <mutex>
 #include <new>
 #include <string>
 #include <thread>
@@ -137,27 +138,68 @@ struct DevVec {            // library-owned growable device array
   }
 };
 
-template <class T>
-struct HostVec {           // library-owned growable pinned host array (async uploads)
-  T* p = nullptr;
-  size_t n = 0;
-  // Growing frees the old array, so the stream is drained first: no copy in
-  // flight may still read it.
-  hipError_t reserve(size_t want, hipStream_t st) {
-    if (want <= n) return hipSuccess;
-    hipError_t e = hipStreamSynchronize(st);
-    if (e != hipSuccess) return e;
-    release();
-    const size_t m = std::max<size_t>(want + want / 4, 256);
-    e = hipHostMalloc(&p, m * sizeof(T));
-    if (e == hipSuccess) n = m;
-    else p = nullptr;
-    return e;
+// Pinned host staging for asynchronous uploads, shared by all handles of the
+// process: a call borrows buffers and gives them back when it returns (after
+// its stream has drained, so no copy in flight still reads them).  Handles
+// that come and go -- one per request -- then pay no pinned allocation.
+class PinnedPool {
+ public:
+  static PinnedPool& get() {
+    static PinnedPool pool;
+    return pool;
   }
-  void release() {
-    if (p) (void)hipHostFree(p);
-    p = nullptr;
-    n = 0;
+  // A buffer of at least `bytes`, or nullptr if the allocation fails.
+  void* take(size_t bytes, size_t* got) {
+    {
+      std::lock_guard<std::mutex> lk(mu_);
+      for (size_t k = 0; k < free_.size(); ++k)
+        if (free_[k].second >= bytes) {
+          auto e = free_[k];
+          free_.erase(free_.begin() + (long)k);
+          *got = e.second;
+          return e.first;
+        }
+    }
+    const size_t m = std::max<size_t>(bytes + bytes / 4, 1u << 16);
+    void* p = nullptr;
+    if (hipHostMalloc(&p, m) != hipSuccess) return nullptr;
+    *got = m;
+    return p;
+  }
+  void give(void* p, size_t bytes) {
+    std::lock_guard<std::mutex> lk(mu_);
+    free_.emplace_back(p, bytes);
+  }
+
+ private:
+  std::mutex mu_;
+  std::vector<std::pair<void*, size_t>> free_;
+};
+
+// Staging borrowed for one call: grown on demand (growth drains the stream
+// first), returned to the pool with the stream drained.
+template <class T>
+struct Staging {
+  hipStream_t st;
+  T* p = nullptr;
+  size_t bytes = 0;
+  explicit Staging(hipStream_t s) : st(s) {}
+  hipError_t reserve(size_t n) {
+    if (n * sizeof(T) <= bytes) return hipSuccess;
+    if (p) {
+      hipError_t e = hipStreamSynchronize(st);
+      if (e != hipSuccess) return e;
+      PinnedPool::get().give(p, bytes);
+      p = nullptr;
+      bytes = 0;
+    }
+    p = static_cast<T*>(PinnedPool::get().take(n * sizeof(T), &bytes));
+    return p ? hipSuccess : hipErrorOutOfMemory;
+  }
+  ~Staging() {
+    if (!p) return;
+    (void)hipStreamSynchronize(st);
+    PinnedPool::get().give(p, bytes);
   }
 };
 
@@ -199,8 +241,6 @@ struct sim_t {
   DevVec<MonoDesc> descs;
   DevVec<BsGroup> grp_ops;     // grouped bit-sliced ops of the current call
   std::vector<BsGroup> h_grp;
-  HostVec<MonoDesc> h_desc;    // pinned staging of descriptor uploads
-  HostVec<BsGroup> h_grp_pin;  // pinned staging of group uploads
   std::vector<sim_gate> conv;  // sim_apply_ops: converted ops, kept between calls
   RunCompiler rc;              // MONO descriptors and bytecode of the current call
   DevVec<MeasRec> recs;
@@ -494,8 +534,6 @@ int sim_destroy(sim_t* s) {
   if (s->stream || s->ws) (void)hipStreamSynchronize(s->stream);
   s->descs.release();
   s->grp_ops.release();
-  s->h_desc.release();
-  s->h_grp_pin.release();
   s->recs.release();
   s->outcomes.release();
   for (hipEvent_t e : s->ev_pool) (void)hipEventDestroy(e);
@@ -673,13 +711,18 @@ int sim_apply_gates(sim_t* s, const sim_gate* gates, size_t n, int32_t* outcomes
       if (t.joinable()) t.join();
     }
   } compiler;
-  if (bs_allowed) compiler.t = std::thread([s]() { s->rc.compile(s->cfg.n_qubits); });
+  // (Small lists compile on this thread: starting a thread costs more.)
+  if (bs_allowed && n_mono < 8192) s->rc.compile(s->cfg.n_qubits);
+  else if (bs_allowed) compiler.t = std::thread([s]() { s->rc.compile(s->cfg.n_qubits); });
   HIP_TRY(s->descs.reserve(n_mono));
   HIP_TRY(s->recs.reserve(n_meas));
   HIP_TRY(s->outcomes.reserve(n_meas));
-  // Descriptors are uploaded run by run, for the runs that take the
-  // per-entry kernel, from pinned staging (asynchronous).
-  HIP_TRY(s->h_desc.reserve(n_mono, s->stream));
+  // Descriptors are uploaded for the runs that take the per-entry kernel,
+  // a window of runs at a time, and the bit-sliced groups run by run, both
+  // from pinned staging (asynchronous).
+  Staging<MonoDesc> h_desc(s->stream);
+  Staging<BsGroup> h_grp_pin(s->stream);
+  size_t desc_lo = 0, desc_hi = 0;   // descriptors [desc_lo, desc_hi) are on the device
   // Grouped kernel ops of the bit-sliced runs, appended run by run.  A run
   // of k > 0 ops has at most k + 1 groups (every group but an evening pad
   // holds an op), so reserving two groups per op before the first run keeps
@@ -690,12 +733,12 @@ int sim_apply_gates(sim_t* s, const sim_gate* gates, size_t n, int32_t* outcomes
     if (compiled) return SIM_OK;
     {
       HTimer t_(s, KC_H_PREPARE);
-      compiler.t.join();
+      if (compiler.t.joinable()) compiler.t.join();
     }
     compiled = true;
     s->h_grp.reserve(2 * s->rc.ops.size() + 2);
     HIP_TRY(s->grp_ops.reserve(2 * s->rc.ops.size() + 2));
-    HIP_TRY(s->h_grp_pin.reserve(2 * s->rc.ops.size() + 2, s->stream));
+    HIP_TRY(h_grp_pin.reserve(2 * s->rc.ops.size() + 2));
     return SIM_OK;
   };
 
@@ -754,8 +797,8 @@ int sim_apply_gates(sim_t* s, const sim_gate* gates, size_t n, int32_t* outcomes
       const size_t ng = s->h_grp.size() - g0;
       if (s->h_grp.size() > s->grp_ops.n) return fail(SIM_E_STATE, "bit-sliced op groups exceed their buffer");
       if (ng) {
-        std::memcpy(s->h_grp_pin.p + g0, s->h_grp.data() + g0, ng * sizeof(BsGroup));
-        HIP_TRY(hipMemcpyAsync(s->grp_ops.p + g0, s->h_grp_pin.p + g0, ng * sizeof(BsGroup), hipMemcpyHostToDevice,
+        std::memcpy(h_grp_pin.p + g0, s->h_grp.data() + g0, ng * sizeof(BsGroup));
+        HIP_TRY(hipMemcpyAsync(s->grp_ops.p + g0, h_grp_pin.p + g0, ng * sizeof(BsGroup), hipMemcpyHostToDevice,
                                s->stream));
       }
       KTimer t_(s, KC_MONO);
@@ -763,9 +806,15 @@ int sim_apply_gates(sim_t* s, const sim_gate* gates, size_t n, int32_t* outcomes
                      bs_grid(s, ub));
       st.bitslice_passes++;
     } else {
-      std::memcpy(s->h_desc.p + run_begin, s->rc.descs.data() + run_begin, run_len * sizeof(MonoDesc));
-      HIP_TRY(hipMemcpyAsync(s->descs.p + run_begin, s->h_desc.p + run_begin, run_len * sizeof(MonoDesc),
-                             hipMemcpyHostToDevice, s->stream));
+      if (run_begin < desc_lo || run_begin + run_len > desc_hi) {
+        // This run and those after it, up to 1024 descriptors, in one copy.
+        desc_lo = run_begin;
+        desc_hi = std::min(s->rc.descs.size(), run_begin + std::max<size_t>(run_len, 1024));
+        HIP_TRY(h_desc.reserve(s->rc.descs.size()));
+        std::memcpy(h_desc.p + desc_lo, s->rc.descs.data() + desc_lo, (desc_hi - desc_lo) * sizeof(MonoDesc));
+        HIP_TRY(hipMemcpyAsync(s->descs.p + desc_lo, h_desc.p + desc_lo, (desc_hi - desc_lo) * sizeof(MonoDesc),
+                               hipMemcpyHostToDevice, s->stream));
+      }
       KTimer t_(s, KC_MONO);
       launch_mono(s->stream, s->wide, s->buf[s->cur], d_nnz(s, s->cur), s->descs.p + run_begin, (uint32_t)run_len,
                   run_flags, run_bpe, s->ctl, mono_grid(s, ub), block_of(s));
@@ -789,7 +838,7 @@ int sim_apply_gates(sim_t* s, const sim_gate* gates, size_t n, int32_t* outcomes
       if (h.op == SIM_OP_MONO) ++len;
       else if (h.op != SIM_OP_U2 || !h.cap) break;
     }
-    if (len == 0) return SIM_OK;
+    if (len < 1024) return SIM_OK;   // short runs group in microseconds
     BsRun probe;
     if (!s->rc.run_params(begin, len, s->cfg.mono_mode, s->cfg.bs_min_gates, &probe)) return SIM_OK;
     if (spec.ready && spec.begin == begin && spec.len == len) return SIM_OK;
