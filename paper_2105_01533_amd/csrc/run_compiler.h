@@ -39,6 +39,10 @@ struct RunCompiler {
   std::vector<uint32_t> start;      // ops of MONO op k: [start[k], start[k+1])
   std::vector<BsGateInfo> info;
   std::vector<std::vector<BsOp>> part_ops;   // compile's per-thread output, kept between calls
+  // Ops a pair attempt looks ahead over.  Wider finds more pairs (faster
+  // passes) at more host time; the batched server, which groups on its
+  // critical path, uses a narrower one.
+  uint32_t pair_window = 128;
 
   // Fill ops/start/info from descs.
   void compile(uint32_t nq);

@@ -247,17 +247,22 @@ void RunCompiler::group(size_t begin, size_t len, std::vector<BsGroup>& out, BsR
     br->g_turn += d_turn;
   }
   const uint32_t n = (uint32_t)xo.size();
+  const size_t g0 = out.size();
   if (n < 2 * 2048) {
     group_range(xo.data(), n, out);
-    return;
+  } else {
+    std::vector<std::vector<BsGroup>> parts(kHostThreads);
+    parallel_parts(n, 2048, [&](size_t b, size_t e, size_t p) {
+      std::vector<BsGroup> mine;   // on this thread's stack: the parts' vectors share cache lines
+      group_range(xo.data() + b, (uint32_t)(e - b), mine);
+      parts[p].swap(mine);
+    });
+    for (auto& v : parts) out.insert(out.end(), v.begin(), v.end());
   }
-  std::vector<std::vector<BsGroup>> parts(kHostThreads);
-  parallel_parts(n, 2048, [&](size_t b, size_t e, size_t p) {
-    std::vector<BsGroup> mine;   // on this thread's stack: the parts' vectors share cache lines
-    group_range(xo.data() + b, (uint32_t)(e - b), mine);
-    parts[p].swap(mine);
-  });
-  for (auto& v : parts) out.insert(out.end(), v.begin(), v.end());
+  // The kernel reads a run's groups 64 at a time and a pair's second group
+  // from the next lane: a pair that would start on the last lane of a batch
+  // is split into its two groups, each valid on its own.
+  for (size_t p = g0 + 63; p < out.size(); p += 64) out[p].a[1] &= ~kPairBit;
 }
 
 // Uncontrolled X gates only relabel: instead of flipping a plane each time,
@@ -375,7 +380,7 @@ void RunCompiler::group_range(const BsOp* src, uint32_t n, std::vector<BsGroup>&
   // their condition planes, so TURN groups look further ahead.
   auto select = [&](uint32_t want, uint32_t* sel, uint32_t cap) -> uint32_t {
     uint32_t k = 0, seen = 0;
-    const uint32_t window = want == kShapeTurn ? 4 * kWindow : cap > (uint32_t)kBsGroup ? 2 * kWindow : kWindow;
+    const uint32_t window = want == kShapeTurn ? 4 * kWindow : cap > (uint32_t)kBsGroup ? pair_window : kWindow;
     Mask gr, gw, br, bw;   // group reads / writes, reads / writes of ops passed over
     for (uint32_t j = nxt[n]; j != n && seen < window && k < cap; j = nxt[j], ++seen) {
       const Item& it = items[j];
@@ -435,10 +440,9 @@ void RunCompiler::group_range(const BsOp* src, uint32_t n, std::vector<BsGroup>&
   while (nxt[n] != n) {
     const uint32_t hs = items[nxt[n]].shape;
     const bool flip = hs == kShapeX || hs == kShapeCX || hs == kShapeCCX;
-    // Flip groups at even positions may pair with the next group: eight
-    // mutually independent ops of one shape, read together by the kernel.
-    const bool can_pair = flip && ((out.size() - base) & 1) == 0;
-    uint32_t np = select(hs, pick, can_pair ? 2 * kBsGroup : kBsGroup);
+    // A flip group may pair with the next group: eight mutually independent
+    // ops of one shape, read together by the kernel.
+    uint32_t np = select(hs, pick, flip ? 2 * kBsGroup : kBsGroup);
     if (np == 2 * kBsGroup) {
       emit(pick, kBsGroup, hs);
       out.back().a[1] |= kPairBit;
@@ -462,8 +466,7 @@ void RunCompiler::group_range(const BsOp* src, uint32_t n, std::vector<BsGroup>&
     }
     emit(pick, np, shape);
   }
-  // An even count keeps pairs aligned when ranges are concatenated.
-  if ((out.size() - base) & 1) emit(pick, 0, kShapeX);
+  (void)base;
 }
 
 }  // namespace sparsesim

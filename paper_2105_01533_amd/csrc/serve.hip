@@ -282,6 +282,7 @@ void compile_request(Request& r) {
       r.rc.descs.push_back(mono_desc(r.gates[i]));
       r.mono_op.push_back(i);
     }
+  r.rc.pair_window = 64;   // grouping happens on the tick's critical path
   if (r.cfg.mono_mode != SIM_MONO_DIRECT) r.rc.compile(r.cfg.n_qubits);
   else r.rc.n_qubits = r.cfg.n_qubits;
   r.compiled = true;

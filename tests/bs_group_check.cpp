@@ -93,11 +93,11 @@ bool apply_pair(State& s, const BsGroup& G0, const BsGroup& G1, uint32_t nq, std
 
 bool apply_groups(State& s, const std::vector<BsGroup>& groups, uint32_t nq, std::string* why) {
   const uint32_t scratch = nq + 1;
-  if (groups.size() & 1) return *why = "odd number of groups", false;
   for (size_t gi = 0; gi < groups.size(); ++gi) {
     const BsGroup& G = groups[gi];
     if (G.a[1] & kPairBit) {
-      if (gi & 1) return *why = "pair at an odd position", false;
+      if (gi % 64 == 63) return *why = "pair across a batch of 64 groups", false;
+      if (gi + 1 >= groups.size()) return *why = "pair without a second group", false;
       if (!apply_pair(s, G, groups[gi + 1], nq, why)) return false;
       ++gi;
       continue;
