@@ -142,6 +142,26 @@ __device__ __forceinline__ void flip_ccx(char* Lb, const uint32_t* a) {
   for (int u = 0; u < N; ++u) plane(Lb, off_t(a[u])) = tv[u] ^ (c0[u] & c1[u]);
 }
 
+// N eighth-turn ops (all plane reads first), alternating between the two
+// counters (e) and (f).
+template <int N>
+__device__ __forceinline__ void omega_ops(char* Lb, const uint32_t* a, uint32_t& e0, uint32_t& e1, uint32_t& e2,
+                                          uint32_t& f0, uint32_t& f1, uint32_t& f2) {
+  uint32_t tv[N];
+#pragma unroll
+  for (int u = 0; u < N; ++u) tv[u] = plane(Lb, off_t(a[u]));
+#pragma unroll
+  for (int u = 0; u < N; ++u) {
+    const uint32_t m0 = (uint32_t)__builtin_amdgcn_sbfe((int)a[u], 2, 1);
+    const uint32_t m1 = (uint32_t)__builtin_amdgcn_sbfe((int)a[u], 3, 1);
+    const uint32_t m2 = (uint32_t)__builtin_amdgcn_sbfe((int)a[u], 4, 1);
+    if (u & 1)
+      omega_add_m(f0, f1, f2, tv[u], m0, m1, m2);
+    else
+      omega_add_m(e0, e1, e2, tv[u], m0, m1, m2);
+  }
+}
+
 // Apply ngroups grouped ops to the 2048-entry tile at base (lim valid
 // entries): labels to LDS planes, gates, labels back, one phase multiply per
 // amplitude.  L = LDS base + lane; the all-ones plane must be set.
@@ -217,18 +237,16 @@ __device__ __forceinline__ void bs_tile(const Buf& b, uint64_t base, uint32_t li
           if (shape == kShapeOmega) {
             // Eighth-turn phase ops conditioned on their target bit only
             // (Z, S, T and their adjoints): read-only on the planes.
-            uint32_t tv[kBsGroup];
-#pragma unroll
-            for (int u = 0; u < kBsGroup; ++u) tv[u] = plane(Lb, off_t(a[u]));
-#pragma unroll
-            for (int u = 0; u < kBsGroup; ++u) {
-              const uint32_t m0 = (uint32_t)__builtin_amdgcn_sbfe((int)a[u], 2, 1);
-              const uint32_t m1 = (uint32_t)__builtin_amdgcn_sbfe((int)a[u], 3, 1);
-              const uint32_t m2 = (uint32_t)__builtin_amdgcn_sbfe((int)a[u], 4, 1);
-              if (u & 1)
-                omega_add_m(f0, f1, f2, tv[u], m0, m1, m2);
-              else
-                omega_add_m(e0, e1, e2, tv[u], m0, m1, m2);
+            if (a[1] & kPairBit) {
+              uint32_t a8[2 * kBsGroup] = {a[0], a[1], a[2], a[3],
+                                           (uint32_t)__builtin_amdgcn_readlane(ca.x, g + 1),
+                                           (uint32_t)__builtin_amdgcn_readlane(ca.y, g + 1),
+                                           (uint32_t)__builtin_amdgcn_readlane(ca.z, g + 1),
+                                           (uint32_t)__builtin_amdgcn_readlane(ca.w, g + 1)};
+              omega_ops<2 * kBsGroup>(Lb, a8, e0, e1, e2, f0, f1, f2);
+              ++g;
+            } else {
+              omega_ops<kBsGroup>(Lb, a, e0, e1, e2, f0, f1, f2);
             }
           } else {
             // General group: every op writes its plane t; a flip xors the

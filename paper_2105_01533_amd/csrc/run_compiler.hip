@@ -440,9 +440,9 @@ void RunCompiler::group_range(const BsOp* src, uint32_t n, std::vector<BsGroup>&
   while (nxt[n] != n) {
     const uint32_t hs = items[nxt[n]].shape;
     const bool flip = hs == kShapeX || hs == kShapeCX || hs == kShapeCCX;
-    // A flip group may pair with the next group: eight mutually independent
-    // ops of one shape, read together by the kernel.
-    uint32_t np = select(hs, pick, flip ? 2 * kBsGroup : kBsGroup);
+    // A flip or OMEGA group may pair with the next group: eight mutually
+    // independent ops of one shape, read together by the kernel.
+    uint32_t np = select(hs, pick, flip || hs == kShapeOmega ? 2 * kBsGroup : kBsGroup);
     if (np == 2 * kBsGroup) {
       emit(pick, kBsGroup, hs);
       out.back().a[1] |= kPairBit;

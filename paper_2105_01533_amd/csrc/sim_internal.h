@@ -76,9 +76,9 @@ static_assert(sizeof(BsOp) == 16, "BsOp is 16 bytes");
 constexpr int kBsGroup = 4;
 constexpr uint32_t kShapeGeneric = 0, kShapeX = 1, kShapeCX = 2, kShapeCCX = 3, kShapeTurn = 4, kShapePhase = 5,
                    kShapeOmega = 6;
-// In a[1] of an X, CX or CCX group: the next group has the same shape and no
-// plane conflict with this one, so the kernel applies the eight ops as one
-// (all reads, then all writes).  Never set on the last group of a batch of 64
+// In a[1] of an X, CX, CCX or OMEGA group: the next group has the same shape
+// and no plane conflict with this one, so the kernel applies the eight ops as
+// one (all reads, then all writes).  Never set on the last group of a batch of 64
 // (position 63 mod 64 in its run).
 constexpr uint32_t kPairBit = 1u << 5;
 // In a[1] of a TURN group: no op of the group has controls, so each op's

@@ -66,10 +66,26 @@ uint32_t f_p2(uint32_t b) { return (b >> 8) & 0xffu; }
 // (all reads before all writes).
 bool apply_pair(State& s, const BsGroup& G0, const BsGroup& G1, uint32_t nq, std::string* why) {
   const uint32_t shape = f_shape(G0.a[0]), scratch = nq + 1;
-  if (shape < kShapeX || shape > kShapeCCX || f_shape(G1.a[0]) != shape) return *why = "bad pair shapes", false;
   if (G1.a[1] & kPairBit) return *why = "pair flag on a pair's second group", false;
   uint32_t a[8];
   for (int u = 0; u < 4; ++u) a[u] = G0.a[u], a[4 + u] = G1.a[u];
+  if (shape == kShapeOmega && f_shape(G1.a[0]) == kShapeOmega) {
+    // Eight eighth-turn ops on their target bits: read-only, so any eight commute.
+    for (int u = 0; u < 8; ++u) {
+      if (f_op(a[u]) != kBsOmega) return *why = "non-omega op in an OMEGA pair", false;
+      const BsGroup& G = u < 4 ? G0 : G1;
+      if (f_p0(a[u]) != nq || f_p1(a[u]) != nq || f_p2(G.b[u & 3]) != nq)
+        return *why = "controlled op in an OMEGA pair", false;
+    }
+    for (int w = 0; w < kWords; ++w)
+      for (int u = 0; u < 8; ++u) {
+        const uint32_t tv = s.p(f_t(a[u]), w);
+        for (int j = 0; j < 32; ++j)
+          if ((tv >> j) & 1u) s.omega[(size_t)w * 32 + j] = (uint8_t)((s.omega[(size_t)w * 32 + j] + f_k(a[u])) & 7u);
+      }
+    return true;
+  }
+  if (shape < kShapeX || shape > kShapeCCX || f_shape(G1.a[0]) != shape) return *why = "bad pair shapes", false;
   for (int u = 0; u < 8; ++u) {
     if (f_op(a[u]) != kBsFlip) return *why = "non-flip op in a pair", false;
     if (f_t(a[u]) == scratch) continue;
