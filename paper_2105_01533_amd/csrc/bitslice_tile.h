@@ -142,6 +142,21 @@ __device__ __forceinline__ void flip_ccx(char* Lb, const uint32_t* a) {
   for (int u = 0; u < N; ++u) plane(Lb, off_t(a[u])) = tv[u] ^ (c0[u] & c1[u]);
 }
 
+// The a words of groups g .. g + 3 of the current batch (a quad).
+__device__ __forceinline__ void gather_quad(const uint32_t* a, const uint4& ca, uint32_t g, uint32_t* a16) {
+  a16[0] = a[0];
+  a16[1] = a[1];
+  a16[2] = a[2];
+  a16[3] = a[3];
+#pragma unroll
+  for (int k = 1; k < 4; ++k) {
+    a16[4 * k + 0] = (uint32_t)__builtin_amdgcn_readlane(ca.x, g + k);
+    a16[4 * k + 1] = (uint32_t)__builtin_amdgcn_readlane(ca.y, g + k);
+    a16[4 * k + 2] = (uint32_t)__builtin_amdgcn_readlane(ca.z, g + k);
+    a16[4 * k + 3] = (uint32_t)__builtin_amdgcn_readlane(ca.w, g + k);
+  }
+}
+
 // N eighth-turn ops (all plane reads first), alternating between the two
 // counters (e) and (f).
 template <int N>
@@ -214,7 +229,12 @@ __device__ __forceinline__ void bs_tile(const Buf& b, uint64_t base, uint32_t li
           // group (its a words are at the next lane).
 #define BS_FLIP_CASE(SHAPE, BODY)                                  \
   case SHAPE:                                                      \
-    if (a[1] & kPairBit) {                                         \
+    if (a[1] & kQuadBit) {                                         \
+      uint32_t a16[4 * kBsGroup];                                  \
+      gather_quad(a, ca, g, a16);                                  \
+      BODY<4 * kBsGroup>(Lb, a16);                                 \
+      g += 3;                                                      \
+    } else if (a[1] & kPairBit) {                                  \
       uint32_t a8[2 * kBsGroup] = {a[0], a[1], a[2], a[3],         \
                                    (uint32_t)__builtin_amdgcn_readlane(ca.x, g + 1), \
                                    (uint32_t)__builtin_amdgcn_readlane(ca.y, g + 1), \
@@ -237,7 +257,12 @@ __device__ __forceinline__ void bs_tile(const Buf& b, uint64_t base, uint32_t li
           if (shape == kShapeOmega) {
             // Eighth-turn phase ops conditioned on their target bit only
             // (Z, S, T and their adjoints): read-only on the planes.
-            if (a[1] & kPairBit) {
+            if (a[1] & kQuadBit) {
+              uint32_t a16[4 * kBsGroup];
+              gather_quad(a, ca, g, a16);
+              omega_ops<4 * kBsGroup>(Lb, a16, e0, e1, e2, f0, f1, f2);
+              g += 3;
+            } else if (a[1] & kPairBit) {
               uint32_t a8[2 * kBsGroup] = {a[0], a[1], a[2], a[3],
                                            (uint32_t)__builtin_amdgcn_readlane(ca.x, g + 1),
                                            (uint32_t)__builtin_amdgcn_readlane(ca.y, g + 1),

@@ -259,10 +259,19 @@ void RunCompiler::group(size_t begin, size_t len, std::vector<BsGroup>& out, BsR
     });
     for (auto& v : parts) out.insert(out.end(), v.begin(), v.end());
   }
-  // The kernel reads a run's groups 64 at a time and a pair's second group
-  // from the next lane: a pair that would start on the last lane of a batch
-  // is split into its two groups, each valid on its own.
-  for (size_t p = g0 + 63; p < out.size(); p += 64) out[p].a[1] &= ~kPairBit;
+  // The kernel reads a run's groups 64 at a time and a pair's or quad's later
+  // groups from the next lanes: where they would cross into the next batch,
+  // the quad becomes pairs and single groups, the pair single groups (every
+  // part is valid on its own).
+  for (size_t p = g0; p < out.size(); ++p) {
+    const size_t lane = (p - g0) % 64;
+    if ((out[p].a[1] & kQuadBit) && lane > 60) {
+      out[p].a[1] &= ~kQuadBit;
+      for (size_t k = 0; k < 4; k += 2)
+        if ((lane + k) % 64 != 63) out[p + k].a[1] |= kPairBit;
+    }
+    if ((out[p].a[1] & kPairBit) && lane == 63) out[p].a[1] &= ~kPairBit;
+  }
 }
 
 // Uncontrolled X gates only relabel: instead of flipping a plane each time,
@@ -436,17 +445,21 @@ void RunCompiler::group_range(const BsOp* src, uint32_t n, std::vector<BsGroup>&
     out.push_back(grp);
   };
   const size_t base = out.size();
-  uint32_t pick[2 * kBsGroup], best[kBsGroup];
+  uint32_t pick[4 * kBsGroup], best[kBsGroup];
   while (nxt[n] != n) {
     const uint32_t hs = items[nxt[n]].shape;
     const bool flip = hs == kShapeX || hs == kShapeCX || hs == kShapeCCX;
-    // A flip or OMEGA group may pair with the next group: eight mutually
-    // independent ops of one shape, read together by the kernel.
-    uint32_t np = select(hs, pick, flip || hs == kShapeOmega ? 2 * kBsGroup : kBsGroup);
-    if (np == 2 * kBsGroup) {
-      emit(pick, kBsGroup, hs);
-      out.back().a[1] |= kPairBit;
-      emit(pick + kBsGroup, kBsGroup, hs);
+    // A flip or OMEGA group may join the next one or three groups: eight or
+    // sixteen mutually independent ops of one shape, read together by the
+    // kernel.
+    uint32_t np = select(hs, pick, flip || hs == kShapeOmega ? 4 * kBsGroup : kBsGroup);
+    if (np >= 2 * kBsGroup) {
+      const uint32_t ng = np == 4 * kBsGroup ? 4 : 2;
+      for (uint32_t k = 0; k < ng; ++k) {
+        emit(pick + k * kBsGroup, kBsGroup, hs);
+        if (k == 0) out.back().a[1] |= ng == 4 ? kQuadBit : kPairBit;
+      }
+      // Picks beyond the emitted groups stay pending.
       continue;
     }
     np = std::min<uint32_t>(np, kBsGroup);

@@ -81,6 +81,9 @@ constexpr uint32_t kShapeGeneric = 0, kShapeX = 1, kShapeCX = 2, kShapeCCX = 3, 
 // one (all reads, then all writes).  Never set on the last group of a batch of 64
 // (position 63 mod 64 in its run).
 constexpr uint32_t kPairBit = 1u << 5;
+// In a[1] of such a group instead: the next three groups too (sixteen ops,
+// one burst of reads).  Never set where the four would cross a batch of 64.
+constexpr uint32_t kQuadBit = 1u << 7;
 // In a[1] of a TURN group: no op of the group has controls, so each op's
 // condition is its target plane alone (the kernel reads only that plane).
 constexpr uint32_t kBareBit = 1u << 6;

@@ -62,34 +62,37 @@ uint32_t f_p0(uint32_t a) { return (a >> 16) & 0xffu; }
 uint32_t f_p1(uint32_t a) { return a >> 24; }
 uint32_t f_p2(uint32_t b) { return (b >> 8) & 0xffu; }
 
-// Paired flip groups: eight independent ops of one shape applied as one
-// (all reads before all writes).
-bool apply_pair(State& s, const BsGroup& G0, const BsGroup& G1, uint32_t nq, std::string* why) {
-  const uint32_t shape = f_shape(G0.a[0]), scratch = nq + 1;
-  if (G1.a[1] & kPairBit) return *why = "pair flag on a pair's second group", false;
-  uint32_t a[8];
-  for (int u = 0; u < 4; ++u) a[u] = G0.a[u], a[4 + u] = G1.a[u];
-  if (shape == kShapeOmega && f_shape(G1.a[0]) == kShapeOmega) {
-    // Eight eighth-turn ops on their target bits: read-only, so any eight commute.
-    for (int u = 0; u < 8; ++u) {
+// Paired (or quad) flip or OMEGA groups: 8 (16) independent ops of one shape
+// applied as one (all reads before all writes).
+bool apply_multi(State& s, const BsGroup* G, int ng, uint32_t nq, std::string* why) {
+  const uint32_t shape = f_shape(G[0].a[0]), scratch = nq + 1;
+  for (int k = 1; k < ng; ++k) {
+    if (G[k].a[1] & (kPairBit | kQuadBit)) return *why = "pair or quad flag inside a pair or quad", false;
+    if (f_shape(G[k].a[0]) != shape) return *why = "mixed shapes in a pair or quad", false;
+  }
+  const int n = 4 * ng;
+  uint32_t a[16], b[16];
+  for (int k = 0; k < ng; ++k)
+    for (int u = 0; u < 4; ++u) a[4 * k + u] = G[k].a[u], b[4 * k + u] = G[k].b[u];
+  if (shape == kShapeOmega) {
+    // Eighth-turn ops on their target bits: read-only, so any of them commute.
+    for (int u = 0; u < n; ++u) {
       if (f_op(a[u]) != kBsOmega) return *why = "non-omega op in an OMEGA pair", false;
-      const BsGroup& G = u < 4 ? G0 : G1;
-      if (f_p0(a[u]) != nq || f_p1(a[u]) != nq || f_p2(G.b[u & 3]) != nq)
-        return *why = "controlled op in an OMEGA pair", false;
+      if (f_p0(a[u]) != nq || f_p1(a[u]) != nq || f_p2(b[u]) != nq) return *why = "controlled op in an OMEGA pair", false;
     }
     for (int w = 0; w < kWords; ++w)
-      for (int u = 0; u < 8; ++u) {
+      for (int u = 0; u < n; ++u) {
         const uint32_t tv = s.p(f_t(a[u]), w);
         for (int j = 0; j < 32; ++j)
           if ((tv >> j) & 1u) s.omega[(size_t)w * 32 + j] = (uint8_t)((s.omega[(size_t)w * 32 + j] + f_k(a[u])) & 7u);
       }
     return true;
   }
-  if (shape < kShapeX || shape > kShapeCCX || f_shape(G1.a[0]) != shape) return *why = "bad pair shapes", false;
-  for (int u = 0; u < 8; ++u) {
+  if (shape < kShapeX || shape > kShapeCCX) return *why = "bad pair shapes", false;
+  for (int u = 0; u < n; ++u) {
     if (f_op(a[u]) != kBsFlip) return *why = "non-flip op in a pair", false;
     if (f_t(a[u]) == scratch) continue;
-    for (int v = 0; v < 8; ++v) {
+    for (int v = 0; v < n; ++v) {
       if (v == u) continue;
       const uint32_t r[3] = {f_t(a[v]), shape >= kShapeCX ? f_p0(a[v]) : 0xffffu, shape >= kShapeCCX ? f_p1(a[v]) : 0xffffu};
       for (uint32_t q : r)
@@ -97,12 +100,12 @@ bool apply_pair(State& s, const BsGroup& G0, const BsGroup& G1, uint32_t nq, std
     }
   }
   for (int w = 0; w < kWords; ++w) {
-    uint32_t tv[8], c[8];
-    for (int u = 0; u < 8; ++u) {
+    uint32_t tv[16], c[16];
+    for (int u = 0; u < n; ++u) {
       tv[u] = s.p(f_t(a[u]), w);
       c[u] = (shape >= kShapeCX ? s.p(f_p0(a[u]), w) : ~0u) & (shape >= kShapeCCX ? s.p(f_p1(a[u]), w) : ~0u);
     }
-    for (int u = 0; u < 8; ++u) s.p(f_t(a[u]), w) = tv[u] ^ c[u];
+    for (int u = 0; u < n; ++u) s.p(f_t(a[u]), w) = tv[u] ^ c[u];
   }
   return true;
 }
@@ -111,10 +114,18 @@ bool apply_groups(State& s, const std::vector<BsGroup>& groups, uint32_t nq, std
   const uint32_t scratch = nq + 1;
   for (size_t gi = 0; gi < groups.size(); ++gi) {
     const BsGroup& G = groups[gi];
+    if (G.a[1] & kQuadBit) {
+      if (G.a[1] & kPairBit) return *why = "pair and quad flags together", false;
+      if (gi % 64 > 60) return *why = "quad across a batch of 64 groups", false;
+      if (gi + 3 >= groups.size()) return *why = "quad without three more groups", false;
+      if (!apply_multi(s, &groups[gi], 4, nq, why)) return false;
+      gi += 3;
+      continue;
+    }
     if (G.a[1] & kPairBit) {
       if (gi % 64 == 63) return *why = "pair across a batch of 64 groups", false;
       if (gi + 1 >= groups.size()) return *why = "pair without a second group", false;
-      if (!apply_pair(s, G, groups[gi + 1], nq, why)) return false;
+      if (!apply_multi(s, &groups[gi], 2, nq, why)) return false;
       ++gi;
       continue;
     }
