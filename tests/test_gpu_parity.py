@@ -228,6 +228,53 @@ def test_bitslice_random_circuits(sim, n, seed):
     assert st["bitslice_passes"] > 0
 
 
+def _x_heavy_circuit(seed, n, gates, superposed):
+    """H on a few qubits, then gates dominated by uncontrolled X, mixed with
+    CNOTs, Toffolis, uncontrolled and controlled phases (Z/S/T/Rz/PHASE) on
+    few qubits, so X gates often meet the controls and targets of later ops."""
+    rng = W.SplitMix64(seed)
+    c = W.Circuit()
+    for q in range(superposed):
+        c.h(q)
+    qs = list(range(min(n, 12)))
+    for _ in range(gates):
+        u = rng.uniform()
+        if u < 0.45:
+            c.x(qs[rng.randint(len(qs))])
+        elif u < 0.65:
+            a, b = rng.distinct(len(qs), 2)
+            c.x(qs[b], (qs[a],))
+        elif u < 0.75:
+            a, b, t = rng.distinct(len(qs), 3)
+            c.x(qs[t], (qs[a], qs[b]))
+        else:
+            kind = (W.K_Z, W.K_S, W.K_T, W.K_SDG, W.K_RZ, W.K_PHASE, W.K_Y)[rng.randint(7)]
+            nc = rng.randint(3) if u > 0.9 else 0
+            pick = rng.distinct(len(qs), nc + 1)
+            c.gate(kind, qs[pick[-1]], tuple(qs[k] for k in pick[:-1]), param=rng.uniform() * 6.0)
+    return W.Workload(f"xheavy_{n}q", n, 0.0, c.array(), capacity=1 << superposed)
+
+
+@pytest.mark.parametrize("n,seed", [(12, 21), (70, 22), (128, 23)])
+def test_bitslice_pending_x(sim, n, seed):
+    """The run compiler carries uncontrolled X gates to the end of each
+    bit-sliced run (CNOT controls toggle the target's pending X, target-bit
+    phases are negated into the run constant, Toffoli and controlled-phase
+    controls apply them first): long runs dense in such meetings, with the
+    labels spread over both words when n > 64."""
+    w = _x_heavy_circuit(seed, n, 3000, 10)
+    if n > 12:   # move the register to the top qubits (across the word boundary for n = 70)
+        ops = w.ops.copy()
+        shift = n - 12
+        ops["target"] += shift
+        for r in ops:
+            m = (int(r["ctrl_lo"]) | (int(r["ctrl_hi"]) << 64)) << shift
+            r["ctrl_lo"], r["ctrl_hi"] = m & ((1 << 64) - 1), m >> 64
+        w = W.Workload(w.name, n, w.eps, ops, w.capacity)
+    g, st = check_vs_oracle(sim, w, mono_mode=sim.SIM_MONO_BITSLICE, bs_min_gates=1)
+    assert st["bitslice_passes"] > 0
+
+
 @pytest.mark.parametrize("n_entries", [1, 2047, 2048, 2049, 6145, 100_003])
 def test_bitslice_ragged_tiles(sim, n_entries):
     nq = 100 if n_entries % 2 else 50
