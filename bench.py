@@ -347,6 +347,14 @@ def main():
     s.apply_gates(gates)
     ks_all = sim.sim_kernel_stats(s.h)
     kernel_ms = {k: round(v["total_ms"], 3) for k, v in ks_all.items() if v["launches"] and not k.startswith("host_")}
+    # Every pass with algorithmic bytes, against the HBM roofline (one step,
+    # every launch bracketed by events, so slightly slower than untimed).
+    passes = {k: {"launches": v["launches"], "ms": round(v["total_ms"], 3),
+                  "alg_MB": round(v["alg_bytes"] / 1e6, 2),
+                  "GB/s": round(v["alg_bytes"] / (v["total_ms"] * 1e-3) / 1e9, 1),
+                  "frac": round(v["alg_bytes"] / (v["total_ms"] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+              for k, v in ks_all.items() if v["alg_bytes"] > 0 and v["total_ms"] > 0}
+    log(f"[bench] passes {passes}")
     sim.sim_set_profiling(s.h, sim.SIM_PROFILE_MONO)
     sim.sim_kernel_stats_reset(s.h)
     torch.cuda.synchronize()
@@ -385,7 +393,7 @@ def main():
         "hbm": hbm, "alu": alu,
         "launches_per_step": mono["launches"] / args.steps,
         "alg_bytes_per_launch": bytes_per_launch, "alg_ops_per_launch": ops_per_launch,
-        "ms_per_launch": ms_per_launch,
+        "ms_per_launch": ms_per_launch, "passes": passes,
         "updates_per_s_in_kernel": mono["updates"] / (mono["total_ms"] * 1e-3) if mono["total_ms"] else 0.0,
     }
     value = updates / dt

@@ -286,9 +286,15 @@ int sim_device_state(sim_t* s, uint64_t** key_lo, uint64_t** key_hi, double** am
 /* Per-kernel-class counters, cumulative since creation or the last reset.
  * With profiling on for a class (sim_set_profiling), every launch of it is
  * bracketed by HIP events on the handle's stream and total_ms sums their
- * elapsed times; otherwise total_ms is 0.  alg_bytes is the algorithmic HBM traffic of the
- * fused phase/permutation pass (label read, label write if any gate flips,
- * amplitude read+write if any gate has a phase), 0 for the other classes;
+ * elapsed times; otherwise total_ms is 0.  alg_bytes is the algorithmic HBM
+ * traffic of a class, the bytes its pass must move at least: for the fused
+ * phase/permutation pass the label read, label write if any gate flips and
+ * amplitude read+write if any gate has a phase; for u2_count every input
+ * entry read; for u2_write every input entry read and every output entry
+ * written; for measure_reduce the label word holding the measured qubit and the
+ * amplitude of every entry; for measure_write that label word of every entry, the
+ * rest of each kept entry and the kept entries written; 0 for the others
+ * (index, scan and decide work is overhead);
  * updates counts gate-entry updates done by the class.  Three host classes
  * follow the kernel classes, always measured on the host's wall clock:
  * host_prepare (validation and op compilation at the start of a call),

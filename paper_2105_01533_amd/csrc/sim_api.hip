@@ -225,6 +225,7 @@ struct sim_t {
   uint64_t k_launches[KC_COUNT] = {};
   double k_ms[KC_COUNT] = {};
   uint64_t mono_bytes_base = 0, mono_updates = 0;
+  uint64_t pass_bytes_base[4] = {};
   hipStream_t stream;
   bool wide;
   char* ws;
@@ -394,7 +395,7 @@ int run_u2(sim_t* s, const sim_gate& g, bool* over) {
   }
   {
     KTimer t_(s, KC_SCAN);
-    launch_scan(s->stream, s->bs.tot, G, d_nnz(s, other), s->ctl);
+    launch_scan(s->stream, s->bs.tot, G, d_nnz(s, other), s->ctl, s->wide ? 32u : 24u);
   }
   HIP_TRY(hipGetLastError());
   if (check) {
@@ -407,7 +408,7 @@ int run_u2(sim_t* s, const sim_gate& g, bool* over) {
   }
   {
     KTimer t_(s, KC_U2_WRITE);
-    launch_u2_write(s->stream, s->wide, s->buf[s->cur], s->buf[other], nnz_in, s->partner, s->bs.tot, d, G, 256);
+    launch_u2_write(s->stream, s->wide, s->buf[s->cur], s->buf[other], nnz_in, s->partner, s->bs.tot, d, s->ctl, G, 256);
   }
   HIP_TRY(hipGetLastError());
   s->cur = other;
@@ -428,7 +429,8 @@ int run_measure(sim_t* s, uint32_t q, double u, int32_t forced, MeasRec* rec, in
   }
   {
     KTimer t_(s, KC_M_DECIDE);
-    launch_measure_decide(s->stream, s->bs, G, nnz_in, d_nnz(s, other), u, forced, rec, outcome, s->ctl);
+    launch_measure_decide(s->stream, s->bs, G, nnz_in, d_nnz(s, other), u, forced, rec, outcome, s->ctl,
+                          s->wide ? 32u : 24u);
   }
   HIP_TRY(hipGetLastError());
   if (forced >= 0 || ub == 0) {
@@ -1081,6 +1083,8 @@ int sim_kernel_stats(sim_t* s, sim_kernel_stat* out, int cap, int* n) {
       k.alg_bytes = (double)(s->h_ctl->mono_bytes - s->mono_bytes_base);
       k.updates = (double)(s->h_ctl->mono_updates - s->mono_updates);
     }
+    const int pass = c == KC_U2_COUNT ? 0 : c == KC_U2_WRITE ? 1 : c == KC_M_REDUCE ? 2 : c == KC_M_WRITE ? 3 : -1;
+    if (pass >= 0) k.alg_bytes = (double)(s->h_ctl->pass_bytes[pass] - s->pass_bytes_base[pass]);
   }
   return SIM_OK;
 }
@@ -1094,6 +1098,7 @@ int sim_kernel_stats_reset(sim_t* s) {
     s->k_ms[c] = 0.0;
   }
   s->mono_bytes_base = s->h_ctl->mono_bytes;
+  for (int k = 0; k < 4; ++k) s->pass_bytes_base[k] = s->h_ctl->pass_bytes[k];
   s->mono_updates = s->h_ctl->mono_updates;
   return SIM_OK;
 }

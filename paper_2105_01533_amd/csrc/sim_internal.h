@@ -136,6 +136,9 @@ struct Ctl {
   uint64_t pruned;
   uint64_t mono_bytes;         // algorithmic bytes of the fused phase/permutation passes
   uint64_t mono_updates;       // gate-entry updates of the fused passes
+  // Algorithmic bytes (entries read and written) of the branching count and
+  // write passes and of the measurement reduce and write passes.
+  uint64_t pass_bytes[4];
   uint32_t error;              // nonzero: a measurement had no valid outcome
   uint32_t pad;
 };
@@ -223,13 +226,13 @@ void launch_u2_probe(hipStream_t st, bool wide, Buf b, const uint64_t* nnz, cons
                      const U2Desc& d, uint32_t* partner, int grid, int block);
 void launch_u2_count(hipStream_t st, bool wide, Buf b, const uint64_t* nnz, const U2Desc& d, const uint32_t* partner,
                      uint32_t* tot, Ctl* ctl, int grid, int block);
-void launch_scan(hipStream_t st, uint32_t* tot, int nblocks, uint64_t* nnz_out, Ctl* ctl);
+void launch_scan(hipStream_t st, uint32_t* tot, int nblocks, uint64_t* nnz_out, Ctl* ctl, uint32_t entry_bytes);
 void launch_u2_write(hipStream_t st, bool wide, Buf in, Buf out, const uint64_t* nnz, const uint32_t* partner,
-                     const uint32_t* off, const U2Desc& d, int grid, int block);
+                     const uint32_t* off, const U2Desc& d, Ctl* ctl, int grid, int block);
 void launch_measure_reduce(hipStream_t st, bool wide, Buf b, const uint64_t* nnz, uint32_t q, BlockScratch s,
                            int grid, int block);
 void launch_measure_decide(hipStream_t st, BlockScratch s, int nblocks, const uint64_t* nnz_in, uint64_t* nnz_out,
-                           double u, int32_t forced, MeasRec* rec, int32_t* outcome, Ctl* ctl);
+                           double u, int32_t forced, MeasRec* rec, int32_t* outcome, Ctl* ctl, uint32_t entry_bytes);
 void launch_measure_write(hipStream_t st, bool wide, Buf in, Buf out, const uint64_t* nnz, uint32_t q,
                           const MeasRec* rec, const uint32_t* off, int grid, int block);
 

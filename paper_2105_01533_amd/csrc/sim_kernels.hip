@@ -313,13 +313,17 @@ __global__ __launch_bounds__(256) void k_u2_count(Buf b, const uint64_t* __restr
   if (threadIdx.x == 0) {
     tot[blockIdx.x] = emit;
     if (dropped) atomicAdd((unsigned long long*)&ctl->pruned, (unsigned long long)dropped);
-    if (blockIdx.x == 0) atomicAdd((unsigned long long*)&ctl->updates, (unsigned long long)n);
+    if (blockIdx.x == 0) {
+      atomicAdd((unsigned long long*)&ctl->updates, (unsigned long long)n);
+      atomicAdd((unsigned long long*)&ctl->pass_bytes[0], (unsigned long long)(n * (WIDE ? 32u : 24u)));
+    }
   }
 }
 
 // One block: exclusive scan of per-block counts in place; the total becomes
 // the entry count of the output buffer.
-__global__ __launch_bounds__(1024) void k_scan(uint32_t* __restrict__ tot, int nb, uint64_t* nnz_out, Ctl* ctl) {
+__global__ __launch_bounds__(1024) void k_scan(uint32_t* __restrict__ tot, int nb, uint64_t* nnz_out, Ctl* ctl,
+                                               uint32_t entry_bytes) {
   __shared__ uint32_t sh[1024];
   const int per = (nb + blockDim.x - 1) / blockDim.x;
   const int first = threadIdx.x * per;
@@ -347,15 +351,18 @@ __global__ __launch_bounds__(1024) void k_scan(uint32_t* __restrict__ tot, int n
     const uint64_t total = sh[threadIdx.x];
     *nnz_out = total;
     if (total > ctl->peak) ctl->peak = total;
+    ctl->pass_bytes[1] += total * entry_bytes;   // the write pass's output
   }
 }
 
 template <bool WIDE>
 __global__ __launch_bounds__(256) void k_u2_write(Buf in, Buf out, const uint64_t* __restrict__ nnz_p,
                                                   const uint32_t* __restrict__ partner,
-                                                  const uint32_t* __restrict__ off, U2Desc d) {
+                                                  const uint32_t* __restrict__ off, U2Desc d, Ctl* ctl) {
   __shared__ uint32_t s_wave[16];
   const uint64_t n = *nnz_p;
+  if (blockIdx.x == 0 && threadIdx.x == 0)
+    atomicAdd((unsigned long long*)&ctl->pass_bytes[1], (unsigned long long)(n * (WIDE ? 32u : 24u)));
   uint64_t begin, end;
   chunk_range(n, begin, end);
   uint64_t base = off[blockIdx.x];
@@ -443,7 +450,7 @@ __global__ __launch_bounds__(1024) void k_measure_decide(const double2* __restri
                                                          uint32_t* __restrict__ off, int nb,
                                                          const uint64_t* __restrict__ nnz_in, uint64_t* nnz_out,
                                                          double u, int32_t forced, MeasRec* rec, int32_t* outcome,
-                                                         Ctl* ctl) {
+                                                         Ctl* ctl, uint32_t entry_bytes) {
   __shared__ double2 shd[1024];
   __shared__ uint32_t shu[1024];
   __shared__ int s_o;
@@ -503,7 +510,14 @@ __global__ __launch_bounds__(1024) void k_measure_decide(const double2* __restri
       run += o == 1 ? cnt1[bidx] : (o == 0 ? len - cnt1[bidx] : 0u);
     }
   }
-  if (threadIdx.x == blockDim.x - 1) *nnz_out = shu[threadIdx.x];
+  if (threadIdx.x == blockDim.x - 1) {
+    const uint64_t kept = shu[threadIdx.x];
+    *nnz_out = kept;
+    // reduce: the label word holding the qubit and the amplitude of every entry
+    ctl->pass_bytes[2] += n * 24u;
+    // write: that label word of every entry, the rest of each kept entry, and the kept entries written
+    ctl->pass_bytes[3] += n * 8u + kept * (2u * entry_bytes - 8u);
+  }
 }
 
 template <bool WIDE>
@@ -589,16 +603,16 @@ void launch_u2_count(hipStream_t st, bool wide, Buf b, const uint64_t* nnz, cons
     hipLaunchKernelGGL(k_u2_count<false>, dim3(grid), dim3(block), 0, st, b, nnz, d, partner, tot, ctl);
 }
 
-void launch_scan(hipStream_t st, uint32_t* tot, int nblocks, uint64_t* nnz_out, Ctl* ctl) {
-  hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, st, tot, nblocks, nnz_out, ctl);
+void launch_scan(hipStream_t st, uint32_t* tot, int nblocks, uint64_t* nnz_out, Ctl* ctl, uint32_t entry_bytes) {
+  hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, st, tot, nblocks, nnz_out, ctl, entry_bytes);
 }
 
 void launch_u2_write(hipStream_t st, bool wide, Buf in, Buf out, const uint64_t* nnz, const uint32_t* partner,
-                     const uint32_t* off, const U2Desc& d, int grid, int block) {
+                     const uint32_t* off, const U2Desc& d, Ctl* ctl, int grid, int block) {
   if (wide)
-    hipLaunchKernelGGL(k_u2_write<true>, dim3(grid), dim3(block), 0, st, in, out, nnz, partner, off, d);
+    hipLaunchKernelGGL(k_u2_write<true>, dim3(grid), dim3(block), 0, st, in, out, nnz, partner, off, d, ctl);
   else
-    hipLaunchKernelGGL(k_u2_write<false>, dim3(grid), dim3(block), 0, st, in, out, nnz, partner, off, d);
+    hipLaunchKernelGGL(k_u2_write<false>, dim3(grid), dim3(block), 0, st, in, out, nnz, partner, off, d, ctl);
 }
 
 void launch_measure_reduce(hipStream_t st, bool wide, Buf b, const uint64_t* nnz, uint32_t q, BlockScratch s,
@@ -610,9 +624,10 @@ void launch_measure_reduce(hipStream_t st, bool wide, Buf b, const uint64_t* nnz
 }
 
 void launch_measure_decide(hipStream_t st, BlockScratch s, int nblocks, const uint64_t* nnz_in, uint64_t* nnz_out,
-                           double u, int32_t forced, MeasRec* rec, int32_t* outcome, Ctl* ctl) {
+                           double u, int32_t forced, MeasRec* rec, int32_t* outcome, Ctl* ctl,
+                           uint32_t entry_bytes) {
   hipLaunchKernelGGL(k_measure_decide, dim3(1), dim3(1024), 0, st, s.part, s.cnt1, s.tot, nblocks, nnz_in, nnz_out,
-                     u, forced, rec, outcome, ctl);
+                     u, forced, rec, outcome, ctl, entry_bytes);
 }
 
 void launch_measure_write(hipStream_t st, bool wide, Buf in, Buf out, const uint64_t* nnz, uint32_t q,

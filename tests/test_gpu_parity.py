@@ -362,6 +362,30 @@ def test_profiling_modes(sim):
         s.close()
 
 
+@pytest.mark.parametrize("n", [20, 70])
+def test_pass_byte_counters(sim, n):
+    """Algorithmic bytes per pass class on a circuit whose entry counts are
+    known: three Hadamards take 1 -> 2 -> 4 -> 8 entries, then a measurement
+    with a forced outcome keeps 4 of 8."""
+    c = W.Circuit()
+    for q in (0, 1, n - 1):
+        c.h(q)
+    c.measure(1, 0.5, forced=0)
+    s = sim.Simulator(n, 1 << 10, 0.0)
+    try:
+        sim.sim_kernel_stats_reset(s.h)
+        s.apply_ops(c.array())
+        ks = sim.sim_kernel_stats(s.h)
+    finally:
+        s.close()
+    eb = 32 if n > 64 else 24
+    assert ks["u2_count"]["alg_bytes"] == (1 + 2 + 4) * eb
+    assert ks["u2_write"]["alg_bytes"] == ((1 + 2) + (2 + 4) + (4 + 8)) * eb
+    assert ks["measure_reduce"]["alg_bytes"] == 8 * 24
+    assert ks["measure_write"]["alg_bytes"] == 8 * 8 + 4 * (2 * eb - 8)
+    assert ks["block_scan"]["alg_bytes"] == 0 and ks["index_build"]["alg_bytes"] == 0
+
+
 # --- gate commuting (Sec. 3.3) ---------------------------------------------------------
 def check_commuting(S, w, tol=1e-12, **kw):
     """GPU run of sim_commute_ops' output vs the oracle's commuting runner."""
