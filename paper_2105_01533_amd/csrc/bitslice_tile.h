@@ -318,6 +318,12 @@ __device__ __forceinline__ void bs_tile(const Buf& b, uint64_t base, uint32_t li
           bw[1] = __builtin_amdgcn_readlane(cb.y, g);
           bw[2] = __builtin_amdgcn_readlane(cb.z, g);
           bw[3] = __builtin_amdgcn_readlane(cb.w, g);
+          // The group's turn fractions: scalar loads, issued before the plane
+          // reads so that their latency overlaps the reads and transposes.
+          const uint32_t tg = 16u * (g0 + g) + 8u;   // in 32-bit words
+          uint64_t tau[kBsGroup];
+#pragma unroll
+          for (int u = 0; u < kBsGroup; ++u) tau[u] = ((uint64_t)taus[tg + 2 * u + 1] << 32) | taus[tg + 2 * u];
           uint32_t x[kBsGroup];
           if (a[1] & kBareBit) {
 #pragma unroll
@@ -328,20 +334,6 @@ __device__ __forceinline__ void bs_tile(const Buf& b, uint64_t base, uint32_t li
               x[u] = plane(Lb, off_p0(a[u])) & plane(Lb, off_p1(a[u])) & plane(Lb, off_p2(bw[u])) &
                      plane(Lb, off_t(a[u]));
           }
-          const uint32_t tg = 16u * (g0 + g) + 8u;   // the group's turn fractions, in 32-bit words
-          uint64_t tau[kBsGroup];
-#pragma unroll
-          for (int u = 0; u < kBsGroup; ++u) tau[u] = ((uint64_t)taus[tg + 2 * u + 1] << 32) | taus[tg + 2 * u];
-          // An entry gains the sum of the fractions of the ops whose condition
-          // holds for it: one of 16 subset sums, kept as 8-byte words in the
-          // table plane (entry m = the sum over the ops named by m's bits) and
-          // read per entry with one 64-bit LDS load.  The wave's LDS accesses
-          // complete in order, so the table is written before any load of it.
-          uint64_t S = 0;
-#pragma unroll
-          for (int u = 0; u < kBsGroup; ++u) S += tau[u] & (0ull - (uint64_t)((lane >> u) & 1));
-          char* table = Lb - 4 * lane + (nq + 2) * 256;
-          if (lane < 16) *reinterpret_cast<uint64_t*>(table + 8 * lane) = S;
           // Nibble i of W[c] = the ops (bit u = op u) that hold for entry
           // 8c + i: a byte transpose of the four masks, then each word's
           // 4 x 8 bit matrix transposed by rotating its bit index
@@ -358,6 +350,33 @@ __device__ __forceinline__ void bs_tile(const Buf& b, uint64_t base, uint32_t li
             t = (w ^ (w >> 1)) & 0x22222222u;  w ^= t ^ (t << 1);    // 0 <-> 1
             W[c] = w;
           }
+          // Each index times eight, one per byte: byte m of E[c] for entry
+          // 8c + 2m, of O[c] for entry 8c + 2m + 1 (the byte is the entry's
+          // table offset).
+          uint32_t E[4], O[4];
+#pragma unroll
+          for (int c = 0; c < 4; ++c) {
+            E[c] = (W[c] << 3) & 0x78787878u;
+            O[c] = (W[c] >> 1) & 0x78787878u;
+            // Keep the byte extraction below a single bit-field extract per
+            // entry (otherwise it is folded back into a shift and a mask).
+            asm volatile("" : "+v"(E[c]), "+v"(O[c]));
+          }
+          // An entry gains the sum of the fractions of the ops whose condition
+          // holds for it: one of 16 subset sums, kept as 8-byte words in a
+          // static LDS table (entry m = the sum over the ops named by m's
+          // bits) and read per entry with one 64-bit LDS load.  Its address
+          // is a constant, so an entry's load address is its index times
+          // eight.  The wave's LDS accesses complete in order, so the table is
+          // written before any load of it.
+          __shared__ uint64_t s_table[16];
+          uint64_t S = 0;
+#pragma unroll
+          for (int u = 0; u < kBsGroup; ++u) S += tau[u] & (0ull - (uint64_t)((lane >> u) & 1));
+          // Every lane forms S, so the loads are not moved into the branch.
+          asm volatile("" ::"v"(S));
+          const char* table = reinterpret_cast<const char*>(s_table);
+          if (lane < 16) s_table[lane] = S;
           // Table loads go out fourteen at a time (the LDS counter counts to
           // fifteen) before their sums are added.
 #pragma unroll
@@ -366,8 +385,8 @@ __device__ __forceinline__ void bs_tile(const Buf& b, uint64_t base, uint32_t li
 #pragma unroll
             for (int k = 0; k < 14 && j0 + k < 32; ++k) {
               const int j = j0 + k, c = j >> 3, i = j & 7;
-              const uint32_t nib = __builtin_amdgcn_ubfe(W[c], 4 * i, 4);
-              v[k] = *reinterpret_cast<const uint64_t*>(table + 8 * nib);
+              const uint32_t off = __builtin_amdgcn_ubfe((i & 1) ? O[c] : E[c], 8 * (i >> 1), 8);
+              v[k] = *reinterpret_cast<const uint64_t*>(table + off);
             }
             __builtin_amdgcn_sched_barrier(0);
 #pragma unroll

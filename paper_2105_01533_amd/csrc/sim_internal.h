@@ -87,9 +87,10 @@ constexpr uint32_t kQuadBit = 1u << 7;
 // In a[1] of a TURN group: no op of the group has controls, so each op's
 // condition is its target plane alone (the kernel reads only that plane).
 constexpr uint32_t kBareBit = 1u << 6;
-// LDS planes of a tile beyond the label planes: all-ones, scratch, and the
-// TURN groups' 16-entry table of 8-byte subset sums.
-constexpr uint32_t kExtraPlanes = 3;
+// LDS planes of a tile beyond the label planes: all-ones and scratch.  (The
+// TURN groups' table of subset sums is a static LDS array, placed before the
+// planes.)
+constexpr uint32_t kExtraPlanes = 2;
 struct BsGroup {
   uint32_t a[kBsGroup], b[kBsGroup];
   uint64_t tau[kBsGroup];
@@ -163,7 +164,7 @@ struct BlockScratch {
 // launch.
 constexpr uint32_t kChunk = 2048;          // entries per unit (= one bit-sliced tile)
 constexpr uint32_t kFillUnit = 8192;       // index slots per fill unit
-constexpr uint32_t kMaxPlanes = 128 + kExtraPlanes;   // label planes + all-ones, scratch, turn table
+constexpr uint32_t kMaxPlanes = 128 + kExtraPlanes;   // label planes + all-ones, scratch
 constexpr uint32_t kStOverflow = 1u, kStMeasure = 2u;
 
 // Per-state control words, one slot each, read back after every tick.
