@@ -67,7 +67,7 @@ uint64_t table_slots(uint64_t n, double lf) {
 
 struct Layout {
   size_t buf_lo[2], buf_hi[2], buf_amp[2];
-  size_t table, partner, tot, cnt1, part, ctl, total;
+  size_t table, partner, tot, tot2, cnt1, part, ctl, total;
   uint64_t slots;
 };
 
@@ -106,6 +106,8 @@ Layout layout_of(const sim_config* c) {
   L.partner = off;
   off += align_up(cap * 4);
   L.tot = off;
+  off += align_up(kMaxBlocks * 4);
+  L.tot2 = off;
   off += align_up(kMaxBlocks * 4);
   L.cnt1 = off;
   off += align_up(kMaxBlocks * 4);
@@ -226,6 +228,14 @@ struct sim_t {
   double k_ms[KC_COUNT] = {};
   uint64_t mono_bytes_base = 0, mono_updates = 0;
   uint64_t pass_bytes_base[4] = {};
+  // Sums of a qubit formed by the last measurement's write (see run_measure);
+  // valid only until the next operation.
+  struct {
+    bool valid;
+    uint32_t q;
+    int grid;
+    const uint32_t* off;
+  } mchain = {false, 0, 0, nullptr};
   hipStream_t stream;
   bool wide;
   char* ws;
@@ -417,20 +427,30 @@ int run_u2(sim_t* s, const sim_gate& g, bool* over) {
   return SIM_OK;
 }
 
-int run_measure(sim_t* s, uint32_t q, double u, int32_t forced, MeasRec* rec, int32_t* outcome, bool* bad) {
+// Measurement: reduce, decide, write.  A chain of consecutive measurements
+// skips the reduce after the first: each write forms the sums of the next
+// measured qubit over the entries it writes (q_next >= 0), and the next
+// measurement takes block b's input range from the offsets that write used.
+// s->mchain records such sums (their qubit, grid and offsets array).
+int run_measure(sim_t* s, uint32_t q, double u, int32_t forced, MeasRec* rec, int32_t* outcome, bool* bad,
+                int32_t q_next = -1) {
   *bad = false;
   const uint64_t ub = s->nnz_known ? s->nnz_exact : s->nnz_ub;
   const int G = chunk_grid(ub);
   const int other = s->cur ^ 1;
   const uint64_t* nnz_in = d_nnz(s, s->cur);
-  {
+  const bool chained = s->mchain.valid && s->mchain.q == q && s->mchain.grid == G;
+  const uint32_t* in_off = chained ? s->mchain.off : nullptr;
+  uint32_t* out_off = in_off == s->bs.tot ? s->bs.tot2 : s->bs.tot;
+  s->mchain.valid = false;
+  if (!chained) {
     KTimer t_(s, KC_M_REDUCE);
     launch_measure_reduce(s->stream, s->wide, s->buf[s->cur], nnz_in, q, s->bs, G, 256);
   }
   {
     KTimer t_(s, KC_M_DECIDE);
-    launch_measure_decide(s->stream, s->bs, G, nnz_in, d_nnz(s, other), u, forced, rec, outcome, s->ctl,
-                          s->wide ? 32u : 24u);
+    launch_measure_decide(s->stream, s->bs.part, s->bs.cnt1, out_off, G, nnz_in, d_nnz(s, other), u, forced, rec,
+                          outcome, s->ctl, s->wide ? 32u : 24u, in_off);
   }
   HIP_TRY(hipGetLastError());
   if (forced >= 0 || ub == 0) {
@@ -446,12 +466,14 @@ int run_measure(sim_t* s, uint32_t q, double u, int32_t forced, MeasRec* rec, in
   }
   {
     KTimer t_(s, KC_M_WRITE);
-    launch_measure_write(s->stream, s->wide, s->buf[s->cur], s->buf[other], nnz_in, q, rec, s->bs.tot, G, 256);
+    launch_measure_write(s->stream, s->wide, s->buf[s->cur], s->buf[other], nnz_in, q, rec, out_off, in_off, q_next,
+                         s->bs.part, s->bs.cnt1, G);
   }
   HIP_TRY(hipGetLastError());
   s->cur = other;
   s->nnz_known = false;
   s->nnz_ub = ub;
+  if (q_next >= 0) s->mchain = {true, (uint32_t)q_next, G, out_off};
   return SIM_OK;
 }
 
@@ -506,6 +528,7 @@ int sim_create(const sim_config* cfg, void* stream, void* workspace, size_t ws_b
   s->table = reinterpret_cast<uint64_t*>(s->ws + s->L.table);
   s->partner = reinterpret_cast<uint32_t*>(s->ws + s->L.partner);
   s->bs.tot = reinterpret_cast<uint32_t*>(s->ws + s->L.tot);
+  s->bs.tot2 = reinterpret_cast<uint32_t*>(s->ws + s->L.tot2);
   s->bs.cnt1 = reinterpret_cast<uint32_t*>(s->ws + s->L.cnt1);
   s->bs.part = reinterpret_cast<double2*>(s->ws + s->L.part);
   s->ctl = reinterpret_cast<Ctl*>(s->ws + s->L.ctl);
@@ -667,6 +690,7 @@ int sim_gates_from_ops(const sim_op* ops, size_t n, sim_gate* out) {
 int sim_apply_gates(sim_t* s, const sim_gate* gates, size_t n, int32_t* outcomes, sim_stats* stats) {
   if (!s) return fail(SIM_E_ARG, "null handle");
   if (n && !gates) return fail(SIM_E_ARG, "null gate array");
+  s->mchain.valid = false;
   sim_stats st;
   std::memset(&st, 0, sizeof st);
   size_t n_mono = 0, n_meas = 0;
@@ -903,7 +927,9 @@ int sim_apply_gates(sim_t* s, const sim_gate* gates, size_t n, int32_t* outcomes
     int rc = flush();
     if (rc) return rc;
     bool bad = false;
-    rc = run_measure(s, g.target, g.u, g.forced, s->recs.p + meas_seen, s->outcomes.p + meas_seen, &bad);
+    // A measurement right after this one takes its sums from this write.
+    const int32_t q_next = i + 1 < n && gates[i + 1].op == SIM_OP_MEASURE ? (int32_t)gates[i + 1].target : -1;
+    rc = run_measure(s, g.target, g.u, g.forced, s->recs.p + meas_seen, s->outcomes.p + meas_seen, &bad, q_next);
     if (rc) return rc;
     if (bad) {
       result = fail(SIM_E_STATE, "measurement outcome has zero probability");
@@ -920,12 +946,15 @@ int sim_apply_gates(sim_t* s, const sim_gate* gates, size_t n, int32_t* outcomes
     HIP_TRY(hipMemcpyAsync(outcomes, s->outcomes.p, meas_seen * 4, hipMemcpyDeviceToHost, s->stream));
   int rc = read_ctl(s);
   if (rc) return rc;
-  if (result == SIM_OK && s->h_ctl->error) {
+  if (s->h_ctl->error) {
+    // Cleared whatever the result (a forced zero-probability outcome sets it
+    // too), so that it never carries over to a later call.
     s->h_ctl->error = 0;
     HIP_TRY(hipMemcpyAsync(&s->ctl->error, &s->h_ctl->error, 4, hipMemcpyHostToDevice, s->stream));
     HIP_TRY(timed_sync(s));
-    result = fail(SIM_E_STATE, "measurement of an empty state");
+    if (result == SIM_OK) result = fail(SIM_E_STATE, "measurement of an empty state");
   }
+  s->mchain.valid = false;
   st.gates_applied = i;
   st.updates = s->h_ctl->updates - s->last_updates;
   st.pruned = s->h_ctl->pruned - s->last_pruned;
@@ -976,6 +1005,7 @@ int sim_measure(sim_t* s, uint32_t qubit, double u, int32_t forced, int32_t* out
   HIP_TRY(s->recs.reserve(1));
   HIP_TRY(s->outcomes.reserve(1));
   bool bad = false;
+  s->mchain.valid = false;
   rc = run_measure(s, qubit, u, forced, s->recs.p, s->outcomes.p, &bad);
   if (rc) return rc;
   MeasRec rec;

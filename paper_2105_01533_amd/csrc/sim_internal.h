@@ -153,6 +153,7 @@ struct MeasRec {
 // Scratch of the chunked kernels, kMaxBlocks entries each.
 struct BlockScratch {
   uint32_t* tot;               // per-block emitted counts, scanned in place to offsets
+  uint32_t* tot2;              // measurement: the other offsets array (consecutive measurements alternate)
   uint32_t* cnt1;              // measurement: per-block count of labels with the qubit set
   double2* part;               // measurement: per-block (P0, P1)
 };
@@ -232,9 +233,11 @@ void launch_u2_write(hipStream_t st, bool wide, Buf in, Buf out, const uint64_t*
                      const uint32_t* off, const U2Desc& d, Ctl* ctl, int grid, int block);
 void launch_measure_reduce(hipStream_t st, bool wide, Buf b, const uint64_t* nnz, uint32_t q, BlockScratch s,
                            int grid, int block);
-void launch_measure_decide(hipStream_t st, BlockScratch s, int nblocks, const uint64_t* nnz_in, uint64_t* nnz_out,
-                           double u, int32_t forced, MeasRec* rec, int32_t* outcome, Ctl* ctl, uint32_t entry_bytes);
+void launch_measure_decide(hipStream_t st, const double2* part, const uint32_t* cnt1, uint32_t* off, int nblocks,
+                           const uint64_t* nnz_in, uint64_t* nnz_out, double u, int32_t forced, MeasRec* rec,
+                           int32_t* outcome, Ctl* ctl, uint32_t entry_bytes, const uint32_t* in_off);
 void launch_measure_write(hipStream_t st, bool wide, Buf in, Buf out, const uint64_t* nnz, uint32_t q,
-                          const MeasRec* rec, const uint32_t* off, int grid, int block);
+                          const MeasRec* rec, const uint32_t* off, const uint32_t* in_off, int32_t q_next,
+                          double2* part_next, uint32_t* cnt1_next, int grid);
 
 }  // namespace sparsesim

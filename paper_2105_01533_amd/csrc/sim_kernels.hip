@@ -450,7 +450,8 @@ __global__ __launch_bounds__(1024) void k_measure_decide(const double2* __restri
                                                          uint32_t* __restrict__ off, int nb,
                                                          const uint64_t* __restrict__ nnz_in, uint64_t* nnz_out,
                                                          double u, int32_t forced, MeasRec* rec, int32_t* outcome,
-                                                         Ctl* ctl, uint32_t entry_bytes) {
+                                                         Ctl* ctl, uint32_t entry_bytes,
+                                                         const uint32_t* __restrict__ in_off) {
   __shared__ double2 shd[1024];
   __shared__ uint32_t shu[1024];
   __shared__ int s_o;
@@ -477,19 +478,22 @@ __global__ __launch_bounds__(1024) void k_measure_decide(const double2* __restri
   __syncthreads();
   const int o = s_o;
   // Output counts per block for the chosen outcome, then exclusive scan.
+  // A block's input range is its uniform chunk, or (in_off given) the range
+  // the previous measurement's write block b produced.
   const uint64_t n = *nnz_in;
   const uint64_t chunk = (n + nb - 1) / nb;
   const int per = (nb + blockDim.x - 1) / blockDim.x;
   const int first = threadIdx.x * per;
+  auto block_len = [&](int bidx) -> uint32_t {
+    if (in_off) return (uint32_t)((bidx + 1 < nb ? (uint64_t)in_off[bidx + 1] : n) - in_off[bidx]);
+    uint64_t bb = (uint64_t)bidx * chunk, be = bb + chunk < n ? bb + chunk : n;
+    if (bb > be) bb = be;
+    return (uint32_t)(be - bb);
+  };
   uint32_t s = 0;
   for (int k = 0; k < per; ++k) {
     const int bidx = first + k;
-    if (bidx < nb) {
-      uint64_t bb = (uint64_t)bidx * chunk, be = bb + chunk < n ? bb + chunk : n;
-      if (bb > be) bb = be;
-      const uint32_t len = (uint32_t)(be - bb);
-      s += o == 1 ? cnt1[bidx] : (o == 0 ? len - cnt1[bidx] : 0u);
-    }
+    if (bidx < nb) s += o == 1 ? cnt1[bidx] : (o == 0 ? block_len(bidx) - cnt1[bidx] : 0u);
   }
   shu[threadIdx.x] = s;
   __syncthreads();
@@ -503,35 +507,52 @@ __global__ __launch_bounds__(1024) void k_measure_decide(const double2* __restri
   for (int k = 0; k < per; ++k) {
     const int bidx = first + k;
     if (bidx < nb) {
-      uint64_t bb = (uint64_t)bidx * chunk, be = bb + chunk < n ? bb + chunk : n;
-      if (bb > be) bb = be;
-      const uint32_t len = (uint32_t)(be - bb);
       off[bidx] = run;
-      run += o == 1 ? cnt1[bidx] : (o == 0 ? len - cnt1[bidx] : 0u);
+      run += o == 1 ? cnt1[bidx] : (o == 0 ? block_len(bidx) - cnt1[bidx] : 0u);
     }
   }
   if (threadIdx.x == blockDim.x - 1) {
     const uint64_t kept = shu[threadIdx.x];
     *nnz_out = kept;
-    // reduce: the label word holding the qubit and the amplitude of every entry
-    ctl->pass_bytes[2] += n * 24u;
+    // reduce: the label word holding the qubit and the amplitude of every
+    // entry (none when the previous write formed the sums)
+    if (!in_off) ctl->pass_bytes[2] += n * 24u;
     // write: that label word of every entry, the rest of each kept entry, and the kept entries written
     ctl->pass_bytes[3] += n * 8u + kept * (2u * entry_bytes - 8u);
   }
 }
 
+// Ordered compaction of the entries with the measured outcome, scaled.  The
+// block's input range is its uniform chunk, or (in_off given) the range the
+// previous measurement's write block produced.  With q_next >= 0 the block
+// also forms the next measurement's sums over the entries it writes, in the
+// same form as the reduce kernel (its output range is then that
+// measurement's input range for this block).
 template <bool WIDE>
 __global__ __launch_bounds__(256) void k_measure_write(Buf in, Buf out, const uint64_t* __restrict__ nnz_p,
                                                        uint32_t q, const MeasRec* __restrict__ rec,
-                                                       const uint32_t* __restrict__ off) {
+                                                       const uint32_t* __restrict__ off,
+                                                       const uint32_t* __restrict__ in_off, int32_t q_next,
+                                                       double2* __restrict__ part_next,
+                                                       uint32_t* __restrict__ cnt1_next) {
   __shared__ uint32_t s_wave[16];
+  __shared__ double2 shd[256];
+  __shared__ uint32_t shu[256];
   const uint64_t n = *nnz_p;
   uint64_t begin, end;
-  chunk_range(n, begin, end);
+  if (in_off) {
+    begin = in_off[blockIdx.x];
+    end = blockIdx.x + 1 < gridDim.x ? in_off[blockIdx.x + 1] : n;
+  } else {
+    chunk_range(n, begin, end);
+  }
   const int o = rec->outcome;
   const double scale = rec->scale;
   uint64_t base = off[blockIdx.x];
   const bool qhi = WIDE && q >= 64;
+  const bool nhi = WIDE && q_next >= 64;
+  double p0 = 0.0, p1 = 0.0;
+  uint32_t c1 = 0;
   for (uint64_t tile = begin; tile < end; tile += blockDim.x) {
     const uint64_t i = tile + threadIdx.x;
     bool keep = false;
@@ -546,11 +567,29 @@ __global__ __launch_bounds__(256) void k_measure_write(Buf in, Buf out, const ui
     const uint64_t pos = base + block_prefix012(keep ? 1u : 0u, s_wave, &tile_total);
     if (keep) {
       const double2 a = in.amp[i];
+      const double2 v = make_double2(a.x * scale, a.y * scale);
       out.key_lo[pos] = lo;
       if (WIDE) out.key_hi[pos] = hi;
-      out.amp[pos] = make_double2(a.x * scale, a.y * scale);
+      out.amp[pos] = v;
+      if (q_next >= 0) {
+        const double p = v.x * v.x + v.y * v.y;
+        if ((((nhi ? hi : lo) >> (q_next & 63)) & 1ull) != 0) {
+          p1 += p;
+          ++c1;
+        } else {
+          p0 += p;
+        }
+      }
     }
     base += tile_total;
+  }
+  if (q_next >= 0) {
+    const double2 sum = block_sum(make_double2(p0, p1), shd);
+    const uint32_t c = block_sum(c1, shu);
+    if (threadIdx.x == 0) {
+      part_next[blockIdx.x] = sum;
+      cnt1_next[blockIdx.x] = c;
+    }
   }
 }
 
@@ -623,19 +662,22 @@ void launch_measure_reduce(hipStream_t st, bool wide, Buf b, const uint64_t* nnz
     hipLaunchKernelGGL(k_measure_reduce<false>, dim3(grid), dim3(block), 0, st, b, nnz, q, s.part, s.cnt1);
 }
 
-void launch_measure_decide(hipStream_t st, BlockScratch s, int nblocks, const uint64_t* nnz_in, uint64_t* nnz_out,
-                           double u, int32_t forced, MeasRec* rec, int32_t* outcome, Ctl* ctl,
-                           uint32_t entry_bytes) {
-  hipLaunchKernelGGL(k_measure_decide, dim3(1), dim3(1024), 0, st, s.part, s.cnt1, s.tot, nblocks, nnz_in, nnz_out,
-                     u, forced, rec, outcome, ctl, entry_bytes);
+void launch_measure_decide(hipStream_t st, const double2* part, const uint32_t* cnt1, uint32_t* off, int nblocks,
+                           const uint64_t* nnz_in, uint64_t* nnz_out, double u, int32_t forced, MeasRec* rec,
+                           int32_t* outcome, Ctl* ctl, uint32_t entry_bytes, const uint32_t* in_off) {
+  hipLaunchKernelGGL(k_measure_decide, dim3(1), dim3(1024), 0, st, part, cnt1, off, nblocks, nnz_in, nnz_out, u,
+                     forced, rec, outcome, ctl, entry_bytes, in_off);
 }
 
 void launch_measure_write(hipStream_t st, bool wide, Buf in, Buf out, const uint64_t* nnz, uint32_t q,
-                          const MeasRec* rec, const uint32_t* off, int grid, int block) {
+                          const MeasRec* rec, const uint32_t* off, const uint32_t* in_off, int32_t q_next,
+                          double2* part_next, uint32_t* cnt1_next, int grid) {
   if (wide)
-    hipLaunchKernelGGL(k_measure_write<true>, dim3(grid), dim3(block), 0, st, in, out, nnz, q, rec, off);
+    hipLaunchKernelGGL(k_measure_write<true>, dim3(grid), dim3(256), 0, st, in, out, nnz, q, rec, off, in_off, q_next,
+                       part_next, cnt1_next);
   else
-    hipLaunchKernelGGL(k_measure_write<false>, dim3(grid), dim3(block), 0, st, in, out, nnz, q, rec, off);
+    hipLaunchKernelGGL(k_measure_write<false>, dim3(grid), dim3(256), 0, st, in, out, nnz, q, rec, off, in_off,
+                       q_next, part_next, cnt1_next);
 }
 
 }  // namespace sparsesim

@@ -386,6 +386,71 @@ def test_pass_byte_counters(sim, n):
     assert ks["block_scan"]["alg_bytes"] == 0 and ks["index_build"]["alg_bytes"] == 0
 
 
+@pytest.mark.parametrize("n,qs", [(20, [3, 0, 19, 7, 11, 5, 16, 2]),
+                                  (100, [3, 70, 64, 63, 99, 10, 80, 0])])
+def test_measurement_chain(sim, n, qs):
+    """Consecutive measurements: after the first, each takes its sums from the
+    previous measurement's write (one reduce pass per chain).  Outcomes and
+    the state match the oracle, and match the same measurements made one at a
+    time; the chain crosses the 64-bit word boundary and holds a forced
+    outcome."""
+    lo, hi, amp = W.random_state(1201 + n, 50_000, n)
+    rng = W.SplitMix64(1301 + n)
+    c = W.Circuit()
+    for k, q in enumerate(qs):
+        c.measure(q, rng.uniform(), forced=1 if k == 4 else -1)
+    ops = c.array()
+    s = sim.Simulator(n, 1 << 17, 0.0)
+    try:
+        s.import_state(lo, hi, amp)
+        sim.sim_kernel_stats_reset(s.h)
+        _, outs, st = s.apply_ops(ops)
+        ks = sim.sim_kernel_stats(s.h)
+        g = s.export()
+        s.import_state(lo, hi, amp)
+        one = [s.measure(int(r["target"]), float(r["param"]), int(r["forced"]))[0] for r in ops]
+        g1 = s.export()
+    finally:
+        s.close()
+    assert ks["measure_reduce"]["launches"] == 1 and ks["measure_write"]["launches"] == len(qs)
+    o = Oracle(n, 0.0)
+    o.import_state(lo, hi, amp)
+    oouts, _ = o.run(ops)
+    assert list(outs) == list(oouts) == one
+    assert_same_state(g, o.export(), what=f"chain n={n}")
+    assert_same_state(g, g1, 1e-14, what="chained vs one at a time")
+    assert st["measures"] == len(qs)
+
+
+def test_measurement_chain_zero_probability(sim):
+    """A forced outcome of probability zero inside a chain stops the list
+    there; the state is the one after the measurements before it."""
+    n = 100
+    lo, hi, amp = W.random_state(1401, 20_000, n)
+    c = W.Circuit()
+    c.measure(3, 0.5, forced=0)
+    c.measure(70, 0.25)
+    c.measure(3, 0.5, forced=1)
+    c.measure(5, 0.5)
+    s = sim.Simulator(n, 1 << 16, 0.0)
+    try:
+        s.import_state(lo, hi, amp)
+        rc, outs, st = s.apply_ops(c.array(), raise_on_error=False)
+        g = s.export()
+        # the failed outcome leaves no error behind for the next call
+        c2 = W.Circuit()
+        c2.measure(5, 0.5)
+        rc2, _, _ = s.apply_ops(c2.array(), raise_on_error=False)
+    finally:
+        s.close()
+    assert rc == sim.SIM_E_STATE and st["measures"] == 2 and rc2 == sim.SIM_OK
+    o = Oracle(n, 0.0)
+    o.import_state(lo, hi, amp)
+    oouts, _ = o.run(c.array()[:2])
+    assert list(outs[:2]) == list(oouts)
+    assert_same_state(g, o.export(), what="chain stopped")
+
+
 # --- gate commuting (Sec. 3.3) ---------------------------------------------------------
 def check_commuting(S, w, tol=1e-12, **kw):
     """GPU run of sim_commute_ops' output vs the oracle's commuting runner."""
