@@ -158,10 +158,17 @@ typedef struct sim_config {
   double eps;           /* prune threshold on |a|^2 after branching gates (0 = drop exact zeros only) */
   double load_factor;   /* hash index target load, (0, 0.9] (default 0.5) */
   uint32_t block;       /* threads per block of the per-entry fused pass: 64, 128 or 256 (default 256) */
-  uint32_t flags;       /* reserved, must be 0 */
+  uint32_t flags;       /* SIM_FLAG_* bits; others must be 0 */
   uint32_t mono_mode;   /* fused-pass kernel: SIM_MONO_AUTO, SIM_MONO_DIRECT or SIM_MONO_BITSLICE */
   uint32_t bs_min_gates; /* SIM_MONO_AUTO: bit-sliced pass for runs of at least this many gates (default 16) */
 } sim_config;
+
+/* Branching gates whose outputs are known to fit the capacity run as one
+ * pass (evaluation, a chained scan over 2048-entry tiles, and the ordered
+ * write in one kernel) on states of up to 2^24 entries; this flag makes them
+ * run as separate count, scan and write passes instead.  The results are
+ * identical. */
+#define SIM_FLAG_U2_TWO_PASS 1u
 
 /* Fused phase/permutation pass variants.  DIRECT evaluates every gate on every
  * entry with sequential complex products (results bit-identical to a plain
@@ -311,8 +318,8 @@ typedef struct sim_kernel_stat {
 /* Change the launch tuning of a live handle: fuse_max, block, mono_mode and
  * bs_min_gates are taken from t (zero = default); load_factor is taken if it
  * is at least the creation value (the index was sized for that one); other
- * fields of t are ignored.  Results change only by rounding (mono_mode) or
- * not at all.  SIM_E_ARG on invalid values. */
+ * fields of t are ignored; flags is taken as well.  Results change only by
+ * rounding (mono_mode) or not at all.  SIM_E_ARG on invalid values. */
 int sim_set_tuning(sim_t* s, const sim_config* t);
 
 /* Bandwidth reference: copy `bytes` (a multiple of 16) from device src to

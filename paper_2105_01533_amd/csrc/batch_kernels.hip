@@ -21,6 +21,11 @@ __device__ __forceinline__ double2 cmul2(double2 a, double2 b) {
 }
 
 __device__ __forceinline__ double2 cadd2(double2 a, double2 b) { return make_double2(a.x + b.x, a.y + b.y); }
+// c ? x : y component by component (a conditional on the vector type itself
+// is lowered through a stack temporary).
+__device__ __forceinline__ double2 sel2b(bool c, double2 x, double2 y) {
+  return make_double2(c ? x.x : y.x, c ? x.y : y.y);
+}
 
 __device__ __forceinline__ bool survives2(double2 a, double eps) {
   return !((a.x * a.x + a.y * a.y < eps) || (a.x == 0.0 && a.y == 0.0));
@@ -77,15 +82,17 @@ __device__ __forceinline__ bool pivot_set2(const U2Desc& d, uint64_t lo, uint64_
 __device__ __forceinline__ int u2_entry(const BItem& it, uint64_t lo, uint64_t hi, double2 a, uint32_t j,
                                         double2* o0, double2* o1) {
   const U2Desc& d = it.u2;
-  if (!ctrl_ok(d, lo, hi, it.wide)) {
-    *o0 = a;
-    return 0;
-  }
+  // Both outputs are written on every path (keeps them in registers).
+  *o0 = a;
+  *o1 = a;
+  if (!ctrl_ok(d, lo, hi, it.wide)) return 0;
   const bool v = pivot_set2(d, lo, hi, it.wide);
   if (!v && j != kNoPartner) return 2;
   const double2 zero = make_double2(0.0, 0.0);
-  const double2 a0 = v ? (j != kNoPartner ? it.in.amp[j] : zero) : a;
-  const double2 a1 = v ? a : zero;
+  double2 aj = zero;
+  if (v && j != kNoPartner) aj = it.in.amp[j];
+  const double2 a0 = sel2b(v, aj, a);
+  const double2 a1 = sel2b(v, a, zero);
   // off-diagonal sign from b0, the pair's label with the pivot bit clear
   const uint64_t b0lo = v ? lo ^ d.x_lo : lo, b0hi = v ? hi ^ d.x_hi : hi;
   const bool odd = ((__popcll(b0lo & d.z_lo) + (it.wide ? __popcll(b0hi & d.z_hi) : 0)) & 1) != 0;
@@ -157,7 +164,8 @@ __global__ __launch_bounds__(64, 2) void kb_mono(const BTick* __restrict__ hdr, 
       for (uint32_t e = threadIdx.x; e < lim; e += 64) {
         const uint64_t idx = base + e;
         uint64_t lo = it.in.key_lo[idx], hi = it.wide ? it.in.key_hi[idx] : 0ull;
-        double2 a = phase ? it.in.amp[idx] : make_double2(0.0, 0.0);
+        double2 a = make_double2(0.0, 0.0);
+        if (phase) a = it.in.amp[idx];
         for (uint32_t k = 0; k < it.n_dops; ++k) {
           const MonoDesc d = it.dops[k];
           const bool c = (lo & d.ctrl_lo) == d.ctrl_lo && (!it.wide || (hi & d.ctrl_hi) == d.ctrl_hi);
@@ -165,8 +173,8 @@ __global__ __launch_bounds__(64, 2) void kb_mono(const BTick* __restrict__ hdr, 
           const uint64_t tbit = 1ull << (d.target & 63);
           const uint64_t w = thi ? hi : lo;
           if (d.flags & kHasPhase) {
-            const double2 r = cmul2(a, (w & tbit) ? d.m1 : d.m0);
-            a = c ? r : a;
+            const double2 r = cmul2(a, sel2b((w & tbit) != 0, d.m1, d.m0));
+            a = sel2b(c, r, a);
           }
           if (d.flags & kFlip) {
             const uint64_t f = c ? tbit : 0ull;

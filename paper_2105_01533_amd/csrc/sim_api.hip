@@ -67,7 +67,7 @@ uint64_t table_slots(uint64_t n, double lf) {
 
 struct Layout {
   size_t buf_lo[2], buf_hi[2], buf_amp[2];
-  size_t table, partner, tot, tot2, cnt1, part, ctl, total;
+  size_t table, partner, tot, tot2, status, cnt1, part, ctl, total;
   uint64_t slots;
 };
 
@@ -80,7 +80,7 @@ bool config_ok(const sim_config* c, std::string* why) {
     return *why = "load_factor must be in (0, 0.9]", false;
   if (c->block != 0 && c->block != 64 && c->block != 128 && c->block != 256)
     return *why = "block must be 64, 128 or 256", false;
-  if (c->flags != 0) return *why = "flags must be 0", false;
+  if (c->flags & ~SIM_FLAG_U2_TWO_PASS) return *why = "unknown flags", false;
   if (c->mono_mode > SIM_MONO_BITSLICE) return *why = "unknown mono_mode", false;
   return true;
 }
@@ -109,6 +109,8 @@ Layout layout_of(const sim_config* c) {
   off += align_up(kMaxBlocks * 4);
   L.tot2 = off;
   off += align_up(kMaxBlocks * 4);
+  L.status = off;
+  off += align_up(kMaxBlocks * 8);
   L.cnt1 = off;
   off += align_up(kMaxBlocks * 4);
   L.part = off;
@@ -228,6 +230,11 @@ struct sim_t {
   double k_ms[KC_COUNT] = {};
   uint64_t mono_bytes_base = 0, mono_updates = 0;
   uint64_t pass_bytes_base[4] = {};
+  // Single-pass branching kernel: tile status words, the launch epoch and the
+  // tile counter's value at the start of the next launch.
+  uint64_t* status = nullptr;
+  uint32_t u2_epoch = 0;
+  uint32_t ticket_base = 0;
   // Sums of a qubit formed by the last measurement's write (see run_measure);
   // valid only until the next operation.
   struct {
@@ -399,6 +406,25 @@ int run_u2(sim_t* s, const sim_gate& g, bool* over) {
     launch_u2_probe(s->stream, s->wide, s->buf[s->cur], nnz_in, s->table, slots - 1, d, s->partner, flat_grid(ub),
                     256);
   }
+  if (!check && !(s->cfg.flags & SIM_FLAG_U2_TWO_PASS) && ub <= (uint64_t)kMaxBlocks * kU2Tile) {
+    // Outputs fit (2 ub <= capacity): evaluate, scan and write in one pass.
+    const int T = (int)std::max<uint64_t>(1, (ub + kU2Tile - 1) / kU2Tile);
+    if (++s->u2_epoch >= (1u << 30)) {   // epochs are 30 bits: start over on cleared words
+      launch_fill(s->stream, s->status, 0ull, kMaxBlocks);
+      s->u2_epoch = 1;
+    }
+    {
+      KTimer t_(s, KC_U2_WRITE);
+      launch_u2_fused(s->stream, s->wide, s->buf[s->cur], s->buf[other], nnz_in, s->partner, d, s->ctl, s->status,
+                      s->ticket_base, s->u2_epoch, d_nnz(s, other), T);
+    }
+    s->ticket_base += (uint32_t)T;
+    HIP_TRY(hipGetLastError());
+    s->cur = other;
+    s->nnz_known = false;
+    s->nnz_ub = std::min<uint64_t>(2 * ub, cap);
+    return SIM_OK;
+  }
   {
     KTimer t_(s, KC_U2_COUNT);
     launch_u2_count(s->stream, s->wide, s->buf[s->cur], nnz_in, d, s->partner, s->bs.tot, s->ctl, G, 256);
@@ -532,6 +558,7 @@ int sim_create(const sim_config* cfg, void* stream, void* workspace, size_t ws_b
   s->bs.cnt1 = reinterpret_cast<uint32_t*>(s->ws + s->L.cnt1);
   s->bs.part = reinterpret_cast<double2*>(s->ws + s->L.part);
   s->ctl = reinterpret_cast<Ctl*>(s->ws + s->L.ctl);
+  s->status = reinterpret_cast<uint64_t*>(s->ws + s->L.status);
   if (hipHostMalloc(&s->h_pinned, 64) != hipSuccess || hipHostMalloc(&s->h_ctl, sizeof(Ctl)) != hipSuccess) {
     sim_destroy(s);
     return fail(SIM_E_NOMEM, "pinned host allocation failed");
@@ -542,6 +569,7 @@ int sim_create(const sim_config* cfg, void* stream, void* workspace, size_t ws_b
     return fail(SIM_E_HIP, "initialising the control block failed");
   }
   s->cur = 0;
+  launch_fill(s->stream, s->status, 0ull, kMaxBlocks);   // epoch 0: no launch has published yet
   launch_set_basis(s->stream, s->buf[0], d_nnz(s, 0), 0, 0);
   if (hipStreamSynchronize(s->stream) != hipSuccess || hipGetLastError() != hipSuccess) {
     sim_destroy(s);
@@ -946,13 +974,15 @@ int sim_apply_gates(sim_t* s, const sim_gate* gates, size_t n, int32_t* outcomes
     HIP_TRY(hipMemcpyAsync(outcomes, s->outcomes.p, meas_seen * 4, hipMemcpyDeviceToHost, s->stream));
   int rc = read_ctl(s);
   if (rc) return rc;
-  if (s->h_ctl->error) {
+  if (const uint32_t err = s->h_ctl->error) {
     // Cleared whatever the result (a forced zero-probability outcome sets it
     // too), so that it never carries over to a later call.
     s->h_ctl->error = 0;
     HIP_TRY(hipMemcpyAsync(&s->ctl->error, &s->h_ctl->error, 4, hipMemcpyHostToDevice, s->stream));
     HIP_TRY(timed_sync(s));
-    if (result == SIM_OK) result = fail(SIM_E_STATE, "measurement of an empty state");
+    if (result == SIM_OK)
+      result = (err & 2u) ? fail(SIM_E_HIP, "single-pass branching kernel gave up waiting for a tile")
+                                      : fail(SIM_E_STATE, "measurement of an empty state");
   }
   s->mchain.valid = false;
   st.gates_applied = i;
@@ -1072,12 +1102,14 @@ int sim_set_tuning(sim_t* s, const sim_config* t) {
   if (t->block != 0 && t->block != 64 && t->block != 128 && t->block != 256)
     return fail(SIM_E_ARG, "block must be 64, 128 or 256");
   if (t->mono_mode > SIM_MONO_BITSLICE) return fail(SIM_E_ARG, "unknown mono_mode");
+  if (t->flags & ~SIM_FLAG_U2_TWO_PASS) return fail(SIM_E_ARG, "unknown flags");
   if (t->load_factor != 0.0 && !(t->load_factor > 0.0 && t->load_factor <= 0.9))
     return fail(SIM_E_ARG, "load_factor must be in (0, 0.9]");
   s->cfg.fuse_max = t->fuse_max ? t->fuse_max : 65536;
   s->cfg.block = t->block;
   s->cfg.mono_mode = t->mono_mode;
   s->cfg.bs_min_gates = t->bs_min_gates;
+  s->cfg.flags = t->flags;
   if (t->load_factor >= lf_of(&s->cfg)) s->cfg.load_factor = t->load_factor;
   return SIM_OK;
 }

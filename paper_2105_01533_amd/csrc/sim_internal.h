@@ -140,8 +140,8 @@ struct Ctl {
   // Algorithmic bytes (entries read and written) of the branching count and
   // write passes and of the measurement reduce and write passes.
   uint64_t pass_bytes[4];
-  uint32_t error;              // nonzero: a measurement had no valid outcome
-  uint32_t pad;
+  uint32_t error;              // bit 0: a measurement had no valid outcome; bit 1: a chained scan gave up waiting
+  uint32_t ticket;             // tile counter of the single-pass branching kernel (wraps)
 };
 
 // Per-measurement record written by the decide kernel.
@@ -231,6 +231,12 @@ void launch_u2_count(hipStream_t st, bool wide, Buf b, const uint64_t* nnz, cons
 void launch_scan(hipStream_t st, uint32_t* tot, int nblocks, uint64_t* nnz_out, Ctl* ctl, uint32_t entry_bytes);
 void launch_u2_write(hipStream_t st, bool wide, Buf in, Buf out, const uint64_t* nnz, const uint32_t* partner,
                      const uint32_t* off, const U2Desc& d, Ctl* ctl, int grid, int block);
+// Entries per block of the single-pass branching kernel; it serves states of
+// at most kMaxBlocks tiles.
+constexpr uint32_t kU2Tile = 2048;
+void launch_u2_fused(hipStream_t st, bool wide, Buf in, Buf out, const uint64_t* nnz, const uint32_t* partner,
+                     const U2Desc& d, Ctl* ctl, uint64_t* status, uint32_t ticket_base, uint32_t epoch,
+                     uint64_t* nnz_out, int grid);
 void launch_measure_reduce(hipStream_t st, bool wide, Buf b, const uint64_t* nnz, uint32_t q, BlockScratch s,
                            int grid, int block);
 void launch_measure_decide(hipStream_t st, const double2* part, const uint32_t* cnt1, uint32_t* off, int nblocks,

@@ -24,6 +24,11 @@ __device__ __forceinline__ double2 cmul(double2 a, double2 b) {
 }
 
 __device__ __forceinline__ double2 cadd(double2 a, double2 b) { return make_double2(a.x + b.x, a.y + b.y); }
+// c ? x : y component by component (a conditional on the vector type itself
+// is lowered through a stack temporary).
+__device__ __forceinline__ double2 sel2(bool c, double2 x, double2 y) {
+  return make_double2(c ? x.x : y.x, c ? x.y : y.y);
+}
 
 // T_eps: an entry survives iff |a|^2 >= eps and it is not exactly zero.
 __device__ __forceinline__ bool survives(double2 a, double eps) {
@@ -123,7 +128,8 @@ __global__ __launch_bounds__(256) void k_mono(Buf b, const uint64_t* __restrict_
       const bool ok = idx < n;
       lo[i] = ok ? b.key_lo[idx] : 0ull;
       hi[i] = (WIDE && ok) ? b.key_hi[idx] : 0ull;
-      a[i] = (ok && run_phase) ? b.amp[idx] : make_double2(0.0, 0.0);
+      a[i] = make_double2(0.0, 0.0);
+      if (ok && run_phase) a[i] = b.amp[idx];
     }
     for (uint32_t j = 0; j < ng; ++j) {
       const MonoDesc d = g[j];
@@ -136,9 +142,9 @@ __global__ __launch_bounds__(256) void k_mono(Buf b, const uint64_t* __restrict_
         if (WIDE) c = c && ((hi[i] & d.ctrl_hi) == d.ctrl_hi);
         const uint64_t w = thi ? hi[i] : lo[i];
         if (d.flags & kHasPhase) {
-          const double2 m = (w & tbit) ? d.m1 : d.m0;
+          const double2 m = sel2((w & tbit) != 0, d.m1, d.m0);
           const double2 r = cmul(a[i], m);
-          a[i] = c ? r : a[i];
+          a[i] = sel2(c, r, a[i]);
         }
         if (d.flags & kFlip) {
           const uint64_t f = c ? tbit : 0ull;
@@ -269,8 +275,10 @@ __device__ __forceinline__ U2Out u2_eval(const Buf& b, const U2Desc& d, uint64_t
     return r;
   }
   const double2 zero = make_double2(0.0, 0.0);
-  const double2 a0 = v ? (j != kNoPartner ? b.amp[j] : zero) : a;
-  const double2 a1 = v ? a : zero;
+  double2 aj = zero;
+  if (v && j != kNoPartner) aj = b.amp[j];
+  const double2 a0 = sel2(v, aj, a);
+  const double2 a1 = sel2(v, a, zero);
   // The off-diagonal sign comes from b0, the pair's label with the pivot clear.
   const uint64_t b0lo = v ? lo ^ d.x_lo : lo, b0hi = v ? hi ^ d.x_hi : hi;
   const bool odd = ((__popcll(b0lo & d.z_lo) + (WIDE ? __popcll(b0hi & d.z_hi) : 0)) & 1) != 0;
@@ -409,6 +417,137 @@ __global__ __launch_bounds__(256) void k_u2_write(Buf in, Buf out, const uint64_
       }
     }
     base += tile_total;
+  }
+}
+
+// Single-pass branching gate, for states whose outputs are known to fit:
+// each block evaluates one tile of kU2Tile entries once (Eq. 2 with T_eps, the
+// results held in registers) and finds where its outputs go by a chained scan
+// over the tiles: it publishes its tile's output count, adds its
+// predecessors' counts back to the first published inclusive prefix,
+// publishes its own inclusive prefix, then writes.  Blocks take tile numbers
+// from a counter in the order they start, so a tile waited on always belongs
+// to a block already running; the wait is bounded even so (a block that gives
+// up sets error bit 2 and its outputs are wrong, but the kernel ends).  A
+// status word packs (epoch, flag, count) and is read and written atomically at
+// device scope, so no fence is needed; the epoch tells this launch's words
+// from those of earlier launches.  Output order is input order, as in the
+// two-pass form.
+constexpr uint64_t kStAgg = 1ull << 32, kStPrefix = 2ull << 32;
+constexpr uint32_t kSpinMax = 1u << 22;
+
+__device__ __forceinline__ uint64_t st_word(uint32_t epoch, uint64_t flag, uint32_t v) {
+  return ((uint64_t)epoch << 34) | flag | v;
+}
+
+template <bool WIDE>
+__global__ __launch_bounds__(256) void k_u2_fused(Buf in, Buf out, const uint64_t* __restrict__ nnz_p,
+                                                  const uint32_t* __restrict__ partner, U2Desc d, Ctl* ctl,
+                                                  uint64_t* status, uint32_t ticket_base, uint32_t epoch,
+                                                  uint64_t* nnz_out) {
+  constexpr int kItems = kU2Tile / 256;
+  __shared__ uint32_t s_wave[16];
+  __shared__ uint32_t sh[256];
+  __shared__ uint32_t s_tile, s_excl;
+  const uint64_t n = *nnz_p;
+  if (threadIdx.x == 0) s_tile = atomicAdd(&ctl->ticket, 1u) - ticket_base;
+  __syncthreads();
+  const uint32_t tile = s_tile;
+  if (tile >= gridDim.x) {   // the counter and the host's base disagree: touch nothing
+    if (threadIdx.x == 0) atomicOr(&ctl->error, 2u);
+    return;
+  }
+  const uint64_t begin = (uint64_t)tile * kU2Tile;
+  U2Out r[kItems];
+  uint64_t lo[kItems], hi[kItems];
+  uint32_t pos[kItems];
+  bool k0[kItems], k1[kItems];
+  uint32_t run = 0, dropped = 0;
+#pragma unroll
+  for (int k = 0; k < kItems; ++k) {
+    const uint64_t i = begin + (uint64_t)k * 256 + threadIdx.x;
+    r[k].mode = 2;
+    k0[k] = k1[k] = false;
+    lo[k] = hi[k] = 0;
+    if (i < n) {
+      lo[k] = in.key_lo[i];
+      hi[k] = WIDE ? in.key_hi[i] : 0ull;
+      r[k] = u2_eval<WIDE>(in, d, lo[k], hi[k], in.amp[i], partner[i]);
+      if (r[k].mode == 0) {
+        k0[k] = survives(r[k].o0, d.eps);
+        dropped += k0[k] ? 0u : 1u;
+      } else if (r[k].mode == 1) {
+        k0[k] = survives(r[k].o0, d.eps);
+        k1[k] = survives(r[k].o1, d.eps);
+        dropped += (k0[k] ? 0u : 1u) + (k1[k] ? 0u : 1u);
+      }
+    }
+    uint32_t tt;
+    pos[k] = run + block_prefix012((k0[k] ? 1u : 0u) + (k1[k] ? 1u : 0u), s_wave, &tt);
+    run += tt;
+  }
+  dropped = block_sum(dropped, sh);
+  if (threadIdx.x == 0) {
+    if (dropped) atomicAdd((unsigned long long*)&ctl->pruned, (unsigned long long)dropped);
+    uint32_t excl = 0;
+    if (tile == 0) {
+      __hip_atomic_store(&status[0], st_word(epoch, kStPrefix, run), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      atomicAdd((unsigned long long*)&ctl->updates, (unsigned long long)n);
+    } else {
+      __hip_atomic_store(&status[tile], st_word(epoch, kStAgg, run), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      uint32_t j = tile - 1, spins = 0;
+      for (;;) {
+        const uint64_t v = __hip_atomic_load(&status[j], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if ((uint32_t)(v >> 34) != epoch) {
+          if (++spins > kSpinMax) {
+            atomicOr(&ctl->error, 2u);
+            break;
+          }
+          __builtin_amdgcn_s_sleep(1);
+          continue;
+        }
+        excl += (uint32_t)v;
+        if ((v & kStPrefix) || j == 0) break;   // tile 0 only ever publishes a prefix
+        --j;
+      }
+      __hip_atomic_store(&status[tile], st_word(epoch, kStPrefix, excl + run), __ATOMIC_RELAXED,
+                         __HIP_MEMORY_SCOPE_AGENT);
+    }
+    s_excl = excl;
+    if (tile == gridDim.x - 1) {
+      const uint32_t eb = WIDE ? 32u : 24u;
+      const uint64_t total = (uint64_t)excl + run;
+      *nnz_out = total;
+      if (total > ctl->peak) ctl->peak = total;
+      atomicAdd((unsigned long long*)&ctl->pass_bytes[1], (unsigned long long)((n + total) * eb));
+    }
+  }
+  __syncthreads();
+  const uint64_t base = s_excl;
+#pragma unroll
+  for (int k = 0; k < kItems; ++k) {
+    uint64_t p = base + pos[k];
+    if (r[k].mode == 0) {
+      if (k0[k]) {
+        out.key_lo[p] = lo[k];
+        if (WIDE) out.key_hi[p] = hi[k];
+        out.amp[p] = r[k].o0;
+      }
+    } else if (r[k].mode == 1) {
+      const bool v = pivot_set<WIDE>(d, lo[k], hi[k]);
+      const uint64_t lo0 = v ? lo[k] ^ d.x_lo : lo[k], hi0 = v ? hi[k] ^ d.x_hi : hi[k];
+      if (k0[k]) {
+        out.key_lo[p] = lo0;
+        if (WIDE) out.key_hi[p] = hi0;
+        out.amp[p] = r[k].o0;
+        ++p;
+      }
+      if (k1[k]) {
+        out.key_lo[p] = lo0 ^ d.x_lo;
+        if (WIDE) out.key_hi[p] = hi0 ^ d.x_hi;
+        out.amp[p] = r[k].o1;
+      }
+    }
   }
 }
 
@@ -652,6 +791,17 @@ void launch_u2_write(hipStream_t st, bool wide, Buf in, Buf out, const uint64_t*
     hipLaunchKernelGGL(k_u2_write<true>, dim3(grid), dim3(block), 0, st, in, out, nnz, partner, off, d, ctl);
   else
     hipLaunchKernelGGL(k_u2_write<false>, dim3(grid), dim3(block), 0, st, in, out, nnz, partner, off, d, ctl);
+}
+
+void launch_u2_fused(hipStream_t st, bool wide, Buf in, Buf out, const uint64_t* nnz, const uint32_t* partner,
+                     const U2Desc& d, Ctl* ctl, uint64_t* status, uint32_t ticket_base, uint32_t epoch,
+                     uint64_t* nnz_out, int grid) {
+  if (wide)
+    hipLaunchKernelGGL(k_u2_fused<true>, dim3(grid), dim3(256), 0, st, in, out, nnz, partner, d, ctl, status,
+                       ticket_base, epoch, nnz_out);
+  else
+    hipLaunchKernelGGL(k_u2_fused<false>, dim3(grid), dim3(256), 0, st, in, out, nnz, partner, d, ctl, status,
+                       ticket_base, epoch, nnz_out);
 }
 
 void launch_measure_reduce(hipStream_t st, bool wide, Buf b, const uint64_t* nnz, uint32_t q, BlockScratch s,

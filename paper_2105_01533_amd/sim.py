@@ -26,6 +26,7 @@ SIM_OK, SIM_E_ARG, SIM_E_NOMEM, SIM_E_CAPACITY, SIM_E_BUFFER, SIM_E_HIP, SIM_E_S
 SIM_OP_MONO, SIM_OP_U2, SIM_OP_MEASURE = 0, 1, 2
 SIM_MONO_AUTO, SIM_MONO_DIRECT, SIM_MONO_BITSLICE = 0, 1, 2
 SIM_PROFILE_OFF, SIM_PROFILE_ALL, SIM_PROFILE_MONO = 0, 1, 2
+SIM_FLAG_U2_TWO_PASS = 1
 
 GATE_DTYPE = np.dtype([
     ("op", "<u4"), ("target", "<u4"), ("ctrl_lo", "<u8"), ("ctrl_hi", "<u8"),
@@ -264,9 +265,9 @@ def sim_device_state(h):
 
 
 def sim_set_tuning(h, fuse_max: int = 0, block: int = 0, mono_mode: int = 0, bs_min_gates: int = 0,
-                   load_factor: float = 0.0):
+                   load_factor: float = 0.0, flags: int = 0):
     t = sim_config(fuse_max=fuse_max, block=block, mono_mode=mono_mode, bs_min_gates=bs_min_gates,
-                   load_factor=load_factor)
+                   load_factor=load_factor, flags=flags)
     _check(_lib.sim_set_tuning(h, ctypes.byref(t)), "sim_set_tuning")
 
 
@@ -300,9 +301,9 @@ class Simulator:
 
     def __init__(self, n_qubits: int, capacity: int, eps: float = 0.0, fuse_max: int = 0,
                  load_factor: float = 0.0, block: int = 0, mono_mode: int = 0, bs_min_gates: int = 0,
-                 device: str = "cuda"):
+                 flags: int = 0, device: str = "cuda"):
         self.cfg = sim_config(n_qubits=n_qubits, fuse_max=fuse_max, capacity=capacity, eps=eps,
-                              load_factor=load_factor, block=block, flags=0, mono_mode=mono_mode,
+                              load_factor=load_factor, block=block, flags=flags, mono_mode=mono_mode,
                               bs_min_gates=bs_min_gates)
         nbytes = sim_workspace_bytes(self.cfg)
         if nbytes == 0:

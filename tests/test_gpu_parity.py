@@ -362,16 +362,51 @@ def test_profiling_modes(sim):
         s.close()
 
 
-@pytest.mark.parametrize("n", [20, 70])
-def test_pass_byte_counters(sim, n):
+@pytest.mark.parametrize("which", ["c0", "c2_small", "c2_wide_ctrl"])
+def test_u2_single_pass_matches_two_pass(sim, which):
+    """Branching gates whose outputs fit run as one pass (evaluation, chained
+    scan over 2048-entry tiles, ordered write); the state is bitwise the one
+    the separate count, scan and write passes produce, in the same order."""
+    if which == "c0":
+        w = W.config0(seed=W.seed_for(0, 3))
+    elif which == "c2_small":
+        w = W.config2(41, n=100, h_qubits=14, gates=8000, round_gates=2000, meas_per_round=3)
+    else:
+        w = W.config2(43, n=128, h_qubits=12, gates=6000, round_gates=3000, meas_per_round=2)
+    out = []
+    for flags in (0, sim.SIM_FLAG_U2_TWO_PASS):
+        s = sim.Simulator(w.n_qubits, w.capacity, w.eps, flags=flags)
+        try:
+            s.set_basis(*w.basis)
+            sim.sim_kernel_stats_reset(s.h)
+            _, outs, st = s.apply_ops(w.ops)
+            ks = sim.sim_kernel_stats(s.h)
+            out.append((s.export(sort=False), list(outs), st, ks))
+        finally:
+            s.close()
+    (a, oa, sa, ka), (b, ob, sb, kb) = out
+    for x, y in zip(a, b):
+        assert x.tobytes() == y.tobytes()
+    assert oa == ob
+    for k in ("u2_applied", "u2_skipped", "pruned", "peak_nnz", "updates"):
+        assert sa[k] == sb[k], k
+    assert ka["u2_write"]["launches"] == kb["u2_write"]["launches"] == sa["u2_applied"]
+    assert kb["u2_count"]["launches"] == sa["u2_applied"]
+    assert ka["u2_count"]["launches"] < sa["u2_applied"]       # most ran as one pass
+    assert ka["u2_write"]["alg_bytes"] == kb["u2_write"]["alg_bytes"]
+
+
+@pytest.mark.parametrize("n,two_pass", [(20, False), (70, False), (70, True)])
+def test_pass_byte_counters(sim, n, two_pass):
     """Algorithmic bytes per pass class on a circuit whose entry counts are
     known: three Hadamards take 1 -> 2 -> 4 -> 8 entries, then a measurement
-    with a forced outcome keeps 4 of 8."""
+    with a forced outcome keeps 4 of 8.  The count pass exists only in the
+    two-pass form of branching gates."""
     c = W.Circuit()
     for q in (0, 1, n - 1):
         c.h(q)
     c.measure(1, 0.5, forced=0)
-    s = sim.Simulator(n, 1 << 10, 0.0)
+    s = sim.Simulator(n, 1 << 10, 0.0, flags=sim.SIM_FLAG_U2_TWO_PASS if two_pass else 0)
     try:
         sim.sim_kernel_stats_reset(s.h)
         s.apply_ops(c.array())
@@ -379,7 +414,7 @@ def test_pass_byte_counters(sim, n):
     finally:
         s.close()
     eb = 32 if n > 64 else 24
-    assert ks["u2_count"]["alg_bytes"] == (1 + 2 + 4) * eb
+    assert ks["u2_count"]["alg_bytes"] == ((1 + 2 + 4) * eb if two_pass else 0)
     assert ks["u2_write"]["alg_bytes"] == ((1 + 2) + (2 + 4) + (4 + 8)) * eb
     assert ks["measure_reduce"]["alg_bytes"] == 8 * 24
     assert ks["measure_write"]["alg_bytes"] == 8 * 8 + 4 * (2 * eb - 8)
