@@ -487,39 +487,56 @@ __global__ __launch_bounds__(256) void k_u2_fused(Buf in, Buf out, const uint64_
     run += tt;
   }
   dropped = block_sum(dropped, sh);
+  // Publish this tile's count, then the first wave looks back 64 tiles per
+  // poll (lane l reads tile - 1 - l) and adds counts back to the nearest
+  // published inclusive prefix; positions before tile 0 count as a prefix of 0.
   if (threadIdx.x == 0) {
     if (dropped) atomicAdd((unsigned long long*)&ctl->pruned, (unsigned long long)dropped);
+    __hip_atomic_store(&status[tile], st_word(epoch, tile == 0 ? kStPrefix : kStAgg, run), __ATOMIC_RELAXED,
+                       __HIP_MEMORY_SCOPE_AGENT);
+    if (tile == 0) atomicAdd((unsigned long long*)&ctl->updates, (unsigned long long)n);
+  }
+  if (threadIdx.x < 64) {
+    const int lane = threadIdx.x;
     uint32_t excl = 0;
-    if (tile == 0) {
-      __hip_atomic_store(&status[0], st_word(epoch, kStPrefix, run), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      atomicAdd((unsigned long long*)&ctl->updates, (unsigned long long)n);
-    } else {
-      __hip_atomic_store(&status[tile], st_word(epoch, kStAgg, run), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      uint32_t j = tile - 1, spins = 0;
-      for (;;) {
-        const uint64_t v = __hip_atomic_load(&status[j], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        if ((uint32_t)(v >> 34) != epoch) {
-          if (++spins > kSpinMax) {
-            atomicOr(&ctl->error, 2u);
-            break;
-          }
-          __builtin_amdgcn_s_sleep(1);
-          continue;
+    int64_t hi_tile = (int64_t)tile - 1;
+    uint32_t spins = 0;
+    while (hi_tile >= 0) {
+      const int64_t j = hi_tile - lane;
+      const uint64_t v = j >= 0 ? __hip_atomic_load(&status[j], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
+                                : st_word(epoch, kStPrefix, 0);
+      const bool ready = (uint32_t)(v >> 34) == epoch;
+      const uint64_t pmask = __ballot(ready && (v & kStPrefix));
+      const uint64_t nready = __ballot(!ready);
+      const int first = pmask ? __builtin_ctzll(pmask) : 63;   // nearest prefix in the window, else all 64
+      const uint64_t need = first == 63 ? ~0ull : ((2ull << first) - 1);
+      if (nready & need) {
+        if (++spins > kSpinMax) {
+          if (lane == 0) atomicOr(&ctl->error, 2u);
+          break;
         }
-        excl += (uint32_t)v;
-        if ((v & kStPrefix) || j == 0) break;   // tile 0 only ever publishes a prefix
-        --j;
+        __builtin_amdgcn_s_sleep(1);
+        continue;
       }
-      __hip_atomic_store(&status[tile], st_word(epoch, kStPrefix, excl + run), __ATOMIC_RELAXED,
-                         __HIP_MEMORY_SCOPE_AGENT);
+      uint32_t x = lane <= first ? (uint32_t)v : 0u;
+#pragma unroll
+      for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o);
+      excl += x;
+      if (pmask) break;
+      hi_tile -= 64;
     }
-    s_excl = excl;
-    if (tile == gridDim.x - 1) {
-      const uint32_t eb = WIDE ? 32u : 24u;
-      const uint64_t total = (uint64_t)excl + run;
-      *nnz_out = total;
-      if (total > ctl->peak) ctl->peak = total;
-      atomicAdd((unsigned long long*)&ctl->pass_bytes[1], (unsigned long long)((n + total) * eb));
+    if (lane == 0) {
+      if (tile != 0)
+        __hip_atomic_store(&status[tile], st_word(epoch, kStPrefix, excl + run), __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
+      s_excl = excl;
+      if (tile == gridDim.x - 1) {
+        const uint32_t eb = WIDE ? 32u : 24u;
+        const uint64_t total = (uint64_t)excl + run;
+        *nnz_out = total;
+        if (total > ctl->peak) ctl->peak = total;
+        atomicAdd((unsigned long long*)&ctl->pass_bytes[1], (unsigned long long)((n + total) * eb));
+      }
     }
   }
   __syncthreads();
