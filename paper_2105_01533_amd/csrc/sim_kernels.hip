@@ -611,8 +611,42 @@ __global__ __launch_bounds__(1024) void k_measure_decide(const double2* __restri
   __shared__ double2 shd[1024];
   __shared__ uint32_t shu[1024];
   __shared__ int s_o;
+  // Every load is issued before any sum needs it (a rolled loop would wait on
+  // each in turn); the sums keep the per-thread order k, k + 1024, ...
+  constexpr int kPer = kMaxBlocks / 1024;
+  const uint64_t n = *nnz_in;
+  double2 pv[kPer];
+#pragma unroll
+  for (int i = 0; i < kPer; ++i) {
+    const int k = threadIdx.x + 1024 * i;
+    pv[i] = make_double2(0.0, 0.0);
+    if (k < nb) pv[i] = part[k];
+  }
+  // Per-block kept counts need each block's input length: its uniform chunk,
+  // or (in_off given) the range the previous measurement's write block
+  // produced.  Thread t owns blocks [t per, (t + 1) per).
+  const uint64_t chunk = (n + nb - 1) / nb;
+  const int per = (nb + 1023) / 1024;
+  const int first = threadIdx.x * per;
+  uint32_t c1[kPer], len[kPer];
+#pragma unroll
+  for (int i = 0; i < kPer; ++i) {
+    const int bidx = first + i;
+    c1[i] = len[i] = 0;
+    if (i < per && bidx < nb) {
+      c1[i] = cnt1[bidx];
+      if (in_off) {
+        len[i] = (uint32_t)((bidx + 1 < nb ? (uint64_t)in_off[bidx + 1] : n) - in_off[bidx]);
+      } else {
+        uint64_t bb = (uint64_t)bidx * chunk, be = bb + chunk < n ? bb + chunk : n;
+        if (bb > be) bb = be;
+        len[i] = (uint32_t)(be - bb);
+      }
+    }
+  }
   double2 acc = make_double2(0.0, 0.0);
-  for (int k = threadIdx.x; k < nb; k += blockDim.x) acc = cadd(acc, part[k]);
+#pragma unroll
+  for (int i = 0; i < kPer; ++i) acc = cadd(acc, pv[i]);
   const double2 P = block_sum(acc, shd);
   if (threadIdx.x == 0) {
     const double tot = P.x + P.y;
@@ -634,22 +668,12 @@ __global__ __launch_bounds__(1024) void k_measure_decide(const double2* __restri
   __syncthreads();
   const int o = s_o;
   // Output counts per block for the chosen outcome, then exclusive scan.
-  // A block's input range is its uniform chunk, or (in_off given) the range
-  // the previous measurement's write block b produced.
-  const uint64_t n = *nnz_in;
-  const uint64_t chunk = (n + nb - 1) / nb;
-  const int per = (nb + blockDim.x - 1) / blockDim.x;
-  const int first = threadIdx.x * per;
-  auto block_len = [&](int bidx) -> uint32_t {
-    if (in_off) return (uint32_t)((bidx + 1 < nb ? (uint64_t)in_off[bidx + 1] : n) - in_off[bidx]);
-    uint64_t bb = (uint64_t)bidx * chunk, be = bb + chunk < n ? bb + chunk : n;
-    if (bb > be) bb = be;
-    return (uint32_t)(be - bb);
-  };
+  uint32_t kept_b[kPer];
   uint32_t s = 0;
-  for (int k = 0; k < per; ++k) {
-    const int bidx = first + k;
-    if (bidx < nb) s += o == 1 ? cnt1[bidx] : (o == 0 ? block_len(bidx) - cnt1[bidx] : 0u);
+#pragma unroll
+  for (int i = 0; i < kPer; ++i) {
+    kept_b[i] = o == 1 ? c1[i] : (o == 0 ? len[i] - c1[i] : 0u);
+    s += kept_b[i];
   }
   shu[threadIdx.x] = s;
   __syncthreads();
@@ -660,11 +684,12 @@ __global__ __launch_bounds__(1024) void k_measure_decide(const double2* __restri
     __syncthreads();
   }
   uint32_t run = shu[threadIdx.x] - s;
-  for (int k = 0; k < per; ++k) {
-    const int bidx = first + k;
-    if (bidx < nb) {
+#pragma unroll
+  for (int i = 0; i < kPer; ++i) {
+    const int bidx = first + i;
+    if (i < per && bidx < nb) {
       off[bidx] = run;
-      run += o == 1 ? cnt1[bidx] : (o == 0 ? block_len(bidx) - cnt1[bidx] : 0u);
+      run += kept_b[i];
     }
   }
   if (threadIdx.x == blockDim.x - 1) {
