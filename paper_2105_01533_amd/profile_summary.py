@@ -1,7 +1,8 @@
 """Summaries of rocprofv3 runs of bench.py, for the committed profiles.
 
-  stats   <kernel-trace dir> <out.md> <command>   per-kernel calls / total / average duration
-  traffic <FETCH_SIZE dir> <WRITE_SIZE dir> <out.md> <out.json> <command...>
+  stats   <kernel-trace dir> <out.md> <command> [<title>]
+          per-kernel calls / total / average duration
+  traffic <FETCH_SIZE dir> <WRITE_SIZE dir> <out.md> <out.json> <workload> <command...>
           per-kernel KiB per dispatch from the two counter runs, scaled by what
           the same counters read for the reference copy kernel (k_copy16, which
           moves a known number of bytes each way), and the fused pass's HBM
