@@ -418,8 +418,8 @@ int run_u2(sim_t* s, const sim_gate& g, bool* over) {
       launch_u2_fused(s->stream, s->wide, s->buf[s->cur], s->buf[other], nnz_in, s->partner, d, s->ctl, s->status,
                       s->ticket_base, s->u2_epoch, d_nnz(s, other), T);
     }
-    s->ticket_base += (uint32_t)T;
     HIP_TRY(hipGetLastError());
+    s->ticket_base += (uint32_t)T;   // only a launched kernel advances the device counter
     s->cur = other;
     s->nnz_known = false;
     s->nnz_ub = std::min<uint64_t>(2 * ub, cap);
