@@ -334,33 +334,24 @@ __device__ __forceinline__ void bs_tile(const Buf& b, uint64_t base, uint32_t li
               x[u] = plane(Lb, off_p0(a[u])) & plane(Lb, off_p1(a[u])) & plane(Lb, off_p2(bw[u])) &
                      plane(Lb, off_t(a[u]));
           }
-          // Nibble i of W[c] = the ops (bit u = op u) that hold for entry
-          // 8c + i: a byte transpose of the four masks, then each word's
-          // 4 x 8 bit matrix transposed by rotating its bit index
-          // (u1 u0 i2 i1 i0) -> (i2 i1 i0 u1 u0) with four delta swaps.
-          uint32_t W[4];
+          // Entry j's table offset, 8 x (the ops, bit u = op u, whose
+          // condition holds for it), is byte j >> 3 of B[j & 7]: bit j of mask
+          // u moves to bit 8 (j >> 3) + 3 + u by one constant shift, and the
+          // four masks merge under disjoint byte-lane masks.
+          uint32_t B[8];
 #pragma unroll
-          for (int c = 0; c < 4; ++c) {
-            uint32_t w = ((x[0] >> (8 * c)) & 0xffu) | (((x[1] >> (8 * c)) & 0xffu) << 8) |
-                         (((x[2] >> (8 * c)) & 0xffu) << 16) | (((x[3] >> (8 * c)) & 0xffu) << 24);
-            uint32_t t;
-            t = (w ^ (w >> 12)) & 0x0000F0F0u; w ^= t ^ (t << 12);   // index bits 2 <-> 4
-            t = (w ^ (w >> 6)) & 0x00CC00CCu;  w ^= t ^ (t << 6);    // 1 <-> 3
-            t = (w ^ (w >> 3)) & 0x0A0A0A0Au;  w ^= t ^ (t << 3);    // 0 <-> 2
-            t = (w ^ (w >> 1)) & 0x22222222u;  w ^= t ^ (t << 1);    // 0 <-> 1
-            W[c] = w;
-          }
-          // Each index times eight, one per byte: byte m of E[c] for entry
-          // 8c + 2m, of O[c] for entry 8c + 2m + 1 (the byte is the entry's
-          // table offset).
-          uint32_t E[4], O[4];
+          for (int w = 0; w < 8; ++w) {
+            uint32_t r = 0;
 #pragma unroll
-          for (int c = 0; c < 4; ++c) {
-            E[c] = (W[c] << 3) & 0x78787878u;
-            O[c] = (W[c] >> 1) & 0x78787878u;
+            for (int u = 0; u < kBsGroup; ++u) {
+              const int sh = w - 3 - u;
+              const uint32_t y = sh >= 0 ? x[u] >> sh : x[u] << -sh;
+              r |= y & (0x01010101u << (3 + u));
+            }
+            B[w] = r;
             // Keep the byte extraction below a single bit-field extract per
-            // entry (otherwise it is folded back into a shift and a mask).
-            asm volatile("" : "+v"(E[c]), "+v"(O[c]));
+            // entry (otherwise it is folded back into shifts and masks).
+            asm volatile("" : "+v"(B[w]));
           }
           // An entry gains the sum of the fractions of the ops whose condition
           // holds for it: one of 16 subset sums, kept as 8-byte words in a
@@ -384,8 +375,8 @@ __device__ __forceinline__ void bs_tile(const Buf& b, uint64_t base, uint32_t li
             uint64_t v[14];
 #pragma unroll
             for (int k = 0; k < 14 && j0 + k < 32; ++k) {
-              const int j = j0 + k, c = j >> 3, i = j & 7;
-              const uint32_t off = __builtin_amdgcn_ubfe((i & 1) ? O[c] : E[c], 8 * (i >> 1), 8);
+              const int j = j0 + k;
+              const uint32_t off = __builtin_amdgcn_ubfe(B[j & 7], 8 * (j >> 3), 8);
               v[k] = *reinterpret_cast<const uint64_t*>(table + off);
             }
             __builtin_amdgcn_sched_barrier(0);
