@@ -74,16 +74,29 @@ __device__ __forceinline__ uint32_t block_prefix012(uint32_t e, uint32_t* s_wave
   return woff + pre;
 }
 
-// Sum over the block in a fixed tree order (deterministic).
+// Sum over the block in a fixed order (deterministic): a butterfly within
+// each wave, then the waves' sums in wave order.  sh needs one slot per wave.
+__device__ __forceinline__ uint32_t wave_sum(uint32_t v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+  return v;
+}
+__device__ __forceinline__ double2 wave_sum(double2 v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    const double x = __shfl_xor(v.x, o), y = __shfl_xor(v.y, o);
+    v = make_double2(v.x + x, v.y + y);
+  }
+  return v;
+}
 template <typename T>
 __device__ __forceinline__ T block_sum(T v, T* sh) {
-  sh[threadIdx.x] = v;
+  const int nw = blockDim.x >> 6;
+  v = wave_sum(v);
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
   __syncthreads();
-  for (unsigned s = blockDim.x >> 1; s > 0; s >>= 1) {
-    if (threadIdx.x < s) sh[threadIdx.x] = sh[threadIdx.x] + sh[threadIdx.x + s];
-    __syncthreads();
-  }
-  const T r = sh[0];
+  T r = sh[0];
+  for (int w = 1; w < nw; ++w) r = r + sh[w];
   __syncthreads();
   return r;
 }
@@ -675,15 +688,23 @@ __global__ __launch_bounds__(1024) void k_measure_decide(const double2* __restri
     kept_b[i] = o == 1 ? c1[i] : (o == 0 ? len[i] - c1[i] : 0u);
     s += kept_b[i];
   }
-  shu[threadIdx.x] = s;
-  __syncthreads();
-  for (unsigned d = 1; d < blockDim.x; d <<= 1) {
-    const uint32_t x = threadIdx.x >= d ? shu[threadIdx.x - d] : 0u;
-    __syncthreads();
-    shu[threadIdx.x] += x;
-    __syncthreads();
+  // Inclusive scan of the per-thread counts: within each wave by shuffles,
+  // then the preceding waves' totals.
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  uint32_t incl = s;
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    const uint32_t y = __shfl_up(incl, d);
+    if (lane >= d) incl += y;
   }
-  uint32_t run = shu[threadIdx.x] - s;
+  if (lane == 63) shu[wid] = incl;
+  __syncthreads();
+  uint32_t kept_total = 0;
+  for (int w = 0; w < (int)(blockDim.x >> 6); ++w) {
+    if (w < wid) incl += shu[w];
+    kept_total += shu[w];
+  }
+  uint32_t run = incl - s;
 #pragma unroll
   for (int i = 0; i < kPer; ++i) {
     const int bidx = first + i;
@@ -693,7 +714,7 @@ __global__ __launch_bounds__(1024) void k_measure_decide(const double2* __restri
     }
   }
   if (threadIdx.x == blockDim.x - 1) {
-    const uint64_t kept = shu[threadIdx.x];
+    const uint64_t kept = kept_total;
     *nnz_out = kept;
     // reduce: the label word holding the qubit and the amplitude of every
     // entry (none when the previous write formed the sums)
