@@ -235,6 +235,11 @@ struct sim_t {
   uint64_t* status = nullptr;
   uint32_t u2_epoch = 0;
   uint32_t ticket_base = 0;
+  // Hash index slots [0, table_dirty) may hold entries; the rest are empty
+  // (the whole index is emptied at creation).  The single-pass branching
+  // kernel empties the slots its gate used, so a separate clearing launch is
+  // needed only after the two-pass form.
+  uint64_t table_dirty = 0;
   // Sums of a qubit formed by the last measurement's write (see run_measure);
   // valid only until the next operation.
   struct {
@@ -392,10 +397,12 @@ int run_u2(sim_t* s, const sim_gate& g, bool* over) {
   const uint64_t* nnz_in = d_nnz(s, s->cur);
   const U2Desc d = u2_desc(g, s->cfg.eps);
   const int G = chunk_grid(ub);
-  {
+  const uint64_t prior = s->table_dirty;
+  if (const uint64_t dirty = std::min<uint64_t>(prior, slots)) {
     KTimer t_(s, KC_FILL);
-    launch_fill(s->stream, s->table, kEmptySlot, slots);
+    launch_fill(s->stream, s->table, kEmptySlot, dirty);
   }
+  s->table_dirty = std::max<uint64_t>(prior, slots);   // the build below writes into [0, slots)
   {
     KTimer t_(s, KC_BUILD);
     launch_index_build(s->stream, s->wide, s->buf[s->cur], nnz_in, s->table, slots - 1, d, s->partner,
@@ -416,10 +423,11 @@ int run_u2(sim_t* s, const sim_gate& g, bool* over) {
     {
       KTimer t_(s, KC_U2_WRITE);
       launch_u2_fused(s->stream, s->wide, s->buf[s->cur], s->buf[other], nnz_in, s->partner, d, s->ctl, s->status,
-                      s->ticket_base, s->u2_epoch, d_nnz(s, other), T);
+                      s->ticket_base, s->u2_epoch, d_nnz(s, other), s->table, slots, T);
     }
     HIP_TRY(hipGetLastError());
     s->ticket_base += (uint32_t)T;   // only a launched kernel advances the device counter
+    s->table_dirty = prior > slots ? prior : 0;   // [0, slots) emptied by the kernel
     s->cur = other;
     s->nnz_known = false;
     s->nnz_ub = std::min<uint64_t>(2 * ub, cap);
@@ -570,6 +578,7 @@ int sim_create(const sim_config* cfg, void* stream, void* workspace, size_t ws_b
   }
   s->cur = 0;
   launch_fill(s->stream, s->status, 0ull, kMaxBlocks);   // epoch 0: no launch has published yet
+  launch_fill(s->stream, s->table, kEmptySlot, s->L.slots);
   launch_set_basis(s->stream, s->buf[0], d_nnz(s, 0), 0, 0);
   if (hipStreamSynchronize(s->stream) != hipSuccess || hipGetLastError() != hipSuccess) {
     sim_destroy(s);

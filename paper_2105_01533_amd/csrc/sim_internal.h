@@ -236,7 +236,7 @@ void launch_u2_write(hipStream_t st, bool wide, Buf in, Buf out, const uint64_t*
 constexpr uint32_t kU2Tile = 2048;
 void launch_u2_fused(hipStream_t st, bool wide, Buf in, Buf out, const uint64_t* nnz, const uint32_t* partner,
                      const U2Desc& d, Ctl* ctl, uint64_t* status, uint32_t ticket_base, uint32_t epoch,
-                     uint64_t* nnz_out, int grid);
+                     uint64_t* nnz_out, uint64_t* table, uint64_t clear_slots, int grid);
 void launch_measure_reduce(hipStream_t st, bool wide, Buf b, const uint64_t* nnz, uint32_t q, BlockScratch s,
                            int grid, int block);
 void launch_measure_decide(hipStream_t st, const double2* part, const uint32_t* cnt1, uint32_t* off, int nblocks,

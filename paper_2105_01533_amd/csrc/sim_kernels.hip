@@ -457,12 +457,18 @@ template <bool WIDE>
 __global__ __launch_bounds__(256) void k_u2_fused(Buf in, Buf out, const uint64_t* __restrict__ nnz_p,
                                                   const uint32_t* __restrict__ partner, U2Desc d, Ctl* ctl,
                                                   uint64_t* status, uint32_t ticket_base, uint32_t epoch,
-                                                  uint64_t* nnz_out) {
+                                                  uint64_t* nnz_out, uint64_t* __restrict__ table,
+                                                  uint64_t clear_slots) {
   constexpr int kItems = kU2Tile / 256;
   __shared__ uint32_t s_wave[16];
   __shared__ uint32_t sh[256];
   __shared__ uint32_t s_tile, s_excl;
   const uint64_t n = *nnz_p;
+  // This gate is done with the hash index: empty its first clear_slots slots
+  // for the next branching gate (every block, by block index).
+  for (uint64_t k = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; k < clear_slots;
+       k += (uint64_t)gridDim.x * blockDim.x)
+    table[k] = kEmptySlot;
   if (threadIdx.x == 0) s_tile = atomicAdd(&ctl->ticket, 1u) - ticket_base;
   __syncthreads();
   const uint32_t tile = s_tile;
@@ -858,13 +864,13 @@ void launch_u2_write(hipStream_t st, bool wide, Buf in, Buf out, const uint64_t*
 
 void launch_u2_fused(hipStream_t st, bool wide, Buf in, Buf out, const uint64_t* nnz, const uint32_t* partner,
                      const U2Desc& d, Ctl* ctl, uint64_t* status, uint32_t ticket_base, uint32_t epoch,
-                     uint64_t* nnz_out, int grid) {
+                     uint64_t* nnz_out, uint64_t* table, uint64_t clear_slots, int grid) {
   if (wide)
     hipLaunchKernelGGL(k_u2_fused<true>, dim3(grid), dim3(256), 0, st, in, out, nnz, partner, d, ctl, status,
-                       ticket_base, epoch, nnz_out);
+                       ticket_base, epoch, nnz_out, table, clear_slots);
   else
     hipLaunchKernelGGL(k_u2_fused<false>, dim3(grid), dim3(256), 0, st, in, out, nnz, partner, d, ctl, status,
-                       ticket_base, epoch, nnz_out);
+                       ticket_base, epoch, nnz_out, table, clear_slots);
 }
 
 void launch_measure_reduce(hipStream_t st, bool wide, Buf b, const uint64_t* nnz, uint32_t q, BlockScratch s,
