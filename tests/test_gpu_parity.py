@@ -396,6 +396,31 @@ def test_u2_single_pass_matches_two_pass(sim, which):
     assert ka["u2_write"]["alg_bytes"] == kb["u2_write"]["alg_bytes"]
 
 
+def test_index_reuse_across_forms_and_sizes(sim):
+    """The hash index is emptied by the single-pass kernel for the next gate
+    and by a clearing launch only where that cannot be known (after the
+    two-pass form, or beyond what the last gate used).  Alternating forms and
+    state sizes on one handle, every result matches the oracle."""
+    n = 80
+    s = sim.Simulator(n, 1 << 21, 0.0)
+    try:
+        for step, (entries, two_pass) in enumerate([(60_000, True), (3_000, False), (50_000, False),
+                                                     (500, True), (40_000, False), (70_000, False)]):
+            lo, hi, amp = W.random_state(1500 + step, entries, n)
+            c = W.Circuit()
+            for q in (3, 40, 70, 5):
+                c.h(q, ctrls=(11,) if q == 40 else ())
+            sim.sim_set_tuning(s.h, flags=sim.SIM_FLAG_U2_TWO_PASS if two_pass else 0)
+            s.import_state(lo, hi, amp)
+            s.apply_ops(c.array())
+            o = Oracle(n, 0.0)
+            o.import_state(lo, hi, amp)
+            o.run(c.array())
+            assert_same_state(s.export(), o.export(), what=f"step {step}")
+    finally:
+        s.close()
+
+
 @pytest.mark.parametrize("n,two_pass", [(20, False), (70, False), (70, True)])
 def test_pass_byte_counters(sim, n, two_pass):
     """Algorithmic bytes per pass class on a circuit whose entry counts are
