@@ -291,6 +291,11 @@ int sim_export_state(sim_t* s, sim_key* keys, sim_c64* amps, uint64_t cap, uint6
 int sim_device_state(sim_t* s, uint64_t** key_lo, uint64_t** key_hi, double** amp, uint64_t** d_nnz);
 
 /* Per-kernel-class counters, cumulative since creation or the last reset.
+ * The kernel classes are mono_pass, index_fill, index_build, u2_probe,
+ * u2_count, block_scan, u2_write (the single-pass branching kernel counts
+ * here; u2_count and block_scan run only in the two-pass form),
+ * measure_reduce, measure_decide and measure_write (a chain of consecutive
+ * measurements runs one reduce).
  * With profiling on for a class (sim_set_profiling), every launch of it is
  * bracketed by HIP events on the handle's stream and total_ms sums their
  * elapsed times; otherwise total_ms is 0.  alg_bytes is the algorithmic HBM
