@@ -387,13 +387,18 @@ void RunCompiler::group_range(const BsOp* src, uint32_t n, std::vector<BsGroup>&
   // only go in TURN groups).
   // Turn ops are sparse but commute with every op that does not flip one of
   // their condition planes, so TURN groups look further ahead.
+  // kAnyFlip12: flips with one or two controls, for CCX-shaped groups (a
+  // CNOT's second control slot names the all-ones plane).
+  constexpr uint32_t kAnyFlip12 = 0x100;
   auto select = [&](uint32_t want, uint32_t* sel, uint32_t cap) -> uint32_t {
     uint32_t k = 0, seen = 0;
     const uint32_t window = want == kShapeTurn ? 4 * kWindow : cap > (uint32_t)kBsGroup ? pair_window : kWindow;
     Mask gr, gw, br, bw;   // group reads / writes, reads / writes of ops passed over
     for (uint32_t j = nxt[n]; j != n && seen < window && k < cap; j = nxt[j], ++seen) {
       const Item& it = items[j];
-      const bool shape_ok = want == kShapeGeneric ? it.shape != kShapeTurn : it.shape == want;
+      const bool shape_ok = want == kShapeGeneric ? it.shape != kShapeTurn
+                            : want == kAnyFlip12  ? it.shape == kShapeCX || it.shape == kShapeCCX
+                                                  : it.shape == want;
       const bool commutes = !it.w.meets(br) && !it.w.meets(bw) && !it.r.meets(bw);
       const bool fits = !it.w.meets(gr) && !it.w.meets(gw) && !it.r.meets(gw);
       if (shape_ok && commutes && fits) {
@@ -445,7 +450,7 @@ void RunCompiler::group_range(const BsOp* src, uint32_t n, std::vector<BsGroup>&
     out.push_back(grp);
   };
   const size_t base = out.size();
-  uint32_t pick[4 * kBsGroup], best[kBsGroup];
+  uint32_t pick[4 * kBsGroup], best[kBsGroup], best_flip[4 * kBsGroup];
   while (nxt[n] != n) {
     const uint32_t hs = items[nxt[n]].shape;
     const bool flip = hs == kShapeX || hs == kShapeCX || hs == kShapeCCX;
@@ -453,10 +458,21 @@ void RunCompiler::group_range(const BsOp* src, uint32_t n, std::vector<BsGroup>&
     // sixteen mutually independent ops of one shape, read together by the
     // kernel.
     uint32_t np = select(hs, pick, flip || hs == kShapeOmega ? 4 * kBsGroup : kBsGroup);
+    uint32_t gshape = hs;
+    if ((hs == kShapeCX || hs == kShapeCCX) && np < 2 * kBsGroup) {
+      // No pair of one shape: CNOTs and Toffolis together may make a
+      // CCX-shaped pair or quad (eight or sixteen reads in flight).
+      const uint32_t nm = select(kAnyFlip12, best_flip, 4 * kBsGroup);
+      if (nm >= 2 * kBsGroup) {
+        for (uint32_t u = 0; u < nm; ++u) pick[u] = best_flip[u];
+        np = nm;
+        gshape = kShapeCCX;
+      }
+    }
     if (np >= 2 * kBsGroup) {
       const uint32_t ng = np == 4 * kBsGroup ? 4 : 2;
       for (uint32_t k = 0; k < ng; ++k) {
-        emit(pick + k * kBsGroup, kBsGroup, hs);
+        emit(pick + k * kBsGroup, kBsGroup, gshape);
         if (k == 0) out.back().a[1] |= ng == 4 ? kQuadBit : kPairBit;
       }
       // Picks beyond the emitted groups stay pending.
