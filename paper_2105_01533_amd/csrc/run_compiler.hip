@@ -450,25 +450,17 @@ void RunCompiler::group_range(const BsOp* src, uint32_t n, std::vector<BsGroup>&
     out.push_back(grp);
   };
   const size_t base = out.size();
-  uint32_t pick[4 * kBsGroup], best[kBsGroup], best_flip[4 * kBsGroup];
+  uint32_t pick[4 * kBsGroup], best[kBsGroup];
   while (nxt[n] != n) {
     const uint32_t hs = items[nxt[n]].shape;
     const bool flip = hs == kShapeX || hs == kShapeCX || hs == kShapeCCX;
     // A flip or OMEGA group may join the next one or three groups: eight or
     // sixteen mutually independent ops of one shape, read together by the
     // kernel.
-    uint32_t np = select(hs, pick, flip || hs == kShapeOmega ? 4 * kBsGroup : kBsGroup);
-    uint32_t gshape = hs;
-    if ((hs == kShapeCX || hs == kShapeCCX) && np < 2 * kBsGroup) {
-      // No pair of one shape: CNOTs and Toffolis together may make a
-      // CCX-shaped pair or quad (eight or sixteen reads in flight).
-      const uint32_t nm = select(kAnyFlip12, best_flip, 4 * kBsGroup);
-      if (nm >= 2 * kBsGroup) {
-        for (uint32_t u = 0; u < nm; ++u) pick[u] = best_flip[u];
-        np = nm;
-        gshape = kShapeCCX;
-      }
-    }
+    // A Toffoli head gathers CNOTs too (their second control slot names the
+    // all-ones plane), so that CCX-shaped groups pair and quad far more often.
+    const uint32_t gshape = hs;
+    uint32_t np = select(hs == kShapeCCX ? kAnyFlip12 : hs, pick, flip || hs == kShapeOmega ? 4 * kBsGroup : kBsGroup);
     if (np >= 2 * kBsGroup) {
       const uint32_t ng = np == 4 * kBsGroup ? 4 : 2;
       for (uint32_t k = 0; k < ng; ++k) {
