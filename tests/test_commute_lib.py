@@ -42,7 +42,7 @@ def test_random_circuits(seed):
 
 
 def test_configs():
-    # (Skip caps are judged where a gate is applied, so commuting suits
+    # (Skip caps are decided where a gate is applied, so commuting suits
     # circuits without them.  On the Trotter-like circuit the postponed
     # basis-change H's keep transient states large, so few terms here.)
     for w in (W.config3(terms=15), W.config1(3, w=6, adds=4, n=24)):
