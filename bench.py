@@ -314,8 +314,8 @@ def main():
     ap.add_argument("--fuse-max", type=int, default=0)
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py measures one GPU only (got --gpus {args.gpus}); this build has no multi-GPU path.",
-              file=sys.stderr)
+        print(f"bench.py measures one GPU only (got --gpus {args.gpus}): the library runs a state on one GPU "
+              f"and has no multi-GPU path.", file=sys.stderr)
         sys.exit(2)
 
     import torch
