@@ -470,7 +470,9 @@ int run_measure(sim_t* s, uint32_t q, double u, int32_t forced, MeasRec* rec, in
                 int32_t q_next = -1) {
   *bad = false;
   const uint64_t ub = s->nnz_known ? s->nnz_exact : s->nnz_ub;
-  const int G = chunk_grid(ub);
+  // 8192 entries per block: a quarter of the partial sums the decide kernel
+  // reads, each block still several tiles of work.
+  const int G = (int)std::max<uint64_t>(1, std::min<uint64_t>((ub + 8191) / 8192, kMaxBlocks));
   const int other = s->cur ^ 1;
   const uint64_t* nnz_in = d_nnz(s, s->cur);
   const bool chained = s->mchain.valid && s->mchain.q == q && s->mchain.grid == G;
