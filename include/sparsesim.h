@@ -170,6 +170,11 @@ typedef struct sim_config {
  * identical. */
 #define SIM_FLAG_U2_TWO_PASS 1u
 
+/* The bit-sliced fused pass keeps a tile's label bit-planes in VGPRs and
+ * addresses them by index (the default); this flag selects the form that
+ * keeps them in LDS instead.  The results are identical. */
+#define SIM_FLAG_BS_LDS 2u
+
 /* Fused phase/permutation pass variants.  DIRECT evaluates every gate on every
  * entry with sequential complex products (results bit-identical to a plain
  * sequential evaluation).  BITSLICE transposes 2048-entry tiles into bit-planes

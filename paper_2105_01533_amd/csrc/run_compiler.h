@@ -58,6 +58,15 @@ struct RunCompiler {
   void defer_x(const BsOp* in, uint32_t n, std::vector<BsOp>& out, uint32_t* d_omega, uint64_t* d_turn) const;
   // Groups of n bit-sliced ops, appended to out.
   void group_range(const BsOp* src, uint32_t n, std::vector<BsGroup>& out) const;
+  // Register-plane program of MONO ops [begin, begin+len) (segments of one
+  // shape), appended to out; br as for group().
+  void schedule(size_t begin, size_t len, std::vector<RpRec>& out, BsRun* br) const;
+  // Segments of n bit-sliced ops, appended to out.
+  void schedule_range(const BsOp* src, uint32_t n, std::vector<RpRec>& out) const;
+  // Records the program of n_ops bit-sliced ops on nq qubits may take at most
+  // (the rewrite of uncontrolled X gates at most doubles the ops and adds nq;
+  // a segment adds a header and up to three padding ops).
+  static size_t rp_records_bound(size_t n_ops, uint32_t nq) { return 8 * (2 * n_ops + nq) + 16; }
 };
 
 }  // namespace sparsesim

@@ -4,6 +4,7 @@
 #include "host_pool.h"
 
 #include <algorithm>
+#include <array>
 #include <cmath>
 #include <cstring>
 
@@ -488,6 +489,170 @@ void RunCompiler::group_range(const BsOp* src, uint32_t n, std::vector<BsGroup>&
     emit(pick, np, shape);
   }
   (void)base;
+}
+
+// Register-plane programs.  The kernel runs a segment's ops in order, so ops
+// of one segment need not be independent; what a segment needs is length
+// (one dispatch per segment).  Ops are list-scheduled: the first pending op
+// opens a segment of its shape, and later pending ops of the same shape join
+// it when they commute with every pending op they pass (neither writes a
+// plane the other reads or writes; phase accumulations commute exactly).
+// Eighth-turn ops conditioned on their target alone all commute, so a
+// segment of them is split by k into sub-segments (one add sequence each).
+void RunCompiler::schedule(size_t begin, size_t len, std::vector<RpRec>& out, BsRun* br) const {
+  const uint32_t i0 = start[begin], i1 = start[begin + len];
+  std::vector<BsOp> xo;
+  uint32_t d_omega = 0;
+  uint64_t d_turn = 0;
+  defer_x(ops.data() + i0, i1 - i0, xo, &d_omega, &d_turn);
+  if (br) {
+    br->g_omega = (br->g_omega + d_omega) & 7u;
+    br->g_turn += d_turn;
+  }
+  const uint32_t n = (uint32_t)xo.size();
+  if (n < 2 * 2048) {
+    schedule_range(xo.data(), n, out);
+  } else {
+    std::vector<std::vector<RpRec>> parts(kHostThreads);
+    parallel_parts(n, 2048, [&](size_t b, size_t e, size_t p) {
+      std::vector<RpRec> mine;
+      schedule_range(xo.data() + b, (uint32_t)(e - b), mine);
+      parts[p].swap(mine);
+    });
+    for (auto& v : parts) out.insert(out.end(), v.begin(), v.end());
+  }
+}
+
+void RunCompiler::schedule_range(const BsOp* src, uint32_t n, std::vector<RpRec>& out) const {
+  const uint32_t ones = n_qubits, scratch = n_qubits + 1, zero = n_qubits + 2;
+  struct Mask {
+    uint64_t lo = 0, hi = 0;
+    void set(uint32_t q) { (q < 64 ? lo : hi) |= 1ull << (q & 63); }
+    bool meets(const Mask& o) const { return ((lo & o.lo) | (hi & o.hi)) != 0; }
+    void add(const Mask& o) {
+      lo |= o.lo;
+      hi |= o.hi;
+    }
+  };
+  struct Item {
+    Mask r, w;
+    uint32_t shape;   // kRpF1..F3, kRpOB (any k), kRpOG, kRpTB, kRpTG
+  };
+  if (n == 0) return;
+  std::vector<Item> items(n);
+  std::vector<uint32_t> nxt(n + 1), prv(n + 1);
+  for (uint32_t i = 0; i < n; ++i) {
+    const BsOp& o = src[i];
+    Item& it = items[i];
+    for (int c = 0; c < o.nctrl; ++c) it.r.set(o.ctrl[c]);
+    if (o.cmode || o.op == kBsFlip) it.r.set(o.target);
+    if (o.op == kBsFlip) it.w.set(o.target);
+    const bool bare = o.nctrl == 0 && o.cmode;
+    it.shape = o.op == kBsFlip    ? (o.nctrl <= 1 ? kRpF1 : o.nctrl == 2 ? kRpF2 : kRpF3)
+               : o.op == kBsOmega ? (bare ? kRpOB : kRpOG)
+                                  : (bare ? kRpTB : kRpTG);
+    nxt[i] = i + 1;
+    prv[i + 1] = i;
+  }
+  prv[0] = n;
+  nxt[n] = 0;
+  auto unlink = [&](uint32_t j) {
+    nxt[prv[j]] = nxt[j];
+    prv[nxt[j]] = prv[j];
+  };
+  // A condition word: the target (or all-ones) plane and three control slots.
+  auto cond_word = [&](const BsOp& o) {
+    uint32_t c[3] = {ones, ones, ones};
+    for (int q = 0; q < o.nctrl; ++q) c[q] = o.ctrl[q];
+    const uint32_t t = o.cmode ? (uint32_t)o.target : ones;
+    return t | c[0] << 8 | c[1] << 16 | c[2] << 24;
+  };
+  auto header = [&](uint32_t shape, uint32_t count) { out.push_back(RpRec{{shape | count << 8, 0, 0, 0}}); };
+  // Quads of one-word ops, padded with `pad` words.
+  auto word_quads = [&](uint32_t shape, const std::vector<uint32_t>& words, uint32_t pad) {
+    const uint32_t nq4 = ((uint32_t)words.size() + 3) / 4;
+    header(shape, nq4);
+    for (uint32_t q = 0; q < nq4; ++q) {
+      RpRec r;
+      for (uint32_t u = 0; u < 4; ++u) r.w[u] = 4 * q + u < words.size() ? words[4 * q + u] : pad;
+      out.push_back(r);
+    }
+  };
+  constexpr uint32_t kWindow = 256;
+  std::vector<uint32_t> sel, words;
+  sel.reserve(kWindow);
+  words.reserve(kWindow);
+  while (nxt[n] != n) {
+    const uint32_t shape = items[nxt[n]].shape;
+    sel.clear();
+    Mask br, bw;   // reads / writes of the pending ops passed over
+    uint32_t seen = 0;
+    for (uint32_t j = nxt[n]; j != n && seen < kWindow; j = nxt[j], ++seen) {
+      const Item& it = items[j];
+      if (it.shape == shape && !it.w.meets(br) && !it.w.meets(bw) && !it.r.meets(bw)) {
+        sel.push_back(j);
+      } else {
+        br.add(it.r);
+        bw.add(it.w);
+      }
+    }
+    for (uint32_t j : sel) unlink(j);
+    const uint32_t ns = (uint32_t)sel.size();
+    if (shape == kRpTB || shape == kRpTG) {
+      const uint32_t ng = (ns + 3) / 4;
+      header(shape, ng);
+      for (uint32_t g = 0; g < ng; ++g) {
+        RpRec cw;
+        uint64_t tau[4] = {0, 0, 0, 0};
+        for (uint32_t u = 0; u < 4; ++u) {
+          const uint32_t k = 4 * g + u;
+          if (k < ns) {
+            cw.w[u] = cond_word(src[sel[k]]);
+            tau[u] = src[sel[k]].arg;
+          } else {
+            cw.w[u] = zero | zero << 8 | zero << 16 | zero << 24;   // adds 0 turns
+          }
+        }
+        out.push_back(cw);
+        out.push_back(RpRec{{(uint32_t)tau[0], (uint32_t)(tau[0] >> 32), (uint32_t)tau[1], (uint32_t)(tau[1] >> 32)}});
+        out.push_back(RpRec{{(uint32_t)tau[2], (uint32_t)(tau[2] >> 32), (uint32_t)tau[3], (uint32_t)(tau[3] >> 32)}});
+      }
+      continue;
+    }
+    if (shape == kRpOG) {
+      const uint32_t nq2 = (ns + 1) / 2;
+      header(shape, nq2);
+      for (uint32_t q = 0; q < nq2; ++q) {
+        RpRec r;
+        for (uint32_t h = 0; h < 2; ++h) {
+          const uint32_t k = 2 * q + h;
+          r.w[2 * h] = k < ns ? cond_word(src[sel[k]]) : (zero | zero << 8 | zero << 16 | zero << 24);
+          r.w[2 * h + 1] = k < ns ? (uint32_t)src[sel[k]].arg & 7u : 0u;
+        }
+        out.push_back(r);
+      }
+      continue;
+    }
+    if (shape == kRpOB) {
+      // All commute: one sub-segment per k (padding ops read the zero plane).
+      for (uint32_t k = 1; k < 8; ++k) {
+        words.clear();
+        for (uint32_t j : sel)
+          if (((uint32_t)src[j].arg & 7u) == k) words.push_back(src[j].target);
+        if (!words.empty()) word_quads(kRpOB + k, words, zero);
+      }
+      continue;
+    }
+    words.clear();
+    for (uint32_t j : sel) {
+      const BsOp& o = src[j];
+      uint32_t c[3] = {ones, ones, ones};
+      for (int q = 0; q < o.nctrl; ++q) c[q] = o.ctrl[q];
+      words.push_back((uint32_t)o.target | c[0] << 8 | c[1] << 16 | c[2] << 24);
+    }
+    // Padding: scratch ^= AND of zero planes (no change).
+    word_quads(shape, words, scratch | zero << 8 | zero << 16 | zero << 24);
+  }
 }
 
 }  // namespace sparsesim

@@ -80,7 +80,7 @@ bool config_ok(const sim_config* c, std::string* why) {
     return *why = "load_factor must be in (0, 0.9]", false;
   if (c->block != 0 && c->block != 64 && c->block != 128 && c->block != 256)
     return *why = "block must be 64, 128 or 256", false;
-  if (c->flags & ~SIM_FLAG_U2_TWO_PASS) return *why = "unknown flags", false;
+  if (c->flags & ~(SIM_FLAG_U2_TWO_PASS | SIM_FLAG_BS_LDS)) return *why = "unknown flags", false;
   if (c->mono_mode > SIM_MONO_BITSLICE) return *why = "unknown mono_mode", false;
   return true;
 }
@@ -262,8 +262,10 @@ struct sim_t {
   uint64_t* h_pinned;          // [0] nnz readback, [1..] scratch
   Ctl* h_ctl;                  // pinned mirror of ctl
   DevVec<MonoDesc> descs;
-  DevVec<BsGroup> grp_ops;     // grouped bit-sliced ops of the current call
+  DevVec<BsGroup> grp_ops;     // grouped bit-sliced ops of the current call (LDS-plane kernel)
   std::vector<BsGroup> h_grp;
+  DevVec<RpRec> rp_prog;       // register-plane programs of the current call
+  std::vector<RpRec> h_rp;     // the program of the run being prepared
   std::vector<sim_gate> conv;  // sim_apply_ops: converted ops, kept between calls
   RunCompiler rc;              // MONO descriptors and bytecode of the current call
   DevVec<MeasRec> recs;
@@ -598,6 +600,7 @@ int sim_destroy(sim_t* s) {
   if (s->stream || s->ws) (void)hipStreamSynchronize(s->stream);
   s->descs.release();
   s->grp_ops.release();
+  s->rp_prog.release();
   s->recs.release();
   s->outcomes.release();
   for (hipEvent_t e : s->ev_pool) (void)hipEventDestroy(e);
@@ -787,6 +790,12 @@ int sim_apply_gates(sim_t* s, const sim_gate* gates, size_t n, int32_t* outcomes
   // from pinned staging (asynchronous).
   Staging<MonoDesc> h_desc(s->stream);
   Staging<BsGroup> h_grp_pin(s->stream);
+  // Register-plane programs go through pinned staging into rp_prog at
+  // rp_used; when a run's program does not fit, the stream is drained (every
+  // earlier program has been read) and filling starts over at 0.
+  Staging<RpRec> h_rp_pin(s->stream);
+  size_t rp_used = 0;
+  const bool use_rp = !(s->cfg.flags & SIM_FLAG_BS_LDS);
   size_t desc_lo = 0, desc_hi = 0;   // descriptors [desc_lo, desc_hi) are on the device
   // Grouped kernel ops of the bit-sliced runs, appended run by run.  A run
   // of k > 0 ops has at most k + 1 groups (every group but an evening pad
@@ -801,9 +810,14 @@ int sim_apply_gates(sim_t* s, const sim_gate* gates, size_t n, int32_t* outcomes
       if (compiler.t.joinable()) compiler.t.join();
     }
     compiled = true;
-    s->h_grp.reserve(2 * s->rc.ops.size() + 2);
-    HIP_TRY(s->grp_ops.reserve(2 * s->rc.ops.size() + 2));
-    HIP_TRY(h_grp_pin.reserve(2 * s->rc.ops.size() + 2));
+    if (use_rp) {
+      HIP_TRY(s->rp_prog.reserve(4 * s->rc.ops.size() + 64));
+      HIP_TRY(h_rp_pin.reserve(4 * s->rc.ops.size() + 64));
+    } else {
+      s->h_grp.reserve(2 * s->rc.ops.size() + 2);
+      HIP_TRY(s->grp_ops.reserve(2 * s->rc.ops.size() + 2));
+      HIP_TRY(h_grp_pin.reserve(2 * s->rc.ops.size() + 2));
+    }
     return SIM_OK;
   };
 
@@ -818,6 +832,7 @@ int sim_apply_gates(sim_t* s, const sim_gate* gates, size_t n, int32_t* outcomes
     bool ready = false;          // t has run (or runs) for [begin, begin + len)
     size_t begin = 0, len = 0;
     std::vector<BsGroup> grp;
+    std::vector<RpRec> rp;       // register-plane program (use_rp)
     BsRun delta{};               // run constants the grouping moved (see RunCompiler::group)
     void join() {
       if (t.joinable()) t.join();
@@ -844,7 +859,39 @@ int sim_apply_gates(sim_t* s, const sim_gate* gates, size_t n, int32_t* outcomes
       int rc = ensure_compiled();
       if (rc) return rc;
     }
-    if (bs_allowed && s->rc.run_params(run_begin, run_len, s->cfg.mono_mode, s->cfg.bs_min_gates, &br)) {
+    if (bs_allowed && use_rp && s->rc.run_params(run_begin, run_len, s->cfg.mono_mode, s->cfg.bs_min_gates, &br)) {
+      br.bytes_per_entry = run_bpe;
+      {
+        HTimer tg_(s, KC_H_GROUP);
+        if (spec.ready && spec.begin == run_begin && spec.len == run_len) {
+          spec.join();
+          s->h_rp.swap(spec.rp);
+          br.g_omega = (br.g_omega + spec.delta.g_omega) & 7u;
+          br.g_turn += spec.delta.g_turn;
+          spec.ready = false;
+        } else {
+          s->h_rp.clear();
+          s->rc.schedule(run_begin, run_len, s->h_rp, &br);
+        }
+      }
+      const size_t nr = s->h_rp.size();
+      if (rp_used + nr > s->rp_prog.n || (rp_used + nr) * sizeof(RpRec) > h_rp_pin.bytes) {
+        HIP_TRY(timed_sync(s));
+        rp_used = 0;
+        HIP_TRY(s->rp_prog.reserve(2 * nr));
+        HIP_TRY(h_rp_pin.reserve(2 * nr));
+      }
+      std::memcpy(h_rp_pin.p + rp_used, s->h_rp.data(), nr * sizeof(RpRec));
+      HIP_TRY(hipMemcpyAsync(s->rp_prog.p + rp_used, h_rp_pin.p + rp_used, nr * sizeof(RpRec), hipMemcpyHostToDevice,
+                             s->stream));
+      {
+        KTimer t_(s, KC_MONO);
+        launch_mono_rp(s->stream, s->buf[s->cur], d_nnz(s, s->cur), s->rp_prog.p + rp_used, (uint32_t)nr, br, s->ctl,
+                       bs_grid(s, ub));
+      }
+      rp_used += nr;
+      st.bitslice_passes++;
+    } else if (bs_allowed && s->rc.run_params(run_begin, run_len, s->cfg.mono_mode, s->cfg.bs_min_gates, &br)) {
       br.bytes_per_entry = run_bpe;
       const size_t g0 = s->h_grp.size();
       {
@@ -911,10 +958,12 @@ int sim_apply_gates(sim_t* s, const sim_gate* gates, size_t n, int32_t* outcomes
     spec.ready = true;
     spec.begin = begin;
     spec.len = len;
-    spec.t = std::thread([s, &spec]() {
+    spec.t = std::thread([s, &spec, use_rp]() {
       spec.grp.clear();
+      spec.rp.clear();
       spec.delta = BsRun{};
-      s->rc.group(spec.begin, spec.len, spec.grp, &spec.delta);
+      if (use_rp) s->rc.schedule(spec.begin, spec.len, spec.rp, &spec.delta);
+      else s->rc.group(spec.begin, spec.len, spec.grp, &spec.delta);
     });
     return SIM_OK;
   };

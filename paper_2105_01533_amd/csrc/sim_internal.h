@@ -102,6 +102,31 @@ __host__ __device__ constexpr uint32_t bs_pack_a(uint32_t op, uint32_t k, uint32
 __host__ __device__ constexpr uint32_t bs_pack_b(uint32_t p2) { return p2 << 8; }
 __host__ __device__ constexpr uint32_t bs_shape(uint32_t a0) { return (a0 >> 5) & 7u; }
 
+// Register-plane program (the fused pass with planes held in VGPRs): a list
+// of 16-byte quads.  A segment header quad (shape | count << 8, 0, 0, 0) is
+// followed by count quads of ops, all of one shape:
+//   F1, F2, F3  flips with 1, 2, 3 control planes, four per quad, one word
+//               each: t | c0 << 8 | c1 << 16 | c2 << 24; plane t ^= AND of the
+//               controls (an uncontrolled X names the all-ones plane);
+//   OB + k      (k = 1..7) eighth-turn ops adding k where plane t holds, four
+//               per quad, one word each: t;
+//   OG          general eighth-turn ops, two per quad: (cond, k, cond, k),
+//               cond = t | c0 << 8 | c1 << 16 | c2 << 24, condition = AND of
+//               those four planes;
+//   TB, TG      turn ops in groups of four, three quads per group: the four
+//               cond words, then the four 64-bit turn fractions (lo, hi
+//               words); TB: condition = plane t alone (cond = t), TG: AND of
+//               the four planes of cond.  count = groups.
+// A zero header (END) ends the program; the kernel reads the program through
+// a buffer resource that returns zeros past its end.  Planes nq, nq + 1,
+// nq + 2 are all-ones, scratch and zero; padding ops name them so that they
+// change nothing.
+constexpr uint32_t kRpEnd = 0, kRpF1 = 1, kRpF2 = 2, kRpF3 = 3, kRpOG = 5, kRpTB = 6, kRpTG = 7, kRpOB = 8;
+struct RpRec {
+  uint32_t w[4];
+};
+static_assert(sizeof(RpRec) == 16, "RpRec is 16 bytes");
+
 // Run-level parameters of a bit-sliced pass.
 struct BsRun {
   uint32_t n_planes;           // LDS planes per wave (= qubit count)
@@ -219,6 +244,10 @@ void launch_set_basis(hipStream_t st, Buf b, uint64_t* nnz, uint64_t lo, uint64_
 void launch_mono(hipStream_t st, bool wide, Buf b, const uint64_t* nnz, const MonoDesc* g, uint32_t ng,
                  uint32_t run_flags, uint32_t bytes_per_entry, Ctl* ctl, int grid, int block);
 void launch_mono_bs(hipStream_t st, Buf b, const uint64_t* nnz, const BsGroup* groups, uint32_t ngroups, const BsRun& run,
+                    Ctl* ctl, int grid);
+// Register-plane fused pass: one 2048-entry tile per block; grid covers the
+// entry count's upper bound.
+void launch_mono_rp(hipStream_t st, Buf b, const uint64_t* nnz, const RpRec* prog, uint32_t nrec, const BsRun& run,
                     Ctl* ctl, int grid);
 void launch_fill(hipStream_t st, uint64_t* p, uint64_t v, uint64_t n);
 void launch_copy16(hipStream_t st, void* dst, const void* src, uint64_t n16);
