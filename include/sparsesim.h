@@ -197,6 +197,9 @@ typedef struct sim_stats {
   uint64_t peak_nnz;       /* largest entry count reached */
   uint64_t pruned;         /* entries dropped by the eps rule */
   uint64_t bitslice_passes; /* fused passes that ran the bit-sliced kernel */
+  double pruned_mass;      /* sum of |a|^2 of the dropped entries (summed in no fixed
+                              order: equal to the oracle's to rounding); the batched
+                              server counts neither pruned nor pruned_mass (0) */
 } sim_stats;
 
 typedef struct sim_t sim_t;

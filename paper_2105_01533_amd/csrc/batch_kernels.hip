@@ -12,34 +12,14 @@
 // different states never touch each other's memory, so the families need no
 // ordering among themselves.
 #include "bitslice_tile.h"
+#include "entry_ops.h"
 
 namespace sparsesim {
 namespace {
 
-__device__ __forceinline__ double2 cmul2(double2 a, double2 b) {
-  return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
-}
-
-__device__ __forceinline__ double2 cadd2(double2 a, double2 b) { return make_double2(a.x + b.x, a.y + b.y); }
-// c ? x : y component by component (a conditional on the vector type itself
-// is lowered through a stack temporary).
-__device__ __forceinline__ double2 sel2b(bool c, double2 x, double2 y) {
-  return make_double2(c ? x.x : y.x, c ? x.y : y.y);
-}
-
-__device__ __forceinline__ bool survives2(double2 a, double eps) {
-  return !((a.x * a.x + a.y * a.y < eps) || (a.x == 0.0 && a.y == 0.0));
-}
-
-__device__ __forceinline__ uint64_t hash_label2(uint64_t lo, uint64_t hi) {
-  uint64_t k = lo + hi * 0x9E3779B97F4A7C15ull;
-  k ^= k >> 33;
-  k *= 0xff51afd7ed558ccdull;
-  k ^= k >> 33;
-  k *= 0xc4ceb9fe1a85ec53ull;
-  k ^= k >> 33;
-  return k;
-}
+using ent::cadd;
+using ent::hash_label;
+using ent::survives;
 
 // Largest i in [0, n) with u0[i] <= u (u0 ascending, u0[0] = 0).
 __device__ __forceinline__ int find_item(const uint32_t* __restrict__ u0, int n, uint32_t u) {
@@ -52,12 +32,10 @@ __device__ __forceinline__ int find_item(const uint32_t* __restrict__ u0, int n,
   return lo;
 }
 
-__device__ __forceinline__ bool ctrl_ok(const U2Desc& d, uint64_t lo, uint64_t hi, bool wide) {
-  return (lo & d.ctrl_lo) == d.ctrl_lo && (!wide || (hi & d.ctrl_hi) == d.ctrl_hi);
-}
+using ent::ctrl_ok;
 
 __device__ __forceinline__ uint32_t find_label2(const BItem& it, uint64_t lo, uint64_t hi) {
-  const uint64_t h = hash_label2(lo, hi);
+  const uint64_t h = hash_label(lo, hi);
   const uint32_t fp = (uint32_t)(h >> 32);
   uint64_t slot = h & it.mask;
   for (uint64_t p = 0; p <= it.mask; ++p) {
@@ -72,38 +50,16 @@ __device__ __forceinline__ uint32_t find_label2(const BItem& it, uint64_t lo, ui
   return kNoPartner;
 }
 
-__device__ __forceinline__ bool pivot_set2(const U2Desc& d, uint64_t lo, uint64_t hi, bool wide) {
-  const uint64_t w = (wide && d.target >= 64) ? hi : lo;
-  return ((w >> (d.target & 63)) & 1ull) != 0;
-}
+using ent::pivot_set;
 
 // Eq. 2 for one entry, given its partner (label ^ x): mode 0 passes through, 1
 // emits the pair (o0 for the pivot-0 label b0, o1 for b0 ^ x), 2 emits nothing.
 __device__ __forceinline__ int u2_entry(const BItem& it, uint64_t lo, uint64_t hi, double2 a, uint32_t j,
                                         double2* o0, double2* o1) {
-  const U2Desc& d = it.u2;
-  // Both outputs are written on every path (keeps them in registers).
-  *o0 = a;
-  *o1 = a;
-  if (!ctrl_ok(d, lo, hi, it.wide)) return 0;
-  const bool v = pivot_set2(d, lo, hi, it.wide);
-  if (!v && j != kNoPartner) return 2;
-  const double2 zero = make_double2(0.0, 0.0);
-  double2 aj = zero;
-  if (v && j != kNoPartner) aj = it.in.amp[j];
-  const double2 a0 = sel2b(v, aj, a);
-  const double2 a1 = sel2b(v, a, zero);
-  // off-diagonal sign from b0, the pair's label with the pivot bit clear
-  const uint64_t b0lo = v ? lo ^ d.x_lo : lo, b0hi = v ? hi ^ d.x_hi : hi;
-  const bool odd = ((__popcll(b0lo & d.z_lo) + (it.wide ? __popcll(b0hi & d.z_hi) : 0)) & 1) != 0;
-  double2 p01 = cmul2(d.u[1], a1), p10 = cmul2(d.u[2], a0);
-  if (odd) {
-    p01 = make_double2(-p01.x, -p01.y);
-    p10 = make_double2(-p10.x, -p10.y);
-  }
-  *o0 = cadd2(cmul2(d.u[0], a0), p01);
-  *o1 = cadd2(p10, cmul2(d.u[3], a1));
-  return 1;
+  const ent::U2Out r = ent::u2_eval(it.u2, it.wide, it.in.amp, lo, hi, a, j);
+  *o0 = r.o0;
+  *o1 = r.o1;
+  return r.mode;
 }
 
 template <typename T>
@@ -119,7 +75,7 @@ __device__ __forceinline__ T bsum(T v, T* sh) {
   return r;
 }
 
-__device__ __forceinline__ double2 operator+(double2 a, double2 b) { return cadd2(a, b); }
+__device__ __forceinline__ double2 operator+(double2 a, double2 b) { return cadd(a, b); }
 
 __device__ __forceinline__ uint32_t prefix012(uint32_t e, uint32_t* s_wave, uint32_t* total) {
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
@@ -173,8 +129,8 @@ __global__ __launch_bounds__(64, 2) void kb_mono(const BTick* __restrict__ hdr, 
           const uint64_t tbit = 1ull << (d.target & 63);
           const uint64_t w = thi ? hi : lo;
           if (d.flags & kHasPhase) {
-            const double2 r = cmul2(a, sel2b((w & tbit) != 0, d.m1, d.m0));
-            a = sel2b(c, r, a);
+            const double2 r = ent::cmul(a, ent::sel2((w & tbit) != 0, d.m1, d.m0));
+            a = ent::sel2(c, r, a);
           }
           if (d.flags & kFlip) {
             const uint64_t f = c ? tbit : 0ull;
@@ -228,8 +184,8 @@ __global__ __launch_bounds__(256) void kb_build(const BTick* __restrict__ hdr, c
       // slot starts empty.
       it.partner[e] = kNoPartner;
       const uint64_t lo = it.in.key_lo[e], hi = it.wide ? it.in.key_hi[e] : 0ull;
-      if (!ctrl_ok(it.u2, lo, hi, it.wide) || pivot_set2(it.u2, lo, hi, it.wide)) continue;
-      const uint64_t h = hash_label2(lo, hi);
+      if (!ctrl_ok(it.u2, lo, hi, it.wide) || pivot_set(it.u2, lo, hi, it.wide)) continue;
+      const uint64_t h = hash_label(lo, hi);
       const unsigned long long val = ((h >> 32) << 32) | e;
       uint64_t slot = h & it.mask;
       for (uint64_t p = 0; p <= it.mask; ++p) {
@@ -256,7 +212,7 @@ __global__ __launch_bounds__(256) void kb_u2_probe(const BTick* __restrict__ hdr
     const uint64_t e1 = e0 + kChunk < it.nnz ? e0 + kChunk : it.nnz;
     for (uint64_t e = e0 + threadIdx.x; e < e1; e += blockDim.x) {
       const uint64_t lo = it.in.key_lo[e], hi = it.wide ? it.in.key_hi[e] : 0ull;
-      if (!ctrl_ok(it.u2, lo, hi, it.wide) || !pivot_set2(it.u2, lo, hi, it.wide)) continue;
+      if (!ctrl_ok(it.u2, lo, hi, it.wide) || !pivot_set(it.u2, lo, hi, it.wide)) continue;
       const uint32_t j = find_label2(it, lo ^ it.u2.x_lo, it.wide ? (hi ^ it.u2.x_hi) : 0ull);
       if (j == kNoPartner) continue;
       it.partner[e] = j;
@@ -284,8 +240,8 @@ __global__ __launch_bounds__(256) void kb_u2_count(const BTick* __restrict__ hdr
       const uint64_t lo = it.in.key_lo[e], hi = it.wide ? it.in.key_hi[e] : 0ull;
       double2 o0, o1;
       const int mode = u2_entry(it, lo, hi, it.in.amp[e], it.partner[e], &o0, &o1);
-      if (mode == 0) emit += survives2(o0, it.u2.eps) ? 1u : 0u;
-      else if (mode == 1) emit += (survives2(o0, it.u2.eps) ? 1u : 0u) + (survives2(o1, it.u2.eps) ? 1u : 0u);
+      if (mode == 0) emit += survives(o0, it.u2.eps) ? 1u : 0u;
+      else if (mode == 1) emit += (survives(o0, it.u2.eps) ? 1u : 0u) + (survives(o1, it.u2.eps) ? 1u : 0u);
     }
     emit = bsum(emit, sh);
     if (threadIdx.x == 0) it.tot[c] = emit;
@@ -361,10 +317,10 @@ __global__ __launch_bounds__(256) void kb_u2_write(const BTick* __restrict__ hdr
         lo = it.in.key_lo[e];
         hi = it.wide ? it.in.key_hi[e] : 0ull;
         mode = u2_entry(it, lo, hi, it.in.amp[e], it.partner[e], &o0, &o1);
-        if (mode == 0) k0 = survives2(o0, it.u2.eps);
+        if (mode == 0) k0 = survives(o0, it.u2.eps);
         if (mode == 1) {
-          k0 = survives2(o0, it.u2.eps);
-          k1 = survives2(o1, it.u2.eps);
+          k0 = survives(o0, it.u2.eps);
+          k1 = survives(o1, it.u2.eps);
         }
         cnt = (k0 ? 1u : 0u) + (k1 ? 1u : 0u);
       }
@@ -375,7 +331,7 @@ __global__ __launch_bounds__(256) void kb_u2_write(const BTick* __restrict__ hdr
         if (it.wide) it.out.key_hi[pos] = hi;
         it.out.amp[pos] = o0;
       } else if (mode == 1) {
-        const bool v = pivot_set2(it.u2, lo, hi, it.wide);
+        const bool v = pivot_set(it.u2, lo, hi, it.wide);
         const uint64_t lo0 = v ? lo ^ it.u2.x_lo : lo, hi0 = v ? hi ^ it.u2.x_hi : hi;
         if (k0) {
           it.out.key_lo[pos] = lo0;
@@ -445,7 +401,7 @@ __global__ __launch_bounds__(256) void kb_m_decide(const BTick* __restrict__ hdr
     const BItem& it = m[i];
     const uint32_t nc = u0[i + 1] - u0[i];
     double2 acc = make_double2(0.0, 0.0);
-    for (uint32_t k = threadIdx.x; k < nc; k += blockDim.x) acc = cadd2(acc, it.part[k]);
+    for (uint32_t k = threadIdx.x; k < nc; k += blockDim.x) acc = cadd(acc, it.part[k]);
     const double2 P = bsum(acc, shd);
     if (threadIdx.x == 0) {
       const double tot = P.x + P.y;

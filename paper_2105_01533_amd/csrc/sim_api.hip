@@ -274,6 +274,7 @@ struct sim_t {
   bool nnz_known;
   uint64_t nnz_exact, nnz_ub;
   uint64_t last_updates, last_pruned;
+  double last_mass;
 };
 
 namespace {
@@ -441,7 +442,7 @@ int run_u2(sim_t* s, const sim_gate& g, bool* over) {
   }
   {
     KTimer t_(s, KC_SCAN);
-    launch_scan(s->stream, s->bs.tot, G, d_nnz(s, other), s->ctl, s->wide ? 32u : 24u);
+    launch_scan(s->stream, s->bs.tot, G, d_nnz(s, other), s->ctl, s->wide ? 32u : 24u, cap);
   }
   HIP_TRY(hipGetLastError());
   if (check) {
@@ -591,6 +592,7 @@ int sim_create(const sim_config* cfg, void* stream, void* workspace, size_t ws_b
   s->nnz_known = true;
   s->nnz_exact = s->nnz_ub = 1;
   s->last_updates = s->last_pruned = 0;
+  s->last_mass = 0.0;
   *out = s;
   return SIM_OK;
 }
@@ -1048,9 +1050,11 @@ int sim_apply_gates(sim_t* s, const sim_gate* gates, size_t n, int32_t* outcomes
   st.gates_applied = i;
   st.updates = s->h_ctl->updates - s->last_updates;
   st.pruned = s->h_ctl->pruned - s->last_pruned;
+  st.pruned_mass = s->h_ctl->pruned_mass - s->last_mass;
   st.peak_nnz = s->h_ctl->peak;
   s->last_updates = s->h_ctl->updates;
   s->last_pruned = s->h_ctl->pruned;
+  s->last_mass = s->h_ctl->pruned_mass;
   s->nnz_known = true;
   s->nnz_exact = s->nnz_ub = s->h_ctl->nnz[s->cur];
   if (s->nnz_exact > st.peak_nnz) st.peak_nnz = s->nnz_exact;

@@ -167,6 +167,12 @@ struct Ctl {
   uint64_t pass_bytes[4];
   uint32_t error;              // bit 0: a measurement had no valid outcome; bit 1: a chained scan gave up waiting
   uint32_t ticket;             // tile counter of the single-pass branching kernel (wraps)
+  double pruned_mass;          // sum of |a|^2 of the entries T_eps dropped
+  // Counters of a two-pass branching gate, staged by its count pass and
+  // committed by the scan only if the output fits the capacity (a gate
+  // rejected for capacity changes no counter).
+  uint64_t st_updates, st_pruned;
+  double st_mass;
 };
 
 // Per-measurement record written by the decide kernel.
@@ -257,7 +263,9 @@ void launch_u2_probe(hipStream_t st, bool wide, Buf b, const uint64_t* nnz, cons
                      const U2Desc& d, uint32_t* partner, int grid, int block);
 void launch_u2_count(hipStream_t st, bool wide, Buf b, const uint64_t* nnz, const U2Desc& d, const uint32_t* partner,
                      uint32_t* tot, Ctl* ctl, int grid, int block);
-void launch_scan(hipStream_t st, uint32_t* tot, int nblocks, uint64_t* nnz_out, Ctl* ctl, uint32_t entry_bytes);
+// cap: the count pass's staged counters are committed only if the total fits.
+void launch_scan(hipStream_t st, uint32_t* tot, int nblocks, uint64_t* nnz_out, Ctl* ctl, uint32_t entry_bytes,
+                 uint64_t cap);
 void launch_u2_write(hipStream_t st, bool wide, Buf in, Buf out, const uint64_t* nnz, const uint32_t* partner,
                      const uint32_t* off, const U2Desc& d, Ctl* ctl, int grid, int block);
 // Entries per block of the single-pass branching kernel; it serves states of

@@ -14,37 +14,16 @@
 // complex products are (a.re*b.re - a.im*b.im, a.re*b.im + a.im*b.re), sums of
 // two products are evaluated left to right, |a|^2 = re*re + im*im, and the
 // library is compiled with -ffp-contract=off.
-#include "sim_internal.h"
+#include "entry_ops.h"
 
 namespace sparsesim {
 namespace {
 
-__device__ __forceinline__ double2 cmul(double2 a, double2 b) {
-  return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
-}
-
-__device__ __forceinline__ double2 cadd(double2 a, double2 b) { return make_double2(a.x + b.x, a.y + b.y); }
-// c ? x : y component by component (a conditional on the vector type itself
-// is lowered through a stack temporary).
-__device__ __forceinline__ double2 sel2(bool c, double2 x, double2 y) {
-  return make_double2(c ? x.x : y.x, c ? x.y : y.y);
-}
-
-// T_eps: an entry survives iff |a|^2 >= eps and it is not exactly zero.
-__device__ __forceinline__ bool survives(double2 a, double eps) {
-  return !((a.x * a.x + a.y * a.y < eps) || (a.x == 0.0 && a.y == 0.0));
-}
-
-// 64-bit finalizer of MurmurHash3 (Appleby), applied to a 128-bit label.
-__device__ __forceinline__ uint64_t hash_label(uint64_t lo, uint64_t hi) {
-  uint64_t k = lo + hi * 0x9E3779B97F4A7C15ull;
-  k ^= k >> 33;
-  k *= 0xff51afd7ed558ccdull;
-  k ^= k >> 33;
-  k *= 0xc4ceb9fe1a85ec53ull;
-  k ^= k >> 33;
-  return k;
-}
+using ent::cadd;
+using ent::cmul;
+using ent::hash_label;
+using ent::sel2;
+using ent::survives;
 
 __device__ __forceinline__ void chunk_range(uint64_t n, uint64_t& begin, uint64_t& end) {
   const uint64_t chunk = (n + gridDim.x - 1) / gridDim.x;
@@ -256,54 +235,14 @@ __global__ __launch_bounds__(256) void k_u2_probe(Buf b, const uint64_t* __restr
 
 template <bool WIDE>
 __device__ __forceinline__ bool pivot_set(const U2Desc& d, uint64_t lo, uint64_t hi) {
-  const uint64_t w = (WIDE && d.target >= 64) ? hi : lo;
-  return ((w >> (d.target & 63)) & 1ull) != 0;
+  return ent::pivot_set(d, lo, hi, WIDE);
 }
 
-// Branching gate outputs of entry i, given its partner index j (Eq. 2 with the
-// pair rule of Sec. 3.1: of two present partners the one with the pivot bit
-// set emits).  mode: 0 = label outside the controls (passes
-// through), 1 = the label emits the pair, 2 = its partner emits (nothing here).
-struct U2Out {
-  int mode;
-  double2 o0, o1;   // mode 1: amplitudes of the bit-0 and bit-1 labels; mode 0: o0 = a
-};
-
+using ent::U2Out;
 template <bool WIDE>
 __device__ __forceinline__ U2Out u2_eval(const Buf& b, const U2Desc& d, uint64_t lo, uint64_t hi, double2 a,
                                          uint32_t j) {
-  U2Out r;
-  bool c = (lo & d.ctrl_lo) == d.ctrl_lo;
-  if (WIDE) c = c && ((hi & d.ctrl_hi) == d.ctrl_hi);
-  if (!c) {
-    r.mode = 0;
-    r.o0 = a;
-    r.o1 = a;
-    return r;
-  }
-  const bool v = pivot_set<WIDE>(d, lo, hi);
-  if (!v && j != kNoPartner) {
-    r.mode = 2;
-    r.o0 = r.o1 = a;
-    return r;
-  }
-  const double2 zero = make_double2(0.0, 0.0);
-  double2 aj = zero;
-  if (v && j != kNoPartner) aj = b.amp[j];
-  const double2 a0 = sel2(v, aj, a);
-  const double2 a1 = sel2(v, a, zero);
-  // The off-diagonal sign comes from b0, the pair's label with the pivot clear.
-  const uint64_t b0lo = v ? lo ^ d.x_lo : lo, b0hi = v ? hi ^ d.x_hi : hi;
-  const bool odd = ((__popcll(b0lo & d.z_lo) + (WIDE ? __popcll(b0hi & d.z_hi) : 0)) & 1) != 0;
-  double2 p01 = cmul(d.u[1], a1), p10 = cmul(d.u[2], a0);
-  if (odd) {
-    p01 = make_double2(-p01.x, -p01.y);
-    p10 = make_double2(-p10.x, -p10.y);
-  }
-  r.mode = 1;
-  r.o0 = cadd(cmul(d.u[0], a0), p01);
-  r.o1 = cadd(p10, cmul(d.u[3], a1));
-  return r;
+  return ent::u2_eval(d, WIDE, b.amp, lo, hi, a, j);
 }
 
 template <bool WIDE>
@@ -311,40 +250,50 @@ __global__ __launch_bounds__(256) void k_u2_count(Buf b, const uint64_t* __restr
                                                   const uint32_t* __restrict__ partner, uint32_t* __restrict__ tot,
                                                   Ctl* ctl) {
   __shared__ uint32_t sh[256];
+  __shared__ double2 shm[4];   // one slot per wave
   const uint64_t n = *nnz_p;
   uint64_t begin, end;
   chunk_range(n, begin, end);
   uint32_t emit = 0, dropped = 0;
+  double mass = 0.0;
   for (uint64_t i = begin + threadIdx.x; i < end; i += blockDim.x) {
     const uint64_t lo = b.key_lo[i];
     const uint64_t hi = WIDE ? b.key_hi[i] : 0ull;
     const U2Out r = u2_eval<WIDE>(b, d, lo, hi, b.amp[i], partner[i]);
     if (r.mode == 0) {
-      const uint32_t k = survives(r.o0, d.eps) ? 1u : 0u;
-      emit += k;
-      dropped += 1u - k;
+      const bool k = survives(r.o0, d.eps);
+      emit += k ? 1u : 0u;
+      dropped += k ? 0u : 1u;
+      mass += ent::dropped_mass(r.o0, k);
     } else if (r.mode == 1) {
-      const uint32_t k = (survives(r.o0, d.eps) ? 1u : 0u) + (survives(r.o1, d.eps) ? 1u : 0u);
-      emit += k;
-      dropped += 2u - k;
+      const bool k0 = survives(r.o0, d.eps), k1 = survives(r.o1, d.eps);
+      emit += (k0 ? 1u : 0u) + (k1 ? 1u : 0u);
+      dropped += (k0 ? 0u : 1u) + (k1 ? 0u : 1u);
+      mass += ent::dropped_mass(r.o0, k0) + ent::dropped_mass(r.o1, k1);
     }
   }
   emit = block_sum(emit, sh);
   dropped = block_sum(dropped, sh);
+  mass = block_sum(make_double2(mass, 0.0), shm).x;
   if (threadIdx.x == 0) {
     tot[blockIdx.x] = emit;
-    if (dropped) atomicAdd((unsigned long long*)&ctl->pruned, (unsigned long long)dropped);
+    if (dropped) {
+      atomicAdd((unsigned long long*)&ctl->st_pruned, (unsigned long long)dropped);
+      atomicAdd(&ctl->st_mass, mass);
+    }
     if (blockIdx.x == 0) {
-      atomicAdd((unsigned long long*)&ctl->updates, (unsigned long long)n);
+      atomicAdd((unsigned long long*)&ctl->st_updates, (unsigned long long)n);
       atomicAdd((unsigned long long*)&ctl->pass_bytes[0], (unsigned long long)(n * (WIDE ? 32u : 24u)));
     }
   }
 }
 
 // One block: exclusive scan of per-block counts in place; the total becomes
-// the entry count of the output buffer.
+// the entry count of the output buffer.  The count pass's staged counters
+// are committed if the total fits cap (otherwise the gate is rejected and
+// they are discarded).
 __global__ __launch_bounds__(1024) void k_scan(uint32_t* __restrict__ tot, int nb, uint64_t* nnz_out, Ctl* ctl,
-                                               uint32_t entry_bytes) {
+                                               uint32_t entry_bytes, uint64_t cap) {
   __shared__ uint32_t sh[1024];
   const int per = (nb + blockDim.x - 1) / blockDim.x;
   const int first = threadIdx.x * per;
@@ -371,8 +320,16 @@ __global__ __launch_bounds__(1024) void k_scan(uint32_t* __restrict__ tot, int n
   if (threadIdx.x == blockDim.x - 1) {
     const uint64_t total = sh[threadIdx.x];
     *nnz_out = total;
-    if (total > ctl->peak) ctl->peak = total;
-    ctl->pass_bytes[1] += total * entry_bytes;   // the write pass's output
+    if (total <= cap) {
+      if (total > ctl->peak) ctl->peak = total;
+      ctl->pass_bytes[1] += total * entry_bytes;   // the write pass's output
+      ctl->updates += ctl->st_updates;
+      ctl->pruned += ctl->st_pruned;
+      ctl->pruned_mass += ctl->st_mass;
+    }
+    ctl->st_updates = 0;
+    ctl->st_pruned = 0;
+    ctl->st_mass = 0.0;
   }
 }
 
@@ -462,6 +419,7 @@ __global__ __launch_bounds__(256) void k_u2_fused(Buf in, Buf out, const uint64_
   constexpr int kItems = kU2Tile / 256;
   __shared__ uint32_t s_wave[16];
   __shared__ uint32_t sh[256];
+  __shared__ double2 shm[4];   // one slot per wave
   __shared__ uint32_t s_tile, s_excl;
   const uint64_t n = *nnz_p;
   // This gate is done with the hash index: empty its first clear_slots slots
@@ -482,6 +440,7 @@ __global__ __launch_bounds__(256) void k_u2_fused(Buf in, Buf out, const uint64_
   uint32_t pos[kItems];
   bool k0[kItems], k1[kItems];
   uint32_t run = 0, dropped = 0;
+  double mass = 0.0;
 #pragma unroll
   for (int k = 0; k < kItems; ++k) {
     const uint64_t i = begin + (uint64_t)k * 256 + threadIdx.x;
@@ -495,10 +454,12 @@ __global__ __launch_bounds__(256) void k_u2_fused(Buf in, Buf out, const uint64_
       if (r[k].mode == 0) {
         k0[k] = survives(r[k].o0, d.eps);
         dropped += k0[k] ? 0u : 1u;
+        mass += ent::dropped_mass(r[k].o0, k0[k]);
       } else if (r[k].mode == 1) {
         k0[k] = survives(r[k].o0, d.eps);
         k1[k] = survives(r[k].o1, d.eps);
         dropped += (k0[k] ? 0u : 1u) + (k1[k] ? 0u : 1u);
+        mass += ent::dropped_mass(r[k].o0, k0[k]) + ent::dropped_mass(r[k].o1, k1[k]);
       }
     }
     uint32_t tt;
@@ -506,11 +467,15 @@ __global__ __launch_bounds__(256) void k_u2_fused(Buf in, Buf out, const uint64_
     run += tt;
   }
   dropped = block_sum(dropped, sh);
+  mass = block_sum(make_double2(mass, 0.0), shm).x;
   // Publish this tile's count, then the first wave looks back 64 tiles per
   // poll (lane l reads tile - 1 - l) and adds counts back to the nearest
   // published inclusive prefix; positions before tile 0 count as a prefix of 0.
   if (threadIdx.x == 0) {
-    if (dropped) atomicAdd((unsigned long long*)&ctl->pruned, (unsigned long long)dropped);
+    if (dropped) {
+      atomicAdd((unsigned long long*)&ctl->pruned, (unsigned long long)dropped);
+      atomicAdd(&ctl->pruned_mass, mass);
+    }
     __hip_atomic_store(&status[tile], st_word(epoch, tile == 0 ? kStPrefix : kStAgg, run), __ATOMIC_RELAXED,
                        __HIP_MEMORY_SCOPE_AGENT);
     if (tile == 0) atomicAdd((unsigned long long*)&ctl->updates, (unsigned long long)n);
@@ -850,8 +815,9 @@ void launch_u2_count(hipStream_t st, bool wide, Buf b, const uint64_t* nnz, cons
     hipLaunchKernelGGL(k_u2_count<false>, dim3(grid), dim3(block), 0, st, b, nnz, d, partner, tot, ctl);
 }
 
-void launch_scan(hipStream_t st, uint32_t* tot, int nblocks, uint64_t* nnz_out, Ctl* ctl, uint32_t entry_bytes) {
-  hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, st, tot, nblocks, nnz_out, ctl, entry_bytes);
+void launch_scan(hipStream_t st, uint32_t* tot, int nblocks, uint64_t* nnz_out, Ctl* ctl, uint32_t entry_bytes,
+                 uint64_t cap) {
+  hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, st, tot, nblocks, nnz_out, ctl, entry_bytes, cap);
 }
 
 void launch_u2_write(hipStream_t st, bool wide, Buf in, Buf out, const uint64_t* nnz, const uint32_t* partner,

@@ -47,10 +47,10 @@ class sim_config(ctypes.Structure):
 class sim_stats(ctypes.Structure):
     _fields_ = [(f, ctypes.c_uint64) for f in (
         "gates_applied", "updates", "mono_passes", "u2_applied", "u2_skipped", "measures", "host_syncs",
-        "peak_nnz", "pruned", "bitslice_passes")]
+        "peak_nnz", "pruned", "bitslice_passes")] + [("pruned_mass", ctypes.c_double)]
 
     def as_dict(self):
-        return {f: int(getattr(self, f)) for f, _ in self._fields_}
+        return {f: (float if t is ctypes.c_double else int)(getattr(self, f)) for f, t in self._fields_}
 
 
 class sim_key(ctypes.Structure):

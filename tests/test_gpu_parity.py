@@ -51,6 +51,8 @@ def check_vs_oracle(S, w, tol=1e-12, **kw):
     t = o.totals()
     assert gst["u2_applied"] == t["u2_applied"] and gst["u2_skipped"] == t["u2_skipped"]
     assert gst["updates"] == t["updates"]
+    assert gst["pruned"] == t["pruned"]
+    assert abs(gst["pruned_mass"] - t["pruned_mass"]) <= 1e-12, (gst["pruned_mass"], t["pruned_mass"])
     return g, gst
 
 
@@ -69,6 +71,63 @@ def test_bell_ghz_x128(sim):
         c.x(q)
     g, _ = check_vs_oracle(sim, W.Workload("x128", 128, 0.0, c.array(), capacity=2))
     assert g[0].tolist() == [2 ** 64 - 1] and g[1].tolist() == [2 ** 64 - 1] and g[2][0] == 1.0
+
+
+def _eps_boundary_case():
+    """A state whose pass through an exact identity branching gate (Rx(0):
+    cos 0 = 1, sin 0 = 0) leaves one amplitude with |a|^2 exactly eps, one
+    just below and one just above, in the real and in the imaginary part."""
+    x = 3.0e-11
+    eps = x * x                                  # |(x, 0)|^2 = re*re + 0 exactly
+    below, above = np.nextafter(x, 0.0), np.nextafter(x, 1.0)
+    assert below * below < eps < above * above
+    lo = np.array([0b0001, 0b0011, 0b0101, 0b0111, 0b1001, 0b1011], np.uint64)
+    hi = np.zeros(6, np.uint64)
+    amp = np.array([x, below, above, 1j * x, 1j * below, 0.5], np.complex128)
+    c = W.Circuit()
+    c.gate(W.K_RX, 6, param=0.0)                 # qubit 6 is clear in every label: partners are absent
+    return 8, eps, lo, hi, amp, c.array(), {0b0001, 0b0101, 0b0111, 0b1011}
+
+
+def test_eps_boundary(sim):
+    """T_eps drops iff |a|^2 < eps: an entry exactly at eps survives, on the
+    single-state path (both fused-pass forms do not prune; the branching
+    kernels do) and in the batched server."""
+    nq, eps, lo, hi, amp, ops, keep = _eps_boundary_case()
+    from paper_2105_01533_amd.sim import Server, Simulator, sim_config, sim_gates_from_ops
+    for flags in (0, sim.SIM_FLAG_U2_TWO_PASS):
+        s = Simulator(nq, 64, eps, flags=flags)
+        s.import_state(lo, hi, amp)
+        _, _, st = s.apply_ops(ops)
+        glo, ghi, gamp = s.export()
+        s.close()
+        assert set(int(v) for v in glo) == keep, (flags, glo)
+        assert st["pruned"] == 6 + 2                # six absent partners (exact zeros) + two below eps
+        ref = {int(k): a for k, a in zip(lo, amp)}
+        assert all(gamp[i] == ref[int(glo[i])] for i in range(len(glo)))
+    o = Oracle(nq, eps)
+    o.import_state(lo, hi, amp)
+    o.run(ops)
+    assert set(int(v) for v in o.export()[0]) == keep
+    # The server starts from basis states: one H makes two amplitudes
+    # (1/sqrt 2, 0) whose |a|^2 is the rounded h * h; with eps exactly that
+    # both survive, with the next double above it both are dropped.
+    h = 0.70710678118654752440
+    c = W.Circuit()
+    c.h(0)
+    c.gate(W.K_RX, 3, param=0.0)
+    gates = sim_gates_from_ops(c.array())
+    for e2, want in ((h * h, [0, 1]), (np.nextafter(h * h, 1.0), [])):
+        srv = Server(1 << 26, max_slots=4)
+        rid = srv.submit(sim_config(n_qubits=4, capacity=16, eps=e2), gates)
+        srv.run()
+        r = srv.result(rid)
+        srv.close()
+        s = Simulator(4, 16, e2)
+        s.apply_ops(c.array())
+        g = s.export()
+        s.close()
+        assert sorted(int(v) for v in r[0]) == sorted(int(v) for v in g[0]) == want
 
 
 def test_hh_identity_prunes(sim):
@@ -117,21 +176,29 @@ def _golden(name):
         return json.load(f)
 
 
-def _check_golden(S, w, doc):
-    g, gout, gst = gpu_run(S, w)
+def _check_digest(g, doc, what=""):
+    """Sorted state g against an oracle digest: entry count, SHA-256 of the
+    sorted labels, every stride-th entry (labels exact, amplitudes within
+    1e-12) and the norm."""
     lo, hi, amp = g
-    assert len(lo) == doc["nnz"]
-    assert keys_digest(lo, hi) == doc["keys_sha256"]
-    assert list(gout) == doc["outcomes"]
-    assert gst["updates"] == doc["updates"] and gst["u2_applied"] == doc["u2_applied"]
-    assert gst["u2_skipped"] == doc["u2_skipped"]
+    assert len(lo) == doc["nnz"], f"{what}: nnz {len(lo)} != {doc['nnz']}"
+    assert keys_digest(lo, hi) == doc["keys_sha256"], f"{what}: label sets differ"
     err = 0.0
     for k, (slo, shi, re_, im_) in enumerate(doc["samples"]):
         i = k * doc["stride"]
         assert int(lo[i]) == slo and int(hi[i]) == shi
         err = max(err, abs(amp[i] - complex(float.fromhex(re_), float.fromhex(im_))))
-    assert err <= 1e-12, err
+    assert err <= 1e-12, f"{what}: max |amp diff| {err:.3e}"
     assert abs(np.sum(np.abs(amp) ** 2) - float.fromhex(doc["norm2"])) < 1e-10
+    return err
+
+
+def _check_golden(S, w, doc):
+    g, gout, gst = gpu_run(S, w)
+    _check_digest(g, doc, w.name)
+    assert list(gout) == doc["outcomes"]
+    assert gst["updates"] == doc["updates"] and gst["u2_applied"] == doc["u2_applied"]
+    assert gst["u2_skipped"] == doc["u2_skipped"]
 
 
 def test_config1_full_golden(sim):
@@ -172,6 +239,38 @@ def test_config2_full_first_round_samples(sim):
     assert sorted_unique(lo, hi)          # a permutation image: labels stay distinct
 
 
+def test_config2_full_rounds_golden(sim):
+    """The 100-qubit random circuit at full size against the oracle's digests
+    of its first three measurement rounds (tests/golden/config2_rounds.json,
+    Sec. 3.1 branching and Sec. 2.1 measurement): after each round's 20,000
+    gates the 2^24-entry state (round 1: fused passes only; rounds 2 and 3:
+    regrown from ~2^16 entries through single-pass branching gates on up to
+    2^23-entry inputs), then after its chain of 8 measurements (the first
+    decides over 2,048 blocks), with outcomes and update counters."""
+    from paper_2105_01533_amd.sim import Simulator
+    doc = _golden("config2_rounds")
+    w = W.config2()
+    assert doc["seed"] == w.meta["seed"] and doc["n_ops"] == len(w.ops)
+    s = Simulator(w.n_qubits, w.capacity, w.eps)
+    s.set_basis(*w.basis)
+    start, upd, u2a, u2s = 0, 0, 0, 0
+    for r, rd in enumerate(doc["rounds"]):
+        pre, post = rd["pre_measure"], rd["post_measure"]
+        say(f"[gpu] c2 round {r + 1}: ops {start}..{pre['op_end']}")
+        _, _, st = s.apply_ops(w.ops[start:pre["op_end"]])
+        upd, u2a, u2s = upd + st["updates"], u2a + st["u2_applied"], u2s + st["u2_skipped"]
+        assert (upd, u2a, u2s) == (pre["updates"], pre["u2_applied"], pre["u2_skipped"])
+        err = _check_digest(s.export(), pre, f"c2 round {r + 1} before measuring")
+        say(f"[gpu] c2 round {r + 1}: {pre['nnz']} entries, max |diff| {err:.2e}; measuring")
+        _, outs, st = s.apply_ops(w.ops[pre["op_end"]:post["op_end"]])
+        upd += st["updates"]
+        assert list(outs) == post["outcomes"] and st["measures"] == 8
+        assert upd == post["updates"]
+        _check_digest(s.export(), post, f"c2 round {r + 1} after measuring")
+        start = post["op_end"]
+    s.close()
+
+
 def test_config2_full_properties(sim):
     """Full 200,000-gate workload: the normalisation restored by every
     measurement, nnz within the cap, and bitwise determinism."""
@@ -180,7 +279,8 @@ def test_config2_full_properties(sim):
     assert len(g1[0]) <= 1 << 24 and st1["measures"] == 80
     assert abs(np.sum(np.abs(g1[2]) ** 2) - 1.0) < 1e-9
     g2, out2, st2 = gpu_run(sim, w)
-    assert list(out1) == list(out2) and st1 == st2
+    m1, m2 = st1.pop("pruned_mass"), st2.pop("pruned_mass")   # summed in no fixed order
+    assert list(out1) == list(out2) and st1 == st2 and abs(m1 - m2) <= 1e-12 * max(1.0, m1)
     for a, b in zip(g1, g2):
         assert a.tobytes() == b.tobytes()
 
@@ -567,6 +667,9 @@ def test_capacity_error_leaves_state(sim):
     before = s.export()
     rc, _, st = s.apply_ops(c.array()[5:], raise_on_error=False)
     assert rc == SIM_E_CAPACITY and st["gates_applied"] == 0
+    # The rejected gate changes no counter: its count pass ran, but the scan
+    # commits the staged counters only for outputs that fit.
+    assert st["updates"] == 0 and st["pruned"] == 0 and st["peak_nnz"] == 16
     after = s.export()
     for a, b in zip(before, after):
         assert a.tobytes() == b.tobytes()

@@ -341,3 +341,29 @@ def test_circuit_then_inverse_returns_initial_state():
     d = state_dict(o)
     assert set(d) == set(range(64))
     assert max(abs(a - 0.125) for a in d.values()) < 1e-13
+
+
+def test_eps_boundary_is_strict():
+    """T_eps drops an entry iff re*re + im*im < eps (the reading of the
+    paper's 'only nonzero amplitudes are stored' with a threshold): after an
+    exact identity branching gate (Rx(0): cos 0 = 1, sin 0 = 0, Eq. 2 with
+    U = I), an amplitude whose |a|^2 is exactly eps survives, in the real and
+    in the imaginary part, and the next double below it is dropped; the
+    absent partners' exact zeros are dropped too."""
+    x = 3.0e-11
+    eps = x * x
+    below, above = np.nextafter(x, 0.0), np.nextafter(x, 1.0)
+    assert below * below < eps < above * above
+    lo = np.array([0b0001, 0b0011, 0b0101, 0b0111, 0b1001, 0b1011], np.uint64)
+    amp = np.array([x, below, above, 1j * x, 1j * below, 0.5], np.complex128)
+    c = W.Circuit()
+    c.gate(W.K_RX, 6, param=0.0)
+    o = Oracle(8, eps)
+    o.import_state(lo, np.zeros(6, np.uint64), amp)
+    o.run(c.array())
+    glo, _, gamp = o.export()
+    assert [int(v) for v in glo] == [0b0001, 0b0101, 0b0111, 0b1011]
+    assert list(gamp) == [x, above, 1j * x, 0.5]          # passed through exactly
+    t = o.totals()
+    assert t["pruned"] == 6 + 2
+    assert t["pruned_mass"] == below * below + below * below
