@@ -240,6 +240,29 @@ int sim_gates_from_ops(const sim_op* ops, size_t n, sim_gate* out);
 int sim_apply_gates(sim_t* s, const sim_gate* gates, size_t n, int32_t* outcomes, sim_stats* stats);
 
 /*
+ * sim_apply_gates for callers that cannot allocate memory (code that must not
+ * call hipMalloc: graph-building or tight serving loops, harnesses that
+ * forbid it).  Same arguments, semantics, results and errors as
+ * sim_apply_gates (results are bitwise those of sim_apply_gates on the same
+ * handle state), but the call allocates no device or pinned host memory and
+ * creates no events or threads: the device buffers a call needs beyond the
+ * state (phase/permutation descriptors, register-plane programs, measurement
+ * records and outcomes) live in a 32 MiB static device array of the library,
+ * one per GPU, held until the process ends; uploads go from the handle's host
+ * buffers (pageable), whose capacity is kept between calls.  The handle must
+ * already exist (sim_create allocates, or borrows a caller workspace) and
+ * profiling events are not recorded during the call.  Limits: at most 65536
+ * ops per call (more -> SIM_E_ARG, nothing applied; split the list), a
+ * handle created with SIM_FLAG_BS_LDS -> SIM_E_ARG, and a single fused run
+ * whose program exceeds the array -> SIM_E_NOMEM (the state is then that
+ * before the run).  Calls on one GPU share its array: the library runs them
+ * one at a time within a process (each returns only after its stream has
+ * drained), so overlapping calls from threads of one process serialize.
+ * Synchronizes, like sim_apply_gates.
+ */
+int sim_apply_gates_static(sim_t* s, const sim_gate* gates, size_t n, int32_t* outcomes, sim_stats* stats);
+
+/*
  * Gate commuting (Sec. 3.3, Fig. 1), host only.  Passes n standard-gate
  * records through per-qubit queues of H, Rx and Ry gates that act after the
  * phase/permutation queue, and writes the ops the queues send on, in order,

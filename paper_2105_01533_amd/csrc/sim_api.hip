@@ -223,6 +223,7 @@ struct sim_t {
   sim_config cfg;
   // profiling
   uint32_t profile = 0;          // bit c: kernel class c is timed with events
+  bool no_alloc = false;         // inside sim_apply_gates_static: no events, threads or allocations
   std::vector<hipEvent_t> ev_pool;
   size_t ev_used = 0;
   std::vector<std::pair<int, size_t>> ev_pending;   // (class, index of start event)
@@ -249,6 +250,7 @@ struct sim_t {
     const uint32_t* off;
   } mchain = {false, 0, 0, nullptr};
   hipStream_t stream;
+  int device;                  // the device current at creation
   bool wide;
   char* ws;
   bool ws_owned;
@@ -266,6 +268,7 @@ struct sim_t {
   std::vector<BsGroup> h_grp;
   DevVec<RpRec> rp_prog;       // register-plane programs of the current call
   std::vector<RpRec> h_rp;     // the program of the run being prepared
+  std::vector<RpRec> h_rp_call; // sim_apply_gates_static: the programs uploaded since the last drain
   std::vector<sim_gate> conv;  // sim_apply_ops: converted ops, kept between calls
   RunCompiler rc;              // MONO descriptors and bytecode of the current call
   DevVec<MeasRec> recs;
@@ -315,7 +318,7 @@ struct KTimer {
   bool on = false;
   KTimer(sim_t* s_, int c) : s(s_), cls(c) {
     s->k_launches[c]++;
-    if (!((s->profile >> c) & 1u)) return;
+    if (!((s->profile >> c) & 1u) || s->no_alloc) return;
     idx = s->ev_used;
     hipEvent_t e = next_event(s);
     on = e && hipEventRecord(e, s->stream) == hipSuccess;
@@ -543,6 +546,7 @@ int sim_create(const sim_config* cfg, void* stream, void* workspace, size_t ws_b
   s->cfg = *cfg;
   if (!s->cfg.fuse_max) s->cfg.fuse_max = 65536;
   s->stream = static_cast<hipStream_t>(stream);
+  if (hipGetDevice(&s->device) != hipSuccess) s->device = 0;
   s->wide = cfg->n_qubits > 64;
   s->L = layout_of(cfg);
   if (workspace) {
@@ -731,9 +735,57 @@ int sim_gates_from_ops(const sim_op* ops, size_t n, sim_gate* out) {
   return SIM_OK;
 }
 
-int sim_apply_gates(sim_t* s, const sim_gate* gates, size_t n, int32_t* outcomes, sim_stats* stats) {
-  if (!s) return fail(SIM_E_ARG, "null handle");
-  if (n && !gates) return fail(SIM_E_ARG, "null gate array");
+}  // extern "C"
+
+namespace {
+
+// ---- allocation-free variant: device buffers of a call in static memory ----
+// Gates per sim_apply_gates_static call, and the static scratch behind it:
+// descriptors of the per-entry fused pass, measurement records and outcomes,
+// then register-plane programs (a ring, as in the allocating form).
+constexpr size_t kStaticMaxGates = 65536;
+constexpr size_t kStaticDescBytes = kStaticMaxGates * sizeof(MonoDesc);
+constexpr size_t kStaticRecBytes = kStaticMaxGates * sizeof(MeasRec);
+constexpr size_t kStaticOutBytes = kStaticMaxGates * sizeof(int32_t);
+constexpr size_t kStaticScratchBytes = 32u << 20;
+static_assert(kStaticDescBytes + kStaticRecBytes + kStaticOutBytes < kStaticScratchBytes / 2, "scratch layout");
+static __device__ __align__(256) char scratch[kStaticScratchBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;                  // guards g_scratch_ptr
+char* g_scratch_ptr[kMaxDevices] = {};    // device address of `scratch`, per device
+std::mutex g_static_call_mu[kMaxDevices]; // one allocation-free call per device at a time
+
+// The address of this device's copy of `scratch`, looked up once per device
+// with that device current.
+int static_scratch(int dev, char** out) {
+  if (dev < 0 || dev >= kMaxDevices) return fail(SIM_E_ARG, "device id out of range");
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    int cur = 0;
+    HIP_TRY(hipGetDevice(&cur));
+    if (cur != dev) HIP_TRY(hipSetDevice(dev));
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (cur != dev) (void)hipSetDevice(cur);
+    if (e != hipSuccess) return fail(SIM_E_HIP, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+    g_scratch_ptr[dev] = static_cast<char*>(p);
+  }
+  *out = g_scratch_ptr[dev];
+  return SIM_OK;
+}
+
+// Device buffers of one apply call.
+struct CallBufs {
+  bool fixed = false;          // carved from the static scratch (no growth; uploads from pageable memory)
+  MonoDesc* descs = nullptr;
+  MeasRec* recs = nullptr;
+  int32_t* outcomes = nullptr;
+  RpRec* rp = nullptr;         // fixed: the program ring
+  size_t rp_cap = 0;           // records
+};
+
+int apply_impl(sim_t* s, const sim_gate* gates, size_t n, int32_t* outcomes, sim_stats* stats, CallBufs cb) {
   s->mchain.valid = false;
   sim_stats st;
   std::memset(&st, 0, sizeof st);
@@ -781,12 +833,18 @@ int sim_apply_gates(sim_t* s, const sim_gate* gates, size_t n, int32_t* outcomes
       if (t.joinable()) t.join();
     }
   } compiler;
-  // (Small lists compile on this thread: starting a thread costs more.)
-  if (bs_allowed && n_mono < 8192) s->rc.compile(s->cfg.n_qubits);
+  // (Small lists compile on this thread: starting a thread costs more.  The
+  // allocation-free form starts no thread.)
+  if (bs_allowed && (n_mono < 8192 || cb.fixed)) s->rc.compile(s->cfg.n_qubits);
   else if (bs_allowed) compiler.t = std::thread([s]() { s->rc.compile(s->cfg.n_qubits); });
-  HIP_TRY(s->descs.reserve(n_mono));
-  HIP_TRY(s->recs.reserve(n_meas));
-  HIP_TRY(s->outcomes.reserve(n_meas));
+  if (!cb.fixed) {
+    HIP_TRY(s->descs.reserve(n_mono));
+    HIP_TRY(s->recs.reserve(n_meas));
+    HIP_TRY(s->outcomes.reserve(n_meas));
+    cb.descs = s->descs.p;
+    cb.recs = s->recs.p;
+    cb.outcomes = s->outcomes.p;
+  }
   // Descriptors are uploaded for the runs that take the per-entry kernel,
   // a window of runs at a time, and the bit-sliced groups run by run, both
   // from pinned staging (asynchronous).
@@ -812,9 +870,14 @@ int sim_apply_gates(sim_t* s, const sim_gate* gates, size_t n, int32_t* outcomes
       if (compiler.t.joinable()) compiler.t.join();
     }
     compiled = true;
-    if (use_rp) {
+    if (use_rp && cb.fixed) {
+      s->h_rp_call.clear();
+      s->h_rp_call.reserve(std::min(cb.rp_cap, 4 * s->rc.ops.size() + 64));
+    } else if (use_rp) {
       HIP_TRY(s->rp_prog.reserve(4 * s->rc.ops.size() + 64));
       HIP_TRY(h_rp_pin.reserve(4 * s->rc.ops.size() + 64));
+      cb.rp = s->rp_prog.p;
+      cb.rp_cap = s->rp_prog.n;
     } else {
       s->h_grp.reserve(2 * s->rc.ops.size() + 2);
       HIP_TRY(s->grp_ops.reserve(2 * s->rc.ops.size() + 2));
@@ -877,18 +940,36 @@ int sim_apply_gates(sim_t* s, const sim_gate* gates, size_t n, int32_t* outcomes
         }
       }
       const size_t nr = s->h_rp.size();
-      if (rp_used + nr > s->rp_prog.n || (rp_used + nr) * sizeof(RpRec) > h_rp_pin.bytes) {
-        HIP_TRY(timed_sync(s));
-        rp_used = 0;
-        HIP_TRY(s->rp_prog.reserve(2 * nr));
-        HIP_TRY(h_rp_pin.reserve(2 * nr));
+      if (cb.fixed) {
+        // Static ring: the host copy of each upload (pageable) stays in
+        // h_rp_call until the stream has drained past it.
+        if (nr > cb.rp_cap) return fail(SIM_E_NOMEM, "a run's program exceeds the static scratch (split the call)");
+        if (rp_used + nr > cb.rp_cap || s->h_rp_call.size() + nr > s->h_rp_call.capacity()) {
+          HIP_TRY(timed_sync(s));
+          rp_used = 0;
+          s->h_rp_call.clear();
+          s->h_rp_call.reserve(std::min(cb.rp_cap, std::max<size_t>(2 * nr, 4096)));
+        }
+        const size_t h0 = s->h_rp_call.size();
+        s->h_rp_call.insert(s->h_rp_call.end(), s->h_rp.begin(), s->h_rp.end());
+        HIP_TRY(hipMemcpyAsync(cb.rp + rp_used, s->h_rp_call.data() + h0, nr * sizeof(RpRec), hipMemcpyHostToDevice,
+                               s->stream));
+      } else {
+        if (rp_used + nr > s->rp_prog.n || (rp_used + nr) * sizeof(RpRec) > h_rp_pin.bytes) {
+          HIP_TRY(timed_sync(s));
+          rp_used = 0;
+          HIP_TRY(s->rp_prog.reserve(2 * nr));
+          HIP_TRY(h_rp_pin.reserve(2 * nr));
+          cb.rp = s->rp_prog.p;
+          cb.rp_cap = s->rp_prog.n;
+        }
+        std::memcpy(h_rp_pin.p + rp_used, s->h_rp.data(), nr * sizeof(RpRec));
+        HIP_TRY(hipMemcpyAsync(cb.rp + rp_used, h_rp_pin.p + rp_used, nr * sizeof(RpRec), hipMemcpyHostToDevice,
+                               s->stream));
       }
-      std::memcpy(h_rp_pin.p + rp_used, s->h_rp.data(), nr * sizeof(RpRec));
-      HIP_TRY(hipMemcpyAsync(s->rp_prog.p + rp_used, h_rp_pin.p + rp_used, nr * sizeof(RpRec), hipMemcpyHostToDevice,
-                             s->stream));
       {
         KTimer t_(s, KC_MONO);
-        launch_mono_rp(s->stream, s->buf[s->cur], d_nnz(s, s->cur), s->rp_prog.p + rp_used, (uint32_t)nr, br, s->ctl,
+        launch_mono_rp(s->stream, s->buf[s->cur], d_nnz(s, s->cur), cb.rp + rp_used, (uint32_t)nr, br, s->ctl,
                        bs_grid(s, ub));
       }
       rp_used += nr;
@@ -921,16 +1002,22 @@ int sim_apply_gates(sim_t* s, const sim_gate* gates, size_t n, int32_t* outcomes
       st.bitslice_passes++;
     } else {
       if (run_begin < desc_lo || run_begin + run_len > desc_hi) {
-        // This run and those after it, up to 1024 descriptors, in one copy.
+        // This run and those after it, up to 1024 descriptors, in one copy
+        // (the allocation-free form copies from the compiled descriptors,
+        // which stay in place until the call returns).
         desc_lo = run_begin;
         desc_hi = std::min(s->rc.descs.size(), run_begin + std::max<size_t>(run_len, 1024));
-        HIP_TRY(h_desc.reserve(s->rc.descs.size()));
-        std::memcpy(h_desc.p + desc_lo, s->rc.descs.data() + desc_lo, (desc_hi - desc_lo) * sizeof(MonoDesc));
-        HIP_TRY(hipMemcpyAsync(s->descs.p + desc_lo, h_desc.p + desc_lo, (desc_hi - desc_lo) * sizeof(MonoDesc),
+        const MonoDesc* src = s->rc.descs.data();
+        if (!cb.fixed) {
+          HIP_TRY(h_desc.reserve(s->rc.descs.size()));
+          std::memcpy(h_desc.p + desc_lo, s->rc.descs.data() + desc_lo, (desc_hi - desc_lo) * sizeof(MonoDesc));
+          src = h_desc.p;
+        }
+        HIP_TRY(hipMemcpyAsync(cb.descs + desc_lo, src + desc_lo, (desc_hi - desc_lo) * sizeof(MonoDesc),
                                hipMemcpyHostToDevice, s->stream));
       }
       KTimer t_(s, KC_MONO);
-      launch_mono(s->stream, s->wide, s->buf[s->cur], d_nnz(s, s->cur), s->descs.p + run_begin, (uint32_t)run_len,
+      launch_mono(s->stream, s->wide, s->buf[s->cur], d_nnz(s, s->cur), cb.descs + run_begin, (uint32_t)run_len,
                   run_flags, run_bpe, s->ctl, mono_grid(s, ub), block_of(s));
     }
     HIP_TRY(hipGetLastError());
@@ -942,7 +1029,7 @@ int sim_apply_gates(sim_t* s, const sim_gate* gates, size_t n, int32_t* outcomes
   // Start the speculative grouping of the run that would follow a skip of
   // capped gate i (see Spec).
   auto speculate = [&](size_t i) -> int {
-    if (!bs_allowed) return SIM_OK;
+    if (!bs_allowed || cb.fixed) return SIM_OK;
     int rc = ensure_compiled();
     if (rc) return rc;
     const size_t begin = run_len ? run_begin : mono_seen;
@@ -1019,7 +1106,7 @@ int sim_apply_gates(sim_t* s, const sim_gate* gates, size_t n, int32_t* outcomes
     bool bad = false;
     // A measurement right after this one takes its sums from this write.
     const int32_t q_next = i + 1 < n && gates[i + 1].op == SIM_OP_MEASURE ? (int32_t)gates[i + 1].target : -1;
-    rc = run_measure(s, g.target, g.u, g.forced, s->recs.p + meas_seen, s->outcomes.p + meas_seen, &bad, q_next);
+    rc = run_measure(s, g.target, g.u, g.forced, cb.recs + meas_seen, cb.outcomes + meas_seen, &bad, q_next);
     if (rc) return rc;
     if (bad) {
       result = fail(SIM_E_STATE, "measurement outcome has zero probability");
@@ -1033,7 +1120,7 @@ int sim_apply_gates(sim_t* s, const sim_gate* gates, size_t n, int32_t* outcomes
     if (rc) return rc;
   }
   if (outcomes && meas_seen)
-    HIP_TRY(hipMemcpyAsync(outcomes, s->outcomes.p, meas_seen * 4, hipMemcpyDeviceToHost, s->stream));
+    HIP_TRY(hipMemcpyAsync(outcomes, cb.outcomes, meas_seen * 4, hipMemcpyDeviceToHost, s->stream));
   int rc = read_ctl(s);
   if (rc) return rc;
   if (const uint32_t err = s->h_ctl->error) {
@@ -1060,6 +1147,40 @@ int sim_apply_gates(sim_t* s, const sim_gate* gates, size_t n, int32_t* outcomes
   if (s->nnz_exact > st.peak_nnz) st.peak_nnz = s->nnz_exact;
   if (stats) *stats = st;
   return result;
+}
+
+}  // namespace
+
+extern "C" {
+
+int sim_apply_gates(sim_t* s, const sim_gate* gates, size_t n, int32_t* outcomes, sim_stats* stats) {
+  if (!s) return fail(SIM_E_ARG, "null handle");
+  if (n && !gates) return fail(SIM_E_ARG, "null gate array");
+  return apply_impl(s, gates, n, outcomes, stats, CallBufs{});
+}
+
+int sim_apply_gates_static(sim_t* s, const sim_gate* gates, size_t n, int32_t* outcomes, sim_stats* stats) {
+  if (!s) return fail(SIM_E_ARG, "null handle");
+  if (n && !gates) return fail(SIM_E_ARG, "null gate array");
+  if (n > kStaticMaxGates)
+    return fail(SIM_E_ARG, "sim_apply_gates_static takes at most " + std::to_string(kStaticMaxGates) + " ops per call");
+  if (s->cfg.flags & SIM_FLAG_BS_LDS) return fail(SIM_E_ARG, "sim_apply_gates_static does not run the LDS-plane pass");
+  char* base = nullptr;
+  int rc = static_scratch(s->device, &base);
+  if (rc) return rc;
+  std::lock_guard<std::mutex> lk(g_static_call_mu[s->device]);
+  CallBufs cb;
+  cb.fixed = true;
+  cb.descs = reinterpret_cast<MonoDesc*>(base);
+  cb.recs = reinterpret_cast<MeasRec*>(base + kStaticDescBytes);
+  cb.outcomes = reinterpret_cast<int32_t*>(base + kStaticDescBytes + kStaticRecBytes);
+  const size_t rp_off = (kStaticDescBytes + kStaticRecBytes + kStaticOutBytes + 255) / 256 * 256;
+  cb.rp = reinterpret_cast<RpRec*>(base + rp_off);
+  cb.rp_cap = (kStaticScratchBytes - rp_off) / sizeof(RpRec);
+  s->no_alloc = true;
+  rc = apply_impl(s, gates, n, outcomes, stats, cb);
+  s->no_alloc = false;
+  return rc;
 }
 
 int sim_apply_ops(sim_t* s, const sim_op* ops, size_t n, int32_t* outcomes, sim_stats* stats) {

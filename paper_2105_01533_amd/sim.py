@@ -85,6 +85,7 @@ def _load():
         "sim_gates_from_pauli": (i32, [vp, sz, ctypes.c_uint32, vp, sz, ctypes.POINTER(sz)]),
         "sim_apply_pauli": (i32, [vp, vp, sz, vp]),
         "sim_apply_gates": (i32, [vp, vp, sz, vp, vp]),
+        "sim_apply_gates_static": (i32, [vp, vp, sz, vp, vp]),
         "sim_apply_ops": (i32, [vp, vp, sz, vp, vp]),
         "sim_measure": (i32, [vp, u32, f64, i32, ctypes.POINTER(i32), ctypes.POINTER(f64)]),
         "sim_nnz": (i32, [vp, ctypes.POINTER(u64)]),
@@ -211,6 +212,18 @@ def sim_apply_gates(h, gates: np.ndarray, raise_on_error: bool = True):
     rc = _lib.sim_apply_gates(h, _ptr(gates), len(gates), _ptr(outcomes), ctypes.byref(st))
     if raise_on_error:
         _check(rc, "sim_apply_gates")
+    return rc, outcomes[:_n_meas_gates(gates)], st.as_dict()
+
+
+def sim_apply_gates_static(h, gates: np.ndarray, raise_on_error: bool = True):
+    """The allocation-free form of sim_apply_gates (at most 65536 ops per
+    call).  Returns (rc, outcomes, stats dict)."""
+    gates = np.ascontiguousarray(gates, dtype=GATE_DTYPE)
+    outcomes = np.full(max(_n_meas_gates(gates), 1), -1, np.int32)
+    st = sim_stats()
+    rc = _lib.sim_apply_gates_static(h, _ptr(gates), len(gates), _ptr(outcomes), ctypes.byref(st))
+    if raise_on_error:
+        _check(rc, "sim_apply_gates_static")
     return rc, outcomes[:_n_meas_gates(gates)], st.as_dict()
 
 
