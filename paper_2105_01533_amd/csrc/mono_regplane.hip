@@ -23,7 +23,7 @@ __global__ __launch_bounds__(64, 2) __attribute__((amdgpu_num_vgpr(40))) void k_
   else if constexpr (VMAX == rp::kVmaxMid) asm volatile("" ::: "v163");
   else asm volatile("" ::: "v230");
   extern __shared__ uint64_t rp_acc[];
-  __shared__ uint64_t s_table[16];
+  __shared__ uint64_t s_table[32];   // two 16-entry subset-sum tables
   const uint64_t n = *nnz_p;
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     atomicAdd((unsigned long long*)&ctl->updates, (unsigned long long)(n * run.n_gates));

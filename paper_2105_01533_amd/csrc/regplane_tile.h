@@ -317,13 +317,17 @@ __device__ __forceinline__ void omega_general(Fetch& f, uint32_t nquads) {
 
 // TURN groups: three quads per group of four ops (cond words; fractions of
 // ops 0, 1; of ops 2, 3).  Each entry's accumulator (LDS, acc[64 j + lane])
-// gains the sum of the fractions of the ops whose condition holds for it: one
-// of 16 subset sums, kept in a 16-entry LDS table and read with one 64-bit
-// load per entry.
-template <bool BARE>
-__device__ __forceinline__ void turn_groups(Fetch& f, uint32_t ng, uint64_t* acc, uint64_t* table) {
+// gains the sum of the fractions of the ops whose condition holds for it: per
+// group, one of 16 subset sums, kept in a 16-entry LDS table and read with
+// one 64-bit load per entry.  C groups share one read-modify-write of the
+// accumulators (C tables side by side), which is what bounds the pass on
+// LDS bandwidth.
+template <bool BARE, int C>
+__device__ __forceinline__ void turn_chunk(Fetch& f, uint64_t* acc, uint64_t* table) {
   const int lane = threadIdx.x;
-  for (uint32_t g = 0; g < ng; ++g) {
+  uint32_t B[C][8];
+#pragma unroll
+  for (int c = 0; c < C; ++c) {
     uint32_t cw[4], t01[4], t23[4];
     next_quad(f, cw);
     next_quad(f, t01);
@@ -336,11 +340,10 @@ __device__ __forceinline__ void turn_groups(Fetch& f, uint32_t ng, uint64_t* acc
     }
     const uint64_t tau[4] = {((uint64_t)t01[1] << 32) | t01[0], ((uint64_t)t01[3] << 32) | t01[2],
                              ((uint64_t)t23[1] << 32) | t23[0], ((uint64_t)t23[3] << 32) | t23[2]};
-    // Entry j's table offset, 8 x (the ops, bit u = op u, whose condition
-    // holds for it), is byte j >> 3 of B[j & 7]: bit j of x[u] moves to bit
-    // 8 (j >> 3) + 3 + u by one constant shift; the four merge under
-    // disjoint byte-lane masks.
-    uint32_t B[8];
+    // Entry j's offset in table c, 8 x (the ops, bit u = op u, whose
+    // condition holds for it), is byte j >> 3 of B[c][j & 7]: bit j of x[u]
+    // moves to bit 8 (j >> 3) + 3 + u by one constant shift; the four merge
+    // under disjoint byte-lane masks.
 #pragma unroll
     for (int w = 0; w < 8; ++w) {
       uint32_t v = 0;
@@ -350,26 +353,49 @@ __device__ __forceinline__ void turn_groups(Fetch& f, uint32_t ng, uint64_t* acc
         const uint32_t y = sh >= 0 ? x[u] >> sh : x[u] << -sh;
         v |= y & (0x01010101u << (3 + u));
       }
-      B[w] = v;
+      B[c][w] = v;
     }
+    // Table entry m (lane m < 16) is the sum of the fractions named by m's
+    // bits.  (The lane number is made opaque here so that the four masks are
+    // formed where they are used, not kept live across the whole tile.)
+    int l = lane;
+    asm volatile("" : "+v"(l));
     uint64_t S = 0;
 #pragma unroll
-    for (int u = 0; u < 4; ++u) S += tau[u] & (0ull - (uint64_t)((lane >> u) & 1));
-    if (lane < 16) table[lane] = S;   // the wave's LDS accesses complete in order
-    const char* tb = reinterpret_cast<const char*>(table);
-#pragma unroll
-    for (int j0 = 0; j0 < 32; j0 += 8) {
-      uint64_t v[8], a[8];
-#pragma unroll
-      for (int k = 0; k < 8; ++k) {
-        const int j = j0 + k;
-        v[k] = *reinterpret_cast<const uint64_t*>(tb + __builtin_amdgcn_ubfe(B[j & 7], 8 * (j >> 3), 8));
-        a[k] = acc[64 * j + lane];
-      }
-#pragma unroll
-      for (int k = 0; k < 8; ++k) acc[64 * (j0 + k) + lane] = a[k] + v[k];
-    }
+    for (int u = 0; u < 4; ++u) S += tau[u] & (0ull - (uint64_t)((l >> u) & 1));
+    if (l < 16) table[16 * c + l] = S;   // the wave's LDS accesses complete in order
+    __builtin_amdgcn_sched_barrier(0);  // one group's planes at a time
   }
+  const char* tb = reinterpret_cast<const char*>(table);
+#pragma unroll
+  for (int j0 = 0; j0 < 32; j0 += 4) {
+    uint64_t a[4], v[C][4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const int j = j0 + k;
+      a[k] = acc[64 * j + lane];
+#pragma unroll
+      for (int c = 0; c < C; ++c)
+        v[c][k] = *reinterpret_cast<const uint64_t*>(tb + 128 * c + __builtin_amdgcn_ubfe(B[c][j & 7], 8 * (j >> 3), 8));
+    }
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      uint64_t t = a[k];
+#pragma unroll
+      for (int c = 0; c < C; ++c) t += v[c][k];
+      acc[64 * (j0 + k) + lane] = t;
+    }
+    // Keep the blocks apart (otherwise every entry's table address is formed
+    // up front, and they do not fit the registers).
+    __builtin_amdgcn_sched_barrier(0);
+  }
+}
+
+template <bool BARE>
+__device__ __forceinline__ void turn_groups(Fetch& f, uint32_t ng, uint64_t* acc, uint64_t* table) {
+  uint32_t g = 0;
+  for (; g + 2 <= ng; g += 2) turn_chunk<BARE, 2>(f, acc, table);
+  if (g < ng) turn_chunk<BARE, 1>(f, acc, table);
 }
 
 // Labels of the tile (word w of each label: bits 32w..32w+31) into planes.
