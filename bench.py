@@ -77,6 +77,19 @@ def cpu_baseline(w, seconds_budget: float = 20.0):
     kinds = ops["kind"]
     first_body = int(np.argmax(kinds != W.K_H)) if np.any(kinds != W.K_H) else len(ops)
     n_body = 64
+    # One core, as the paper's single-core measurements: the process is pinned
+    # to the last CPU it may use for the oracle runs, then released.
+    allowed = sorted(os.sched_getaffinity(0))
+    core = allowed[-1]
+    os.sched_setaffinity(0, {core})
+    try:
+        return _cpu_baseline_pinned(w, seconds_budget, ops, first_body, n_body, core)
+    finally:
+        os.sched_setaffinity(0, set(allowed))
+
+
+def _cpu_baseline_pinned(w, seconds_budget, ops, first_body, n_body, core):
+    from oracle import Oracle
     while True:
         o = Oracle(w.n_qubits, w.eps)
         o.set_basis(*w.basis)
@@ -91,7 +104,8 @@ def cpu_baseline(w, seconds_budget: float = 20.0):
     n_body, dt, upd = best
     return {"value": upd / dt, "unit": "updates/s", "cores": 1, "kind": "oracle",
             "sample": f"{w.name}: initial {first_body} H gates + next {n_body} gates, "
-                      f"{upd} updates in {dt:.1f} s, single thread", "host": host_cpu()}
+                      f"{upd} updates in {dt:.1f} s, single thread pinned to CPU {core}",
+            "pinned_cpu": core, "host": host_cpu()}
 
 
 def cpu_parallel(h_qubits: int = 20, body: int = 1200, threads: int = 0):
@@ -274,6 +288,27 @@ def pauli_bench(sim, W, reps=3):
     return out
 
 
+def copy_bandwidth(sim, torch, nbytes=1 << 30, reps=5):
+    """The library's plain streaming copy (sim_device_copy, 16 B per thread)
+    of nbytes, timed with HIP events on the stream it runs on: bytes read plus
+    bytes written per second, beside the 8 TB/s HBM peak."""
+    a = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    b = torch.empty_like(a)
+    st = torch.cuda.current_stream()
+    sim.sim_device_copy(b.data_ptr(), a.data_ptr(), nbytes, st.cuda_stream)   # warm
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(st)
+    for _ in range(reps):
+        sim.sim_device_copy(b.data_ptr(), a.data_ptr(), nbytes, st.cuda_stream)
+    e1.record(st)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    del a, b
+    gbs = 2 * nbytes / (ms * 1e-3) / 1e9
+    return {"bytes_per_copy": 2 * nbytes, "ms": round(ms, 4), "GB/s": round(gbs, 1), "peak": HBM_PEAK_GBS,
+            "frac": round(gbs / HBM_PEAK_GBS, 4)}
+
+
 def measured_traffic():
     """Per-launch HBM bytes of the fused pass from the committed counter runs
     (profiles/mono_pass_traffic.json), or None if the kernel sources changed
@@ -329,6 +364,8 @@ def main():
             sim.sim_device_copy(b.data_ptr(), a.data_ptr(), 1 << 30, torch.cuda.current_stream().cuda_stream)
         torch.cuda.synchronize()
         del a, b
+    copy = copy_bandwidth(sim, torch)
+    log(f"[bench] reference copy: {copy}")
     fn, desc = WORKLOADS[args.workload]
     w = getattr(W, fn)()
     log(f"[bench] workload {w.name}: {len(w.ops)} ops, capacity {w.capacity}")
@@ -386,9 +423,16 @@ def main():
     alu = {"achieved": round(alu_tops, 4), "peak": round(ALU_PEAK_TOPS, 2), "unit": "TOP/s",
            "frac": round(alu_tops / ALU_PEAK_TOPS, 5),
            "floor_ms_per_launch": ops_per_launch / (ALU_PEAK_TOPS * 1e12) * 1e3}
+    # Roofline: the higher of the two floors is the roof the pass would meet
+    # first (at c2's depth, F of a few thousand gates, the HBM floor is ~4x
+    # the ALU one).  What keeps the pass far below it is neither resource but
+    # instruction issue (scalar index setup and vector plane operations per
+    # gate), measured by the SQ counters and reported as `limiter`.
     bound, view = ("alu", alu) if alu["floor_ms_per_launch"] > hbm["floor_ms_per_launch"] else ("hbm", hbm)
     roofline = {
         "kernel": "mono_pass", "dominant_kernel": dom, "bound": bound, "achieved": view["achieved"],
+        "limiter": "instruction issue (scalar plane-index setup and vector plane ops per gate; SQ counters in "
+                   "profiles/mono_pass_sq_c2_random_100q.md)",
         "peak": view["peak"], "unit": view["unit"], "frac": view["frac"], "traffic": measured_traffic(),
         "hbm": hbm, "alu": alu,
         "launches_per_step": mono["launches"] / args.steps,
@@ -409,6 +453,7 @@ def main():
                    "u2_applied": st["u2_applied"], "u2_skipped": st["u2_skipped"], "measures": st["measures"],
                    "kernel_ms_per_step": kernel_ms, "host_ms_per_step": host_ms},
         "roofline": roofline,
+        "copy": copy,
     }
     s.close()
     if not args.no_sweep:
