@@ -404,7 +404,11 @@ int sim_kernel_stats_reset(sim_t* s);
 
 typedef struct srv_config {
   uint64_t budget_bytes; /* device bytes for request states (the pool) */
-  uint64_t arena_bytes;  /* per-tick upload area for fused-run ops (default 64 MiB) */
+  uint64_t arena_bytes;  /* per-tick upload area for fused-run ops (0 = 64 MiB, else at least 1 MiB).
+                            A fused run is never cut by the arena: runs are at most as long as fit
+                            an empty arena, and a run that does not fit what a tick has left waits
+                            whole for the next tick (first in line), so results do not depend on
+                            the mix */
   uint32_t max_slots;    /* requests running at once, 1..4096 */
   uint32_t flags;        /* SRV_FLAG_* */
   uint64_t tick_updates; /* cap on one request's fused-run work per tick, in gate-entry updates

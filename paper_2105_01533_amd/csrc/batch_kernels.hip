@@ -11,7 +11,7 @@
 // count, scan, write); measurements (reduce, decide, write).  Items of
 // different states never touch each other's memory, so the families need no
 // ordering among themselves.
-#include "bitslice_tile.h"
+#include "batch_units.h"
 #include "entry_ops.h"
 
 namespace sparsesim {
@@ -21,16 +21,6 @@ using ent::cadd;
 using ent::hash_label;
 using ent::survives;
 
-// Largest i in [0, n) with u0[i] <= u (u0 ascending, u0[0] = 0).
-__device__ __forceinline__ int find_item(const uint32_t* __restrict__ u0, int n, uint32_t u) {
-  int lo = 0, hi = n - 1;
-  while (lo < hi) {
-    const int mid = (lo + hi + 1) >> 1;
-    if (u0[mid] <= u) lo = mid;
-    else hi = mid - 1;
-  }
-  return lo;
-}
 
 using ent::ctrl_ok;
 
@@ -96,10 +86,16 @@ __device__ __forceinline__ uint32_t prefix012(uint32_t e, uint32_t* s_wave, uint
 }
 
 // ---- fused runs: one 2048-entry tile per unit, one wave per block ----------
-__global__ __launch_bounds__(64, 2) void kb_mono(const BTick* __restrict__ hdr, const BItem* __restrict__ items,
-                                              const uint32_t* __restrict__ units) {
-  extern __shared__ uint32_t lds_all[];
-  uint32_t* L = lds_all + threadIdx.x;
+// Bit-sliced runs take the register-plane tile (its planes in v100 and up,
+// which the compiler may not allocate: amdgpu_num_vgpr counts pairs on
+// gfx950, 40 = v0..v79; the clobber makes the kernel's VGPR count cover
+// 131 planes).
+
+// Per-entry fused pass over the tiles of runs the bit-sliced form cannot take
+// (the same tiles as the register-plane kernel; each kernel skips the other's
+// items).
+__global__ __launch_bounds__(64) void kb_mono_entry(const BTick* __restrict__ hdr, const BItem* __restrict__ items,
+                                                    const uint32_t* __restrict__ units) {
   const int n = (int)hdr->n_mono;
   if (n == 0) return;
   const uint32_t* u0 = units + hdr->mono_u0;
@@ -107,43 +103,36 @@ __global__ __launch_bounds__(64, 2) void kb_mono(const BTick* __restrict__ hdr, 
   for (uint32_t u = blockIdx.x; u < total; u += gridDim.x) {
     const int i = find_item(u0, n, u);
     const BItem& it = items[i];
+    if (it.prog) continue;   // kb_mono's
     const uint64_t base = (uint64_t)(u - u0[i]) * kChunk;
     const uint32_t lim = (uint32_t)(it.nnz - base < kChunk ? it.nnz - base : kChunk);
-    if (it.gops) {
-      if (it.run.has_turns)
-        bs::bs_tile<true>(it.in, base, lim, it.gops, it.ngroups, it.run, L);
-      else
-        bs::bs_tile<false>(it.in, base, lim, it.gops, it.ngroups, it.run, L);
-    } else {
-      // Per-entry fused pass over the tile (runs the bit-sliced form cannot take).
-      const bool phase = it.run_flags & kRunPhase, flip = it.run_flags & kRunFlip;
-      for (uint32_t e = threadIdx.x; e < lim; e += 64) {
-        const uint64_t idx = base + e;
-        uint64_t lo = it.in.key_lo[idx], hi = it.wide ? it.in.key_hi[idx] : 0ull;
-        double2 a = make_double2(0.0, 0.0);
-        if (phase) a = it.in.amp[idx];
-        for (uint32_t k = 0; k < it.n_dops; ++k) {
-          const MonoDesc d = it.dops[k];
-          const bool c = (lo & d.ctrl_lo) == d.ctrl_lo && (!it.wide || (hi & d.ctrl_hi) == d.ctrl_hi);
-          const bool thi = it.wide && d.target >= 64;
-          const uint64_t tbit = 1ull << (d.target & 63);
-          const uint64_t w = thi ? hi : lo;
-          if (d.flags & kHasPhase) {
-            const double2 r = ent::cmul(a, ent::sel2((w & tbit) != 0, d.m1, d.m0));
-            a = ent::sel2(c, r, a);
-          }
-          if (d.flags & kFlip) {
-            const uint64_t f = c ? tbit : 0ull;
-            if (thi) hi ^= f;
-            else lo ^= f;
-          }
+    const bool phase = it.run_flags & kRunPhase, flip = it.run_flags & kRunFlip;
+    for (uint32_t e = threadIdx.x; e < lim; e += 64) {
+      const uint64_t idx = base + e;
+      uint64_t lo = it.in.key_lo[idx], hi = it.wide ? it.in.key_hi[idx] : 0ull;
+      double2 a = make_double2(0.0, 0.0);
+      if (phase) a = it.in.amp[idx];
+      for (uint32_t k = 0; k < it.n_dops; ++k) {
+        const MonoDesc d = it.dops[k];
+        const bool c = (lo & d.ctrl_lo) == d.ctrl_lo && (!it.wide || (hi & d.ctrl_hi) == d.ctrl_hi);
+        const bool thi = it.wide && d.target >= 64;
+        const uint64_t tbit = 1ull << (d.target & 63);
+        const uint64_t w = thi ? hi : lo;
+        if (d.flags & kHasPhase) {
+          const double2 r = ent::cmul(a, ent::sel2((w & tbit) != 0, d.m1, d.m0));
+          a = ent::sel2(c, r, a);
         }
-        if (flip) {
-          it.in.key_lo[idx] = lo;
-          if (it.wide) it.in.key_hi[idx] = hi;
+        if (d.flags & kFlip) {
+          const uint64_t f = c ? tbit : 0ull;
+          if (thi) hi ^= f;
+          else lo ^= f;
         }
-        if (phase) it.in.amp[idx] = a;
       }
+      if (flip) {
+        it.in.key_lo[idx] = lo;
+        if (it.wide) it.in.key_hi[idx] = hi;
+      }
+      if (phase) it.in.amp[idx] = a;
     }
   }
 }
@@ -498,8 +487,8 @@ __global__ __launch_bounds__(256) void kb_m_write(const BTick* __restrict__ hdr,
 
 // The whole tick, in order, on fixed grids (capturable).
 void launch_batch_tick(hipStream_t st, const BTick* hdr, const BItem* items, const uint32_t* units, int grid) {
-  const size_t lds = (size_t)kMaxPlanes * 64 * 4;
-  hipLaunchKernelGGL(kb_mono, dim3(grid), dim3(64), lds, st, hdr, items, units);
+  launch_batch_mono_rp(st, hdr, items, units, grid);
+  hipLaunchKernelGGL(kb_mono_entry, dim3(grid), dim3(64), 0, st, hdr, items, units);
   hipLaunchKernelGGL(kb_fill, dim3(grid), dim3(256), 0, st, hdr, items, units);
   hipLaunchKernelGGL(kb_build, dim3(grid), dim3(256), 0, st, hdr, items, units);
   hipLaunchKernelGGL(kb_u2_probe, dim3(grid), dim3(256), 0, st, hdr, items, units);

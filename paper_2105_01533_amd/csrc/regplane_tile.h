@@ -262,7 +262,7 @@ struct Fetch {
 };
 
 // Load chunks 0 and 1 of the program; v89 = 16 x lane.
-__device__ __forceinline__ void fetch_start(Fetch& f, const RpRec* prog, uint32_t nrec) {
+__device__ __forceinline__ void fetch_start(Fetch& f, const RpRec* prog, uint32_t nrec, int lane) {
   f.rs = buf_rsrc_v4(prog, 16u * nrec);
   f.lane = 0;
   f.off = 2048;
@@ -271,7 +271,7 @@ __device__ __forceinline__ void fetch_start(Fetch& f, const RpRec* prog, uint32_
       "buffer_load_dwordx4 v[90:93], v89, %[rs], 0 offen\n\t"
       "v_add_u32 v88, 1024, v89\n\t"
       "buffer_load_dwordx4 v[94:97], v88, %[rs], 0 offen\n\t"
-      "s_waitcnt vmcnt(0)" ::[id] "v"((uint32_t)threadIdx.x),
+      "s_waitcnt vmcnt(0)" ::[id] "v"(lane),
       [rs] "s"(f.rs)
       : "memory");
 }
@@ -323,8 +323,7 @@ __device__ __forceinline__ void omega_general(Fetch& f, uint32_t nquads) {
 // accumulators (C tables side by side), which is what bounds the pass on
 // LDS bandwidth.
 template <bool BARE, int C>
-__device__ __forceinline__ void turn_chunk(Fetch& f, uint64_t* acc, uint64_t* table) {
-  const int lane = threadIdx.x;
+__device__ __forceinline__ void turn_chunk(Fetch& f, uint64_t* acc, uint64_t* table, int lane) {
   uint32_t B[C][8];
 #pragma unroll
   for (int c = 0; c < C; ++c) {
@@ -392,16 +391,16 @@ __device__ __forceinline__ void turn_chunk(Fetch& f, uint64_t* acc, uint64_t* ta
 }
 
 template <bool BARE>
-__device__ __forceinline__ void turn_groups(Fetch& f, uint32_t ng, uint64_t* acc, uint64_t* table) {
+__device__ __forceinline__ void turn_groups(Fetch& f, uint32_t ng, uint64_t* acc, uint64_t* table, int lane) {
   uint32_t g = 0;
-  for (; g + 2 <= ng; g += 2) turn_chunk<BARE, 2>(f, acc, table);
-  if (g < ng) turn_chunk<BARE, 1>(f, acc, table);
+  for (; g + 2 <= ng; g += 2) turn_chunk<BARE, 2>(f, acc, table, lane);
+  if (g < ng) turn_chunk<BARE, 1>(f, acc, table, lane);
 }
 
 // Labels of the tile (word w of each label: bits 32w..32w+31) into planes.
-__device__ __forceinline__ void load_word(const Buf& b, uint64_t base, uint32_t lim, int w) {
+__device__ __forceinline__ void load_word(const Buf& b, uint64_t base, uint32_t lim, int w, int lane) {
   const __amdgpu_buffer_rsrc_t rs = buf_rsrc((w < 2 ? b.key_lo : b.key_hi) + base, 8 * lim);
-  const int off = 8 * (int)threadIdx.x + 4 * (w & 1);
+  const int off = 8 * lane + 4 * (w & 1);
   uint32_t a[32];
 #pragma unroll
   for (int j = 0; j < 32; ++j) a[j] = __builtin_amdgcn_raw_buffer_load_b32(rs, off, 512 * j, 0);
@@ -412,9 +411,9 @@ __device__ __forceinline__ void load_word(const Buf& b, uint64_t base, uint32_t 
   else { RP_IN_WORD3(a) }
 }
 
-__device__ __forceinline__ void store_word(const Buf& b, uint64_t base, uint32_t lim, int w, int nq) {
+__device__ __forceinline__ void store_word(const Buf& b, uint64_t base, uint32_t lim, int w, int nq, int lane) {
   const __amdgpu_buffer_rsrc_t rs = buf_rsrc((w < 2 ? b.key_lo : b.key_hi) + base, 8 * lim);
-  const int off = 8 * (int)threadIdx.x + 4 * (w & 1);
+  const int off = 8 * lane + 4 * (w & 1);
   uint32_t a[32];
   if (w == 0) { RP_OUT_WORD0(a) }
   else if (w == 1) { RP_OUT_WORD1(a) }
@@ -430,25 +429,30 @@ __device__ __forceinline__ void store_word(const Buf& b, uint64_t base, uint32_t
 }
 
 // Apply a run's program (nrec records) to the tile at base (lim valid
-// entries).  acc: the wave's turn accumulators (TURNS only), table: its
-// 16-entry subset-sum table.
+// entries).  TURNS: the kernel provides acc, the wave's turn accumulators in
+// LDS, and table, its subset-sum tables; a run uses them if it has turn ops
+// (the result does not depend on TURNS otherwise).
 template <bool TURNS>
 __device__ __forceinline__ void rp_tile(const Buf& b, uint64_t base, uint32_t lim, const RpRec* prog, uint32_t nrec,
                                         const BsRun& run, uint64_t* acc, uint64_t* table) {
-  const int lane = threadIdx.x;
+  // The lane number, opaque to the optimizer: values derived from it are
+  // formed where used, not kept live across a kernel's loop over tiles.
+  int lane = threadIdx.x;
+  asm volatile("" : "+v"(lane));
   const uint32_t nq = run.n_planes;
+  const bool turns = TURNS && run.has_turns;
   const uint32_t rw = run.words_read | run.words_write;
   Fetch f;
-  fetch_start(f, prog, nrec);
+  fetch_start(f, prog, nrec, lane);
 #pragma unroll
   for (int w = 0; w < 4; ++w)
-    if (rw & (1u << w)) load_word(b, base, lim, w);
+    if (rw & (1u << w)) load_word(b, base, lim, w, lane);
   wr_plane(nq, ~0u);       // all ones
   wr_plane(nq + 2, 0u);    // zero
   asm volatile(
       "v_mov_b32 v80, 0\n\tv_mov_b32 v81, 0\n\tv_mov_b32 v82, 0\n\t"
       "v_mov_b32 v83, 0\n\tv_mov_b32 v84, 0\n\tv_mov_b32 v85, 0");
-  if (TURNS) {
+  if (turns) {
 #pragma unroll
     for (int j = 0; j < 32; ++j) acc[64 * j + lane] = 0;
   }
@@ -461,9 +465,9 @@ __device__ __forceinline__ void rp_tile(const Buf& b, uint64_t base, uint32_t li
     if (shape == kRpOG) {
       omega_general(f, cnt);
     } else if (shape == kRpTB || shape == kRpTG) {
-      if (TURNS) {
-        if (shape == kRpTB) turn_groups<true>(f, cnt, acc, table);
-        else turn_groups<false>(f, cnt, acc, table);
+      if (turns) {
+        if (shape == kRpTB) turn_groups<true>(f, cnt, acc, table, lane);
+        else turn_groups<false>(f, cnt, acc, table, lane);
       } else {
         break;   // the host never sends turn ops to this variant
       }
@@ -475,7 +479,7 @@ __device__ __forceinline__ void rp_tile(const Buf& b, uint64_t base, uint32_t li
   // Labels back to memory (only words some gate flips).
 #pragma unroll
   for (int w = 0; w < 4; ++w)
-    if (run.words_write & (1u << w)) store_word(b, base, lim, w, (int)nq);
+    if (run.words_write & (1u << w)) store_word(b, base, lim, w, (int)nq, lane);
   if (!run.has_phase) return;
   uint32_t P, Q0, Q1, R0, R1, R2;
   asm volatile(
@@ -491,10 +495,10 @@ __device__ __forceinline__ void rp_tile(const Buf& b, uint64_t base, uint32_t li
     const uint32_t qj = ((Q0 >> j) & 1u) | (((Q1 >> j) & 1u) << 1);
     const uint32_t k = (rj + 2u * qj + 4u * ((P >> j) & 1u) + run.g_omega) & 7u;
     double2 f2;
-    if (!TURNS && run.g_turn == 0) {
+    if (!turns && run.g_turn == 0) {
       f2 = omega_pow(k);
     } else {
-      const uint64_t tj = TURNS ? acc[64 * j + lane] : 0ull;
+      const uint64_t tj = turns ? acc[64 * j + lane] : 0ull;
       const uint64_t T = tj + run.g_turn + ((uint64_t)k << 61);
       double sn, cs;
       sincospi((double)(T >> 11) * 0x1p-52, &sn, &cs);   // angle = 2 pi T / 2^64

@@ -45,6 +45,7 @@ int sfail(int code, const std::string& msg) {
   } while (0)
 
 constexpr size_t kA = 256;
+constexpr uint64_t kMinArena = 1ull << 20;   // smallest per-tick op arena
 size_t al(size_t x) { return (x + kA - 1) / kA * kA; }
 
 uint64_t pow2_at_least(uint64_t x) {
@@ -162,6 +163,7 @@ struct Request {
   // progress
   size_t i = 0;
   size_t mono_seen = 0;
+  bool deferred = false;              // its last fused run did not fit the tick's arena
   SegKind seg = SEG_NONE;
   sim_stats st{};
   std::vector<int32_t> outcomes;
@@ -214,9 +216,21 @@ int capture_tick(srv_t* s) {
 
 // Next segment of r, consuming skipped branching gates; sets r.seg and the
 // run [begin, begin + len) of MONO ordinals or the op index of the gate.
+// Longest fused run whose ops always fit an empty arena (records of the
+// register-plane program or per-entry descriptors, worst case): a run is cut
+// there whatever else shares the tick, so a request's runs -- and with them
+// its rounding -- are the same alone and in any mix.
+uint64_t arena_run_cap(const srv_t* s, const Request& r) {
+  const uint64_t recs = s->cfg.arena_bytes / sizeof(RpRec);
+  const uint64_t by_prog = recs > 16 + 8ull * r.cfg.n_qubits ? (recs - 16 - 8ull * r.cfg.n_qubits) / (8 * 2 * 3) : 1;
+  const uint64_t by_desc = s->cfg.arena_bytes / sizeof(MonoDesc);
+  return std::max<uint64_t>(1, std::min(by_prog, by_desc));
+}
+
 SegKind next_segment(srv_t* s, Request& r, size_t* begin, size_t* len, size_t* op) {
   uint64_t fuse_max = r.cfg.fuse_max ? r.cfg.fuse_max : 65536u;
   if (s->cfg.tick_updates) fuse_max = std::min<uint64_t>(fuse_max, std::max<uint64_t>(1, s->cfg.tick_updates / std::max<uint64_t>(r.nnz, 1)));
+  fuse_max = std::min<uint64_t>(fuse_max, arena_run_cap(s, r));
   size_t run_len = 0, run_begin = r.mono_seen;
   const size_t n = r.gates.size();
   while (r.i < n) {
@@ -282,7 +296,6 @@ void compile_request(Request& r) {
       r.rc.descs.push_back(mono_desc(r.gates[i]));
       r.mono_op.push_back(i);
     }
-  r.rc.pair_window = 64;   // grouping happens on the tick's critical path
   if (r.cfg.mono_mode != SIM_MONO_DIRECT) r.rc.compile(r.cfg.n_qubits);
   else r.rc.n_qubits = r.cfg.n_qubits;
   r.compiled = true;
@@ -351,6 +364,8 @@ int srv_create(const srv_config* cfg, void* stream, void* pool, size_t pool_byte
   *out = nullptr;
   if (cfg->max_slots < 1 || cfg->max_slots > 4096) return sfail(SIM_E_ARG, "max_slots must be in 1..4096");
   if (cfg->budget_bytes < kA) return sfail(SIM_E_ARG, "budget_bytes too small");
+  if (cfg->arena_bytes && cfg->arena_bytes < kMinArena)
+    return sfail(SIM_E_ARG, "arena_bytes must be 0 (default 64 MiB) or at least 1 MiB");
   std::unique_ptr<srv_t> s(new srv_t());
   s->cfg = *cfg;
   if (!s->cfg.arena_bytes) s->cfg.arena_bytes = 64ull << 20;
@@ -464,11 +479,14 @@ int srv_tick(srv_t* s, uint32_t* running, uint32_t* queued) {
     size_t b = 0, len = 0, op = 0;
     bool bsl = false;
     BsRun br{};
-    std::vector<BsGroup> grp;
+    std::vector<RpRec> prog;
   };
   std::vector<Seg> segs;
   segs.reserve(s->running.size());
   std::vector<size_t> to_group;
+  // Requests whose fused run was deferred last tick (the arena was full) go
+  // first, so that none waits more than one tick for arena space.
+  std::stable_partition(s->running.begin(), s->running.end(), [](const Request* r) { return r->deferred; });
   for (Request* r : s->running) {
     Seg sg{r, SEG_NONE};
     sg.k = next_segment(s, *r, &sg.b, &sg.len, &sg.op);
@@ -487,7 +505,7 @@ int srv_tick(srv_t* s, uint32_t* running, uint32_t* queued) {
     const auto t_g = std::chrono::steady_clock::now();
     HostPool::get().run(to_group.size(), [&](size_t t) {
       Seg& sg = segs[to_group[t]];
-      sg.r->rc.group(sg.b, sg.len, sg.grp, &sg.br);
+      sg.r->rc.schedule(sg.b, sg.len, sg.prog, &sg.br);
     });
     s->stats.group_ms += ms_since(t_g);
   }
@@ -496,7 +514,6 @@ int srv_tick(srv_t* s, uint32_t* running, uint32_t* queued) {
     const SegKind k = sg.k;
     size_t b = sg.b, len = sg.len;
     const size_t op = sg.op;
-    std::vector<BsGroup>& grp = sg.grp;
     BItem it{};
     it.in = r->buf[r->cur];
     it.out = r->buf[r->cur ^ 1];
@@ -506,7 +523,6 @@ int srv_tick(srv_t* s, uint32_t* running, uint32_t* queued) {
     it.nnz = r->nnz;
     it.cap = r->cfg.capacity;
     if (k == SEG_MONO) {
-      BsRun br = sg.br;
       const bool bsl = sg.bsl;
       uint32_t flags = 0;
       for (size_t q = b; q < b + len; ++q) {
@@ -514,41 +530,26 @@ int srv_tick(srv_t* s, uint32_t* running, uint32_t* queued) {
         if (r->rc.descs[q].flags & kFlip) flags |= kRunFlip;
       }
       it.run_flags = flags;
-      // Ops of the run; if they do not fit the rest of the work list, keep a
-      // shorter prefix of the run (possibly none) for this tick.
-      size_t bytes = 0, keep = len;
-      for (;;) {
-        if (bsl) {
-          if (keep < len) {   // the whole run did not fit: regroup a prefix
-            grp.clear();
-            const auto t_g = std::chrono::steady_clock::now();
-            r->rc.run_params(b, keep, r->cfg.mono_mode, 1, &br);
-            r->rc.group(b, keep, grp, &br);
-            s->stats.group_ms += ms_since(t_g);
-          }
-          bytes = grp.size() * sizeof(BsGroup);
-        } else {
-          bytes = keep * sizeof(MonoDesc);
-        }
-        if (keep == 0 || arena_used + al(bytes) <= s->cfg.arena_bytes) break;
-        keep /= 2;
-      }
-      if (keep < len) {
-        // Give back ops from MONO ordinal b + keep on: they are re-read next
-        // tick (skip decisions there depend only on nnz, which this run keeps).
-        const size_t back_to = r->mono_op[b + keep];
+      // The run's ops go into the tick's arena.  A run that does not fit what
+      // is left is deferred whole to the next tick (never cut: that would
+      // change its rounding); every run fits an empty arena (arena_run_cap).
+      const size_t bytes = bsl ? sg.prog.size() * sizeof(RpRec) : len * sizeof(MonoDesc);
+      r->deferred = arena_used + al(bytes) > s->cfg.arena_bytes;
+      if (r->deferred) {
+        // Give back the run's ops: they are re-read next tick (skip decisions
+        // there depend only on nnz, which is unchanged).
+        const size_t back_to = r->mono_op[b];
         for (size_t q = back_to; q < r->i; ++q)
           if (r->gates[q].op == SIM_OP_U2) r->st.u2_skipped--;
         r->i = back_to;
-        r->mono_seen = b + keep;
-        len = keep;
+        r->mono_seen = b;
+        continue;
       }
-      if (len == 0) continue;
       if (bsl) {
-        std::memcpy(arena + arena_used, grp.data(), bytes);
-        it.gops = reinterpret_cast<const BsGroup*>(s->d_tick + s->arena_off + arena_used);
-        it.ngroups = (uint32_t)grp.size();
-        it.run = br;
+        std::memcpy(arena + arena_used, sg.prog.data(), bytes);
+        it.prog = reinterpret_cast<const RpRec*>(s->d_tick + s->arena_off + arena_used);
+        it.nrec = (uint32_t)sg.prog.size();
+        it.run = sg.br;
         s->stats.bitslice_runs++;
       } else {
         std::memcpy(arena + arena_used, r->rc.descs.data() + b, bytes);

@@ -216,8 +216,8 @@ struct BItem {
   uint64_t nnz;                // entries at input (exact)
   uint64_t cap;                // capacity of the state
   // fused run
-  const BsGroup* gops;         // bit-sliced groups (gops != null) ...
-  uint32_t ngroups, n_dops;
+  const RpRec* prog;           // register-plane program (prog != null) ...
+  uint32_t nrec, n_dops;
   const MonoDesc* dops;        // ... or per-entry descriptors
   BsRun run;
   uint32_t run_flags, pad0;
@@ -244,6 +244,8 @@ struct BTick {
 };
 
 void launch_batch_tick(hipStream_t st, const BTick* hdr, const BItem* items, const uint32_t* units, int grid);
+// The tick's register-plane fused runs (first step of launch_batch_tick).
+void launch_batch_mono_rp(hipStream_t st, const BTick* hdr, const BItem* items, const uint32_t* units, int grid);
 
 // ---- launchers (sim_kernels.hip) -------------------------------------------
 void launch_set_basis(hipStream_t st, Buf b, uint64_t* nnz, uint64_t lo, uint64_t hi);

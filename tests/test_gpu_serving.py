@@ -47,8 +47,8 @@ def mix():
     return ws
 
 
-def run_server(S, ws, budget=1 << 30, slots=64, graph=True, **tuning):
-    srv = S.Server(budget, max_slots=slots, graph=graph)
+def run_server(S, ws, budget=1 << 30, slots=64, graph=True, arena_bytes=0, **tuning):
+    srv = S.Server(budget, max_slots=slots, graph=graph, arena_bytes=arena_bytes)
     ids = [srv.submit_workload(w, **tuning) for w in ws]
     srv.run()
     out = []
@@ -155,3 +155,25 @@ def test_failures_stay_in_their_request(S):
     for p, q in zip(a[:4], b[:4]):
         assert p.tobytes() == q.tobytes()
     srv.close()
+
+
+def test_small_arena_defers_runs_alone_equals_mix(S):
+    """With a 1 MiB op arena the mix's fused runs cannot all share a tick:
+    runs that do not fit wait whole for the next tick (they are never cut,
+    which would change their rounding), so every result is still bitwise the
+    same alone and in the mix, and matches the oracle."""
+    ws = [W.config0(51 + k, n=24, h_qubits=8, gates=20000, cap=1 << 12) for k in range(6)]
+    together, stats = run_server(S, ws, arena_bytes=1 << 20)
+    assert stats["completed"] == len(ws)
+    for w, res in zip(ws, together):
+        alone, _ = run_server(S, [w], arena_bytes=1 << 20)
+        for a, b in zip(alone[0][:4], res[:4]):
+            assert a.tobytes() == b.tobytes(), w.name
+        o, oout, _ = oracle_run(w)
+        assert list(res[3]) == list(oout), w.name
+        assert_same_state(res[:3], o.export(), what=w.name)
+
+
+def test_arena_too_small_is_rejected(S):
+    with pytest.raises(S.ServerError):
+        S.Server(1 << 24, max_slots=4, arena_bytes=1 << 16)
