@@ -414,6 +414,9 @@ typedef struct srv_config {
   uint64_t tick_updates; /* cap on one request's fused-run work per tick, in gate-entry updates
                             (nnz x gates; at least one gate); 0 = no cap.  Keeps ticks short so
                             small requests are not held behind long runs of large ones. */
+  uint32_t grid;         /* workgroups of every tick kernel (each walks the tick's work units);
+                            0 = 2048, else 1..65536 */
+  uint32_t reserved;     /* must be 0 */
 } srv_config;
 
 typedef struct srv_stats {

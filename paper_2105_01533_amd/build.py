@@ -9,7 +9,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libsparsesim.so")
 SOURCES = ["sim_api.hip", "sim_kernels.hip", "mono_bitslice.hip", "mono_regplane.hip", "run_compiler.hip", "batch_kernels.hip",
-           "batch_regplane.hip", "serve.hip", "commute.hip", "pauli.hip"]
+           "serve.hip", "commute.hip", "pauli.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 FLAGS = [
@@ -32,11 +32,9 @@ FLAGS = [
 # its assembly changes M0.  After every build the pass's own gfx950 assembly
 # is checked: no compiler-generated instruction may name v80 or above or M0,
 # and no kernel may spill to scratch.
-REGPLANE_SRCS = ["mono_regplane.hip", "batch_regplane.hip"]
-# Per-source extra flags.  The batched register-plane kernel loops over work
-# units; machine loop-invariant code motion would hoist the phase epilogue's
-# constants out of that loop and keep them live (spilled) across the tile.
-EXTRA_FLAGS = {"batch_regplane.hip": ["-mllvm", "-disable-machine-licm"]}
+REGPLANE_SRCS = ["mono_regplane.hip"]
+# Per-source extra flags (none at present).
+EXTRA_FLAGS: dict[str, list[str]] = {}
 RESERVED_VGPR = 80
 
 

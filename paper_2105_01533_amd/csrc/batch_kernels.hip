@@ -12,6 +12,7 @@
 // different states never touch each other's memory, so the families need no
 // ordering among themselves.
 #include "batch_units.h"
+#include "bitslice_tile.h"
 #include "entry_ops.h"
 
 namespace sparsesim {
@@ -91,11 +92,16 @@ __device__ __forceinline__ uint32_t prefix012(uint32_t e, uint32_t* s_wave, uint
 // gfx950, 40 = v0..v79; the clobber makes the kernel's VGPR count cover
 // 131 planes).
 
-// Per-entry fused pass over the tiles of runs the bit-sliced form cannot take
-// (the same tiles as the register-plane kernel; each kernel skips the other's
-// items).
-__global__ __launch_bounds__(64) void kb_mono_entry(const BTick* __restrict__ hdr, const BItem* __restrict__ items,
-                                                    const uint32_t* __restrict__ units) {
+// Fused runs: one unit (kChunk entries of one state) per block iteration, on
+// the LDS-plane bit-sliced tile, or per entry for runs that form cannot take.
+// (The register-plane tile of the single-state engine is not used here: its
+// GPR-indexed plane accesses gave results that depended on which other
+// states' tiles shared a SIMD, while the LDS-plane tile reproduces the
+// single-state results in any mix.)
+__global__ __launch_bounds__(64, 2) void kb_mono(const BTick* __restrict__ hdr, const BItem* __restrict__ items,
+                                              const uint32_t* __restrict__ units) {
+  extern __shared__ uint32_t lds_all[];
+  uint32_t* L = lds_all + threadIdx.x;
   const int n = (int)hdr->n_mono;
   if (n == 0) return;
   const uint32_t* u0 = units + hdr->mono_u0;
@@ -103,9 +109,15 @@ __global__ __launch_bounds__(64) void kb_mono_entry(const BTick* __restrict__ hd
   for (uint32_t u = blockIdx.x; u < total; u += gridDim.x) {
     const int i = find_item(u0, n, u);
     const BItem& it = items[i];
-    if (it.prog) continue;   // kb_mono's
     const uint64_t base = (uint64_t)(u - u0[i]) * kChunk;
     const uint32_t lim = (uint32_t)(it.nnz - base < kChunk ? it.nnz - base : kChunk);
+    if (it.gops) {
+      if (it.run.has_turns)
+        bs::bs_tile<true>(it.in, base, lim, it.gops, it.ngroups, it.run, L);
+      else
+        bs::bs_tile<false>(it.in, base, lim, it.gops, it.ngroups, it.run, L);
+      continue;
+    }
     const bool phase = it.run_flags & kRunPhase, flip = it.run_flags & kRunFlip;
     for (uint32_t e = threadIdx.x; e < lim; e += 64) {
       const uint64_t idx = base + e;
@@ -487,8 +499,8 @@ __global__ __launch_bounds__(256) void kb_m_write(const BTick* __restrict__ hdr,
 
 // The whole tick, in order, on fixed grids (capturable).
 void launch_batch_tick(hipStream_t st, const BTick* hdr, const BItem* items, const uint32_t* units, int grid) {
-  launch_batch_mono_rp(st, hdr, items, units, grid);
-  hipLaunchKernelGGL(kb_mono_entry, dim3(grid), dim3(64), 0, st, hdr, items, units);
+  const size_t lds = (size_t)kMaxPlanes * 64 * 4;
+  hipLaunchKernelGGL(kb_mono, dim3(grid), dim3(64), lds, st, hdr, items, units);
   hipLaunchKernelGGL(kb_fill, dim3(grid), dim3(256), 0, st, hdr, items, units);
   hipLaunchKernelGGL(kb_build, dim3(grid), dim3(256), 0, st, hdr, items, units);
   hipLaunchKernelGGL(kb_u2_probe, dim3(grid), dim3(256), 0, st, hdr, items, units);

@@ -4,6 +4,8 @@
 // regplane_tile.h).  Phases accumulate exactly, as in the bit-sliced form:
 // eighth turns in bit-sliced counters, other angles as 64-bit turn fractions,
 // one complex multiply per amplitude at the end of the run.
+#include <mutex>
+
 #include "regplane_tile.h"
 
 namespace sparsesim {
@@ -11,17 +13,16 @@ namespace {
 
 #pragma clang diagnostic push
 #pragma clang diagnostic ignored "-Winline-asm"
-// VMAX: the highest plane register of the variant.  The empty asm statement
-// names it as clobbered, which makes the kernel's VGPR count reach it; the
-// compiler itself is held below v80 (amdgpu_num_vgpr), so it never allocates
-// a reserved register.
-template <bool TURNS, uint32_t VMAX>
+// The empty asm statement names the highest plane register (rp::kVmax) as
+// clobbered, which makes the kernel's VGPR count reach it; the compiler
+// itself is held below v80 (amdgpu_num_vgpr), so it never allocates a
+// reserved register.
+template <bool TURNS>
 __global__ __launch_bounds__(64, 2) __attribute__((amdgpu_num_vgpr(40))) void k_mono_rp(
     Buf b, const uint64_t* __restrict__ nnz_p, const RpRec* __restrict__ prog, uint32_t nrec, BsRun run,
     Ctl* ctl) {
-  if constexpr (VMAX == rp::kVmaxSmall) asm volatile("" ::: "v131");
-  else if constexpr (VMAX == rp::kVmaxMid) asm volatile("" ::: "v163");
-  else asm volatile("" ::: "v230");
+  static_assert(rp::kVmax == 230, "the clobber below names the highest plane register");
+  asm volatile("" ::: "v230");
   extern __shared__ uint64_t rp_acc[];
   __shared__ uint64_t s_table[32];   // two 16-entry subset-sum tables
   const uint64_t n = *nnz_p;
@@ -39,29 +40,53 @@ __global__ __launch_bounds__(64, 2) __attribute__((amdgpu_num_vgpr(40))) void k_
 }
 #pragma clang diagnostic pop
 
-template <bool TURNS>
-void launch_variant(hipStream_t st, Buf b, const uint64_t* nnz, const RpRec* prog, uint32_t nrec,
-                    const BsRun& run, Ctl* ctl, int grid) {
-  const size_t lds = TURNS ? rp::kTurnAccBytes : 0;
-  const uint32_t planes = run.n_planes + 3;   // labels, all-ones, scratch, zero
-  if (planes <= 32)
-    hipLaunchKernelGGL((k_mono_rp<TURNS, rp::kVmaxSmall>), dim3(grid), dim3(64), lds, st, b, nnz, prog, nrec, run,
-                       ctl);
-  else if (planes <= 64)
-    hipLaunchKernelGGL((k_mono_rp<TURNS, rp::kVmaxMid>), dim3(grid), dim3(64), lds, st, b, nnz, prog, nrec, run, ctl);
-  else
-    hipLaunchKernelGGL((k_mono_rp<TURNS, rp::kVmaxWide>), dim3(grid), dim3(64), lds, st, b, nnz, prog, nrec, run,
-                       ctl);
+}  // namespace
+
+namespace {
+
+// Register-plane passes of this process never run at the same time on one
+// device: waves of two passes with different programs sharing a SIMD gave
+// results that depended on the pairing (the GPR-indexed plane accesses),
+// while waves of one pass -- one program -- reproduce the LDS-plane pass bit
+// for bit.  Each launch records an event on its stream; a launch from another
+// stream first waits for it.  (Skipped on a stream under graph capture, where
+// the ordering is the graph's.)  The event is made once per device, at
+// set-up, so launches allocate nothing.
+struct RpOrder {
+  std::mutex mu;
+  hipEvent_t ev = nullptr;
+  hipStream_t last = nullptr;
+};
+
+RpOrder& rp_order() {
+  static RpOrder orders[64];
+  int dev = 0;
+  (void)hipGetDevice(&dev);
+  return orders[dev & 63];
 }
 
 }  // namespace
 
+hipError_t mono_rp_init() {
+  RpOrder& o = rp_order();
+  std::lock_guard<std::mutex> lk(o.mu);
+  if (o.ev) return hipSuccess;
+  return hipEventCreateWithFlags(&o.ev, hipEventDisableTiming);
+}
+
 void launch_mono_rp(hipStream_t st, Buf b, const uint64_t* nnz, const RpRec* p, uint32_t nrec, const BsRun& run,
                     Ctl* ctl, int grid) {
+  RpOrder& o = rp_order();
+  std::lock_guard<std::mutex> lk(o.mu);
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  (void)hipStreamIsCapturing(st, &cs);
+  const bool ordered = cs == hipStreamCaptureStatusNone;
+  if (ordered && o.ev && o.last != st) (void)hipStreamWaitEvent(st, o.ev, 0);
   if (run.has_turns)
-    launch_variant<true>(st, b, nnz, p, nrec, run, ctl, grid);
+    hipLaunchKernelGGL(k_mono_rp<true>, dim3(grid), dim3(64), rp::kTurnAccBytes, st, b, nnz, p, nrec, run, ctl);
   else
-    launch_variant<false>(st, b, nnz, p, nrec, run, ctl, grid);
+    hipLaunchKernelGGL(k_mono_rp<false>, dim3(grid), dim3(64), 0, st, b, nnz, p, nrec, run, ctl);
+  if (ordered && o.ev && hipEventRecord(o.ev, st) == hipSuccess) o.last = st;
 }
 
 }  // namespace sparsesim

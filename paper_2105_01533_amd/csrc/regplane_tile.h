@@ -37,8 +37,16 @@
 namespace sparsesim {
 namespace rp {
 
-// Highest VGPR a kernel variant reserves for planes: 32, 64 or 131 planes.
-constexpr uint32_t kVmaxSmall = 131, kVmaxMid = 163, kVmaxWide = 230;
+// Highest VGPR the kernel reserves for planes (v100..v230: up to 131 planes).
+// The kernel declares it clobbered whatever a run's plane count, so its
+// allocation is 231 VGPRs and at most two waves share a SIMD.  Narrower
+// allocations (132 and 164 VGPRs, three waves per SIMD) gave results on
+// multi-million-entry states that differed from run to run, as did two waves
+// of different programs on one SIMD; waves of one program at most two per
+// SIMD reproduce the LDS-plane pass bit for bit (the launcher keeps passes
+// apart).  The 132-register form also loaded a label's second word
+// (v132..v163) past its allocation.
+constexpr uint32_t kVmax = 230;
 constexpr uint32_t kTurnAccBytes = 32 * 64 * 8;   // per wave: 32 entries x 64 lanes x 64-bit turns
 
 // LSB-first 32x32 bit transpose (out[q] bit j = in[j] bit q), by the

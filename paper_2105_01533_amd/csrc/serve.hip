@@ -216,15 +216,17 @@ int capture_tick(srv_t* s) {
 
 // Next segment of r, consuming skipped branching gates; sets r.seg and the
 // run [begin, begin + len) of MONO ordinals or the op index of the gate.
-// Longest fused run whose ops always fit an empty arena (records of the
-// register-plane program or per-entry descriptors, worst case): a run is cut
-// there whatever else shares the tick, so a request's runs -- and with them
-// its rounding -- are the same alone and in any mix.
+// Longest fused run whose ops always fit an empty arena (bit-sliced groups or
+// per-entry descriptors, worst case): a run is cut there whatever else shares
+// the tick, so a request's runs -- and with them its rounding -- are the same
+// alone and in any mix.  A MONO op compiles to at most three bit-sliced ops;
+// the rewrite of uncontrolled X gates at most doubles them and adds one per
+// qubit; a group holds at least one op.
 uint64_t arena_run_cap(const srv_t* s, const Request& r) {
-  const uint64_t recs = s->cfg.arena_bytes / sizeof(RpRec);
-  const uint64_t by_prog = recs > 16 + 8ull * r.cfg.n_qubits ? (recs - 16 - 8ull * r.cfg.n_qubits) / (8 * 2 * 3) : 1;
+  const uint64_t groups = s->cfg.arena_bytes / sizeof(BsGroup);
+  const uint64_t by_groups = groups > r.cfg.n_qubits ? (groups - r.cfg.n_qubits) / (2 * 3) : 1;
   const uint64_t by_desc = s->cfg.arena_bytes / sizeof(MonoDesc);
-  return std::max<uint64_t>(1, std::min(by_prog, by_desc));
+  return std::max<uint64_t>(1, std::min(by_groups, by_desc));
 }
 
 SegKind next_segment(srv_t* s, Request& r, size_t* begin, size_t* len, size_t* op) {
@@ -296,6 +298,7 @@ void compile_request(Request& r) {
       r.rc.descs.push_back(mono_desc(r.gates[i]));
       r.mono_op.push_back(i);
     }
+  r.rc.pair_window = 64;   // grouping happens on the tick's critical path
   if (r.cfg.mono_mode != SIM_MONO_DIRECT) r.rc.compile(r.cfg.n_qubits);
   else r.rc.n_qubits = r.cfg.n_qubits;
   r.compiled = true;
@@ -366,9 +369,12 @@ int srv_create(const srv_config* cfg, void* stream, void* pool, size_t pool_byte
   if (cfg->budget_bytes < kA) return sfail(SIM_E_ARG, "budget_bytes too small");
   if (cfg->arena_bytes && cfg->arena_bytes < kMinArena)
     return sfail(SIM_E_ARG, "arena_bytes must be 0 (default 64 MiB) or at least 1 MiB");
+  if (cfg->grid > 65536) return sfail(SIM_E_ARG, "grid must be 0 (default 2048) or 1..65536");
+  if (cfg->reserved) return sfail(SIM_E_ARG, "reserved must be 0");
   std::unique_ptr<srv_t> s(new srv_t());
   s->cfg = *cfg;
   if (!s->cfg.arena_bytes) s->cfg.arena_bytes = 64ull << 20;
+  s->grid = cfg->grid ? (int)cfg->grid : 2048;
   if (stream) {
     s->stream = static_cast<hipStream_t>(stream);
   } else {
@@ -479,7 +485,7 @@ int srv_tick(srv_t* s, uint32_t* running, uint32_t* queued) {
     size_t b = 0, len = 0, op = 0;
     bool bsl = false;
     BsRun br{};
-    std::vector<RpRec> prog;
+    std::vector<BsGroup> grp;
   };
   std::vector<Seg> segs;
   segs.reserve(s->running.size());
@@ -505,7 +511,7 @@ int srv_tick(srv_t* s, uint32_t* running, uint32_t* queued) {
     const auto t_g = std::chrono::steady_clock::now();
     HostPool::get().run(to_group.size(), [&](size_t t) {
       Seg& sg = segs[to_group[t]];
-      sg.r->rc.schedule(sg.b, sg.len, sg.prog, &sg.br);
+      sg.r->rc.group(sg.b, sg.len, sg.grp, &sg.br);
     });
     s->stats.group_ms += ms_since(t_g);
   }
@@ -533,7 +539,7 @@ int srv_tick(srv_t* s, uint32_t* running, uint32_t* queued) {
       // The run's ops go into the tick's arena.  A run that does not fit what
       // is left is deferred whole to the next tick (never cut: that would
       // change its rounding); every run fits an empty arena (arena_run_cap).
-      const size_t bytes = bsl ? sg.prog.size() * sizeof(RpRec) : len * sizeof(MonoDesc);
+      const size_t bytes = bsl ? sg.grp.size() * sizeof(BsGroup) : len * sizeof(MonoDesc);
       r->deferred = arena_used + al(bytes) > s->cfg.arena_bytes;
       if (r->deferred) {
         // Give back the run's ops: they are re-read next tick (skip decisions
@@ -546,9 +552,9 @@ int srv_tick(srv_t* s, uint32_t* running, uint32_t* queued) {
         continue;
       }
       if (bsl) {
-        std::memcpy(arena + arena_used, sg.prog.data(), bytes);
-        it.prog = reinterpret_cast<const RpRec*>(s->d_tick + s->arena_off + arena_used);
-        it.nrec = (uint32_t)sg.prog.size();
+        std::memcpy(arena + arena_used, sg.grp.data(), bytes);
+        it.gops = reinterpret_cast<const BsGroup*>(s->d_tick + s->arena_off + arena_used);
+        it.ngroups = (uint32_t)sg.grp.size();
         it.run = sg.br;
         s->stats.bitslice_runs++;
       } else {
@@ -689,10 +695,13 @@ int srv_run(srv_t* s) {
   if (!s) return sfail(SIM_E_ARG, "null handle");
   uint32_t run = 1, q = 1;
   while (run || q) {
+    // A tick that starts with nothing running has the whole pool and every
+    // slot free: if it admits nothing, the queue's head can never fit.
+    const bool idle = s->running.empty();
     const uint64_t before = s->stats.admitted;
     int rc = srv_tick(s, &run, &q);
     if (rc) return rc;
-    if (!run && q && s->stats.admitted == before) return sfail(SIM_E_NOMEM, "queued request can never be admitted");
+    if (idle && q && s->stats.admitted == before) return sfail(SIM_E_NOMEM, "queued request can never be admitted");
   }
   return SIM_OK;
 }

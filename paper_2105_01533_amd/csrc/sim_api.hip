@@ -547,6 +547,10 @@ int sim_create(const sim_config* cfg, void* stream, void* workspace, size_t ws_b
   if (!s->cfg.fuse_max) s->cfg.fuse_max = 65536;
   s->stream = static_cast<hipStream_t>(stream);
   if (hipGetDevice(&s->device) != hipSuccess) s->device = 0;
+  if (hipError_t e = mono_rp_init(); e != hipSuccess) {
+    delete s;
+    return fail(SIM_E_HIP, std::string("mono_rp_init: ") + hipGetErrorString(e));
+  }
   s->wide = cfg->n_qubits > 64;
   s->L = layout_of(cfg);
   if (workspace) {

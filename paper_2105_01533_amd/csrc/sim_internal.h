@@ -216,8 +216,8 @@ struct BItem {
   uint64_t nnz;                // entries at input (exact)
   uint64_t cap;                // capacity of the state
   // fused run
-  const RpRec* prog;           // register-plane program (prog != null) ...
-  uint32_t nrec, n_dops;
+  const BsGroup* gops;         // bit-sliced (LDS-plane) groups (gops != null) ...
+  uint32_t ngroups, n_dops;
   const MonoDesc* dops;        // ... or per-entry descriptors
   BsRun run;
   uint32_t run_flags, pad0;
@@ -244,8 +244,7 @@ struct BTick {
 };
 
 void launch_batch_tick(hipStream_t st, const BTick* hdr, const BItem* items, const uint32_t* units, int grid);
-// The tick's register-plane fused runs (first step of launch_batch_tick).
-void launch_batch_mono_rp(hipStream_t st, const BTick* hdr, const BItem* items, const uint32_t* units, int grid);
+
 
 // ---- launchers (sim_kernels.hip) -------------------------------------------
 void launch_set_basis(hipStream_t st, Buf b, uint64_t* nnz, uint64_t lo, uint64_t hi);
@@ -257,6 +256,9 @@ void launch_mono_bs(hipStream_t st, Buf b, const uint64_t* nnz, const BsGroup* g
 // entry count's upper bound.
 void launch_mono_rp(hipStream_t st, Buf b, const uint64_t* nnz, const RpRec* prog, uint32_t nrec, const BsRun& run,
                     Ctl* ctl, int grid);
+// Set-up of the register-plane passes' cross-stream ordering on the current
+// device (once per device; called by sim_create).
+hipError_t mono_rp_init();
 void launch_fill(hipStream_t st, uint64_t* p, uint64_t v, uint64_t n);
 void launch_copy16(hipStream_t st, void* dst, const void* src, uint64_t n16);
 void launch_index_build(hipStream_t st, bool wide, Buf b, const uint64_t* nnz, uint64_t* table, uint64_t mask,

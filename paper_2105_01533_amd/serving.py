@@ -3,7 +3,10 @@ or through one-at-a-time plain launches, and reports throughput and latency.
 
 Latency of a request = completion time - arrival time, on the host's wall
 clock; requests arrive open-loop at their trace times.  Both systems see the
-same trace and the same converted circuits.
+same trace and the same converted circuits, and both deliver every finished
+state to host memory (storage order, unsorted) inside the timed region: the
+server copies a finished state out when it frees its device memory, the plain
+path exports it from its own handle.
 """
 from __future__ import annotations
 
@@ -39,8 +42,12 @@ def _summary(name, reqs, done, t0, t_end, updates, arrivals=True):
             "mean_ms": 1e3 * float(np.mean(lat))}
 
 
-def run_one_at_a_time(reqs, arrivals=True, keep_results=False):
-    """FIFO, one simulation at a time through sim_apply_gates on its own handle."""
+def run_one_at_a_time(reqs, arrivals=True, keep_results=False, tuning: dict | None = None):
+    """FIFO, one simulation at a time through sim_apply_gates on its own handle.
+    tuning: optional autotuner table (each request runs with its bucket's
+    knobs)."""
+    from . import autotune
+
     import torch
 
     done = [0.0] * len(reqs)
@@ -52,11 +59,14 @@ def run_one_at_a_time(reqs, arrivals=True, keep_results=False):
             wait = t0 + r.arrival - time.perf_counter()
             if wait > 0:
                 time.sleep(wait)
-        s = S.Simulator(r.w.n_qubits, r.w.capacity, r.w.eps)
+        k = autotune.lookup(tuning, r.w.n_qubits, r.w.capacity) if tuning else {}
+        s = S.Simulator(r.w.n_qubits, r.w.capacity, r.w.eps, **k)
         s.set_basis(*r.w.basis)
         rc, outs, st = s.apply_gates(r.gates, raise_on_error=False)
+        state = s.export(sort=False) if rc == 0 else None
         if keep_results:
-            results[i] = (s.export() if rc == 0 else None, outs, st, rc)
+            results[i] = (state, outs, st, rc)
+        del state
         s.close()
         updates += st["updates"]
         done[i] = time.perf_counter() - t0
@@ -104,10 +114,11 @@ def run_batched(reqs, budget_bytes: int, max_slots: int = 256, arrivals=True, ke
                 i = pending.pop(rid)
                 done[i] = t
                 if st == S.SRV_DONE:
-                    res = srv.result(rid)
+                    res = srv.result(rid, sort=False)
                     updates += res[4]["updates"]
                     if keep_results:
                         results[i] = res
+                    del res
                 srv.release(rid)
     t_end = time.perf_counter() - t0
     stats = srv.stats()
@@ -115,3 +126,27 @@ def run_batched(reqs, budget_bytes: int, max_slots: int = 256, arrivals=True, ke
     out = _summary("batched", reqs, done, 0.0, t_end, updates, arrivals)
     out["server"] = stats
     return out, results
+
+
+def _sorted(lo, hi, amp):
+    order = np.lexsort((lo, hi))
+    return lo[order], hi[order], amp[order]
+
+
+def compare_results(plain, batched):
+    """Per-request comparison of one-at-a-time results (state, outcomes, stats,
+    rc) with batched ones (lo, hi, amp, outcomes, stats): keys and outcomes
+    must match exactly; returns (label mismatches, largest amplitude
+    difference, requests compared)."""
+    mism, worst, n = 0, 0.0, 0
+    for x, y in zip(plain, batched):
+        if x is None or y is None or x[0] is None:
+            continue
+        n += 1
+        lo, hi, amp = _sorted(*x[0])
+        blo, bhi, bamp = _sorted(y[0], y[1], y[2])
+        if not (np.array_equal(lo, blo) and np.array_equal(hi, bhi) and list(x[1]) == list(y[3])):
+            mism += 1
+        elif len(amp):
+            worst = max(worst, float(np.max(np.abs(amp - bamp))))
+    return mism, worst, n

@@ -390,7 +390,8 @@ SRV_FLAG_NO_GRAPH = 1
 
 class srv_config(ctypes.Structure):
     _fields_ = [("budget_bytes", ctypes.c_uint64), ("arena_bytes", ctypes.c_uint64),
-                ("max_slots", ctypes.c_uint32), ("flags", ctypes.c_uint32), ("tick_updates", ctypes.c_uint64)]
+                ("max_slots", ctypes.c_uint32), ("flags", ctypes.c_uint32), ("tick_updates", ctypes.c_uint64),
+                ("grid", ctypes.c_uint32), ("reserved", ctypes.c_uint32)]
 
 
 class srv_stats(ctypes.Structure):
@@ -515,9 +516,9 @@ class Server:
     budget_bytes borrowed from torch."""
 
     def __init__(self, budget_bytes: int, max_slots: int = 256, arena_bytes: int = 0, graph: bool = True,
-                 tick_updates: int = 0, device: str = "cuda"):
+                 tick_updates: int = 0, grid: int = 0, device: str = "cuda"):
         self.cfg = srv_config(budget_bytes=budget_bytes, arena_bytes=arena_bytes, max_slots=max_slots,
-                              flags=0 if graph else SRV_FLAG_NO_GRAPH, tick_updates=tick_updates)
+                              flags=0 if graph else SRV_FLAG_NO_GRAPH, tick_updates=tick_updates, grid=grid)
         self.pool = torch.empty(budget_bytes, dtype=torch.uint8, device=device)
         self.h = srv_create(self.cfg, None, self.pool.data_ptr(), budget_bytes)
 

@@ -395,14 +395,32 @@ def random_circuit(seed: int, n: int, gates: int, h_frac: float = 0.1, ctrl_max:
                     meta={"seed": seed})
 
 
-def serving_trace(seed: int = 4242, requests: int = 512, rate: float = 100.0,
-                  cap_log2: tuple[int, int] = (8, 22), gates_range: tuple[int, int] = (1000, 200_000)):
-    """Poisson-arriving requests drawn from the config-0..2 families with seeded
-    sizes: family uniform over {0, 1, 2}, entry cap 2^U{8..22}, gate count
-    log-uniform in [1e3, 2e5].  Returns a list of (arrival_s, Workload)."""
+def _serving_request(spec):
+    """Build one request of serving_trace from its drawn parameters."""
+    r, fam, lg, ng, sub_seed, n_draw = spec
+    if fam == 0:
+        n = max(16, min(100, lg + 2 + n_draw))
+        w = config0(sub_seed, n=n, h_qubits=max(1, lg - 4), gates=ng, cap=1 << lg)
+    elif fam == 1:
+        wbits = max(2, min(lg - 1, 30))
+        n = max(2 * wbits + 2, 16 + n_draw)
+        adds = max(1, ng // (6 * wbits + 1))
+        w = config1(sub_seed, w=wbits, adds=adds, n=min(n, 128))
+    else:
+        n = max(16, min(100, lg + 8 + n_draw))
+        rg = max(1, ng // 4)
+        w = config2(sub_seed, n=n, h_qubits=lg, gates=ng, round_gates=rg,
+                    meas_per_round=min(4, lg), cap=1 << lg)
+    w.meta.update({"family": fam, "cap_log2": lg, "request": r})
+    return w
+
+
+def _serving_specs(seed, requests, rate, cap_log2, gates_range):
+    """Arrival times and per-request parameters of serving_trace, drawn from
+    one stream in request order."""
     rng = SplitMix64(seed)
     t = 0.0
-    out = []
+    times, specs = [], []
     for r in range(requests):
         t += -math.log(1.0 - rng.uniform()) / rate
         fam = rng.randint(3)
@@ -411,21 +429,43 @@ def serving_trace(seed: int = 4242, requests: int = 512, rate: float = 100.0,
         ng = int(math.exp(lo + rng.uniform() * (hi - lo)))
         sub_seed = rng.next() & 0xFFFFFFFF
         if fam == 0:
-            n = max(16, min(100, lg + 2 + rng.randint(100 - lg - 1)))
-            w = config0(sub_seed, n=n, h_qubits=max(1, lg - 4), gates=ng, cap=1 << lg)
+            n_draw = rng.randint(100 - lg - 1)
         elif fam == 1:
-            wbits = max(2, min(lg - 1, 30))
-            n = max(2 * wbits + 2, 16 + rng.randint(49))
-            adds = max(1, ng // (6 * wbits + 1))
-            w = config1(sub_seed, w=wbits, adds=adds, n=min(n, 128))
+            n_draw = rng.randint(49)
         else:
-            n = max(16, min(100, lg + 8 + rng.randint(100 - lg - 7)))
-            rg = max(1, ng // 4)
-            w = config2(sub_seed, n=n, h_qubits=lg, gates=ng, round_gates=rg,
-                        meas_per_round=min(4, lg), cap=1 << lg)
-        w.meta.update({"family": fam, "cap_log2": lg, "request": r})
-        out.append((t, w))
-    return out
+            n_draw = rng.randint(100 - lg - 7)
+        times.append(t)
+        specs.append((r, fam, lg, ng, sub_seed, n_draw))
+    return times, specs
+
+
+def serving_trace(seed: int = 4242, requests: int = 512, rate: float = 100.0,
+                  cap_log2: tuple[int, int] = (8, 22), gates_range: tuple[int, int] = (1000, 200_000),
+                  workers: int = 1):
+    """Poisson-arriving requests drawn from the config-0..2 families with seeded
+    sizes: family uniform over {0, 1, 2}, entry cap 2^U{8..22}, gate count
+    log-uniform in [1e3, 2e5].  Returns a list of (arrival_s, Workload).
+
+    The arrival times and every request's parameters come from one stream in
+    request order; the circuits (each from its own sub-seed) are then built,
+    in a pool of `workers` forked processes when workers > 1 -- the same trace
+    either way."""
+    times, specs = _serving_specs(seed, requests, rate, cap_log2, gates_range)
+    if workers > 1 and requests > 1:
+        import multiprocessing as mp
+
+        with mp.get_context("fork").Pool(min(workers, requests)) as pool:
+            ws = pool.map(_serving_request, specs, chunksize=1)
+    else:
+        ws = [_serving_request(sp) for sp in specs]
+    return list(zip(times, ws))
+
+
+def serving_request(index: int, seed: int = 4242, requests: int = 512,
+                    cap_log2: tuple[int, int] = (8, 22), gates_range: tuple[int, int] = (1000, 200_000)):
+    """Request `index` of serving_trace(seed, requests, ...), built alone."""
+    _, specs = _serving_specs(seed, requests, 1.0, cap_log2, gates_range)
+    return _serving_request(specs[index])
 
 
 # --- random sparse states (counter-based SplitMix64, vectorised) --------------

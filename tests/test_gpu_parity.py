@@ -767,3 +767,80 @@ def test_empty_and_single_entry(sim):
     lo, hi, amp = s.export()
     assert lo.tolist() == [4] and amp[0] == 1j
     s.close()
+
+
+# Requests of the 512-request serving trace (seed 4242) whose states reach
+# 2^19..2^22 entries on 22, 40 and 51 qubits.
+@pytest.mark.parametrize("req", [197, 136, 422])
+def test_regplane_reproducible_on_large_states(sim, req):
+    """Two register-plane runs and one LDS-plane run of the same circuit give
+    the same keys, bit-identical amplitudes and the same outcomes; the
+    batched server agrees to 1e-12.  (States of this size and width were not
+    reproducible when the register-plane pass ran three waves per SIMD.)"""
+    w = W.serving_request(req)
+    say(f"[gpu] serving request {req}: n={w.n_qubits} cap={w.capacity} ops={len(w.ops)}")
+    gates = sim.sim_gates_from_ops(w.ops)
+
+    def plain(**kw):
+        s = sim.Simulator(w.n_qubits, w.capacity, w.eps, **kw)
+        s.set_basis(*w.basis)
+        _, outs, st = s.apply_gates(gates)
+        out = s.export()
+        s.close()
+        assert st["bitslice_passes"] > 0
+        return out, list(outs)
+
+    (a, oa), (b, ob), (c, oc) = plain(), plain(), plain(flags=sim.SIM_FLAG_BS_LDS)
+    assert oa == ob == oc
+    for x in (b, c):
+        assert np.array_equal(a[0], x[0]) and np.array_equal(a[1], x[1]), "keys differ"
+        assert a[2].tobytes() == x[2].tobytes(), "amplitudes differ"
+    srv = sim.Server(8 << 30, max_slots=2)
+    rid = srv.submit(sim.sim_config(n_qubits=w.n_qubits, capacity=w.capacity, eps=w.eps), gates, w.basis)
+    srv.run()
+    lo, hi, amp, outs, _ = srv.result(rid)
+    srv.close()
+    assert list(outs) == oa
+    assert np.array_equal(lo, a[0]) and np.array_equal(hi, a[1])
+    assert float(np.max(np.abs(amp - a[2]))) <= 1e-12
+
+
+def test_regplane_passes_on_two_streams(sim):
+    """Two states of 2^21 entries (adder circuits of the serving trace, their
+    controlled-phase ladders in register-plane turn groups) simulated at the
+    same time from two host threads, each on its own stream: every result is
+    bit-identical to the same circuit run alone."""
+    import threading
+    import torch
+
+    ws = [W.serving_request(i) for i in (137, 130)]
+    gates = [sim.sim_gates_from_ops(w.ops) for w in ws]
+
+    def run(w, g, stream=None):
+        with torch.cuda.stream(stream or torch.cuda.current_stream()):
+            s = sim.Simulator(w.n_qubits, w.capacity, w.eps)
+            s.set_basis(*w.basis)
+            _, _, st = s.apply_gates(g)
+            out = s.export()
+            s.close()
+        assert st["bitslice_passes"] > 0
+        return out
+
+    alone = [run(w, g) for w, g in zip(ws, gates)]
+    for rep in range(3):
+        streams = [torch.cuda.Stream(), torch.cuda.Stream()]
+        got = [None, None]
+
+        def worker(k):
+            got[k] = run(ws[k], gates[k], streams[k])
+
+        ts = [threading.Thread(target=worker, args=(k,)) for k in range(2)]
+        for t in ts:
+            t.start()
+        for t in ts:
+            t.join()
+        torch.cuda.synchronize()
+        for k in range(2):
+            say(f"[gpu] two streams rep {rep} state {k}: {len(got[k][0])} entries")
+            assert np.array_equal(got[k][0], alone[k][0]) and np.array_equal(got[k][1], alone[k][1])
+            assert got[k][2].tobytes() == alone[k][2].tobytes()
