@@ -183,17 +183,29 @@ def hbm_sweep(sim, W, n_qubits=100, log2n=24, depths=(1, 2, 4, 16, 64)):
     return out
 
 
-def serving_bench(sim, W, requests=128, max_log2=18, max_gates=50_000, budget_gib=32, check=True):
-    """Continuous batching vs one-at-a-time plain launches on one Poisson
-    trace (config-0..2 families, entry caps 2^8..2^max_log2, 10^3..max_gates
-    gates).  The arrival rate is 0.8x the one-at-a-time service rate measured
-    on the same requests back to back."""
-    import numpy as np
+def serving_trace(requests, max_log2, max_gates, workers=16):
+    """The serving trace (seed 4242): config-0..2 families, entry caps
+    2^8..2^max_log2, 10^3..max_gates gates, arrivals drawn at rate 1 (rescaled
+    later).  Built in a pool of forked workers: call before the GPU is used."""
+    from paper_2105_01533_amd import workloads as W
 
+    t0 = time.perf_counter()
+    trace = W.serving_trace(4242, requests=requests, rate=1.0, cap_log2=(8, max_log2),
+                            gates_range=(1000, max_gates), workers=workers)
+    log(f"[bench] serving trace: {requests} requests, {sum(len(w.ops) for _, w in trace)} ops, "
+        f"built in {time.perf_counter() - t0:.1f} s")
+    return trace
+
+
+def serving_bench(sim, trace, max_log2, max_gates, budget_gib=64, tick_updates=0, grid=0, check=True):
+    """Continuous batching vs one-at-a-time plain launches on one Poisson
+    trace.  The arrival rate is 0.8x the one-at-a-time service rate measured
+    on the same requests back to back (closed loop).  Both systems deliver
+    every state to host memory inside the timed region; the results are
+    compared afterwards (labels and outcomes exactly, amplitudes to 1e-12)."""
     from paper_2105_01533_amd import serving
 
-    trace = W.serving_trace(4242, requests=requests, rate=1.0, cap_log2=(8, max_log2),
-                            gates_range=(1000, max_gates))
+    requests = len(trace)
     reqs = serving.prepare(trace)
     closed, _ = serving.run_one_at_a_time(reqs, arrivals=False)
     rate = 0.8 * closed["requests_per_s"]
@@ -201,33 +213,30 @@ def serving_bench(sim, W, requests=128, max_log2=18, max_gates=50_000, budget_gi
     for r, (t, _) in zip(reqs, trace):
         r.arrival = t * scale
     log(f"[bench] serving: closed-loop one-at-a-time {closed['requests_per_s']:.1f} req/s -> lambda {rate:.1f}/s")
-    sat, _ = serving.run_batched(reqs, budget_gib << 30, arrivals=False)
+    srv_kw = dict(budget_bytes=budget_gib << 30, tick_updates=tick_updates, grid=grid)
+    sat, _ = serving.run_batched(reqs, arrivals=False, **srv_kw)
     log(f"[bench] serving batched, all requests at t=0: {sat}")
     base, rb = serving.run_one_at_a_time(reqs, arrivals=True, keep_results=check)
     log(f"[bench] serving one-at-a-time: {base}")
-    bat, rs = serving.run_batched(reqs, budget_gib << 30, arrivals=True, keep_results=check)
+    bat, rs = serving.run_batched(reqs, arrivals=True, keep_results=check, **srv_kw)
     log(f"[bench] serving batched: {bat}")
-    worst = 0.0
-    mism = 0
-    if check:
-        for x, y in zip(rb, rs):
-            if x is None or y is None or x[0] is None:
-                continue
-            (lo, hi, amp), outs = x[0], x[1]
-            if not (np.array_equal(lo, y[0]) and np.array_equal(hi, y[1]) and list(outs) == list(y[3])):
-                mism += 1
-            elif len(amp):
-                worst = max(worst, float(np.max(np.abs(amp - y[2]))))
-    return {"trace": f"{requests} Poisson requests, families c0/c1/c2, caps 2^8..2^{max_log2}, "
+    mism, worst, compared = serving.compare_results(rb, rs) if check else (None, None, 0)
+    del rb, rs
+    log(f"[bench] serving results: {compared} compared, {mism} label/outcome mismatches, max |d amp| {worst}")
+    return {"trace": f"{requests} Poisson requests (seed 4242), families c0/c1/c2, caps 2^8..2^{max_log2}, "
                      f"1e3..{max_gates} gates, lambda = 0.8 x one-at-a-time rate = {rate:.2f}/s",
+            "server": {"budget_gib": budget_gib, "max_slots": 256, "tick_updates": tick_updates,
+                       "grid": grid or 2048, "graph": True},
             "batched": bat, "one_at_a_time": base,
             "saturated": {"batched_requests_per_s": sat["requests_per_s"],
                           "one_at_a_time_requests_per_s": closed["requests_per_s"],
                           "batched_updates_per_s": sat["updates_per_s"],
                           "one_at_a_time_updates_per_s": closed["updates_per_s"],
+                          "batched_p99_ms": sat["p99_ms"], "one_at_a_time_p99_ms": closed["p99_ms"],
                           "throughput_ratio": sat["requests_per_s"] / closed["requests_per_s"]},
             "throughput_ratio": bat["requests_per_s"] / base["requests_per_s"],
-            "results_max_abs_diff": worst, "results_label_mismatches": mism}
+            "p99_ratio": bat["p99_ms"] / base["p99_ms"],
+            "results_compared": compared, "results_max_abs_diff": worst, "results_label_mismatches": mism}
 
 
 def commuting_bench(sim, W, n=64, superposed=20, blocks=2000):
@@ -341,9 +350,12 @@ def main():
     ap.add_argument("--no-cpu-parallel", action="store_true", help="skip the multithreaded-oracle leg")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run the 1 GiB reference copy kernel (for hardware byte-counter scaling) first")
-    ap.add_argument("--serving-requests", type=int, default=128)
-    ap.add_argument("--serving-max-log2", type=int, default=18)
-    ap.add_argument("--serving-max-gates", type=int, default=50_000)
+    ap.add_argument("--serving-requests", type=int, default=512)
+    ap.add_argument("--serving-max-log2", type=int, default=22)
+    ap.add_argument("--serving-max-gates", type=int, default=200_000)
+    ap.add_argument("--serving-tick-updates", type=int, default=0,
+                    help="server cap on one request's fused-run work per tick (0 = none)")
+    ap.add_argument("--serving-grid", type=int, default=0, help="server tick grid (0 = 2048)")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--mono-mode", type=int, default=0, help="0 auto, 1 direct, 2 bit-sliced")
     ap.add_argument("--fuse-max", type=int, default=0)
@@ -352,6 +364,11 @@ def main():
         print(f"bench.py measures one GPU only (got --gpus {args.gpus}): the library runs a state on one GPU "
               f"and has no multi-GPU path.", file=sys.stderr)
         sys.exit(2)
+
+    # The serving trace is built in forked worker processes, before this
+    # process touches the GPU.
+    trace = None if args.no_serving else serving_trace(args.serving_requests, args.serving_max_log2,
+                                                       args.serving_max_gates)
 
     import torch
 
@@ -459,8 +476,9 @@ def main():
     if not args.no_sweep:
         out["hbm_sweep"] = hbm_sweep(sim, W)
     if not args.no_serving:
-        out["serving"] = serving_bench(sim, W, args.serving_requests, args.serving_max_log2,
-                                       args.serving_max_gates)
+        out["serving"] = serving_bench(sim, trace, args.serving_max_log2, args.serving_max_gates,
+                                       tick_updates=args.serving_tick_updates, grid=args.serving_grid)
+        del trace
     if not args.no_commuting:
         out["commuting"] = commuting_bench(sim, W)
     if not args.no_pauli:

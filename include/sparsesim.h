@@ -416,8 +416,18 @@ typedef struct srv_config {
                             small requests are not held behind long runs of large ones. */
   uint32_t grid;         /* workgroups of every tick kernel (each walks the tick's work units);
                             0 = 2048, else 1..65536 */
+  uint32_t lane_capacity; /* requests whose capacity is at least this many entries run on the
+                            large-state lane: the single-state engine (sim_apply_gates, whole
+                            circuit, no host round trip per gate) on a stream and host thread of
+                            its own, its workspace (sim_workspace_bytes) taken from the pool,
+                            concurrently with the batched ticks; queued in a FIFO of their own.
+                            0 = 2^12; SRV_LANE_OFF = never (every request batched). */
+  uint32_t lane_workers; /* lane threads (each with its own stream), so that as many large
+                            requests run at once; 0 = 8, else 1..64 */
   uint32_t reserved;     /* must be 0 */
 } srv_config;
+
+#define SRV_LANE_OFF 0xFFFFFFFFu
 
 typedef struct srv_stats {
   uint64_t submitted, admitted, completed, failed;
@@ -428,6 +438,8 @@ typedef struct srv_stats {
   double host_ms;           /* wall time in srv_tick outside the wait for the GPU */
   double wait_ms;           /* wall time srv_tick waited for the GPU */
   double group_ms;          /* of host_ms: grouping fused runs for the bit-sliced form */
+  uint64_t lane_completed;  /* requests finished (done or failed) on the large-state lane */
+  double lane_ms;           /* wall time the lane spent running requests */
 } srv_stats;
 
 typedef struct srv_t srv_t;

@@ -9,16 +9,26 @@
 // captured tick graph, and reads back every slot's control words.  Finished
 // requests are copied to host memory and their device memory is returned to
 // the pool, which lets queued requests in on the next tick.
+//
+// Requests of large capacity take the large-state lane instead: host threads
+// run each through the single-state engine (sim_apply_gates on a workspace
+// from the pool, on a stream per thread), whole, while the ticks go on.  A
+// tick is as long as its longest item, and a large state's runs would hold
+// every small request in the tick for as long; on the lane a large request
+// also needs no host round trip per gate.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <condition_variable>
 #include <cstring>
 #include <deque>
 #include <map>
 #include <memory>
+#include <mutex>
 #include <string>
+#include <thread>
 #include <unordered_map>
 #include <vector>
 
@@ -164,6 +174,8 @@ struct Request {
   size_t i = 0;
   size_t mono_seen = 0;
   bool deferred = false;              // its last fused run did not fit the tick's arena
+  bool large = false;                 // runs on the large-state lane
+  int lane_rc = SIM_OK;               // the lane's result code
   SegKind seg = SEG_NONE;
   sim_stats st{};
   std::vector<int32_t> outcomes;
@@ -196,6 +208,20 @@ struct srv_t {
   std::deque<uint64_t> queue;
   std::vector<Request*> running;
   srv_stats stats{};
+  int device = 0;
+  // large-state lane
+  uint64_t lane_cap = 1ull << 12;     // capacity from which a request takes the lane (0: no lane)
+  std::deque<uint64_t> lane_queue;    // queued large requests (FIFO)
+  int lane_in_flight = 0;             // admitted to the lane, not yet folded back (tick thread)
+  std::vector<std::thread> lane_threads;
+  std::vector<hipStream_t> lane_streams;
+  int lane_depth = 0;                 // lane requests admitted at once (workers + 1)
+  std::mutex lane_mu;
+  std::condition_variable lane_cv, lane_done_cv;
+  std::deque<Request*> lane_todo;     // admitted, waiting for the lane thread
+  std::vector<Request*> lane_done;    // finished by the lane thread
+  bool lane_stop = false;
+  double lane_ms = 0.0;               // lane thread only (read under lane_mu)
 };
 
 namespace {
@@ -304,11 +330,103 @@ void compile_request(Request& r) {
   r.compiled = true;
 }
 
+// ---- large-state lane ----------------------------------------------------------
+// One request, whole, through the single-state engine on the lane's stream;
+// the state is copied out to the request's host result.  Runs on the lane
+// thread; touches only the request (the tick thread does not, meanwhile).
+void lane_run(srv_t* s, Request& r, hipStream_t stream) {
+  sim_t* h = nullptr;
+  size_t n_meas = 0;
+  for (const sim_gate& g : r.gates) n_meas += g.op == SIM_OP_MEASURE;
+  std::vector<int32_t> outs(n_meas);
+  int rc = sim_create(&r.cfg, stream, s->pool_mem + r.off, r.fp.total, &h);
+  if (rc == SIM_OK) rc = sim_set_basis(h, r.basis);
+  if (rc == SIM_OK) rc = sim_apply_gates(h, r.gates.data(), r.gates.size(), outs.data(), &r.st);
+  uint64_t n = 0;
+  if (rc == SIM_OK) rc = sim_nnz(h, &n);
+  if (rc == SIM_OK) {
+    r.keys.resize(n);
+    r.amps.resize(n);
+    uint64_t got = 0;
+    rc = sim_export_state(h, r.keys.data(), r.amps.data(), n, &got);
+  }
+  if (h) (void)sim_destroy(h);
+  r.outcomes.assign(outs.begin(), outs.begin() + std::min<size_t>(outs.size(), r.st.measures));
+  r.lane_rc = rc;
+}
+
+void lane_main(srv_t* s, hipStream_t stream) {
+  (void)hipSetDevice(s->device);
+  for (;;) {
+    Request* r = nullptr;
+    {
+      std::unique_lock<std::mutex> lk(s->lane_mu);
+      s->lane_cv.wait(lk, [&] { return s->lane_stop || !s->lane_todo.empty(); });
+      if (s->lane_todo.empty()) return;   // stopping
+      r = s->lane_todo.front();
+      s->lane_todo.pop_front();
+    }
+    const auto t0 = std::chrono::steady_clock::now();
+    lane_run(s, *r, stream);
+    const double ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    {
+      std::lock_guard<std::mutex> lk(s->lane_mu);
+      s->lane_ms += ms;
+      s->lane_done.push_back(r);
+    }
+    s->lane_done_cv.notify_all();
+  }
+}
+
+// Fold the lane's finished requests back (tick thread): result state, pool
+// memory, counters.
+void lane_fold(srv_t* s) {
+  std::vector<Request*> fin;
+  {
+    std::lock_guard<std::mutex> lk(s->lane_mu);
+    fin.swap(s->lane_done);
+    s->stats.lane_ms = s->lane_ms;
+  }
+  for (Request* r : fin) {
+    --s->lane_in_flight;
+    s->pool.release(r->off, r->fp.total);
+    r->state = r->lane_rc == SIM_OK ? SRV_DONE : SRV_FAILED;
+    r->error = r->lane_rc;
+    if (r->state == SRV_DONE) s->stats.completed++;
+    else s->stats.failed++;
+    s->stats.lane_completed++;
+    r->gates.clear();
+    r->gates.shrink_to_fit();
+  }
+}
+
+// Admit large requests in FIFO order while the pool has room: one per lane
+// worker and one more waiting with its memory, so no worker idles between
+// requests.
+void lane_admit(srv_t* s) {
+  while (!s->lane_queue.empty() && s->lane_in_flight < s->lane_depth) {
+    Request& r = *s->reqs[s->lane_queue.front()];
+    size_t off;
+    if (!s->pool.alloc(r.fp.total, &off)) break;
+    s->lane_queue.pop_front();
+    r.off = off;
+    r.state = SRV_RUNNING;
+    ++s->lane_in_flight;
+    s->stats.admitted++;
+    {
+      std::lock_guard<std::mutex> lk(s->lane_mu);
+      s->lane_todo.push_back(&r);
+    }
+    s->lane_cv.notify_one();
+  }
+}
+
 // Admission uploads read from these (and from the request and the pinned
 // control words), which outlive the copies.
 const double kUnitAmp[2] = {1.0, 0.0};
 
 int admit(srv_t* s) {
+  lane_admit(s);
   std::vector<Request*> fresh;
   while (!s->queue.empty() && !s->free_slots.empty()) {
     Request& r = *s->reqs[s->queue.front()];
@@ -370,11 +488,14 @@ int srv_create(const srv_config* cfg, void* stream, void* pool, size_t pool_byte
   if (cfg->arena_bytes && cfg->arena_bytes < kMinArena)
     return sfail(SIM_E_ARG, "arena_bytes must be 0 (default 64 MiB) or at least 1 MiB");
   if (cfg->grid > 65536) return sfail(SIM_E_ARG, "grid must be 0 (default 2048) or 1..65536");
+  if (cfg->lane_workers > 64) return sfail(SIM_E_ARG, "lane_workers must be 0 (default 8) or 1..64");
   if (cfg->reserved) return sfail(SIM_E_ARG, "reserved must be 0");
   std::unique_ptr<srv_t> s(new srv_t());
   s->cfg = *cfg;
   if (!s->cfg.arena_bytes) s->cfg.arena_bytes = 64ull << 20;
   s->grid = cfg->grid ? (int)cfg->grid : 2048;
+  s->lane_cap = cfg->lane_capacity == SRV_LANE_OFF ? 0 : (cfg->lane_capacity ? cfg->lane_capacity : 1ull << 12);
+  if (hipGetDevice(&s->device) != hipSuccess) s->device = 0;
   if (stream) {
     s->stream = static_cast<hipStream_t>(stream);
   } else {
@@ -404,12 +525,33 @@ int srv_create(const srv_config* cfg, void* stream, void* pool, size_t pool_byte
   SRV_HIP(hipStreamSynchronize(s->stream));
   int rc = capture_tick(s.get());
   if (rc) return rc;
+  if (s->lane_cap) {
+    const int nw = cfg->lane_workers ? (int)cfg->lane_workers : 8;
+    s->lane_depth = nw + 1;
+    srv_t* raw = s.get();
+    for (int k = 0; k < nw; ++k) {
+      hipStream_t st = nullptr;
+      SRV_HIP(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
+      s->lane_streams.push_back(st);
+      s->lane_threads.emplace_back([raw, st] { lane_main(raw, st); });
+    }
+  }
   *out = s.release();
   return SIM_OK;
 }
 
 int srv_destroy(srv_t* s) {
   if (!s) return SIM_OK;
+  if (!s->lane_threads.empty()) {
+    {
+      std::lock_guard<std::mutex> lk(s->lane_mu);
+      s->lane_stop = true;
+      s->lane_todo.clear();   // requests running now finish; queued ones are dropped
+    }
+    s->lane_cv.notify_all();
+    for (auto& t : s->lane_threads) t.join();
+  }
+  for (hipStream_t st : s->lane_streams) (void)hipStreamDestroy(st);
   (void)hipStreamSynchronize(s->stream);
   if (s->exec) (void)hipGraphExecDestroy(s->exec);
   if (s->graph) (void)hipGraphDestroy(s->graph);
@@ -434,7 +576,14 @@ int srv_submit(srv_t* s, const sim_config* cfg, const sim_gate* gates, size_t n,
   r->cfg = *cfg;
   r->cfg.load_factor = lf_or_default(cfg->load_factor);
   if (!(r->cfg.load_factor > 0.0 && r->cfg.load_factor <= 0.9)) return sfail(SIM_E_ARG, "load_factor out of range");
-  r->fp = footprint_of(r->cfg, r->cfg.load_factor);
+  r->large = s->lane_cap && cfg->capacity >= s->lane_cap;
+  if (r->large) {
+    r->fp = Footprint{};
+    r->fp.total = al(sim_workspace_bytes(&r->cfg));
+    if (r->fp.total == 0) return sfail(SIM_E_ARG, "invalid configuration for the large-state lane");
+  } else {
+    r->fp = footprint_of(r->cfg, r->cfg.load_factor);
+  }
   if (r->fp.total > s->pool.size) return sfail(SIM_E_CAPACITY, "request footprint exceeds the pool");
   r->basis = basis;
   r->gates.assign(gates, gates + n);
@@ -443,7 +592,7 @@ int srv_submit(srv_t* s, const sim_config* cfg, const sim_gate* gates, size_t n,
     if (!gate_valid(cfg->n_qubits, gates[i], &why)) return sfail(SIM_E_ARG, "op " + std::to_string(i) + ": " + why);
   r->id = s->next_id++;
   *id = r->id;
-  s->queue.push_back(r->id);
+  (r->large ? s->lane_queue : s->queue).push_back(r->id);
   s->reqs[r->id] = std::move(r);
   s->stats.submitted++;
   return SIM_OK;
@@ -465,6 +614,7 @@ int srv_tick(srv_t* s, uint32_t* running, uint32_t* queued) {
     double wait0;
     ~HostTime() { s->stats.host_ms += ms_since(t0) - (s->stats.wait_ms - wait0); }
   } host_time{s, t_tick, wait0};
+  lane_fold(s);
   int rc = admit(s);
   if (rc) return rc;
   // Assemble the work list.
@@ -684,8 +834,16 @@ int srv_tick(srv_t* s, uint32_t* running, uint32_t* queued) {
       s->running.erase(std::find(s->running.begin(), s->running.end(), f.first));
     }
   }
-  if (running) *running = (uint32_t)s->running.size();
-  if (queued) *queued = (uint32_t)s->queue.size();
+  if (s->running.empty() && s->lane_in_flight) {
+    // Nothing batched to do: wait (briefly) for the lane instead of spinning.
+    const auto t_w = std::chrono::steady_clock::now();
+    std::unique_lock<std::mutex> lk(s->lane_mu);
+    s->lane_done_cv.wait_for(lk, std::chrono::microseconds(200), [&] { return !s->lane_done.empty(); });
+    lk.unlock();
+    s->stats.wait_ms += ms_since(t_w);
+  }
+  if (running) *running = (uint32_t)(s->running.size() + s->lane_in_flight);
+  if (queued) *queued = (uint32_t)(s->queue.size() + s->lane_queue.size());
   s->stats.pool_peak_bytes = s->pool.peak;
   s->stats.pool_used_bytes = s->pool.used;
   return SIM_OK;
@@ -697,7 +855,7 @@ int srv_run(srv_t* s) {
   while (run || q) {
     // A tick that starts with nothing running has the whole pool and every
     // slot free: if it admits nothing, the queue's head can never fit.
-    const bool idle = s->running.empty();
+    const bool idle = s->running.empty() && s->lane_in_flight == 0;
     const uint64_t before = s->stats.admitted;
     int rc = srv_tick(s, &run, &q);
     if (rc) return rc;

@@ -77,13 +77,15 @@ def run_one_at_a_time(reqs, arrivals=True, keep_results=False, tuning: dict | No
 
 
 def run_batched(reqs, budget_bytes: int, max_slots: int = 256, arrivals=True, keep_results=False, graph=True,
-                tick_updates: int = 1 << 27, tuning: dict | None = None):
+                tick_updates: int = 0, grid: int = 0, lane_capacity: int = 0, lane_workers: int = 0,
+                tuning: dict | None = None):
     """Replay through the continuous-batching server (open loop when
     arrivals, else every request at time 0).  tuning: optional autotuner
     table; each request then runs with the knobs of its bucket."""
     from . import autotune
 
-    srv = S.Server(budget_bytes, max_slots=max_slots, graph=graph, tick_updates=tick_updates)
+    srv = S.Server(budget_bytes, max_slots=max_slots, graph=graph, tick_updates=tick_updates, grid=grid,
+                   lane_capacity=lane_capacity, lane_workers=lane_workers)
     if tuning:
         for r in reqs:
             k = autotune.lookup(tuning, r.w.n_qubits, r.w.capacity)

@@ -386,18 +386,21 @@ def run_pauli_workload(w, **kw):
 # --- continuous-batching server (srv_*) -----------------------------------------
 SRV_QUEUED, SRV_RUNNING, SRV_DONE, SRV_FAILED = 0, 1, 2, 3
 SRV_FLAG_NO_GRAPH = 1
+SRV_LANE_OFF = 0xFFFFFFFF
 
 
 class srv_config(ctypes.Structure):
     _fields_ = [("budget_bytes", ctypes.c_uint64), ("arena_bytes", ctypes.c_uint64),
                 ("max_slots", ctypes.c_uint32), ("flags", ctypes.c_uint32), ("tick_updates", ctypes.c_uint64),
-                ("grid", ctypes.c_uint32), ("reserved", ctypes.c_uint32)]
+                ("grid", ctypes.c_uint32), ("lane_capacity", ctypes.c_uint32),
+                ("lane_workers", ctypes.c_uint32), ("reserved", ctypes.c_uint32)]
 
 
 class srv_stats(ctypes.Structure):
     _fields_ = [(f, ctypes.c_uint64) for f in (
         "submitted", "admitted", "completed", "failed", "ticks", "items", "bitslice_runs",
-        "pool_used_bytes", "pool_peak_bytes")] + [(f, ctypes.c_double) for f in ("host_ms", "wait_ms", "group_ms")]
+        "pool_used_bytes", "pool_peak_bytes")] + [(f, ctypes.c_double) for f in ("host_ms", "wait_ms", "group_ms")] + [
+        ("lane_completed", ctypes.c_uint64), ("lane_ms", ctypes.c_double)]
 
     def as_dict(self):
         return {f: (round(getattr(self, f), 3) if t is ctypes.c_double else int(getattr(self, f)))
@@ -516,9 +519,11 @@ class Server:
     budget_bytes borrowed from torch."""
 
     def __init__(self, budget_bytes: int, max_slots: int = 256, arena_bytes: int = 0, graph: bool = True,
-                 tick_updates: int = 0, grid: int = 0, device: str = "cuda"):
+                 tick_updates: int = 0, grid: int = 0, lane_capacity: int = 0, lane_workers: int = 0,
+                 device: str = "cuda"):
         self.cfg = srv_config(budget_bytes=budget_bytes, arena_bytes=arena_bytes, max_slots=max_slots,
-                              flags=0 if graph else SRV_FLAG_NO_GRAPH, tick_updates=tick_updates, grid=grid)
+                              flags=0 if graph else SRV_FLAG_NO_GRAPH, tick_updates=tick_updates, grid=grid,
+                              lane_capacity=lane_capacity, lane_workers=lane_workers)
         self.pool = torch.empty(budget_bytes, dtype=torch.uint8, device=device)
         self.h = srv_create(self.cfg, None, self.pool.data_ptr(), budget_bytes)
 

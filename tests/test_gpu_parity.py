@@ -795,7 +795,7 @@ def test_regplane_reproducible_on_large_states(sim, req):
     for x in (b, c):
         assert np.array_equal(a[0], x[0]) and np.array_equal(a[1], x[1]), "keys differ"
         assert a[2].tobytes() == x[2].tobytes(), "amplitudes differ"
-    srv = sim.Server(8 << 30, max_slots=2)
+    srv = sim.Server(8 << 30, max_slots=2, lane_capacity=sim.SRV_LANE_OFF)   # the batched kernels
     rid = srv.submit(sim.sim_config(n_qubits=w.n_qubits, capacity=w.capacity, eps=w.eps), gates, w.basis)
     srv.run()
     lo, hi, amp, outs, _ = srv.result(rid)

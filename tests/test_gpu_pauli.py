@@ -170,7 +170,7 @@ def test_server_runs_pauli_gates(S):
     small = W.random_pauli_terms(95, 70, 25, max_weight=4, ctrl_max=2)
     other = W.random_circuit(96, n=12, gates=200, h_frac=0.2, ctrl_max=2)
     other.capacity = 1 << 12
-    srv = S.Server(1 << 28, max_slots=8)
+    srv = S.Server(1 << 28, max_slots=8, lane_capacity=S.SRV_LANE_OFF)   # the batched kernels
     ids = [srv.submit(S.sim_config(n_qubits=w.n_qubits, capacity=1 << 14, eps=w.eps), gates, w.basis),
            srv.submit(S.sim_config(n_qubits=70, capacity=1 << 16, eps=0.0), S.sim_gates_from_pauli(small, 70)),
            srv.submit_workload(other)]

@@ -47,8 +47,10 @@ def mix():
     return ws
 
 
-def run_server(S, ws, budget=1 << 30, slots=64, graph=True, arena_bytes=0, **tuning):
-    srv = S.Server(budget, max_slots=slots, graph=graph, arena_bytes=arena_bytes)
+def run_server(S, ws, budget=1 << 30, slots=64, graph=True, arena_bytes=0, lane=None, **tuning):
+    """Every request batched unless `lane` (a lane threshold) is given."""
+    srv = S.Server(budget, max_slots=slots, graph=graph, arena_bytes=arena_bytes,
+                   lane_capacity=S.SRV_LANE_OFF if lane is None else lane)
     ids = [srv.submit_workload(w, **tuning) for w in ws]
     srv.run()
     out = []
@@ -105,7 +107,7 @@ def test_budget_fifo_and_queueing(S):
     fb, fs = S.srv_footprint(cfg(big)), S.srv_footprint(cfg(small))
     assert fb > 4 * fs
     budget = fb + fs                                 # room for big + one small, never big + two small
-    srv = S.Server(budget, max_slots=8)
+    srv = S.Server(budget, max_slots=8, lane_capacity=S.SRV_LANE_OFF)
     ids = [srv.submit_workload(w) for w in (small, big, small, small)]
     srv.tick()
     states = [srv.poll(i)[0] for i in ids]
@@ -135,7 +137,7 @@ def test_oversized_and_invalid_requests_rejected(S):
 
 
 def test_failures_stay_in_their_request(S):
-    srv = S.Server(1 << 28, max_slots=8)
+    srv = S.Server(1 << 28, max_slots=8, lane_capacity=S.SRV_LANE_OFF)
     good = W.config0(54, n=20, h_qubits=5, gates=300, cap=1 << 8)
     c = W.Circuit()
     for q in range(6):
@@ -177,3 +179,55 @@ def test_small_arena_defers_runs_alone_equals_mix(S):
 def test_arena_too_small_is_rejected(S):
     with pytest.raises(S.ServerError):
         S.Server(1 << 24, max_slots=4, arena_bytes=1 << 16)
+
+
+def test_large_lane_matches_single_state_and_oracle(S):
+    """With the lane threshold at 2^12 entries, the mix's larger requests run
+    whole through the single-state engine on the lane while the rest are
+    batched: each lane result is bitwise the engine's own (the same code on a
+    workspace from the pool), every result matches the oracle, and the lane
+    counters add up."""
+    ws = mix()
+    lane = [w.capacity >= (1 << 12) for w in ws]
+    assert any(lane) and not all(lane)
+    srv = S.Server(1 << 30, max_slots=64, lane_capacity=1 << 12)
+    ids = [srv.submit_workload(w) for w in ws]
+    srv.run()
+    stats = srv.stats()
+    assert stats["completed"] == len(ws) and stats["failed"] == 0
+    assert stats["lane_completed"] == sum(lane)
+    for w, rid, on_lane in zip(ws, ids, lane):
+        lo, hi, amp, outs, st = srv.result(rid)
+        o, oout, _ = oracle_run(w)
+        assert list(outs) == list(oout), w.name
+        assert_same_state((lo, hi, amp), o.export(), what=w.name)
+        if on_lane:
+            s, eouts, est = S.run_workload(w)
+            elo, ehi, eamp = s.export()
+            s.close()
+            assert np.array_equal(lo, elo) and np.array_equal(hi, ehi) and amp.tobytes() == eamp.tobytes(), w.name
+            assert list(outs) == list(eouts) and st["updates"] == est["updates"]
+    srv.close()
+
+
+def test_large_lane_fifo_and_failures(S):
+    """Lane requests queue in their own FIFO, are admitted by pool memory,
+    and a failing one (capacity exceeded) fails alone."""
+    big = [W.config0(61 + k, n=30, h_qubits=10, gates=2000, cap=1 << 13) for k in range(4)]
+    c = W.Circuit()
+    for q in range(14):
+        c.h(q)                                   # 2^14 entries > capacity 2^13
+    over = W.Workload("over", 20, 0.0, c.array(), capacity=1 << 13)
+    srv = S.Server(1 << 30, max_slots=8, lane_capacity=1 << 13)
+    ids = [srv.submit_workload(w) for w in (big[0], over, big[1], big[2], big[3])]
+    srv.run()
+    res = [srv.poll(i) for i in ids]
+    assert res[1] == (S.SRV_FAILED, S.SIM_E_CAPACITY)
+    assert all(r == (S.SRV_DONE, 0) for k, r in enumerate(res) if k != 1)
+    assert srv.stats()["lane_completed"] == 5
+    for w, rid in zip([big[0], big[1], big[2], big[3]], [ids[0], ids[2], ids[3], ids[4]]):
+        lo, hi, amp, outs, _ = srv.result(rid)
+        o, oout, _ = oracle_run(w)
+        assert list(outs) == list(oout)
+        assert_same_state((lo, hi, amp), o.export(), what=w.name)
+    srv.close()
