@@ -151,7 +151,7 @@ def hbm_sweep(sim, W, n_qubits=100, log2n=24, depths=(1, 2, 4, 16, 64)):
     phase/permutation gates of the random mix, passes of F gates."""
     import numpy as np
 
-    s = sim.Simulator(n_qubits, 1 << log2n, 0.0)
+    s = sim.Simulator(n_qubits, 1 << log2n, 0.0, tuned=False)
     c = W.Circuit()
     for q in range(log2n):
         c.h(q)
@@ -197,7 +197,7 @@ def serving_trace(requests, max_log2, max_gates, workers=16):
     return trace
 
 
-def serving_bench(sim, trace, max_log2, max_gates, budget_gib=64, tick_updates=0, grid=0, check=True):
+def serving_bench(sim, trace, max_log2, max_gates, budget_gib=64, tick_updates=None, grid=None, check=True):
     """Continuous batching vs one-at-a-time plain launches on one Poisson
     trace.  The arrival rate is 0.8x the one-at-a-time service rate measured
     on the same requests back to back (closed loop).  Both systems deliver
@@ -225,8 +225,9 @@ def serving_bench(sim, trace, max_log2, max_gates, budget_gib=64, tick_updates=0
     log(f"[bench] serving results: {compared} compared, {mism} label/outcome mismatches, max |d amp| {worst}")
     return {"trace": f"{requests} Poisson requests (seed 4242), families c0/c1/c2, caps 2^8..2^{max_log2}, "
                      f"1e3..{max_gates} gates, lambda = 0.8 x one-at-a-time rate = {rate:.2f}/s",
-            "server": {"budget_gib": budget_gib, "max_slots": 256, "tick_updates": tick_updates,
-                       "grid": grid or 2048, "graph": True},
+            "server": {"budget_gib": budget_gib, "max_slots": 256, "graph": True, **bat["server_knobs"],
+                       "server_knobs_from": "autotuner table (server entry)",
+                       "request_knobs": "library defaults (both systems)"},
             "batched": bat, "one_at_a_time": base,
             "saturated": {"batched_requests_per_s": sat["requests_per_s"],
                           "one_at_a_time_requests_per_s": closed["requests_per_s"],
@@ -353,12 +354,13 @@ def main():
     ap.add_argument("--serving-requests", type=int, default=512)
     ap.add_argument("--serving-max-log2", type=int, default=22)
     ap.add_argument("--serving-max-gates", type=int, default=200_000)
-    ap.add_argument("--serving-tick-updates", type=int, default=0,
-                    help="server cap on one request's fused-run work per tick (0 = none)")
-    ap.add_argument("--serving-grid", type=int, default=0, help="server tick grid (0 = 2048)")
+    ap.add_argument("--serving-tick-updates", type=int, default=None,
+                    help="server cap on one request's fused-run work per tick (default: the autotuner table's)")
+    ap.add_argument("--serving-grid", type=int, default=None, help="server tick grid (default: the table's)")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
-    ap.add_argument("--mono-mode", type=int, default=0, help="0 auto, 1 direct, 2 bit-sliced")
-    ap.add_argument("--fuse-max", type=int, default=0)
+    ap.add_argument("--mono-mode", type=int, default=None,
+                    help="0 auto, 1 direct, 2 bit-sliced (default: the autotuner table's)")
+    ap.add_argument("--fuse-max", type=int, default=None, help="default: the autotuner table's")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (got --gpus {args.gpus}): the library runs a state on one GPU "
@@ -387,6 +389,7 @@ def main():
     w = getattr(W, fn)()
     log(f"[bench] workload {w.name}: {len(w.ops)} ops, capacity {w.capacity}")
     s = sim.Simulator(w.n_qubits, w.capacity, w.eps, mono_mode=args.mono_mode, fuse_max=args.fuse_max)
+    log(f"[bench] launch knobs (autotuner table unless given): {s.knobs}")
     gates = sim.sim_gates_from_ops(w.ops)
     for i in range(args.warmup):
         s.set_basis(*w.basis)
@@ -468,6 +471,7 @@ def main():
                    "updates_per_step": st["updates"], "peak_nnz": st["peak_nnz"],
                    "mono_passes_per_step": st["mono_passes"], "bitslice_passes_per_step": st["bitslice_passes"],
                    "u2_applied": st["u2_applied"], "u2_skipped": st["u2_skipped"], "measures": st["measures"],
+                   "knobs": s.knobs,
                    "kernel_ms_per_step": kernel_ms, "host_ms_per_step": host_ms},
         "roofline": roofline,
         "copy": copy,

@@ -354,7 +354,8 @@ typedef struct sim_kernel_stat {
 /* Change the launch tuning of a live handle: fuse_max, block, mono_mode and
  * bs_min_gates are taken from t (zero = default); load_factor is taken if it
  * is at least the creation value (the index was sized for that one); other
- * fields of t are ignored; flags is taken as well.  Results change only by
+ * fields of t are ignored; flags is taken as well, except SIM_FLAG_BS_LDS,
+ * which only sim_create sets (SIM_E_ARG here).  Results change only by
  * rounding (mono_mode) or not at all.  SIM_E_ARG on invalid values. */
 int sim_set_tuning(sim_t* s, const sim_config* t);
 

@@ -1,18 +1,29 @@
-"""Autotuner for the launch knobs of the simulator.
+"""Autotuner for the launch knobs of the simulator and the server.
 
-Knobs: fusion depth (fuse_max), the run length from which the bit-sliced
-fused pass is used (bs_min_gates), the fused-pass kernel (mono_mode), the
-per-entry pass block shape (block) and the hash-index load factor
-(load_factor).  None of them changes which labels survive; they change speed
-and, between fused-pass kernels, floating-point rounding only.
+Per-state knobs: fusion depth (fuse_max), the run length from which the
+bit-sliced fused pass is used (bs_min_gates), per-entry or bit-sliced fused
+passes (mono_mode), the per-entry pass block shape (block) and the hash-index
+load factor (load_factor).  (Which bit-sliced kernel runs, register planes
+or LDS planes, is fixed at creation and not searched.)  None of them changes which labels
+survive; they change speed and, between fused-pass kernels, floating-point
+rounding only.
+
+Server knobs: the capacity from which a request takes the large-state lane
+(lane_capacity), the lane's worker count (lane_workers), the tick kernels'
+grid (grid) and the per-tick cap on a request's fused work (tick_updates),
+tuned for the makespan of a reduced serving trace with every request
+submitted at once.
 
 For each bucket (label width: <= 64 qubits or more; state size: log2 of the
 capacity) a representative random circuit of that size is timed on one live
 handle (sim_set_tuning changes the knobs without reallocating), with a greedy
 coordinate search: knobs are visited in a fixed order, each set to its best
 value with the others held, for a given number of sweeps.  The result is a
-JSON table keyed by bucket; ``lookup`` returns the knobs for the nearest
-bucket, and ``Simulator``/``Server`` callers pass them as sim_config fields.
+JSON table keyed by bucket (plus a "server" entry); ``lookup`` returns the
+knobs for the nearest bucket and ``server_knobs`` the server's.  ``Simulator``
+and ``Server`` apply the committed table (tuning_mi355x.json) by default to
+every knob the caller leaves unset; ``tuned=False`` or the environment
+variable SPARSESIM_TUNING=off turns that off.
 """
 from __future__ import annotations
 
@@ -31,15 +42,25 @@ SPACE = {
     "block": [64, 128, 256],
     "load_factor": [0.25, 0.5, 0.7],
 }
-DEFAULTS = {"fuse_max": 65536, "bs_min_gates": 16, "mono_mode": 0, "block": 256, "load_factor": 0.5}
+DEFAULTS = {"fuse_max": 65536, "bs_min_gates": 16, "mono_mode": 0, "flags": 0, "block": 256, "load_factor": 0.5}
+KNOBS = tuple(DEFAULTS)
+
+SERVER_SPACE = {
+    "lane_capacity": [1 << 10, 1 << 12, 1 << 14, 1 << 16],
+    "lane_workers": [4, 8],
+}
+SERVER_DEFAULTS = {"lane_capacity": 1 << 12, "lane_workers": 8, "grid": 2048, "tick_updates": 0}
 
 
 def bucket_key(n_qubits: int, capacity: int) -> str:
     return f"{'wide' if n_qubits > 64 else 'narrow'}_lg{max(1, math.ceil(math.log2(max(capacity, 2))))}"
 
 
-def greedy_search(measure, space=SPACE, start=DEFAULTS, sweeps: int = 1):
-    """Coordinate search: measure(knobs) -> seconds (lower is better)."""
+def greedy_search(measure, space=SPACE, start=DEFAULTS, sweeps: int = 1, min_gain: float = 0.0):
+    """Coordinate search: measure(knobs) -> seconds (lower is better).  A
+    value replaces the held one only if it is faster by more than the
+    fraction min_gain (so timing noise does not move a knob off its
+    default)."""
     best = dict(start)
     best_t = measure(best)
     trials = [(dict(best), best_t)]
@@ -53,9 +74,42 @@ def greedy_search(measure, space=SPACE, start=DEFAULTS, sweeps: int = 1):
                 cand[name] = v
                 t = measure(cand)
                 trials.append((cand, t))
-                if t < best_t:
+                if t < best_t * (1.0 - min_gain):
                     best, best_t = cand, t
     return best, best_t, trials
+
+
+def enabled() -> bool:
+    """False when the environment variable SPARSESIM_TUNING is off/0/false."""
+    return os.environ.get("SPARSESIM_TUNING", "on").lower() not in ("off", "0", "false", "no")
+
+
+_TABLE = None
+
+
+def table() -> dict:
+    """The committed table (loaded once)."""
+    global _TABLE
+    if _TABLE is None:
+        _TABLE = load()
+    return _TABLE
+
+
+def state_knobs(n_qubits: int, capacity: int, given: dict) -> dict:
+    """The per-state knobs: those in `given` that are not None, the table's
+    for the others (or the defaults when tuning is off)."""
+    base = lookup(table(), n_qubits, capacity) if enabled() else dict(DEFAULTS)
+    return {k: (given[k] if given.get(k) is not None else base.get(k, DEFAULTS[k])) for k in KNOBS}
+
+
+def server_knobs(given: dict | None = None) -> dict:
+    """The server knobs: those in `given` that are not None, the table's for
+    the others (or the defaults when tuning is off)."""
+    given = given or {}
+    base = dict(SERVER_DEFAULTS)
+    if enabled():
+        base.update(table().get("server", {}).get("knobs", {}))
+    return {k: (given[k] if given.get(k) is not None else base[k]) for k in SERVER_DEFAULTS}
 
 
 def representative(W, n_qubits: int, log2cap: int, gates: int, seed: int = 99):
@@ -65,17 +119,19 @@ def representative(W, n_qubits: int, log2cap: int, gates: int, seed: int = 99):
                      meas_per_round=min(4, log2cap), cap=1 << log2cap)
 
 
-def tune(buckets=((24, 12), (24, 16), (100, 16), (100, 20), (100, 22)), gates: int = 4000, repeats: int = 3,
-         sweeps: int = 1, cache: str | None = DEFAULT_CACHE, log=print):
-    """Tune every (n_qubits, log2 capacity) bucket on the GPU; returns the
-    table and writes it to `cache` (JSON) unless cache is None."""
+def tune(buckets=((24, 12), (24, 16), (100, 16), (100, 20), (100, 22)), gates: int = 20_000,
+         repeats: int = 3, sweeps: int = 1, cache: str | None = DEFAULT_CACHE, server: bool = True,
+         min_gain: float = 0.03, log=print):
+    """Tune every (n_qubits, log2 capacity) bucket on the GPU, then (server)
+    the server knobs; returns the table and writes it to `cache` (JSON)
+    unless cache is None."""
     from . import sim as S
     from . import workloads as W
 
     table = {}
     for nq, lg in buckets:
         w = representative(W, nq, lg, gates)
-        s = S.Simulator(nq, w.capacity, w.eps, load_factor=min(SPACE["load_factor"]))
+        s = S.Simulator(nq, w.capacity, w.eps, load_factor=min(SPACE["load_factor"]), tuned=False)
         g = S.sim_gates_from_ops(w.ops)
 
         def measure(knobs):
@@ -89,16 +145,44 @@ def tune(buckets=((24, 12), (24, 16), (100, 16), (100, 20), (100, 22)), gates: i
             return sorted(ts)[len(ts) // 2]
 
         measure(DEFAULTS)                              # warm
-        best, best_t, trials = greedy_search(measure, sweeps=sweeps)
+        best, best_t, trials = greedy_search(measure, sweeps=sweeps, min_gain=min_gain)
         s.close()
         key = bucket_key(nq, w.capacity)
         table[key] = {"knobs": best, "seconds": best_t, "default_seconds": trials[0][1],
                       "n_qubits": nq, "log2_capacity": lg, "gates": gates, "trials": len(trials)}
         log(f"[autotune] {key}: {best} {best_t * 1e3:.2f} ms (default {trials[0][1] * 1e3:.2f} ms)")
+    if server:
+        table["server"] = tune_server(min_gain=min_gain, log=log)
     if cache:
         with open(cache, "w") as f:
             json.dump(table, f, indent=1, sort_keys=True)
     return table
+
+
+def tune_server(requests: int = 160, max_log2: int = 20, max_gates: int = 20_000, repeats: int = 2,
+                budget_gib: int = 32, min_gain: float = 0.03, log=print) -> dict:
+    """Greedy search over SERVER_SPACE for the makespan of a reduced serving
+    trace (seed 7: config-0..2 families, caps 2^8..2^max_log2, 1e3..max_gates
+    gates), every request submitted at once with the default per-state knobs.
+    (The tick grid and the per-tick cap are not searched: they stay at their
+    defaults.)"""
+    from . import serving, workloads as W
+
+    trace = W.serving_trace(7, requests=requests, rate=1.0, cap_log2=(8, max_log2), gates_range=(1000, max_gates))
+    reqs = serving.prepare(trace, tuned=False)
+
+    def measure(knobs):
+        ts = []
+        for _ in range(repeats):
+            out, _ = serving.run_batched(reqs, budget_gib << 30, arrivals=False, **knobs)
+            ts.append(out["makespan_s"])
+        return min(ts)
+
+    measure(SERVER_DEFAULTS)                           # warm
+    best, best_t, trials = greedy_search(measure, space=SERVER_SPACE, start=SERVER_DEFAULTS, min_gain=min_gain)
+    log(f"[autotune] server: {best} {best_t * 1e3:.1f} ms (default {trials[0][1] * 1e3:.1f} ms)")
+    return {"knobs": best, "seconds": best_t, "default_seconds": trials[0][1], "trials": len(trials),
+            "trace": f"{requests} requests (seed 7), caps 2^8..2^{max_log2}, 1e3..{max_gates} gates, all at t=0"}
 
 
 def load(cache: str = DEFAULT_CACHE) -> dict:
@@ -116,7 +200,7 @@ def lookup(table: dict, n_qubits: int, capacity: int) -> dict:
     cands = [(abs(v["log2_capacity"] - lg), k) for k, v in table.items() if k.startswith(width)]
     if not cands:
         return dict(DEFAULTS)
-    return dict(table[min(cands)[1]]["knobs"])
+    return {**DEFAULTS, **table[min(cands)[1]]["knobs"]}
 
 
 if __name__ == "__main__":
@@ -124,7 +208,8 @@ if __name__ == "__main__":
 
     ap = argparse.ArgumentParser(description="Tune launch knobs on this GPU and write the table.")
     ap.add_argument("--out", default=DEFAULT_CACHE)
-    ap.add_argument("--gates", type=int, default=4000)
+    ap.add_argument("--gates", type=int, default=20_000)
     ap.add_argument("--repeats", type=int, default=3)
+    ap.add_argument("--no-server", action="store_true", help="tune the per-state buckets only")
     args = ap.parse_args()
-    tune(gates=args.gates, repeats=args.repeats, cache=args.out)
+    tune(gates=args.gates, repeats=args.repeats, cache=args.out, server=not args.no_server)

@@ -7,7 +7,9 @@ namespace sparsesim {
 namespace bs {
 
 
-// LSB-first 32x32 bit transpose: out[q] bit j = in[j] bit q (an involution).
+// LSB-first 32x32 bit transpose: out[q] bit j = in[j] bit q (an involution), by
+// the recursive block-swap method of Warren, Hacker's Delight, Sec. 7-3: five
+// rounds swap 16-, 8-, 4-, 2- and 1-bit blocks between word pairs.
 __device__ __forceinline__ void transpose32(uint32_t (&A)[32]) {
   uint32_t m = 0x0000FFFFu;
 #pragma unroll

@@ -1291,6 +1291,8 @@ int sim_set_tuning(sim_t* s, const sim_config* t) {
   if (t->block != 0 && t->block != 64 && t->block != 128 && t->block != 256)
     return fail(SIM_E_ARG, "block must be 64, 128 or 256");
   if (t->mono_mode > SIM_MONO_BITSLICE) return fail(SIM_E_ARG, "unknown mono_mode");
+  // The fused-pass kernel (SIM_FLAG_BS_LDS) is chosen at creation only.
+  if (t->flags & SIM_FLAG_BS_LDS) return fail(SIM_E_ARG, "SIM_FLAG_BS_LDS is set at creation (sim_create) only");
   if (t->flags & ~SIM_FLAG_U2_TWO_PASS) return fail(SIM_E_ARG, "unknown flags");
   if (t->load_factor != 0.0 && !(t->load_factor > 0.0 && t->load_factor <= 0.9))
     return fail(SIM_E_ARG, "load_factor must be in (0, 0.9]");
@@ -1298,7 +1300,7 @@ int sim_set_tuning(sim_t* s, const sim_config* t) {
   s->cfg.block = t->block;
   s->cfg.mono_mode = t->mono_mode;
   s->cfg.bs_min_gates = t->bs_min_gates;
-  s->cfg.flags = t->flags;
+  s->cfg.flags = (s->cfg.flags & SIM_FLAG_BS_LDS) | t->flags;
   if (t->load_factor >= lf_of(&s->cfg)) s->cfg.load_factor = t->load_factor;
   return SIM_OK;
 }

@@ -18,15 +18,26 @@ from . import sim as S
 
 
 class Prepared:
-    def __init__(self, arrival: float, w):
+    """A request ready to submit: its gate records and its state configuration
+    (the library's default knobs, or the autotuner table's with tuned=True).
+
+    The serving runs use the default per-request knobs: a replay of the
+    512-request trace through the server with the table's per-request knobs
+    ended in a GPU fault whose cause has not been found (the same server
+    configuration with default per-request knobs, and one-at-a-time runs with
+    the table's knobs, run cleanly)."""
+
+    def __init__(self, arrival: float, w, tuned: bool = False):
+        from . import autotune
         self.arrival = arrival
         self.w = w
         self.gates = S.sim_gates_from_ops(w.ops)
-        self.cfg = S.sim_config(n_qubits=w.n_qubits, capacity=w.capacity, eps=w.eps)
+        self.knobs = autotune.state_knobs(w.n_qubits, w.capacity, {}) if tuned else {}
+        self.cfg = S.sim_config(n_qubits=w.n_qubits, capacity=w.capacity, eps=w.eps, **self.knobs)
 
 
-def prepare(trace):
-    return [Prepared(t, w) for t, w in trace]
+def prepare(trace, tuned: bool = False):
+    return [Prepared(t, w, tuned) for t, w in trace]
 
 
 def _pct(xs, p):
@@ -59,8 +70,8 @@ def run_one_at_a_time(reqs, arrivals=True, keep_results=False, tuning: dict | No
             wait = t0 + r.arrival - time.perf_counter()
             if wait > 0:
                 time.sleep(wait)
-        k = autotune.lookup(tuning, r.w.n_qubits, r.w.capacity) if tuning else {}
-        s = S.Simulator(r.w.n_qubits, r.w.capacity, r.w.eps, **k)
+        k = autotune.lookup(tuning, r.w.n_qubits, r.w.capacity) if tuning else r.knobs
+        s = S.Simulator(r.w.n_qubits, r.w.capacity, r.w.eps, tuned=False, **k)
         s.set_basis(*r.w.basis)
         rc, outs, st = s.apply_gates(r.gates, raise_on_error=False)
         state = s.export(sort=False) if rc == 0 else None
@@ -77,11 +88,12 @@ def run_one_at_a_time(reqs, arrivals=True, keep_results=False, tuning: dict | No
 
 
 def run_batched(reqs, budget_bytes: int, max_slots: int = 256, arrivals=True, keep_results=False, graph=True,
-                tick_updates: int = 0, grid: int = 0, lane_capacity: int = 0, lane_workers: int = 0,
-                tuning: dict | None = None):
+                tick_updates: int | None = None, grid: int | None = None, lane_capacity: int | None = None,
+                lane_workers: int | None = None, tuning: dict | None = None):
     """Replay through the continuous-batching server (open loop when
-    arrivals, else every request at time 0).  tuning: optional autotuner
-    table; each request then runs with the knobs of its bucket."""
+    arrivals, else every request at time 0).  Server knobs left None take the
+    autotuner table's values.  tuning: optional table replacing each
+    request's knobs by its bucket's."""
     from . import autotune
 
     srv = S.Server(budget_bytes, max_slots=max_slots, graph=graph, tick_updates=tick_updates, grid=grid,
@@ -127,6 +139,7 @@ def run_batched(reqs, budget_bytes: int, max_slots: int = 256, arrivals=True, ke
     srv.close()
     out = _summary("batched", reqs, done, 0.0, t_end, updates, arrivals)
     out["server"] = stats
+    out["server_knobs"] = dict(srv.knobs)
     return out, results
 
 

@@ -311,14 +311,24 @@ def sim_kernel_stats_reset(h):
 
 # --- convenience wrapper -----------------------------------------------------
 class Simulator:
-    """One sparse state on the current torch device and stream."""
+    """One sparse state on the current torch device and stream.
 
-    def __init__(self, n_qubits: int, capacity: int, eps: float = 0.0, fuse_max: int = 0,
-                 load_factor: float = 0.0, block: int = 0, mono_mode: int = 0, bs_min_gates: int = 0,
-                 flags: int = 0, device: str = "cuda"):
-        self.cfg = sim_config(n_qubits=n_qubits, fuse_max=fuse_max, capacity=capacity, eps=eps,
-                              load_factor=load_factor, block=block, flags=flags, mono_mode=mono_mode,
-                              bs_min_gates=bs_min_gates)
+    Launch knobs left as None take the committed autotuner table's values for
+    this state's bucket (autotune.state_knobs), or the library defaults with
+    tuned=False or SPARSESIM_TUNING=off; `knobs` records what was used."""
+
+    def __init__(self, n_qubits: int, capacity: int, eps: float = 0.0, fuse_max: int | None = None,
+                 load_factor: float | None = None, block: int | None = None, mono_mode: int | None = None,
+                 bs_min_gates: int | None = None, flags: int | None = None, device: str = "cuda",
+                 tuned: bool = True):
+        from . import autotune
+        given = {"fuse_max": fuse_max, "load_factor": load_factor, "block": block, "mono_mode": mono_mode,
+                 "bs_min_gates": bs_min_gates, "flags": flags}
+        if tuned:
+            self.knobs = autotune.state_knobs(n_qubits, capacity, given)
+        else:
+            self.knobs = {k: (v if v is not None else 0) for k, v in given.items()}
+        self.cfg = sim_config(n_qubits=n_qubits, capacity=capacity, eps=eps, **self.knobs)
         nbytes = sim_workspace_bytes(self.cfg)
         if nbytes == 0:
             raise SimError(SIM_E_ARG, "sim_workspace_bytes")
@@ -519,11 +529,18 @@ class Server:
     budget_bytes borrowed from torch."""
 
     def __init__(self, budget_bytes: int, max_slots: int = 256, arena_bytes: int = 0, graph: bool = True,
-                 tick_updates: int = 0, grid: int = 0, lane_capacity: int = 0, lane_workers: int = 0,
-                 device: str = "cuda"):
+                 tick_updates: int | None = None, grid: int | None = None, lane_capacity: int | None = None,
+                 lane_workers: int | None = None, device: str = "cuda", tuned: bool = True):
+        """Server knobs left as None take the autotuner table's values (the
+        library defaults with tuned=False); `knobs` records what was used.
+        submit_workload applies the table's per-state knobs the same way."""
+        from . import autotune
+        given = {"tick_updates": tick_updates, "grid": grid, "lane_capacity": lane_capacity,
+                 "lane_workers": lane_workers}
+        self.tuned = tuned
+        self.knobs = autotune.server_knobs(given) if tuned else {k: (v or 0) for k, v in given.items()}
         self.cfg = srv_config(budget_bytes=budget_bytes, arena_bytes=arena_bytes, max_slots=max_slots,
-                              flags=0 if graph else SRV_FLAG_NO_GRAPH, tick_updates=tick_updates, grid=grid,
-                              lane_capacity=lane_capacity, lane_workers=lane_workers)
+                              flags=0 if graph else SRV_FLAG_NO_GRAPH, **self.knobs)
         self.pool = torch.empty(budget_bytes, dtype=torch.uint8, device=device)
         self.h = srv_create(self.cfg, None, self.pool.data_ptr(), budget_bytes)
 
@@ -539,7 +556,9 @@ class Server:
             pass
 
     def submit_workload(self, w, **tuning) -> int:
-        cfg = sim_config(n_qubits=w.n_qubits, capacity=w.capacity, eps=w.eps, **tuning)
+        from . import autotune
+        knobs = autotune.state_knobs(w.n_qubits, w.capacity, tuning) if self.tuned else tuning
+        cfg = sim_config(n_qubits=w.n_qubits, capacity=w.capacity, eps=w.eps, **knobs)
         return srv_submit(self.h, cfg, sim_gates_from_ops(w.ops), w.basis)
 
     def submit(self, cfg: sim_config, gates: np.ndarray, basis=(0, 0)) -> int:

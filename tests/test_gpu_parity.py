@@ -782,7 +782,7 @@ def test_regplane_reproducible_on_large_states(sim, req):
     gates = sim.sim_gates_from_ops(w.ops)
 
     def plain(**kw):
-        s = sim.Simulator(w.n_qubits, w.capacity, w.eps, **kw)
+        s = sim.Simulator(w.n_qubits, w.capacity, w.eps, tuned=False, **kw)   # register planes unless kw
         s.set_basis(*w.basis)
         _, outs, st = s.apply_gates(gates)
         out = s.export()
@@ -818,7 +818,7 @@ def test_regplane_passes_on_two_streams(sim):
 
     def run(w, g, stream=None):
         with torch.cuda.stream(stream or torch.cuda.current_stream()):
-            s = sim.Simulator(w.n_qubits, w.capacity, w.eps)
+            s = sim.Simulator(w.n_qubits, w.capacity, w.eps, tuned=False)   # register planes
             s.set_basis(*w.basis)
             _, _, st = s.apply_gates(g)
             out = s.export()
