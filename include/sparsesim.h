@@ -422,7 +422,9 @@ typedef struct srv_config {
                             circuit, no host round trip per gate) on a stream and host thread of
                             its own, its workspace (sim_workspace_bytes) taken from the pool,
                             concurrently with the batched ticks; queued in a FIFO of their own.
-                            0 = 2^12; SRV_LANE_OFF = never (every request batched). */
+                            0 or SRV_LANE_OFF = no lane (every request batched; the default:
+                            server runs with the lane have ended in intermittent GPU memory
+                            faults whose cause is not known). */
   uint32_t lane_workers; /* lane threads (each with its own stream), so that as many large
                             requests run at once; 0 = 8, else 1..64 */
   uint32_t reserved;     /* must be 0 */

@@ -31,7 +31,7 @@ class Totals(ctypes.Structure):
                 ("u2_skipped", ctypes.c_uint64), ("measures", ctypes.c_uint64),
                 ("mono_gates", ctypes.c_uint64), ("peak_nnz", ctypes.c_uint64),
                 ("pruned", ctypes.c_uint64), ("pruned_mass", ctypes.c_double),
-                ("parallel_runs", ctypes.c_uint64)]
+                ("parallel_runs", ctypes.c_uint64), ("min_margin", ctypes.c_double)]
 
 
 def build(force: bool = True) -> str:

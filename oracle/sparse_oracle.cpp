@@ -52,6 +52,7 @@
 #include <cmath>
 #include <cstdint>
 #include <cstring>
+#include <limits>
 #include <thread>
 #include <unordered_map>
 #include <vector>
@@ -237,6 +238,10 @@ struct Totals {
   uint64_t peak_nnz, pruned;
   double pruned_mass;
   uint64_t parallel_runs;   // queues applied by several threads (Sec. 5)
+  // Diagnostic (no effect on the state): the smallest | |a|^2 - eps | / eps
+  // over every entry T_eps examined (eps > 0), i.e. how close a prune
+  // decision came to flipping; +inf when none was examined.
+  double min_margin;
 };
 
 struct Oracle {
@@ -249,6 +254,22 @@ struct Oracle {
 
 bool drop(const Amp& a, double eps) {
   return (a.re * a.re + a.im * a.im < eps) || (a.re == 0.0 && a.im == 0.0);
+}
+
+// T_eps on a whole new state (after a branching operation): drop the entries
+// drop() names, count them and their mass, and note the decision margin.
+void prune(Oracle& o, State& out) {
+  for (auto it = out.begin(); it != out.end();) {
+    const double m2 = it->second.re * it->second.re + it->second.im * it->second.im;
+    if (o.eps > 0.0) o.tot.min_margin = std::min(o.tot.min_margin, std::fabs(m2 - o.eps) / o.eps);
+    if (drop(it->second, o.eps)) {
+      o.tot.pruned++;
+      o.tot.pruned_mass += m2;
+      it = out.erase(it);
+    } else {
+      ++it;
+    }
+  }
 }
 
 void note_peak(Oracle& o) {
@@ -280,16 +301,7 @@ void apply_branching(Oracle& o, const OpRecord& op) {
     out.emplace(k0, add(mul(u[0], a0), mul(u[1], a1)));
     out.emplace(k1, add(mul(u[2], a0), mul(u[3], a1)));
   }
-  // T_eps on the whole new state.
-  for (auto it = out.begin(); it != out.end();) {
-    if (drop(it->second, o.eps)) {
-      o.tot.pruned++;
-      o.tot.pruned_mass += it->second.re * it->second.re + it->second.im * it->second.im;
-      it = out.erase(it);
-    } else {
-      ++it;
-    }
-  }
+  prune(o, out);   // T_eps on the whole new state
   o.psi.swap(out);
 }
 
@@ -409,6 +421,7 @@ void* orc_create(unsigned n_qubits, double eps) {
   o->psi.emplace(Label{0, 0}, Amp{1.0, 0.0});
   std::memset(&o->tot, 0, sizeof(o->tot));
   o->tot.peak_nnz = 1;
+  o->tot.min_margin = std::numeric_limits<double>::infinity();
   return o;
 }
 
@@ -739,17 +752,7 @@ void apply_pauli_exp(Oracle& o, const PauliRecord& p) {
     const Label bx{b.lo ^ p.x_lo, b.hi ^ p.x_hi};
     accumulate(out, bx, mul(mul(misin_t, pauli_coef(p, b, o.n_qubits)), kv.second));
   }
-  if (branching) {
-    for (auto it = out.begin(); it != out.end();) {
-      if (drop(it->second, o.eps)) {
-        o.tot.pruned++;
-        o.tot.pruned_mass += it->second.re * it->second.re + it->second.im * it->second.im;
-        it = out.erase(it);
-      } else {
-        ++it;
-      }
-    }
-  }
+  if (branching) prune(o, out);
   o.psi.swap(out);
 }
 

@@ -9,10 +9,9 @@ survive; they change speed and, between fused-pass kernels, floating-point
 rounding only.
 
 Server knobs: the capacity from which a request takes the large-state lane
-(lane_capacity), the lane's worker count (lane_workers), the tick kernels'
-grid (grid) and the per-tick cap on a request's fused work (tick_updates),
-tuned for the makespan of a reduced serving trace with every request
-submitted at once.
+(lane_capacity) and the lane's worker count (lane_workers), tuned for the p99
+latency of a reduced serving trace replayed at 0.8x the one-at-a-time rate
+(the tick grid and per-tick cap stay at their defaults).
 
 For each bucket (label width: <= 64 qubits or more; state size: log2 of the
 capacity) a representative random circuit of that size is timed on one live
@@ -49,7 +48,10 @@ SERVER_SPACE = {
     "lane_capacity": [1 << 10, 1 << 12, 1 << 14, 1 << 16],
     "lane_workers": [4, 8],
 }
-SERVER_DEFAULTS = {"lane_capacity": 1 << 12, "lane_workers": 8, "grid": 2048, "tick_updates": 0}
+# The lane is off by default (lane_capacity 0): server runs with it ended in
+# intermittent GPU memory faults whose cause is not known, so it is neither
+# used nor tuned by default.
+SERVER_DEFAULTS = {"lane_capacity": 0, "lane_workers": 8, "grid": 2048, "tick_updates": 0}
 
 
 def bucket_key(n_qubits: int, capacity: int) -> str:
@@ -120,7 +122,7 @@ def representative(W, n_qubits: int, log2cap: int, gates: int, seed: int = 99):
 
 
 def tune(buckets=((24, 12), (24, 16), (100, 16), (100, 20), (100, 22)), gates: int = 20_000,
-         repeats: int = 3, sweeps: int = 1, cache: str | None = DEFAULT_CACHE, server: bool = True,
+         repeats: int = 3, sweeps: int = 1, cache: str | None = DEFAULT_CACHE, server: bool = False,
          min_gain: float = 0.03, log=print):
     """Tune every (n_qubits, log2 capacity) bucket on the GPU, then (server)
     the server knobs; returns the table and writes it to `cache` (JSON)
@@ -159,30 +161,39 @@ def tune(buckets=((24, 12), (24, 16), (100, 16), (100, 20), (100, 22)), gates: i
     return table
 
 
-def tune_server(requests: int = 160, max_log2: int = 20, max_gates: int = 20_000, repeats: int = 2,
+def tune_server(requests: int = 128, max_log2: int = 22, max_gates: int = 100_000, repeats: int = 2,
                 budget_gib: int = 32, min_gain: float = 0.03, log=print) -> dict:
-    """Greedy search over SERVER_SPACE for the makespan of a reduced serving
-    trace (seed 7: config-0..2 families, caps 2^8..2^max_log2, 1e3..max_gates
-    gates), every request submitted at once with the default per-state knobs.
-    (The tick grid and the per-tick cap are not searched: they stay at their
-    defaults.)"""
+    """Greedy search over SERVER_SPACE for the p99 latency of a reduced
+    serving trace (seed 7: config-0..2 families, caps 2^8..2^max_log2,
+    1e3..max_gates gates) replayed open loop at 0.8x the one-at-a-time service
+    rate (measured first, closed loop, on the same requests), with the default
+    per-state knobs.  (The tick grid and the per-tick cap are not searched:
+    they stay at their defaults.)"""
     from . import serving, workloads as W
 
     trace = W.serving_trace(7, requests=requests, rate=1.0, cap_log2=(8, max_log2), gates_range=(1000, max_gates))
     reqs = serving.prepare(trace, tuned=False)
+    closed, _ = serving.run_one_at_a_time(reqs, arrivals=False)
+    rate = 0.8 * closed["requests_per_s"]
+    for r, (t, _) in zip(reqs, trace):
+        r.arrival = t / rate
 
     def measure(knobs):
-        ts = []
+        ps = []
         for _ in range(repeats):
-            out, _ = serving.run_batched(reqs, budget_gib << 30, arrivals=False, **knobs)
-            ts.append(out["makespan_s"])
-        return min(ts)
+            out, _ = serving.run_batched(reqs, budget_gib << 30, arrivals=True, **knobs)
+            ps.append(out["p99_ms"] * 1e-3)
+        return min(ps)
 
+    base, _ = serving.run_one_at_a_time(reqs, arrivals=True)
     measure(SERVER_DEFAULTS)                           # warm
     best, best_t, trials = greedy_search(measure, space=SERVER_SPACE, start=SERVER_DEFAULTS, min_gain=min_gain)
-    log(f"[autotune] server: {best} {best_t * 1e3:.1f} ms (default {trials[0][1] * 1e3:.1f} ms)")
-    return {"knobs": best, "seconds": best_t, "default_seconds": trials[0][1], "trials": len(trials),
-            "trace": f"{requests} requests (seed 7), caps 2^8..2^{max_log2}, 1e3..{max_gates} gates, all at t=0"}
+    log(f"[autotune] server: {best} p99 {best_t * 1e3:.1f} ms (default {trials[0][1] * 1e3:.1f} ms; "
+        f"one at a time {base['p99_ms']:.1f} ms at {rate:.1f} requests/s)")
+    return {"knobs": best, "p99_s": best_t, "default_p99_s": trials[0][1], "one_at_a_time_p99_s": base["p99_ms"] * 1e-3,
+            "rate_per_s": rate, "trials": len(trials),
+            "trace": f"{requests} requests (seed 7), caps 2^8..2^{max_log2}, 1e3..{max_gates} gates, Poisson at "
+                     f"0.8x the one-at-a-time rate"}
 
 
 def load(cache: str = DEFAULT_CACHE) -> dict:
@@ -210,6 +221,7 @@ if __name__ == "__main__":
     ap.add_argument("--out", default=DEFAULT_CACHE)
     ap.add_argument("--gates", type=int, default=20_000)
     ap.add_argument("--repeats", type=int, default=3)
-    ap.add_argument("--no-server", action="store_true", help="tune the per-state buckets only")
+    ap.add_argument("--server", action="store_true",
+                    help="also tune the server's lane knobs (runs the large-state lane; see SERVER_DEFAULTS)")
     args = ap.parse_args()
-    tune(gates=args.gates, repeats=args.repeats, cache=args.out, server=not args.no_server)
+    tune(gates=args.gates, repeats=args.repeats, cache=args.out, server=args.server)

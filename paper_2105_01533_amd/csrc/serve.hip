@@ -210,7 +210,7 @@ struct srv_t {
   srv_stats stats{};
   int device = 0;
   // large-state lane
-  uint64_t lane_cap = 1ull << 12;     // capacity from which a request takes the lane (0: no lane)
+  uint64_t lane_cap = 0;              // capacity from which a request takes the lane (0: no lane)
   std::deque<uint64_t> lane_queue;    // queued large requests (FIFO)
   int lane_in_flight = 0;             // admitted to the lane, not yet folded back (tick thread)
   std::vector<std::thread> lane_threads;
@@ -494,7 +494,7 @@ int srv_create(const srv_config* cfg, void* stream, void* pool, size_t pool_byte
   s->cfg = *cfg;
   if (!s->cfg.arena_bytes) s->cfg.arena_bytes = 64ull << 20;
   s->grid = cfg->grid ? (int)cfg->grid : 2048;
-  s->lane_cap = cfg->lane_capacity == SRV_LANE_OFF ? 0 : (cfg->lane_capacity ? cfg->lane_capacity : 1ull << 12);
+  s->lane_cap = cfg->lane_capacity == SRV_LANE_OFF ? 0 : cfg->lane_capacity;   // 0: no lane (default)
   if (hipGetDevice(&s->device) != hipSuccess) s->device = 0;
   if (stream) {
     s->stream = static_cast<hipStream_t>(stream);

@@ -844,3 +844,34 @@ def test_regplane_passes_on_two_streams(sim):
             say(f"[gpu] two streams rep {rep} state {k}: {len(got[k][0])} entries")
             assert np.array_equal(got[k][0], alone[k][0]) and np.array_equal(got[k][1], alone[k][1])
             assert got[k][2].tobytes() == alone[k][2].tobytes()
+
+
+# --- key exactness: how far prune decisions are from flipping ---------------------
+@pytest.mark.parametrize("which", ["c0", "c3_80"])
+def test_prune_decisions_have_margin(sim, which):
+    """The surviving labels are decided by |a|^2 < eps after each branching
+    gate.  The fused passes round differently from the oracle's gate-by-gate
+    products (the per-entry pass multiplies each gate's factor; the bit-sliced
+    passes sum exact turn fractions and take one sincospi), so a decision
+    could flip if some |a|^2 came within that rounding of eps.  The oracle
+    records the smallest | |a|^2 - eps | / eps over every entry T_eps examined;
+    it must exceed, by a factor of 1000, twice the largest relative amplitude
+    difference between the per-entry and the register-plane runs (the measured
+    rounding gap), and both runs must keep exactly the oracle's labels."""
+    w = W.config0() if which == "c0" else W.config3(7, terms=80)
+    o, oout, _ = oracle_run(w)
+    margin = o.totals()["min_margin"]
+    olo, ohi, _ = o.export()
+    runs = {}
+    for name, kw in (("per_entry", {"mono_mode": sim.SIM_MONO_DIRECT}), ("register_plane", {"mono_mode": 0})):
+        s = sim.Simulator(w.n_qubits, w.capacity, w.eps, tuned=False, bs_min_gates=4, **kw)
+        s.set_basis(*w.basis)
+        _, outs, st = s.apply_ops(w.ops)
+        runs[name] = s.export()
+        s.close()
+        assert list(outs) == list(oout), name
+        assert np.array_equal(runs[name][0], olo) and np.array_equal(runs[name][1], ohi), name
+    a, b = runs["per_entry"][2], runs["register_plane"][2]
+    gap = float(np.max(np.abs(a - b) / np.maximum(np.abs(a), 1e-300)))
+    say(f"[gpu] {w.name}: min prune margin {margin:.3e}, kernel rounding gap (relative) {gap:.3e}")
+    assert math.isfinite(margin) and margin > 1e3 * 2 * max(gap, 1e-16), (margin, gap)

@@ -181,6 +181,8 @@ def test_arena_too_small_is_rejected(S):
         S.Server(1 << 24, max_slots=4, arena_bytes=1 << 16)
 
 
+@pytest.mark.skip(reason="the large-state lane is off: server runs with it ended in intermittent GPU "
+                         "memory faults whose cause has not been found")
 def test_large_lane_matches_single_state_and_oracle(S):
     """With the lane threshold at 2^12 entries, the mix's larger requests run
     whole through the single-state engine on the lane while the rest are
@@ -210,6 +212,8 @@ def test_large_lane_matches_single_state_and_oracle(S):
     srv.close()
 
 
+@pytest.mark.skip(reason="the large-state lane is off: server runs with it ended in intermittent GPU "
+                         "memory faults whose cause has not been found")
 def test_large_lane_fifo_and_failures(S):
     """Lane requests queue in their own FIFO, are admitted by pool memory,
     and a failing one (capacity exceeded) fails alone."""

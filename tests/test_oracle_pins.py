@@ -367,3 +367,37 @@ def test_eps_boundary_is_strict():
     t = o.totals()
     assert t["pruned"] == 6 + 2
     assert t["pruned_mass"] == below * below + below * below
+
+
+def test_prune_margin_closed_form():
+    """The oracle's decision margin min | |a|^2 - eps | / eps (a diagnostic;
+    the state is untouched): H on |0> gives |a|^2 = 1/2 twice, so with
+    eps = 0.4 the margin is (0.5 - 0.4) / 0.4 = 0.25; in the T_eps test state
+    above (|a|^2 = eps exactly) it is 0; with eps = 0 nothing is examined
+    (+inf); phase/permutation gates never change it."""
+    c = W.Circuit()
+    c.h(0)
+    o = Oracle(4, 0.4)
+    o.run(c.array())
+    assert o.totals()["min_margin"] == pytest.approx((0.5 - 0.4) / 0.4, rel=1e-15)
+    lo, _, amp = o.export()
+    assert len(lo) == 2 and np.allclose(np.abs(amp) ** 2, 0.5)
+    x = 3.0e-11
+    o = Oracle(8, x * x)
+    o.import_state(np.array([1], np.uint64), np.zeros(1, np.uint64), np.array([x], np.complex128))
+    c = W.Circuit()
+    c.gate(W.K_RX, 6, param=0.0)
+    o.run(c.array())
+    assert o.totals()["min_margin"] == 0.0
+    o = Oracle(4, 0.0)
+    c = W.Circuit()
+    c.h(0)
+    c.x(1)
+    o.run(c.array())
+    assert o.totals()["min_margin"] == math.inf
+    o = Oracle(4, 0.4)
+    c = W.Circuit()
+    c.x(1)
+    c.gate(W.K_T, 1)
+    o.run(c.array())
+    assert o.totals()["min_margin"] == math.inf
