@@ -317,6 +317,12 @@ int sim_sync(sim_t* s);
  * copied and SIM_E_BUFFER is returned.  Synchronizes. */
 int sim_export_state(sim_t* s, sim_key* keys, sim_c64* amps, uint64_t cap, uint64_t* nnz);
 
+/* The same into separate arrays: key_lo[i] and key_hi[i] are the low and
+ * high 64 bits of entry i's label (key_hi may be NULL when the high words are
+ * not wanted; zeros for <= 64 qubits), amps[i] its amplitude.  Arrays of cap
+ * entries, caller-owned; sizes and errors as sim_export_state. */
+int sim_export_state_soa(sim_t* s, uint64_t* key_lo, uint64_t* key_hi, sim_c64* amps, uint64_t cap, uint64_t* nnz);
+
 /* Device addresses of the current state buffers (key_lo, key_hi, amp) and
  * the device nnz word, for zero-copy inspection; valid until the next call. */
 int sim_device_state(sim_t* s, uint64_t** key_lo, uint64_t** key_hi, double** amp, uint64_t** d_nnz);
@@ -443,6 +449,12 @@ typedef struct srv_stats {
   double group_ms;          /* of host_ms: grouping fused runs for the bit-sliced form */
   uint64_t lane_completed;  /* requests finished (done or failed) on the large-state lane */
   double lane_ms;           /* wall time the lane spent running requests */
+  uint64_t ahead_hits;      /* fused runs whose grouping was made during the previous tick */
+  double ahead_ms;          /* of host_ms: work done while a tick ran on the GPU (copying out
+                               finished states, grouping expected next runs, compiling queued
+                               requests) */
+  double copy_ms;           /* copying finished states to host memory, summed over the
+                               host threads that did it */
 } srv_stats;
 
 typedef struct srv_t srv_t;
@@ -480,6 +492,11 @@ int srv_poll(srv_t* s, uint64_t id, int32_t* state, int32_t* error);
  * *n_out receive the sizes; SIM_E_BUFFER if a buffer is too small. */
 int srv_result(srv_t* s, uint64_t id, sim_key* keys, sim_c64* amps, uint64_t cap, uint64_t* nnz, int32_t* outcomes,
                uint64_t out_cap, uint64_t* n_out, sim_stats* stats);
+
+/* srv_result into separate arrays, as sim_export_state_soa (key_hi may be
+ * NULL); sizes and errors as srv_result. */
+int srv_result_soa(srv_t* s, uint64_t id, uint64_t* key_lo, uint64_t* key_hi, sim_c64* amps, uint64_t cap,
+                   uint64_t* nnz, int32_t* outcomes, uint64_t out_cap, uint64_t* n_out, sim_stats* stats);
 
 /* Forget a finished or failed request's host-side result. */
 int srv_release(srv_t* s, uint64_t id);

@@ -9,7 +9,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libsparsesim.so")
 SOURCES = ["sim_api.hip", "sim_kernels.hip", "mono_bitslice.hip", "mono_regplane.hip", "run_compiler.hip", "batch_kernels.hip",
-           "serve.hip", "commute.hip", "pauli.hip"]
+           "serve.hip", "commute.hip", "pauli.hip", "state_copy.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 FLAGS = [

@@ -18,7 +18,7 @@ namespace sparsesim {
 
 class HostPool {
  public:
-  static constexpr unsigned kMaxThreads = 8;   // including the caller
+  static constexpr unsigned kMaxThreads = 16;  // including the caller
 
   static HostPool& get() {
     static HostPool pool;

@@ -150,11 +150,32 @@ Footprint footprint_of(const sim_config& c, double lf) {
 
 enum SegKind { SEG_NONE = 0, SEG_MONO, SEG_U2, SEG_MEAS };
 
+// Allocator whose resize leaves new elements uninitialised (they are written
+// whole right after).
+template <class T>
+struct NoInit : std::allocator<T> {
+  template <class U>
+  struct rebind {
+    using other = NoInit<U>;
+  };
+  NoInit() = default;
+  template <class U>
+  NoInit(const NoInit<U>&) noexcept {}
+  template <class U>
+  void construct(U* p) noexcept {
+    ::new (static_cast<void*>(p)) U;
+  }
+  template <class U, class... A>
+  void construct(U* p, A&&... a) {
+    ::new (static_cast<void*>(p)) U(std::forward<A>(a)...);
+  }
+};
+
 struct Request {
   uint64_t id = 0;
   sim_config cfg{};
   sim_key basis{};
-  std::vector<sim_gate> gates;
+  std::vector<sim_gate, NoInit<sim_gate>> gates;
   std::vector<size_t> mono_op;        // MONO ordinal -> op index
   RunCompiler rc;
   bool compiled = false;              // descriptors and bit-sliced ops built (at admission)
@@ -174,14 +195,32 @@ struct Request {
   size_t i = 0;
   size_t mono_seen = 0;
   bool deferred = false;              // its last fused run did not fit the tick's arena
+  bool copied = false;                // final state copied to keys/amps
+  // Grouping of the fused run expected next, made while the previous tick ran
+  // on the GPU; used only if the run that comes is exactly [b, b + len).
+  struct Ahead {
+    bool valid = false;
+    size_t b = 0, len = 0;
+    BsRun br{};
+    std::vector<BsGroup> grp;
+  } ahead;
   bool large = false;                 // runs on the large-state lane
   int lane_rc = SIM_OK;               // the lane's result code
   SegKind seg = SEG_NONE;
   sim_stats st{};
   std::vector<int32_t> outcomes;
-  // result
-  std::vector<sim_key> keys;
-  std::vector<sim_c64> amps;
+  // result (storage order; res_hi only for more than 64 qubits)
+  uint64_t res_n = 0;
+  std::unique_ptr<uint64_t[]> res_lo, res_hi;
+  std::unique_ptr<sim_c64[]> res_amp;
+
+  // Result arrays for n entries (left uninitialised: they are written whole).
+  void alloc_result(uint64_t n) {
+    res_n = n;
+    res_lo.reset(new uint64_t[std::max<uint64_t>(n, 1)]);
+    res_hi.reset(cfg.n_qubits > 64 ? new uint64_t[std::max<uint64_t>(n, 1)] : nullptr);
+    res_amp.reset(new sim_c64[std::max<uint64_t>(n, 1)]);
+  }
 };
 
 }  // namespace
@@ -240,8 +279,6 @@ int capture_tick(srv_t* s) {
   return SIM_OK;
 }
 
-// Next segment of r, consuming skipped branching gates; sets r.seg and the
-// run [begin, begin + len) of MONO ordinals or the op index of the gate.
 // Longest fused run whose ops always fit an empty arena (bit-sliced groups or
 // per-entry descriptors, worst case): a run is cut there whatever else shares
 // the tick, so a request's runs -- and with them its rounding -- are the same
@@ -255,29 +292,38 @@ uint64_t arena_run_cap(const srv_t* s, const Request& r) {
   return std::max<uint64_t>(1, std::min(by_groups, by_desc));
 }
 
-SegKind next_segment(srv_t* s, Request& r, size_t* begin, size_t* len, size_t* op) {
+// Position in a request's op list.
+struct Cursor {
+  size_t i, mono_seen;
+  uint64_t skipped;   // branching gates skipped by the cap
+};
+
+// The segment that starts at c for a state of nnz entries; advances c past it.
+// Reads only the request's ops and configuration.
+SegKind scan_segment(const srv_t* s, const Request& r, uint64_t nnz, Cursor& c, size_t* begin, size_t* len,
+                     size_t* op) {
   uint64_t fuse_max = r.cfg.fuse_max ? r.cfg.fuse_max : 65536u;
-  if (s->cfg.tick_updates) fuse_max = std::min<uint64_t>(fuse_max, std::max<uint64_t>(1, s->cfg.tick_updates / std::max<uint64_t>(r.nnz, 1)));
+  if (s->cfg.tick_updates) fuse_max = std::min<uint64_t>(fuse_max, std::max<uint64_t>(1, s->cfg.tick_updates / std::max<uint64_t>(nnz, 1)));
   fuse_max = std::min<uint64_t>(fuse_max, arena_run_cap(s, r));
-  size_t run_len = 0, run_begin = r.mono_seen;
+  size_t run_len = 0, run_begin = c.mono_seen;
   const size_t n = r.gates.size();
-  while (r.i < n) {
-    const sim_gate& g = r.gates[r.i];
+  while (c.i < n) {
+    const sim_gate& g = r.gates[c.i];
     if (g.op == SIM_OP_MONO) {
-      if (!run_len) run_begin = r.mono_seen;
+      if (!run_len) run_begin = c.mono_seen;
       ++run_len;
-      ++r.mono_seen;
-      ++r.i;
+      ++c.mono_seen;
+      ++c.i;
       if (run_len >= fuse_max) break;
       continue;
     }
-    if (g.op == SIM_OP_U2 && g.cap && 2 * r.nnz > g.cap) {
-      r.st.u2_skipped++;
-      ++r.i;
+    if (g.op == SIM_OP_U2 && g.cap && 2 * nnz > g.cap) {
+      ++c.skipped;
+      ++c.i;
       continue;
     }
     if (run_len) break;
-    *op = r.i++;
+    *op = c.i++;
     return g.op == SIM_OP_U2 ? SEG_U2 : SEG_MEAS;
   }
   if (run_len) {
@@ -288,20 +334,34 @@ SegKind next_segment(srv_t* s, Request& r, size_t* begin, size_t* len, size_t* o
   return SEG_NONE;
 }
 
+// Next segment of r, consuming skipped branching gates; sets r.seg and the
+// run [begin, begin + len) of MONO ordinals or the op index of the gate.
+SegKind next_segment(srv_t* s, Request& r, size_t* begin, size_t* len, size_t* op) {
+  Cursor c{r.i, r.mono_seen, 0};
+  const SegKind k = scan_segment(s, r, r.nnz, c, begin, len, op);
+  r.i = c.i;
+  r.mono_seen = c.mono_seen;
+  r.st.u2_skipped += c.skipped;
+  return k;
+}
+
+// The request's final state into its host result.  Touches only r, so it
+// may run for several requests at once on the host thread pool.
+hipError_t copy_out(Request& r) {
+  r.alloc_result(r.nnz);
+  const Buf& b = r.buf[r.cur];
+  const bool wide = r.cfg.n_qubits > 64;
+  const hipError_t e = copy_state_to_host_soa(b.key_lo, wide ? b.key_hi : nullptr, b.amp, r.nnz, r.res_lo.get(),
+                                              wide ? r.res_hi.get() : nullptr, r.res_amp.get());
+  if (e == hipSuccess) r.copied = true;
+  return e;
+}
+
 int finish(srv_t* s, Request& r, int32_t state, int32_t err) {
   r.state = state;
   r.error = err;
   if (state == SRV_DONE) {
-    const uint64_t n = r.nnz;
-    std::vector<uint64_t> lo(n), hi(n, 0);
-    r.amps.resize(n);
-    r.keys.resize(n);
-    if (n) {
-      SRV_HIP(hipMemcpy(lo.data(), r.buf[r.cur].key_lo, n * 8, hipMemcpyDeviceToHost));
-      if (r.cfg.n_qubits > 64) SRV_HIP(hipMemcpy(hi.data(), r.buf[r.cur].key_hi, n * 8, hipMemcpyDeviceToHost));
-      SRV_HIP(hipMemcpy(r.amps.data(), r.buf[r.cur].amp, n * 16, hipMemcpyDeviceToHost));
-    }
-    for (uint64_t k = 0; k < n; ++k) r.keys[k] = sim_key{lo[k], hi[k]};
+    if (!r.copied) SRV_HIP(copy_out(r));
     r.st.gates_applied = r.gates.size();
     s->stats.completed++;
   } else {
@@ -314,6 +374,7 @@ int finish(srv_t* s, Request& r, int32_t state, int32_t err) {
   r.gates.clear();
   r.gates.shrink_to_fit();
   r.rc = RunCompiler{};
+  r.ahead = Request::Ahead{};
   return SIM_OK;
 }
 
@@ -345,10 +406,9 @@ void lane_run(srv_t* s, Request& r, hipStream_t stream) {
   uint64_t n = 0;
   if (rc == SIM_OK) rc = sim_nnz(h, &n);
   if (rc == SIM_OK) {
-    r.keys.resize(n);
-    r.amps.resize(n);
+    r.alloc_result(n);
     uint64_t got = 0;
-    rc = sim_export_state(h, r.keys.data(), r.amps.data(), n, &got);
+    rc = sim_export_state_soa(h, r.res_lo.get(), r.res_hi.get(), r.res_amp.get(), n, &got);
   }
   if (h) (void)sim_destroy(h);
   r.outcomes.assign(outs.begin(), outs.begin() + std::min<size_t>(outs.size(), r.st.measures));
@@ -586,10 +646,24 @@ int srv_submit(srv_t* s, const sim_config* cfg, const sim_gate* gates, size_t n,
   }
   if (r->fp.total > s->pool.size) return sfail(SIM_E_CAPACITY, "request footprint exceeds the pool");
   r->basis = basis;
-  r->gates.assign(gates, gates + n);
-  std::string why;
-  for (size_t i = 0; i < n; ++i)
-    if (!gate_valid(cfg->n_qubits, gates[i], &why)) return sfail(SIM_E_ARG, "op " + std::to_string(i) + ": " + why);
+  // Copy and validate on the host thread pool; the first invalid op is reported.
+  r->gates.resize(n);
+  std::vector<size_t> bad(HostPool::kMaxThreads, SIZE_MAX);
+  parallel_parts(n, 16384, [&](size_t b, size_t e, size_t p) {
+    std::memcpy(r->gates.data() + b, gates + b, (e - b) * sizeof(sim_gate));
+    std::string ignored;
+    for (size_t i = b; i < e; ++i)
+      if (!gate_valid(cfg->n_qubits, gates[i], &ignored)) {
+        bad[p] = i;
+        break;
+      }
+  });
+  const size_t first_bad = *std::min_element(bad.begin(), bad.end());
+  if (first_bad != SIZE_MAX) {
+    std::string why;
+    gate_valid(cfg->n_qubits, gates[first_bad], &why);
+    return sfail(SIM_E_ARG, "op " + std::to_string(first_bad) + ": " + why);
+  }
   r->id = s->next_id++;
   *id = r->id;
   (r->large ? s->lane_queue : s->queue).push_back(r->id);
@@ -601,6 +675,81 @@ int srv_submit(srv_t* s, const sim_config* cfg, const sim_gate* gates, size_t n,
 namespace {
 double ms_since(std::chrono::steady_clock::time_point t0) {
   return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+}
+
+// Queued requests compiled ahead of their admission, at most this many per tick.
+constexpr size_t kCompileAhead = 16;
+
+// Host work done while a tick runs on the GPU, on the host thread pool:
+// - requests that finished before the tick have their states copied out;
+// - each request in the tick gets the grouping of the fused run it is expected
+//   to take next.  Its state size after the tick is predicted (unchanged by a
+//   fused run or, as an upper bound, by a measurement; doubled, up to the
+//   capacity, by a branching gate), which fixes the cap's skip decisions and
+//   with them where the run ends.  The next tick uses the grouping only if the
+//   run that comes is the same, so a wrong prediction costs time, not results.
+// - the first queued requests not yet compiled are compiled.
+int work_ahead(srv_t* s, const std::vector<Request*>& done, const std::vector<Request*>& mono,
+               const std::vector<Request*>& u2, const std::vector<Request*>& meas) {
+  enum Kind { COPY, GROUP, COMPILE };
+  struct Task {
+    Request* r;
+    Kind kind;
+    size_t weight;
+  };
+  std::vector<Task> tasks;
+  auto plan = [&](Request* r, uint64_t nnz) {
+    Cursor c{r->i, r->mono_seen, 0};
+    size_t b = 0, len = 0, op = 0;
+    if (scan_segment(s, *r, nnz, c, &b, &len, &op) != SEG_MONO) return;
+    BsRun br{};
+    if (!r->rc.run_params(b, len, r->cfg.mono_mode, r->cfg.bs_min_gates, &br)) return;
+    r->ahead.valid = false;
+    r->ahead.b = b;
+    r->ahead.len = len;
+    r->ahead.br = br;
+    r->ahead.grp.clear();
+    tasks.push_back(Task{r, GROUP, len});
+  };
+  for (Request* r : done) tasks.push_back(Task{r, COPY, 8 * r->nnz});
+  for (Request* r : mono) plan(r, r->nnz);
+  for (Request* r : meas) plan(r, r->nnz);
+  for (Request* r : u2) plan(r, std::min<uint64_t>(2 * r->nnz, r->cfg.capacity));
+  size_t compiles = 0;
+  for (uint64_t id : s->queue) {
+    if (compiles == kCompileAhead) break;
+    Request& r = *s->reqs[id];
+    if (r.compiled) continue;
+    tasks.push_back(Task{&r, COMPILE, r.gates.size()});
+    ++compiles;
+  }
+  // Longest first, for balance across the pool.
+  std::stable_sort(tasks.begin(), tasks.end(), [](const Task& a, const Task& b) { return a.weight > b.weight; });
+  std::vector<hipError_t> err(tasks.size(), hipSuccess);
+  std::vector<double> copy_ms(tasks.size(), 0.0);
+  HostPool::get().run(tasks.size(), [&](size_t t) {
+    Request& r = *tasks[t].r;
+    switch (tasks[t].kind) {
+      case COPY: {
+        const auto t0 = std::chrono::steady_clock::now();
+        err[t] = copy_out(r);
+        copy_ms[t] = ms_since(t0);
+        break;
+      }
+      case COMPILE:
+        compile_request(r);
+        break;
+      case GROUP:
+        r.rc.group(r.ahead.b, r.ahead.len, r.ahead.grp, &r.ahead.br);
+        r.ahead.valid = true;
+        break;
+    }
+  });
+  for (size_t t = 0; t < tasks.size(); ++t) {
+    s->stats.copy_ms += copy_ms[t];
+    if (err[t] != hipSuccess) return sfail(SIM_E_HIP, std::string("copying a finished state out: ") + hipGetErrorString(err[t]));
+  }
+  return SIM_OK;
 }
 }  // namespace
 
@@ -653,8 +802,20 @@ int srv_tick(srv_t* s, uint32_t* running, uint32_t* queued) {
     }
     if (sg.k == SEG_MONO) {
       sg.bsl = r->rc.run_params(sg.b, sg.len, r->cfg.mono_mode, r->cfg.bs_min_gates, &sg.br);
-      if (sg.bsl) to_group.push_back(segs.size());
+      if (sg.bsl) {
+        // group() depends only on the run, so a grouping made ahead for the
+        // same run is the one it would make now.
+        if (r->ahead.valid && r->ahead.b == sg.b && r->ahead.len == sg.len) {
+          sg.grp = std::move(r->ahead.grp);
+          sg.br = r->ahead.br;
+          s->stats.ahead_hits++;
+        } else {
+          to_group.push_back(segs.size());
+        }
+      }
     }
+    r->ahead.valid = false;
+    r->ahead.grp.clear();
     segs.push_back(std::move(sg));
   }
   {
@@ -693,12 +854,20 @@ int srv_tick(srv_t* s, uint32_t* running, uint32_t* queued) {
       r->deferred = arena_used + al(bytes) > s->cfg.arena_bytes;
       if (r->deferred) {
         // Give back the run's ops: they are re-read next tick (skip decisions
-        // there depend only on nnz, which is unchanged).
+        // there depend only on nnz, which is unchanged), and so is the run,
+        // whose grouping is kept for it.
         const size_t back_to = r->mono_op[b];
         for (size_t q = back_to; q < r->i; ++q)
           if (r->gates[q].op == SIM_OP_U2) r->st.u2_skipped--;
         r->i = back_to;
         r->mono_seen = b;
+        if (bsl) {
+          r->ahead.valid = true;
+          r->ahead.b = b;
+          r->ahead.len = len;
+          r->ahead.br = sg.br;
+          r->ahead.grp = std::move(sg.grp);
+        }
         continue;
       }
       if (bsl) {
@@ -741,11 +910,17 @@ int srv_tick(srv_t* s, uint32_t* running, uint32_t* queued) {
       meas_items.push_back(it);
     }
   }
-  for (Request* r : done_now) {
-    rc = finish(s, *r, SRV_DONE, SIM_OK);
-    if (rc) return rc;
-    s->running.erase(std::find(s->running.begin(), s->running.end(), r));
-  }
+  // Finished requests are copied out while the tick runs (their memory is
+  // not in it; it is reused from the next tick's admission on).
+  auto retire_done = [&]() -> int {
+    for (Request* r : done_now) {
+      const int frc = finish(s, *r, SRV_DONE, SIM_OK);
+      if (frc) return frc;
+      s->running.erase(std::find(s->running.begin(), s->running.end(), r));
+    }
+    done_now.clear();
+    return SIM_OK;
+  };
   const uint32_t nm = (uint32_t)mono_items.size(), nu = (uint32_t)u2_items.size(), nq = (uint32_t)meas_items.size();
   if (nm + nu + nq) {
     std::memset(hdr, 0, sizeof(BTick));
@@ -797,6 +972,15 @@ int srv_tick(srv_t* s, uint32_t* running, uint32_t* queued) {
     for (Request* r : s->running) max_slot = std::max(max_slot, r->slot);
     SRV_HIP(hipMemcpyAsync(s->h_ctl, s->d_ctl, (size_t)(max_slot + 1) * sizeof(SlotCtl), hipMemcpyDeviceToHost,
                            s->stream));
+    // Host work that does not wait for this tick runs while it does.
+    {
+      const auto t_a = std::chrono::steady_clock::now();
+      rc = work_ahead(s, done_now, mono, u2, meas);
+      if (rc) return rc;
+      rc = retire_done();
+      if (rc) return rc;
+      s->stats.ahead_ms += ms_since(t_a);
+    }
     {
       const auto t_w = std::chrono::steady_clock::now();
       SRV_HIP(hipStreamSynchronize(s->stream));
@@ -834,6 +1018,8 @@ int srv_tick(srv_t* s, uint32_t* running, uint32_t* queued) {
       s->running.erase(std::find(s->running.begin(), s->running.end(), f.first));
     }
   }
+  rc = retire_done();
+  if (rc) return rc;
   if (s->running.empty() && s->lane_in_flight) {
     // Nothing batched to do: wait (briefly) for the lane instead of spinning.
     const auto t_w = std::chrono::steady_clock::now();
@@ -873,20 +1059,66 @@ int srv_poll(srv_t* s, uint64_t id, int32_t* state, int32_t* error) {
   return SIM_OK;
 }
 
-int srv_result(srv_t* s, uint64_t id, sim_key* keys, sim_c64* amps, uint64_t cap, uint64_t* nnz, int32_t* outcomes,
-               uint64_t out_cap, uint64_t* n_out, sim_stats* stats) {
-  if (!s || !nnz) return sfail(SIM_E_ARG, "null argument");
+namespace {
+// The finished request id, or an error.
+int done_request(srv_t* s, uint64_t id, Request** out) {
   auto it = s->reqs.find(id);
   if (it == s->reqs.end()) return sfail(SIM_E_ARG, "unknown request id");
   Request& r = *it->second;
   if (r.state != SRV_DONE) return sfail(r.state == SRV_FAILED ? r.error : SIM_E_STATE, "request not done");
-  *nnz = r.keys.size();
+  *out = &r;
+  return SIM_OK;
+}
+
+int result_rest(Request& r, uint64_t cap, uint64_t* nnz, int32_t* outcomes, uint64_t out_cap, uint64_t* n_out,
+                sim_stats* stats) {
+  *nnz = r.res_n;
   if (n_out) *n_out = r.outcomes.size();
   if (stats) *stats = r.st;
-  if (cap < r.keys.size() || (outcomes && out_cap < r.outcomes.size())) return sfail(SIM_E_BUFFER, "buffer too small");
-  if (keys && !r.keys.empty()) std::memcpy(keys, r.keys.data(), r.keys.size() * sizeof(sim_key));
-  if (amps && !r.amps.empty()) std::memcpy(amps, r.amps.data(), r.amps.size() * sizeof(sim_c64));
+  if (cap < r.res_n || (outcomes && out_cap < r.outcomes.size())) return sfail(SIM_E_BUFFER, "buffer too small");
   if (outcomes && !r.outcomes.empty()) std::memcpy(outcomes, r.outcomes.data(), r.outcomes.size() * 4);
+  return SIM_OK;
+}
+}  // namespace
+
+int srv_result(srv_t* s, uint64_t id, sim_key* keys, sim_c64* amps, uint64_t cap, uint64_t* nnz, int32_t* outcomes,
+               uint64_t out_cap, uint64_t* n_out, sim_stats* stats) {
+  if (!s || !nnz) return sfail(SIM_E_ARG, "null argument");
+  Request* r = nullptr;
+  int rc = done_request(s, id, &r);
+  if (rc) return rc;
+  rc = result_rest(*r, cap, nnz, outcomes, out_cap, n_out, stats);
+  if (rc) return rc;
+  const uint64_t* lo = r->res_lo.get();
+  const uint64_t* hi = r->res_hi.get();
+  const sim_c64* a = r->res_amp.get();
+  parallel_parts(r->res_n, 1u << 16, [&](size_t b, size_t e, size_t) {
+    if (keys)
+      for (size_t k = b; k < e; ++k) keys[k] = sim_key{lo[k], hi ? hi[k] : 0};
+    if (amps) std::memcpy(amps + b, a + b, (e - b) * sizeof(sim_c64));
+  });
+  return SIM_OK;
+}
+
+int srv_result_soa(srv_t* s, uint64_t id, uint64_t* key_lo, uint64_t* key_hi, sim_c64* amps, uint64_t cap,
+                   uint64_t* nnz, int32_t* outcomes, uint64_t out_cap, uint64_t* n_out, sim_stats* stats) {
+  if (!s || !nnz) return sfail(SIM_E_ARG, "null argument");
+  Request* r = nullptr;
+  int rc = done_request(s, id, &r);
+  if (rc) return rc;
+  rc = result_rest(*r, cap, nnz, outcomes, out_cap, n_out, stats);
+  if (rc) return rc;
+  const uint64_t* lo = r->res_lo.get();
+  const uint64_t* hi = r->res_hi.get();
+  const sim_c64* a = r->res_amp.get();
+  parallel_parts(r->res_n, 1u << 16, [&](size_t b, size_t e, size_t) {
+    if (key_lo) std::memcpy(key_lo + b, lo + b, (e - b) * 8);
+    if (key_hi) {
+      if (hi) std::memcpy(key_hi + b, hi + b, (e - b) * 8);
+      else std::memset(key_hi + b, 0, (e - b) * 8);
+    }
+    if (amps) std::memcpy(amps + b, a + b, (e - b) * sizeof(sim_c64));
+  });
   return SIM_OK;
 }
 

@@ -1267,12 +1267,22 @@ int sim_export_state(sim_t* s, sim_key* keys, sim_c64* amps, uint64_t cap, uint6
   if (cap < n) return fail(SIM_E_BUFFER, "export buffer smaller than nnz");
   if (!n) return SIM_OK;
   if (!keys || !amps) return fail(SIM_E_ARG, "null export arrays");
-  std::vector<uint64_t> lo(n), hi(n, 0);
   const Buf& b = s->buf[s->cur];
-  HIP_TRY(hipMemcpy(lo.data(), b.key_lo, n * 8, hipMemcpyDeviceToHost));
-  if (s->wide) HIP_TRY(hipMemcpy(hi.data(), b.key_hi, n * 8, hipMemcpyDeviceToHost));
-  HIP_TRY(hipMemcpy(amps, b.amp, n * 16, hipMemcpyDeviceToHost));
-  for (uint64_t i = 0; i < n; ++i) keys[i] = sim_key{lo[i], hi[i]};
+  HIP_TRY(copy_state_to_host(b.key_lo, s->wide ? b.key_hi : nullptr, b.amp, n, keys, amps));
+  return SIM_OK;
+}
+
+int sim_export_state_soa(sim_t* s, uint64_t* key_lo, uint64_t* key_hi, sim_c64* amps, uint64_t cap, uint64_t* nnz) {
+  if (!s || !nnz) return fail(SIM_E_ARG, "null argument");
+  uint64_t n;
+  int rc = read_nnz(s, &n);
+  if (rc) return rc;
+  *nnz = n;
+  if (cap < n) return fail(SIM_E_BUFFER, "export buffer smaller than nnz");
+  if (!n) return SIM_OK;
+  if (!key_lo || !amps) return fail(SIM_E_ARG, "null export arrays");
+  const Buf& b = s->buf[s->cur];
+  HIP_TRY(copy_state_to_host_soa(b.key_lo, s->wide ? b.key_hi : nullptr, b.amp, n, key_lo, key_hi, amps));
   return SIM_OK;
 }
 

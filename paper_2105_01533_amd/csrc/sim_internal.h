@@ -259,6 +259,15 @@ void launch_mono_rp(hipStream_t st, Buf b, const uint64_t* nnz, const RpRec* pro
 // Set-up of the register-plane passes' cross-stream ordering on the current
 // device (once per device; called by sim_create).
 hipError_t mono_rp_init();
+// n entries of a device state (key_lo, key_hi or null for <= 64 qubits, amp)
+// into host key records and amplitudes, through the calling thread's pinned
+// staging buffer; safe to call from several host threads at once.
+hipError_t copy_state_to_host(const uint64_t* lo, const uint64_t* hi, const double2* amp, uint64_t n, sim_key* keys,
+                              sim_c64* amps);
+// The same into separate arrays (key_hi may be null: high words not wanted;
+// zeros are written for a null hi).
+hipError_t copy_state_to_host_soa(const uint64_t* lo, const uint64_t* hi, const double2* amp, uint64_t n,
+                                  uint64_t* key_lo, uint64_t* key_hi, sim_c64* amps);
 void launch_fill(hipStream_t st, uint64_t* p, uint64_t v, uint64_t n);
 void launch_copy16(hipStream_t st, void* dst, const void* src, uint64_t n16);
 void launch_index_build(hipStream_t st, bool wide, Buf b, const uint64_t* nnz, uint64_t* table, uint64_t mask,

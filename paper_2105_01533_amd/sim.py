@@ -91,6 +91,7 @@ def _load():
         "sim_nnz": (i32, [vp, ctypes.POINTER(u64)]),
         "sim_sync": (i32, [vp]),
         "sim_export_state": (i32, [vp, vp, vp, u64, ctypes.POINTER(u64)]),
+        "sim_export_state_soa": (i32, [vp, vp, vp, vp, u64, ctypes.POINTER(u64)]),
         "sim_device_state": (i32, [vp, vp, vp, vp, vp]),
         "sim_set_tuning": (i32, [vp, vp]),
         "sim_device_copy": (i32, [vp, vp, sz, vp]),
@@ -257,14 +258,19 @@ def sim_sync(h):
 
 
 def sim_export_state(h, sort: bool = True):
+    """(lo, hi, amp) numpy arrays; sorted ascending by (hi, lo) when sort.
+    The arrays are written directly by sim_export_state_soa."""
+    return sim_export_state_soa(h, sort)
+
+
+def sim_export_state_soa(h, sort: bool = True):
     """(lo, hi, amp) numpy arrays; sorted ascending by (hi, lo) when sort."""
     n = sim_nnz(h)
-    keys = np.empty(max(n, 1), KEY_DTYPE)
-    amp = np.empty(max(n, 1), np.complex128)
+    lo, hi = np.empty(n, np.uint64), np.empty(n, np.uint64)
+    amp = np.empty(n, np.complex128)
     got = ctypes.c_uint64()
-    _check(_lib.sim_export_state(h, _ptr(keys), _ptr(amp), len(keys), ctypes.byref(got)), "sim_export_state")
-    n = got.value
-    lo, hi, amp = keys["lo"][:n].copy(), keys["hi"][:n].copy(), amp[:n].copy()
+    _check(_lib.sim_export_state_soa(h, _ptr(lo), _ptr(hi), _ptr(amp), n, ctypes.byref(got)), "sim_export_state_soa")
+    assert got.value == n
     if sort:
         order = np.lexsort((lo, hi))
         lo, hi, amp = lo[order], hi[order], amp[order]
@@ -410,7 +416,8 @@ class srv_stats(ctypes.Structure):
     _fields_ = [(f, ctypes.c_uint64) for f in (
         "submitted", "admitted", "completed", "failed", "ticks", "items", "bitslice_runs",
         "pool_used_bytes", "pool_peak_bytes")] + [(f, ctypes.c_double) for f in ("host_ms", "wait_ms", "group_ms")] + [
-        ("lane_completed", ctypes.c_uint64), ("lane_ms", ctypes.c_double)]
+        ("lane_completed", ctypes.c_uint64), ("lane_ms", ctypes.c_double), ("ahead_hits", ctypes.c_uint64),
+        ("ahead_ms", ctypes.c_double), ("copy_ms", ctypes.c_double)]
 
     def as_dict(self):
         return {f: (round(getattr(self, f), 3) if t is ctypes.c_double else int(getattr(self, f)))
@@ -428,6 +435,7 @@ def _srv_sigs():
         "srv_run": (i32, [vp]),
         "srv_poll": (i32, [vp, u64, ctypes.POINTER(i32), ctypes.POINTER(i32)]),
         "srv_result": (i32, [vp, u64, vp, vp, u64, ctypes.POINTER(u64), vp, u64, ctypes.POINTER(u64), vp]),
+        "srv_result_soa": (i32, [vp, u64, vp, vp, vp, u64, ctypes.POINTER(u64), vp, u64, ctypes.POINTER(u64), vp]),
         "srv_release": (i32, [vp, u64]),
         "srv_get_stats": (i32, [vp, vp]),
         "srv_last_error": (ctypes.c_char_p, []),
@@ -495,19 +503,24 @@ def srv_poll(h, rid: int):
 
 
 def srv_result(h, rid: int, sort: bool = True):
+    """(lo, hi, amp, outcomes, stats dict) of a finished request; the arrays
+    are written directly by srv_result_soa."""
+    return srv_result_soa(h, rid, sort)
+
+
+def srv_result_soa(h, rid: int, sort: bool = True):
     """(lo, hi, amp, outcomes, stats dict) of a finished request."""
     nnz, nout = ctypes.c_uint64(), ctypes.c_uint64()
     st = sim_stats()
     rc = _lib.srv_result(h, rid, None, None, 0, ctypes.byref(nnz), None, 0, ctypes.byref(nout), ctypes.byref(st))
     if rc not in (SIM_OK, SIM_E_BUFFER):
         raise ServerError(rc, "srv_result")
-    keys = np.empty(max(nnz.value, 1), KEY_DTYPE)
-    amp = np.empty(max(nnz.value, 1), np.complex128)
-    outs = np.empty(max(nout.value, 1), np.int32)
-    _scheck(_lib.srv_result(h, rid, _ptr(keys), _ptr(amp), len(keys), ctypes.byref(nnz), _ptr(outs), len(outs),
-                            ctypes.byref(nout), ctypes.byref(st)), "srv_result")
     n = nnz.value
-    lo, hi, amp = keys["lo"][:n].copy(), keys["hi"][:n].copy(), amp[:n].copy()
+    lo, hi = np.empty(n, np.uint64), np.empty(n, np.uint64)
+    amp = np.empty(n, np.complex128)
+    outs = np.empty(max(nout.value, 1), np.int32)
+    _scheck(_lib.srv_result_soa(h, rid, _ptr(lo), _ptr(hi), _ptr(amp), n, ctypes.byref(nnz), _ptr(outs), len(outs),
+                                ctypes.byref(nout), ctypes.byref(st)), "srv_result_soa")
     if sort:
         order = np.lexsort((lo, hi))
         lo, hi, amp = lo[order], hi[order], amp[order]

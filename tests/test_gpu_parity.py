@@ -875,3 +875,42 @@ def test_prune_decisions_have_margin(sim, which):
     gap = float(np.max(np.abs(a - b) / np.maximum(np.abs(a), 1e-300)))
     say(f"[gpu] {w.name}: min prune margin {margin:.3e}, kernel rounding gap (relative) {gap:.3e}")
     assert math.isfinite(margin) and margin > 1e3 * 2 * max(gap, 1e-16), (margin, gap)
+
+
+@pytest.mark.parametrize("n_qubits", [40, 100])
+def test_export_records_and_arrays_round_trip(sim, n_qubits):
+    """An imported state comes back in storage order, identically, through
+    both export calls: records (sim_export_state) and separate arrays
+    (sim_export_state_soa).  The size spans three staging chunks and a ragged
+    tail for both label widths."""
+    import ctypes
+
+    S = sim
+    n = 3 * 524_288 + 17
+    say(f"[gpu] export round trip: {n_qubits} qubits, {n} entries")
+    rng = np.random.default_rng(11 + n_qubits)
+    idx = rng.permutation(1 << 21)[:n].astype(np.uint64)          # unique low bits
+    if n_qubits <= 64:
+        lo = idx | (rng.integers(0, 1 << 19, n, dtype=np.uint64) << np.uint64(21))
+        hi = np.zeros(n, np.uint64)
+    else:
+        lo = idx | (rng.integers(0, 1 << 43, n, dtype=np.uint64) << np.uint64(21))
+        hi = rng.integers(0, 1 << (n_qubits - 64), n, dtype=np.uint64)
+    amp = rng.standard_normal(n) + 1j * rng.standard_normal(n)
+    s = S.Simulator(n_qubits, 1 << 22, 0.0)
+    s.import_state(lo, hi, amp)
+    a_lo, a_hi, a_amp = s.export(sort=False)
+    assert np.array_equal(a_lo, lo) and np.array_equal(a_hi, hi)
+    assert a_amp.tobytes() == amp.tobytes()
+    keys = np.empty(n, S.KEY_DTYPE)
+    amps = np.empty(n, np.complex128)
+    got = ctypes.c_uint64()
+    assert S._lib.sim_export_state(s.h, S._ptr(keys), S._ptr(amps), n, ctypes.byref(got)) == 0
+    assert got.value == n
+    assert np.array_equal(keys["lo"], lo) and np.array_equal(keys["hi"], hi)
+    assert amps.tobytes() == amp.tobytes()
+    # a buffer one entry short is refused, nothing written
+    short = np.zeros(n - 1, np.uint64)
+    assert S._lib.sim_export_state_soa(s.h, S._ptr(short), None, S._ptr(amps), n - 1, ctypes.byref(got)) == S.SIM_E_BUFFER
+    assert got.value == n and not short.any()
+    s.close()

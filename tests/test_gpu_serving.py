@@ -235,3 +235,31 @@ def test_large_lane_fifo_and_failures(S):
         assert list(outs) == list(oout)
         assert_same_state((lo, hi, amp), o.export(), what=w.name)
     srv.close()
+
+
+def test_result_records_equal_arrays(S):
+    """srv_result (key records) and srv_result_soa (separate arrays) return
+    the same state, storage order, for narrow and wide requests."""
+    import ctypes
+
+    ws = mix()[:5]
+    srv = S.Server(1 << 30, max_slots=64, lane_capacity=S.SRV_LANE_OFF)
+    ids = [srv.submit_workload(w) for w in ws]
+    srv.run()
+    for w, rid in zip(ws, ids):
+        lo, hi, amp, outs, st = srv.result(rid, sort=False)
+        n = len(lo)
+        assert n > 0, w.name
+        keys = np.empty(n, S.KEY_DTYPE)
+        amps = np.empty(n, np.complex128)
+        o = np.empty(max(len(outs), 1), np.int32)
+        nnz, nout = ctypes.c_uint64(), ctypes.c_uint64()
+        assert S._lib.srv_result(srv.h, rid, S._ptr(keys), S._ptr(amps), n, ctypes.byref(nnz), S._ptr(o), len(o),
+                                 ctypes.byref(nout), None) == 0
+        assert nnz.value == n and nout.value == len(outs)
+        assert np.array_equal(keys["lo"], lo) and np.array_equal(keys["hi"], hi), w.name
+        assert amps.tobytes() == amp.tobytes(), w.name
+        assert list(o[:nout.value]) == list(outs)
+        if w.n_qubits <= 64:
+            assert not hi.any()
+    srv.close()
