@@ -175,6 +175,12 @@ typedef struct sim_config {
  * keeps them in LDS instead.  The results are identical. */
 #define SIM_FLAG_BS_LDS 2u
 
+/* Branching gates on small states (at most 4096 entries) run as one block
+ * whose partner index is in LDS; this flag sends them through the global
+ * index (index build, probe, single pass) like larger states.  Both give the
+ * same outputs in the same order. */
+#define SIM_FLAG_U2_GLOBAL_INDEX 4u
+
 /* Fused phase/permutation pass variants.  DIRECT evaluates every gate on every
  * entry with sequential complex products (results bit-identical to a plain
  * sequential evaluation).  BITSLICE transposes 2048-entry tiles into bit-planes
@@ -332,7 +338,8 @@ int sim_device_state(sim_t* s, uint64_t** key_lo, uint64_t** key_hi, double** am
  * u2_count, block_scan, u2_write (the single-pass branching kernel counts
  * here; u2_count and block_scan run only in the two-pass form),
  * measure_reduce, measure_decide and measure_write (a chain of consecutive
- * measurements runs one reduce).
+ * measurements runs one reduce), and u2_lds (the one-block branching kernel
+ * of states of at most 4096 entries, index in LDS).
  * With profiling on for a class (sim_set_profiling), every launch of it is
  * bracketed by HIP events on the handle's stream and total_ms sums their
  * elapsed times; otherwise total_ms is 0.  alg_bytes is the algorithmic HBM
@@ -340,7 +347,7 @@ int sim_device_state(sim_t* s, uint64_t** key_lo, uint64_t** key_hi, double** am
  * phase/permutation pass the label read, label write if any gate flips and
  * amplitude read+write if any gate has a phase; for u2_count every input
  * entry read; for u2_write every input entry read and every output entry
- * written; for measure_reduce the label word holding the measured qubit and the
+ * written, and the same for u2_lds; for measure_reduce the label word holding the measured qubit and the
  * amplitude of every entry; for measure_write that label word of every entry, the
  * rest of each kept entry and the kept entries written; 0 for the others
  * (index, scan and decide work is overhead);

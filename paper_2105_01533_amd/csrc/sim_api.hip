@@ -80,7 +80,7 @@ bool config_ok(const sim_config* c, std::string* why) {
     return *why = "load_factor must be in (0, 0.9]", false;
   if (c->block != 0 && c->block != 64 && c->block != 128 && c->block != 256)
     return *why = "block must be 64, 128 or 256", false;
-  if (c->flags & ~(SIM_FLAG_U2_TWO_PASS | SIM_FLAG_BS_LDS)) return *why = "unknown flags", false;
+  if (c->flags & ~(SIM_FLAG_U2_TWO_PASS | SIM_FLAG_BS_LDS | SIM_FLAG_U2_GLOBAL_INDEX)) return *why = "unknown flags", false;
   if (c->mono_mode > SIM_MONO_BITSLICE) return *why = "unknown mono_mode", false;
   return true;
 }
@@ -214,10 +214,12 @@ struct Staging {
 // at the start of a call, grouping of bit-sliced runs, and time blocked in
 // stream synchronisations.
 enum KClass { KC_MONO = 0, KC_FILL, KC_BUILD, KC_U2_PROBE, KC_U2_COUNT, KC_SCAN, KC_U2_WRITE, KC_M_REDUCE,
-              KC_M_DECIDE, KC_M_WRITE, KC_KERNELS, KC_H_PREPARE = KC_KERNELS, KC_H_GROUP, KC_H_SYNC, KC_COUNT };
+              KC_M_DECIDE, KC_M_WRITE, KC_U2_LDS, KC_KERNELS, KC_H_PREPARE = KC_KERNELS, KC_H_GROUP, KC_H_SYNC,
+              KC_COUNT };
 static const char* const kClassNames[KC_COUNT] = {"mono_pass", "index_fill", "index_build", "u2_probe", "u2_count",
                                                   "block_scan", "u2_write", "measure_reduce", "measure_decide",
-                                                  "measure_write", "host_prepare", "host_group", "host_sync"};
+                                                  "measure_write", "u2_lds", "host_prepare", "host_group",
+                                                  "host_sync"};
 
 struct sim_t {
   sim_config cfg;
@@ -230,7 +232,7 @@ struct sim_t {
   uint64_t k_launches[KC_COUNT] = {};
   double k_ms[KC_COUNT] = {};
   uint64_t mono_bytes_base = 0, mono_updates = 0;
-  uint64_t pass_bytes_base[4] = {};
+  uint64_t pass_bytes_base[5] = {};
   // Single-pass branching kernel: tile status words, the launch epoch and the
   // tile counter's value at the start of the next launch.
   uint64_t* status = nullptr;
@@ -403,6 +405,19 @@ int run_u2(sim_t* s, const sim_gate& g, bool* over) {
   const uint64_t* nnz_in = d_nnz(s, s->cur);
   const U2Desc d = u2_desc(g, s->cfg.eps);
   const int G = chunk_grid(ub);
+  if (!check && !(s->cfg.flags & (SIM_FLAG_U2_TWO_PASS | SIM_FLAG_U2_GLOBAL_INDEX)) && ub <= kLdsU2Max) {
+    // Small state (2 ub <= capacity): the whole gate in one block, its
+    // partner index in LDS; the global index is not touched.
+    {
+      KTimer t_(s, KC_U2_LDS);
+      launch_u2_lds(s->stream, s->wide, s->buf[s->cur], s->buf[other], nnz_in, d, s->ctl, d_nnz(s, other));
+    }
+    HIP_TRY(hipGetLastError());
+    s->cur = other;
+    s->nnz_known = false;
+    s->nnz_ub = std::min<uint64_t>(2 * ub, cap);
+    return SIM_OK;
+  }
   const uint64_t prior = s->table_dirty;
   if (const uint64_t dirty = std::min<uint64_t>(prior, slots)) {
     KTimer t_(s, KC_FILL);
@@ -1134,7 +1149,8 @@ int apply_impl(sim_t* s, const sim_gate* gates, size_t n, int32_t* outcomes, sim
     HIP_TRY(hipMemcpyAsync(&s->ctl->error, &s->h_ctl->error, 4, hipMemcpyHostToDevice, s->stream));
     HIP_TRY(timed_sync(s));
     if (result == SIM_OK)
-      result = (err & 2u) ? fail(SIM_E_HIP, "single-pass branching kernel gave up waiting for a tile")
+      result = (err & 2u)   ? fail(SIM_E_HIP, "single-pass branching kernel gave up waiting for a tile")
+               : (err & 4u) ? fail(SIM_E_HIP, "one-block branching kernel launched on a state too large for it")
                                       : fail(SIM_E_STATE, "measurement of an empty state");
   }
   s->mchain.valid = false;
@@ -1303,7 +1319,7 @@ int sim_set_tuning(sim_t* s, const sim_config* t) {
   if (t->mono_mode > SIM_MONO_BITSLICE) return fail(SIM_E_ARG, "unknown mono_mode");
   // The fused-pass kernel (SIM_FLAG_BS_LDS) is chosen at creation only.
   if (t->flags & SIM_FLAG_BS_LDS) return fail(SIM_E_ARG, "SIM_FLAG_BS_LDS is set at creation (sim_create) only");
-  if (t->flags & ~SIM_FLAG_U2_TWO_PASS) return fail(SIM_E_ARG, "unknown flags");
+  if (t->flags & ~(SIM_FLAG_U2_TWO_PASS | SIM_FLAG_U2_GLOBAL_INDEX)) return fail(SIM_E_ARG, "unknown flags");
   if (t->load_factor != 0.0 && !(t->load_factor > 0.0 && t->load_factor <= 0.9))
     return fail(SIM_E_ARG, "load_factor must be in (0, 0.9]");
   s->cfg.fuse_max = t->fuse_max ? t->fuse_max : 65536;
@@ -1346,7 +1362,12 @@ int sim_kernel_stats(sim_t* s, sim_kernel_stat* out, int cap, int* n) {
       k.alg_bytes = (double)(s->h_ctl->mono_bytes - s->mono_bytes_base);
       k.updates = (double)(s->h_ctl->mono_updates - s->mono_updates);
     }
-    const int pass = c == KC_U2_COUNT ? 0 : c == KC_U2_WRITE ? 1 : c == KC_M_REDUCE ? 2 : c == KC_M_WRITE ? 3 : -1;
+    const int pass = c == KC_U2_COUNT  ? 0
+                     : c == KC_U2_WRITE ? 1
+                     : c == KC_M_REDUCE ? 2
+                     : c == KC_M_WRITE  ? 3
+                     : c == KC_U2_LDS   ? 4
+                                        : -1;
     if (pass >= 0) k.alg_bytes = (double)(s->h_ctl->pass_bytes[pass] - s->pass_bytes_base[pass]);
   }
   return SIM_OK;
@@ -1361,7 +1382,7 @@ int sim_kernel_stats_reset(sim_t* s) {
     s->k_ms[c] = 0.0;
   }
   s->mono_bytes_base = s->h_ctl->mono_bytes;
-  for (int k = 0; k < 4; ++k) s->pass_bytes_base[k] = s->h_ctl->pass_bytes[k];
+  for (int k = 0; k < 5; ++k) s->pass_bytes_base[k] = s->h_ctl->pass_bytes[k];
   s->mono_updates = s->h_ctl->mono_updates;
   return SIM_OK;
 }

@@ -164,8 +164,9 @@ struct Ctl {
   uint64_t mono_updates;       // gate-entry updates of the fused passes
   // Algorithmic bytes (entries read and written) of the branching count and
   // write passes and of the measurement reduce and write passes.
-  uint64_t pass_bytes[4];
-  uint32_t error;              // bit 0: a measurement had no valid outcome; bit 1: a chained scan gave up waiting
+  uint64_t pass_bytes[5];      // index 4: the one-block (LDS-index) branching kernel
+  uint32_t error;              // bit 0: a measurement had no valid outcome; bit 1: a chained scan gave up
+                               // waiting; bit 2: the one-block branching kernel met a state too large for it
   uint32_t ticket;             // tile counter of the single-pass branching kernel (wraps)
   double pruned_mass;          // sum of |a|^2 of the entries T_eps dropped
   // Counters of a two-pass branching gate, staged by its count pass and
@@ -287,6 +288,14 @@ constexpr uint32_t kU2Tile = 2048;
 void launch_u2_fused(hipStream_t st, bool wide, Buf in, Buf out, const uint64_t* nnz, const uint32_t* partner,
                      const U2Desc& d, Ctl* ctl, uint64_t* status, uint32_t ticket_base, uint32_t epoch,
                      uint64_t* nnz_out, uint64_t* table, uint64_t clear_slots, int grid);
+// Largest state the one-block branching kernel takes (its partner index and
+// partner slots live in LDS).
+constexpr uint32_t kLdsU2Max = 4096;
+// One block: a branching gate on a state of at most kLdsU2Max entries, index
+// and look-up in LDS; outputs, their order and the counters as the
+// multi-kernel path's single pass (pruned_mass up to summation order).
+void launch_u2_lds(hipStream_t st, bool wide, Buf in, Buf out, const uint64_t* nnz, const U2Desc& d, Ctl* ctl,
+                   uint64_t* nnz_out);
 void launch_measure_reduce(hipStream_t st, bool wide, Buf b, const uint64_t* nnz, uint32_t q, BlockScratch s,
                            int grid, int block);
 void launch_measure_decide(hipStream_t st, const double2* part, const uint32_t* cnt1, uint32_t* off, int nblocks,

@@ -28,6 +28,7 @@ SIM_MONO_AUTO, SIM_MONO_DIRECT, SIM_MONO_BITSLICE = 0, 1, 2
 SIM_PROFILE_OFF, SIM_PROFILE_ALL, SIM_PROFILE_MONO = 0, 1, 2
 SIM_FLAG_U2_TWO_PASS = 1
 SIM_FLAG_BS_LDS = 2
+SIM_FLAG_U2_GLOBAL_INDEX = 4
 
 GATE_DTYPE = np.dtype([
     ("op", "<u4"), ("target", "<u4"), ("ctrl_lo", "<u8"), ("ctrl_hi", "<u8"),

@@ -87,11 +87,14 @@ def test_workspace_bytes_and_config_validation():
     lds = sim.sim_config(n_qubits=100, capacity=1 << 20, eps=0.0, load_factor=0.5, block=256,
                          flags=sim.SIM_FLAG_BS_LDS)
     assert sim.sim_workspace_bytes(lds) == nb
+    glob = sim.sim_config(n_qubits=100, capacity=1 << 20, eps=0.0, load_factor=0.5, block=256,
+                          flags=sim.SIM_FLAG_U2_GLOBAL_INDEX)
+    assert sim.sim_workspace_bytes(glob) == nb
     for bad in [sim.sim_config(n_qubits=0, capacity=10), sim.sim_config(n_qubits=129, capacity=10),
                 sim.sim_config(n_qubits=10, capacity=0), sim.sim_config(n_qubits=10, capacity=1 << 31),
                 sim.sim_config(n_qubits=10, capacity=10, load_factor=0.95),
                 sim.sim_config(n_qubits=10, capacity=10, block=96),
-                sim.sim_config(n_qubits=10, capacity=10, flags=4)]:
+                sim.sim_config(n_qubits=10, capacity=10, flags=8)]:
         assert sim.sim_workspace_bytes(bad) == 0
         with pytest.raises(sim.SimError) as e:
             sim.sim_create(bad)

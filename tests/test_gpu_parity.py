@@ -465,8 +465,10 @@ def test_profiling_modes(sim):
 @pytest.mark.parametrize("which", ["c0", "c2_small", "c2_wide_ctrl"])
 def test_u2_single_pass_matches_two_pass(sim, which):
     """Branching gates whose outputs fit run as one pass (evaluation, chained
-    scan over 2048-entry tiles, ordered write); the state is bitwise the one
-    the separate count, scan and write passes produce, in the same order."""
+    scan over 2048-entry tiles, ordered write), or, on states of at most 4096
+    entries, as one block with the partner index in LDS; the state is bitwise
+    the one the separate count, scan and write passes produce, in the same
+    order, and the one the global index gives for every size."""
     if which == "c0":
         w = W.config0(seed=W.seed_for(0, 3))
     elif which == "c2_small":
@@ -474,7 +476,7 @@ def test_u2_single_pass_matches_two_pass(sim, which):
     else:
         w = W.config2(43, n=128, h_qubits=12, gates=6000, round_gates=3000, meas_per_round=2)
     out = []
-    for flags in (0, sim.SIM_FLAG_U2_TWO_PASS):
+    for flags in (0, sim.SIM_FLAG_U2_TWO_PASS, sim.SIM_FLAG_U2_GLOBAL_INDEX):
         s = sim.Simulator(w.n_qubits, w.capacity, w.eps, flags=flags)
         try:
             s.set_basis(*w.basis)
@@ -484,16 +486,23 @@ def test_u2_single_pass_matches_two_pass(sim, which):
             out.append((s.export(sort=False), list(outs), st, ks))
         finally:
             s.close()
-    (a, oa, sa, ka), (b, ob, sb, kb) = out
-    for x, y in zip(a, b):
-        assert x.tobytes() == y.tobytes()
-    assert oa == ob
-    for k in ("u2_applied", "u2_skipped", "pruned", "peak_nnz", "updates"):
-        assert sa[k] == sb[k], k
-    assert ka["u2_write"]["launches"] == kb["u2_write"]["launches"] == sa["u2_applied"]
+    (a, oa, sa, ka), (b, ob, sb, kb), (c, oc, sc, kc) = out
+    for other, oo, so in ((b, ob, sb), (c, oc, sc)):
+        for x, y in zip(a, other):
+            assert x.tobytes() == y.tobytes()
+        assert oa == oo
+        for k in ("u2_applied", "u2_skipped", "pruned", "peak_nnz", "updates"):
+            assert sa[k] == so[k], k
+    # default: small states in the one-block LDS-index kernel, the rest in
+    # the single pass; global index: every gate in the single pass
+    assert ka["u2_lds"]["launches"] > 0 and kb["u2_lds"]["launches"] == kc["u2_lds"]["launches"] == 0
+    assert ka["u2_write"]["launches"] + ka["u2_lds"]["launches"] == sa["u2_applied"]
+    assert kb["u2_write"]["launches"] == kc["u2_write"]["launches"] == sa["u2_applied"]
     assert kb["u2_count"]["launches"] == sa["u2_applied"]
     assert ka["u2_count"]["launches"] < sa["u2_applied"]       # most ran as one pass
-    assert ka["u2_write"]["alg_bytes"] == kb["u2_write"]["alg_bytes"]
+    assert kc["u2_count"]["launches"] < sa["u2_applied"]
+    assert ka["u2_write"]["alg_bytes"] + ka["u2_lds"]["alg_bytes"] == kb["u2_write"]["alg_bytes"]
+    assert kc["u2_write"]["alg_bytes"] == kb["u2_write"]["alg_bytes"]
 
 
 def test_index_reuse_across_forms_and_sizes(sim):
@@ -540,7 +549,10 @@ def test_pass_byte_counters(sim, n, two_pass):
         s.close()
     eb = 32 if n > 64 else 24
     assert ks["u2_count"]["alg_bytes"] == ((1 + 2 + 4) * eb if two_pass else 0)
-    assert ks["u2_write"]["alg_bytes"] == ((1 + 2) + (2 + 4) + (4 + 8)) * eb
+    # small states: the one-block LDS-index kernel unless in the two-pass form
+    u2 = ((1 + 2) + (2 + 4) + (4 + 8)) * eb
+    assert ks["u2_write"]["alg_bytes"] == (u2 if two_pass else 0)
+    assert ks["u2_lds"]["alg_bytes"] == (0 if two_pass else u2)
     assert ks["measure_reduce"]["alg_bytes"] == 8 * 24
     assert ks["measure_write"]["alg_bytes"] == 8 * 8 + 4 * (2 * eb - 8)
     assert ks["block_scan"]["alg_bytes"] == 0 and ks["index_build"]["alg_bytes"] == 0
@@ -914,3 +926,83 @@ def test_export_records_and_arrays_round_trip(sim, n_qubits):
     assert S._lib.sim_export_state_soa(s.h, S._ptr(short), None, S._ptr(amps), n - 1, ctypes.byref(got)) == S.SIM_E_BUFFER
     assert got.value == n and not short.any()
     s.close()
+
+
+def _paired_state(seed, size, n, t):
+    """size distinct labels on n qubits where about a third of the entries
+    have their partner (label ^ 2^t) present: P pairs and size - 2P singles."""
+    rng = np.random.default_rng(seed)
+    P = size // 3
+    K = size - P
+    seen, base = set(), []
+    while len(base) < K:
+        lo = int(rng.integers(0, 1 << min(n, 63))) | (int(rng.integers(0, 2)) << 63 if n > 63 else 0)
+        hi = int(rng.integers(0, 1 << (n - 64))) if n > 64 else 0
+        if t < 64:
+            lo &= ~(1 << t)
+        else:
+            hi &= ~(1 << (t - 64))
+        if (lo, hi) not in seen:
+            seen.add((lo, hi))
+            base.append((lo, hi))
+    flip = (1 << t) if t < 64 else 0, (1 << (t - 64)) if t >= 64 else 0
+    labels = []
+    for k, (lo, hi) in enumerate(base):
+        if k < P:
+            labels += [(lo, hi), (lo ^ flip[0], hi ^ flip[1])]
+        elif rng.integers(0, 2):
+            labels.append((lo ^ flip[0], hi ^ flip[1]))
+        else:
+            labels.append((lo, hi))
+    order = rng.permutation(len(labels))
+    lo = np.array([labels[i][0] for i in order], np.uint64)
+    hi = np.array([labels[i][1] for i in order], np.uint64)
+    amp = rng.uniform(-1, 1, size) + 1j * rng.uniform(-1, 1, size)
+    return lo, hi, amp / np.linalg.norm(amp)
+
+
+@pytest.mark.parametrize("n", [30, 100])
+@pytest.mark.parametrize("size", [1, 3, 4095, 4096, 4097])
+def test_u2_lds_kernel_around_its_limit(sim, n, size):
+    """Branching gates on imported states at and around the one-block
+    kernel's limit (4096 entries): a controlled Ry, an H on the same target
+    and an H on a high qubit (a third of the entries have their partner
+    present).  Against the oracle, and bit for bit against the global-index
+    path; the one-block kernel runs exactly when the state has at most 4096
+    entries."""
+    t = 5 if n <= 64 else 70
+    lo, hi, amp = _paired_state(9000 + size + n, size, n, t)
+    c = W.Circuit()
+    c.gate(W.K_RY, t, controls=(n - 2,), param=0.7)
+    c.h(t)
+    c.h(n - 1)
+    ops = c.array()
+    res = []
+    for flags in (0, sim.SIM_FLAG_U2_GLOBAL_INDEX):
+        s = sim.Simulator(n, 1 << 15, 1e-30, flags=flags)
+        try:
+            s.import_state(lo, hi, amp)
+            sim.sim_kernel_stats_reset(s.h)
+            _, _, st = s.apply_ops(ops)
+            ks = sim.sim_kernel_stats(s.h)
+            res.append((s.export(sort=False), st, ks))
+        finally:
+            s.close()
+    (a, sa, ka), (b, sb, kb) = res
+    for x, y in zip(a, b):
+        assert x.tobytes() == y.tobytes()
+    for k in ("u2_applied", "pruned", "peak_nnz", "updates"):
+        assert sa[k] == sb[k], k
+    # The engine's bound on the entry count before the three gates is size,
+    # 2 size and 4 size (the import's count is exact; a branching gate at
+    # most doubles it); the one-block kernel runs where that bound is <= 4096.
+    assert sa["u2_applied"] == 3
+    assert ka["u2_lds"]["launches"] == sum(ub <= 4096 for ub in (size, 2 * size, 4 * size))
+    assert kb["u2_lds"]["launches"] == 0
+    o = Oracle(n, 1e-30)
+    o.import_state(lo, hi, amp)
+    o.run(ops)
+    order = np.lexsort((a[0], a[1]))
+    assert_same_state(tuple(x[order] for x in a), o.export(), 1e-12, f"lds {n} {size}")
+    t_ = o.totals()
+    assert sa["updates"] == t_["updates"] and sa["pruned"] == t_["pruned"]
