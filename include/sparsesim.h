@@ -415,6 +415,10 @@ int sim_kernel_stats_reset(sim_t* s);
 #define SRV_FAILED 3
 
 #define SRV_FLAG_NO_GRAPH 1u /* launch the tick kernels directly instead of replaying the graph */
+/* Branching gates of states of at most 4096 entries run one block per state
+ * with the partner index in LDS; this flag sends them through the global
+ * index kernels like larger states (same outputs, same order). */
+#define SRV_FLAG_U2_GLOBAL_INDEX 2u
 
 typedef struct srv_config {
   uint64_t budget_bytes; /* device bytes for request states (the pool) */

@@ -14,6 +14,7 @@
 #include "batch_units.h"
 #include "bitslice_tile.h"
 #include "entry_ops.h"
+#include "u2_lds.h"
 
 namespace sparsesim {
 namespace {
@@ -351,6 +352,31 @@ __global__ __launch_bounds__(256) void kb_u2_write(const BTick* __restrict__ hdr
   }
 }
 
+// Branching gates of small states (at most kLdsU2Max entries), one item per
+// block, partner index in LDS (lds::u2_block): the outputs and their order are
+// those of the fill/build/probe/count/scan/write kernels above; more outputs
+// than the capacity set the overflow flag (the state's current buffer is not
+// written).
+__global__ __launch_bounds__(1024) void kb_u2_lds(const BTick* __restrict__ hdr, const BItem* __restrict__ items) {
+  __shared__ lds::Smem sm;
+  const int n = (int)hdr->n_u2s;
+  const BItem* u2s = items + hdr->n_mono + hdr->n_u2 + hdr->n_meas;
+  for (int i = blockIdx.x; i < n; i += gridDim.x) {
+    const BItem& it = u2s[i];
+    if (it.nnz > kLdsU2Max) {   // the host sends only small states here
+      if (threadIdx.x == 0) it.ctl->status |= kStOverflow;
+      continue;
+    }
+    const lds::Totals t = it.wide ? lds::u2_block<true>(it.in, it.out, (uint32_t)it.nnz, it.u2, it.cap, sm)
+                                  : lds::u2_block<false>(it.in, it.out, (uint32_t)it.nnz, it.u2, it.cap, sm);
+    if (threadIdx.x == 0) {
+      if (t.out > it.cap) it.ctl->status |= kStOverflow;
+      else it.ctl->nnz[it.other] = t.out;
+    }
+    __syncthreads();   // the next item reuses the LDS
+  }
+}
+
 // ---- measurements ------------------------------------------------------------
 __global__ __launch_bounds__(256) void kb_m_reduce(const BTick* __restrict__ hdr, const BItem* __restrict__ items,
                                                    const uint32_t* __restrict__ units) {
@@ -507,6 +533,7 @@ void launch_batch_tick(hipStream_t st, const BTick* hdr, const BItem* items, con
   hipLaunchKernelGGL(kb_u2_count, dim3(grid), dim3(256), 0, st, hdr, items, units);
   hipLaunchKernelGGL(kb_u2_scan, dim3(grid), dim3(256), 0, st, hdr, items, units);
   hipLaunchKernelGGL(kb_u2_write, dim3(grid), dim3(256), 0, st, hdr, items, units);
+  hipLaunchKernelGGL(kb_u2_lds, dim3(grid < 256 ? grid : 256), dim3(lds::kThreads), 0, st, hdr, items);
   hipLaunchKernelGGL(kb_m_reduce, dim3(grid), dim3(256), 0, st, hdr, items, units);
   hipLaunchKernelGGL(kb_m_decide, dim3(grid), dim3(256), 0, st, hdr, items, units);
   hipLaunchKernelGGL(kb_m_write, dim3(grid), dim3(256), 0, st, hdr, items, units);

@@ -550,6 +550,7 @@ int srv_create(const srv_config* cfg, void* stream, void* pool, size_t pool_byte
   if (cfg->grid > 65536) return sfail(SIM_E_ARG, "grid must be 0 (default 2048) or 1..65536");
   if (cfg->lane_workers > 64) return sfail(SIM_E_ARG, "lane_workers must be 0 (default 8) or 1..64");
   if (cfg->reserved) return sfail(SIM_E_ARG, "reserved must be 0");
+  if (cfg->flags & ~(SRV_FLAG_NO_GRAPH | SRV_FLAG_U2_GLOBAL_INDEX)) return sfail(SIM_E_ARG, "unknown flags");
   std::unique_ptr<srv_t> s(new srv_t());
   s->cfg = *cfg;
   if (!s->cfg.arena_bytes) s->cfg.arena_bytes = 64ull << 20;
@@ -773,7 +774,7 @@ int srv_tick(srv_t* s, uint32_t* running, uint32_t* queued) {
   char* arena = s->h_tick + s->arena_off;
   size_t arena_used = 0;
   std::vector<Request*> mono, u2, meas;
-  std::vector<BItem> mono_items, u2_items, meas_items;
+  std::vector<BItem> mono_items, u2_items, meas_items, u2s_items;
   std::vector<Request*> done_now;
   // Every request's next segment; the fused runs that take the bit-sliced
   // form are grouped on the host thread pool, one request per task (runs of
@@ -897,7 +898,9 @@ int srv_tick(srv_t* s, uint32_t* running, uint32_t* queued) {
       it.tot = r->tot;
       r->st.updates += r->nnz;
       u2.push_back(r);
-      u2_items.push_back(it);
+      // Small states take the one-block kernel with the index in LDS.
+      const bool small = r->nnz <= kLdsU2Max && !(s->cfg.flags & SRV_FLAG_U2_GLOBAL_INDEX);
+      (small ? u2s_items : u2_items).push_back(it);
     } else {
       const sim_gate& g = r->gates[op];
       it.q = g.target;
@@ -922,11 +925,13 @@ int srv_tick(srv_t* s, uint32_t* running, uint32_t* queued) {
     return SIM_OK;
   };
   const uint32_t nm = (uint32_t)mono_items.size(), nu = (uint32_t)u2_items.size(), nq = (uint32_t)meas_items.size();
-  if (nm + nu + nq) {
+  const uint32_t ns = (uint32_t)u2s_items.size();
+  if (nm + nu + nq + ns) {
     std::memset(hdr, 0, sizeof(BTick));
     hdr->n_mono = nm;
     hdr->n_u2 = nu;
     hdr->n_meas = nq;
+    hdr->n_u2s = ns;
     uint32_t w = 0;
     auto prefix = [&](uint32_t* at, const std::vector<BItem>& v, auto units_of) {
       uint32_t acc = 0;
@@ -953,7 +958,7 @@ int srv_tick(srv_t* s, uint32_t* running, uint32_t* queued) {
     prefix(units + w, meas_items, chunks);
     w += nq + 1;
     size_t ni = 0;
-    for (const auto& v : {&mono_items, &u2_items, &meas_items})
+    for (const auto& v : {&mono_items, &u2_items, &meas_items, &u2s_items})
       for (const BItem& it : *v) items[ni++] = it;
     SRV_HIP(hipMemcpyAsync(s->d_tick, s->h_tick, s->items_off + ni * sizeof(BItem), hipMemcpyHostToDevice,
                            s->stream));
@@ -987,7 +992,7 @@ int srv_tick(srv_t* s, uint32_t* running, uint32_t* queued) {
       s->stats.wait_ms += ms_since(t_w);
     }
     s->stats.ticks++;
-    s->stats.items += nm + nu + nq;
+    s->stats.items += nm + nu + nq + ns;
     // Fold the results back.
     std::vector<std::pair<Request*, int>> failed;
     for (Request* r : u2) {

@@ -239,7 +239,9 @@ struct BItem {
 // Tick header: item counts and the offsets (in uint32 words from the start
 // of the unit table) of each family's first-unit arrays (length n + 1).
 struct BTick {
-  uint32_t n_mono, n_u2, n_meas, pad;
+  uint32_t n_mono, n_u2, n_meas;
+  uint32_t n_u2s;              // small branching items (one block each, index in LDS), after the
+                               // measurement items
   uint32_t mono_u0, fill_u0, build_u0, chunk_u0, meas_u0;
   uint32_t pad2[3];
 };

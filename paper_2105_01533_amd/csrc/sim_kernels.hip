@@ -15,6 +15,7 @@
 // two products are evaluated left to right, |a|^2 = re*re + im*im, and the
 // library is compiled with -ffp-contract=off.
 #include "entry_ops.h"
+#include "u2_lds.h"
 
 namespace sparsesim {
 namespace {
@@ -553,141 +554,30 @@ __global__ __launch_bounds__(256) void k_u2_fused(Buf in, Buf out, const uint64_
 }
 
 // ---------------------------------------------------------------------------
-// Branching gate on a small state in one block (Sec. 3.1), with the partner
-// index in LDS: the same entries are indexed (under the controls, pivot bit
-// clear) by the same label hash, the same look-ups pair them, and Eq. 2 is
-// evaluated by the same function, so the outputs and their order are those
-// of the index-build / probe / single-pass kernels -- in one launch, with no
-// global index to fill, probe or empty.  A slot holds a 19-bit fingerprint
-// above entry index + 1 (13 bits; 0 = empty); the table has twice as many
-// slots as the largest state, so it is at most half full.
-constexpr uint32_t kLdsSlots = 2 * kLdsU2Max;
-constexpr int kLdsThreads = 1024;
-constexpr int kLdsItems = (int)(kLdsU2Max / kLdsThreads);
-static_assert(kLdsU2Max < (1u << 13) && kLdsItems * kLdsThreads == (int)kLdsU2Max, "index field of a slot");
-
+// Branching gate on a state of at most kLdsU2Max entries in one block, its
+// partner index in LDS (lds::u2_block): same outputs, order and counters as
+// the index-build / probe / single-pass kernels, in one launch.
 template <bool WIDE>
 __global__ __launch_bounds__(1024) void k_u2_lds(Buf in, Buf out, const uint64_t* __restrict__ nnz_p, U2Desc d,
                                                  Ctl* ctl, uint64_t* nnz_out) {
-  __shared__ uint32_t s_tab[kLdsSlots];
-  __shared__ uint32_t s_par[kLdsU2Max];
-  __shared__ uint32_t s_wave[16];
-  __shared__ uint32_t sh[16];
-  __shared__ double2 shm[16];
-  constexpr uint32_t kMask = kLdsSlots - 1;
+  __shared__ lds::Smem sm;
   const uint64_t n = *nnz_p;
   if (n > kLdsU2Max) {   // the host launches this kernel only below the bound
     if (threadIdx.x == 0) atomicOr(&ctl->error, 4u);
     return;
   }
-  for (uint32_t k = threadIdx.x; k < kLdsSlots; k += kLdsThreads) s_tab[k] = 0u;
-  uint64_t lo[kLdsItems], hi[kLdsItems];
-#pragma unroll
-  for (int k = 0; k < kLdsItems; ++k) {
-    const uint32_t i = (uint32_t)k * kLdsThreads + threadIdx.x;
-    lo[k] = hi[k] = 0;
-    if (i < n) {
-      lo[k] = in.key_lo[i];
-      hi[k] = WIDE ? in.key_hi[i] : 0ull;
-      s_par[i] = kNoPartner;
-    }
-  }
-  __syncthreads();
-#pragma unroll
-  for (int k = 0; k < kLdsItems; ++k) {
-    const uint32_t i = (uint32_t)k * kLdsThreads + threadIdx.x;
-    if (i >= n || !ent::ctrl_ok(d, lo[k], hi[k], WIDE) || pivot_set<WIDE>(d, lo[k], hi[k])) continue;
-    const uint64_t h = hash_label(lo[k], hi[k]);
-    const uint32_t val = ((uint32_t)(h >> 45) << 13) | (i + 1u);
-    uint32_t slot = (uint32_t)h & kMask;
-    for (uint32_t p = 0; p < kLdsSlots; ++p) {
-      if (atomicCAS(&s_tab[slot], 0u, val) == 0u) break;
-      slot = (slot + 1u) & kMask;
-    }
-  }
-  __syncthreads();
-#pragma unroll
-  for (int k = 0; k < kLdsItems; ++k) {
-    const uint32_t i = (uint32_t)k * kLdsThreads + threadIdx.x;
-    if (i >= n || !ent::ctrl_ok(d, lo[k], hi[k], WIDE) || !pivot_set<WIDE>(d, lo[k], hi[k])) continue;
-    const uint64_t qlo = lo[k] ^ d.x_lo, qhi = WIDE ? (hi[k] ^ d.x_hi) : 0ull;
-    const uint64_t h = hash_label(qlo, qhi);
-    const uint32_t fp = (uint32_t)(h >> 45);
-    uint32_t slot = (uint32_t)h & kMask;
-    for (uint32_t p = 0; p < kLdsSlots; ++p) {
-      const uint32_t v = s_tab[slot];
-      if (v == 0u) break;
-      if ((v >> 13) == fp) {
-        const uint32_t j = (v & 0x1FFFu) - 1u;
-        if (in.key_lo[j] == qlo && (!WIDE || in.key_hi[j] == qhi)) {
-          s_par[i] = j;
-          s_par[j] = i;
-          break;
-        }
-      }
-      slot = (slot + 1u) & kMask;
-    }
-  }
-  __syncthreads();
-  // Evaluate and emit in entry order, 1024 entries per round.
-  uint32_t run = 0, dropped = 0;
-  double mass = 0.0;
-#pragma unroll
-  for (int k = 0; k < kLdsItems; ++k) {
-    const uint32_t i = (uint32_t)k * kLdsThreads + threadIdx.x;
-    U2Out r;
-    r.mode = 2;
-    r.o0 = r.o1 = make_double2(0.0, 0.0);
-    bool k0 = false, k1 = false;
-    if (i < n) {
-      r = u2_eval<WIDE>(in, d, lo[k], hi[k], in.amp[i], s_par[i]);
-      if (r.mode == 0) {
-        k0 = survives(r.o0, d.eps);
-        dropped += k0 ? 0u : 1u;
-        mass += ent::dropped_mass(r.o0, k0);
-      } else if (r.mode == 1) {
-        k0 = survives(r.o0, d.eps);
-        k1 = survives(r.o1, d.eps);
-        dropped += (k0 ? 0u : 1u) + (k1 ? 0u : 1u);
-        mass += ent::dropped_mass(r.o0, k0) + ent::dropped_mass(r.o1, k1);
-      }
-    }
-    uint32_t tt;
-    uint64_t p = run + block_prefix012((k0 ? 1u : 0u) + (k1 ? 1u : 0u), s_wave, &tt);
-    run += tt;
-    if (r.mode == 0) {
-      if (k0) {
-        out.key_lo[p] = lo[k];
-        if (WIDE) out.key_hi[p] = hi[k];
-        out.amp[p] = r.o0;
-      }
-    } else if (r.mode == 1) {
-      const bool v = pivot_set<WIDE>(d, lo[k], hi[k]);
-      const uint64_t lo0 = v ? lo[k] ^ d.x_lo : lo[k], hi0 = v ? hi[k] ^ d.x_hi : hi[k];
-      if (k0) {
-        out.key_lo[p] = lo0;
-        if (WIDE) out.key_hi[p] = hi0;
-        out.amp[p] = r.o0;
-        ++p;
-      }
-      if (k1) {
-        out.key_lo[p] = lo0 ^ d.x_lo;
-        if (WIDE) out.key_hi[p] = hi0 ^ d.x_hi;
-        out.amp[p] = r.o1;
-      }
-    }
-  }
-  dropped = block_sum(dropped, sh);
-  mass = block_sum(make_double2(mass, 0.0), shm).x;
+  // Outputs number at most 2 n, which the host has checked against the
+  // capacity, so the bound passed here never refuses a write.
+  const lds::Totals t = lds::u2_block<WIDE>(in, out, (uint32_t)n, d, ~0ull, sm);
   if (threadIdx.x == 0) {
-    if (dropped) {
-      atomicAdd((unsigned long long*)&ctl->pruned, (unsigned long long)dropped);
-      atomicAdd(&ctl->pruned_mass, mass);
+    if (t.dropped) {
+      atomicAdd((unsigned long long*)&ctl->pruned, (unsigned long long)t.dropped);
+      atomicAdd(&ctl->pruned_mass, t.mass);
     }
     atomicAdd((unsigned long long*)&ctl->updates, (unsigned long long)n);
-    *nnz_out = run;
-    if (run > ctl->peak) ctl->peak = run;
-    atomicAdd((unsigned long long*)&ctl->pass_bytes[4], (unsigned long long)((n + run) * (WIDE ? 32u : 24u)));
+    *nnz_out = t.out;
+    if (t.out > ctl->peak) ctl->peak = t.out;
+    atomicAdd((unsigned long long*)&ctl->pass_bytes[4], (unsigned long long)((n + t.out) * (WIDE ? 32u : 24u)));
   }
 }
 
@@ -981,9 +871,9 @@ void launch_u2_fused(hipStream_t st, bool wide, Buf in, Buf out, const uint64_t*
 void launch_u2_lds(hipStream_t st, bool wide, Buf in, Buf out, const uint64_t* nnz, const U2Desc& d, Ctl* ctl,
                    uint64_t* nnz_out) {
   if (wide)
-    hipLaunchKernelGGL(k_u2_lds<true>, dim3(1), dim3(kLdsThreads), 0, st, in, out, nnz, d, ctl, nnz_out);
+    hipLaunchKernelGGL(k_u2_lds<true>, dim3(1), dim3(lds::kThreads), 0, st, in, out, nnz, d, ctl, nnz_out);
   else
-    hipLaunchKernelGGL(k_u2_lds<false>, dim3(1), dim3(kLdsThreads), 0, st, in, out, nnz, d, ctl, nnz_out);
+    hipLaunchKernelGGL(k_u2_lds<false>, dim3(1), dim3(lds::kThreads), 0, st, in, out, nnz, d, ctl, nnz_out);
 }
 
 void launch_measure_reduce(hipStream_t st, bool wide, Buf b, const uint64_t* nnz, uint32_t q, BlockScratch s,

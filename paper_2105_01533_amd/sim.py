@@ -403,6 +403,7 @@ def run_pauli_workload(w, **kw):
 # --- continuous-batching server (srv_*) -----------------------------------------
 SRV_QUEUED, SRV_RUNNING, SRV_DONE, SRV_FAILED = 0, 1, 2, 3
 SRV_FLAG_NO_GRAPH = 1
+SRV_FLAG_U2_GLOBAL_INDEX = 2
 SRV_LANE_OFF = 0xFFFFFFFF
 
 
@@ -544,7 +545,7 @@ class Server:
 
     def __init__(self, budget_bytes: int, max_slots: int = 256, arena_bytes: int = 0, graph: bool = True,
                  tick_updates: int | None = None, grid: int | None = None, lane_capacity: int | None = None,
-                 lane_workers: int | None = None, device: str = "cuda", tuned: bool = True):
+                 lane_workers: int | None = None, device: str = "cuda", tuned: bool = True, flags: int = 0):
         """Server knobs left as None take the autotuner table's values (the
         library defaults with tuned=False); `knobs` records what was used.
         submit_workload applies the table's per-state knobs the same way."""
@@ -554,7 +555,7 @@ class Server:
         self.tuned = tuned
         self.knobs = autotune.server_knobs(given) if tuned else {k: (v or 0) for k, v in given.items()}
         self.cfg = srv_config(budget_bytes=budget_bytes, arena_bytes=arena_bytes, max_slots=max_slots,
-                              flags=0 if graph else SRV_FLAG_NO_GRAPH, **self.knobs)
+                              flags=flags | (0 if graph else SRV_FLAG_NO_GRAPH), **self.knobs)
         self.pool = torch.empty(budget_bytes, dtype=torch.uint8, device=device)
         self.h = srv_create(self.cfg, None, self.pool.data_ptr(), budget_bytes)
 

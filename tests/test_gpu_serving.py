@@ -47,10 +47,10 @@ def mix():
     return ws
 
 
-def run_server(S, ws, budget=1 << 30, slots=64, graph=True, arena_bytes=0, lane=None, **tuning):
+def run_server(S, ws, budget=1 << 30, slots=64, graph=True, arena_bytes=0, lane=None, flags=0, **tuning):
     """Every request batched unless `lane` (a lane threshold) is given."""
     srv = S.Server(budget, max_slots=slots, graph=graph, arena_bytes=arena_bytes,
-                   lane_capacity=S.SRV_LANE_OFF if lane is None else lane)
+                   lane_capacity=S.SRV_LANE_OFF if lane is None else lane, flags=flags)
     ids = [srv.submit_workload(w, **tuning) for w in ws]
     srv.run()
     out = []
@@ -263,3 +263,28 @@ def test_result_records_equal_arrays(S):
         if w.n_qubits <= 64:
             assert not hi.any()
     srv.close()
+
+
+def test_small_states_lds_index_equals_global_index(S):
+    """Branching gates of batched states of at most 4096 entries run one
+    block per state with the partner index in LDS; the results are bit for bit
+    those of the global-index kernels (SRV_FLAG_U2_GLOBAL_INDEX), alone and in
+    the mix, and each matches the oracle."""
+    ws = mix()
+    a, sa = run_server(S, ws)
+    b, sb = run_server(S, ws, flags=S.SRV_FLAG_U2_GLOBAL_INDEX)
+    assert sa["ticks"] == sb["ticks"]
+    for w, x, y in zip(ws, a, b):
+        for p, q in zip(x[:4], y[:4]):
+            assert p.tobytes() == q.tobytes(), w.name
+    # a state that crosses the limit: 12 Hadamards reach 4096 entries, the
+    # 13th and 14th run on 4096 and 8192 entries
+    c = W.Circuit()
+    for q in range(14):
+        c.h(q)
+    c.gate(W.K_RY, 3, controls=(20,), param=0.3)
+    w = W.Workload("h14", 24, 0.0, c.array(), 1 << 15, (1 << 20, 0))
+    for flags in (0, S.SRV_FLAG_U2_GLOBAL_INDEX):
+        res, _ = run_server(S, [w, ws[0]], flags=flags)
+        o, oout, _ = oracle_run(w)
+        assert_same_state(res[0][:3], o.export(), what=f"h14 flags={flags}")
