@@ -461,6 +461,12 @@ def main():
         "updates_per_s_in_kernel": mono["updates"] / (mono["total_ms"] * 1e-3) if mono["total_ms"] else 0.0,
     }
     value = updates / dt
+    # Partner-index counters from one more (untimed) step with counting on.
+    sim.sim_set_tuning(s.h, **{k: v for k, v in s.knobs.items() if k != "flags"},
+                       flags=s.knobs.get("flags", 0) | sim.SIM_FLAG_COUNT_INDEX)
+    s.set_basis(*w.basis)
+    _, _, st_ix = s.apply_gates(gates)
+    torch.cuda.synchronize()
     out = {
         "metric": "nonzero-amplitude gate updates/s",
         "value": value, "unit": "updates/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
@@ -472,6 +478,10 @@ def main():
                    "mono_passes_per_step": st["mono_passes"], "bitslice_passes_per_step": st["bitslice_passes"],
                    "u2_applied": st["u2_applied"], "u2_skipped": st["u2_skipped"], "measures": st["measures"],
                    "knobs": s.knobs,
+                   "index_per_step": {
+                       "inserts": st_ix["index_inserts"], "lookups": st_ix["index_lookups"],
+                       "cas_per_insert": round(st_ix["index_cas"] / max(st_ix["index_inserts"], 1), 4),
+                       "probes_per_lookup": round(st_ix["index_probes"] / max(st_ix["index_lookups"], 1), 4)},
                    "kernel_ms_per_step": kernel_ms, "host_ms_per_step": host_ms},
         "roofline": roofline,
         "copy": copy,

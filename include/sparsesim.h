@@ -181,6 +181,11 @@ typedef struct sim_config {
  * same outputs in the same order. */
 #define SIM_FLAG_U2_GLOBAL_INDEX 4u
 
+/* Count the global index's work (sim_stats index_*): one atomic add per
+ * block of the index-build and look-up kernels, so off by default.  The
+ * one-block LDS-index kernel always counts (four adds per gate). */
+#define SIM_FLAG_COUNT_INDEX 8u
+
 /* Fused phase/permutation pass variants.  DIRECT evaluates every gate on every
  * entry with sequential complex products (results bit-identical to a plain
  * sequential evaluation).  BITSLICE transposes 2048-entry tiles into bit-planes
@@ -206,6 +211,14 @@ typedef struct sim_stats {
   double pruned_mass;      /* sum of |a|^2 of the dropped entries (summed in no fixed
                               order: equal to the oracle's to rounding); the batched
                               server counts neither pruned nor pruned_mass (0) */
+  /* Partner-index work of the branching gates (Sec. 3.1): entries inserted,
+   * insert CAS attempts (inserts + collisions), partner look-ups and the index
+   * slots they read (probes / look-up is the mean probe length).  Always
+   * counted for the one-block LDS index; for the global index only with
+   * SIM_FLAG_COUNT_INDEX.  CAS attempts and probes depend on the order in
+   * which threads insert, so they vary from run to run; the batched server
+   * does not count them (0). */
+  uint64_t index_inserts, index_cas, index_lookups, index_probes;
 } sim_stats;
 
 typedef struct sim_t sim_t;

@@ -80,7 +80,8 @@ bool config_ok(const sim_config* c, std::string* why) {
     return *why = "load_factor must be in (0, 0.9]", false;
   if (c->block != 0 && c->block != 64 && c->block != 128 && c->block != 256)
     return *why = "block must be 64, 128 or 256", false;
-  if (c->flags & ~(SIM_FLAG_U2_TWO_PASS | SIM_FLAG_BS_LDS | SIM_FLAG_U2_GLOBAL_INDEX)) return *why = "unknown flags", false;
+  if (c->flags & ~(SIM_FLAG_U2_TWO_PASS | SIM_FLAG_BS_LDS | SIM_FLAG_U2_GLOBAL_INDEX | SIM_FLAG_COUNT_INDEX))
+    return *why = "unknown flags", false;
   if (c->mono_mode > SIM_MONO_BITSLICE) return *why = "unknown mono_mode", false;
   return true;
 }
@@ -279,6 +280,7 @@ struct sim_t {
   bool nnz_known;
   uint64_t nnz_exact, nnz_ub;
   uint64_t last_updates, last_pruned;
+  uint64_t last_ix[4];
   double last_mass;
 };
 
@@ -427,11 +429,13 @@ int run_u2(sim_t* s, const sim_gate& g, bool* over) {
   {
     KTimer t_(s, KC_BUILD);
     launch_index_build(s->stream, s->wide, s->buf[s->cur], nnz_in, s->table, slots - 1, d, s->partner,
+                       (s->cfg.flags & SIM_FLAG_COUNT_INDEX) ? s->ctl : nullptr,
                        flat_grid(ub), 256);
   }
   {
     KTimer t_(s, KC_U2_PROBE);
-    launch_u2_probe(s->stream, s->wide, s->buf[s->cur], nnz_in, s->table, slots - 1, d, s->partner, flat_grid(ub),
+    launch_u2_probe(s->stream, s->wide, s->buf[s->cur], nnz_in, s->table, slots - 1, d, s->partner,
+                    (s->cfg.flags & SIM_FLAG_COUNT_INDEX) ? s->ctl : nullptr, flat_grid(ub),
                     256);
   }
   if (!check && !(s->cfg.flags & SIM_FLAG_U2_TWO_PASS) && ub <= (uint64_t)kMaxBlocks * kU2Tile) {
@@ -615,6 +619,7 @@ int sim_create(const sim_config* cfg, void* stream, void* workspace, size_t ws_b
   s->nnz_known = true;
   s->nnz_exact = s->nnz_ub = 1;
   s->last_updates = s->last_pruned = 0;
+  for (int k = 0; k < 4; ++k) s->last_ix[k] = 0;
   s->last_mass = 0.0;
   *out = s;
   return SIM_OK;
@@ -1158,6 +1163,11 @@ int apply_impl(sim_t* s, const sim_gate* gates, size_t n, int32_t* outcomes, sim
   st.updates = s->h_ctl->updates - s->last_updates;
   st.pruned = s->h_ctl->pruned - s->last_pruned;
   st.pruned_mass = s->h_ctl->pruned_mass - s->last_mass;
+  st.index_inserts = s->h_ctl->ix[0] - s->last_ix[0];
+  st.index_cas = s->h_ctl->ix[1] - s->last_ix[1];
+  st.index_lookups = s->h_ctl->ix[2] - s->last_ix[2];
+  st.index_probes = s->h_ctl->ix[3] - s->last_ix[3];
+  for (int k = 0; k < 4; ++k) s->last_ix[k] = s->h_ctl->ix[k];
   st.peak_nnz = s->h_ctl->peak;
   s->last_updates = s->h_ctl->updates;
   s->last_pruned = s->h_ctl->pruned;
@@ -1319,7 +1329,8 @@ int sim_set_tuning(sim_t* s, const sim_config* t) {
   if (t->mono_mode > SIM_MONO_BITSLICE) return fail(SIM_E_ARG, "unknown mono_mode");
   // The fused-pass kernel (SIM_FLAG_BS_LDS) is chosen at creation only.
   if (t->flags & SIM_FLAG_BS_LDS) return fail(SIM_E_ARG, "SIM_FLAG_BS_LDS is set at creation (sim_create) only");
-  if (t->flags & ~(SIM_FLAG_U2_TWO_PASS | SIM_FLAG_U2_GLOBAL_INDEX)) return fail(SIM_E_ARG, "unknown flags");
+  if (t->flags & ~(SIM_FLAG_U2_TWO_PASS | SIM_FLAG_U2_GLOBAL_INDEX | SIM_FLAG_COUNT_INDEX))
+    return fail(SIM_E_ARG, "unknown flags");
   if (t->load_factor != 0.0 && !(t->load_factor > 0.0 && t->load_factor <= 0.9))
     return fail(SIM_E_ARG, "load_factor must be in (0, 0.9]");
   s->cfg.fuse_max = t->fuse_max ? t->fuse_max : 65536;

@@ -165,6 +165,9 @@ struct Ctl {
   // Algorithmic bytes (entries read and written) of the branching count and
   // write passes and of the measurement reduce and write passes.
   uint64_t pass_bytes[5];      // index 4: the one-block (LDS-index) branching kernel
+  // Partner index work of branching gates: entries inserted, CAS attempts
+  // (inserts + collisions), partner look-ups, slots the look-ups read.
+  uint64_t ix[4];
   uint32_t error;              // bit 0: a measurement had no valid outcome; bit 1: a chained scan gave up
                                // waiting; bit 2: the one-block branching kernel met a state too large for it
   uint32_t ticket;             // tile counter of the single-pass branching kernel (wraps)
@@ -273,10 +276,11 @@ hipError_t copy_state_to_host_soa(const uint64_t* lo, const uint64_t* hi, const 
                                   uint64_t* key_lo, uint64_t* key_hi, sim_c64* amps);
 void launch_fill(hipStream_t st, uint64_t* p, uint64_t v, uint64_t n);
 void launch_copy16(hipStream_t st, void* dst, const void* src, uint64_t n16);
+// ctl: where the index counters go (Ctl::ix), or null to count nothing.
 void launch_index_build(hipStream_t st, bool wide, Buf b, const uint64_t* nnz, uint64_t* table, uint64_t mask,
-                        const U2Desc& d, uint32_t* partner, int grid, int block);
+                        const U2Desc& d, uint32_t* partner, Ctl* ctl, int grid, int block);
 void launch_u2_probe(hipStream_t st, bool wide, Buf b, const uint64_t* nnz, const uint64_t* table, uint64_t mask,
-                     const U2Desc& d, uint32_t* partner, int grid, int block);
+                     const U2Desc& d, uint32_t* partner, Ctl* ctl, int grid, int block);
 void launch_u2_count(hipStream_t st, bool wide, Buf b, const uint64_t* nnz, const U2Desc& d, const uint32_t* partner,
                      uint32_t* tot, Ctl* ctl, int grid, int block);
 // cap: the count pass's staged counters are committed only if the total fits.

@@ -170,11 +170,24 @@ __global__ __launch_bounds__(256) void k_mono(Buf b, const uint64_t* __restrict_
 // Only the entries a partner look-up can ask for are indexed: those under
 // the op's controls with the pivot bit clear (the look-ups come from their
 // partners, whose pivot bit is set).  Every entry's partner slot starts empty.
+// Block sums of two per-thread counters added to dst[0], dst[1] by thread 0
+// (one atomic pair per block); nothing when dst is null (counting off).
+__device__ __forceinline__ void add_counters(unsigned long long* dst, uint32_t a, uint32_t b) {
+  __shared__ uint32_t sh_a[4], sh_b[4];
+  if (!dst) return;   // uniform: a kernel argument
+  const uint32_t x = block_sum(a, sh_a), y = block_sum(b, sh_b);
+  if (threadIdx.x == 0) {
+    if (x) atomicAdd(dst, (unsigned long long)x);
+    if (y) atomicAdd(dst + 1, (unsigned long long)y);
+  }
+}
+
 template <bool WIDE>
 __global__ __launch_bounds__(256) void k_index_build(Buf b, const uint64_t* __restrict__ nnz_p,
                                                      unsigned long long* table, uint64_t mask, U2Desc d,
-                                                     uint32_t* __restrict__ partner) {
+                                                     uint32_t* __restrict__ partner, unsigned long long* count) {
   const uint64_t n = *nnz_p;
+  uint32_t inserts = 0, cas = 0;
   for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x) {
     partner[i] = kNoPartner;
     const uint64_t lo = b.key_lo[i];
@@ -186,21 +199,25 @@ __global__ __launch_bounds__(256) void k_index_build(Buf b, const uint64_t* __re
     const uint64_t h = hash_label(lo, hi);
     const unsigned long long val = ((h >> 32) << 32) | i;
     uint64_t slot = h & mask;
+    ++inserts;
     for (uint64_t p = 0; p <= mask; ++p) {
+      ++cas;
       if (atomicCAS(&table[slot], (unsigned long long)kEmptySlot, val) == kEmptySlot) break;
       slot = (slot + 1) & mask;
     }
   }
+  add_counters(count, inserts, cas);
 }
 
 template <bool WIDE>
 __device__ __forceinline__ uint32_t find_label(const Buf& b, const uint64_t* __restrict__ table, uint64_t mask,
-                                               uint64_t lo, uint64_t hi) {
+                                               uint64_t lo, uint64_t hi, uint32_t& steps) {
   const uint64_t h = hash_label(lo, hi);
   const uint32_t fp = (uint32_t)(h >> 32);
   uint64_t slot = h & mask;
   for (uint64_t p = 0; p <= mask; ++p) {
     const uint64_t s = table[slot];
+    ++steps;
     if (s == kEmptySlot) return kNoPartner;
     if ((uint32_t)(s >> 32) == fp) {
       const uint32_t j = (uint32_t)s;
@@ -218,8 +235,9 @@ __device__ __forceinline__ uint32_t find_label(const Buf& b, const uint64_t* __r
 template <bool WIDE>
 __global__ __launch_bounds__(256) void k_u2_probe(Buf b, const uint64_t* __restrict__ nnz_p,
                                                   const uint64_t* __restrict__ table, uint64_t mask, U2Desc d,
-                                                  uint32_t* __restrict__ partner) {
+                                                  uint32_t* __restrict__ partner, unsigned long long* count) {
   const uint64_t n = *nnz_p;
+  uint32_t lookups = 0, steps = 0;
   for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x) {
     const uint64_t lo = b.key_lo[i];
     const uint64_t hi = WIDE ? b.key_hi[i] : 0ull;
@@ -227,11 +245,13 @@ __global__ __launch_bounds__(256) void k_u2_probe(Buf b, const uint64_t* __restr
     if (WIDE) c = c && ((hi & d.ctrl_hi) == d.ctrl_hi);
     const uint64_t w = (WIDE && d.target >= 64) ? hi : lo;
     if (!c || !((w >> (d.target & 63)) & 1ull)) continue;
-    const uint32_t j = find_label<WIDE>(b, table, mask, lo ^ d.x_lo, WIDE ? (hi ^ d.x_hi) : 0ull);
+    ++lookups;
+    const uint32_t j = find_label<WIDE>(b, table, mask, lo ^ d.x_lo, WIDE ? (hi ^ d.x_hi) : 0ull, steps);
     if (j == kNoPartner) continue;
     partner[i] = j;
     partner[j] = (uint32_t)i;
   }
+  add_counters(count, lookups, steps);
 }
 
 template <bool WIDE>
@@ -575,6 +595,8 @@ __global__ __launch_bounds__(1024) void k_u2_lds(Buf in, Buf out, const uint64_t
       atomicAdd(&ctl->pruned_mass, t.mass);
     }
     atomicAdd((unsigned long long*)&ctl->updates, (unsigned long long)n);
+    for (int k = 0; k < 4; ++k)
+      if (t.ix[k]) atomicAdd((unsigned long long*)&ctl->ix[k], (unsigned long long)t.ix[k]);
     *nnz_out = t.out;
     if (t.out > ctl->peak) ctl->peak = t.out;
     atomicAdd((unsigned long long*)&ctl->pass_bytes[4], (unsigned long long)((n + t.out) * (WIDE ? 32u : 24u)));
@@ -820,20 +842,22 @@ void launch_mono(hipStream_t st, bool wide, Buf b, const uint64_t* nnz, const Mo
 }
 
 void launch_index_build(hipStream_t st, bool wide, Buf b, const uint64_t* nnz, uint64_t* table, uint64_t mask,
-                        const U2Desc& d, uint32_t* partner, int grid, int block) {
+                        const U2Desc& d, uint32_t* partner, Ctl* ctl, int grid, int block) {
   auto* t = reinterpret_cast<unsigned long long*>(table);
+  auto* count = ctl ? reinterpret_cast<unsigned long long*>(&ctl->ix[0]) : nullptr;
   if (wide)
-    hipLaunchKernelGGL(k_index_build<true>, dim3(grid), dim3(block), 0, st, b, nnz, t, mask, d, partner);
+    hipLaunchKernelGGL(k_index_build<true>, dim3(grid), dim3(block), 0, st, b, nnz, t, mask, d, partner, count);
   else
-    hipLaunchKernelGGL(k_index_build<false>, dim3(grid), dim3(block), 0, st, b, nnz, t, mask, d, partner);
+    hipLaunchKernelGGL(k_index_build<false>, dim3(grid), dim3(block), 0, st, b, nnz, t, mask, d, partner, count);
 }
 
 void launch_u2_probe(hipStream_t st, bool wide, Buf b, const uint64_t* nnz, const uint64_t* table, uint64_t mask,
-                     const U2Desc& d, uint32_t* partner, int grid, int block) {
+                     const U2Desc& d, uint32_t* partner, Ctl* ctl, int grid, int block) {
+  auto* count = ctl ? reinterpret_cast<unsigned long long*>(&ctl->ix[2]) : nullptr;
   if (wide)
-    hipLaunchKernelGGL(k_u2_probe<true>, dim3(grid), dim3(block), 0, st, b, nnz, table, mask, d, partner);
+    hipLaunchKernelGGL(k_u2_probe<true>, dim3(grid), dim3(block), 0, st, b, nnz, table, mask, d, partner, count);
   else
-    hipLaunchKernelGGL(k_u2_probe<false>, dim3(grid), dim3(block), 0, st, b, nnz, table, mask, d, partner);
+    hipLaunchKernelGGL(k_u2_probe<false>, dim3(grid), dim3(block), 0, st, b, nnz, table, mask, d, partner, count);
 }
 
 void launch_u2_count(hipStream_t st, bool wide, Buf b, const uint64_t* nnz, const U2Desc& d, const uint32_t* partner,

@@ -37,6 +37,7 @@ struct Totals {
   uint32_t out;       // outputs (entries of the new state)
   uint32_t dropped;   // outputs T_eps dropped
   double mass;        // their |a|^2, summed in a fixed order
+  uint32_t ix[4];     // index work: inserts, CAS attempts, look-ups, slots read by look-ups
 };
 
 // Exclusive prefix over the block of e in {0, 1, 2}, in thread order; *total
@@ -88,6 +89,7 @@ template <bool WIDE>
 __device__ Totals u2_block(const Buf& in, const Buf& out, uint32_t n, const U2Desc& d, uint64_t cap, Smem& sm) {
   constexpr uint32_t kMask = kSlots - 1;
   for (uint32_t k = threadIdx.x; k < kSlots; k += kThreads) sm.tab[k] = 0u;
+  uint32_t inserts = 0, cas = 0, lookups = 0, steps = 0;
   uint64_t lo[kItems], hi[kItems];
 #pragma unroll
   for (int k = 0; k < kItems; ++k) {
@@ -108,7 +110,9 @@ __device__ Totals u2_block(const Buf& in, const Buf& out, uint32_t n, const U2De
     const uint64_t h = ent::hash_label(lo[k], hi[k]);
     const uint32_t val = ((uint32_t)(h >> 45) << 13) | (i + 1u);
     uint32_t slot = (uint32_t)h & kMask;
+    ++inserts;
     for (uint32_t p = 0; p < kSlots; ++p) {
+      ++cas;
       if (atomicCAS(&sm.tab[slot], 0u, val) == 0u) break;
       slot = (slot + 1u) & kMask;
     }
@@ -124,8 +128,10 @@ __device__ Totals u2_block(const Buf& in, const Buf& out, uint32_t n, const U2De
     const uint64_t h = ent::hash_label(qlo, qhi);
     const uint32_t fp = (uint32_t)(h >> 45);
     uint32_t slot = (uint32_t)h & kMask;
+    ++lookups;
     for (uint32_t p = 0; p < kSlots; ++p) {
       const uint32_t v = sm.tab[slot];
+      ++steps;
       if (v == 0u) break;
       if ((v >> 13) == fp) {
         const uint32_t j = (v & 0x1FFFu) - 1u;
@@ -196,6 +202,10 @@ __device__ Totals u2_block(const Buf& in, const Buf& out, uint32_t n, const U2De
   t.out = run;
   t.dropped = sum_u(dropped, sm);
   t.mass = sum_d(mass, sm);
+  t.ix[0] = sum_u(inserts, sm);
+  t.ix[1] = sum_u(cas, sm);
+  t.ix[2] = sum_u(lookups, sm);
+  t.ix[3] = sum_u(steps, sm);
   return t;
 }
 

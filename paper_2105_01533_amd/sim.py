@@ -29,6 +29,7 @@ SIM_PROFILE_OFF, SIM_PROFILE_ALL, SIM_PROFILE_MONO = 0, 1, 2
 SIM_FLAG_U2_TWO_PASS = 1
 SIM_FLAG_BS_LDS = 2
 SIM_FLAG_U2_GLOBAL_INDEX = 4
+SIM_FLAG_COUNT_INDEX = 8
 
 GATE_DTYPE = np.dtype([
     ("op", "<u4"), ("target", "<u4"), ("ctrl_lo", "<u8"), ("ctrl_hi", "<u8"),
@@ -48,7 +49,8 @@ class sim_config(ctypes.Structure):
 class sim_stats(ctypes.Structure):
     _fields_ = [(f, ctypes.c_uint64) for f in (
         "gates_applied", "updates", "mono_passes", "u2_applied", "u2_skipped", "measures", "host_syncs",
-        "peak_nnz", "pruned", "bitslice_passes")] + [("pruned_mass", ctypes.c_double)]
+        "peak_nnz", "pruned", "bitslice_passes")] + [("pruned_mass", ctypes.c_double)] + [
+        (f, ctypes.c_uint64) for f in ("index_inserts", "index_cas", "index_lookups", "index_probes")]
 
     def as_dict(self):
         return {f: (float if t is ctypes.c_double else int)(getattr(self, f)) for f, t in self._fields_}

@@ -280,6 +280,8 @@ def test_config2_full_properties(sim):
     assert abs(np.sum(np.abs(g1[2]) ** 2) - 1.0) < 1e-9
     g2, out2, st2 = gpu_run(sim, w)
     m1, m2 = st1.pop("pruned_mass"), st2.pop("pruned_mass")   # summed in no fixed order
+    for k in ("index_cas", "index_probes"):                      # depend on the insert order
+        st1.pop(k), st2.pop(k)
     assert list(out1) == list(out2) and st1 == st2 and abs(m1 - m2) <= 1e-12 * max(1.0, m1)
     for a, b in zip(g1, g2):
         assert a.tobytes() == b.tobytes()
@@ -1006,3 +1008,57 @@ def test_u2_lds_kernel_around_its_limit(sim, n, size):
     assert_same_state(tuple(x[order] for x in a), o.export(), 1e-12, f"lds {n} {size}")
     t_ = o.totals()
     assert sa["updates"] == t_["updates"] and sa["pruned"] == t_["pruned"]
+
+
+@pytest.mark.parametrize("n", [30, 100])
+@pytest.mark.parametrize("size", [3000, 50_000])
+def test_index_counters(sim, n, size):
+    """Partner-index counters (SIM_FLAG_COUNT_INDEX) of one controlled
+    branching gate on an imported state: inserts are the entries under the
+    control with the pivot bit clear
+    and look-ups those with it set (exact, for the one-block LDS index at 3000
+    entries and the global index at 50,000); CAS attempts and probes are at
+    least one per insert and per look-up, and at load factor <= 1/2 stay
+    close to one."""
+    t, ctl = (5, n - 2)
+    lo, hi, amp = _paired_state(7000 + size + n, size, n, t)
+    c = W.Circuit()
+    c.gate(W.K_RY, t, controls=(ctl,), param=0.4)
+    for flags in (sim.SIM_FLAG_COUNT_INDEX, sim.SIM_FLAG_U2_GLOBAL_INDEX | sim.SIM_FLAG_COUNT_INDEX):
+        s = sim.Simulator(n, 1 << 17, 0.0, flags=flags)
+        try:
+            s.import_state(lo, hi, amp)
+            _, _, st = s.apply_ops(c.array())
+        finally:
+            s.close()
+        cw = hi if ctl >= 64 else lo
+        under = ((cw >> np.uint64(ctl & 63)) & np.uint64(1)).astype(bool)
+        piv = ((lo >> np.uint64(t)) & np.uint64(1)).astype(bool)
+        assert st["index_inserts"] == int(np.sum(under & ~piv)), flags
+        assert st["index_lookups"] == int(np.sum(under & piv)), flags
+        assert st["index_inserts"] <= st["index_cas"] <= 2 * st["index_inserts"] + 64
+        assert st["index_lookups"] <= st["index_probes"] <= 3 * st["index_lookups"] + 64
+        say(f"[gpu] index counters n={n} size={size} flags={flags}: {st['index_cas'] / max(st['index_inserts'], 1):.3f} "
+            f"CAS/insert, {st['index_probes'] / max(st['index_lookups'], 1):.3f} probes/look-up")
+
+
+def test_index_counting_is_opt_in_for_the_global_index(sim):
+    """Without SIM_FLAG_COUNT_INDEX the global index counts nothing (its
+    kernels do no counter atomics); the result is the same either way."""
+    lo, hi, amp = _paired_state(7777, 50_000, 40, 5)
+    c = W.Circuit()
+    c.h(5)
+    out = []
+    for flags in (0, sim.SIM_FLAG_COUNT_INDEX):
+        s = sim.Simulator(40, 1 << 17, 0.0, flags=flags)
+        try:
+            s.import_state(lo, hi, amp)
+            _, _, st = s.apply_ops(c.array())
+            out.append((s.export(sort=False), st))
+        finally:
+            s.close()
+    (a, sa), (b, sb) = out
+    for x, y in zip(a, b):
+        assert x.tobytes() == y.tobytes()
+    assert sa["index_inserts"] == sa["index_lookups"] == sa["index_cas"] == sa["index_probes"] == 0
+    assert sb["index_inserts"] > 0 and sb["index_lookups"] > 0

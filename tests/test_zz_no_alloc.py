@@ -24,6 +24,9 @@ def _same(S, A, B, gates, what):
     _, oa, sa = S.sim_apply_gates(A.h, gates)
     _, ob, sb = S.sim_apply_gates_static(B.h, gates)
     ma, mb = sa.pop("pruned_mass"), sb.pop("pruned_mass")
+    # CAS attempts and probe lengths depend on the order threads insert in
+    for k, base in (("index_cas", "index_inserts"), ("index_probes", "index_lookups")):
+        assert sa.pop(k) >= sa[base] and sb.pop(k) >= sb[base], what
     assert list(oa) == list(ob), what
     assert sa == sb, (what, sa, sb)
     assert abs(ma - mb) <= 1e-12 * max(1.0, ma), what
