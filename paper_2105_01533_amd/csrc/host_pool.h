@@ -26,6 +26,10 @@ class HostPool {
   }
 
   unsigned threads() const { return (unsigned)workers_.size() + 1; }
+  // Parallel work asked for by the calling thread runs serially on it from
+  // now on (for the library's other worker threads, so that they never wait
+  // for this pool's jobs).
+  static void run_serially_here() { in_task() = true; }
 
   // fn(i) for i in [0, n); blocks until every task has finished and every
   // worker has left the job.

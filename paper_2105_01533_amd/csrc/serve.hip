@@ -21,6 +21,7 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <atomic>
 #include <condition_variable>
 #include <cstring>
 #include <deque>
@@ -195,7 +196,12 @@ struct Request {
   size_t i = 0;
   size_t mono_seen = 0;
   bool deferred = false;              // its last fused run did not fit the tick's arena
-  bool copied = false;                // final state copied to keys/amps
+  bool copied = false;                // final state copied to the result arrays
+  hipError_t copy_err = hipSuccess;
+  // A background host job (compile, grouping or copy out) is in flight for
+  // this request; what it writes is the tick thread's to read once this is
+  // false (stored under the server's bg_mu, read with acquire).
+  std::atomic<bool> bg_busy{false};
   // Grouping of the fused run expected next, made while the previous tick ran
   // on the GPU; used only if the run that comes is exactly [b, b + len).
   struct Ahead {
@@ -261,6 +267,16 @@ struct srv_t {
   std::vector<Request*> lane_done;    // finished by the lane thread
   bool lane_stop = false;
   double lane_ms = 0.0;               // lane thread only (read under lane_mu)
+  // Background host workers (host work only; a copy out reads device memory
+  // with hipMemcpy): compiling submitted circuits, grouping the runs requests
+  // are expected to take next, copying finished states out.
+  std::vector<std::thread> bg_threads;
+  std::mutex bg_mu;
+  std::condition_variable bg_cv, bg_done_cv;
+  std::deque<std::pair<Request*, int>> bg_urgent, bg_normal;   // groupings; compiles and copies
+  bool bg_stop = false;
+  double bg_copy_ms = 0.0;            // under bg_mu
+  std::vector<Request*> copying;      // finished, state being copied out (tick thread)
 };
 
 namespace {
@@ -481,13 +497,97 @@ void lane_admit(srv_t* s) {
   }
 }
 
+// ---- background host workers -------------------------------------------------
+enum BgKind { BG_COMPILE, BG_GROUP, BG_COPY };
+constexpr int kBgThreads = 8;
+
+double bg_ms_since(std::chrono::steady_clock::time_point t0) {
+  return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+}
+
+// Queue a job for r (at most one in flight per request).  A grouping job
+// finds its run in r.ahead (b, len, br), set by the caller beforehand.
+void bg_push(srv_t* s, Request* r, BgKind k) {
+  r->bg_busy.store(true, std::memory_order_relaxed);
+  {
+    std::lock_guard<std::mutex> lk(s->bg_mu);
+    (k == BG_GROUP ? s->bg_urgent : s->bg_normal).emplace_back(r, (int)k);
+  }
+  s->bg_cv.notify_one();
+}
+
+void bg_main(srv_t* s) {
+  (void)hipSetDevice(s->device);
+  HostPool::run_serially_here();
+  for (;;) {
+    std::pair<Request*, int> job;
+    {
+      std::unique_lock<std::mutex> lk(s->bg_mu);
+      s->bg_cv.wait(lk, [&] { return s->bg_stop || !s->bg_urgent.empty() || !s->bg_normal.empty(); });
+      if (s->bg_stop) return;
+      auto& q = s->bg_urgent.empty() ? s->bg_normal : s->bg_urgent;
+      job = q.front();
+      q.pop_front();
+    }
+    Request& r = *job.first;
+    double ms = 0.0;
+    switch (job.second) {
+      case BG_COMPILE:
+        compile_request(r);
+        break;
+      case BG_GROUP:
+        r.rc.group(r.ahead.b, r.ahead.len, r.ahead.grp, &r.ahead.br);
+        r.ahead.valid = true;
+        break;
+      case BG_COPY: {
+        const auto t0 = std::chrono::steady_clock::now();
+        r.copy_err = copy_out(r);
+        ms = bg_ms_since(t0);
+        break;
+      }
+    }
+    {
+      std::lock_guard<std::mutex> lk(s->bg_mu);
+      s->bg_copy_ms += ms;
+      r.bg_busy.store(false, std::memory_order_release);
+    }
+    s->bg_done_cv.notify_all();
+  }
+}
+
+// Wait until r has no background job in flight.
+void bg_wait(srv_t* s, Request* r) {
+  std::unique_lock<std::mutex> lk(s->bg_mu);
+  s->bg_done_cv.wait(lk, [&] { return !r->bg_busy.load(std::memory_order_acquire); });
+}
+
+// Wait (at most `us` microseconds) for any background job to finish.
+void bg_wait_any(srv_t* s, int us) {
+  std::unique_lock<std::mutex> lk(s->bg_mu);
+  s->bg_done_cv.wait_for(lk, std::chrono::microseconds(us));
+}
+
+void bg_shutdown(srv_t* s) {
+  {
+    std::lock_guard<std::mutex> lk(s->bg_mu);
+    s->bg_stop = true;
+    s->bg_urgent.clear();   // jobs running now finish; queued ones are dropped
+    s->bg_normal.clear();
+  }
+  s->bg_cv.notify_all();
+  for (auto& t : s->bg_threads) t.join();
+  s->bg_threads.clear();
+}
+
 // Admission uploads read from these (and from the request and the pinned
 // control words), which outlive the copies.
 const double kUnitAmp[2] = {1.0, 0.0};
 
+// Admits queued requests in FIFO order while memory and slots last.  Their
+// circuits are compiled in the background from submission on; a request
+// takes no segment until that is done.
 int admit(srv_t* s) {
   lane_admit(s);
-  std::vector<Request*> fresh;
   while (!s->queue.empty() && !s->free_slots.empty()) {
     Request& r = *s->reqs[s->queue.front()];
     size_t off;
@@ -523,10 +623,7 @@ int admit(srv_t* s) {
     r.state = SRV_RUNNING;
     s->running.push_back(&r);
     s->stats.admitted++;
-    if (!r.compiled) fresh.push_back(&r);
   }
-  // Newly admitted circuits are compiled on the host thread pool.
-  HostPool::get().run(fresh.size(), [&](size_t k) { compile_request(*fresh[k]); });
   return SIM_OK;
 }
 
@@ -597,12 +694,17 @@ int srv_create(const srv_config* cfg, void* stream, void* pool, size_t pool_byte
       s->lane_threads.emplace_back([raw, st] { lane_main(raw, st); });
     }
   }
+  {
+    srv_t* raw = s.get();
+    for (int k = 0; k < kBgThreads; ++k) s->bg_threads.emplace_back([raw] { bg_main(raw); });
+  }
   *out = s.release();
   return SIM_OK;
 }
 
 int srv_destroy(srv_t* s) {
   if (!s) return SIM_OK;
+  bg_shutdown(s);
   if (!s->lane_threads.empty()) {
     {
       std::lock_guard<std::mutex> lk(s->lane_mu);
@@ -668,8 +770,10 @@ int srv_submit(srv_t* s, const sim_config* cfg, const sim_gate* gates, size_t n,
   r->id = s->next_id++;
   *id = r->id;
   (r->large ? s->lane_queue : s->queue).push_back(r->id);
+  Request* raw = r.get();
   s->reqs[r->id] = std::move(r);
   s->stats.submitted++;
+  if (!raw->large) bg_push(s, raw, BG_COMPILE);
   return SIM_OK;
 }
 
@@ -678,27 +782,15 @@ double ms_since(std::chrono::steady_clock::time_point t0) {
   return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
 }
 
-// Queued requests compiled ahead of their admission, at most this many per tick.
-constexpr size_t kCompileAhead = 16;
-
-// Host work done while a tick runs on the GPU, on the host thread pool:
-// - requests that finished before the tick have their states copied out;
-// - each request in the tick gets the grouping of the fused run it is expected
-//   to take next.  Its state size after the tick is predicted (unchanged by a
-//   fused run or, as an upper bound, by a measurement; doubled, up to the
-//   capacity, by a branching gate), which fixes the cap's skip decisions and
-//   with them where the run ends.  The next tick uses the grouping only if the
-//   run that comes is the same, so a wrong prediction costs time, not results.
-// - the first queued requests not yet compiled are compiled.
-int work_ahead(srv_t* s, const std::vector<Request*>& done, const std::vector<Request*>& mono,
-               const std::vector<Request*>& u2, const std::vector<Request*>& meas) {
-  enum Kind { COPY, GROUP, COMPILE };
-  struct Task {
-    Request* r;
-    Kind kind;
-    size_t weight;
-  };
-  std::vector<Task> tasks;
+// After a tick is launched, each request in it has the grouping of the fused
+// run it is expected to take next made in the background.  Its state size
+// after the tick is predicted (unchanged by a fused run or, as an upper bound,
+// by a measurement; doubled, up to the capacity, by a branching gate), which
+// fixes the cap's skip decisions and with them where the run ends.  A later
+// tick uses the grouping only if the run that comes is the same, so a wrong
+// prediction costs time, not results.
+void group_ahead(srv_t* s, const std::vector<Request*>& mono, const std::vector<Request*>& u2,
+                 const std::vector<Request*>& meas) {
   auto plan = [&](Request* r, uint64_t nnz) {
     Cursor c{r->i, r->mono_seen, 0};
     size_t b = 0, len = 0, op = 0;
@@ -710,45 +802,28 @@ int work_ahead(srv_t* s, const std::vector<Request*>& done, const std::vector<Re
     r->ahead.len = len;
     r->ahead.br = br;
     r->ahead.grp.clear();
-    tasks.push_back(Task{r, GROUP, len});
+    bg_push(s, r, BG_GROUP);
   };
-  for (Request* r : done) tasks.push_back(Task{r, COPY, 8 * r->nnz});
   for (Request* r : mono) plan(r, r->nnz);
   for (Request* r : meas) plan(r, r->nnz);
   for (Request* r : u2) plan(r, std::min<uint64_t>(2 * r->nnz, r->cfg.capacity));
-  size_t compiles = 0;
-  for (uint64_t id : s->queue) {
-    if (compiles == kCompileAhead) break;
-    Request& r = *s->reqs[id];
-    if (r.compiled) continue;
-    tasks.push_back(Task{&r, COMPILE, r.gates.size()});
-    ++compiles;
-  }
-  // Longest first, for balance across the pool.
-  std::stable_sort(tasks.begin(), tasks.end(), [](const Task& a, const Task& b) { return a.weight > b.weight; });
-  std::vector<hipError_t> err(tasks.size(), hipSuccess);
-  std::vector<double> copy_ms(tasks.size(), 0.0);
-  HostPool::get().run(tasks.size(), [&](size_t t) {
-    Request& r = *tasks[t].r;
-    switch (tasks[t].kind) {
-      case COPY: {
-        const auto t0 = std::chrono::steady_clock::now();
-        err[t] = copy_out(r);
-        copy_ms[t] = ms_since(t0);
-        break;
-      }
-      case COMPILE:
-        compile_request(r);
-        break;
-      case GROUP:
-        r.rc.group(r.ahead.b, r.ahead.len, r.ahead.grp, &r.ahead.br);
-        r.ahead.valid = true;
-        break;
+}
+
+// Finished requests whose states have been copied out release their memory
+// and become done.
+int fold_copies(srv_t* s) {
+  for (size_t k = 0; k < s->copying.size();) {
+    Request* r = s->copying[k];
+    if (r->bg_busy.load(std::memory_order_acquire)) {
+      ++k;
+      continue;
     }
-  });
-  for (size_t t = 0; t < tasks.size(); ++t) {
-    s->stats.copy_ms += copy_ms[t];
-    if (err[t] != hipSuccess) return sfail(SIM_E_HIP, std::string("copying a finished state out: ") + hipGetErrorString(err[t]));
+    if (r->copy_err != hipSuccess)
+      return sfail(SIM_E_HIP, std::string("copying a finished state out: ") + hipGetErrorString(r->copy_err));
+    const int rc = finish(s, *r, SRV_DONE, SIM_OK);
+    if (rc) return rc;
+    s->copying[k] = s->copying.back();
+    s->copying.pop_back();
   }
   return SIM_OK;
 }
@@ -765,7 +840,9 @@ int srv_tick(srv_t* s, uint32_t* running, uint32_t* queued) {
     ~HostTime() { s->stats.host_ms += ms_since(t0) - (s->stats.wait_ms - wait0); }
   } host_time{s, t_tick, wait0};
   lane_fold(s);
-  int rc = admit(s);
+  int rc = fold_copies(s);
+  if (rc) return rc;
+  rc = admit(s);
   if (rc) return rc;
   // Assemble the work list.
   auto* hdr = reinterpret_cast<BTick*>(s->h_tick);
@@ -793,7 +870,12 @@ int srv_tick(srv_t* s, uint32_t* running, uint32_t* queued) {
   // Requests whose fused run was deferred last tick (the arena was full) go
   // first, so that none waits more than one tick for arena space.
   std::stable_partition(s->running.begin(), s->running.end(), [](const Request* r) { return r->deferred; });
+  size_t waiting = 0;   // requests whose background job (compile, grouping) is not done
   for (Request* r : s->running) {
+    if (r->bg_busy.load(std::memory_order_acquire)) {
+      ++waiting;
+      continue;
+    }
     Seg sg{r, SEG_NONE};
     sg.k = next_segment(s, *r, &sg.b, &sg.len, &sg.op);
     r->seg = sg.k;
@@ -913,17 +995,13 @@ int srv_tick(srv_t* s, uint32_t* running, uint32_t* queued) {
       meas_items.push_back(it);
     }
   }
-  // Finished requests are copied out while the tick runs (their memory is
-  // not in it; it is reused from the next tick's admission on).
-  auto retire_done = [&]() -> int {
-    for (Request* r : done_now) {
-      const int frc = finish(s, *r, SRV_DONE, SIM_OK);
-      if (frc) return frc;
-      s->running.erase(std::find(s->running.begin(), s->running.end(), r));
-    }
-    done_now.clear();
-    return SIM_OK;
-  };
+  // Finished requests leave the tick; their states are copied out in the
+  // background (their memory is released once that is done).
+  for (Request* r : done_now) {
+    s->running.erase(std::find(s->running.begin(), s->running.end(), r));
+    s->copying.push_back(r);
+    bg_push(s, r, BG_COPY);
+  }
   const uint32_t nm = (uint32_t)mono_items.size(), nu = (uint32_t)u2_items.size(), nq = (uint32_t)meas_items.size();
   const uint32_t ns = (uint32_t)u2s_items.size();
   if (nm + nu + nq + ns) {
@@ -977,13 +1055,10 @@ int srv_tick(srv_t* s, uint32_t* running, uint32_t* queued) {
     for (Request* r : s->running) max_slot = std::max(max_slot, r->slot);
     SRV_HIP(hipMemcpyAsync(s->h_ctl, s->d_ctl, (size_t)(max_slot + 1) * sizeof(SlotCtl), hipMemcpyDeviceToHost,
                            s->stream));
-    // Host work that does not wait for this tick runs while it does.
+    // The expected next runs are grouped in the background while the tick runs.
     {
       const auto t_a = std::chrono::steady_clock::now();
-      rc = work_ahead(s, done_now, mono, u2, meas);
-      if (rc) return rc;
-      rc = retire_done();
-      if (rc) return rc;
+      group_ahead(s, mono, u2, meas);
       s->stats.ahead_ms += ms_since(t_a);
     }
     {
@@ -1018,13 +1093,20 @@ int srv_tick(srv_t* s, uint32_t* running, uint32_t* queued) {
       r->st.measures++;
     }
     for (auto& f : failed) {
+      bg_wait(s, f.first);   // a grouping made for it may be in flight
       rc = finish(s, *f.first, SRV_FAILED, f.second);
       if (rc) return rc;
       s->running.erase(std::find(s->running.begin(), s->running.end(), f.first));
     }
   }
-  rc = retire_done();
+  rc = fold_copies(s);
   if (rc) return rc;
+  if (nm + nu + nq + ns == 0 && (waiting || !s->copying.empty())) {
+    // Nothing launched: wait (briefly) for the background work instead of spinning.
+    const auto t_w = std::chrono::steady_clock::now();
+    bg_wait_any(s, 200);
+    s->stats.wait_ms += ms_since(t_w);
+  }
   if (s->running.empty() && s->lane_in_flight) {
     // Nothing batched to do: wait (briefly) for the lane instead of spinning.
     const auto t_w = std::chrono::steady_clock::now();
@@ -1033,7 +1115,7 @@ int srv_tick(srv_t* s, uint32_t* running, uint32_t* queued) {
     lk.unlock();
     s->stats.wait_ms += ms_since(t_w);
   }
-  if (running) *running = (uint32_t)(s->running.size() + s->lane_in_flight);
+  if (running) *running = (uint32_t)(s->running.size() + s->copying.size() + s->lane_in_flight);
   if (queued) *queued = (uint32_t)(s->queue.size() + s->lane_queue.size());
   s->stats.pool_peak_bytes = s->pool.peak;
   s->stats.pool_used_bytes = s->pool.used;
@@ -1046,7 +1128,7 @@ int srv_run(srv_t* s) {
   while (run || q) {
     // A tick that starts with nothing running has the whole pool and every
     // slot free: if it admits nothing, the queue's head can never fit.
-    const bool idle = s->running.empty() && s->lane_in_flight == 0;
+    const bool idle = s->running.empty() && s->copying.empty() && s->lane_in_flight == 0;
     const uint64_t before = s->stats.admitted;
     int rc = srv_tick(s, &run, &q);
     if (rc) return rc;
@@ -1139,6 +1221,10 @@ int srv_release(srv_t* s, uint64_t id) {
 
 int srv_get_stats(srv_t* s, srv_stats* out) {
   if (!s || !out) return sfail(SIM_E_ARG, "null argument");
+  {
+    std::lock_guard<std::mutex> lk(s->bg_mu);
+    s->stats.copy_ms = s->bg_copy_ms;
+  }
   *out = s->stats;
   return SIM_OK;
 }

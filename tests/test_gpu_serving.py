@@ -85,7 +85,9 @@ def test_graph_replay_equals_direct_launches(S):
     ws = mix()[:5]
     a, sa = run_server(S, ws, graph=True)
     b, sb = run_server(S, ws, graph=False)
-    assert sa["ticks"] == sb["ticks"]
+    # (tick counts may differ: a request sits out a tick while its circuit is
+    # still being compiled or its next run grouped in the background)
+    assert sa["completed"] == sb["completed"] == len(ws)
     for x, y in zip(a, b):
         for p, q in zip(x[:4], y[:4]):
             assert p.tobytes() == q.tobytes()
@@ -273,7 +275,7 @@ def test_small_states_lds_index_equals_global_index(S):
     ws = mix()
     a, sa = run_server(S, ws)
     b, sb = run_server(S, ws, flags=S.SRV_FLAG_U2_GLOBAL_INDEX)
-    assert sa["ticks"] == sb["ticks"]
+    assert sa["completed"] == sb["completed"] == len(ws)
     for w, x, y in zip(ws, a, b):
         for p, q in zip(x[:4], y[:4]):
             assert p.tobytes() == q.tobytes(), w.name
