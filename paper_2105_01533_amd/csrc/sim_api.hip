@@ -440,7 +440,8 @@ int run_u2(sim_t* s, const sim_gate& g, bool* over) {
   }
   if (!check && !(s->cfg.flags & SIM_FLAG_U2_TWO_PASS) && ub <= (uint64_t)kMaxBlocks * kU2Tile) {
     // Outputs fit (2 ub <= capacity): evaluate, scan and write in one pass.
-    const int T = (int)std::max<uint64_t>(1, (ub + kU2Tile - 1) / kU2Tile);
+    const uint32_t tile = u2_tile_for(ub);
+    const int T = (int)std::max<uint64_t>(1, (ub + tile - 1) / tile);
     if (++s->u2_epoch >= (1u << 30)) {   // epochs are 30 bits: start over on cleared words
       launch_fill(s->stream, s->status, 0ull, kMaxBlocks);
       s->u2_epoch = 1;
@@ -448,7 +449,7 @@ int run_u2(sim_t* s, const sim_gate& g, bool* over) {
     {
       KTimer t_(s, KC_U2_WRITE);
       launch_u2_fused(s->stream, s->wide, s->buf[s->cur], s->buf[other], nnz_in, s->partner, d, s->ctl, s->status,
-                      s->ticket_base, s->u2_epoch, d_nnz(s, other), s->table, slots, T);
+                      s->ticket_base, s->u2_epoch, d_nnz(s, other), s->table, slots, T, tile);
     }
     HIP_TRY(hipGetLastError());
     s->ticket_base += (uint32_t)T;   // only a launched kernel advances the device counter

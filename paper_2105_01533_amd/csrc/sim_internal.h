@@ -288,12 +288,18 @@ void launch_scan(hipStream_t st, uint32_t* tot, int nblocks, uint64_t* nnz_out, 
                  uint64_t cap);
 void launch_u2_write(hipStream_t st, bool wide, Buf in, Buf out, const uint64_t* nnz, const uint32_t* partner,
                      const uint32_t* off, const U2Desc& d, Ctl* ctl, int grid, int block);
-// Entries per block of the single-pass branching kernel; it serves states of
-// at most kMaxBlocks tiles.
+// Entries per block of the single-pass branching kernel (512, 1024 or
+// 2048); it serves states of at most kMaxBlocks tiles of the largest.
 constexpr uint32_t kU2Tile = 2048;
+// The tile for a state of at most ub entries: 512 up to 2^20 entries, 1024 up
+// to kMaxBlocks such tiles, 2048 beyond.
+inline uint32_t u2_tile_for(uint64_t ub) {
+  return ub <= (1ull << 20) ? 512u : ub <= (uint64_t)kMaxBlocks * 1024u ? 1024u : kU2Tile;
+}
+// grid = tiles covering the entry count's bound.
 void launch_u2_fused(hipStream_t st, bool wide, Buf in, Buf out, const uint64_t* nnz, const uint32_t* partner,
                      const U2Desc& d, Ctl* ctl, uint64_t* status, uint32_t ticket_base, uint32_t epoch,
-                     uint64_t* nnz_out, uint64_t* table, uint64_t clear_slots, int grid);
+                     uint64_t* nnz_out, uint64_t* table, uint64_t clear_slots, int grid, uint32_t tile);
 // Largest state the one-block branching kernel takes (its partner index and
 // partner slots live in LDS).
 constexpr uint32_t kLdsU2Max = 4096;

@@ -412,7 +412,7 @@ __global__ __launch_bounds__(256) void k_u2_write(Buf in, Buf out, const uint64_
 }
 
 // Single-pass branching gate, for states whose outputs are known to fit:
-// each block evaluates one tile of kU2Tile entries once (Eq. 2 with T_eps, the
+// each block evaluates one tile of 256 ITEMS entries once (Eq. 2 with T_eps, the
 // results held in registers) and finds where its outputs go by a chained scan
 // over the tiles: it publishes its tile's output count, adds its
 // predecessors' counts back to the first published inclusive prefix,
@@ -431,13 +431,17 @@ __device__ __forceinline__ uint64_t st_word(uint32_t epoch, uint64_t flag, uint3
   return ((uint64_t)epoch << 34) | flag | v;
 }
 
-template <bool WIDE>
+// Tiles of 512, 1024 or 2048 entries (ITEMS = 2, 4, 8): the larger tiles hold
+// more registers (2048: two waves per SIMD), the smaller ones put more blocks
+// in flight, which is what states of up to a few million entries need.
+template <bool WIDE, int ITEMS>
 __global__ __launch_bounds__(256) void k_u2_fused(Buf in, Buf out, const uint64_t* __restrict__ nnz_p,
                                                   const uint32_t* __restrict__ partner, U2Desc d, Ctl* ctl,
                                                   uint64_t* status, uint32_t ticket_base, uint32_t epoch,
                                                   uint64_t* nnz_out, uint64_t* __restrict__ table,
                                                   uint64_t clear_slots) {
-  constexpr int kItems = kU2Tile / 256;
+  constexpr int kItems = ITEMS;
+  constexpr uint32_t kTile = 256u * ITEMS;
   __shared__ uint32_t s_wave[16];
   __shared__ uint32_t sh[256];
   __shared__ double2 shm[4];   // one slot per wave
@@ -455,7 +459,7 @@ __global__ __launch_bounds__(256) void k_u2_fused(Buf in, Buf out, const uint64_
     if (threadIdx.x == 0) atomicOr(&ctl->error, 2u);
     return;
   }
-  const uint64_t begin = (uint64_t)tile * kU2Tile;
+  const uint64_t begin = (uint64_t)tile * kTile;
   U2Out r[kItems];
   uint64_t lo[kItems], hi[kItems];
   uint32_t pos[kItems];
@@ -883,13 +887,20 @@ void launch_u2_write(hipStream_t st, bool wide, Buf in, Buf out, const uint64_t*
 
 void launch_u2_fused(hipStream_t st, bool wide, Buf in, Buf out, const uint64_t* nnz, const uint32_t* partner,
                      const U2Desc& d, Ctl* ctl, uint64_t* status, uint32_t ticket_base, uint32_t epoch,
-                     uint64_t* nnz_out, uint64_t* table, uint64_t clear_slots, int grid) {
-  if (wide)
-    hipLaunchKernelGGL(k_u2_fused<true>, dim3(grid), dim3(256), 0, st, in, out, nnz, partner, d, ctl, status,
-                       ticket_base, epoch, nnz_out, table, clear_slots);
-  else
-    hipLaunchKernelGGL(k_u2_fused<false>, dim3(grid), dim3(256), 0, st, in, out, nnz, partner, d, ctl, status,
-                       ticket_base, epoch, nnz_out, table, clear_slots);
+                     uint64_t* nnz_out, uint64_t* table, uint64_t clear_slots, int grid, uint32_t tile) {
+#define SPARSESIM_U2F(W, I)                                                                                    \
+  hipLaunchKernelGGL((k_u2_fused<W, I>), dim3(grid), dim3(256), 0, st, in, out, nnz, partner, d, ctl, status, \
+                     ticket_base, epoch, nnz_out, table, clear_slots)
+  if (wide) {
+    if (tile == 512) SPARSESIM_U2F(true, 2);
+    else if (tile == 1024) SPARSESIM_U2F(true, 4);
+    else SPARSESIM_U2F(true, 8);
+  } else {
+    if (tile == 512) SPARSESIM_U2F(false, 2);
+    else if (tile == 1024) SPARSESIM_U2F(false, 4);
+    else SPARSESIM_U2F(false, 8);
+  }
+#undef SPARSESIM_U2F
 }
 
 void launch_u2_lds(hipStream_t st, bool wide, Buf in, Buf out, const uint64_t* nnz, const U2Desc& d, Ctl* ctl,

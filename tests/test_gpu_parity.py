@@ -1062,3 +1062,35 @@ def test_index_counting_is_opt_in_for_the_global_index(sim):
         assert x.tobytes() == y.tobytes()
     assert sa["index_inserts"] == sa["index_lookups"] == sa["index_cas"] == sa["index_probes"] == 0
     assert sb["index_inserts"] > 0 and sb["index_lookups"] > 0
+
+
+@pytest.mark.parametrize("size", [300_001, 2_000_003, 8_388_700])
+def test_u2_single_pass_tile_sizes(sim, size):
+    """The single-pass branching kernel takes 512-, 1024- or 2048-entry tiles
+    by state size (these three sizes select one each); a controlled H and an
+    H on imported states give bitwise the two-pass form's state, in the same
+    order (the two-pass form is compared with the oracle elsewhere)."""
+    n = 100
+    k = np.arange(size, dtype=np.uint64)
+    lo = k * np.uint64(0x9E3779B97F4A7C15)            # distinct (odd multiplier)
+    rng = np.random.default_rng(size)
+    hi = rng.integers(0, 1 << 36, size, dtype=np.uint64)
+    amp = rng.uniform(-1, 1, size) + 1j * rng.uniform(-1, 1, size)
+    amp /= np.linalg.norm(amp)
+    c = W.Circuit()
+    c.h(7, ctrls=(80,))
+    c.h(70)
+    say(f"[gpu] single-pass tiles: {size} entries")
+    out = []
+    for flags in (0, sim.SIM_FLAG_U2_TWO_PASS):
+        s = sim.Simulator(n, 1 << 25, 0.0, flags=flags)
+        try:
+            s.import_state(lo, hi, amp)
+            _, _, st = s.apply_ops(c.array())
+            out.append((s.export(sort=False), st))
+        finally:
+            s.close()
+    (a, sa), (b, sb) = out
+    assert sa["u2_applied"] == sb["u2_applied"] == 2
+    for x, y in zip(a, b):
+        assert x.tobytes() == y.tobytes()
