@@ -432,6 +432,11 @@ int sim_kernel_stats_reset(sim_t* s);
  * with the partner index in LDS; this flag sends them through the global
  * index kernels like larger states (same outputs, same order). */
 #define SRV_FLAG_U2_GLOBAL_INDEX 2u
+/* Bit-sliced fused runs of states of at least 65,536 entries run on the
+ * register-plane kernel, one launch per run on the server's stream ahead of
+ * the tick's graph; this flag keeps them on the graph's LDS-plane tile (the
+ * same results, bit for bit). */
+#define SRV_FLAG_NO_RP 4u
 
 typedef struct srv_config {
   uint64_t budget_bytes; /* device bytes for request states (the pool) */
@@ -479,6 +484,7 @@ typedef struct srv_stats {
                                requests) */
   double copy_ms;           /* copying finished states to host memory, summed over the
                                host threads that did it */
+  uint64_t rp_runs;         /* of bitslice_runs: on the register-plane kernel */
 } srv_stats;
 
 typedef struct srv_t srv_t;

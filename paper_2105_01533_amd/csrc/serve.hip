@@ -207,8 +207,10 @@ struct Request {
   struct Ahead {
     bool valid = false;
     size_t b = 0, len = 0;
+    bool rp = false;                  // a register-plane program (prog), else groups (grp)
     BsRun br{};
     std::vector<BsGroup> grp;
+    std::vector<RpRec> prog;
   } ahead;
   bool large = false;                 // runs on the large-state lane
   int lane_rc = SIM_OK;               // the lane's result code
@@ -239,6 +241,7 @@ struct srv_t {
   bool own_pool = false;
   Pool pool;
   SlotCtl* d_ctl = nullptr;
+  Ctl* d_rpctl = nullptr;             // counters of the register-plane launches (not reported)
   SlotCtl* h_ctl = nullptr;
   std::vector<int> free_slots;
   // tick buffer (same layout host/device): header | items | units | ops arena
@@ -300,12 +303,28 @@ int capture_tick(srv_t* s) {
 // the tick, so a request's runs -- and with them its rounding -- are the same
 // alone and in any mix.  A MONO op compiles to at most three bit-sliced ops;
 // the rewrite of uncontrolled X gates at most doubles them and adds one per
-// qubit; a group holds at least one op.
+// qubit; a group holds at least one op; a register-plane program has at most
+// rp_records_bound records.
 uint64_t arena_run_cap(const srv_t* s, const Request& r) {
   const uint64_t groups = s->cfg.arena_bytes / sizeof(BsGroup);
   const uint64_t by_groups = groups > r.cfg.n_qubits ? (groups - r.cfg.n_qubits) / (2 * 3) : 1;
   const uint64_t by_desc = s->cfg.arena_bytes / sizeof(MonoDesc);
-  return std::max<uint64_t>(1, std::min(by_groups, by_desc));
+  // A register-plane program of L ops has at most rp_records_bound(3 L, nq)
+  // records: 8 (6 L + nq) + 16.
+  const uint64_t recs = s->cfg.arena_bytes / sizeof(RpRec);
+  const uint64_t fixed = 8ull * r.cfg.n_qubits + 16;
+  const uint64_t by_prog = recs > fixed ? (recs - fixed) / 48 : 1;
+  return std::max<uint64_t>(1, std::min({by_groups, by_desc, by_prog}));
+}
+
+// Bit-sliced fused runs of states of at least this many entries take the
+// register-plane kernel, one launch per run on the server's stream ahead of
+// the tick's graph (two waves per SIMD on 2048-entry tiles, about twice the
+// LDS-plane tile's speed on large states; the two give the same bits).
+constexpr uint64_t kRpMinEntries = 1ull << 16;
+
+bool use_rp(const srv_t* s, uint64_t nnz) {
+  return !(s->cfg.flags & SRV_FLAG_NO_RP) && nnz >= kRpMinEntries;
 }
 
 // Position in a request's op list.
@@ -536,7 +555,8 @@ void bg_main(srv_t* s) {
         compile_request(r);
         break;
       case BG_GROUP:
-        r.rc.group(r.ahead.b, r.ahead.len, r.ahead.grp, &r.ahead.br);
+        if (r.ahead.rp) r.rc.schedule(r.ahead.b, r.ahead.len, r.ahead.prog, &r.ahead.br);
+        else r.rc.group(r.ahead.b, r.ahead.len, r.ahead.grp, &r.ahead.br);
         r.ahead.valid = true;
         break;
       case BG_COPY: {
@@ -647,7 +667,8 @@ int srv_create(const srv_config* cfg, void* stream, void* pool, size_t pool_byte
   if (cfg->grid > 65536) return sfail(SIM_E_ARG, "grid must be 0 (default 2048) or 1..65536");
   if (cfg->lane_workers > 64) return sfail(SIM_E_ARG, "lane_workers must be 0 (default 8) or 1..64");
   if (cfg->reserved) return sfail(SIM_E_ARG, "reserved must be 0");
-  if (cfg->flags & ~(SRV_FLAG_NO_GRAPH | SRV_FLAG_U2_GLOBAL_INDEX)) return sfail(SIM_E_ARG, "unknown flags");
+  if (cfg->flags & ~(SRV_FLAG_NO_GRAPH | SRV_FLAG_U2_GLOBAL_INDEX | SRV_FLAG_NO_RP))
+    return sfail(SIM_E_ARG, "unknown flags");
   std::unique_ptr<srv_t> s(new srv_t());
   s->cfg = *cfg;
   if (!s->cfg.arena_bytes) s->cfg.arena_bytes = 64ull << 20;
@@ -670,6 +691,12 @@ int srv_create(const srv_config* cfg, void* stream, void* pool, size_t pool_byte
   s->pool.init(cfg->budget_bytes / kA * kA);
   const size_t ns = cfg->max_slots;
   SRV_HIP(hipMalloc(&s->d_ctl, ns * sizeof(SlotCtl)));
+  SRV_HIP(mono_rp_init());
+  SRV_HIP(hipMalloc(&s->d_rpctl, sizeof(Ctl)));
+  {
+    const Ctl zero{};
+    SRV_HIP(hipMemcpy(s->d_rpctl, &zero, sizeof(Ctl), hipMemcpyHostToDevice));
+  }
   SRV_HIP(hipHostMalloc(&s->h_ctl, ns * sizeof(SlotCtl)));
   for (int k = (int)ns - 1; k >= 0; --k) s->free_slots.push_back(k);
   s->items_off = al(sizeof(BTick));
@@ -721,6 +748,7 @@ int srv_destroy(srv_t* s) {
   if (s->d_tick) (void)hipFree(s->d_tick);
   if (s->h_tick) (void)hipHostFree(s->h_tick);
   if (s->d_ctl) (void)hipFree(s->d_ctl);
+  if (s->d_rpctl) (void)hipFree(s->d_rpctl);
   if (s->h_ctl) (void)hipHostFree(s->h_ctl);
   if (s->own_pool && s->pool_mem) (void)hipFree(s->pool_mem);
   if (s->own_stream && s->stream) (void)hipStreamDestroy(s->stream);
@@ -800,8 +828,10 @@ void group_ahead(srv_t* s, const std::vector<Request*>& mono, const std::vector<
     r->ahead.valid = false;
     r->ahead.b = b;
     r->ahead.len = len;
+    r->ahead.rp = use_rp(s, nnz);
     r->ahead.br = br;
     r->ahead.grp.clear();
+    r->ahead.prog.clear();
     bg_push(s, r, BG_GROUP);
   };
   for (Request* r : mono) plan(r, r->nnz);
@@ -861,9 +891,19 @@ int srv_tick(srv_t* s, uint32_t* running, uint32_t* queued) {
     SegKind k;
     size_t b = 0, len = 0, op = 0;
     bool bsl = false;
+    bool rp = false;     // bit-sliced run on the register-plane kernel (prog), else groups
     BsRun br{};
     std::vector<BsGroup> grp;
+    std::vector<RpRec> prog;
   };
+  // Register-plane runs of this tick: (request, arena offset, records, run).
+  struct RpItem {
+    Request* r;
+    size_t off;
+    uint32_t nrec;
+    BsRun br;
+  };
+  std::vector<RpItem> rp_items;
   std::vector<Seg> segs;
   segs.reserve(s->running.size());
   std::vector<size_t> to_group;
@@ -886,10 +926,12 @@ int srv_tick(srv_t* s, uint32_t* running, uint32_t* queued) {
     if (sg.k == SEG_MONO) {
       sg.bsl = r->rc.run_params(sg.b, sg.len, r->cfg.mono_mode, r->cfg.bs_min_gates, &sg.br);
       if (sg.bsl) {
-        // group() depends only on the run, so a grouping made ahead for the
-        // same run is the one it would make now.
-        if (r->ahead.valid && r->ahead.b == sg.b && r->ahead.len == sg.len) {
+        sg.rp = use_rp(s, r->nnz);
+        // group() and schedule() depend only on the run, so a grouping or
+        // program made ahead for the same run is the one they would make now.
+        if (r->ahead.valid && r->ahead.b == sg.b && r->ahead.len == sg.len && r->ahead.rp == sg.rp) {
           sg.grp = std::move(r->ahead.grp);
+          sg.prog = std::move(r->ahead.prog);
           sg.br = r->ahead.br;
           s->stats.ahead_hits++;
         } else {
@@ -899,13 +941,15 @@ int srv_tick(srv_t* s, uint32_t* running, uint32_t* queued) {
     }
     r->ahead.valid = false;
     r->ahead.grp.clear();
+    r->ahead.prog.clear();
     segs.push_back(std::move(sg));
   }
   {
     const auto t_g = std::chrono::steady_clock::now();
     HostPool::get().run(to_group.size(), [&](size_t t) {
       Seg& sg = segs[to_group[t]];
-      sg.r->rc.group(sg.b, sg.len, sg.grp, &sg.br);
+      if (sg.rp) sg.r->rc.schedule(sg.b, sg.len, sg.prog, &sg.br);
+      else sg.r->rc.group(sg.b, sg.len, sg.grp, &sg.br);
     });
     s->stats.group_ms += ms_since(t_g);
   }
@@ -933,7 +977,9 @@ int srv_tick(srv_t* s, uint32_t* running, uint32_t* queued) {
       // The run's ops go into the tick's arena.  A run that does not fit what
       // is left is deferred whole to the next tick (never cut: that would
       // change its rounding); every run fits an empty arena (arena_run_cap).
-      const size_t bytes = bsl ? sg.grp.size() * sizeof(BsGroup) : len * sizeof(MonoDesc);
+      const size_t bytes = !bsl ? len * sizeof(MonoDesc)
+                           : sg.rp ? sg.prog.size() * sizeof(RpRec)
+                                   : sg.grp.size() * sizeof(BsGroup);
       r->deferred = arena_used + al(bytes) > s->cfg.arena_bytes;
       if (r->deferred) {
         // Give back the run's ops: they are re-read next tick (skip decisions
@@ -948,9 +994,24 @@ int srv_tick(srv_t* s, uint32_t* running, uint32_t* queued) {
           r->ahead.valid = true;
           r->ahead.b = b;
           r->ahead.len = len;
+          r->ahead.rp = sg.rp;
           r->ahead.br = sg.br;
           r->ahead.grp = std::move(sg.grp);
+          r->ahead.prog = std::move(sg.prog);
         }
+        continue;
+      }
+      if (bsl && sg.rp) {
+        // Its own launch ahead of the graph; the request has no item in it.
+        std::memcpy(arena + arena_used, sg.prog.data(), bytes);
+        rp_items.push_back(RpItem{r, arena_used, (uint32_t)sg.prog.size(), sg.br});
+        arena_used += al(bytes);
+        r->st.updates += r->nnz * len;
+        r->st.mono_passes++;
+        r->st.bitslice_passes++;
+        s->stats.bitslice_runs++;
+        s->stats.rp_runs++;
+        mono.push_back(r);
         continue;
       }
       if (bsl) {
@@ -1004,7 +1065,8 @@ int srv_tick(srv_t* s, uint32_t* running, uint32_t* queued) {
   }
   const uint32_t nm = (uint32_t)mono_items.size(), nu = (uint32_t)u2_items.size(), nq = (uint32_t)meas_items.size();
   const uint32_t ns = (uint32_t)u2s_items.size();
-  if (nm + nu + nq + ns) {
+  const uint32_t nrp = (uint32_t)rp_items.size();
+  if (nm + nu + nq + ns + nrp) {
     std::memset(hdr, 0, sizeof(BTick));
     hdr->n_mono = nm;
     hdr->n_u2 = nu;
@@ -1043,7 +1105,18 @@ int srv_tick(srv_t* s, uint32_t* running, uint32_t* queued) {
     SRV_HIP(hipMemcpyAsync(s->d_tick + s->units_off, units, w * sizeof(uint32_t), hipMemcpyHostToDevice, s->stream));
     if (arena_used)
       SRV_HIP(hipMemcpyAsync(s->d_tick + s->arena_off, arena, arena_used, hipMemcpyHostToDevice, s->stream));
-    if (s->exec) {
+    // Register-plane runs first, on the same stream: each finishes before the
+    // graph's kernels start, and no two run at once.
+    for (const RpItem& x : rp_items) {
+      Request* r = x.r;
+      const int grid = (int)std::max<uint64_t>(1, (r->nnz + 2047) / 2048);
+      launch_mono_rp(s->stream, r->buf[r->cur], &s->d_ctl[r->slot].nnz[r->cur],
+                     reinterpret_cast<const RpRec*>(s->d_tick + s->arena_off + x.off), x.nrec, x.br, s->d_rpctl, grid);
+      SRV_HIP(hipGetLastError());
+    }
+    if (nm + nu + nq + ns == 0) {
+      // only register-plane runs this tick
+    } else if (s->exec) {
       SRV_HIP(hipGraphLaunch(s->exec, s->stream));
     } else {
       launch_batch_tick(s->stream, reinterpret_cast<const BTick*>(s->d_tick),
@@ -1067,7 +1140,7 @@ int srv_tick(srv_t* s, uint32_t* running, uint32_t* queued) {
       s->stats.wait_ms += ms_since(t_w);
     }
     s->stats.ticks++;
-    s->stats.items += nm + nu + nq + ns;
+    s->stats.items += nm + nu + nq + ns + nrp;
     // Fold the results back.
     std::vector<std::pair<Request*, int>> failed;
     for (Request* r : u2) {
@@ -1101,7 +1174,7 @@ int srv_tick(srv_t* s, uint32_t* running, uint32_t* queued) {
   }
   rc = fold_copies(s);
   if (rc) return rc;
-  if (nm + nu + nq + ns == 0 && (waiting || !s->copying.empty())) {
+  if (nm + nu + nq + ns + nrp == 0 && (waiting || !s->copying.empty())) {
     // Nothing launched: wait (briefly) for the background work instead of spinning.
     const auto t_w = std::chrono::steady_clock::now();
     bg_wait_any(s, 200);

@@ -290,3 +290,26 @@ def test_small_states_lds_index_equals_global_index(S):
         res, _ = run_server(S, [w, ws[0]], flags=flags)
         o, oout, _ = oracle_run(w)
         assert_same_state(res[0][:3], o.export(), what=f"h14 flags={flags}")
+
+
+def test_large_states_register_plane_runs(S):
+    """Fused runs of batched states of at least 2^16 entries take the
+    register-plane kernel (one launch per run ahead of the tick's graph); the
+    results are bit for bit those of the LDS-plane tile (SRV_FLAG_NO_RP), alone
+    and in a mix with small states, and match the oracle."""
+    ws = [W.config2(61, n=100, h_qubits=17, gates=3000, round_gates=1500, meas_per_round=2),
+          W.config1(62, w=16, adds=2, n=40), mix()[0], mix()[6]]
+    a, sa = run_server(S, ws)
+    b, sb = run_server(S, ws, flags=S.SRV_FLAG_NO_RP)
+    assert sa["rp_runs"] > 0 and sb["rp_runs"] == 0
+    for w, x, y in zip(ws, a, b):
+        for p, q in zip(x[:4], y[:4]):
+            assert p.tobytes() == q.tobytes(), w.name
+    alone, _ = run_server(S, [ws[0]])
+    for p, q in zip(alone[0][:4], a[0][:4]):
+        assert p.tobytes() == q.tobytes()
+    for w, res in zip(ws[:2], a[:2]):
+        say(f"[gpu] oracle {w.name}")
+        o, oout, _ = oracle_run(w)
+        assert list(res[3]) == list(oout), w.name
+        assert_same_state(res[:3], o.export(), what=w.name)
