@@ -523,20 +523,27 @@ __global__ __launch_bounds__(256) void kb_m_write(const BTick* __restrict__ hdr,
 
 }  // namespace
 
-// The whole tick, in order, on fixed grids (capturable).
-void launch_batch_tick(hipStream_t st, const BTick* hdr, const BItem* items, const uint32_t* units, int grid) {
+// A tick's kernels, in order, on fixed grids (capturable); families with no
+// items this tick can be left out.
+void launch_batch_tick(hipStream_t st, const BTick* hdr, const BItem* items, const uint32_t* units, int grid,
+                       uint32_t families) {
   const size_t lds = (size_t)kMaxPlanes * 64 * 4;
-  hipLaunchKernelGGL(kb_mono, dim3(grid), dim3(64), lds, st, hdr, items, units);
-  hipLaunchKernelGGL(kb_fill, dim3(grid), dim3(256), 0, st, hdr, items, units);
-  hipLaunchKernelGGL(kb_build, dim3(grid), dim3(256), 0, st, hdr, items, units);
-  hipLaunchKernelGGL(kb_u2_probe, dim3(grid), dim3(256), 0, st, hdr, items, units);
-  hipLaunchKernelGGL(kb_u2_count, dim3(grid), dim3(256), 0, st, hdr, items, units);
-  hipLaunchKernelGGL(kb_u2_scan, dim3(grid), dim3(256), 0, st, hdr, items, units);
-  hipLaunchKernelGGL(kb_u2_write, dim3(grid), dim3(256), 0, st, hdr, items, units);
-  hipLaunchKernelGGL(kb_u2_lds, dim3(grid < 256 ? grid : 256), dim3(lds::kThreads), 0, st, hdr, items);
-  hipLaunchKernelGGL(kb_m_reduce, dim3(grid), dim3(256), 0, st, hdr, items, units);
-  hipLaunchKernelGGL(kb_m_decide, dim3(grid), dim3(256), 0, st, hdr, items, units);
-  hipLaunchKernelGGL(kb_m_write, dim3(grid), dim3(256), 0, st, hdr, items, units);
+  if (families & kFamMono) hipLaunchKernelGGL(kb_mono, dim3(grid), dim3(64), lds, st, hdr, items, units);
+  if (families & kFamU2) {
+    hipLaunchKernelGGL(kb_fill, dim3(grid), dim3(256), 0, st, hdr, items, units);
+    hipLaunchKernelGGL(kb_build, dim3(grid), dim3(256), 0, st, hdr, items, units);
+    hipLaunchKernelGGL(kb_u2_probe, dim3(grid), dim3(256), 0, st, hdr, items, units);
+    hipLaunchKernelGGL(kb_u2_count, dim3(grid), dim3(256), 0, st, hdr, items, units);
+    hipLaunchKernelGGL(kb_u2_scan, dim3(grid), dim3(256), 0, st, hdr, items, units);
+    hipLaunchKernelGGL(kb_u2_write, dim3(grid), dim3(256), 0, st, hdr, items, units);
+  }
+  if (families & kFamU2s)
+    hipLaunchKernelGGL(kb_u2_lds, dim3(grid < 256 ? grid : 256), dim3(lds::kThreads), 0, st, hdr, items);
+  if (families & kFamMeas) {
+    hipLaunchKernelGGL(kb_m_reduce, dim3(grid), dim3(256), 0, st, hdr, items, units);
+    hipLaunchKernelGGL(kb_m_decide, dim3(grid), dim3(256), 0, st, hdr, items, units);
+    hipLaunchKernelGGL(kb_m_write, dim3(grid), dim3(256), 0, st, hdr, items, units);
+  }
 }
 
 }  // namespace sparsesim

@@ -248,8 +248,10 @@ struct srv_t {
   char* d_tick = nullptr;
   char* h_tick = nullptr;
   size_t items_off = 0, units_off = 0, arena_off = 0, tick_bytes = 0;
-  hipGraph_t graph = nullptr;
-  hipGraphExec_t exec = nullptr;
+  // One captured graph per non-empty set of kernel families (index = family
+  // mask), so a tick replays only the kernels it has items for.
+  hipGraph_t graph[16] = {};
+  hipGraphExec_t exec[16] = {};
   int grid = 2048;
   uint64_t next_id = 1;
   std::unordered_map<uint64_t, std::unique_ptr<Request>> reqs;
@@ -289,12 +291,14 @@ int capture_tick(srv_t* s) {
   const auto* items = reinterpret_cast<const BItem*>(s->d_tick + s->items_off);
   const auto* units = reinterpret_cast<const uint32_t*>(s->d_tick + s->units_off);
   if (s->cfg.flags & SRV_FLAG_NO_GRAPH) return SIM_OK;
-  SRV_HIP(hipStreamBeginCapture(s->stream, hipStreamCaptureModeThreadLocal));
-  launch_batch_tick(s->stream, hdr, items, units, s->grid);
-  hipGraph_t g = nullptr;
-  SRV_HIP(hipStreamEndCapture(s->stream, &g));
-  s->graph = g;
-  SRV_HIP(hipGraphInstantiate(&s->exec, s->graph, nullptr, nullptr, 0));
+  for (uint32_t m = 1; m <= kFamAll; ++m) {
+    SRV_HIP(hipStreamBeginCapture(s->stream, hipStreamCaptureModeThreadLocal));
+    launch_batch_tick(s->stream, hdr, items, units, s->grid, m);
+    hipGraph_t g = nullptr;
+    SRV_HIP(hipStreamEndCapture(s->stream, &g));
+    s->graph[m] = g;
+    SRV_HIP(hipGraphInstantiate(&s->exec[m], s->graph[m], nullptr, nullptr, 0));
+  }
   return SIM_OK;
 }
 
@@ -743,8 +747,10 @@ int srv_destroy(srv_t* s) {
   }
   for (hipStream_t st : s->lane_streams) (void)hipStreamDestroy(st);
   (void)hipStreamSynchronize(s->stream);
-  if (s->exec) (void)hipGraphExecDestroy(s->exec);
-  if (s->graph) (void)hipGraphDestroy(s->graph);
+  for (int m = 0; m < 16; ++m) {
+    if (s->exec[m]) (void)hipGraphExecDestroy(s->exec[m]);
+    if (s->graph[m]) (void)hipGraphDestroy(s->graph[m]);
+  }
   if (s->d_tick) (void)hipFree(s->d_tick);
   if (s->h_tick) (void)hipHostFree(s->h_tick);
   if (s->d_ctl) (void)hipFree(s->d_ctl);
@@ -1114,14 +1120,16 @@ int srv_tick(srv_t* s, uint32_t* running, uint32_t* queued) {
                      reinterpret_cast<const RpRec*>(s->d_tick + s->arena_off + x.off), x.nrec, x.br, s->d_rpctl, grid);
       SRV_HIP(hipGetLastError());
     }
-    if (nm + nu + nq + ns == 0) {
+    // Only the kernel families that have items this tick.
+    const uint32_t fam = (nm ? kFamMono : 0u) | (nu ? kFamU2 : 0u) | (ns ? kFamU2s : 0u) | (nq ? kFamMeas : 0u);
+    if (fam == 0) {
       // only register-plane runs this tick
-    } else if (s->exec) {
-      SRV_HIP(hipGraphLaunch(s->exec, s->stream));
+    } else if (s->exec[fam]) {
+      SRV_HIP(hipGraphLaunch(s->exec[fam], s->stream));
     } else {
       launch_batch_tick(s->stream, reinterpret_cast<const BTick*>(s->d_tick),
                         reinterpret_cast<const BItem*>(s->d_tick + s->items_off),
-                        reinterpret_cast<const uint32_t*>(s->d_tick + s->units_off), s->grid);
+                        reinterpret_cast<const uint32_t*>(s->d_tick + s->units_off), s->grid, fam);
       SRV_HIP(hipGetLastError());
     }
     int max_slot = -1;

@@ -249,7 +249,12 @@ struct BTick {
   uint32_t pad2[3];
 };
 
-void launch_batch_tick(hipStream_t st, const BTick* hdr, const BItem* items, const uint32_t* units, int grid);
+// Kernel families of a tick: fused runs; branching gates on the global index;
+// branching gates of small states (LDS index); measurements.
+constexpr uint32_t kFamMono = 1, kFamU2 = 2, kFamU2s = 4, kFamMeas = 8, kFamAll = 15;
+// The kernels of the families in `families`, in tick order.
+void launch_batch_tick(hipStream_t st, const BTick* hdr, const BItem* items, const uint32_t* units, int grid,
+                       uint32_t families);
 
 
 // ---- launchers (sim_kernels.hip) -------------------------------------------
