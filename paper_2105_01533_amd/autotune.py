@@ -8,10 +8,13 @@ or LDS planes, is fixed at creation and not searched.)  None of them changes whi
 survive; they change speed and, between fused-pass kernels, floating-point
 rounding only.
 
-Server knobs: the capacity from which a request takes the large-state lane
-(lane_capacity) and the lane's worker count (lane_workers), tuned for the p99
-latency of a reduced serving trace replayed at 0.8x the one-at-a-time rate
-(the tick grid and per-tick cap stay at their defaults).
+Server knobs: the batched tick's grid (blocks per kernel, grid) and its
+per-request update cap (tick_updates: a fused run is cut so that it makes at
+most that many gate-entry updates in one tick; 0 = no cap), tuned for the p99
+latency of a reduced serving trace replayed at 0.8x the one-at-a-time rate.
+(The large-state lane stays off and is not searched.)  The grid changes speed
+only; a per-tick cap also changes where a request's runs are cut, and with
+that its floating-point rounding, never its labels.
 
 For each bucket (label width: <= 64 qubits or more; state size: log2 of the
 capacity) a representative random circuit of that size is timed on one live
@@ -45,12 +48,11 @@ DEFAULTS = {"fuse_max": 65536, "bs_min_gates": 16, "mono_mode": 0, "flags": 0, "
 KNOBS = tuple(DEFAULTS)
 
 SERVER_SPACE = {
-    "lane_capacity": [1 << 10, 1 << 12, 1 << 14, 1 << 16],
-    "lane_workers": [4, 8],
+    "grid": [512, 1024, 2048, 4096],
+    "tick_updates": [0, 1 << 30, 1 << 32],
 }
-# The lane is off by default (lane_capacity 0): server runs with it ended in
-# intermittent GPU memory faults whose cause is not known, so it is neither
-# used nor tuned by default.
+# The lane is off (lane_capacity 0): server runs with it ended in intermittent
+# GPU memory faults whose cause is not known, so it is neither used nor tuned.
 SERVER_DEFAULTS = {"lane_capacity": 0, "lane_workers": 8, "grid": 2048, "tick_updates": 0}
 
 
@@ -167,8 +169,7 @@ def tune_server(requests: int = 128, max_log2: int = 22, max_gates: int = 100_00
     serving trace (seed 7: config-0..2 families, caps 2^8..2^max_log2,
     1e3..max_gates gates) replayed open loop at 0.8x the one-at-a-time service
     rate (measured first, closed loop, on the same requests), with the default
-    per-state knobs.  (The tick grid and the per-tick cap are not searched:
-    they stay at their defaults.)"""
+    per-state knobs."""
     from . import serving, workloads as W
 
     trace = W.serving_trace(7, requests=requests, rate=1.0, cap_log2=(8, max_log2), gates_range=(1000, max_gates))
@@ -222,6 +223,15 @@ if __name__ == "__main__":
     ap.add_argument("--gates", type=int, default=20_000)
     ap.add_argument("--repeats", type=int, default=3)
     ap.add_argument("--server", action="store_true",
-                    help="also tune the server's lane knobs (runs the large-state lane; see SERVER_DEFAULTS)")
+                    help="also tune the server's tick grid and per-tick update cap (p99 of a reduced trace)")
+    ap.add_argument("--server-only", action="store_true",
+                    help="keep the table's per-state buckets (read from --table) and tune only the server")
+    ap.add_argument("--table", default=DEFAULT_CACHE, help="table read by --server-only")
     args = ap.parse_args()
-    tune(gates=args.gates, repeats=args.repeats, cache=args.out, server=args.server)
+    if args.server_only:
+        t = load(args.table)
+        t["server"] = tune_server()
+        with open(args.out, "w") as f:
+            json.dump(t, f, indent=1, sort_keys=True)
+    else:
+        tune(gates=args.gates, repeats=args.repeats, cache=args.out, server=args.server)

@@ -63,7 +63,8 @@ def test_state_and_server_knobs_follow_table_and_overrides(monkeypatch):
     sk = A.server_knobs({"grid": 512})
     assert sk["grid"] == 512 and set(sk) == set(A.SERVER_DEFAULTS)
     if "server" in t:
-        assert sk["lane_capacity"] == t["server"]["knobs"]["lane_capacity"]
+        assert sk["tick_updates"] == t["server"]["knobs"]["tick_updates"]
+        assert sk["lane_capacity"] == 0   # the lane is never switched on by the table
     monkeypatch.setenv("SPARSESIM_TUNING", "off")
     assert A.state_knobs(100, 1 << 20, {}) == A.DEFAULTS
     assert A.server_knobs() == A.SERVER_DEFAULTS
