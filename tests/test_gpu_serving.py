@@ -313,3 +313,21 @@ def test_large_states_register_plane_runs(S):
         o, oout, _ = oracle_run(w)
         assert list(res[3]) == list(oout), w.name
         assert_same_state(res[:3], o.export(), what=w.name)
+
+
+def test_destroy_with_work_in_flight(S):
+    """A server closed while requests are queued, compiling, running and
+    being copied out shuts its background workers down cleanly; a new server
+    afterwards still gives the oracle's results."""
+    ws = mix()
+    for rounds in (0, 1, 3):
+        srv = S.Server(1 << 30, max_slots=4, lane_capacity=S.SRV_LANE_OFF)
+        ids = [srv.submit_workload(w) for w in ws]
+        for _ in range(rounds):
+            srv.tick()
+        srv.close()
+    res, _ = run_server(S, ws[:2])
+    for w, r in zip(ws[:2], res):
+        o, oout, _ = oracle_run(w)
+        assert list(r[3]) == list(oout), w.name
+        assert_same_state(r[:3], o.export(), what=w.name)
