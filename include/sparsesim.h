@@ -186,6 +186,16 @@ typedef struct sim_config {
  * one-block LDS-index kernel always counts (four adds per gate). */
 #define SIM_FLAG_COUNT_INDEX 8u
 
+/* The library tracks which qubits are the same in every entry (all, after
+ * sim_set_basis; those the imported labels agree on after sim_import_state;
+ * a flip keeps its target so only if its controls are; a branching gate takes
+ * its partner-mask qubits out; a measurement puts its qubit back).  A
+ * branching gate whose partner mask meets that set has no partners, so it
+ * runs without building or probing an index.  This flag turns that off (the
+ * results are the same).  The state must not be changed through the pointers
+ * of sim_device_state. */
+#define SIM_FLAG_NO_UNIFORM 16u
+
 /* Fused phase/permutation pass variants.  DIRECT evaluates every gate on every
  * entry with sequential complex products (results bit-identical to a plain
  * sequential evaluation).  BITSLICE transposes 2048-entry tiles into bit-planes
@@ -219,6 +229,8 @@ typedef struct sim_stats {
    * which threads insert, so they vary from run to run; the batched server
    * does not count them (0). */
   uint64_t index_inserts, index_cas, index_lookups, index_probes;
+  uint64_t u2_split;        /* of u2_applied: gates known to have no partners, run without the global
+                               index (see SIM_FLAG_NO_UNIFORM) */
 } sim_stats;
 
 typedef struct sim_t sim_t;
@@ -343,7 +355,8 @@ int sim_export_state(sim_t* s, sim_key* keys, sim_c64* amps, uint64_t cap, uint6
 int sim_export_state_soa(sim_t* s, uint64_t* key_lo, uint64_t* key_hi, sim_c64* amps, uint64_t cap, uint64_t* nnz);
 
 /* Device addresses of the current state buffers (key_lo, key_hi, amp) and
- * the device nnz word, for zero-copy inspection; valid until the next call. */
+ * the device nnz word, for zero-copy inspection (read only); valid until the
+ * next call. */
 int sim_device_state(sim_t* s, uint64_t** key_lo, uint64_t** key_hi, double** amp, uint64_t** d_nnz);
 
 /* Per-kernel-class counters, cumulative since creation or the last reset.

@@ -80,7 +80,8 @@ bool config_ok(const sim_config* c, std::string* why) {
     return *why = "load_factor must be in (0, 0.9]", false;
   if (c->block != 0 && c->block != 64 && c->block != 128 && c->block != 256)
     return *why = "block must be 64, 128 or 256", false;
-  if (c->flags & ~(SIM_FLAG_U2_TWO_PASS | SIM_FLAG_BS_LDS | SIM_FLAG_U2_GLOBAL_INDEX | SIM_FLAG_COUNT_INDEX))
+  if (c->flags & ~(SIM_FLAG_U2_TWO_PASS | SIM_FLAG_BS_LDS | SIM_FLAG_U2_GLOBAL_INDEX | SIM_FLAG_COUNT_INDEX |
+                   SIM_FLAG_NO_UNIFORM))
     return *why = "unknown flags", false;
   if (c->mono_mode > SIM_MONO_BITSLICE) return *why = "unknown mono_mode", false;
   return true;
@@ -224,6 +225,11 @@ static const char* const kClassNames[KC_COUNT] = {"mono_pass", "index_fill", "in
 
 struct sim_t {
   sim_config cfg;
+  // Qubits whose bit is the same in every entry (host-side, exact for the
+  // states it is set from and kept conservatively: a bit leaves the set on any
+  // gate that could make it differ between entries).  A branching gate whose
+  // partner mask meets the set has no partners (run_u2's split).
+  uint64_t uni_lo = ~0ull, uni_hi = ~0ull;
   // profiling
   uint32_t profile = 0;          // bit c: kernel class c is timed with events
   bool no_alloc = false;         // inside sim_apply_gates_static: no events, threads or allocations
@@ -389,7 +395,10 @@ int bs_grid(const sim_t* s, uint64_t n) {
 }
 
 // Branching op: index, count, scan, (capacity check), write, swap.
-int run_u2(sim_t* s, const sim_gate& g, bool* over) {
+// split: the gate's partner mask touches a qubit that is the same in every
+// entry, so no entry has a partner: no index is filled, built or probed, and
+// the evaluation runs with no partner array.
+int run_u2(sim_t* s, const sim_gate& g, bool* over, bool split) {
   *over = false;
   const uint64_t cap = s->cfg.capacity;
   uint64_t ub = s->nnz_known ? s->nnz_exact : s->nnz_ub;
@@ -421,22 +430,25 @@ int run_u2(sim_t* s, const sim_gate& g, bool* over) {
     return SIM_OK;
   }
   const uint64_t prior = s->table_dirty;
-  if (const uint64_t dirty = std::min<uint64_t>(prior, slots)) {
-    KTimer t_(s, KC_FILL);
-    launch_fill(s->stream, s->table, kEmptySlot, dirty);
-  }
-  s->table_dirty = std::max<uint64_t>(prior, slots);   // the build below writes into [0, slots)
-  {
-    KTimer t_(s, KC_BUILD);
-    launch_index_build(s->stream, s->wide, s->buf[s->cur], nnz_in, s->table, slots - 1, d, s->partner,
-                       (s->cfg.flags & SIM_FLAG_COUNT_INDEX) ? s->ctl : nullptr,
-                       flat_grid(ub), 256);
-  }
-  {
-    KTimer t_(s, KC_U2_PROBE);
-    launch_u2_probe(s->stream, s->wide, s->buf[s->cur], nnz_in, s->table, slots - 1, d, s->partner,
-                    (s->cfg.flags & SIM_FLAG_COUNT_INDEX) ? s->ctl : nullptr, flat_grid(ub),
-                    256);
+  const uint32_t* partner = split ? nullptr : s->partner;
+  if (!split) {
+    if (const uint64_t dirty = std::min<uint64_t>(prior, slots)) {
+      KTimer t_(s, KC_FILL);
+      launch_fill(s->stream, s->table, kEmptySlot, dirty);
+    }
+    s->table_dirty = std::max<uint64_t>(prior, slots);   // the build below writes into [0, slots)
+    {
+      KTimer t_(s, KC_BUILD);
+      launch_index_build(s->stream, s->wide, s->buf[s->cur], nnz_in, s->table, slots - 1, d, s->partner,
+                         (s->cfg.flags & SIM_FLAG_COUNT_INDEX) ? s->ctl : nullptr,
+                         flat_grid(ub), 256);
+    }
+    {
+      KTimer t_(s, KC_U2_PROBE);
+      launch_u2_probe(s->stream, s->wide, s->buf[s->cur], nnz_in, s->table, slots - 1, d, s->partner,
+                      (s->cfg.flags & SIM_FLAG_COUNT_INDEX) ? s->ctl : nullptr, flat_grid(ub),
+                      256);
+    }
   }
   if (!check && !(s->cfg.flags & SIM_FLAG_U2_TWO_PASS) && ub <= (uint64_t)kMaxBlocks * kU2Tile) {
     // Outputs fit (2 ub <= capacity): evaluate, scan and write in one pass.
@@ -448,12 +460,12 @@ int run_u2(sim_t* s, const sim_gate& g, bool* over) {
     }
     {
       KTimer t_(s, KC_U2_WRITE);
-      launch_u2_fused(s->stream, s->wide, s->buf[s->cur], s->buf[other], nnz_in, s->partner, d, s->ctl, s->status,
-                      s->ticket_base, s->u2_epoch, d_nnz(s, other), s->table, slots, T, tile);
+      launch_u2_fused(s->stream, s->wide, s->buf[s->cur], s->buf[other], nnz_in, partner, d, s->ctl, s->status,
+                      s->ticket_base, s->u2_epoch, d_nnz(s, other), s->table, split ? 0 : slots, T, tile);
     }
     HIP_TRY(hipGetLastError());
     s->ticket_base += (uint32_t)T;   // only a launched kernel advances the device counter
-    s->table_dirty = prior > slots ? prior : 0;   // [0, slots) emptied by the kernel
+    if (!split) s->table_dirty = prior > slots ? prior : 0;   // [0, slots) emptied by the kernel
     s->cur = other;
     s->nnz_known = false;
     s->nnz_ub = std::min<uint64_t>(2 * ub, cap);
@@ -461,7 +473,7 @@ int run_u2(sim_t* s, const sim_gate& g, bool* over) {
   }
   {
     KTimer t_(s, KC_U2_COUNT);
-    launch_u2_count(s->stream, s->wide, s->buf[s->cur], nnz_in, d, s->partner, s->bs.tot, s->ctl, G, 256);
+    launch_u2_count(s->stream, s->wide, s->buf[s->cur], nnz_in, d, partner, s->bs.tot, s->ctl, G, 256);
   }
   {
     KTimer t_(s, KC_SCAN);
@@ -478,7 +490,7 @@ int run_u2(sim_t* s, const sim_gate& g, bool* over) {
   }
   {
     KTimer t_(s, KC_U2_WRITE);
-    launch_u2_write(s->stream, s->wide, s->buf[s->cur], s->buf[other], nnz_in, s->partner, s->bs.tot, d, s->ctl, G, 256);
+    launch_u2_write(s->stream, s->wide, s->buf[s->cur], s->buf[other], nnz_in, partner, s->bs.tot, d, s->ctl, G, 256);
   }
   HIP_TRY(hipGetLastError());
   s->cur = other;
@@ -650,6 +662,7 @@ int sim_set_basis(sim_t* s, sim_key k) {
   HIP_TRY(timed_sync(s));
   s->nnz_known = true;
   s->nnz_exact = s->nnz_ub = 1;
+  s->uni_lo = s->uni_hi = ~0ull;
   return SIM_OK;
 }
 
@@ -684,6 +697,15 @@ int sim_import_state(sim_t* s, const sim_key* keys, const sim_c64* amps, uint64_
   HIP_TRY(timed_sync(s));
   s->nnz_known = true;
   s->nnz_exact = s->nnz_ub = n;
+  uint64_t and_lo = ~0ull, and_hi = ~0ull, or_lo = 0, or_hi = 0;
+  for (uint64_t i = 0; i < n; ++i) {
+    and_lo &= lo[i];
+    and_hi &= hi[i];
+    or_lo |= lo[i];
+    or_hi |= hi[i];
+  }
+  s->uni_lo = ~(and_lo ^ or_lo);   // bits equal in every imported label (all, for none)
+  s->uni_hi = ~(and_hi ^ or_hi);
   return SIM_OK;
 }
 
@@ -1085,6 +1107,12 @@ int apply_impl(sim_t* s, const sim_gate* gates, size_t n, int32_t* outcomes, sim
   for (; i < n; ++i) {
     const sim_gate& g = gates[i];
     if (g.op == SIM_OP_MONO) {
+      // A flip keeps its target uniform only if every control is uniform.
+      if (g.flip) {
+        uint64_t& tw = g.target < 64 ? s->uni_lo : s->uni_hi;
+        const uint64_t tb = 1ull << (g.target & 63);
+        if ((tw & tb) && ((g.ctrl.lo & ~s->uni_lo) | (g.ctrl.hi & ~s->uni_hi))) tw &= ~tb;
+      }
       if (run_len == 0) run_begin = mono_seen;
       ++run_len;
       ++mono_seen;
@@ -1115,14 +1143,21 @@ int apply_impl(sim_t* s, const sim_gate* gates, size_t n, int32_t* outcomes, sim
       if (rc) return rc;
       bool over = false;
       const bool was_known = s->nnz_known;
-      rc = run_u2(s, g, &over);
+      // Partner mask x (a standard gate's is its target bit).
+      uint64_t x_lo = g.x.lo, x_hi = g.x.hi;
+      if (!x_lo && !x_hi) (g.target < 64 ? x_lo : x_hi) = 1ull << (g.target & 63);
+      const bool split = !(s->cfg.flags & SIM_FLAG_NO_UNIFORM) && ((x_lo & s->uni_lo) | (x_hi & s->uni_hi));
+      rc = run_u2(s, g, &over, split);
       if (rc) return rc;
       if (!was_known && s->nnz_known) st.host_syncs++;
       if (over) {
         result = fail(SIM_E_CAPACITY, "branching gate would exceed the state capacity");
         break;
       }
+      s->uni_lo &= ~x_lo;
+      s->uni_hi &= ~x_hi;
       st.u2_applied++;
+      if (split) st.u2_split++;
       continue;
     }
     // measurement
@@ -1137,6 +1172,7 @@ int apply_impl(sim_t* s, const sim_gate* gates, size_t n, int32_t* outcomes, sim
       result = fail(SIM_E_STATE, "measurement outcome has zero probability");
       break;
     }
+    (g.target < 64 ? s->uni_lo : s->uni_hi) |= 1ull << (g.target & 63);
     st.measures++;
     ++meas_seen;
   }
@@ -1271,6 +1307,7 @@ int sim_measure(sim_t* s, uint32_t qubit, double u, int32_t forced, int32_t* out
   }
   if (outcome) *outcome = rec.outcome;
   if (p1) *p1 = rec.p1 / (rec.p0 + rec.p1);
+  (qubit < 64 ? s->uni_lo : s->uni_hi) |= 1ull << (qubit & 63);   // collapsed: the bit is the outcome everywhere
   return SIM_OK;
 }
 
@@ -1330,7 +1367,7 @@ int sim_set_tuning(sim_t* s, const sim_config* t) {
   if (t->mono_mode > SIM_MONO_BITSLICE) return fail(SIM_E_ARG, "unknown mono_mode");
   // The fused-pass kernel (SIM_FLAG_BS_LDS) is chosen at creation only.
   if (t->flags & SIM_FLAG_BS_LDS) return fail(SIM_E_ARG, "SIM_FLAG_BS_LDS is set at creation (sim_create) only");
-  if (t->flags & ~(SIM_FLAG_U2_TWO_PASS | SIM_FLAG_U2_GLOBAL_INDEX | SIM_FLAG_COUNT_INDEX))
+  if (t->flags & ~(SIM_FLAG_U2_TWO_PASS | SIM_FLAG_U2_GLOBAL_INDEX | SIM_FLAG_COUNT_INDEX | SIM_FLAG_NO_UNIFORM))
     return fail(SIM_E_ARG, "unknown flags");
   if (t->load_factor != 0.0 && !(t->load_factor > 0.0 && t->load_factor <= 0.9))
     return fail(SIM_E_ARG, "load_factor must be in (0, 0.9]");

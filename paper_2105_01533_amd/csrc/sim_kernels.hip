@@ -254,6 +254,9 @@ __global__ __launch_bounds__(256) void k_u2_probe(Buf b, const uint64_t* __restr
   add_counters(count, lookups, steps);
 }
 
+// The count, write and single-pass kernels take partner == null for a gate
+// whose partner mask touches a qubit that is the same in every entry: then no
+// entry has a partner, and no index is built or probed.
 template <bool WIDE>
 __device__ __forceinline__ bool pivot_set(const U2Desc& d, uint64_t lo, uint64_t hi) {
   return ent::pivot_set(d, lo, hi, WIDE);
@@ -280,7 +283,7 @@ __global__ __launch_bounds__(256) void k_u2_count(Buf b, const uint64_t* __restr
   for (uint64_t i = begin + threadIdx.x; i < end; i += blockDim.x) {
     const uint64_t lo = b.key_lo[i];
     const uint64_t hi = WIDE ? b.key_hi[i] : 0ull;
-    const U2Out r = u2_eval<WIDE>(b, d, lo, hi, b.amp[i], partner[i]);
+    const U2Out r = u2_eval<WIDE>(b, d, lo, hi, b.amp[i], partner ? partner[i] : kNoPartner);
     if (r.mode == 0) {
       const bool k = survives(r.o0, d.eps);
       emit += k ? 1u : 0u;
@@ -375,7 +378,7 @@ __global__ __launch_bounds__(256) void k_u2_write(Buf in, Buf out, const uint64_
     if (i < end) {
       lo = in.key_lo[i];
       hi = WIDE ? in.key_hi[i] : 0ull;
-      r = u2_eval<WIDE>(in, d, lo, hi, in.amp[i], partner[i]);
+      r = u2_eval<WIDE>(in, d, lo, hi, in.amp[i], partner ? partner[i] : kNoPartner);
       if (r.mode == 0) {
         k0 = survives(r.o0, d.eps);
       } else if (r.mode == 1) {
@@ -475,7 +478,7 @@ __global__ __launch_bounds__(256) void k_u2_fused(Buf in, Buf out, const uint64_
     if (i < n) {
       lo[k] = in.key_lo[i];
       hi[k] = WIDE ? in.key_hi[i] : 0ull;
-      r[k] = u2_eval<WIDE>(in, d, lo[k], hi[k], in.amp[i], partner[i]);
+      r[k] = u2_eval<WIDE>(in, d, lo[k], hi[k], in.amp[i], partner ? partner[i] : kNoPartner);
       if (r[k].mode == 0) {
         k0[k] = survives(r[k].o0, d.eps);
         dropped += k0[k] ? 0u : 1u;

@@ -30,6 +30,7 @@ SIM_FLAG_U2_TWO_PASS = 1
 SIM_FLAG_BS_LDS = 2
 SIM_FLAG_U2_GLOBAL_INDEX = 4
 SIM_FLAG_COUNT_INDEX = 8
+SIM_FLAG_NO_UNIFORM = 16
 
 GATE_DTYPE = np.dtype([
     ("op", "<u4"), ("target", "<u4"), ("ctrl_lo", "<u8"), ("ctrl_hi", "<u8"),
@@ -50,7 +51,7 @@ class sim_stats(ctypes.Structure):
     _fields_ = [(f, ctypes.c_uint64) for f in (
         "gates_applied", "updates", "mono_passes", "u2_applied", "u2_skipped", "measures", "host_syncs",
         "peak_nnz", "pruned", "bitslice_passes")] + [("pruned_mass", ctypes.c_double)] + [
-        (f, ctypes.c_uint64) for f in ("index_inserts", "index_cas", "index_lookups", "index_probes")]
+        (f, ctypes.c_uint64) for f in ("index_inserts", "index_cas", "index_lookups", "index_probes", "u2_split")]
 
     def as_dict(self):
         return {f: (float if t is ctypes.c_double else int)(getattr(self, f)) for f, t in self._fields_}

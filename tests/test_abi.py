@@ -94,7 +94,7 @@ def test_workspace_bytes_and_config_validation():
                 sim.sim_config(n_qubits=10, capacity=0), sim.sim_config(n_qubits=10, capacity=1 << 31),
                 sim.sim_config(n_qubits=10, capacity=10, load_factor=0.95),
                 sim.sim_config(n_qubits=10, capacity=10, block=96),
-                sim.sim_config(n_qubits=10, capacity=10, flags=16)]:
+                sim.sim_config(n_qubits=10, capacity=10, flags=32)]:
         assert sim.sim_workspace_bytes(bad) == 0
         with pytest.raises(sim.SimError) as e:
             sim.sim_create(bad)

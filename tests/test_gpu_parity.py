@@ -1094,3 +1094,50 @@ def test_u2_single_pass_tile_sizes(sim, size):
     assert sa["u2_applied"] == sb["u2_applied"] == 2
     for x, y in zip(a, b):
         assert x.tobytes() == y.tobytes()
+
+
+@pytest.mark.parametrize("case", ["handmade", "c0", "c1_small", "random_meas", "c3_small"])
+def test_uniform_qubit_splits_match_index_path(sim, case):
+    """Branching gates whose partner mask meets a qubit that is the same in
+    every entry run without an index; the state, outcomes and counters are
+    bitwise those of the index path (SIM_FLAG_NO_UNIFORM), and such gates do
+    occur."""
+    if case == "handmade":
+        c = W.Circuit()
+        for q in range(6):
+            c.h(q)
+        c.gate(W.K_X, 10, controls=(2,))
+        c.h(10)
+        c.h(11)
+        c.measure(3, 0.4)
+        c.h(3)
+        c.gate(W.K_X, 20, controls=(30, 31))
+        c.h(20)
+        c.gate(W.K_RY, 12, controls=(0,), param=0.9)
+        c.h(0)
+        w = W.Workload("handmade", 40, 0.0, c.array(), 1 << 12)
+    elif case == "c0":
+        w = W.config0(seed=W.seed_for(0, 1))
+    elif case == "c1_small":
+        w = W.config1(71, w=10, adds=4, n=32)
+    elif case == "random_meas":
+        w = W.random_circuit(72, n=12, gates=600, h_frac=0.25, ctrl_max=3, measure_frac=0.03)
+        w.capacity = 1 << 12
+    else:
+        w = W.config3(73, terms=20)
+    out = []
+    for flags in (0, sim.SIM_FLAG_NO_UNIFORM):
+        s, outs, st = sim.run_workload(w, flags=flags)
+        out.append((s.export(sort=False), list(outs), st))
+        s.close()
+    (a, oa, sa), (b, ob, sb) = out
+    for x, y in zip(a, b):
+        assert x.tobytes() == y.tobytes(), case
+    assert oa == ob
+    for k in ("u2_applied", "u2_skipped", "pruned", "updates", "peak_nnz", "measures"):
+        assert sa[k] == sb[k], k
+    assert sa["u2_split"] > 0 and sb["u2_split"] == 0
+    o, oout, _ = oracle_run(w)
+    assert list(oa) == list(oout)
+    order = np.lexsort((a[0], a[1]))
+    assert_same_state(tuple(x[order] for x in a), o.export(), 1e-12, case)
