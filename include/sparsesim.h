@@ -450,6 +450,11 @@ int sim_kernel_stats_reset(sim_t* s);
  * the tick's graph; this flag keeps them on the graph's LDS-plane tile (the
  * same results, bit for bit). */
 #define SRV_FLAG_NO_RP 4u
+/* A branching gate or measurement that directly follows a request's fused
+ * run joins the run's tick (the fused kernels run first, in place, and keep
+ * the entry count): one host round trip for the pair instead of two.  This
+ * flag gives every request one segment per tick (the same results). */
+#define SRV_FLAG_ONE_SEGMENT 8u
 
 typedef struct srv_config {
   uint64_t budget_bytes; /* device bytes for request states (the pool) */
@@ -498,6 +503,8 @@ typedef struct srv_stats {
   double copy_ms;           /* copying finished states to host memory, summed over the
                                host threads that did it */
   uint64_t rp_runs;         /* of bitslice_runs: on the register-plane kernel */
+  uint64_t paired;          /* branching gates and measurements run in the tick of the fused
+                               run before them */
 } srv_stats;
 
 typedef struct srv_t srv_t;

@@ -5,7 +5,8 @@
 // admitted while their device footprint fits the pool and a slot is free.
 // Each tick takes one segment from every running request -- a fused
 // phase/permutation run, one branching gate, or one measurement, exactly as
-// the single-state engine would cut it -- uploads one work list, replays the
+// the single-state engine would cut it, a run together with the gate right
+// after it -- uploads one work list, replays the
 // captured tick graph, and reads back every slot's control words.  Finished
 // requests are copied to host memory and their device memory is returned to
 // the pool, which lets queued requests in on the next tick.
@@ -248,6 +249,7 @@ struct srv_t {
   char* d_tick = nullptr;
   char* h_tick = nullptr;
   size_t items_off = 0, units_off = 0, arena_off = 0, tick_bytes = 0;
+  size_t max_items = 0, max_units = 0;   // capacity of the item and unit areas
   // One captured graph per non-empty set of kernel families (index = family
   // mask), so a tick replays only the kernels it has items for.
   hipGraph_t graph[16] = {};
@@ -671,7 +673,7 @@ int srv_create(const srv_config* cfg, void* stream, void* pool, size_t pool_byte
   if (cfg->grid > 65536) return sfail(SIM_E_ARG, "grid must be 0 (default 2048) or 1..65536");
   if (cfg->lane_workers > 64) return sfail(SIM_E_ARG, "lane_workers must be 0 (default 8) or 1..64");
   if (cfg->reserved) return sfail(SIM_E_ARG, "reserved must be 0");
-  if (cfg->flags & ~(SRV_FLAG_NO_GRAPH | SRV_FLAG_U2_GLOBAL_INDEX | SRV_FLAG_NO_RP))
+  if (cfg->flags & ~(SRV_FLAG_NO_GRAPH | SRV_FLAG_U2_GLOBAL_INDEX | SRV_FLAG_NO_RP | SRV_FLAG_ONE_SEGMENT))
     return sfail(SIM_E_ARG, "unknown flags");
   std::unique_ptr<srv_t> s(new srv_t());
   s->cfg = *cfg;
@@ -703,9 +705,14 @@ int srv_create(const srv_config* cfg, void* stream, void* pool, size_t pool_byte
   }
   SRV_HIP(hipHostMalloc(&s->h_ctl, ns * sizeof(SlotCtl)));
   for (int k = (int)ns - 1; k >= 0; --k) s->free_slots.push_back(k);
+  // A tick has at most two items per running request (a fused run and the
+  // branching gate or measurement paired with it) and at most
+  // n_mono + 3 n_u2 + n_meas + 5 <= 4 ns + 5 unit offsets.
+  s->max_items = 2 * ns;
+  s->max_units = 5 * (ns + 1);
   s->items_off = al(sizeof(BTick));
-  s->units_off = s->items_off + al(ns * sizeof(BItem));
-  s->arena_off = s->units_off + al(5 * (ns + 1) * sizeof(uint32_t));
+  s->units_off = s->items_off + al(s->max_items * sizeof(BItem));
+  s->arena_off = s->units_off + al(s->max_units * sizeof(uint32_t));
   s->tick_bytes = s->arena_off + s->cfg.arena_bytes;
   SRV_HIP(hipMalloc(&s->d_tick, s->tick_bytes));
   SRV_HIP(hipHostMalloc(&s->h_tick, s->tick_bytes));
@@ -959,6 +966,52 @@ int srv_tick(srv_t* s, uint32_t* running, uint32_t* queued) {
     });
     s->stats.group_ms += ms_since(t_g);
   }
+  // A branching gate or measurement item of r (the gate at op index op).
+  auto add_gate = [&](Request* r, BItem it, SegKind k, size_t op) {
+    const sim_gate& g = r->gates[op];
+    if (k == SEG_U2) {
+      it.u2 = u2_desc(g, r->cfg.eps);
+      const uint64_t slots = std::min<uint64_t>(index_slots(r->nnz, r->cfg.load_factor), r->fp.slots);
+      it.table = r->table;
+      it.mask = slots - 1;
+      it.partner = r->partner;
+      it.tot = r->tot;
+      r->st.updates += r->nnz;
+      u2.push_back(r);
+      // Small states take the one-block kernel with the index in LDS.
+      const bool small = r->nnz <= kLdsU2Max && !(s->cfg.flags & SRV_FLAG_U2_GLOBAL_INDEX);
+      (small ? u2s_items : u2_items).push_back(it);
+    } else {
+      it.q = g.target;
+      it.forced = g.forced;
+      it.u = g.u;
+      it.part = r->part;
+      it.cnt1 = r->cnt1;
+      it.tot = r->tot;
+      meas.push_back(r);
+      meas_items.push_back(it);
+    }
+  };
+  // A branching gate or measurement that comes right after a fused run joins
+  // the run's tick: the run works in place and keeps the entry count (so the
+  // cap's skip decisions before the gate are the ones the next tick would
+  // make), register-plane runs go before the graph, and the graph runs the
+  // fused kernels before the branching and measurement kernels.  What is
+  // paired depends on the request alone; its kernels and their inputs are
+  // those of two ticks, so results are unchanged.
+  auto pair_gate = [&](Request* r, const BItem& base) {
+    if (s->cfg.flags & SRV_FLAG_ONE_SEGMENT) return false;
+    Cursor c{r->i, r->mono_seen, 0};
+    size_t b2 = 0, len2 = 0, op2 = 0;
+    const SegKind k2 = scan_segment(s, *r, r->nnz, c, &b2, &len2, &op2);
+    if (k2 != SEG_U2 && k2 != SEG_MEAS) return false;
+    r->i = c.i;
+    r->mono_seen = c.mono_seen;
+    r->st.u2_skipped += c.skipped;
+    add_gate(r, base, k2, op2);
+    s->stats.paired++;
+    return true;
+  };
   for (Seg& sg : segs) {
     Request* r = sg.r;
     const SegKind k = sg.k;
@@ -973,6 +1026,7 @@ int srv_tick(srv_t* s, uint32_t* running, uint32_t* queued) {
     it.nnz = r->nnz;
     it.cap = r->cfg.capacity;
     if (k == SEG_MONO) {
+      const BItem base = it;
       const bool bsl = sg.bsl;
       uint32_t flags = 0;
       for (size_t q = b; q < b + len; ++q) {
@@ -1007,59 +1061,35 @@ int srv_tick(srv_t* s, uint32_t* running, uint32_t* queued) {
         }
         continue;
       }
+      r->st.updates += r->nnz * len;
+      r->st.mono_passes++;
+      if (bsl) {
+        r->st.bitslice_passes++;
+        s->stats.bitslice_runs++;
+      }
       if (bsl && sg.rp) {
         // Its own launch ahead of the graph; the request has no item in it.
         std::memcpy(arena + arena_used, sg.prog.data(), bytes);
         rp_items.push_back(RpItem{r, arena_used, (uint32_t)sg.prog.size(), sg.br});
         arena_used += al(bytes);
-        r->st.updates += r->nnz * len;
-        r->st.mono_passes++;
-        r->st.bitslice_passes++;
-        s->stats.bitslice_runs++;
         s->stats.rp_runs++;
-        mono.push_back(r);
-        continue;
-      }
-      if (bsl) {
-        std::memcpy(arena + arena_used, sg.grp.data(), bytes);
-        it.gops = reinterpret_cast<const BsGroup*>(s->d_tick + s->arena_off + arena_used);
-        it.ngroups = (uint32_t)sg.grp.size();
-        it.run = sg.br;
-        s->stats.bitslice_runs++;
       } else {
-        std::memcpy(arena + arena_used, r->rc.descs.data() + b, bytes);
-        it.dops = reinterpret_cast<const MonoDesc*>(s->d_tick + s->arena_off + arena_used);
-        it.n_dops = (uint32_t)len;
+        if (bsl) {
+          std::memcpy(arena + arena_used, sg.grp.data(), bytes);
+          it.gops = reinterpret_cast<const BsGroup*>(s->d_tick + s->arena_off + arena_used);
+          it.ngroups = (uint32_t)sg.grp.size();
+          it.run = sg.br;
+        } else {
+          std::memcpy(arena + arena_used, r->rc.descs.data() + b, bytes);
+          it.dops = reinterpret_cast<const MonoDesc*>(s->d_tick + s->arena_off + arena_used);
+          it.n_dops = (uint32_t)len;
+        }
+        arena_used += al(bytes);
+        mono_items.push_back(it);
       }
-      arena_used += al(bytes);
-      r->st.updates += r->nnz * len;
-      r->st.mono_passes++;
-      if (bsl) r->st.bitslice_passes++;
-      mono.push_back(r);
-      mono_items.push_back(it);
-    } else if (k == SEG_U2) {
-      const sim_gate& g = r->gates[op];
-      it.u2 = u2_desc(g, r->cfg.eps);
-      const uint64_t slots = std::min<uint64_t>(index_slots(r->nnz, r->cfg.load_factor), r->fp.slots);
-      it.table = r->table;
-      it.mask = slots - 1;
-      it.partner = r->partner;
-      it.tot = r->tot;
-      r->st.updates += r->nnz;
-      u2.push_back(r);
-      // Small states take the one-block kernel with the index in LDS.
-      const bool small = r->nnz <= kLdsU2Max && !(s->cfg.flags & SRV_FLAG_U2_GLOBAL_INDEX);
-      (small ? u2s_items : u2_items).push_back(it);
+      if (!pair_gate(r, base)) mono.push_back(r);
     } else {
-      const sim_gate& g = r->gates[op];
-      it.q = g.target;
-      it.forced = g.forced;
-      it.u = g.u;
-      it.part = r->part;
-      it.cnt1 = r->cnt1;
-      it.tot = r->tot;
-      meas.push_back(r);
-      meas_items.push_back(it);
+      add_gate(r, it, k, op);
     }
   }
   // Finished requests leave the tick; their states are copied out in the
@@ -1073,6 +1103,9 @@ int srv_tick(srv_t* s, uint32_t* running, uint32_t* queued) {
   const uint32_t ns = (uint32_t)u2s_items.size();
   const uint32_t nrp = (uint32_t)rp_items.size();
   if (nm + nu + nq + ns + nrp) {
+    const size_t n_units = (size_t)nm + 3 * (size_t)nu + nq + 5;
+    if ((size_t)nm + nu + nq + ns > s->max_items || n_units > s->max_units)
+      return sfail(SIM_E_NOMEM, "tick work list exceeds its area");
     std::memset(hdr, 0, sizeof(BTick));
     hdr->n_mono = nm;
     hdr->n_u2 = nu;

@@ -408,6 +408,7 @@ SRV_QUEUED, SRV_RUNNING, SRV_DONE, SRV_FAILED = 0, 1, 2, 3
 SRV_FLAG_NO_GRAPH = 1
 SRV_FLAG_U2_GLOBAL_INDEX = 2
 SRV_FLAG_NO_RP = 4
+SRV_FLAG_ONE_SEGMENT = 8
 SRV_LANE_OFF = 0xFFFFFFFF
 
 
@@ -423,7 +424,8 @@ class srv_stats(ctypes.Structure):
         "submitted", "admitted", "completed", "failed", "ticks", "items", "bitslice_runs",
         "pool_used_bytes", "pool_peak_bytes")] + [(f, ctypes.c_double) for f in ("host_ms", "wait_ms", "group_ms")] + [
         ("lane_completed", ctypes.c_uint64), ("lane_ms", ctypes.c_double), ("ahead_hits", ctypes.c_uint64),
-        ("ahead_ms", ctypes.c_double), ("copy_ms", ctypes.c_double), ("rp_runs", ctypes.c_uint64)]
+        ("ahead_ms", ctypes.c_double), ("copy_ms", ctypes.c_double), ("rp_runs", ctypes.c_uint64),
+        ("paired", ctypes.c_uint64)]
 
     def as_dict(self):
         return {f: (round(getattr(self, f), 3) if t is ctypes.c_double else int(getattr(self, f)))

@@ -315,6 +315,37 @@ def test_large_states_register_plane_runs(S):
         assert_same_state(res[:3], o.export(), what=w.name)
 
 
+def test_gate_after_run_shares_its_tick(S):
+    """A branching gate or measurement right after a request's fused run runs
+    in the run's tick; states, outcomes and per-request counters are bit for
+    bit those of one segment per tick (SRV_FLAG_ONE_SEGMENT), with fewer
+    ticks, also when a small arena defers runs, on register-plane states, and
+    with every slot taken (four slots: a tick then has up to eight items, two
+    per request)."""
+    ws = mix() + [W.config2(63, n=100, h_qubits=17, gates=2000, round_gates=1000, meas_per_round=2)]
+    keys = ("updates", "u2_applied", "u2_skipped", "measures", "mono_passes", "bitslice_passes", "peak_nnz")
+    ref = None
+    for arena, slots in ((0, 64), (1 << 20, 64), (0, 4)):
+        say(f"[gpu] server: arena {arena} slots {slots}")
+        a, sa = run_server(S, ws, arena_bytes=arena, slots=slots)
+        b, sb = run_server(S, ws, arena_bytes=arena, slots=slots, flags=S.SRV_FLAG_ONE_SEGMENT)
+        assert sa["completed"] == sb["completed"] == len(ws)
+        assert sa["paired"] > 0 and sb["paired"] == 0
+        assert sa["ticks"] < sb["ticks"], (sa["ticks"], sb["ticks"])
+        assert sa["items"] == sb["items"]
+        if arena == 0:
+            ref = ref or a     # (the arena bounds run length, so rounding depends on its size)
+        for w, x, y, z in zip(ws, a, b, ref if arena == 0 else a):
+            for p, q, r in zip(x[:4], y[:4], z[:4]):
+                assert p.tobytes() == q.tobytes() == r.tobytes(), (w.name, arena, slots)
+            for k in keys:
+                assert x[4][k] == y[4][k], (w.name, k)
+    say(f"[gpu] oracle {ws[-1].name}")
+    o, oout, _ = oracle_run(ws[-1])
+    assert list(a[-1][3]) == list(oout)
+    assert_same_state(a[-1][:3], o.export(), what=ws[-1].name)
+
+
 def test_destroy_with_work_in_flight(S):
     """A server closed while requests are queued, compiling, running and
     being copied out shuts its background workers down cleanly; a new server
