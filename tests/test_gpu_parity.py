@@ -1141,3 +1141,38 @@ def test_uniform_qubit_splits_match_index_path(sim, case):
     assert list(oa) == list(oout)
     order = np.lexsort((a[0], a[1]))
     assert_same_state(tuple(x[order] for x in a), o.export(), 1e-12, case)
+
+
+@pytest.mark.parametrize("n,seed,eps", [(9, 81, 0.0), (30, 82, 1e-9), (64, 83, 0.0), (65, 84, 1e-9),
+                                        (100, 85, 0.0), (128, 86, 1e-9)])
+def test_engine_flags_leave_results_unchanged(sim, n, seed, eps):
+    """Every engine flag that only changes how a result is computed -- the
+    separate count/scan/write passes, the global partner index for small
+    states, the index for gates a uniform qubit splits, LDS planes instead of
+    register planes -- gives the default's state, outcomes and counters bit
+    for bit on random circuits of every gate kind with measurements; the
+    default matches the oracle."""
+    w = W.random_circuit(seed, n=n, gates=700, h_frac=0.15, ctrl_max=3, measure_frac=0.02, cap=1 << 15)
+    w.capacity = 1 << 15
+    w.eps = eps
+    variants = [sim.SIM_FLAG_U2_TWO_PASS, sim.SIM_FLAG_U2_GLOBAL_INDEX, sim.SIM_FLAG_NO_UNIFORM,
+                sim.SIM_FLAG_BS_LDS,
+                sim.SIM_FLAG_U2_TWO_PASS | sim.SIM_FLAG_NO_UNIFORM | sim.SIM_FLAG_BS_LDS,
+                sim.SIM_FLAG_U2_GLOBAL_INDEX | sim.SIM_FLAG_NO_UNIFORM]
+    keys = ("u2_applied", "u2_skipped", "pruned", "updates", "peak_nnz", "measures")
+    out = []
+    for flags in [0] + variants:
+        s, outs, st = sim.run_workload(w, flags=flags)
+        out.append((s.export(sort=False), list(outs), st))
+        s.close()
+    a, oa, sa = out[0]
+    for flags, (b, ob, sb) in zip(variants, out[1:]):
+        for x, y in zip(a, b):
+            assert x.tobytes() == y.tobytes(), flags
+        assert oa == ob, flags
+        for k in keys:
+            assert sa[k] == sb[k], (flags, k)
+    o, oout, _ = oracle_run(w)
+    assert oa == list(oout)
+    order = np.lexsort((a[0], a[1]))
+    assert_same_state(tuple(x[order] for x in a), o.export(), 1e-12, w.name)
