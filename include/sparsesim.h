@@ -452,8 +452,10 @@ int sim_kernel_stats_reset(sim_t* s);
 #define SRV_FLAG_NO_RP 4u
 /* A branching gate or measurement that directly follows a request's fused
  * run joins the run's tick (the fused kernels run first, in place, and keep
- * the entry count): one host round trip for the pair instead of two.  This
- * flag gives every request one segment per tick (the same results). */
+ * the entry count): one host round trip for the pair instead of two; and up
+ * to 8 consecutive measurements of a request run in one tick, one launch
+ * round each, a later one taking its entry count from the device.  This flag
+ * gives every request one segment per tick (the same results). */
 #define SRV_FLAG_ONE_SEGMENT 8u
 
 typedef struct srv_config {
@@ -505,6 +507,7 @@ typedef struct srv_stats {
   uint64_t rp_runs;         /* of bitslice_runs: on the register-plane kernel */
   uint64_t paired;          /* branching gates and measurements run in the tick of the fused
                                run before them */
+  uint64_t chained;         /* measurements run in the tick of the measurement before them */
 } srv_stats;
 
 typedef struct srv_t srv_t;

@@ -378,6 +378,16 @@ __global__ __launch_bounds__(1024) void kb_u2_lds(const BTick* __restrict__ hdr,
 }
 
 // ---- measurements ------------------------------------------------------------
+// Entries of a measurement item's input.  The first measurement of a tick
+// knows its count; a later step of a chain takes the count the previous step
+// wrote (at most it.nnz, the count before the chain, from which its units
+// were laid out: units past the count are empty and add nothing).
+__device__ __forceinline__ uint64_t meas_nnz(const BItem& it) {
+  if (it.chain == 0) return it.nnz;
+  const uint64_t d = it.ctl->nnz[it.other ^ 1u];
+  return d < it.nnz ? d : it.nnz;
+}
+
 __global__ __launch_bounds__(256) void kb_m_reduce(const BTick* __restrict__ hdr, const BItem* __restrict__ items,
                                                    const uint32_t* __restrict__ units) {
   __shared__ double2 shd[256];
@@ -390,9 +400,10 @@ __global__ __launch_bounds__(256) void kb_m_reduce(const BTick* __restrict__ hdr
   for (uint32_t u = blockIdx.x; u < total; u += gridDim.x) {
     const int i = find_item(u0, n, u);
     const BItem& it = m[i];
+    const uint64_t nnz = meas_nnz(it);
     const uint32_t c = u - u0[i];
     const uint64_t e0 = (uint64_t)c * kChunk;
-    const uint64_t e1 = e0 + kChunk < it.nnz ? e0 + kChunk : it.nnz;
+    const uint64_t e1 = e0 + kChunk < nnz ? e0 + kChunk : nnz;
     const bool qhi = it.wide && it.q >= 64;
     double p0 = 0.0, p1 = 0.0;
     uint32_t c1 = 0;
@@ -426,6 +437,7 @@ __global__ __launch_bounds__(256) void kb_m_decide(const BTick* __restrict__ hdr
   const uint32_t* u0 = units + hdr->meas_u0;
   for (int i = blockIdx.x; i < n; i += gridDim.x) {
     const BItem& it = m[i];
+    const uint64_t nnz = meas_nnz(it);
     const uint32_t nc = u0[i + 1] - u0[i];
     double2 acc = make_double2(0.0, 0.0);
     for (uint32_t k = threadIdx.x; k < nc; k += blockDim.x) acc = cadd(acc, it.part[k]);
@@ -445,6 +457,7 @@ __global__ __launch_bounds__(256) void kb_m_decide(const BTick* __restrict__ hdr
       it.ctl->rec.scale = scale;
       it.ctl->rec.outcome = o;
       it.ctl->outcome = o;
+      if (it.chain < kMaxChain) it.ctl->chain_out[it.chain] = o;
       s_o = o;
     }
     __syncthreads();
@@ -453,8 +466,8 @@ __global__ __launch_bounds__(256) void kb_m_decide(const BTick* __restrict__ hdr
     const uint32_t first = threadIdx.x * per;
     auto count = [&](uint32_t k) -> uint32_t {
       const uint64_t b0 = (uint64_t)k * kChunk;
-      const uint64_t b1 = b0 + kChunk < it.nnz ? b0 + kChunk : it.nnz;
-      const uint32_t len = (uint32_t)(b1 - b0);
+      const uint64_t b1 = b0 + kChunk < nnz ? b0 + kChunk : nnz;
+      const uint32_t len = b0 < b1 ? (uint32_t)(b1 - b0) : 0u;
       return o == 1 ? it.cnt1[k] : (o == 0 ? len - it.cnt1[k] : 0u);
     };
     uint32_t s = 0;
@@ -494,9 +507,10 @@ __global__ __launch_bounds__(256) void kb_m_write(const BTick* __restrict__ hdr,
     const int o = it.ctl->rec.outcome;
     if (o < 0) continue;
     const double scale = it.ctl->rec.scale;
+    const uint64_t nnz = meas_nnz(it);
     const uint32_t c = u - u0[i];
     const uint64_t e0 = (uint64_t)c * kChunk;
-    const uint64_t e1 = e0 + kChunk < it.nnz ? e0 + kChunk : it.nnz;
+    const uint64_t e1 = e0 + kChunk < nnz ? e0 + kChunk : nnz;
     const bool qhi = it.wide && it.q >= 64;
     uint64_t base = it.tot[c];
     for (uint64_t tile = e0; tile < e1; tile += blockDim.x) {
@@ -539,11 +553,13 @@ void launch_batch_tick(hipStream_t st, const BTick* hdr, const BItem* items, con
   }
   if (families & kFamU2s)
     hipLaunchKernelGGL(kb_u2_lds, dim3(grid < 256 ? grid : 256), dim3(lds::kThreads), 0, st, hdr, items);
-  if (families & kFamMeas) {
-    hipLaunchKernelGGL(kb_m_reduce, dim3(grid), dim3(256), 0, st, hdr, items, units);
-    hipLaunchKernelGGL(kb_m_decide, dim3(grid), dim3(256), 0, st, hdr, items, units);
-    hipLaunchKernelGGL(kb_m_write, dim3(grid), dim3(256), 0, st, hdr, items, units);
-  }
+  if (families & kFamMeas) launch_batch_meas(st, hdr, items, units, grid);
+}
+
+void launch_batch_meas(hipStream_t st, const BTick* hdr, const BItem* items, const uint32_t* units, int grid) {
+  hipLaunchKernelGGL(kb_m_reduce, dim3(grid), dim3(256), 0, st, hdr, items, units);
+  hipLaunchKernelGGL(kb_m_decide, dim3(grid), dim3(256), 0, st, hdr, items, units);
+  hipLaunchKernelGGL(kb_m_write, dim3(grid), dim3(256), 0, st, hdr, items, units);
 }
 
 }  // namespace sparsesim

@@ -216,6 +216,10 @@ struct Request {
   bool large = false;                 // runs on the large-state lane
   int lane_rc = SIM_OK;               // the lane's result code
   SegKind seg = SEG_NONE;
+  // Measurements this tick: the first and the ones right after it, which run
+  // in later launch rounds of the same tick (op indices).
+  uint32_t chain_len = 0;
+  size_t chain_op[kMaxChain] = {};
   sim_stats st{};
   std::vector<int32_t> outcomes;
   // result (storage order; res_hi only for more than 64 qubits)
@@ -250,6 +254,7 @@ struct srv_t {
   char* h_tick = nullptr;
   size_t items_off = 0, units_off = 0, arena_off = 0, tick_bytes = 0;
   size_t max_items = 0, max_units = 0;   // capacity of the item and unit areas
+  size_t chain_hdr_off = 0;               // headers of a tick's later measurement rounds
   // One captured graph per non-empty set of kernel families (index = family
   // mask), so a tick replays only the kernels it has items for.
   hipGraph_t graph[16] = {};
@@ -705,14 +710,17 @@ int srv_create(const srv_config* cfg, void* stream, void* pool, size_t pool_byte
   }
   SRV_HIP(hipHostMalloc(&s->h_ctl, ns * sizeof(SlotCtl)));
   for (int k = (int)ns - 1; k >= 0; --k) s->free_slots.push_back(k);
-  // A tick has at most two items per running request (a fused run and the
-  // branching gate or measurement paired with it) and at most
-  // n_mono + 3 n_u2 + n_meas + 5 <= 4 ns + 5 unit offsets.
-  s->max_items = 2 * ns;
-  s->max_units = 5 * (ns + 1);
+  // A tick has at most two first-round items per running request (a fused
+  // run and the branching gate or measurement paired with it) and
+  // n_mono + 3 n_u2 + n_meas + 5 <= 4 ns + 5 unit offsets for them; each of
+  // the kMaxChain - 1 later measurement rounds adds at most one item per
+  // request and ns + 1 unit offsets.
+  s->max_items = (2 + (kMaxChain - 1)) * ns;
+  s->max_units = (5 + (kMaxChain - 1)) * (ns + 1);
   s->items_off = al(sizeof(BTick));
   s->units_off = s->items_off + al(s->max_items * sizeof(BItem));
-  s->arena_off = s->units_off + al(s->max_units * sizeof(uint32_t));
+  s->chain_hdr_off = s->units_off + al(s->max_units * sizeof(uint32_t));
+  s->arena_off = s->chain_hdr_off + al((kMaxChain - 1) * sizeof(BTick));
   s->tick_bytes = s->arena_off + s->cfg.arena_bytes;
   SRV_HIP(hipMalloc(&s->d_tick, s->tick_bytes));
   SRV_HIP(hipHostMalloc(&s->h_tick, s->tick_bytes));
@@ -966,6 +974,36 @@ int srv_tick(srv_t* s, uint32_t* running, uint32_t* queued) {
     });
     s->stats.group_ms += ms_since(t_g);
   }
+  // An item of r on its current buffers (the segment fields left empty).
+  auto base_item = [&](Request* r) {
+    BItem it{};
+    it.in = r->buf[r->cur];
+    it.out = r->buf[r->cur ^ 1];
+    it.ctl = s->d_ctl + r->slot;
+    it.other = (uint32_t)(r->cur ^ 1);
+    it.wide = r->cfg.n_qubits > 64 ? 1u : 0u;
+    it.nnz = r->nnz;
+    it.cap = r->cfg.capacity;
+    return it;
+  };
+  // Requests whose measurement this tick has later steps (a chain).
+  std::vector<Request*> chains;
+  // The measurement item of step j of r's chain (base: r's current buffers).
+  auto meas_item = [&](Request* r, BItem it, uint32_t j) {
+    if (j & 1u) {
+      std::swap(it.in, it.out);
+      it.other ^= 1u;
+    }
+    const sim_gate& g = r->gates[r->chain_op[j]];
+    it.chain = j;
+    it.q = g.target;
+    it.forced = g.forced;
+    it.u = g.u;
+    it.part = r->part;
+    it.cnt1 = r->cnt1;
+    it.tot = r->tot;
+    return it;
+  };
   // A branching gate or measurement item of r (the gate at op index op).
   auto add_gate = [&](Request* r, BItem it, SegKind k, size_t op) {
     const sim_gate& g = r->gates[op];
@@ -982,14 +1020,20 @@ int srv_tick(srv_t* s, uint32_t* running, uint32_t* queued) {
       const bool small = r->nnz <= kLdsU2Max && !(s->cfg.flags & SRV_FLAG_U2_GLOBAL_INDEX);
       (small ? u2s_items : u2_items).push_back(it);
     } else {
-      it.q = g.target;
-      it.forced = g.forced;
-      it.u = g.u;
-      it.part = r->part;
-      it.cnt1 = r->cnt1;
-      it.tot = r->tot;
+      // Measurements right after this one run in later rounds of the tick:
+      // each needs only the previous one's output, whose entry count the
+      // kernels read on the device.
+      r->chain_len = 1;
+      r->chain_op[0] = op;
+      if (!(s->cfg.flags & SRV_FLAG_ONE_SEGMENT))
+        while (r->chain_len < kMaxChain && r->i < r->gates.size() && r->gates[r->i].op == SIM_OP_MEASURE)
+          r->chain_op[r->chain_len++] = r->i++;
+      if (r->chain_len > 1) {
+        chains.push_back(r);
+        s->stats.chained += r->chain_len - 1;
+      }
       meas.push_back(r);
-      meas_items.push_back(it);
+      meas_items.push_back(meas_item(r, it, 0));
     }
   };
   // A branching gate or measurement that comes right after a fused run joins
@@ -1017,14 +1061,7 @@ int srv_tick(srv_t* s, uint32_t* running, uint32_t* queued) {
     const SegKind k = sg.k;
     size_t b = sg.b, len = sg.len;
     const size_t op = sg.op;
-    BItem it{};
-    it.in = r->buf[r->cur];
-    it.out = r->buf[r->cur ^ 1];
-    it.ctl = s->d_ctl + r->slot;
-    it.other = (uint32_t)(r->cur ^ 1);
-    it.wide = r->cfg.n_qubits > 64 ? 1u : 0u;
-    it.nnz = r->nnz;
-    it.cap = r->cfg.capacity;
+    BItem it = base_item(r);
     if (k == SEG_MONO) {
       const BItem base = it;
       const bool bsl = sg.bsl;
@@ -1102,9 +1139,21 @@ int srv_tick(srv_t* s, uint32_t* running, uint32_t* queued) {
   const uint32_t nm = (uint32_t)mono_items.size(), nu = (uint32_t)u2_items.size(), nq = (uint32_t)meas_items.size();
   const uint32_t ns = (uint32_t)u2s_items.size();
   const uint32_t nrp = (uint32_t)rp_items.size();
+  // Later measurement rounds: round j holds step j of every chain longer
+  // than j (the count before the chain bounds its units).
+  uint32_t rounds = 1;
+  for (const Request* r : chains) rounds = std::max(rounds, r->chain_len);
+  std::vector<std::vector<BItem>> later(rounds - 1);
+  for (Request* r : chains)
+    for (uint32_t j = 1; j < r->chain_len; ++j) later[j - 1].push_back(meas_item(r, base_item(r), j));
+  size_t n_later = 0, later_units = 0;
+  for (const auto& v : later) {
+    n_later += v.size();
+    later_units += v.size() + 1;
+  }
   if (nm + nu + nq + ns + nrp) {
     const size_t n_units = (size_t)nm + 3 * (size_t)nu + nq + 5;
-    if ((size_t)nm + nu + nq + ns > s->max_items || n_units > s->max_units)
+    if ((size_t)nm + nu + nq + ns + n_later > s->max_items || n_units + later_units > s->max_units)
       return sfail(SIM_E_NOMEM, "tick work list exceeds its area");
     std::memset(hdr, 0, sizeof(BTick));
     hdr->n_mono = nm;
@@ -1139,8 +1188,24 @@ int srv_tick(srv_t* s, uint32_t* running, uint32_t* queued) {
     size_t ni = 0;
     for (const auto& v : {&mono_items, &u2_items, &meas_items, &u2s_items})
       for (const BItem& it : *v) items[ni++] = it;
+    // Each later round: its header (only measurement items), first-unit
+    // array and items after everything before it.
+    std::vector<size_t> later_i0(later.size());
+    auto* later_hdr = reinterpret_cast<BTick*>(s->h_tick + s->chain_hdr_off);
+    for (size_t j = 0; j < later.size(); ++j) {
+      std::memset(&later_hdr[j], 0, sizeof(BTick));
+      later_hdr[j].n_meas = (uint32_t)later[j].size();
+      later_hdr[j].meas_u0 = w;
+      prefix(units + w, later[j], chunks);
+      w += (uint32_t)later[j].size() + 1;
+      later_i0[j] = ni;
+      for (const BItem& it : later[j]) items[ni++] = it;
+    }
     SRV_HIP(hipMemcpyAsync(s->d_tick, s->h_tick, s->items_off + ni * sizeof(BItem), hipMemcpyHostToDevice,
                            s->stream));
+    if (!later.empty())
+      SRV_HIP(hipMemcpyAsync(s->d_tick + s->chain_hdr_off, later_hdr, later.size() * sizeof(BTick),
+                             hipMemcpyHostToDevice, s->stream));
     SRV_HIP(hipMemcpyAsync(s->d_tick + s->units_off, units, w * sizeof(uint32_t), hipMemcpyHostToDevice, s->stream));
     if (arena_used)
       SRV_HIP(hipMemcpyAsync(s->d_tick + s->arena_off, arena, arena_used, hipMemcpyHostToDevice, s->stream));
@@ -1165,6 +1230,13 @@ int srv_tick(srv_t* s, uint32_t* running, uint32_t* queued) {
                         reinterpret_cast<const uint32_t*>(s->d_tick + s->units_off), s->grid, fam);
       SRV_HIP(hipGetLastError());
     }
+    // Later measurement rounds, in order, after the graph.
+    for (size_t j = 0; j < later.size(); ++j) {
+      launch_batch_meas(s->stream, reinterpret_cast<const BTick*>(s->d_tick + s->chain_hdr_off) + j,
+                        reinterpret_cast<const BItem*>(s->d_tick + s->items_off) + later_i0[j],
+                        reinterpret_cast<const uint32_t*>(s->d_tick + s->units_off), s->grid);
+      SRV_HIP(hipGetLastError());
+    }
     int max_slot = -1;
     for (Request* r : s->running) max_slot = std::max(max_slot, r->slot);
     SRV_HIP(hipMemcpyAsync(s->h_ctl, s->d_ctl, (size_t)(max_slot + 1) * sizeof(SlotCtl), hipMemcpyDeviceToHost,
@@ -1181,7 +1253,7 @@ int srv_tick(srv_t* s, uint32_t* running, uint32_t* queued) {
       s->stats.wait_ms += ms_since(t_w);
     }
     s->stats.ticks++;
-    s->stats.items += nm + nu + nq + ns + nrp;
+    s->stats.items += nm + nu + nq + ns + nrp + n_later;
     // Fold the results back.
     std::vector<std::pair<Request*, int>> failed;
     for (Request* r : u2) {
@@ -1196,15 +1268,20 @@ int srv_tick(srv_t* s, uint32_t* running, uint32_t* queued) {
       r->st.peak_nnz = std::max<uint64_t>(r->st.peak_nnz, r->nnz);
     }
     for (Request* r : meas) {
+      // Outcomes up to the first zero-probability one (which fails the
+      // request, as it would have alone).
       const SlotCtl& c = s->h_ctl[r->slot];
-      if ((c.status & kStMeasure) || c.outcome < 0) {
+      uint32_t k = 0;
+      for (; k < r->chain_len && c.chain_out[k] >= 0; ++k) {
+        r->outcomes.push_back(c.chain_out[k]);
+        r->st.measures++;
+      }
+      if (k < r->chain_len || (c.status & kStMeasure)) {
         failed.emplace_back(r, SIM_E_STATE);
         continue;
       }
-      r->cur ^= 1;
+      r->cur ^= (int)(r->chain_len & 1u);
       r->nnz = c.nnz[r->cur];
-      r->outcomes.push_back(c.outcome);
-      r->st.measures++;
     }
     for (auto& f : failed) {
       bg_wait(s, f.first);   // a grouping made for it may be in flight

@@ -202,6 +202,9 @@ constexpr uint32_t kChunk = 2048;          // entries per unit (= one bit-sliced
 constexpr uint32_t kFillUnit = 8192;       // index slots per fill unit
 constexpr uint32_t kMaxPlanes = 128 + kExtraPlanes;   // label planes + all-ones, scratch
 constexpr uint32_t kStOverflow = 1u, kStMeasure = 2u;
+// Consecutive measurements of one state that one tick can run (one launch
+// round each).
+constexpr uint32_t kMaxChain = 8;
 
 // Per-state control words, one slot each, read back after every tick.
 struct SlotCtl {
@@ -209,8 +212,9 @@ struct SlotCtl {
   MeasRec rec;
   int32_t outcome;
   uint32_t status;
+  int32_t chain_out[kMaxChain];   // outcome of each measurement of a chain (-1: zero probability)
 };
-static_assert(sizeof(SlotCtl) == 56, "SlotCtl layout");
+static_assert(sizeof(SlotCtl) == 88, "SlotCtl layout");
 
 struct BItem {
   Buf in, out;                 // current and other buffer of the state
@@ -224,7 +228,9 @@ struct BItem {
   uint32_t ngroups, n_dops;
   const MonoDesc* dops;        // ... or per-entry descriptors
   BsRun run;
-  uint32_t run_flags, pad0;
+  uint32_t run_flags;
+  uint32_t chain;              // measurement: its step in a chain of the tick (0: first; later steps
+                               // take the entry count from ctl, at most nnz)
   // branching gate
   U2Desc u2;
   uint64_t* table;
@@ -255,6 +261,8 @@ constexpr uint32_t kFamMono = 1, kFamU2 = 2, kFamU2s = 4, kFamMeas = 8, kFamAll 
 // The kernels of the families in `families`, in tick order.
 void launch_batch_tick(hipStream_t st, const BTick* hdr, const BItem* items, const uint32_t* units, int grid,
                        uint32_t families);
+// The measurement kernels alone (a later step of measurement chains).
+void launch_batch_meas(hipStream_t st, const BTick* hdr, const BItem* items, const uint32_t* units, int grid);
 
 
 // ---- launchers (sim_kernels.hip) -------------------------------------------

@@ -425,7 +425,7 @@ class srv_stats(ctypes.Structure):
         "pool_used_bytes", "pool_peak_bytes")] + [(f, ctypes.c_double) for f in ("host_ms", "wait_ms", "group_ms")] + [
         ("lane_completed", ctypes.c_uint64), ("lane_ms", ctypes.c_double), ("ahead_hits", ctypes.c_uint64),
         ("ahead_ms", ctypes.c_double), ("copy_ms", ctypes.c_double), ("rp_runs", ctypes.c_uint64),
-        ("paired", ctypes.c_uint64)]
+        ("paired", ctypes.c_uint64), ("chained", ctypes.c_uint64)]
 
     def as_dict(self):
         return {f: (round(getattr(self, f), 3) if t is ctypes.c_double else int(getattr(self, f)))

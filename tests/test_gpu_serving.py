@@ -317,11 +317,12 @@ def test_large_states_register_plane_runs(S):
 
 def test_gate_after_run_shares_its_tick(S):
     """A branching gate or measurement right after a request's fused run runs
-    in the run's tick; states, outcomes and per-request counters are bit for
-    bit those of one segment per tick (SRV_FLAG_ONE_SEGMENT), with fewer
-    ticks, also when a small arena defers runs, on register-plane states, and
-    with every slot taken (four slots: a tick then has up to eight items, two
-    per request)."""
+    in the run's tick, and consecutive measurements in one tick (later launch
+    rounds); states, outcomes and per-request counters are bit for bit those
+    of one segment per tick (SRV_FLAG_ONE_SEGMENT), with fewer ticks, also
+    when a small arena defers runs, on register-plane states, and with every
+    slot taken (four slots: a tick then has up to two first-round items per
+    request)."""
     ws = mix() + [W.config2(63, n=100, h_qubits=17, gates=2000, round_gates=1000, meas_per_round=2)]
     keys = ("updates", "u2_applied", "u2_skipped", "measures", "mono_passes", "bitslice_passes", "peak_nnz")
     ref = None
@@ -331,6 +332,7 @@ def test_gate_after_run_shares_its_tick(S):
         b, sb = run_server(S, ws, arena_bytes=arena, slots=slots, flags=S.SRV_FLAG_ONE_SEGMENT)
         assert sa["completed"] == sb["completed"] == len(ws)
         assert sa["paired"] > 0 and sb["paired"] == 0
+        assert sa["chained"] > 0 and sb["chained"] == 0
         assert sa["ticks"] < sb["ticks"], (sa["ticks"], sb["ticks"])
         assert sa["items"] == sb["items"]
         if arena == 0:
@@ -344,6 +346,49 @@ def test_gate_after_run_shares_its_tick(S):
     o, oout, _ = oracle_run(ws[-1])
     assert list(a[-1][3]) == list(oout)
     assert_same_state(a[-1][:3], o.export(), what=ws[-1].name)
+
+
+def test_measurement_chains(S):
+    """Runs of consecutive measurements (longer than one tick's limit of
+    eight, on narrow and wide labels, forced and sampled) give the outcomes
+    and states of one measurement per tick and of the oracle; a
+    zero-probability forced outcome inside a chain fails its request with the
+    outcomes before it kept, as one at a time, while the other requests of
+    the tick finish."""
+    def chain_circuit(n, forced_zero_at=None):
+        c = W.Circuit()
+        for q in range(12):
+            c.h(q)
+        c.gate(W.K_X, n - 1, controls=(0,))
+        for k in range(11):                       # 11 consecutive measurements: rounds of 8 and 3
+            q = k if k != forced_zero_at else 30
+            c.measure(q, 0.37 + 0.05 * k, forced=1 if k in (2, forced_zero_at) else -1)
+        c.h(3)
+        c.measure(3, 0.5)
+        c.measure(n - 1, 0.2)
+        return c.array()
+    ws = [W.Workload("chain40", 40, 0.0, chain_circuit(40), 1 << 13),
+          W.Workload("chain100", 100, 0.0, chain_circuit(100), 1 << 13),
+          mix()[0]]
+    a, sa = run_server(S, ws)
+    b, sb = run_server(S, ws, flags=S.SRV_FLAG_ONE_SEGMENT)
+    assert sa["chained"] >= 2 * 10 and sb["chained"] == 0
+    for w, x, y in zip(ws, a, b):
+        for p, q in zip(x[:4], y[:4]):
+            assert p.tobytes() == q.tobytes(), w.name
+        o, oout, _ = oracle_run(w)
+        assert list(x[3]) == list(oout), w.name
+        assert_same_state(x[:3], o.export(), what=w.name)
+    # qubit 30 is 0 in every entry: forcing 1 there fails the request
+    bad = W.Workload("chain_zero", 40, 0.0, chain_circuit(40, forced_zero_at=5), 1 << 13)
+    for flags in (0, S.SRV_FLAG_ONE_SEGMENT):
+        srv = S.Server(1 << 30, max_slots=8, lane_capacity=S.SRV_LANE_OFF, flags=flags)
+        ids = [srv.submit_workload(w) for w in (bad, ws[0])]
+        srv.run()
+        st, err = srv.poll(ids[0])
+        assert st == S.SRV_FAILED and err == S.SIM_E_STATE, flags
+        assert srv.poll(ids[1])[0] == S.SRV_DONE
+        srv.close()
 
 
 def test_destroy_with_work_in_flight(S):
