@@ -147,6 +147,49 @@ def cpu_parallel(h_qubits: int = 20, body: int = 1200, threads: int = 0):
                       f"(queue {p_body:.1f} s)"}
 
 
+def cpu_serving(sample, seconds_budget: float = 20.0, threads: int = 0):
+    """The oracle on requests of the serving trace, independent requests
+    spread over the host's cores (a pool of threads, each running one whole
+    request at a time; the oracle library runs outside the interpreter lock):
+    the given requests in arrival order until the budget is spent (the ones
+    in flight then finish).  Context beside the GPU's serving figures, which
+    cover the whole trace."""
+    import concurrent.futures as cf
+
+    from oracle import run_workload as oracle_run
+
+    threads = threads or min(16, len(os.sched_getaffinity(0)))
+
+    def one(w):
+        o, _, _ = oracle_run(w)
+        u = o.totals()["updates"]
+        del o
+        return u
+
+    t0 = time.perf_counter()
+    done = updates = 0
+    with cf.ThreadPoolExecutor(threads) as ex:
+        pending = set()
+        it = iter(sample)
+        while True:
+            while len(pending) < threads and time.perf_counter() - t0 < seconds_budget:
+                w = next(it, None)
+                if w is None:
+                    break
+                pending.add(ex.submit(one, w))
+            if not pending:
+                break
+            fin, pending = cf.wait(pending, return_when=cf.FIRST_COMPLETED)
+            for f in fin:
+                updates += f.result()
+                done += 1
+    dt = time.perf_counter() - t0
+    return {"value": updates / dt, "unit": "updates/s", "requests_per_s": done / dt, "cores": threads,
+            "kind": "oracle, independent requests on all cores", "host": host_cpu(),
+            "sample": f"the serving trace's requests of at most 2^12 entries in arrival order: {done} of "
+                      f"{len(sample)} run in {dt:.1f} s ({updates} updates), {threads} at a time"}
+
+
 def hbm_sweep(sim, W, n_qubits=100, log2n=24, depths=(1, 2, 4, 16, 64)):
     """Fused-pass bandwidth vs fusion depth F on a 2^log2n-entry state: 64
     phase/permutation gates of the random mix, passes of F gates."""
@@ -362,6 +405,7 @@ def main():
     ap.add_argument("--no-commuting", action="store_true", help="skip the gate-commuting comparison")
     ap.add_argument("--no-pauli", action="store_true", help="skip the native Pauli-exponential comparison")
     ap.add_argument("--no-cpu-parallel", action="store_true", help="skip the multithreaded-oracle leg")
+    ap.add_argument("--no-cpu-serving", action="store_true", help="skip the oracle leg on the serving trace")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run the 1 GiB reference copy kernel (for hardware byte-counter scaling) first")
     ap.add_argument("--serving-requests", type=int, default=512)
@@ -506,9 +550,11 @@ def main():
     s.close()
     if not args.no_sweep:
         out["hbm_sweep"] = hbm_sweep(sim, W)
+    cpu_sample = []
     if not args.no_serving:
         out["serving"] = serving_bench(sim, trace, args.serving_max_log2, args.serving_max_gates,
                                        tick_updates=args.serving_tick_updates, grid=args.serving_grid)
+        cpu_sample = [w for _, w in trace if w.capacity <= 1 << 12]
         del trace
     if not args.no_commuting:
         out["commuting"] = commuting_bench(sim, W)
@@ -522,6 +568,10 @@ def main():
             log("[bench] cpu parallel queue (oracle, Sec. 5) ...")
             out["cpu_parallel"] = cpu_parallel()
             log(f"[bench] cpu parallel: {out['cpu_parallel']}")
+        if cpu_sample and not args.no_cpu_serving:
+            log("[bench] cpu serving (oracle, requests on all cores) ...")
+            out["cpu_serving"] = cpu_serving(cpu_sample, args.cpu_seconds)
+            log(f"[bench] cpu serving: {out['cpu_serving']}")
     print(json.dumps(out), flush=True)
 
 
