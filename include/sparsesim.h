@@ -482,7 +482,11 @@ typedef struct srv_config {
                             faults whose cause is not known). */
   uint32_t lane_workers; /* lane threads (each with its own stream), so that as many large
                             requests run at once; 0 = 8, else 1..64 */
-  uint32_t reserved;     /* must be 0 */
+  uint32_t max_run_ops;  /* longest fused run a tick takes from one request, in ops (the request's
+                            own fuse_max still applies); 0 = 4096.  Long runs on small states are
+                            single waves that set a tick's length; cut, they let the other requests
+                            of the tick through sooner.  Where runs are cut changes rounding only,
+                            and depends on the request and this value alone */
 } srv_config;
 
 #define SRV_LANE_OFF 0xFFFFFFFFu

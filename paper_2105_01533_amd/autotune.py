@@ -50,10 +50,11 @@ KNOBS = tuple(DEFAULTS)
 SERVER_SPACE = {
     "grid": [512, 1024, 2048, 4096],
     "tick_updates": [0, 1 << 30, 1 << 32],
+    "max_run_ops": [1024, 4096, 16384, 65536],
 }
 # The lane is off (lane_capacity 0): server runs with it ended in intermittent
 # GPU memory faults whose cause is not known, so it is neither used nor tuned.
-SERVER_DEFAULTS = {"lane_capacity": 0, "lane_workers": 8, "grid": 2048, "tick_updates": 0}
+SERVER_DEFAULTS = {"lane_capacity": 0, "lane_workers": 8, "grid": 2048, "tick_updates": 0, "max_run_ops": 4096}
 
 
 def bucket_key(n_qubits: int, capacity: int) -> str:
@@ -223,7 +224,7 @@ if __name__ == "__main__":
     ap.add_argument("--gates", type=int, default=20_000)
     ap.add_argument("--repeats", type=int, default=3)
     ap.add_argument("--server", action="store_true",
-                    help="also tune the server's tick grid and per-tick update cap (p99 of a reduced trace)")
+                    help="also tune the server's tick grid, per-tick update cap and run cap (p99 of a reduced trace)")
     ap.add_argument("--server-only", action="store_true",
                     help="keep the table's per-state buckets (read from --table) and tune only the server")
     ap.add_argument("--table", default=DEFAULT_CACHE, help="table read by --server-only")

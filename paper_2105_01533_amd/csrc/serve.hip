@@ -260,6 +260,7 @@ struct srv_t {
   hipGraph_t graph[16] = {};
   hipGraphExec_t exec[16] = {};
   int grid = 2048;
+  uint32_t run_ops = 4096;            // longest fused run per request per tick (ops)
   uint64_t next_id = 1;
   std::unordered_map<uint64_t, std::unique_ptr<Request>> reqs;
   std::deque<uint64_t> queue;
@@ -348,7 +349,7 @@ struct Cursor {
 // Reads only the request's ops and configuration.
 SegKind scan_segment(const srv_t* s, const Request& r, uint64_t nnz, Cursor& c, size_t* begin, size_t* len,
                      size_t* op) {
-  uint64_t fuse_max = r.cfg.fuse_max ? r.cfg.fuse_max : 65536u;
+  uint64_t fuse_max = std::min<uint64_t>(r.cfg.fuse_max ? r.cfg.fuse_max : 65536u, s->run_ops);
   if (s->cfg.tick_updates) fuse_max = std::min<uint64_t>(fuse_max, std::max<uint64_t>(1, s->cfg.tick_updates / std::max<uint64_t>(nnz, 1)));
   fuse_max = std::min<uint64_t>(fuse_max, arena_run_cap(s, r));
   size_t run_len = 0, run_begin = c.mono_seen;
@@ -677,13 +678,13 @@ int srv_create(const srv_config* cfg, void* stream, void* pool, size_t pool_byte
     return sfail(SIM_E_ARG, "arena_bytes must be 0 (default 64 MiB) or at least 1 MiB");
   if (cfg->grid > 65536) return sfail(SIM_E_ARG, "grid must be 0 (default 2048) or 1..65536");
   if (cfg->lane_workers > 64) return sfail(SIM_E_ARG, "lane_workers must be 0 (default 8) or 1..64");
-  if (cfg->reserved) return sfail(SIM_E_ARG, "reserved must be 0");
   if (cfg->flags & ~(SRV_FLAG_NO_GRAPH | SRV_FLAG_U2_GLOBAL_INDEX | SRV_FLAG_NO_RP | SRV_FLAG_ONE_SEGMENT))
     return sfail(SIM_E_ARG, "unknown flags");
   std::unique_ptr<srv_t> s(new srv_t());
   s->cfg = *cfg;
   if (!s->cfg.arena_bytes) s->cfg.arena_bytes = 64ull << 20;
   s->grid = cfg->grid ? (int)cfg->grid : 2048;
+  s->run_ops = cfg->max_run_ops ? cfg->max_run_ops : 4096u;
   s->lane_cap = cfg->lane_capacity == SRV_LANE_OFF ? 0 : cfg->lane_capacity;   // 0: no lane (default)
   if (hipGetDevice(&s->device) != hipSuccess) s->device = 0;
   if (stream) {

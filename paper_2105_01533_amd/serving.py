@@ -89,7 +89,8 @@ def run_one_at_a_time(reqs, arrivals=True, keep_results=False, tuning: dict | No
 
 def run_batched(reqs, budget_bytes: int, max_slots: int = 256, arrivals=True, keep_results=False, graph=True,
                 tick_updates: int | None = None, grid: int | None = None, lane_capacity: int | None = None,
-                lane_workers: int | None = None, tuning: dict | None = None, flags: int = 0):
+                lane_workers: int | None = None, tuning: dict | None = None, flags: int = 0,
+                max_run_ops: int | None = None):
     """Replay through the continuous-batching server (open loop when
     arrivals, else every request at time 0).  Server knobs left None take the
     autotuner table's values.  tuning: optional table replacing each
@@ -97,7 +98,7 @@ def run_batched(reqs, budget_bytes: int, max_slots: int = 256, arrivals=True, ke
     from . import autotune
 
     srv = S.Server(budget_bytes, max_slots=max_slots, graph=graph, tick_updates=tick_updates, grid=grid,
-                   lane_capacity=lane_capacity, lane_workers=lane_workers, flags=flags)
+                   lane_capacity=lane_capacity, lane_workers=lane_workers, flags=flags, max_run_ops=max_run_ops)
     if tuning:
         for r in reqs:
             k = autotune.lookup(tuning, r.w.n_qubits, r.w.capacity)

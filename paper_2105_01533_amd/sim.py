@@ -416,7 +416,7 @@ class srv_config(ctypes.Structure):
     _fields_ = [("budget_bytes", ctypes.c_uint64), ("arena_bytes", ctypes.c_uint64),
                 ("max_slots", ctypes.c_uint32), ("flags", ctypes.c_uint32), ("tick_updates", ctypes.c_uint64),
                 ("grid", ctypes.c_uint32), ("lane_capacity", ctypes.c_uint32),
-                ("lane_workers", ctypes.c_uint32), ("reserved", ctypes.c_uint32)]
+                ("lane_workers", ctypes.c_uint32), ("max_run_ops", ctypes.c_uint32)]
 
 
 class srv_stats(ctypes.Structure):
@@ -551,13 +551,14 @@ class Server:
 
     def __init__(self, budget_bytes: int, max_slots: int = 256, arena_bytes: int = 0, graph: bool = True,
                  tick_updates: int | None = None, grid: int | None = None, lane_capacity: int | None = None,
-                 lane_workers: int | None = None, device: str = "cuda", tuned: bool = True, flags: int = 0):
+                 lane_workers: int | None = None, device: str = "cuda", tuned: bool = True, flags: int = 0,
+                 max_run_ops: int | None = None):
         """Server knobs left as None take the autotuner table's values (the
         library defaults with tuned=False); `knobs` records what was used.
         submit_workload applies the table's per-state knobs the same way."""
         from . import autotune
         given = {"tick_updates": tick_updates, "grid": grid, "lane_capacity": lane_capacity,
-                 "lane_workers": lane_workers}
+                 "lane_workers": lane_workers, "max_run_ops": max_run_ops}
         self.tuned = tuned
         self.knobs = autotune.server_knobs(given) if tuned else {k: (v or 0) for k, v in given.items()}
         self.cfg = srv_config(budget_bytes=budget_bytes, arena_bytes=arena_bytes, max_slots=max_slots,

@@ -47,10 +47,11 @@ def mix():
     return ws
 
 
-def run_server(S, ws, budget=1 << 30, slots=64, graph=True, arena_bytes=0, lane=None, flags=0, **tuning):
+def run_server(S, ws, budget=1 << 30, slots=64, graph=True, arena_bytes=0, lane=None, flags=0, max_run_ops=None,
+               **tuning):
     """Every request batched unless `lane` (a lane threshold) is given."""
     srv = S.Server(budget, max_slots=slots, graph=graph, arena_bytes=arena_bytes,
-                   lane_capacity=S.SRV_LANE_OFF if lane is None else lane, flags=flags)
+                   lane_capacity=S.SRV_LANE_OFF if lane is None else lane, flags=flags, max_run_ops=max_run_ops)
     ids = [srv.submit_workload(w, **tuning) for w in ws]
     srv.run()
     out = []
@@ -389,6 +390,38 @@ def test_measurement_chains(S):
         assert st == S.SRV_FAILED and err == S.SIM_E_STATE, flags
         assert srv.poll(ids[1])[0] == S.SRV_DONE
         srv.close()
+
+
+def test_run_cap_changes_rounding_only(S):
+    """max_run_ops cuts each request's fused runs per tick: labels, outcomes
+    and counters other than the pass counts do not depend on it, amplitudes
+    agree to rounding, each setting gives the same bits alone and in a mix,
+    and matches the oracle."""
+    ws = [W.config1(64, w=12, adds=6, n=40), W.config2(65, n=100, h_qubits=10, gates=6000, round_gates=2000,
+                                                        meas_per_round=3), mix()[1]]
+    # (all with eps = 1e-20: a residue of a rounding difference is pruned either way)
+    out = {}
+    for cap in (64, 4096, 65536):
+        srv = S.Server(1 << 30, max_slots=8, lane_capacity=S.SRV_LANE_OFF, max_run_ops=cap)
+        assert srv.knobs["max_run_ops"] == cap
+        ids = [srv.submit_workload(w) for w in ws]
+        srv.run()
+        out[cap] = [srv.result(i) for i in ids]
+        srv.close()
+        alone, _ = run_server(S, [ws[1]], max_run_ops=cap)
+        for p, q in zip(alone[0][:4], out[cap][1][:4]):
+            assert p.tobytes() == q.tobytes(), cap
+    for w, a, b, c in zip(ws, out[64], out[4096], out[65536]):
+        for x in (a, b):
+            assert x[0].tobytes() == c[0].tobytes() and x[1].tobytes() == c[1].tobytes(), w.name
+            assert list(x[3]) == list(c[3]), w.name
+            for k in ("updates", "u2_applied", "u2_skipped", "measures", "peak_nnz"):
+                assert x[4][k] == c[4][k], (w.name, k)
+            assert np.max(np.abs(x[2] - c[2])) <= 1e-12, w.name
+        assert a[4]["mono_passes"] >= c[4]["mono_passes"]
+        o, oout, _ = oracle_run(w)
+        assert list(a[3]) == list(oout), w.name
+        assert_same_state(a[:3], o.export(), what=w.name)
 
 
 def test_destroy_with_work_in_flight(S):
