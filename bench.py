@@ -375,10 +375,10 @@ def copy_bandwidth(sim, torch, nbytes=1 << 30, reps=5):
             "frac": round(gbs / HBM_PEAK_GBS, 4)}
 
 
-def measured_traffic():
+def measured_traffic(workload: str):
     """Per-launch HBM bytes of the fused pass from the committed counter runs
-    (profiles/mono_pass_traffic.json), or None if the kernel sources changed
-    since the counters were taken."""
+    (profiles/mono_pass_traffic.json), or None if they were taken on another
+    workload or the kernel sources changed since."""
     import hashlib
 
     p = os.path.join(ROOT, "profiles", "mono_pass_traffic.json")
@@ -386,6 +386,8 @@ def measured_traffic():
         return None
     with open(p) as f:
         doc = json.load(f)
+    if doc.get("workload") != workload:
+        return None
     h = hashlib.sha256()
     for s in doc["sources"]:
         with open(os.path.join(ROOT, s), "rb") as f:
@@ -512,9 +514,9 @@ def main():
     bound, view = ("alu", alu) if crossed else ("hbm", hbm)
     roofline = {
         "kernel": "mono_pass", "dominant_kernel": dom, "bound": bound, "achieved": view["achieved"],
-        "limiter": "instruction issue (scalar plane-index setup and vector plane ops per gate; SQ counters in "
-                   "profiles/mono_pass_sq_c2_random_100q.md)",
-        "peak": view["peak"], "unit": view["unit"], "frac": view["frac"], "traffic": measured_traffic(),
+        "limiter": ("instruction issue (scalar plane-index setup and vector plane ops per gate; SQ counters in "
+                    "profiles/mono_pass_sq_c2_random_100q.md)" if w.name == "c2_random_100q" else None),
+        "peak": view["peak"], "unit": view["unit"], "frac": view["frac"], "traffic": measured_traffic(w.name),
         "hbm": hbm, "alu": alu,
         "launches_per_step": mono["launches"] / args.steps,
         "alg_bytes_per_launch": bytes_per_launch, "alg_ops_per_launch": ops_per_launch,
