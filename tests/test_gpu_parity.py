@@ -1176,3 +1176,83 @@ def test_engine_flags_leave_results_unchanged(sim, n, seed, eps):
     assert oa == list(oout)
     order = np.lexsort((a[0], a[1]))
     assert_same_state(tuple(x[order] for x in a), o.export(), 1e-12, w.name)
+
+
+def _wrap_circuit(n, rounds, seed):
+    """Branching gates cycling over 12 qubits in superposition (states of
+    2^10..2^12 entries), with controlled ones, CNOTs and a few measurements:
+    hundreds of gates that use the partner index."""
+    rng = W.SplitMix64(seed)
+    c = W.Circuit()
+    for q in range(10):
+        c.h(q)
+    for k in range(rounds):
+        q = k % 12
+        if k % 3 == 0:
+            c.gate(W.K_RY, q, param=(rng.uniform() - 0.5) * 2.0)
+        elif k % 3 == 1:
+            c.h(q, ctrls=((q + 5) % 12,) if k % 5 == 0 else ())
+        else:
+            c.gate(W.K_X, (q + 3) % 12, controls=(q,))
+            c.h(q)
+        if k % 97 == 96:
+            c.measure((q + 7) % 12, rng.uniform())
+    return W.Workload(f"wrap_{n}q", n, 1e-20, c.array(), 1 << 14)
+
+
+@pytest.mark.parametrize("n", [40, 100])
+def test_index_reused_over_many_gates(sim, n):
+    """Over 530 branching gates on one handle (hundreds of them through the
+    partner index) the global index, alone and in the two-pass form, gives the
+    LDS index's state, outcomes and counters bit for bit, and the oracle's."""
+    w = _wrap_circuit(n, 520, 5)
+    out = []
+    for flags in (0, sim.SIM_FLAG_U2_GLOBAL_INDEX, sim.SIM_FLAG_U2_GLOBAL_INDEX | sim.SIM_FLAG_U2_TWO_PASS):
+        s, outs, st = sim.run_workload(w, flags=flags)
+        out.append((s.export(sort=False), list(outs), st))
+        s.close()
+    (a, oa, sa) = out[0]
+    assert sa["u2_applied"] - sa["u2_split"] > 2 * 255
+    for b, ob, sb in out[1:]:
+        for x, y in zip(a, b):
+            assert x.tobytes() == y.tobytes()
+        assert oa == ob
+        for k in ("u2_applied", "u2_skipped", "pruned", "updates", "peak_nnz", "measures", "u2_split"):
+            assert sa[k] == sb[k], k
+    o, oout, _ = oracle_run(w)
+    assert oa == list(oout)
+    order = np.lexsort((a[0], a[1]))
+    assert_same_state(tuple(x[order] for x in a), o.export(), 1e-12, w.name)
+
+
+def test_index_reused_across_table_sizes(sim):
+    """Hundreds of global-index gates alternate between stages on small
+    tables and on large ones on one handle: slots a larger table used before
+    never pair wrong partners later, and every stage matches the oracle."""
+    n = 80
+    s = sim.Simulator(n, 1 << 18, 1e-20, flags=sim.SIM_FLAG_U2_GLOBAL_INDEX)
+    try:
+        # Gates come in inverse pairs on random labels (few partners): the
+        # first doubles the state, the second pairs every entry and brings it
+        # back, and both use the index.
+        stages = [("small", 200), ("large", 120), ("small", 250), ("large", 60)]
+        for k, (kind, gates) in enumerate(stages):
+            lo, hi, amp = W.random_state(1700 + k, 50_000 if kind == "large" else 1500, n)
+            c = W.Circuit()
+            for g in range(gates // 2):
+                q = (7 * g) % 16 if kind == "large" else g % 11
+                if g % 3 == 0:
+                    c.gate(W.K_RY, q, param=0.3 + 0.01 * g)
+                    c.gate(W.K_RY, q, param=-(0.3 + 0.01 * g))
+                else:
+                    ctrls = ((q + 1) % 16,) if g % 3 == 1 else ()
+                    c.h(q, ctrls=ctrls)
+                    c.h(q, ctrls=ctrls)
+            s.import_state(lo, hi, amp)
+            _, _, st = s.apply_ops(c.array())
+            o = Oracle(n, 1e-20)
+            o.import_state(lo, hi, amp)
+            o.run(c.array())
+            assert_same_state(s.export(), o.export(), what=f"stage {k} ({kind})")
+    finally:
+        s.close()
