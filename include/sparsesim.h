@@ -175,7 +175,7 @@ typedef struct sim_config {
  * keeps them in LDS instead.  The results are identical. */
 #define SIM_FLAG_BS_LDS 2u
 
-/* Branching gates on small states (at most 4096 entries) run as one block
+/* Branching gates on small states (at most 8192 entries) run as one block
  * whose partner index is in LDS; this flag sends them through the global
  * index (index build, probe, single pass) like larger states.  Both give the
  * same outputs in the same order. */
@@ -365,7 +365,7 @@ int sim_device_state(sim_t* s, uint64_t** key_lo, uint64_t** key_hi, double** am
  * here; u2_count and block_scan run only in the two-pass form),
  * measure_reduce, measure_decide and measure_write (a chain of consecutive
  * measurements runs one reduce), and u2_lds (the one-block branching kernel
- * of states of at most 4096 entries, index in LDS).
+ * of states of at most 8192 entries, index in LDS).
  * With profiling on for a class (sim_set_profiling), every launch of it is
  * bracketed by HIP events on the handle's stream and total_ms sums their
  * elapsed times; otherwise total_ms is 0.  alg_bytes is the algorithmic HBM
@@ -441,7 +441,7 @@ int sim_kernel_stats_reset(sim_t* s);
 #define SRV_FAILED 3
 
 #define SRV_FLAG_NO_GRAPH 1u /* launch the tick kernels directly instead of replaying the graph */
-/* Branching gates of states of at most 4096 entries run one block per state
+/* Branching gates of states of at most 8192 entries run one block per state
  * with the partner index in LDS; this flag sends them through the global
  * index kernels like larger states (same outputs, same order). */
 #define SRV_FLAG_U2_GLOBAL_INDEX 2u

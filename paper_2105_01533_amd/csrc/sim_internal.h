@@ -315,7 +315,7 @@ void launch_u2_fused(hipStream_t st, bool wide, Buf in, Buf out, const uint64_t*
                      uint64_t* nnz_out, uint64_t* table, uint64_t clear_slots, int grid, uint32_t tile);
 // Largest state the one-block branching kernel takes (its partner index and
 // partner slots live in LDS).
-constexpr uint32_t kLdsU2Max = 4096;
+constexpr uint32_t kLdsU2Max = 8192;
 // One block: a branching gate on a state of at most kLdsU2Max entries, index
 // and look-up in LDS; outputs, their order and the counters as the
 // multi-kernel path's single pass (pruned_mass up to summation order).

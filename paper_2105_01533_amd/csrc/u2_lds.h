@@ -7,8 +7,8 @@
 // the pivot-set entries) pair them; Eq. 2 is evaluated by ent::u2_eval and the
 // outputs are written in entry order.  The outputs and their order are
 // therefore those of the index-build / probe / write kernels, in one launch
-// and with no global index to fill, probe or empty.  A slot holds a 19-bit
-// fingerprint above entry index + 1 (13 bits; 0 = empty); the table has twice
+// and with no global index to fill, probe or empty.  A slot holds an 18-bit
+// fingerprint above entry index + 1 (kIdxBits = 14 bits; 0 = empty); the table has twice
 // as many slots as the largest state, so it is at most half full and every
 // probe sequence meets an empty slot.
 #pragma once
@@ -21,9 +21,11 @@ constexpr uint32_t kSlots = 2 * kLdsU2Max;
 constexpr int kThreads = 1024;
 constexpr int kItems = (int)(kLdsU2Max / kThreads);
 constexpr int kWaves = kThreads / 64;
-static_assert(kLdsU2Max < (1u << 13) && kItems * kThreads == (int)kLdsU2Max, "index field of a slot");
+constexpr int kIdxBits = 14;
+constexpr uint32_t kIdxMask = (1u << kIdxBits) - 1u;
+static_assert(kLdsU2Max < (1u << kIdxBits) && kItems * kThreads == (int)kLdsU2Max, "index field of a slot");
 
-// LDS of one block (about 49 KB); declared by the kernel, whatever the label
+// LDS of one block (about 96 KB); declared by the kernel, whatever the label
 // width, so that both widths share it.
 struct Smem {
   uint32_t tab[kSlots];
@@ -108,7 +110,7 @@ __device__ Totals u2_block(const Buf& in, const Buf& out, uint32_t n, const U2De
     const uint32_t i = (uint32_t)k * kThreads + threadIdx.x;
     if (i >= n || !ent::ctrl_ok(d, lo[k], hi[k], WIDE) || ent::pivot_set(d, lo[k], hi[k], WIDE)) continue;
     const uint64_t h = ent::hash_label(lo[k], hi[k]);
-    const uint32_t val = ((uint32_t)(h >> 45) << 13) | (i + 1u);
+    const uint32_t val = ((uint32_t)(h >> (32 + kIdxBits)) << kIdxBits) | (i + 1u);
     uint32_t slot = (uint32_t)h & kMask;
     ++inserts;
     for (uint32_t p = 0; p < kSlots; ++p) {
@@ -126,15 +128,15 @@ __device__ Totals u2_block(const Buf& in, const Buf& out, uint32_t n, const U2De
     if (i >= n || !ent::ctrl_ok(d, lo[k], hi[k], WIDE) || !ent::pivot_set(d, lo[k], hi[k], WIDE)) continue;
     const uint64_t qlo = lo[k] ^ d.x_lo, qhi = WIDE ? (hi[k] ^ d.x_hi) : 0ull;
     const uint64_t h = ent::hash_label(qlo, qhi);
-    const uint32_t fp = (uint32_t)(h >> 45);
+    const uint32_t fp = (uint32_t)(h >> (32 + kIdxBits));
     uint32_t slot = (uint32_t)h & kMask;
     ++lookups;
     for (uint32_t p = 0; p < kSlots; ++p) {
       const uint32_t v = sm.tab[slot];
       ++steps;
       if (v == 0u) break;
-      if ((v >> 13) == fp) {
-        const uint32_t j = (v & 0x1FFFu) - 1u;
+      if ((v >> kIdxBits) == fp) {
+        const uint32_t j = (v & kIdxMask) - 1u;
         if (in.key_lo[j] == qlo && (!WIDE || in.key_hi[j] == qhi)) {
           sm.par[i] = j;
           sm.par[j] = i;
@@ -153,6 +155,7 @@ __device__ Totals u2_block(const Buf& in, const Buf& out, uint32_t n, const U2De
   double mass = 0.0;
 #pragma unroll
   for (int k = 0; k < kItems; ++k) {
+    if ((uint32_t)k * kThreads >= n) break;   // uniform: no entry in this round or later ones
     const uint32_t i = (uint32_t)k * kThreads + threadIdx.x;
     ent::U2Out r;
     r.mode = 2;

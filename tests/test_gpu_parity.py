@@ -467,7 +467,7 @@ def test_profiling_modes(sim):
 @pytest.mark.parametrize("which", ["c0", "c2_small", "c2_wide_ctrl"])
 def test_u2_single_pass_matches_two_pass(sim, which):
     """Branching gates whose outputs fit run as one pass (evaluation, chained
-    scan over 2048-entry tiles, ordered write), or, on states of at most 4096
+    scan over 2048-entry tiles, ordered write), or, on states of at most 8192
     entries, as one block with the partner index in LDS; the state is bitwise
     the one the separate count, scan and write passes produce, in the same
     order, and the one the global index gives for every size."""
@@ -964,13 +964,13 @@ def _paired_state(seed, size, n, t):
 
 
 @pytest.mark.parametrize("n", [30, 100])
-@pytest.mark.parametrize("size", [1, 3, 4095, 4096, 4097])
+@pytest.mark.parametrize("size", [1, 3, 4096, 8191, 8192, 8193])
 def test_u2_lds_kernel_around_its_limit(sim, n, size):
     """Branching gates on imported states at and around the one-block
-    kernel's limit (4096 entries): a controlled Ry, an H on the same target
+    kernel's limit (8192 entries): a controlled Ry, an H on the same target
     and an H on a high qubit (a third of the entries have their partner
     present).  Against the oracle, and bit for bit against the global-index
-    path; the one-block kernel runs exactly when the state has at most 4096
+    path; the one-block kernel runs exactly when the state has at most 8192
     entries."""
     t = 5 if n <= 64 else 70
     lo, hi, amp = _paired_state(9000 + size + n, size, n, t)
@@ -981,7 +981,7 @@ def test_u2_lds_kernel_around_its_limit(sim, n, size):
     ops = c.array()
     res = []
     for flags in (0, sim.SIM_FLAG_U2_GLOBAL_INDEX):
-        s = sim.Simulator(n, 1 << 15, 1e-30, flags=flags)
+        s = sim.Simulator(n, 1 << 16, 1e-30, flags=flags)
         try:
             s.import_state(lo, hi, amp)
             sim.sim_kernel_stats_reset(s.h)
@@ -997,9 +997,9 @@ def test_u2_lds_kernel_around_its_limit(sim, n, size):
         assert sa[k] == sb[k], k
     # The engine's bound on the entry count before the three gates is size,
     # 2 size and 4 size (the import's count is exact; a branching gate at
-    # most doubles it); the one-block kernel runs where that bound is <= 4096.
+    # most doubles it); the one-block kernel runs where that bound is <= 8192.
     assert sa["u2_applied"] == 3
-    assert ka["u2_lds"]["launches"] == sum(ub <= 4096 for ub in (size, 2 * size, 4 * size))
+    assert ka["u2_lds"]["launches"] == sum(ub <= 8192 for ub in (size, 2 * size, 4 * size))
     assert kb["u2_lds"]["launches"] == 0
     o = Oracle(n, 1e-30)
     o.import_state(lo, hi, amp)

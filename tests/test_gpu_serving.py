@@ -269,7 +269,7 @@ def test_result_records_equal_arrays(S):
 
 
 def test_small_states_lds_index_equals_global_index(S):
-    """Branching gates of batched states of at most 4096 entries run one
+    """Branching gates of batched states of at most 8192 entries run one
     block per state with the partner index in LDS; the results are bit for bit
     those of the global-index kernels (SRV_FLAG_U2_GLOBAL_INDEX), alone and in
     the mix, and each matches the oracle."""
@@ -280,17 +280,17 @@ def test_small_states_lds_index_equals_global_index(S):
     for w, x, y in zip(ws, a, b):
         for p, q in zip(x[:4], y[:4]):
             assert p.tobytes() == q.tobytes(), w.name
-    # a state that crosses the limit: 12 Hadamards reach 4096 entries, the
-    # 13th and 14th run on 4096 and 8192 entries
+    # a state that crosses the limit: 13 Hadamards reach 8192 entries, the
+    # 14th and 15th run on 8192 and 16384 entries
     c = W.Circuit()
-    for q in range(14):
+    for q in range(15):
         c.h(q)
     c.gate(W.K_RY, 3, controls=(20,), param=0.3)
-    w = W.Workload("h14", 24, 0.0, c.array(), 1 << 15, (1 << 20, 0))
+    w = W.Workload("h15", 24, 0.0, c.array(), 1 << 16, (1 << 20, 0))
     for flags in (0, S.SRV_FLAG_U2_GLOBAL_INDEX):
         res, _ = run_server(S, [w, ws[0]], flags=flags)
         o, oout, _ = oracle_run(w)
-        assert_same_state(res[0][:3], o.export(), what=f"h14 flags={flags}")
+        assert_same_state(res[0][:3], o.export(), what=f"h15 flags={flags}")
 
 
 def test_large_states_register_plane_runs(S):
