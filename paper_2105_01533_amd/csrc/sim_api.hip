@@ -358,7 +358,7 @@ int mono_grid(const sim_t* s, uint64_t n) {
 }
 
 int chunk_grid(uint64_t n) {
-  const uint64_t g = (n + 2047) / 2048;
+  const uint64_t g = (n + kTwoPassChunk - 1) / kTwoPassChunk;
   return (int)std::max<uint64_t>(1, std::min<uint64_t>(g, kMaxBlocks));
 }
 
@@ -510,7 +510,7 @@ int run_measure(sim_t* s, uint32_t q, double u, int32_t forced, MeasRec* rec, in
   const uint64_t ub = s->nnz_known ? s->nnz_exact : s->nnz_ub;
   // 8192 entries per block: a quarter of the partial sums the decide kernel
   // reads, each block still several tiles of work.
-  const int G = (int)std::max<uint64_t>(1, std::min<uint64_t>((ub + 8191) / 8192, kMaxBlocks));
+  const int G = (int)std::max<uint64_t>(1, std::min<uint64_t>((ub + kMeasChunk - 1) / kMeasChunk, kMaxBlocks));
   const int other = s->cur ^ 1;
   const uint64_t* nnz_in = d_nnz(s, s->cur);
   const bool chained = s->mchain.valid && s->mchain.q == q && s->mchain.grid == G;

@@ -20,6 +20,11 @@ size_t pauli_op_count(const sim_pauli* terms, size_t n);
 constexpr uint64_t kEmptySlot = ~0ull;   // hash index: free slot
 constexpr uint32_t kNoPartner = ~0u;     // partner look-up miss
 constexpr int kMaxBlocks = 8192;         // blocks of the chunked (ordered) kernels
+// Entries per block of the chunked kernels: the two-pass branching count and
+// write, and the measurement reduce and write.  The host sizes their grids
+// from its bound on the entry count with these; the kernels keep the same
+// block ranges whatever that bound was.
+constexpr uint64_t kTwoPassChunk = 2048, kMeasChunk = 8192;
 
 // One state buffer (structure of arrays).  key_hi is null for states of at
 // most 64 qubits, whose labels fit in key_lo.

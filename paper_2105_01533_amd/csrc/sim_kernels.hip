@@ -4,7 +4,7 @@
 // kernel reads the live entry count from device memory, so the host never has
 // to know it to launch work.  Kernels that change the entry count (branching
 // gates, measurement) are "chunked": block b owns the contiguous entry range
-// [b*chunk, (b+1)*chunk) with chunk = ceil(nnz / gridDim.x), counts what it
+// [b*chunk, (b+1)*chunk) with chunk fixed per kernel (chunk_len), counts what it
 // will emit, a one-block scan turns the counts into output offsets, and the
 // write kernel emits in entry order.  Output order is therefore a fixed
 // function of the input order: runs are deterministic and no floating-point
@@ -26,8 +26,17 @@ using ent::hash_label;
 using ent::sel2;
 using ent::survives;
 
-__device__ __forceinline__ void chunk_range(uint64_t n, uint64_t& begin, uint64_t& end) {
-  const uint64_t chunk = (n + gridDim.x - 1) / gridDim.x;
+// Entries per block of a chunked launch of nb blocks: `per`, or an even split
+// when nb blocks of `per` do not cover n.  The host sizes the grid from its
+// bound on n (at least n), so block ranges, and every sum grouped by block,
+// depend on n alone and not on where the host last read the count.
+__device__ __forceinline__ uint64_t chunk_len(uint64_t n, uint64_t nb, uint64_t per) {
+  const uint64_t even = (n + nb - 1) / nb;
+  return even > per ? even : per;
+}
+
+__device__ __forceinline__ void chunk_range(uint64_t n, uint64_t per, uint64_t& begin, uint64_t& end) {
+  const uint64_t chunk = chunk_len(n, gridDim.x, per);
   begin = (uint64_t)blockIdx.x * chunk;
   end = begin + chunk < n ? begin + chunk : n;
   if (begin > end) begin = end;
@@ -277,7 +286,7 @@ __global__ __launch_bounds__(256) void k_u2_count(Buf b, const uint64_t* __restr
   __shared__ double2 shm[4];   // one slot per wave
   const uint64_t n = *nnz_p;
   uint64_t begin, end;
-  chunk_range(n, begin, end);
+  chunk_range(n, kTwoPassChunk, begin, end);
   uint32_t emit = 0, dropped = 0;
   double mass = 0.0;
   for (uint64_t i = begin + threadIdx.x; i < end; i += blockDim.x) {
@@ -366,7 +375,7 @@ __global__ __launch_bounds__(256) void k_u2_write(Buf in, Buf out, const uint64_
   if (blockIdx.x == 0 && threadIdx.x == 0)
     atomicAdd((unsigned long long*)&ctl->pass_bytes[1], (unsigned long long)(n * (WIDE ? 32u : 24u)));
   uint64_t begin, end;
-  chunk_range(n, begin, end);
+  chunk_range(n, kTwoPassChunk, begin, end);
   uint64_t base = off[blockIdx.x];
   for (uint64_t tile = begin; tile < end; tile += blockDim.x) {
     const uint64_t i = tile + threadIdx.x;
@@ -620,7 +629,7 @@ __global__ __launch_bounds__(256) void k_measure_reduce(Buf b, const uint64_t* _
   __shared__ uint32_t shu[256];
   const uint64_t n = *nnz_p;
   uint64_t begin, end;
-  chunk_range(n, begin, end);
+  chunk_range(n, kMeasChunk, begin, end);
   double p0 = 0.0, p1 = 0.0;
   uint32_t c1 = 0;
   const bool qhi = WIDE && q >= 64;
@@ -667,7 +676,7 @@ __global__ __launch_bounds__(1024) void k_measure_decide(const double2* __restri
   // Per-block kept counts need each block's input length: its uniform chunk,
   // or (in_off given) the range the previous measurement's write block
   // produced.  Thread t owns blocks [t per, (t + 1) per).
-  const uint64_t chunk = (n + nb - 1) / nb;
+  const uint64_t chunk = chunk_len(n, nb, kMeasChunk);
   const int per = (nb + 1023) / 1024;
   const int first = threadIdx.x * per;
   uint32_t c1[kPer], len[kPer];
@@ -775,7 +784,7 @@ __global__ __launch_bounds__(256) void k_measure_write(Buf in, Buf out, const ui
     begin = in_off[blockIdx.x];
     end = blockIdx.x + 1 < gridDim.x ? in_off[blockIdx.x + 1] : n;
   } else {
-    chunk_range(n, begin, end);
+    chunk_range(n, kMeasChunk, begin, end);
   }
   const int o = rec->outcome;
   const double scale = rec->scale;

@@ -1256,3 +1256,42 @@ def test_index_reused_across_table_sizes(sim):
             assert_same_state(s.export(), o.export(), what=f"stage {k} ({kind})")
     finally:
         s.close()
+
+
+def test_results_do_not_depend_on_count_reads(sim):
+    """The host sizes chunked launches from its bound on the entry count and
+    reads the exact count only at some points; block ranges, and the sums
+    grouped by them, depend on the count alone.  Splitting a circuit before
+    applied branching gates (where fused runs end anyway: a gate the cap
+    skips does not end one, and a cut between measurements would break their
+    chain, which sums in another order by design) and reading the count there
+    gives the unsplit run's state and outcomes bit for bit."""
+    w = W.config2(71, n=100, h_qubits=15, gates=3000, round_gates=1000, meas_per_round=3)
+    kinds = w.ops["kind"]
+    o = Oracle(w.n_qubits, w.eps)
+    o.set_basis(*w.basis)
+    _, tr = o.run(w.ops, trace=True)
+    cuts = [i for i in range(1, len(kinds)) if kinds[i] in (W.K_H, W.K_RX, W.K_RY) and tr["applied"][i]]
+    assert len(cuts) >= 20
+    s = sim.Simulator(w.n_qubits, w.capacity, w.eps)
+    try:
+        s.set_basis(*w.basis)
+        outs, prev = [], 0
+        for c in cuts + [len(kinds)]:
+            _, o, _ = s.apply_ops(w.ops[prev:c])
+            outs += list(o)
+            assert s.nnz > 0        # reads the exact count
+            prev = c
+        split = s.export(sort=False)
+    finally:
+        s.close()
+    s2 = sim.Simulator(w.n_qubits, w.capacity, w.eps)
+    try:
+        s2.set_basis(*w.basis)
+        _, o2, _ = s2.apply_ops(w.ops)
+        whole = s2.export(sort=False)
+    finally:
+        s2.close()
+    assert outs == list(o2)
+    for a, b in zip(whole, split):
+        assert a.tobytes() == b.tobytes()
